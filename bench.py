@@ -1,0 +1,216 @@
+#!/usr/bin/env python
+"""Benchmark of the HAMLS hot path on one MI355X.
+
+Workload: S2 ill-distributed nodes, M = 200,000 (8 von Mises-Fisher clusters
+with kappa = 20 plus 20 % uniform, five 20-degree caps removed), bandwidth
+N = 128, MLS degree K = 3 (m = 10), Gauss-Legendre grid 129 x 258 (33,282
+local solves), adaptive radius with n = 40, eps = 0.05, chi-target
+regularization (chi_T = 10, chi_full = 20), one field, FP64.
+
+One step = one whole fit with the inputs resident in device memory:
+node binning + sort + support radii (plan rebind), the MLS value at every grid
+node (Gram assembly + regularized solve), ring DFTs + Legendre contraction.
+value = grid nodes solved per second = M_Q * F * steps / wall time of the
+timed steps.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def flops_per_pair(m, F):
+    """Algorithmic FLOPs of one (grid node, neighbour) pair in the fused MLS
+    step: predicate 5, tangent coordinates 12, weight 10 (distance, Wendland,
+    node weight, square root), monomials and weighting 2m, Gram m(m+1),
+    right-hand sides 2mF."""
+    return 5 + 12 + 10 + 2 * m + m * (m + 1) + 2 * m * F
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU design is "
+                          "described in DESIGN.md and is not built"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2609_39200_amd import hamls as H
+    from paper_2609_39200_amd import workloads as W
+
+    t_gen = time.time()
+    wl = W.s2_clusters()
+    F = wl.values.shape[0]
+    dev = torch.device("cuda:0")
+    nodes = torch.as_tensor(wl.nodes, dtype=torch.float64, device=dev).contiguous()
+    vals = torch.as_tensor(wl.values, dtype=torch.float64, device=dev).contiguous()
+    p = H.params_from_workload(wl.params)
+    stream = torch.cuda.current_stream()
+    plan = H.hamls_plan(p, nodes, stream=stream)
+    info = H.hamls_plan_info_get(plan)
+    MQ = info.num_grid
+    gv = torch.empty((F, MQ), dtype=torch.float64, device=dev)
+    cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=dev)
+    gen_s = time.time() - t_gen
+
+    def step():
+        H.hamls_plan_rebind(plan, nodes, stream=stream)
+        H.hamls_mls_to_grid(plan, vals, gv, stream=stream)
+        H.hamls_grid_to_coeffs(plan, gv, cf, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for ph in H.PHASES:
+        H.hamls_timing_read(plan, ph)  # clear
+    H.hamls_timing_enable(plan, True)
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    H.hamls_timing_enable(plan, False)
+    wall = t1 - t0
+    lat = [a.elapsed_time(b) for a, b in ev]
+    phases = {}
+    for ph in H.PHASES:
+        n, ms = H.hamls_timing_read(plan, ph)
+        if n:
+            phases[ph] = {"launches": n, "avg_ms": ms / n}
+
+    diag = H.hamls_diagnostics(plan)
+    pairs = int(diag["n"].astype(np.int64).sum())
+    n_reg = int(np.sum(diag["status"] & H.ST_REGULARIZED != 0))
+    n_ill = int(np.sum(diag["status"] & H.ST_ILLCOND != 0))
+
+    # roofline of the dominant phase
+    m = info.m
+    dom = max(phases, key=lambda k: phases[k]["avg_ms"])
+    roof = None
+    if dom == "assemble":
+        fl = pairs * flops_per_pair(m, F)
+        ach = fl / (phases[dom]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "assemble", "bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                "units_per_launch": {"pairs": pairs, "flop_per_pair": flops_per_pair(m, F)}}
+    else:
+        # other phases are priced on their algorithmic HBM bytes
+        Mn = info.num_nodes
+        nt, npf = info.grid_dims[0], info.grid_dims[1]
+        N = info.bandwidth
+        bytes_by_phase = {
+            # keys: read 24 B + write 4+4 B; per pass 16 B (2 keys+2 indices, r+w)
+            # x 2 passes; cell table; gather 4+24 B read, 24+4 B write
+            "binning": Mn * (24 + 8 + 2 * 16 + 8 + 56),
+            # every candidate record read once (24 B), radius writes
+            "radius": pairs * 24 + MQ * 17,
+            "solve": MQ * (8 * (m * (m + 1) // 2 + m * F) + 4 + 8 * F + 17),
+            "ring_dft": MQ * 8 * F + nt * (N + 1) * 16 * F,
+            "contract": ((nt + 1) // 2) * ((N + 1) * (N + 2) // 2) * 8 + (N + 1) ** 2 * 16 * F,
+            "gather": Mn * (4 + 16 * F),
+        }
+        b = bytes_by_phase.get(dom, 0)
+        ach = b / (phases[dom]["avg_ms"] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "units_per_launch": {"bytes": b}}
+
+    out = {
+        "metric": "MLS grid nodes solved/s (whole fit: binning + radii + local solves + quadrature)",
+        "value": MQ * F * K / wall,
+        "unit": "grid nodes/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "S2 ill-distributed, M=200000 (8 vMF clusters kappa=20 + 20% uniform, 5 caps of 20 deg "
+                        "removed), N=128, K=3, grid 129x258, kNN n=40 eps=0.05, chi_T=10 chi_full=20, F=1, FP64",
+            "grid_nodes": MQ,
+            "nodes": int(info.num_nodes),
+            "fields": F,
+        },
+        "fits_per_s": K / wall,
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "min": float(min(lat))},
+        "phases_ms": {k: v["avg_ms"] for k, v in phases.items()},
+        "stats": {"pairs": pairs, "mean_neighbours": pairs / MQ, "regularized": n_reg, "illcond": n_ill},
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["accuracy"] = cpu_baseline(wl, plan, gv, H, args.cpu_seconds)
+    H.hamls_plan_destroy(plan)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, plan, gv, H, budget_s):
+    """The FP64 oracle (untuned) on a bounded sample of the same workload:
+    every s-th grid node for step 2 (brute-force neighbours + QR solves), and
+    the full step-3 quadrature (direct sums).  Extrapolated to the whole grid."""
+    import oracle
+
+    po = oracle.params(**wl.params)
+    opts, _ = oracle.grid(po)
+    MQ = opts.shape[0]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    probe = np.arange(0, MQ, max(1, MQ // 256))
+    t = time.perf_counter()
+    oracle.mls(po, opts, wl.nodes, wl.values, rows=probe)
+    per_row = (time.perf_counter() - t) / probe.size
+    n_rows = int(min(MQ, max(probe.size, budget_s / max(per_row, 1e-9))))
+    rows = np.unique(np.linspace(0, MQ - 1, n_rows).astype(np.int64))
+    t = time.perf_counter()
+    om = oracle.mls(po, opts, wl.nodes, wl.values, rows=rows)
+    t_mls = time.perf_counter() - t
+    t = time.perf_counter()
+    gcpu = gv.cpu().numpy()
+    oracle.coeffs(po, gcpu)
+    t_quad = time.perf_counter() - t
+    t_fit = t_mls * MQ / rows.size + t_quad
+    F = wl.values.shape[0]
+    ref = om["values"]
+    got = gcpu[:, rows]
+    ok = ~np.isnan(ref[0])
+    err = float(np.linalg.norm(got[:, ok] - ref[:, ok]) / np.linalg.norm(ref[:, ok]))
+    return (
+        {"value": MQ * F / t_fit, "unit": "grid nodes/s", "cores": threads, "kind": "oracle",
+         "sample": f"step 2 on {rows.size} of {MQ} grid nodes ({t_mls:.1f} s, extrapolated) + full step 3 "
+                   f"({t_quad:.1f} s); FP64 C oracle, OpenMP"},
+        {"rel_l2_vs_oracle_on_sample": err, "sample_rows": int(rows.size)},
+    )
+
+
+if __name__ == "__main__":
+    main()

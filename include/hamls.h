@@ -1,0 +1,198 @@
+/*
+ * hamls.h -- C ABI of the HAMLS hot path on AMD Instinct MI355X (gfx950).
+ *
+ * HAMLS (harmonic approximation via moving least squares; Hielscher, Poeschl,
+ * Wuensche, "Fast and Stable Harmonic Approximation from Ill-distributed Data
+ * using Moving Least Squares") turns scattered samples (x_i, y_i) on S2, SO(3)
+ * or T3 into the harmonic coefficients of a band-limited approximation
+ * (Alg. 1):
+ *   step 1  an exact product quadrature grid (Sec. 2.1)
+ *   step 2  a moving-least-squares value at every grid node, each from its own
+ *           small regularized local polynomial fit (Sec. 2.2, 2.3)
+ *   step 3  the adjoint Fourier transform of the quadrature rule (eq. (25))
+ *
+ * Plain C: no HIP or torch types cross this boundary.  Device buffers are raw
+ * pointers into device memory of the current HIP device; streams are passed as
+ * void* (a hipStream_t, NULL = the default stream).  All array arguments are
+ * FP64 and C-contiguous.  Every call returns a status and never throws; a
+ * non-OK status leaves outputs unspecified and plan state unchanged, and
+ * hamls_last_error() describes it (thread-local).  Work is enqueued on the
+ * given stream and is asynchronous unless a call says otherwise.
+ */
+#ifndef HAMLS_H
+#define HAMLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HAMLS_OK = 0,
+    HAMLS_ERR_INVALID_ARG = -1,   /* argument outside its documented range */
+    HAMLS_ERR_UNSUPPORTED = -2,   /* valid request this build does not handle */
+    HAMLS_ERR_OUT_OF_MEMORY = -3, /* device or host allocation failed */
+    HAMLS_ERR_DEVICE = -4,        /* HIP runtime error (message in hamls_last_error) */
+    HAMLS_ERR_DOMAIN = -5,        /* geometric precondition violated */
+    HAMLS_ERR_NOT_EXACT_GRID = -6 /* grid_shape not exact on Pi_{2N} */
+} hamls_status;
+
+typedef enum { HAMLS_S2 = 0, HAMLS_SO3 = 1, HAMLS_T3 = 2 } hamls_domain;
+
+/* Regularization of the local problems (Sec. 2.3):
+ *  NONE        tau = 0 (plain MLS, eq. (15))
+ *  FIXED       tau = tau_fixed for every centre in eq. (22)
+ *  CHI_TARGET  tau = 0 where chi <= chi_target; otherwise the tau with
+ *              chi_tau = chi_target (eq. (23)), blended in smoothly between
+ *              chi_target and chi_full. */
+typedef enum { HAMLS_REG_NONE = 0, HAMLS_REG_FIXED = 1, HAMLS_REG_CHI_TARGET = 2 } hamls_reg;
+
+/* Arithmetic of step 2 (and step 3):
+ *  FP64   every step in double precision
+ *  MIXED  Gram assembly in FP32 with an FP64 residual refinement, FP64
+ *         factorization of ill-conditioned centres; step 3 contraction in FP32
+ *         (tables generated in FP64). */
+typedef enum { HAMLS_FP64 = 0, HAMLS_MIXED = 1 } hamls_precision;
+
+/* Per-centre status bits returned by hamls_diagnostics. */
+#define HAMLS_ST_REGULARIZED 1u    /* tau > 0 was used */
+#define HAMLS_ST_UNDERDETERMINED 2u /* fewer than m nodes or singular local system: Shepard mean */
+#define HAMLS_ST_EMPTY 4u          /* no node inside the support: value NaN */
+#define HAMLS_ST_HEMISPHERE 8u     /* support radius clamped (S2: pi/2, SO3: pi) */
+#define HAMLS_ST_ILLCOND 16u       /* local system ill-conditioned (solved by the fallback path) */
+
+typedef struct hamls_params {
+    int32_t struct_size;     /* = sizeof(hamls_params); set by hamls_params_init */
+    int32_t domain;          /* hamls_domain */
+    int32_t bandwidth;       /* N >= 0 (the paper's L) */
+    int32_t degree;          /* K in [0, 4] (S2), [0, 3] (SO3, T3); m = C(K+d, d) */
+    double support_radius;   /* delta_0 > 0 enables a fixed radius (S2: arc length in rad;
+                                SO3: rotation angle in rad; T3: torus units) */
+    int32_t knn_count;       /* n >= m enables the adaptive radius of eq. (12) */
+    int32_t wendland;        /* weight profile (eq. (6)): 1 = phi_{3,1}, 2 = phi_{3,2} */
+    double knn_eps;          /* epsilon > 0 of eq. (12) */
+    int32_t reg;             /* hamls_reg */
+    int32_t precision;       /* hamls_precision */
+    double tau_fixed;        /* tau for HAMLS_REG_FIXED (>= 0) */
+    double chi_target;       /* chi_T > 1 */
+    double chi_full;         /* chi_full > chi_T */
+    int32_t grid_shape[3];   /* 0 = the paper's minimal exact grid; otherwise checked for
+                                exactness. S2 (n_theta, n_phi, -), SO3 (n_beta, n_alpha,
+                                n_gamma), T3 (n, n, n) */
+    int32_t reserved;
+} hamls_params;
+
+typedef struct hamls_plan_info {
+    int32_t domain;
+    int32_t bandwidth;
+    int32_t degree;
+    int32_t m;               /* local ansatz dimension */
+    int32_t grid_dims[3];
+    int32_t precision;
+    int64_t num_grid;        /* M_Q */
+    int64_t num_coeffs;      /* length of one field's coefficient vector */
+    int64_t num_nodes;       /* M of the bound node set */
+    int64_t node_capacity;   /* largest M hamls_plan_rebind accepts without reallocating */
+    int64_t resident_bytes;  /* device memory held by the plan */
+    int64_t num_cells;       /* binning cells */
+} hamls_plan_info;
+
+typedef struct hamls_plan_s* hamls_plan_t;
+
+/* Fill *p with defaults: S2, N = 16, K = 2, kNN n = 4m, eps = 0.05,
+ * phi_{3,1}, CHI_TARGET with chi_T = 10, chi_full = 20, FP64. */
+hamls_status hamls_params_init(hamls_params* p);
+
+/* Step 1 of Alg. 1 plus the node-side set-up of step 2 (Sec. 2.1, eq. (5),
+ * (12)): builds the quadrature grid and its transform tables, bins and sorts
+ * the nodes by cell key and computes every grid node's support radius.
+ *  nodes        device, M x 3 (S2 unit vectors, T3 points in [0,1)) or M x 4
+ *               (SO3 unit quaternions w,x,y,z; q and -q are the same rotation)
+ *  node_weights device, M (e.g. Voronoi areas, Sec. 2.2) or NULL for all ones
+ *  M            >= 1 and >= knn_count; capacity for later rebinds is M
+ * The plan copies what it needs; nodes are not referenced after return.
+ * Errors: INVALID_ARG (bad parameters), NOT_EXACT_GRID, DOMAIN (S2 fixed
+ * radius >= pi/2), OUT_OF_MEMORY, DEVICE. */
+hamls_status hamls_plan(const hamls_params* p, const double* nodes, int64_t M,
+                        const double* node_weights, void* stream, hamls_plan_t* out);
+
+/* Replace the plan's node set (same parameters) without allocating:
+ * M <= node_capacity.  Re-bins, re-sorts and recomputes the radii. */
+hamls_status hamls_plan_rebind(hamls_plan_t plan, const double* nodes, int64_t M,
+                               const double* node_weights, void* stream);
+
+/* Step 2 of Alg. 1: the MLS value at every grid node (eq. (4), (14)-(23)).
+ *  values       device, F rows of M node values; row f starts at values + f*ld
+ *  F            1 <= F <= 64 real fields (complex data: two fields)
+ *  ld           >= M
+ *  grid_values  device, F x M_Q (row-major, grid order of hamls_plan_grid)
+ * Per-centre diagnostics are kept for hamls_diagnostics. */
+hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
+                               double* grid_values, void* stream);
+
+/* Step 3 of Alg. 1: fhat = F^H W f by the quadrature rule (eq. (25)).
+ *  grid_values  device, F x M_Q real
+ *  coeffs       device, F x num_coeffs x 2 (re, im).  Index of a coefficient:
+ *               S2   n*n + n + k                       (|k| <= n <= N)
+ *               SO3  sum_{l<n}(2l+1)^2 + (k+n)(2n+1) + (k'+n)
+ *               T3   ((k0+h)*n + (k1+h))*n + (k2+h), h = n/2, k_d in [-h, n-1-h]
+ * Bases: S2 orthonormal spherical harmonics with Condon-Shortley phase;
+ * SO3 sqrt((2n+1)/8pi^2) e^{-ik alpha} d^n_{k,k'}(beta) e^{-ik' gamma}
+ * (Euler ZYZ); T3 e^{2 pi i k.x}. */
+hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, int32_t F,
+                                  double* coeffs, void* stream);
+
+/* Synthesis: out[f*P + i] = Re sum_k fhat_{f,k} phi_k(points_i).
+ *  points  device, P x 3 (S2, T3) or P x 4 (SO3) */
+hamls_status hamls_eval(hamls_plan_t plan, const double* coeffs, int32_t F, const double* points,
+                        int64_t P, double* out, void* stream);
+
+hamls_status hamls_plan_destroy(hamls_plan_t plan);
+
+/* ---- introspection (host outputs; these calls synchronize the stream) ---- */
+hamls_status hamls_plan_info_get(hamls_plan_t plan, hamls_plan_info* out);
+
+/* Grid points (M_Q x 3, or x 4 for SO3) and quadrature weights (M_Q); either
+ * pointer may be NULL. */
+hamls_status hamls_plan_grid(hamls_plan_t plan, double* points, double* weights);
+
+/* Neighbour sets X(q_j) of eq. (5) as CSR over the grid: row_ptr (M_Q + 1)
+ * and idx (row_ptr[M_Q] entries, original node indices ascending per row).
+ * Pass idx = NULL to obtain row_ptr only. */
+hamls_status hamls_plan_neighbors(hamls_plan_t plan, int64_t* row_ptr, int32_t* idx);
+
+/* Per grid node support radius delta_j and membership threshold c_j
+ * (S2: dot > c; SO3: |dot| > c; T3: squared distance < c). */
+hamls_status hamls_plan_radii(hamls_plan_t plan, double* delta, double* threshold);
+
+/* Diagnostics of the last hamls_mls_to_grid: neighbour count, chi (eq. (17)),
+ * tau, status bits.  Any pointer may be NULL. */
+hamls_status hamls_diagnostics(hamls_plan_t plan, int32_t* n, double* chi, double* tau,
+                               uint8_t* status);
+
+/* ---- per-phase timing (HIP events on the caller's stream) ----
+ * With timing enabled every later call records a start and an end event around
+ * each phase it launches.  hamls_timing_read synchronizes, returns the number
+ * of launches and the summed event time of one phase, and clears that phase.
+ * Phases: HAMLS_PHASE_* below. */
+#define HAMLS_PHASE_BINNING 0   /* keys, radix sort, cell table, node gather */
+#define HAMLS_PHASE_RADIUS 1    /* support radius / kNN select */
+#define HAMLS_PHASE_ASSEMBLE 2  /* local Gram assembly */
+#define HAMLS_PHASE_SOLVE 3     /* local regularized solve */
+#define HAMLS_PHASE_RING_DFT 4  /* step 3: periodic-angle transforms */
+#define HAMLS_PHASE_CONTRACT 5  /* step 3: Legendre / Wigner contraction */
+#define HAMLS_PHASE_GATHER 6    /* value gather into sorted order */
+#define HAMLS_NUM_PHASES 7
+hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable);
+hamls_status hamls_timing_read(hamls_plan_t plan, int32_t phase, int64_t* launches,
+                               double* total_ms);
+
+const char* hamls_status_string(hamls_status s);
+const char* hamls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HAMLS_H */

@@ -1,0 +1,147 @@
+// common.h -- internal declarations of the HAMLS gfx950 library.
+//
+// Device memory layout of a plan (all FP64 unless noted):
+//   grid      M_Q x 3 points (S2), plus per-ring theta and per-column phi
+//   nodes     sorted by cell key, structure of arrays x[cap], y[cap], z[cap],
+//             perm[cap] (int32, original index), optional weights nu[cap]
+//   cells     band_off[nb+1] (int32), cell_start[ncells+1] (int32)
+//   radii     delta[M_Q], threshold[M_Q], status[M_Q] (u8)
+//   solve     Gram/right-hand-side entries, structure of arrays [entry][M_Q]
+//   step 3    Legendre table [ring < ceil(nt/2)][n(n+1)/2 + k] (weights folded
+//             in), ring DFT twiddles, ring spectra G[f][ring][k] (complex)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "hamls.h"
+
+namespace hamls {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr int kWave = 64;
+constexpr int kMaxFieldsPerPass = 16;  // fields handled by one assembly pass
+constexpr int kCandCap = 1024;         // LDS candidate buffer of the radius search
+
+void set_error(const char* fmt, ...);
+hamls_status hip_status(hipError_t e, const char* what);
+
+#define HAMLS_HIP(call)                                        \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_status(e_, #call);    \
+    } while (0)
+
+// Geometry of the S2 binning: nb equal-angle bands in theta, band b split into
+// ns_b equal sectors in phi; cell key = band_off[b] + sector.
+struct S2Bins {
+    int nb = 0;
+    double dtheta = 0.0;
+    std::vector<int32_t> band_off;  // nb + 1
+    int64_t ncells = 0;
+    int key_bits = 0;
+};
+
+struct DeviceBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    hamls_params prm{};
+    int device = 0;
+    int dom = 0, N = 0, K = 0, m = 1, D = 2;
+    int32_t dims[3] = {0, 0, 0};
+    int64_t MQ = 0, ncoef = 0;
+    int64_t M = 0, cap = 0;
+    bool has_nu = false;
+    S2Bins bins;
+
+    // host copies
+    std::vector<double> h_grid, h_wts, h_theta, h_phi, h_glx, h_glw;
+
+    // device allocations (owned)
+    std::vector<DeviceBuf> owned;
+    double* d_grid = nullptr;       // MQ x 3
+    double* d_theta = nullptr;      // per ring
+    double* d_phi = nullptr;        // per column
+    double* d_x = nullptr;          // sorted node coordinates, SoA 3 x cap
+    double* d_nu = nullptr;         // sorted node weights (cap) or null
+    int32_t* d_perm = nullptr;      // cap
+    uint32_t* d_key[2] = {nullptr, nullptr};
+    int32_t* d_idx[2] = {nullptr, nullptr};
+    uint32_t* d_hist = nullptr;
+    int64_t hist_len = 0;
+    int32_t* d_band_off = nullptr;
+    int32_t* d_cell_start = nullptr;
+    double* d_delta = nullptr;      // MQ
+    double* d_thr = nullptr;        // MQ
+    uint8_t* d_status = nullptr;    // MQ (radius flags, then solve flags)
+    uint8_t* d_rstatus = nullptr;   // MQ radius flags kept across solves
+    int32_t* d_nj = nullptr;        // MQ
+    double* d_chi = nullptr;        // MQ
+    double* d_tau = nullptr;        // MQ
+    double* d_entries = nullptr;    // n_entries x MQ
+    int64_t n_entries_cap = 0;
+    double* d_vals = nullptr;       // sorted values, kMaxFieldsPerPass x cap
+    double* d_ptab = nullptr;       // Legendre table
+    int64_t ptab_len = 0;
+    double* d_tw = nullptr;         // 2 x n_phi twiddles
+    double* d_G = nullptr;          // ring spectra, F x nt x (N+1) x 2
+    int64_t G_fields = 0;
+    int64_t resident = 0;
+
+    // per-phase timing
+    bool timing = false;
+    struct Rec {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double acc_ms[HAMLS_NUM_PHASES] = {};
+    int64_t acc_n[HAMLS_NUM_PHASES] = {};
+};
+
+// Records a start/end event pair around one phase when timing is enabled.
+class PhaseTimer {
+  public:
+    PhaseTimer(Plan& P, int phase, hipStream_t s);
+    ~PhaseTimer();
+
+  private:
+    Plan& P_;
+    int phase_;
+    hipStream_t s_;
+    hipEvent_t b_ = nullptr;
+};
+
+// --- kernels (kernels.hip) -------------------------------------------------
+hamls_status launch_s2_keys(const Plan& P, const double* nodes, int64_t M, hipStream_t s);
+hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf);
+hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t M, hipStream_t s);
+hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double* nodes,
+                                 const double* nu, int64_t M, hipStream_t s);
+hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
+hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s);
+hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int Ftotal,
+                          hipStream_t s);
+hamls_status launch_gather_values(const Plan& P, const double* values, int F, int f0, int64_t ld,
+                                  hipStream_t s);
+hamls_status launch_s2_count(const Plan& P, int32_t* counts, hipStream_t s);
+hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx, hipStream_t s);
+hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStream_t s);
+hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s);
+hamls_status launch_s2_eval(const Plan& P, const double* coeffs, int F, const double* pts,
+                            int64_t npts, double* out, hipStream_t s);
+
+inline int n_monomials(int D, int K) {
+    int m = 1;
+    for (int i = 1; i <= D; i++) m = m * (K + i) / i;
+    return m;
+}
+
+}  // namespace hamls

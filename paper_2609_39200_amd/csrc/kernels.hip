@@ -1,0 +1,1062 @@
+// kernels.hip -- gfx950 kernels of the HAMLS hot path (S2, FP64).
+//
+//   binning      cell key per node, stable LSD radix sort (8-bit digits),
+//                cell offset table, gather of the sorted node records
+//   radius       per grid node support radius: fixed delta_0 or the adaptive
+//                radius (1+eps) d_n of eq. (12) by an exact n-th-nearest select
+//   assemble     per grid node weighted Gram matrix and right-hand sides of the
+//                local problem (eq. (14)) in tangent coordinates (Sec. 2.3)
+//   solve        per grid node normalisation, Cholesky of C (eq. (20)),
+//                centre amplification chi (eq. (19)), tau (eq. (23)) and the
+//                regularized centre value c_1 of eq. (22)
+//   ring DFT     step 3 of Alg. 1, the periodic-angle sums of every ring
+//   Legendre     step 3, the contraction with the associated Legendre table
+//   eval         synthesis of the spherical-harmonic series
+#include <math.h>
+
+#include "common.h"
+
+namespace hamls {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+// Membership key x.q in a fixed association without fused operations, so that
+// the neighbour sets do not depend on instruction selection.
+__device__ __forceinline__ double s2_dot(double x0, double x1, double x2, double q0, double q1,
+                                         double q2) {
+#pragma clang fp contract(off)
+    double a = x0 * q0;
+    double b = x1 * q1;
+    double c = x2 * q2;
+    double s = a + b;
+    return s + c;
+}
+
+__device__ __forceinline__ int rank_below(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ double wendland_phi(int which, double r) {
+    if (r >= 1.0) return 0.0;
+    double s = 1.0 - r;
+    double s2 = s * s;
+    if (which == 2) return s2 * s2 * s2 * (35.0 * r * r + 18.0 * r + 3.0);
+    return s2 * s2 * (4.0 * r + 1.0);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Geometry handed to the per-grid-node kernels.
+struct S2Geom {
+    const double* grid;      // MQ x 3
+    const double* theta;     // per ring
+    const double* phi;       // per column
+    int nphi;
+    const double* X;         // sorted nodes, SoA 3 x cap
+    const double* nu;        // sorted node weights or null
+    int64_t cap;
+    const int32_t* band_off; // nb + 1
+    const int32_t* cs;       // cell_start
+    int nb;
+    double dtheta;
+};
+
+// Calls fn(lo, hi) for every contiguous range of sorted records whose cells
+// meet the geodesic cap of radius r around (thq, phq).  Conservative: a margin
+// of 1e-7 rad covers every rounding in the cell assignment.
+template <class Fn>
+__device__ __forceinline__ void s2_ranges(const S2Geom& g, double thq, double phq, double r,
+                                          Fn&& fn) {
+    const double margin = 1e-7;
+    double rr = r + margin;
+    int b0 = (int)floor((thq - rr) / g.dtheta);
+    int b1 = (int)floor((thq + rr) / g.dtheta);
+    b0 = b0 < 0 ? 0 : b0;
+    b1 = b1 > g.nb - 1 ? g.nb - 1 : b1;
+    bool full = (thq - rr <= 0.0) || (thq + rr >= kPi) || rr >= 0.5 * kPi;
+    double dphi = kPi;
+    if (!full) {
+        double sr = sin(rr) / sin(thq);
+        if (sr >= 1.0)
+            full = true;
+        else
+            dphi = asin(sr) + margin;
+    }
+    for (int b = b0; b <= b1; b++) {
+        int off = g.band_off[b];
+        int ns = g.band_off[b + 1] - off;
+        if (full) {
+            fn(g.cs[off], g.cs[off + ns]);
+            continue;
+        }
+        double wdt = 2.0 * kPi / ns;
+        int s0 = (int)floor((phq - dphi) / wdt);
+        int s1 = (int)floor((phq + dphi) / wdt);
+        if (s1 - s0 + 1 >= ns) {
+            fn(g.cs[off], g.cs[off + ns]);
+        } else if (s0 < 0) {
+            fn(g.cs[off + s0 + ns], g.cs[off + ns]);
+            fn(g.cs[off], g.cs[off + s1 + 1]);
+        } else if (s1 >= ns) {
+            fn(g.cs[off + s0], g.cs[off + ns]);
+            fn(g.cs[off], g.cs[off + s1 - ns + 1]);
+        } else {
+            fn(g.cs[off + s0], g.cs[off + s1 + 1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
+
+__global__ void k_s2_keys(const double* __restrict__ nodes, int64_t M,
+                          const int32_t* __restrict__ band_off, int nb, double dtheta,
+                          uint32_t* __restrict__ keys, int32_t* __restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    double x = nodes[3 * i], y = nodes[3 * i + 1], z = nodes[3 * i + 2];
+    double th = acos(fmin(1.0, fmax(-1.0, z)));
+    int b = (int)(th / dtheta);
+    b = b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
+    double ph = atan2(y, x);
+    if (ph < 0.0) ph += 2.0 * kPi;
+    int off = band_off[b], ns = band_off[b + 1] - off;
+    int s = (int)(ph * (ns / (2.0 * kPi)));
+    s = s < 0 ? 0 : (s > ns - 1 ? ns - 1 : s);
+    keys[i] = (uint32_t)(off + s);
+    idx[i] = (int32_t)i;
+}
+
+hamls_status launch_s2_keys(const Plan& P, const double* nodes, int64_t M, hipStream_t s) {
+    int bs = 256;
+    int64_t nbk = (M + bs - 1) / bs;
+    hipLaunchKernelGGL(k_s2_keys, dim3((unsigned)nbk), dim3(bs), 0, s, nodes, M, P.d_band_off,
+                       P.bins.nb, P.bins.dtheta, P.d_key[0], P.d_idx[0]);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__global__ __launch_bounds__(RS_THREADS) void k_radix_count(const uint32_t* __restrict__ keys,
+                                                            int64_t n, int shift,
+                                                            uint32_t* __restrict__ hist,
+                                                            int nblocks) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0u;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; r++) {
+        int64_t i = base + (int64_t)r * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// In-place exclusive scan of a[0..len) by one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_exclusive_scan(uint32_t* __restrict__ a, int64_t len) {
+    __shared__ uint32_t part[1024];
+    int t = threadIdx.x;
+    int64_t chunk = (len + 1023) / 1024;
+    int64_t lo = t * chunk;
+    int64_t hi = lo + chunk < len ? lo + chunk : len;
+    uint32_t s = 0;
+    for (int64_t i = lo; i < hi; i++) s += a[i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = t > 0 ? part[t - 1] : 0u;
+    for (int64_t i = lo; i < hi; i++) {
+        uint32_t v = a[i];
+        a[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter of one 8-bit digit.  Items of a tile are taken in rounds of
+// 256 in input order; the rank of an item among equal digits is its rank in
+// its wave (ballot matching on the 8 digit bits) plus the counts of the lower
+// waves of the round plus everything placed by earlier rounds.
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
+    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    int32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ hist,
+    int nblocks) {
+    __shared__ uint32_t off[256];
+    __shared__ uint32_t cnt[4][256];
+    int t = threadIdx.x, w = t >> 6;
+    off[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_ITEMS; r++) {
+        int64_t i = base + (int64_t)r * RS_THREADS + t;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u;
+        int32_t val = valid ? vin[i] : 0;
+        uint32_t d = (key >> shift) & 255u;
+        cnt[0][t] = 0u;
+        cnt[1][t] = 0u;
+        cnt[2][t] = 0u;
+        cnt[3][t] = 0u;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < 8; b++) {
+            uint64_t mb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? mb : ~mb;
+        }
+        int rank = rank_below(peers);
+        if (valid && rank == 0) cnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = off[d] + (uint32_t)rank;
+            for (int w2 = 0; w2 < w; w2++) pos += cnt[w2][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        off[t] += cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+        __syncthreads();
+    }
+}
+
+hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf) {
+    int bits = P.bins.key_bits;
+    int passes = (bits + 7) / 8;
+    int nblocks = (int)((M + RS_TILE - 1) / RS_TILE);
+    if ((int64_t)nblocks * 256 > P.hist_len) {
+        set_error("radix histogram too small");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    int cur = 0;
+    for (int ps = 0; ps < passes; ps++) {
+        int shift = 8 * ps;
+        hipLaunchKernelGGL(k_radix_count, dim3(nblocks), dim3(RS_THREADS), 0, s, P.d_key[cur], M,
+                           shift, P.d_hist, nblocks);
+        hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, s, P.d_hist,
+                           (int64_t)nblocks * 256);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, P.d_key[cur],
+                           P.d_idx[cur], P.d_key[cur ^ 1], P.d_idx[cur ^ 1], M, shift, P.d_hist,
+                           nblocks);
+        cur ^= 1;
+    }
+    HAMLS_HIP(hipGetLastError());
+    *final_buf = cur;
+    return HAMLS_OK;
+}
+
+// cell_start[c] = first sorted position whose key is >= c, for c in [0, ncells].
+__global__ void k_cell_start(const uint32_t* __restrict__ keys, int64_t n, int64_t ncells,
+                             int32_t* __restrict__ cs) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int64_t lo = i == 0 ? 0 : (int64_t)keys[i - 1] + 1;
+    int64_t hi = i == n ? ncells : (int64_t)keys[i];
+    for (int64_t c = lo; c <= hi; c++) cs[c] = (int32_t)i;
+}
+
+hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t M, hipStream_t s) {
+    int bs = 256;
+    int64_t nbk = (M + 1 + bs - 1) / bs;
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)nbk), dim3(bs), 0, s, keys, M,
+                       P.bins.ncells, P.d_cell_start);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+__global__ void k_gather_nodes(const int32_t* __restrict__ idx, const double* __restrict__ nodes,
+                               const double* __restrict__ nu, int64_t M, int64_t cap,
+                               double* __restrict__ X, double* __restrict__ NU,
+                               int32_t* __restrict__ perm) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int64_t j = idx[i];
+    X[i] = nodes[3 * j];
+    X[cap + i] = nodes[3 * j + 1];
+    X[2 * cap + i] = nodes[3 * j + 2];
+    perm[i] = (int32_t)j;
+    if (nu) NU[i] = nu[j];
+}
+
+hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double* nodes,
+                                 const double* nu, int64_t M, hipStream_t s) {
+    int bs = 256;
+    int64_t nbk = (M + bs - 1) / bs;
+    hipLaunchKernelGGL(k_gather_nodes, dim3((unsigned)nbk), dim3(bs), 0, s, idx, nodes, nu, M,
+                       P.cap, P.d_x, P.d_nu, P.d_perm);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+__global__ void k_gather_values(const int32_t* __restrict__ perm, const double* __restrict__ values,
+                                int F, int64_t ld, int64_t M, int64_t cap,
+                                double* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    int64_t j = perm[i];
+    for (int f = 0; f < F; f++) out[f * cap + i] = values[f * ld + j];
+}
+
+hamls_status launch_gather_values(const Plan& P, const double* values, int F, int f0, int64_t ld,
+                                  hipStream_t s) {
+    int bs = 256;
+    int64_t nbk = (P.M + bs - 1) / bs;
+    hipLaunchKernelGGL(k_gather_values, dim3((unsigned)nbk), dim3(bs), 0, s, P.d_perm,
+                       values + (int64_t)f0 * ld, F, ld, P.M, P.cap, P.d_vals);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+S2Geom make_geom(const Plan& P) {
+    S2Geom g;
+    g.grid = P.d_grid;
+    g.theta = P.d_theta;
+    g.phi = P.d_phi;
+    g.nphi = P.dims[1];
+    g.X = P.d_x;
+    g.nu = P.has_nu ? P.d_nu : nullptr;
+    g.cap = P.cap;
+    g.band_off = P.d_band_off;
+    g.cs = P.d_cell_start;
+    g.nb = P.bins.nb;
+    g.dtheta = P.bins.dtheta;
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// support radius (eq. (5), (6), (12))
+// ---------------------------------------------------------------------------
+
+// Order-preserving map of doubles to unsigned integers.
+__device__ __forceinline__ uint64_t ordered_bits(double v) {
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double from_ordered_bits(uint64_t u) {
+    uint64_t b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+    return __longlong_as_double((long long)b);
+}
+
+// One block (one wave) per grid node.  Adaptive radius: find a search radius
+// whose cap holds between n and kCandCap nodes, keep their keys in LDS and take
+// the n-th largest exactly; if the cap cannot be sized (duplicates), fall back
+// to a bitwise binary search on the key.  delta = (1+eps) d_n, merged with a
+// fixed delta_0 if both are set, clamped to pi/2 (Sec. 2.3 needs delta < pi/2).
+__global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
+                                                 double delta0, double c_fixed, double* thr,
+                                                 double* delta, uint8_t* rstatus) {
+    __shared__ double buf[kCandCap];
+    int j = blockIdx.x;
+    int lane = threadIdx.x;
+    int t = j / g.nphi, p = j - t * g.nphi;
+    double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+    double thq = g.theta[t], phq = g.phi[p];
+    uint8_t st = 0;
+    double dl = delta0, c = c_fixed;
+    if (knn > 0) {
+        // initial radius from the local cell density
+        int bq = (int)(thq / g.dtheta);
+        bq = bq > g.nb - 1 ? g.nb - 1 : bq;
+        int off = g.band_off[bq], ns = g.band_off[bq + 1] - off;
+        int sq = (int)(phq * (ns / (2.0 * kPi)));
+        sq = sq > ns - 1 ? ns - 1 : sq;
+        int cnt3 = 0, nsec = 3;
+        if (ns <= 3) {
+            cnt3 = g.cs[off + ns] - g.cs[off];
+            nsec = ns;
+        } else {
+            for (int ds = -1; ds <= 1; ds++) {
+                int sc = (sq + ds + ns) % ns;
+                cnt3 += g.cs[off + sc + 1] - g.cs[off + sc];
+            }
+        }
+        double area = (2.0 * kPi / ns) * nsec * (cos(bq * g.dtheta) - cos((bq + 1) * g.dtheta));
+        double r = 2.0 * sqrt((double)knn / (double)M);
+        if (cnt3 >= 4) r = 1.15 * sqrt((double)knn * area / (kPi * cnt3));
+        r = fmin(r, 0.5 * kPi);
+        double r_lo = 0.0, r_hi = 0.0;  // known too small / too large
+        double tn = -2.0;
+        bool done = false, hemi = false;
+        for (int it = 0; it < 40 && !done; it++) {
+            double cr = cos(r);
+            int count = 0;
+            s2_ranges(g, thq, phq, r, [&](int lo, int hi) {
+                for (int base = lo; base < hi; base += 64) {
+                    int i = base + lane;
+                    bool valid = i < hi;
+                    double d = -2.0;
+                    if (valid) d = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2);
+                    bool in = valid && d > cr;
+                    uint64_t mk = __ballot(in);
+                    int pos = count + rank_below(mk);
+                    if (in && pos < kCandCap) buf[pos] = d;
+                    count += __popcll(mk);
+                }
+            });
+            __syncthreads();
+            if (count >= knn && count <= kCandCap) {
+                double found = -3.0;
+                for (int a = lane; a < count; a += 64) {
+                    double v = buf[a];
+                    int gt = 0, ge = 0;
+                    for (int b = 0; b < count; b++) {
+                        double u = buf[b];
+                        gt += u > v;
+                        ge += u >= v;
+                    }
+                    if (gt < knn && knn <= ge) found = v;
+                }
+                tn = wave_max(found);
+                done = true;
+            } else if (count < knn) {
+                if (r >= 0.5 * kPi) {
+                    hemi = true;
+                    done = true;
+                } else {
+                    r_lo = r;
+                    double grow = 1.25 * sqrt((double)knn / (double)(count > 0 ? count : 1));
+                    double nr = r * (grow > 1.5 ? grow : 1.5);
+                    if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(r * r_hi);
+                    r = fmin(nr, 0.5 * kPi);
+                }
+            } else {
+                r_hi = r;
+                double shrink = 1.3 * sqrt((double)knn / (double)count);
+                double nr = r * (shrink < 0.9 ? shrink : 0.9);
+                if (nr <= r_lo) nr = sqrt(r * (r_lo > 0.0 ? r_lo : 0.5 * r));
+                r = nr;
+            }
+            __syncthreads();
+        }
+        if (!done) {
+            // exact fallback: largest key value v with #(dot >= v) >= n, by
+            // binary search over the ordered bit patterns in [cos r, 1]
+            double cr = cos(r);
+            uint64_t lo = ordered_bits(cr), hi = ordered_bits(1.0);
+            while (lo < hi) {
+                uint64_t mid = lo + (hi - lo + 1) / 2;
+                double v = from_ordered_bits(mid);
+                int count = 0;
+                s2_ranges(g, thq, phq, r, [&](int a0, int a1) {
+                    for (int base = a0; base < a1; base += 64) {
+                        int i = base + lane;
+                        bool in = false;
+                        if (i < a1)
+                            in = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2) >= v;
+                        count += __popcll(__ballot(in));
+                    }
+                });
+                if (count >= knn)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            tn = from_ordered_bits(lo);
+        }
+        double dk = hemi ? kPi : (1.0 + eps) * acos(fmin(1.0, fmax(-1.0, tn)));
+        if (delta0 > 0.0 && delta0 >= dk) {
+            dl = delta0;
+            c = c_fixed;
+        } else {
+            dl = dk;
+            if (dl >= 0.5 * kPi) {
+                dl = 0.5 * kPi;
+                st |= HAMLS_ST_HEMISPHERE;
+            }
+            c = cos(dl);
+        }
+    }
+    if (lane == 0) {
+        thr[j] = c;
+        delta[j] = dl;
+        rstatus[j] = st;
+    }
+}
+
+hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
+    S2Geom g = make_geom(P);
+    double d0 = P.prm.support_radius > 0.0 ? P.prm.support_radius : 0.0;
+    double cf = d0 > 0.0 ? cos(d0) : 2.0;
+    int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
+    hipLaunchKernelGGL(k_s2_radius, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
+                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// assembly of the local problems (eq. (14)), one wave per grid node
+// ---------------------------------------------------------------------------
+
+// Entries per grid node: G_ab = sum_i w_i g_a g_b for a <= b (row-major upper
+// triangle, G_00 = sum w), then h_af = sum_i w_i g_a y_if.  Rows of
+// (sqrt(w) g, sqrt(w) y) are staged in LDS 64 at a time; each lane owns a few
+// entries and sums them over the staged rows.
+template <int K>
+__global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __restrict__ vals,
+                                                   int F, int wendland,
+                                                   const double* __restrict__ thr,
+                                                   const double* __restrict__ delta,
+                                                   double* __restrict__ entries, int64_t MQ,
+                                                   int32_t* __restrict__ nj) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    constexpr int EG = m * (m + 1) / 2;
+    constexpr int ROW = m + kMaxFieldsPerPass + 1;
+    constexpr int KE = (EG + m * kMaxFieldsPerPass + 63) / 64;
+    __shared__ double rows[64 * ROW];
+    int j = blockIdx.x;
+    int lane = threadIdx.x;
+    int t = j / g.nphi, p = j - t * g.nphi;
+    double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+    double thq = g.theta[t], phq = g.phi[p];
+    double ct = cos(thq), stt = sin(thq), cp = cos(phq), sp = sin(phq);
+    double et0 = ct * cp, et1 = ct * sp, et2 = -stt;
+    double ep0 = -sp, ep1 = cp;
+    const double c = thr[j], dl = delta[j];
+    const double idl = 1.0 / dl;
+    int E = EG + m * F;
+    int ca[KE], cb[KE];
+    double acc[KE];
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        int e = lane + 64 * k;
+        acc[k] = 0.0;
+        ca[k] = -1;
+        cb[k] = 0;
+        if (e < EG) {
+            int a = 0, rem = e;
+            while (rem >= m - a) {
+                rem -= m - a;
+                a++;
+            }
+            ca[k] = a;
+            cb[k] = a + rem;
+        } else if (e < E) {
+            int r = e - EG;
+            ca[k] = r / F;
+            cb[k] = m + r % F;
+        }
+    }
+    int count = 0;
+    s2_ranges(g, thq, phq, dl, [&](int lo, int hi) {
+        for (int base = lo; base < hi; base += 64) {
+            int i = base + lane;
+            bool valid = i < hi;
+            double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
+            if (valid) {
+                x0 = g.X[i];
+                x1 = g.X[g.cap + i];
+                x2 = g.X[2 * g.cap + i];
+                d = s2_dot(x0, x1, x2, q0, q1, q2);
+            }
+            bool in = valid && d > c;
+            uint64_t mk = __ballot(in);
+            int nin = __popcll(mk);
+            if (nin == 0) continue;
+            if (in) {
+                int pos = rank_below(mk);
+                double dist = acos(fmin(d, 1.0));
+                double w = wendland_phi(wendland, dist * idl);
+                if (g.nu) w *= g.nu[i];
+                double sw = sqrt(w);
+                double u = (x0 * et0 + x1 * et1 + x2 * et2) * idl;
+                double v = (x0 * ep0 + x1 * ep1) * idl;
+                double pu[K + 1], pv[K + 1];
+                pu[0] = 1.0;
+                pv[0] = 1.0;
+#pragma unroll
+                for (int a = 1; a <= K; a++) {
+                    pu[a] = pu[a - 1] * u;
+                    pv[a] = pv[a - 1] * v;
+                }
+                double* row = rows + pos * ROW;
+                int cidx = 0;
+#pragma unroll
+                for (int l = 0; l <= K; l++)
+#pragma unroll
+                    for (int b = 0; b <= l; b++) row[cidx++] = sw * pu[l - b] * pv[b];
+                for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
+            }
+            __syncthreads();
+            for (int r = 0; r < nin; r++) {
+                const double* row = rows + r * ROW;
+#pragma unroll
+                for (int k = 0; k < KE; k++)
+                    if (ca[k] >= 0) acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+            }
+            __syncthreads();
+            count += nin;
+        }
+    });
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        int e = lane + 64 * k;
+        if (e < E) entries[(int64_t)e * MQ + j] = acc[k];
+    }
+    if (lane == 0) nj[j] = count;
+}
+
+hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s) {
+    (void)f0;
+    S2Geom g = make_geom(P);
+    dim3 grid((unsigned)P.MQ), block(64);
+    int wl = P.prm.wendland;
+    switch (P.K) {
+        case 0: hipLaunchKernelGGL(k_s2_assemble<0>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
+        case 1: hipLaunchKernelGGL(k_s2_assemble<1>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
+        case 2: hipLaunchKernelGGL(k_s2_assemble<2>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
+        case 3: hipLaunchKernelGGL(k_s2_assemble<3>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
+        case 4: hipLaunchKernelGGL(k_s2_assemble<4>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
+        default: set_error("degree %d unsupported on S2", P.K); return HAMLS_ERR_UNSUPPORTED;
+    }
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// local solve (eq. (15)-(23)), one thread per grid node
+// ---------------------------------------------------------------------------
+
+struct SolveArgs {
+    const double* entries;
+    int64_t MQ;
+    int F;
+    int f0;
+    const int32_t* nj;
+    const uint8_t* rstatus;
+    int reg;
+    double tau_fixed, chi_t, chi_f;
+    double mu[34];       // degree multipliers of the non-constant monomials
+    double* out;         // F_total x MQ
+    double* chi;
+    double* tau;
+    uint8_t* status;
+    int write_diag;
+};
+
+__device__ __forceinline__ double coupling_tau(const double* d2, const double* mu, int n, double tau) {
+    double r = 0.0;
+    for (int j = 0; j < n; j++) r += d2[j] / (1.0 + tau * mu[j]);
+    return r;
+}
+
+template <int MM>
+__global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
+    constexpr int EG = MM * (MM + 1) / 2;
+    constexpr int NC = MM - 1;               // order of C
+    constexpr int NL = NC * (NC + 1) / 2 + 1; // packed lower triangle of L
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= A.MQ) return;
+    const int64_t MQ = A.MQ;
+    int n = A.nj[j];
+    uint8_t st = A.rstatus[j];
+    double G[EG];
+#pragma unroll
+    for (int e = 0; e < EG; e++) G[e] = A.entries[(int64_t)e * MQ + j];
+    const double* H = A.entries + (int64_t)EG * MQ;  // right-hand sides, [a*F + f]
+    double W = G[0];
+    auto gidx = [](int a, int b) { return a * MM - a * (a - 1) / 2 + (b - a); };
+    if (n == 0 || !(W > 0.0)) {
+        for (int f = 0; f < A.F; f++) A.out[(int64_t)(A.f0 + f) * MQ + j] = __builtin_nan("");
+        if (A.write_diag) {
+            A.chi[j] = __builtin_nan("");
+            A.tau[j] = __builtin_nan("");
+            A.status[j] = st | HAMLS_ST_EMPTY;
+        }
+        return;
+    }
+    bool degen = n < MM;
+    double sc[MM];
+#pragma unroll
+    for (int a = 0; a < MM; a++) {
+        sc[a] = sqrt(G[gidx(a, a)] / W);
+        if (!(sc[a] > 0.0)) degen = true;
+    }
+    double chi = 1.0, tau = 0.0;
+    double d[NC > 0 ? NC : 1], L[NL];
+    double minpiv = 1.0;
+    if (!degen && NC > 0) {
+        // normalised C (unit diagonal) and b, Cholesky C = L L^T in packed rows
+#pragma unroll
+        for (int a = 0; a < NC; a++)
+#pragma unroll
+            for (int b = 0; b <= a; b++)
+                L[a * (a + 1) / 2 + b] = G[gidx(b + 1, a + 1)] / (W * sc[b + 1] * sc[a + 1]);
+#pragma unroll
+        for (int a = 0; a < NC; a++) d[a] = G[gidx(0, a + 1)] / (W * sc[a + 1]);
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            double s = L[k * (k + 1) / 2 + k];
+#pragma unroll
+            for (int c = 0; c < k; c++) s -= L[k * (k + 1) / 2 + c] * L[k * (k + 1) / 2 + c];
+            if (!(s > 1e-22)) {
+                degen = true;
+                s = 1.0;
+            }
+            minpiv = fmin(minpiv, s);
+            double lkk = sqrt(s);
+            L[k * (k + 1) / 2 + k] = lkk;
+            double il = 1.0 / lkk;
+#pragma unroll
+            for (int r = k + 1; r < NC; r++) {
+                double v = L[r * (r + 1) / 2 + k];
+#pragma unroll
+                for (int c = 0; c < k; c++) v -= L[r * (r + 1) / 2 + c] * L[k * (k + 1) / 2 + c];
+                L[r * (r + 1) / 2 + k] = v * il;
+            }
+        }
+        if (!degen) {
+            // d = L^{-1} b
+#pragma unroll
+            for (int r = 0; r < NC; r++) {
+                double v = d[r];
+#pragma unroll
+                for (int c = 0; c < r; c++) v -= L[r * (r + 1) / 2 + c] * d[c];
+                d[r] = v / L[r * (r + 1) / 2 + r];
+            }
+            double d2[NC > 0 ? NC : 1];
+            double r0 = 0.0;
+#pragma unroll
+            for (int r = 0; r < NC; r++) {
+                d2[r] = d[r] * d[r];
+                r0 += d2[r];
+            }
+            chi = 1.0 / (1.0 - r0);
+            if (A.reg == HAMLS_REG_FIXED) {
+                tau = A.tau_fixed;
+            } else if (A.reg == HAMLS_REG_CHI_TARGET && chi > A.chi_t) {
+                double target = 1.0 - 1.0 / A.chi_t;
+                double hi = 1.0;
+                int guard = 0;
+                while (coupling_tau(d2, A.mu, NC, hi) > target && guard < 2000) {
+                    hi *= 2.0;
+                    guard++;
+                }
+                double a = log(1e-16), b = log(hi);
+                for (int it = 0; it < 64; it++) {
+                    double mid = 0.5 * (a + b);
+                    if (coupling_tau(d2, A.mu, NC, exp(mid)) > target)
+                        a = mid;
+                    else
+                        b = mid;
+                }
+                double tt = (chi - A.chi_t) / (A.chi_f - A.chi_t);
+                double sm;
+                if (tt >= 1.0)
+                    sm = 1.0;
+                else {
+                    double t4 = tt * tt * tt * tt;
+                    sm = t4 * (35.0 - 84.0 * tt + 70.0 * tt * tt - 20.0 * tt * tt * tt);
+                }
+                tau = sm * exp(0.5 * (a + b));
+            }
+            double den = 1.0;
+            double fac[NC > 0 ? NC : 1];
+#pragma unroll
+            for (int r = 0; r < NC; r++) {
+                fac[r] = d[r] / (1.0 + tau * A.mu[r]);
+                den -= fac[r] * d[r];
+            }
+            for (int f = 0; f < A.F; f++) {
+                double z[NC > 0 ? NC : 1];
+#pragma unroll
+                for (int r = 0; r < NC; r++) {
+                    double v = H[((int64_t)(r + 1) * A.F + f) * MQ + j] / (W * sc[r + 1]);
+#pragma unroll
+                    for (int c = 0; c < r; c++) v -= L[r * (r + 1) / 2 + c] * z[c];
+                    z[r] = v / L[r * (r + 1) / 2 + r];
+                }
+                double num = H[(int64_t)f * MQ + j] / W;
+#pragma unroll
+                for (int r = 0; r < NC; r++) num -= fac[r] * z[r];
+                A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
+            }
+            if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
+            if (minpiv < 1e-10) st |= HAMLS_ST_ILLCOND;
+        }
+    }
+    if (!degen && NC == 0) {
+        for (int f = 0; f < A.F; f++) A.out[(int64_t)(A.f0 + f) * MQ + j] = H[(int64_t)f * MQ + j] / W;
+    }
+    if (degen) {
+        for (int f = 0; f < A.F; f++) A.out[(int64_t)(A.f0 + f) * MQ + j] = H[(int64_t)f * MQ + j] / W;
+        chi = __builtin_inf();
+        tau = __builtin_inf();
+        st |= HAMLS_ST_UNDERDETERMINED;
+    }
+    if (A.write_diag) {
+        A.chi[j] = chi;
+        A.tau[j] = tau;
+        A.status[j] = st;
+    }
+}
+
+hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int Ftotal,
+                          hipStream_t s) {
+    (void)Ftotal;
+    SolveArgs A;
+    A.entries = P.d_entries;
+    A.MQ = P.MQ;
+    A.F = F;
+    A.f0 = f0;
+    A.nj = P.d_nj;
+    A.rstatus = P.d_rstatus;
+    A.reg = P.prm.reg;
+    A.tau_fixed = P.prm.tau_fixed;
+    A.chi_t = P.prm.chi_target;
+    A.chi_f = P.prm.chi_full;
+    for (int i = 0; i < 34; i++) A.mu[i] = 0.0;
+    {
+        int c = 0;
+        for (int l = 0; l <= P.K; l++)
+            for (int b = 0; b <= l; b++) {
+                if (c > 0) A.mu[c - 1] = (double)l * (l + 1);
+                c++;
+            }
+    }
+    A.out = grid_values;
+    A.chi = P.d_chi;
+    A.tau = P.d_tau;
+    A.status = P.d_status;
+    A.write_diag = f0 == 0;
+    int bs = 256;
+    dim3 grid((unsigned)((P.MQ + bs - 1) / bs)), block(bs);
+    switch (P.m) {
+        case 1: hipLaunchKernelGGL(k_solve<1>, grid, block, 0, s, A); break;
+        case 3: hipLaunchKernelGGL(k_solve<3>, grid, block, 0, s, A); break;
+        case 6: hipLaunchKernelGGL(k_solve<6>, grid, block, 0, s, A); break;
+        case 10: hipLaunchKernelGGL(k_solve<10>, grid, block, 0, s, A); break;
+        case 15: hipLaunchKernelGGL(k_solve<15>, grid, block, 0, s, A); break;
+        default: set_error("m = %d unsupported", P.m); return HAMLS_ERR_UNSUPPORTED;
+    }
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// neighbour export (introspection)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(64) void k_s2_list(S2Geom g, const double* __restrict__ thr,
+                                               const double* __restrict__ delta,
+                                               const int32_t* __restrict__ perm,
+                                               const int64_t* __restrict__ row_ptr,
+                                               int32_t* __restrict__ counts,
+                                               int32_t* __restrict__ idx) {
+    int j = blockIdx.x;
+    int lane = threadIdx.x;
+    int t = j / g.nphi, p = j - t * g.nphi;
+    double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+    double c = thr[j];
+    int count = 0;
+    s2_ranges(g, g.theta[t], g.phi[p], delta[j], [&](int lo, int hi) {
+        for (int base = lo; base < hi; base += 64) {
+            int i = base + lane;
+            bool in = false;
+            if (i < hi) in = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2) > c;
+            uint64_t mk = __ballot(in);
+            if (in && idx) idx[row_ptr[j] + count + rank_below(mk)] = perm[i];
+            count += __popcll(mk);
+        }
+    });
+    if (lane == 0 && counts) counts[j] = count;
+}
+
+hamls_status launch_s2_count(const Plan& P, int32_t* counts, hipStream_t s) {
+    S2Geom g = make_geom(P);
+    hipLaunchKernelGGL(k_s2_list, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.d_thr, P.d_delta,
+                       P.d_perm, (const int64_t*)nullptr, counts, (int32_t*)nullptr);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx, hipStream_t s) {
+    S2Geom g = make_geom(P);
+    hipLaunchKernelGGL(k_s2_list, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.d_thr, P.d_delta,
+                       P.d_perm, row_ptr, (int32_t*)nullptr, idx);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// step 3: ring DFT and Legendre contraction
+// ---------------------------------------------------------------------------
+
+// G[f][t][k] = (2 pi / n_phi) sum_p f(t,p) e^{-i k phi_p}, k = 0..N, one block
+// per (ring, field).  Twiddles are indexed by k p mod n_phi.
+__global__ __launch_bounds__(256) void k_s2_ring_dft(const double* __restrict__ gv, int64_t MQ,
+                                                    int nt, int np, int N,
+                                                    const double* __restrict__ tw,
+                                                    double* __restrict__ G) {
+    extern __shared__ double sm[];
+    double* ring = sm;
+    double* cs = sm + np;
+    double* sn = sm + 2 * np;
+    int t = blockIdx.x, f = blockIdx.y;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        ring[p] = gv[(int64_t)f * MQ + (int64_t)t * np + p];
+        cs[p] = tw[p];
+        sn[p] = tw[np + p];
+    }
+    __syncthreads();
+    double scale = 2.0 * kPi / np;
+    for (int k = threadIdx.x; k <= N; k += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        int e = 0;
+        for (int p = 0; p < np; p++) {
+            re = fma(ring[p], cs[e], re);
+            im = fma(-ring[p], sn[e], im);
+            e += k;
+            if (e >= np) e -= np;
+        }
+        double* o = G + (((int64_t)f * nt + t) * (N + 1) + k) * 2;
+        o[0] = re * scale;
+        o[1] = im * scale;
+    }
+}
+
+hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStream_t s) {
+    int nt = P.dims[0], np = P.dims[1];
+    size_t lds = sizeof(double) * 3 * (size_t)np;
+    hipLaunchKernelGGL(k_s2_ring_dft, dim3(nt, F), dim3(256), lds, s, gv, P.MQ, nt, np, P.N,
+                       P.d_tw, P.d_G);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// fhat_{n,k} = sum_{t < ceil(nt/2)} w_t P_n^k(x_t) (G_t(k) +- G_{nt-1-t}(k)),
+// the sign by the parity of n+k (P_n^k(-x) = (-1)^{n+k} P_n^k(x)); negative
+// orders from fhat_{n,-k} = (-1)^k conj(fhat_{n,k}) (real fields).
+__global__ __launch_bounds__(256) void k_s2_legendre(const double* __restrict__ tab,
+                                                    const double* __restrict__ G, int nt, int N,
+                                                    int F, double* __restrict__ coeffs) {
+    int64_t na = (int64_t)(N + 1) * (N + 2) / 2;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= na * F) return;
+    int f = (int)(gid / na);
+    int64_t id = gid - (int64_t)f * na;
+    int n = (int)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+    while ((int64_t)n * (n + 1) / 2 > id) n--;
+    while ((int64_t)(n + 1) * (n + 2) / 2 <= id) n++;
+    int k = (int)(id - (int64_t)n * (n + 1) / 2);
+    int th = (nt + 1) / 2;
+    bool even = ((n + k) & 1) == 0;
+    double re = 0.0, im = 0.0;
+    for (int t = 0; t < th; t++) {
+        int t2 = nt - 1 - t;
+        const double* g1 = G + (((int64_t)f * nt + t) * (N + 1) + k) * 2;
+        const double* g2 = G + (((int64_t)f * nt + t2) * (N + 1) + k) * 2;
+        double er, ei;
+        if (t == t2) {
+            er = g1[0];
+            ei = g1[1];
+        } else if (even) {
+            er = g1[0] + g2[0];
+            ei = g1[1] + g2[1];
+        } else {
+            er = g1[0] - g2[0];
+            ei = g1[1] - g2[1];
+        }
+        double pv = tab[(int64_t)t * na + id];
+        re = fma(pv, er, re);
+        im = fma(pv, ei, im);
+    }
+    int64_t nc = (int64_t)(N + 1) * (N + 1);
+    double* o = coeffs + ((int64_t)f * nc + (int64_t)n * n + n + k) * 2;
+    o[0] = re;
+    o[1] = im;
+    if (k > 0) {
+        double sg = (k & 1) ? -1.0 : 1.0;
+        double* o2 = coeffs + ((int64_t)f * nc + (int64_t)n * n + n - k) * 2;
+        o2[0] = sg * re;
+        o2[1] = -sg * im;
+    }
+}
+
+hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s) {
+    int64_t na = (int64_t)(P.N + 1) * (P.N + 2) / 2;
+    int64_t tot = na * F;
+    int bs = 256;
+    hipLaunchKernelGGL(k_s2_legendre, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s,
+                       P.d_ptab, P.d_G, P.dims[0], P.N, F, coeffs);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// synthesis
+// ---------------------------------------------------------------------------
+
+// out[f*P + i] = Re sum_{n,k} fhat_{n,k} P_n^{|k|}(cos th) (sign) e^{ik phi};
+// the normalised associated Legendre functions are generated on the fly by the
+// sectoral start P_k^k and the three-term recurrence in n.
+__global__ __launch_bounds__(128) void k_s2_eval(const double* __restrict__ coeffs, int F, int N,
+                                                const double* __restrict__ pts, int64_t np,
+                                                double* __restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    double x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+    double ct = fmin(1.0, fmax(-1.0, z));
+    double st = sqrt((1.0 - ct) * (1.0 + ct));
+    double ph = atan2(y, x);
+    int64_t nc = (int64_t)(N + 1) * (N + 1);
+    for (int f = 0; f < F; f++) {
+        const double* cf = coeffs + (int64_t)f * nc * 2;
+        double acc = 0.0;
+        double pkk = 1.0 / sqrt(4.0 * kPi);
+        for (int k = 0; k <= N; k++) {
+            if (k > 0) pkk = -sqrt((2.0 * k + 1.0) / (2.0 * k)) * st * pkk;
+            double ck = cos(k * ph), sk = sin(k * ph);
+            double sg = (k & 1) ? -1.0 : 1.0;
+            double pm2 = 0.0, pm1 = pkk;
+            for (int n = k; n <= N; n++) {
+                double pn;
+                if (n == k)
+                    pn = pkk;
+                else if (n == k + 1)
+                    pn = sqrt(2.0 * k + 3.0) * ct * pkk;
+                else {
+                    double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)k * k));
+                    double b = sqrt((((double)n - 1) * (n - 1) - (double)k * k) /
+                                    (4.0 * ((double)n - 1) * (n - 1) - 1.0));
+                    pn = a * (ct * pm1 - b * pm2);
+                }
+                if (n > k) {
+                    pm2 = pm1;
+                    pm1 = pn;
+                }
+                const double* c1 = cf + ((int64_t)n * n + n + k) * 2;
+                double v = c1[0] * ck - c1[1] * sk;
+                if (k > 0) {
+                    const double* c2 = cf + ((int64_t)n * n + n - k) * 2;
+                    v += sg * (c2[0] * ck + c2[1] * sk);
+                }
+                acc = fma(pn, v, acc);
+            }
+        }
+        out[(int64_t)f * np + i] = acc;
+    }
+}
+
+hamls_status launch_s2_eval(const Plan& P, const double* coeffs, int F, const double* pts,
+                            int64_t npts, double* out, hipStream_t s) {
+    int bs = 128;
+    hipLaunchKernelGGL(k_s2_eval, dim3((unsigned)((npts + bs - 1) / bs)), dim3(bs), 0, s, coeffs,
+                       F, P.N, pts, npts, out);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+}  // namespace hamls

@@ -1,0 +1,684 @@
+// plan.hip -- the C ABI of include/hamls.h: parameter checks, the quadrature
+// grid and transform tables (host, FP64), device memory of a plan and the
+// order of kernel launches of every call.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "common.h"
+
+namespace hamls {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+hamls_status hip_status(hipError_t e, const char* what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? HAMLS_ERR_OUT_OF_MEMORY : HAMLS_ERR_DEVICE;
+}
+
+static hipEvent_t take_event(Plan& P) {
+    if (!P.pool.empty()) {
+        hipEvent_t e = P.pool.back();
+        P.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+PhaseTimer::PhaseTimer(Plan& P, int phase, hipStream_t s) : P_(P), phase_(phase), s_(s) {
+    if (!P_.timing) return;
+    b_ = take_event(P_);
+    if (b_) (void)hipEventRecord(b_, s_);
+}
+
+PhaseTimer::~PhaseTimer() {
+    if (!b_) return;
+    hipEvent_t e = take_event(P_);
+    if (!e) return;
+    (void)hipEventRecord(e, s_);
+    P_.pending.push_back({phase_, b_, e});
+}
+
+static void drain_timing(Plan& P) {
+    for (auto& r : P.pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            P.acc_ms[r.phase] += ms;
+            P.acc_n[r.phase] += 1;
+        }
+        P.pool.push_back(r.a);
+        P.pool.push_back(r.b);
+    }
+    P.pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// host geometry (step 1 of Alg. 1, Sec. 2.1)
+// ---------------------------------------------------------------------------
+
+// Gauss-Legendre rule with n nodes on [-1, 1]: Newton iteration on P_n from the
+// Chebyshev-like guess cos(pi (i + 3/4) / (n + 1/2)); nodes returned in
+// descending order (rings by increasing polar angle), mirrored exactly.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    auto eval = [n](double z, double& pn, double& dpn) {
+        double pm = 1.0, pc = z;
+        if (n == 0) {
+            pn = 1.0;
+            dpn = 0.0;
+            return;
+        }
+        for (int k = 2; k <= n; k++) {
+            double pk = ((2.0 * k - 1.0) * z * pc - (k - 1.0) * pm) / k;
+            pm = pc;
+            pc = pk;
+        }
+        pn = pc;
+        dpn = n * (z * pc - pm) / (z * z - 1.0);
+    };
+    for (int i = 0; i < (n + 1) / 2; i++) {
+        double z = cos(kPi * (i + 0.75) / (n + 0.5));
+        double pn, dpn;
+        for (int it = 0; it < 100; it++) {
+            eval(z, pn, dpn);
+            double step = pn / dpn;
+            z -= step;
+            if (fabs(step) < 1e-15) {
+                eval(z, pn, dpn);
+                z -= pn / dpn;
+                break;
+            }
+        }
+        eval(z, pn, dpn);
+        double wi = 2.0 / ((1.0 - z * z) * dpn * dpn);
+        x[i] = z;
+        x[n - 1 - i] = -z;
+        w[i] = wi;
+        w[n - 1 - i] = wi;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+// Normalised associated Legendre functions (Condon-Shortley phase) at x for
+// 0 <= k <= n <= N, at n(n+1)/2 + k: sectoral start and three-term recurrence.
+static void alf_column(int N, double x, double* out) {
+    double s = sqrt((1.0 - x) * (1.0 + x));
+    double pkk = 1.0 / sqrt(4.0 * kPi);
+    for (int k = 0; k <= N; k++) {
+        if (k > 0) pkk = -sqrt((2.0 * k + 1.0) / (2.0 * k)) * s * pkk;
+        out[(size_t)k * (k + 1) / 2 + k] = pkk;
+        if (k == N) break;
+        double p1 = sqrt(2.0 * k + 3.0) * x * pkk;
+        out[(size_t)(k + 1) * (k + 2) / 2 + k] = p1;
+        double pm2 = pkk, pm1 = p1;
+        for (int n = k + 2; n <= N; n++) {
+            double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)k * k));
+            double b = sqrt((((double)n - 1.0) * (n - 1.0) - (double)k * k) /
+                            (4.0 * ((double)n - 1.0) * (n - 1.0) - 1.0));
+            double pn = a * (x * pm1 - b * pm2);
+            out[(size_t)n * (n + 1) / 2 + k] = pn;
+            pm2 = pm1;
+            pm1 = pn;
+        }
+    }
+}
+
+static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
+    if (!p || p->struct_size != (int32_t)sizeof(hamls_params)) {
+        set_error("params: struct_size mismatch (call hamls_params_init)");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->domain != HAMLS_S2) {
+        set_error("domain %d not built in this library version", p->domain);
+        return HAMLS_ERR_UNSUPPORTED;
+    }
+    if (p->precision != HAMLS_FP64) {
+        set_error("precision %d not built in this library version", p->precision);
+        return HAMLS_ERR_UNSUPPORTED;
+    }
+    int N = p->bandwidth;
+    if (N < 0 || N > 1024) {
+        set_error("bandwidth %d outside [0, 1024]", N);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->degree < 0 || p->degree > 4) {
+        set_error("degree %d outside [0, 4]", p->degree);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    int m = n_monomials(2, p->degree);
+    if (!(p->support_radius > 0.0) && p->knn_count <= 0) {
+        set_error("need a fixed support radius or knn_count");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->support_radius < 0.0 || !(p->support_radius == p->support_radius)) {
+        set_error("support_radius must be >= 0");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->support_radius >= 0.5 * kPi) {
+        set_error("S2 support radius must be < pi/2 (tangent projection)");
+        return HAMLS_ERR_DOMAIN;
+    }
+    if (p->knn_count > 0 && (p->knn_count < m || !(p->knn_eps > 0.0))) {
+        set_error("knn_count must be >= m = %d and knn_eps > 0", m);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->wendland != 1 && p->wendland != 2) {
+        set_error("wendland must be 1 or 2");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->reg < HAMLS_REG_NONE || p->reg > HAMLS_REG_CHI_TARGET) {
+        set_error("unknown regularization %d", p->reg);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->reg == HAMLS_REG_FIXED && !(p->tau_fixed >= 0.0)) {
+        set_error("tau_fixed must be >= 0");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->reg == HAMLS_REG_CHI_TARGET && !(p->chi_target > 1.0 && p->chi_full > p->chi_target)) {
+        set_error("need 1 < chi_target < chi_full");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    dims[0] = p->grid_shape[0] > 0 ? p->grid_shape[0] : N + 1;
+    dims[1] = p->grid_shape[1] > 0 ? p->grid_shape[1] : 2 * N + 2;
+    dims[2] = 1;
+    if (dims[0] < N + 1 || dims[1] < 2 * N + 1) {
+        set_error("grid %d x %d is not exact on Pi_2N for N = %d", dims[0], dims[1], N);
+        return HAMLS_ERR_NOT_EXACT_GRID;
+    }
+    return HAMLS_OK;
+}
+
+template <class T>
+static hamls_status dalloc(Plan& P, T** ptr, size_t count) {
+    size_t bytes = sizeof(T) * (count > 0 ? count : 1);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return hip_status(e, "hipMalloc");
+    P.owned.push_back({p, bytes});
+    P.resident += (int64_t)bytes;
+    *ptr = (T*)p;
+    return HAMLS_OK;
+}
+
+#define HAMLS_TRY(x)                       \
+    do {                                   \
+        hamls_status s_ = (x);             \
+        if (s_ != HAMLS_OK) return s_;     \
+    } while (0)
+
+static void free_plan(Plan* P) {
+    if (!P) return;
+    for (auto& r : P->pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : P->pool) (void)hipEventDestroy(e);
+    for (auto& b : P->owned) (void)hipFree(b.p);
+    delete P;
+}
+
+// S2 binning geometry sized so that a cell is about half the expected support
+// radius: nb equal bands in theta, sectors per band proportional to sin(theta).
+static void s2_bins(Plan& P, int64_t M) {
+    double h = 0.0;
+    if (P.prm.knn_count > 0) h = sqrt((double)P.prm.knn_count / (double)M);  // ~ r/2
+    if (P.prm.support_radius > 0.0) {
+        double hf = 0.5 * P.prm.support_radius;
+        h = h > 0.0 ? std::min(h, hf) : hf;
+    }
+    h = std::max(h, kPi / 4096.0);
+    h = std::min(h, kPi / 4.0);
+    int nb = (int)ceil(kPi / h);
+    nb = std::max(4, std::min(nb, 4096));
+    S2Bins& B = P.bins;
+    B.nb = nb;
+    B.dtheta = kPi / nb;
+    B.band_off.assign(nb + 1, 0);
+    for (int b = 0; b < nb; b++) {
+        double th = (b + 0.5) * B.dtheta;
+        int ns = (int)lround(2.0 * kPi * sin(th) / B.dtheta);
+        ns = std::max(1, ns);
+        B.band_off[b + 1] = B.band_off[b] + ns;
+    }
+    B.ncells = B.band_off[nb];
+    int bits = 1;
+    while ((1ll << bits) < B.ncells) bits++;
+    B.key_bits = bits;
+}
+
+static hamls_status bind_nodes(Plan& P, const double* nodes, int64_t M, const double* nu,
+                               hipStream_t s) {
+    P.M = M;
+    P.has_nu = nu != nullptr;
+    {
+        PhaseTimer pt(P, HAMLS_PHASE_BINNING, s);
+        HAMLS_TRY(launch_s2_keys(P, nodes, M, s));
+        int fin = 0;
+        HAMLS_TRY(radix_sort(P, M, s, &fin));
+        HAMLS_TRY(launch_cell_start(P, P.d_key[fin], M, s));
+        HAMLS_TRY(launch_gather_nodes(P, P.d_idx[fin], nodes, nu, M, s));
+    }
+    PhaseTimer pt(P, HAMLS_PHASE_RADIUS, s);
+    HAMLS_TRY(launch_s2_radius(P, s));
+    return HAMLS_OK;
+}
+
+static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nodes, int64_t M,
+                               const double* nu, hipStream_t s) {
+    P.prm = *p;
+    HAMLS_HIP(hipGetDevice(&P.device));
+    P.dom = p->domain;
+    P.N = p->bandwidth;
+    P.K = p->degree;
+    P.D = 2;
+    P.m = n_monomials(2, P.K);
+    int nt = P.dims[0], np = P.dims[1];
+    P.MQ = (int64_t)nt * np;
+    P.ncoef = (int64_t)(P.N + 1) * (P.N + 1);
+    P.cap = M;
+
+    // grid: GL in cos(theta) x trapezoid in phi
+    gauss_legendre(nt, P.h_glx, P.h_glw);
+    P.h_theta.resize(nt);
+    P.h_phi.resize(np);
+    P.h_grid.resize(3 * P.MQ);
+    P.h_wts.resize(P.MQ);
+    std::vector<double> cphi(np), sphi(np);
+    for (int q = 0; q < np; q++) {
+        P.h_phi[q] = 2.0 * kPi * q / np;
+        cphi[q] = cos(P.h_phi[q]);
+        sphi[q] = sin(P.h_phi[q]);
+    }
+    for (int t = 0; t < nt; t++) {
+        double x = P.h_glx[t];
+        double st = sqrt((1.0 - x) * (1.0 + x));
+        P.h_theta[t] = acos(x);
+        for (int q = 0; q < np; q++) {
+            int64_t j = (int64_t)t * np + q;
+            P.h_grid[3 * j + 0] = st * cphi[q];
+            P.h_grid[3 * j + 1] = st * sphi[q];
+            P.h_grid[3 * j + 2] = x;
+            P.h_wts[j] = P.h_glw[t] * 2.0 * kPi / np;
+        }
+    }
+    s2_bins(P, M);
+
+    HAMLS_TRY(dalloc(P, &P.d_grid, 3 * P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_theta, nt));
+    HAMLS_TRY(dalloc(P, &P.d_phi, np));
+    HAMLS_TRY(dalloc(P, &P.d_x, 3 * P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_nu, P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_perm, P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_key[0], P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_key[1], P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_idx[0], P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_idx[1], P.cap));
+    P.hist_len = 256 * ((P.cap + 4095) / 4096 + 1);
+    HAMLS_TRY(dalloc(P, &P.d_hist, P.hist_len));
+    HAMLS_TRY(dalloc(P, &P.d_band_off, P.bins.nb + 1));
+    HAMLS_TRY(dalloc(P, &P.d_cell_start, P.bins.ncells + 1));
+    HAMLS_TRY(dalloc(P, &P.d_delta, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_thr, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_status, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_rstatus, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_nj, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_chi, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_tau, P.MQ));
+    int EG = P.m * (P.m + 1) / 2;
+    P.n_entries_cap = EG + (int64_t)P.m * kMaxFieldsPerPass;
+    HAMLS_TRY(dalloc(P, &P.d_entries, P.n_entries_cap * P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_vals, (size_t)kMaxFieldsPerPass * P.cap));
+
+    // step-3 tables: Legendre table of the northern rings with the GL weights
+    // folded in, and the ring twiddles
+    int th = (nt + 1) / 2;
+    int64_t na = (int64_t)(P.N + 1) * (P.N + 2) / 2;
+    P.ptab_len = (int64_t)th * na;
+    std::vector<double> tab(P.ptab_len);
+    for (int t = 0; t < th; t++) {
+        alf_column(P.N, P.h_glx[t], tab.data() + (size_t)t * na);
+        for (int64_t i = 0; i < na; i++) tab[(size_t)t * na + i] *= P.h_glw[t];
+    }
+    std::vector<double> tw(2 * (size_t)np);
+    for (int q = 0; q < np; q++) {
+        tw[q] = cphi[q];
+        tw[np + q] = sphi[q];
+    }
+    HAMLS_TRY(dalloc(P, &P.d_ptab, P.ptab_len));
+    HAMLS_TRY(dalloc(P, &P.d_tw, 2 * (size_t)np));
+
+    HAMLS_HIP(hipMemcpyAsync(P.d_grid, P.h_grid.data(), sizeof(double) * 3 * P.MQ,
+                             hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipMemcpyAsync(P.d_theta, P.h_theta.data(), sizeof(double) * nt,
+                             hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipMemcpyAsync(P.d_phi, P.h_phi.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipMemcpyAsync(P.d_band_off, P.bins.band_off.data(), sizeof(int32_t) * (P.bins.nb + 1),
+                             hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipMemcpyAsync(P.d_ptab, tab.data(), sizeof(double) * P.ptab_len,
+                             hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipMemcpyAsync(P.d_tw, tw.data(), sizeof(double) * 2 * np, hipMemcpyHostToDevice, s));
+    // the host vectors above are pageable: make the copies complete before
+    // they go out of scope
+    HAMLS_HIP(hipStreamSynchronize(s));
+    return bind_nodes(P, nodes, M, nu, s);
+}
+
+}  // namespace hamls
+
+using namespace hamls;
+
+extern "C" {
+
+hamls_status hamls_params_init(hamls_params* p) {
+    if (!p) {
+        set_error("null params");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    memset(p, 0, sizeof(*p));
+    p->struct_size = (int32_t)sizeof(hamls_params);
+    p->domain = HAMLS_S2;
+    p->bandwidth = 16;
+    p->degree = 2;
+    p->support_radius = 0.0;
+    p->knn_count = 24;
+    p->wendland = 1;
+    p->knn_eps = 0.05;
+    p->reg = HAMLS_REG_CHI_TARGET;
+    p->precision = HAMLS_FP64;
+    p->tau_fixed = 0.0;
+    p->chi_target = 10.0;
+    p->chi_full = 20.0;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan(const hamls_params* p, const double* nodes, int64_t M,
+                        const double* node_weights, void* stream, hamls_plan_t* out) {
+    if (!out || !nodes) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    int32_t dims[3];
+    HAMLS_TRY(check_params(p, dims));
+    if (M < 1 || M > ((int64_t)1 << 31) - 4096 || (p->knn_count > 0 && M < p->knn_count)) {
+        set_error("node count %lld invalid (need 1 <= M < 2^31, M >= knn_count)", (long long)M);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    Plan* P = new (std::nothrow) Plan();
+    if (!P) {
+        set_error("host allocation failed");
+        return HAMLS_ERR_OUT_OF_MEMORY;
+    }
+    memcpy(P->dims, dims, sizeof(dims));
+    hamls_status st = build_plan(*P, p, nodes, M, node_weights, (hipStream_t)stream);
+    if (st != HAMLS_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        free_plan(P);
+        return st;
+    }
+    *out = (hamls_plan_t)P;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_rebind(hamls_plan_t plan, const double* nodes, int64_t M,
+                               const double* node_weights, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P || !nodes) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (M < 1 || M > P->cap || (P->prm.knn_count > 0 && M < P->prm.knn_count)) {
+        set_error("node count %lld outside [max(1, knn_count), capacity %lld]", (long long)M,
+                  (long long)P->cap);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    return bind_nodes(*P, nodes, M, node_weights, (hipStream_t)stream);
+}
+
+hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
+                               double* grid_values, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P || !values || !grid_values) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (F < 1 || F > 64 || ld < P->M) {
+        set_error("need 1 <= F <= 64 and ld >= M");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int f0 = 0; f0 < F; f0 += kMaxFieldsPerPass) {
+        int Fc = std::min(kMaxFieldsPerPass, F - f0);
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_GATHER, s);
+            HAMLS_TRY(launch_gather_values(*P, values, Fc, f0, ld, s));
+        }
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
+            HAMLS_TRY(launch_s2_assemble(*P, Fc, f0, s));
+        }
+        PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
+        HAMLS_TRY(launch_solve(*P, Fc, f0, grid_values, F, s));
+    }
+    return HAMLS_OK;
+}
+
+hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, int32_t F,
+                                  double* coeffs, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P || !grid_values || !coeffs) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (F < 1 || F > 4096) {
+        set_error("F outside [1, 4096]");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (F > P->G_fields) {
+        if (P->d_G) {
+            HAMLS_HIP(hipStreamSynchronize(s));
+            for (auto it = P->owned.begin(); it != P->owned.end(); ++it)
+                if (it->p == P->d_G) {
+                    (void)hipFree(it->p);
+                    P->resident -= (int64_t)it->bytes;
+                    P->owned.erase(it);
+                    break;
+                }
+            P->d_G = nullptr;
+        }
+        HAMLS_TRY(dalloc(*P, &P->d_G, (size_t)F * P->dims[0] * (P->N + 1) * 2));
+        P->G_fields = F;
+    }
+    {
+        PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
+        HAMLS_TRY(launch_s2_ring_dft(*P, grid_values, F, s));
+    }
+    PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s);
+    HAMLS_TRY(launch_s2_legendre(*P, F, coeffs, s));
+    return HAMLS_OK;
+}
+
+hamls_status hamls_eval(hamls_plan_t plan, const double* coeffs, int32_t F, const double* points,
+                        int64_t npts, double* out, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P || !coeffs || !points || !out) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (F < 1 || npts < 0) {
+        set_error("need F >= 1 and P >= 0");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (npts == 0) return HAMLS_OK;
+    return launch_s2_eval(*P, coeffs, F, points, npts, out, (hipStream_t)stream);
+}
+
+hamls_status hamls_plan_destroy(hamls_plan_t plan) {
+    Plan* P = (Plan*)plan;
+    if (!P) return HAMLS_OK;
+    (void)hipDeviceSynchronize();
+    free_plan(P);
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_info_get(hamls_plan_t plan, hamls_plan_info* o) {
+    Plan* P = (Plan*)plan;
+    if (!P || !o) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    memset(o, 0, sizeof(*o));
+    o->domain = P->dom;
+    o->bandwidth = P->N;
+    o->degree = P->K;
+    o->m = P->m;
+    memcpy(o->grid_dims, P->dims, sizeof(P->dims));
+    o->precision = P->prm.precision;
+    o->num_grid = P->MQ;
+    o->num_coeffs = P->ncoef;
+    o->num_nodes = P->M;
+    o->node_capacity = P->cap;
+    o->resident_bytes = P->resident;
+    o->num_cells = P->bins.ncells;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_grid(hamls_plan_t plan, double* points, double* weights) {
+    Plan* P = (Plan*)plan;
+    if (!P) {
+        set_error("null plan");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (points) memcpy(points, P->h_grid.data(), sizeof(double) * P->h_grid.size());
+    if (weights) memcpy(weights, P->h_wts.data(), sizeof(double) * P->h_wts.size());
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_neighbors(hamls_plan_t plan, int64_t* row_ptr, int32_t* idx) {
+    Plan* P = (Plan*)plan;
+    if (!P || !row_ptr) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = nullptr;
+    HAMLS_HIP(hipDeviceSynchronize());
+    int32_t* d_cnt = nullptr;
+    HAMLS_HIP(hipMalloc(&d_cnt, sizeof(int32_t) * P->MQ));
+    hamls_status st = launch_s2_count(*P, d_cnt, s);
+    std::vector<int32_t> cnt(P->MQ);
+    if (st == HAMLS_OK) {
+        hipError_t e = hipMemcpy(cnt.data(), d_cnt, sizeof(int32_t) * P->MQ, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) st = hip_status(e, "hipMemcpy");
+    }
+    (void)hipFree(d_cnt);
+    if (st != HAMLS_OK) return st;
+    row_ptr[0] = 0;
+    for (int64_t j = 0; j < P->MQ; j++) row_ptr[j + 1] = row_ptr[j] + cnt[j];
+    if (!idx) return HAMLS_OK;
+    int64_t tot = row_ptr[P->MQ];
+    int64_t* d_rp = nullptr;
+    int32_t* d_idx = nullptr;
+    HAMLS_HIP(hipMalloc(&d_rp, sizeof(int64_t) * (P->MQ + 1)));
+    hipError_t e = hipMalloc(&d_idx, sizeof(int32_t) * (tot > 0 ? tot : 1));
+    if (e != hipSuccess) {
+        (void)hipFree(d_rp);
+        return hip_status(e, "hipMalloc");
+    }
+    e = hipMemcpy(d_rp, row_ptr, sizeof(int64_t) * (P->MQ + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        st = launch_s2_list(*P, d_rp, d_idx, s);
+        if (st == HAMLS_OK) e = hipMemcpy(idx, d_idx, sizeof(int32_t) * tot, hipMemcpyDeviceToHost);
+    }
+    (void)hipFree(d_rp);
+    (void)hipFree(d_idx);
+    if (e != hipSuccess) return hip_status(e, "neighbour export");
+    if (st != HAMLS_OK) return st;
+    for (int64_t j = 0; j < P->MQ; j++) std::sort(idx + row_ptr[j], idx + row_ptr[j + 1]);
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_radii(hamls_plan_t plan, double* delta, double* threshold) {
+    Plan* P = (Plan*)plan;
+    if (!P) {
+        set_error("null plan");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    HAMLS_HIP(hipDeviceSynchronize());
+    if (delta) HAMLS_HIP(hipMemcpy(delta, P->d_delta, sizeof(double) * P->MQ, hipMemcpyDeviceToHost));
+    if (threshold)
+        HAMLS_HIP(hipMemcpy(threshold, P->d_thr, sizeof(double) * P->MQ, hipMemcpyDeviceToHost));
+    return HAMLS_OK;
+}
+
+hamls_status hamls_diagnostics(hamls_plan_t plan, int32_t* n, double* chi, double* tau,
+                               uint8_t* status) {
+    Plan* P = (Plan*)plan;
+    if (!P) {
+        set_error("null plan");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    HAMLS_HIP(hipDeviceSynchronize());
+    if (n) HAMLS_HIP(hipMemcpy(n, P->d_nj, sizeof(int32_t) * P->MQ, hipMemcpyDeviceToHost));
+    if (chi) HAMLS_HIP(hipMemcpy(chi, P->d_chi, sizeof(double) * P->MQ, hipMemcpyDeviceToHost));
+    if (tau) HAMLS_HIP(hipMemcpy(tau, P->d_tau, sizeof(double) * P->MQ, hipMemcpyDeviceToHost));
+    if (status)
+        HAMLS_HIP(hipMemcpy(status, P->d_status, sizeof(uint8_t) * P->MQ, hipMemcpyDeviceToHost));
+    return HAMLS_OK;
+}
+
+hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable) {
+    Plan* P = (Plan*)plan;
+    if (!P) {
+        set_error("null plan");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    P->timing = enable != 0;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_timing_read(hamls_plan_t plan, int32_t phase, int64_t* launches,
+                               double* total_ms) {
+    Plan* P = (Plan*)plan;
+    if (!P || phase < 0 || phase >= HAMLS_NUM_PHASES) {
+        set_error("bad plan or phase");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    drain_timing(*P);
+    if (launches) *launches = P->acc_n[phase];
+    if (total_ms) *total_ms = P->acc_ms[phase];
+    P->acc_n[phase] = 0;
+    P->acc_ms[phase] = 0.0;
+    return HAMLS_OK;
+}
+
+const char* hamls_status_string(hamls_status s) {
+    switch (s) {
+        case HAMLS_OK: return "ok";
+        case HAMLS_ERR_INVALID_ARG: return "invalid argument";
+        case HAMLS_ERR_UNSUPPORTED: return "unsupported";
+        case HAMLS_ERR_OUT_OF_MEMORY: return "out of memory";
+        case HAMLS_ERR_DEVICE: return "device error";
+        case HAMLS_ERR_DOMAIN: return "domain error";
+        case HAMLS_ERR_NOT_EXACT_GRID: return "grid not exact";
+    }
+    return "unknown status";
+}
+
+const char* hamls_last_error(void) { return g_err; }
+
+}  // extern "C"
