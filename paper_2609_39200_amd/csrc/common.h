@@ -85,6 +85,8 @@ struct Plan {
     double* d_chi = nullptr;        // MQ
     double* d_tau = nullptr;        // MQ
     double* d_entries = nullptr;    // n_entries x MQ
+    int32_t* d_qr_list = nullptr;   // MQ, centres re-solved by QR
+    int32_t* d_qr_count = nullptr;  // 1
     int64_t n_entries_cap = 0;
     double* d_vals = nullptr;       // sorted values, kMaxFieldsPerPass x cap
     double* d_ptab = nullptr;       // Legendre table

@@ -302,8 +302,9 @@ hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double
 
 __global__ void k_gather_values(const int32_t* __restrict__ perm, const double* __restrict__ values,
                                 int F, int64_t ld, int64_t M, int64_t cap,
-                                double* __restrict__ out) {
+                                double* __restrict__ out, int32_t* __restrict__ qr_count) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *qr_count = 0;  // the solve that follows appends its QR list from zero
     if (i >= M) return;
     int64_t j = perm[i];
     for (int f = 0; f < F; f++) out[f * cap + i] = values[f * ld + j];
@@ -314,7 +315,7 @@ hamls_status launch_gather_values(const Plan& P, const double* values, int F, in
     int bs = 256;
     int64_t nbk = (P.M + bs - 1) / bs;
     hipLaunchKernelGGL(k_gather_values, dim3((unsigned)nbk), dim3(bs), 0, s, P.d_perm,
-                       values + (int64_t)f0 * ld, F, ld, P.M, P.cap, P.d_vals);
+                       values + (int64_t)f0 * ld, F, ld, P.M, P.cap, P.d_vals, P.d_qr_count);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -626,8 +627,15 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// local solve (eq. (15)-(23)), one thread per grid node
+// local solve (eq. (15)-(23))
 // ---------------------------------------------------------------------------
+
+// A centre whose normal-matrix factorisation is not trustworthy to ~1e-12 is
+// re-solved by QR: Cholesky failure, condition estimate 1/min pivot of C (unit
+// diagonal) above kCondQR, or chi above kCondQR.
+constexpr double kCondQR = 1e4;
+// |R_jj| of the unit-column V at or below which V is taken as rank deficient.
+constexpr double kRankTol = 1e-11;
 
 struct SolveArgs {
     const double* entries;
@@ -644,6 +652,8 @@ struct SolveArgs {
     double* tau;
     uint8_t* status;
     int write_diag;
+    int32_t* qr_list;    // centres handed to the QR path
+    int32_t* qr_count;
 };
 
 __device__ __forceinline__ double coupling_tau(const double* d2, const double* mu, int n, double tau) {
@@ -652,6 +662,42 @@ __device__ __forceinline__ double coupling_tau(const double* d2, const double* m
     return r;
 }
 
+// tau of eq. (22).  Chi-target: 0 for chi <= chi_T; otherwise the tau with
+// chi_tau = chi_T (eq. (23)) by bisection on log tau (64 halvings between 1e-16
+// and the first power of two that overshoots), times the C^3 smoothstep
+// S(t) = 35t^4 - 84t^5 + 70t^6 - 20t^7 of t = (chi - chi_T)/(chi_full - chi_T).
+__device__ double choose_tau(int reg, double chi, const double* d2, const double* mu, int n,
+                             double tau_fixed, double chi_t, double chi_f) {
+    if (reg == HAMLS_REG_FIXED) return tau_fixed;
+    if (reg != HAMLS_REG_CHI_TARGET || !(chi > chi_t)) return 0.0;
+    double target = 1.0 - 1.0 / chi_t;
+    double hi = 1.0;
+    int guard = 0;
+    while (coupling_tau(d2, mu, n, hi) > target && guard < 2000) {
+        hi *= 2.0;
+        guard++;
+    }
+    double a = log(1e-16), b = log(hi);
+    for (int it = 0; it < 64; it++) {
+        double mid = 0.5 * (a + b);
+        if (coupling_tau(d2, mu, n, exp(mid)) > target)
+            a = mid;
+        else
+            b = mid;
+    }
+    double tt = (chi - chi_t) / (chi_f - chi_t);
+    double sm = 1.0;
+    if (tt < 1.0) {
+        double t4 = tt * tt * tt * tt;
+        sm = t4 * (35.0 - 84.0 * tt + 70.0 * tt * tt - 20.0 * tt * tt * tt);
+    }
+    return sm * exp(0.5 * (a + b));
+}
+
+// One thread per grid node: normalise (unit weights sum, unit-norm columns),
+// Cholesky of C, d = L^{-1} b, chi = 1/(1 - |d|^2), tau, and
+//   c_1 = (r_1 - sum_j d_j z_j / (1 + tau mu_j)) / (1 - sum_j d_j^2 / (1 + tau mu_j)),
+// z = L^{-1} r[1:], the Schur complement of the first unknown in (22).
 template <int MM>
 __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
     constexpr int EG = MM * (MM + 1) / 2;
@@ -687,6 +733,7 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
     double chi = 1.0, tau = 0.0;
     double d[NC > 0 ? NC : 1], L[NL];
     double minpiv = 1.0;
+    bool ill = false;
     if (!degen && NC > 0) {
         // normalised C (unit diagonal) and b, Cholesky C = L L^T in packed rows
 #pragma unroll
@@ -701,8 +748,8 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
             double s = L[k * (k + 1) / 2 + k];
 #pragma unroll
             for (int c = 0; c < k; c++) s -= L[k * (k + 1) / 2 + c] * L[k * (k + 1) / 2 + c];
-            if (!(s > 1e-22)) {
-                degen = true;
+            if (!(s > 1e-300)) {
+                ill = true;
                 s = 1.0;
             }
             minpiv = fmin(minpiv, s);
@@ -717,7 +764,8 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
                 L[r * (r + 1) / 2 + k] = v * il;
             }
         }
-        if (!degen) {
+        double d2[NC > 0 ? NC : 1];
+        if (!ill) {
             // d = L^{-1} b
 #pragma unroll
             for (int r = 0; r < NC; r++) {
@@ -726,7 +774,6 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
                 for (int c = 0; c < r; c++) v -= L[r * (r + 1) / 2 + c] * d[c];
                 d[r] = v / L[r * (r + 1) / 2 + r];
             }
-            double d2[NC > 0 ? NC : 1];
             double r0 = 0.0;
 #pragma unroll
             for (int r = 0; r < NC; r++) {
@@ -734,58 +781,36 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
                 r0 += d2[r];
             }
             chi = 1.0 / (1.0 - r0);
-            if (A.reg == HAMLS_REG_FIXED) {
-                tau = A.tau_fixed;
-            } else if (A.reg == HAMLS_REG_CHI_TARGET && chi > A.chi_t) {
-                double target = 1.0 - 1.0 / A.chi_t;
-                double hi = 1.0;
-                int guard = 0;
-                while (coupling_tau(d2, A.mu, NC, hi) > target && guard < 2000) {
-                    hi *= 2.0;
-                    guard++;
-                }
-                double a = log(1e-16), b = log(hi);
-                for (int it = 0; it < 64; it++) {
-                    double mid = 0.5 * (a + b);
-                    if (coupling_tau(d2, A.mu, NC, exp(mid)) > target)
-                        a = mid;
-                    else
-                        b = mid;
-                }
-                double tt = (chi - A.chi_t) / (A.chi_f - A.chi_t);
-                double sm;
-                if (tt >= 1.0)
-                    sm = 1.0;
-                else {
-                    double t4 = tt * tt * tt * tt;
-                    sm = t4 * (35.0 - 84.0 * tt + 70.0 * tt * tt - 20.0 * tt * tt * tt);
-                }
-                tau = sm * exp(0.5 * (a + b));
-            }
-            double den = 1.0;
-            double fac[NC > 0 ? NC : 1];
+            if (!(chi >= 1.0) || chi > kCondQR || 1.0 / minpiv > kCondQR) ill = true;
+        }
+        if (ill) {
+            int slot = atomicAdd(A.qr_count, 1);
+            A.qr_list[slot] = (int32_t)j;
+            return;
+        }
+        tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
+        double den = 1.0;
+        double fac[NC > 0 ? NC : 1];
+#pragma unroll
+        for (int r = 0; r < NC; r++) {
+            fac[r] = d[r] / (1.0 + tau * A.mu[r]);
+            den -= fac[r] * d[r];
+        }
+        for (int f = 0; f < A.F; f++) {
+            double z[NC > 0 ? NC : 1];
 #pragma unroll
             for (int r = 0; r < NC; r++) {
-                fac[r] = d[r] / (1.0 + tau * A.mu[r]);
-                den -= fac[r] * d[r];
+                double v = H[((int64_t)(r + 1) * A.F + f) * MQ + j] / (W * sc[r + 1]);
+#pragma unroll
+                for (int c = 0; c < r; c++) v -= L[r * (r + 1) / 2 + c] * z[c];
+                z[r] = v / L[r * (r + 1) / 2 + r];
             }
-            for (int f = 0; f < A.F; f++) {
-                double z[NC > 0 ? NC : 1];
+            double num = H[(int64_t)f * MQ + j] / W;
 #pragma unroll
-                for (int r = 0; r < NC; r++) {
-                    double v = H[((int64_t)(r + 1) * A.F + f) * MQ + j] / (W * sc[r + 1]);
-#pragma unroll
-                    for (int c = 0; c < r; c++) v -= L[r * (r + 1) / 2 + c] * z[c];
-                    z[r] = v / L[r * (r + 1) / 2 + r];
-                }
-                double num = H[(int64_t)f * MQ + j] / W;
-#pragma unroll
-                for (int r = 0; r < NC; r++) num -= fac[r] * z[r];
-                A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
-            }
-            if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
-            if (minpiv < 1e-10) st |= HAMLS_ST_ILLCOND;
+            for (int r = 0; r < NC; r++) num -= fac[r] * z[r];
+            A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
         }
+        if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
     }
     if (!degen && NC == 0) {
         for (int f = 0; f < A.F; f++) A.out[(int64_t)(A.f0 + f) * MQ + j] = H[(int64_t)f * MQ + j] / W;
@@ -800,6 +825,172 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
         A.chi[j] = chi;
         A.tau[j] = tau;
         A.status[j] = st;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// QR path for the centres flagged by k_solve: the rows (V_i | v1_i | y_w,i) of
+// the normalised weighted local problem (eq. (14)) are streamed in batches of
+// up to 64 and folded into the m-row upper-trapezoidal factor T of [V | v1 | y_w]
+// by Householder reflections (a tall-skinny QR over the first m columns).  At
+// the end, with S = sign(diag R_V):  L = R_V^T S is the Cholesky factor of C
+// (eq. (20)), d = S (Q^T v1)[0:m-1], z = S (Q^T y_w)[0:m-1], and the last
+// factor row gives rho = |(I - P_V) v1| and w = the matching component of y_w,
+// so that 1 - |d|^2 = rho^2 and r_1 - d.z = rho w without cancellation:
+//   c_1 = (rho w + sum_j d_j z_j tau mu_j/(1 + tau mu_j))
+//       / (rho^2 + sum_j d_j^2 tau mu_j/(1 + tau mu_j)).
+template <int K>
+__global__ __launch_bounds__(64) void k_s2_qr(S2Geom g, const double* __restrict__ vals, int wendland,
+                                             const double* __restrict__ thr,
+                                             const double* __restrict__ delta, SolveArgs A) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    constexpr int NC = m - 1;
+    constexpr int LD = m + 1 + kMaxFieldsPerPass;
+    __shared__ double T[(m + 64) * LD];
+    const int lane = threadIdx.x;
+    const int F = A.F;
+    const int cols = m + F;
+    const int64_t MQ = A.MQ;
+    const int total = *A.qr_count;
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    for (int li = blockIdx.x; li < total; li += gridDim.x) {
+        const int j = A.qr_list[li];
+        const int t = j / g.nphi, p = j - t * g.nphi;
+        const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+        const double thq = g.theta[t], phq = g.phi[p];
+        const double ct = cos(thq), stt = sin(thq), cp = cos(phq), sp = sin(phq);
+        const double et0 = ct * cp, et1 = ct * sp, et2 = -stt, ep0 = -sp, ep1 = cp;
+        const double c = thr[j], dl = delta[j], idl = 1.0 / dl;
+        const double W = A.entries[j];
+        double isc[m];
+#pragma unroll
+        for (int a = 0; a < m; a++) isc[a] = 1.0 / sqrt(A.entries[(int64_t)gidx(a, a) * MQ + j] / W);
+        for (int e = lane; e < m * LD; e += 64) T[e] = 0.0;
+        __syncthreads();
+        s2_ranges(g, thq, phq, dl, [&](int lo, int hi) {
+            for (int base = lo; base < hi; base += 64) {
+                int i = base + lane;
+                bool valid = i < hi;
+                double x0 = 0.0, x1 = 0.0, x2 = 0.0, dd = -2.0;
+                if (valid) {
+                    x0 = g.X[i];
+                    x1 = g.X[g.cap + i];
+                    x2 = g.X[2 * g.cap + i];
+                    dd = s2_dot(x0, x1, x2, q0, q1, q2);
+                }
+                bool in = valid && dd > c;
+                uint64_t mk = __ballot(in);
+                int nin = __popcll(mk);
+                if (nin == 0) continue;
+                if (in) {
+                    double w = wendland_phi(wendland, acos(fmin(dd, 1.0)) * idl);
+                    if (g.nu) w *= g.nu[i];
+                    double b = sqrt(w / W);
+                    double u = (x0 * et0 + x1 * et1 + x2 * et2) * idl;
+                    double v = (x0 * ep0 + x1 * ep1) * idl;
+                    double pu[K + 1], pv[K + 1];
+                    pu[0] = 1.0;
+                    pv[0] = 1.0;
+#pragma unroll
+                    for (int a = 1; a <= K; a++) {
+                        pu[a] = pu[a - 1] * u;
+                        pv[a] = pv[a - 1] * v;
+                    }
+                    double* row = T + (m + rank_below(mk)) * LD;
+                    int cidx = 0;
+#pragma unroll
+                    for (int l = 0; l <= K; l++)
+#pragma unroll
+                        for (int bb = 0; bb <= l; bb++) {
+                            if (cidx > 0) row[cidx - 1] = b * pu[l - bb] * pv[bb] * isc[cidx];
+                            cidx++;
+                        }
+                    row[NC] = b;
+                    for (int f = 0; f < F; f++) row[m + f] = b * vals[(int64_t)f * g.cap + i];
+                }
+                __syncthreads();
+                const int R = m + nin;
+                for (int k = 0; k < m; k++) {
+                    double part = 0.0;
+                    for (int r = k + lane; r < R; r += 64) {
+                        double v = T[r * LD + k];
+                        part += v * v;
+                    }
+                    double nrm2 = wave_sum(part);
+                    double x0k = T[k * LD + k];
+                    __syncthreads();
+                    // The columns have unit discrete norm; a residual below
+                    // 1e-100 is rounding noise (a batch of fewer than m rows
+                    // leaves such noise that each further reflection squares,
+                    // until 2/v.v would overflow).  Nothing to eliminate.
+                    if (!(nrm2 > 1e-200)) continue;
+                    double nrm = sqrt(nrm2);
+                    double alpha = x0k > 0.0 ? -nrm : nrm;
+                    double v0 = x0k - alpha;
+                    double vv = nrm2 - x0k * x0k + v0 * v0;
+                    for (int jc = k + 1 + lane; jc < cols; jc += 64) {
+                        double sdot = v0 * T[k * LD + jc];
+                        for (int r = k + 1; r < R; r++) sdot += T[r * LD + k] * T[r * LD + jc];
+                        sdot *= 2.0 / vv;
+                        T[k * LD + jc] -= sdot * v0;
+                        for (int r = k + 1; r < R; r++) T[r * LD + jc] -= sdot * T[r * LD + k];
+                    }
+                    __syncthreads();
+                    if (lane == 0) T[k * LD + k] = alpha;
+                    for (int r = k + 1 + lane; r < R; r += 64) T[r * LD + k] = 0.0;
+                    __syncthreads();
+                }
+            }
+        });
+        // finish on lane 0 (m - 1 <= 14 unknowns)
+        if (lane == 0) {
+            uint8_t st = A.rstatus[j] | HAMLS_ST_ILLCOND;
+            double rmin = 1e300;
+            for (int k = 0; k < NC; k++) rmin = fmin(rmin, fabs(T[k * LD + k]));
+            double chi, tau;
+            if (!(rmin > kRankTol)) {
+                for (int f = 0; f < F; f++)
+                    A.out[(int64_t)(A.f0 + f) * MQ + j] = A.entries[(int64_t)(m * (m + 1) / 2 + f) * MQ + j] / W;
+                chi = __builtin_inf();
+                tau = __builtin_inf();
+                st |= HAMLS_ST_UNDERDETERMINED;
+            } else {
+                double dv[NC], d2[NC], sg[NC];
+#pragma unroll
+                for (int k = 0; k < NC; k++) {
+                    sg[k] = T[k * LD + k] < 0.0 ? -1.0 : 1.0;
+                    dv[k] = sg[k] * T[k * LD + NC];
+                    d2[k] = dv[k] * dv[k];
+                }
+                const double rho = T[NC * LD + NC];
+                chi = 1.0 / (rho * rho);
+                tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
+                double den = rho * rho;
+                double fac[NC];
+#pragma unroll
+                for (int k = 0; k < NC; k++) {
+                    double tm = tau * A.mu[k];
+                    fac[k] = tm > 0.0 ? dv[k] * (tm / (1.0 + tm)) : 0.0;
+                    den += fac[k] * dv[k];
+                }
+                for (int f = 0; f < F; f++) {
+                    double num = rho * T[NC * LD + m + f];
+                    for (int k = 0; k < NC; k++) num += fac[k] * sg[k] * T[k * LD + m + f];
+                    A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
+                }
+                if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
+            }
+            if (A.write_diag) {
+                A.chi[j] = chi;
+                A.tau[j] = tau;
+                A.status[j] = st;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -831,6 +1022,8 @@ hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int
     A.tau = P.d_tau;
     A.status = P.d_status;
     A.write_diag = f0 == 0;
+    A.qr_list = P.d_qr_list;
+    A.qr_count = P.d_qr_count;
     int bs = 256;
     dim3 grid((unsigned)((P.MQ + bs - 1) / bs)), block(bs);
     switch (P.m) {
@@ -842,6 +1035,19 @@ hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int
         default: set_error("m = %d unsupported", P.m); return HAMLS_ERR_UNSUPPORTED;
     }
     HAMLS_HIP(hipGetLastError());
+    if (P.m > 1) {
+        S2Geom g = make_geom(P);
+        dim3 qg((unsigned)(P.MQ < 2048 ? P.MQ : 2048)), qb(64);
+        int wl = P.prm.wendland;
+        switch (P.K) {
+            case 1: hipLaunchKernelGGL(k_s2_qr<1>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
+            case 2: hipLaunchKernelGGL(k_s2_qr<2>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
+            case 3: hipLaunchKernelGGL(k_s2_qr<3>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
+            case 4: hipLaunchKernelGGL(k_s2_qr<4>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
+            default: break;
+        }
+        HAMLS_HIP(hipGetLastError());
+    }
     return HAMLS_OK;
 }
 

@@ -341,6 +341,8 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     int EG = P.m * (P.m + 1) / 2;
     P.n_entries_cap = EG + (int64_t)P.m * kMaxFieldsPerPass;
     HAMLS_TRY(dalloc(P, &P.d_entries, P.n_entries_cap * P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_qr_list, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_qr_count, 64));
     HAMLS_TRY(dalloc(P, &P.d_vals, (size_t)kMaxFieldsPerPass * P.cap));
 
     // step-3 tables: Legendre table of the northern rings with the GL weights

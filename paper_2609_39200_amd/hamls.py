@@ -174,9 +174,9 @@ def hamls_plan_rebind(plan: int, nodes, node_weights=None, stream=None):
 
 
 def hamls_mls_to_grid(plan: int, values, grid_values, stream=None):
-    """values: (F, M) (row stride = values.stride(0)); grid_values: (F, M_Q)."""
+    """values: (F, M) contiguous; grid_values: (F, M_Q)."""
     F = values.shape[0]
-    _check(_lib.hamls_mls_to_grid(C.c_void_p(plan), _dev(values, "values"), F, values.stride(0),
+    _check(_lib.hamls_mls_to_grid(C.c_void_p(plan), _dev(values, "values"), F, values.shape[1],
                                   _dev(grid_values, "grid_values"), _stream(stream)), "hamls_mls_to_grid")
 
 
