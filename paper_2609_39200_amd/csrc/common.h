@@ -68,6 +68,8 @@ struct Plan {
     double* d_grid = nullptr;       // MQ x 3
     double* d_theta = nullptr;      // per ring
     double* d_phi = nullptr;        // per column
+    double* d_ring_cs = nullptr;    // per ring cos(theta), sin(theta)
+    double* d_col_cs = nullptr;     // per column cos(phi), sin(phi)
     double* d_x = nullptr;          // sorted node coordinates, SoA 3 x cap
     double* d_nu = nullptr;         // sorted node weights (cap) or null
     int32_t* d_perm = nullptr;      // cap

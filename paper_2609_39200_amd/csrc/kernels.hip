@@ -58,6 +58,8 @@ struct S2Geom {
     const double* theta;     // per ring
     const double* phi;       // per column
     int nphi;
+    const double* ring_cs;   // per ring: cos(theta) = x_t, sin(theta)
+    const double* col_cs;    // per column: cos(phi), sin(phi)
     const double* X;         // sorted nodes, SoA 3 x cap
     const double* nu;        // sorted node weights or null
     int64_t cap;
@@ -67,48 +69,178 @@ struct S2Geom {
     double dtheta;
 };
 
-// Calls fn(lo, hi) for every contiguous range of sorted records whose cells
-// meet the geodesic cap of radius r around (thq, phq).  Conservative: a margin
-// of 1e-7 rad covers every rounding in the cell assignment.
-template <class Fn>
-__device__ __forceinline__ void s2_ranges(const S2Geom& g, double thq, double phq, double r,
-                                          Fn&& fn) {
+// Geometry of the cell cover of a geodesic cap (thq, phq, r): the bands it
+// meets and its longitude half-width.  Conservative: a margin of 1e-7 rad
+// covers every rounding in the cell assignment.
+struct CapGeo {
+    int b0, b1;
+    bool full, pole, north;
+    double dphi, cq, sq, crr;
+};
+
+__device__ __forceinline__ CapGeo cap_geo(const S2Geom& g, double thq, double cq, double sq, double r) {
     const double margin = 1e-7;
+    CapGeo G;
     double rr = r + margin;
     int b0 = (int)floor((thq - rr) / g.dtheta);
     int b1 = (int)floor((thq + rr) / g.dtheta);
-    b0 = b0 < 0 ? 0 : b0;
-    b1 = b1 > g.nb - 1 ? g.nb - 1 : b1;
-    bool full = (thq - rr <= 0.0) || (thq + rr >= kPi) || rr >= 0.5 * kPi;
-    double dphi = kPi;
-    if (!full) {
-        double sr = sin(rr) / sin(thq);
-        if (sr >= 1.0)
-            full = true;
+    G.b0 = b0 < 0 ? 0 : b0;
+    G.b1 = b1 > g.nb - 1 ? g.nb - 1 : b1;
+    const bool north = thq - rr <= 0.0, south = thq + rr >= kPi;
+    // A cap that holds a pole narrows in longitude away from it: per band the
+    // half-width is largest at the band edge nearest the pole, where
+    // cos(dphi) = (cos r - cos th cos thq) / (sin th sin thq)  (FP64).
+    G.north = north;
+    G.pole = (north != south) && rr < 0.5 * kPi;
+    G.full = north || south || rr >= 0.5 * kPi;
+    G.dphi = kPi;
+    if (!G.full) {
+        // longitude half-width asin(sin r / sin thq): a bound only, so FP32
+        // with the ratio inflated by 1e-5 and 1e-5 rad added covers its error
+        float sr = sinf((float)rr) / (float)sq * 1.00001f;
+        if (sr >= 1.0f)
+            G.full = true;
         else
-            dphi = asin(sr) + margin;
+            G.dphi = (double)asinf(sr) + 1e-5;
     }
-    for (int b = b0; b <= b1; b++) {
-        int off = g.band_off[b];
-        int ns = g.band_off[b + 1] - off;
-        if (full) {
-            fn(g.cs[off], g.cs[off + ns]);
-            continue;
+    G.cq = cq;
+    G.sq = sq;
+    G.crr = G.pole ? cos(rr) : 0.0;
+    return G;
+}
+
+// The (at most two) record ranges [lo1, lo1+len1), [lo2, lo2+len2) of band b
+// inside the cover.
+__device__ __forceinline__ void band_ranges(const S2Geom& g, const CapGeo& G, int b, double phq,
+                                            int& lo1, int& len1, int& lo2, int& len2) {
+    const double margin = 1e-7;
+    int off = g.band_off[b];
+    int ns = g.band_off[b + 1] - off;
+    bool fullb = G.full;
+    double dphi = G.dphi;
+    lo2 = 0;
+    len2 = 0;
+    if (G.pole) {
+        double te = G.north ? b * g.dtheta : (b + 1) * g.dtheta;  // edge nearest the pole
+        fullb = true;
+        if (te > 1e-12 && te < kPi - 1e-12) {
+            double A = (G.crr - cos(te) * G.cq) / (sin(te) * G.sq);
+            if (A > -1.0) {
+                fullb = false;
+                dphi = A >= 1.0 ? margin : acos(A) + 4.0 * margin;
+            }
         }
+    }
+    int sa = 0, sb = ns - 1, sc = 0, sd = -1;  // sector ranges [sa, sb], [sc, sd]
+    if (!fullb) {
         double wdt = 2.0 * kPi / ns;
         int s0 = (int)floor((phq - dphi) / wdt);
         int s1 = (int)floor((phq + dphi) / wdt);
-        if (s1 - s0 + 1 >= ns) {
-            fn(g.cs[off], g.cs[off + ns]);
-        } else if (s0 < 0) {
-            fn(g.cs[off + s0 + ns], g.cs[off + ns]);
-            fn(g.cs[off], g.cs[off + s1 + 1]);
-        } else if (s1 >= ns) {
-            fn(g.cs[off + s0], g.cs[off + ns]);
-            fn(g.cs[off], g.cs[off + s1 - ns + 1]);
-        } else {
-            fn(g.cs[off + s0], g.cs[off + s1 + 1]);
+        if (s1 - s0 + 1 < ns) {
+            if (s0 < 0) {
+                sa = s0 + ns;
+                sb = ns - 1;
+                sc = 0;
+                sd = s1;
+            } else if (s1 >= ns) {
+                sa = s0;
+                sb = ns - 1;
+                sc = 0;
+                sd = s1 - ns;
+            } else {
+                sa = s0;
+                sb = s1;
+            }
         }
+    }
+    lo1 = g.cs[off + sa];
+    len1 = g.cs[off + sb + 1] - lo1;
+    if (sd >= sc) {
+        lo2 = g.cs[off + sc];
+        len2 = g.cs[off + sd + 1] - lo2;
+    }
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan_int(int v) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Number of sorted records in the cell cover of a cap (an upper bound on the
+// nodes inside it), from the cell table alone, one band per lane.
+__device__ __forceinline__ int s2_cover_count(const S2Geom& g, double thq, double cq, double sq,
+                                              double phq, double r) {
+    CapGeo G = cap_geo(g, thq, cq, sq, r);
+    const int lane = threadIdx.x & 63;
+    int tot = 0;
+    for (int bb = G.b0; bb <= G.b1; bb += 64) {
+        int b = bb + lane, lo1 = 0, len1 = 0, lo2 = 0, len2 = 0;
+        if (b <= G.b1) band_ranges(g, G, b, phq, lo1, len1, lo2, len2);
+        tot += wave_sum_int(len1 + len2);
+    }
+    return tot;
+}
+
+// Ints of LDS one wave needs for s2_scan.
+constexpr int kScanLds = 4 * 64 + 1;
+
+// Visits every sorted record in the cell cover of the cap, 64*U per step: the
+// lanes first enumerate up to 64 bands at once, a wave prefix sum flattens
+// their ranges, and every step then hands each lane U slots of the flattened
+// list (slot base + 64u + lane), so that U independent record loads per lane
+// are in flight before any is used.  body(valid[U], idx[U]) is called by all
+// 64 lanes in every step (idx = sorted record index, meaningful when valid),
+// so body may synchronise the wave.
+template <int U, class Fn>
+__device__ __forceinline__ void s2_scan(const S2Geom& g, double thq, double cq, double sq, double phq,
+                                        double r, int* sh, Fn&& body) {
+    CapGeo G = cap_geo(g, thq, cq, sq, r);
+    const int lane = threadIdx.x & 63;
+    int* s_lo1 = sh;
+    int* s_len1 = sh + 64;
+    int* s_lo2 = sh + 128;
+    int* s_pre = sh + 192;  // 65 entries
+    for (int bb = G.b0; bb <= G.b1; bb += 64) {
+        int b = bb + lane, lo1 = 0, len1 = 0, lo2 = 0, len2 = 0;
+        if (b <= G.b1) band_ranges(g, G, b, phq, lo1, len1, lo2, len2);
+        int len = len1 + len2;
+        int incl = wave_incl_scan_int(len);
+        int total = __shfl(incl, 63, 64);
+        s_lo1[lane] = lo1;
+        s_len1[lane] = len1;
+        s_lo2[lane] = lo2;
+        s_pre[lane] = incl - len;
+        if (lane == 63) s_pre[64] = incl;
+        __syncthreads();
+        int kc = 0;
+        for (int base = 0; base < total; base += 64 * U) {
+            while (s_pre[kc + 1] <= base) kc++;  // band of the step's first slot
+            bool valid[U];
+            int idx[U];
+            int k = kc;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                int sl = base + 64 * u + lane;
+                valid[u] = sl < total;
+                idx[u] = 0;
+                if (valid[u]) {
+                    while (s_pre[k + 1] <= sl) k++;
+                    int o = sl - s_pre[k];
+                    idx[u] = o < s_len1[k] ? s_lo1[k] + o : s_lo2[k] + (o - s_len1[k]);
+                }
+            }
+            body(valid, idx);
+        }
+        __syncthreads();
     }
 }
 
@@ -326,6 +458,8 @@ S2Geom make_geom(const Plan& P) {
     g.theta = P.d_theta;
     g.phi = P.d_phi;
     g.nphi = P.dims[1];
+    g.ring_cs = P.d_ring_cs;
+    g.col_cs = P.d_col_cs;
     g.X = P.d_x;
     g.nu = P.has_nu ? P.d_nu : nullptr;
     g.cap = P.cap;
@@ -350,74 +484,194 @@ __device__ __forceinline__ double from_ordered_bits(uint64_t u) {
     return __longlong_as_double((long long)b);
 }
 
-// One block (one wave) per grid node.  Adaptive radius: find a search radius
-// whose cap holds between n and kCandCap nodes, keep their keys in LDS and take
-// the n-th largest exactly; if the cap cannot be sized (duplicates), fall back
-// to a bitwise binary search on the key.  delta = (1+eps) d_n, merged with a
-// fixed delta_0 if both are set, clamped to pi/2 (Sec. 2.3 needs delta < pi/2).
+
+// Support radius, one grid node per block (one wave):
+//  1. an initial radius from the cell density around the node; only where the
+//     surroundings are sparse (holes), grow it on the cell-cover count (cell
+//     table only, no record reads) until the cover holds 3n nodes;
+//  2. scan the cap, keeping the keys dot > cos r in LDS; if fewer than n or
+//     more than kCandCap, resize (bracketed) and rescan;
+//  3. the n-th largest key t_n exactly (rank count); if the search cannot be
+//     sized (duplicates), a bitwise binary search over the key instead.
+// delta = (1+eps) arccos(t_n), merged with a fixed delta_0 if both are set,
+// clamped to pi/2 (the tangent projection needs delta < pi/2).
 __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
                                                  double delta0, double c_fixed, double* thr,
                                                  double* delta, uint8_t* rstatus) {
+    constexpr int U = 4;
+    constexpr int kBinCap = 128;
     __shared__ double buf[kCandCap];
-    int j = blockIdx.x;
-    int lane = threadIdx.x;
-    int t = j / g.nphi, p = j - t * g.nphi;
-    double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
-    double thq = g.theta[t], phq = g.phi[p];
+    __shared__ double binbuf[kBinCap];
+    __shared__ int sh[kScanLds];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int t = j / g.nphi, p = j - t * g.nphi;
+    const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+    const double thq = g.theta[t], phq = g.phi[p];
+    const double cq = g.ring_cs[2 * t], sq = g.ring_cs[2 * t + 1];
     uint8_t st = 0;
     double dl = delta0, c = c_fixed;
     if (knn > 0) {
-        // initial radius from the local cell density
         int bq = (int)(thq / g.dtheta);
         bq = bq > g.nb - 1 ? g.nb - 1 : bq;
         int off = g.band_off[bq], ns = g.band_off[bq + 1] - off;
-        int sq = (int)(phq * (ns / (2.0 * kPi)));
-        sq = sq > ns - 1 ? ns - 1 : sq;
+        int sc0 = (int)(phq * (ns / (2.0 * kPi)));
+        sc0 = sc0 > ns - 1 ? ns - 1 : sc0;
         int cnt3 = 0, nsec = 3;
         if (ns <= 3) {
             cnt3 = g.cs[off + ns] - g.cs[off];
             nsec = ns;
         } else {
-            for (int ds = -1; ds <= 1; ds++) {
-                int sc = (sq + ds + ns) % ns;
-                cnt3 += g.cs[off + sc + 1] - g.cs[off + sc];
+            int a0 = (sc0 + ns - 1) % ns, a2 = (sc0 + 1) % ns;
+            cnt3 = (g.cs[off + a0 + 1] - g.cs[off + a0]) + (g.cs[off + sc0 + 1] - g.cs[off + sc0]) +
+                   (g.cs[off + a2 + 1] - g.cs[off + a2]);
+        }
+        double r;
+        if (cnt3 >= 4) {
+            double area = (2.0 * kPi / ns) * nsec * (cos(bq * g.dtheta) - cos((bq + 1) * g.dtheta));
+            r = fmin(1.2 * sqrt((double)knn * area / (kPi * cnt3)), 0.5 * kPi);
+        } else {
+            // grow on the cover count to a bracket [rl, r] around 3n covered
+            // nodes, then bisect it three times
+            r = fmin(2.0 * sqrt((double)knn / (double)M), 0.5 * kPi);
+            double rl = 0.0;
+            for (int it = 0; it < 24 && r < 0.5 * kPi; it++) {
+                int cov = s2_cover_count(g, thq, cq, sq, phq, r);
+                if (cov >= 3 * knn) break;
+                rl = r;
+                r = fmin(0.5 * kPi, r * (cov < knn / 2 ? 1.6 : 1.25));
+            }
+            for (int it = 0; it < 3 && rl > 0.0; it++) {
+                double rm = sqrt(rl * r);
+                if (s2_cover_count(g, thq, cq, sq, phq, rm) >= 3 * knn)
+                    r = rm;
+                else
+                    rl = rm;
             }
         }
-        double area = (2.0 * kPi / ns) * nsec * (cos(bq * g.dtheta) - cos((bq + 1) * g.dtheta));
-        double r = 2.0 * sqrt((double)knn / (double)M);
-        if (cnt3 >= 4) r = 1.15 * sqrt((double)knn * area / (kPi * cnt3));
-        r = fmin(r, 0.5 * kPi);
         double r_lo = 0.0, r_hi = 0.0;  // known too small / too large
         double tn = -2.0;
         bool done = false, hemi = false;
         for (int it = 0; it < 40 && !done; it++) {
-            double cr = cos(r);
+            const double cr = cos(r);
             int count = 0;
-            s2_ranges(g, thq, phq, r, [&](int lo, int hi) {
-                for (int base = lo; base < hi; base += 64) {
-                    int i = base + lane;
-                    bool valid = i < hi;
-                    double d = -2.0;
-                    if (valid) d = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2);
-                    bool in = valid && d > cr;
+            s2_scan<U>(g, thq, cq, sq, phq, r, sh, [&](const bool* valid, const int* idx) {
+                double d[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    d[u] = -2.0;
+                    if (valid[u]) {
+                        int i = idx[u];
+                        d[u] = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    bool in = d[u] > cr;
                     uint64_t mk = __ballot(in);
                     int pos = count + rank_below(mk);
-                    if (in && pos < kCandCap) buf[pos] = d;
+                    if (in && pos < kCandCap) buf[pos] = d[u];
                     count += __popcll(mk);
                 }
             });
             __syncthreads();
             if (count >= knn && count <= kCandCap) {
+                // n-th largest key: the value with fewer than n keys above it
+                // and at least n at or above it
                 double found = -3.0;
-                for (int a = lane; a < count; a += 64) {
-                    double v = buf[a];
-                    int gt = 0, ge = 0;
+                if (count <= 256) {
+                    double v[4];
+                    int gt[4] = {0, 0, 0, 0}, ge[4] = {0, 0, 0, 0};
+#pragma unroll
+                    for (int q = 0; q < 4; q++) v[q] = lane + 64 * q < count ? buf[lane + 64 * q] : 3.0;
+#pragma unroll 4
                     for (int b = 0; b < count; b++) {
                         double u = buf[b];
-                        gt += u > v;
-                        ge += u >= v;
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            gt[q] += u > v[q];
+                            ge[q] += u >= v[q];
+                        }
                     }
-                    if (gt < knn && knn <= ge) found = v;
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        if (lane + 64 * q < count && gt[q] < knn && knn <= ge[q]) found = v[q];
+                } else {
+                    // histogram select: bins of 1 - key (monotone in the key)
+                    // over [0, 1 - cos r); keys of lower bins are larger
+                    int* hist = sh;
+                    const double scale = 256.0 / (1.0 - cr);
+#pragma unroll
+                    for (int q = 0; q < 4; q++) hist[4 * lane + q] = 0;
+                    __syncthreads();
+                    for (int a = lane; a < count; a += 64) {
+                        int bin = (int)((1.0 - buf[a]) * scale);
+                        bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
+                        atomicAdd(&hist[bin], 1);
+                    }
+                    __syncthreads();
+                    int h4[4], s4 = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        h4[q] = hist[4 * lane + q];
+                        s4 += h4[q];
+                    }
+                    int incl = wave_incl_scan_int(s4);
+                    int before = incl - s4, bsel = -1, bbefore = 0;
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        if (bsel < 0 && before < knn && knn <= before + h4[q]) {
+                            bsel = 4 * lane + q;
+                            bbefore = before;
+                        }
+                        before += h4[q];
+                    }
+                    uint64_t owner = __ballot(bsel >= 0);
+                    int src = __ffsll((unsigned long long)owner) - 1;
+                    const int B = __shfl(bsel, src, 64);
+                    const int kth = knn - __shfl(bbefore, src, 64);  // rank inside bin B
+                    const int nB = hist[B];
+                    __syncthreads();
+                    if (nB <= kBinCap) {
+                        int m = 0;
+                        for (int base = 0; base < count; base += 64) {
+                            int a = base + lane;
+                            bool inb = false;
+                            double v = 0.0;
+                            if (a < count) {
+                                v = buf[a];
+                                int bin = (int)((1.0 - v) * scale);
+                                bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
+                                inb = bin == B;
+                            }
+                            uint64_t mk = __ballot(inb);
+                            if (inb) binbuf[m + rank_below(mk)] = v;
+                            m += __popcll(mk);
+                        }
+                        __syncthreads();
+                        for (int a = lane; a < nB; a += 64) {
+                            double v = binbuf[a];
+                            int gt = 0, ge = 0;
+                            for (int b = 0; b < nB; b++) {
+                                double u = binbuf[b];
+                                gt += u > v;
+                                ge += u >= v;
+                            }
+                            if (gt < kth && kth <= ge) found = v;
+                        }
+                    } else {
+                        for (int a = lane; a < count; a += 64) {
+                            double v = buf[a];
+                            int gt = 0, ge = 0;
+#pragma unroll 4
+                            for (int b = 0; b < count; b++) {
+                                double u = buf[b];
+                                gt += u > v;
+                                ge += u >= v;
+                            }
+                            if (gt < knn && knn <= ge) found = v;
+                        }
+                    }
                 }
                 tn = wave_max(found);
                 done = true;
@@ -428,7 +682,8 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
                 } else {
                     r_lo = r;
                     double grow = 1.25 * sqrt((double)knn / (double)(count > 0 ? count : 1));
-                    double nr = r * (grow > 1.5 ? grow : 1.5);
+                    grow = grow < 1.25 ? 1.25 : (grow > 2.0 ? 2.0 : grow);
+                    double nr = r * grow;
                     if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(r * r_hi);
                     r = fmin(nr, 0.5 * kPi);
                 }
@@ -450,14 +705,13 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
                 uint64_t mid = lo + (hi - lo + 1) / 2;
                 double v = from_ordered_bits(mid);
                 int count = 0;
-                s2_ranges(g, thq, phq, r, [&](int a0, int a1) {
-                    for (int base = a0; base < a1; base += 64) {
-                        int i = base + lane;
-                        bool in = false;
-                        if (i < a1)
-                            in = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2) >= v;
-                        count += __popcll(__ballot(in));
+                s2_scan<1>(g, thq, cq, sq, phq, r, sh, [&](const bool* valid, const int* idx) {
+                    bool in = false;
+                    if (valid[0]) {
+                        int i = idx[0];
+                        in = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2) >= v;
                     }
+                    count += __popcll(__ballot(in));
                 });
                 if (count >= knn)
                     lo = mid;
@@ -467,10 +721,7 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
             tn = from_ordered_bits(lo);
         }
         double dk = hemi ? kPi : (1.0 + eps) * acos(fmin(1.0, fmax(-1.0, tn)));
-        if (delta0 > 0.0 && delta0 >= dk) {
-            dl = delta0;
-            c = c_fixed;
-        } else {
+        if (!(delta0 > 0.0 && delta0 >= dk)) {
             dl = dk;
             if (dl >= 0.5 * kPi) {
                 dl = 0.5 * kPi;
@@ -517,12 +768,14 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
     constexpr int ROW = m + kMaxFieldsPerPass + 1;
     constexpr int KE = (EG + m * kMaxFieldsPerPass + 63) / 64;
     __shared__ double rows[64 * ROW];
+    __shared__ int sh[kScanLds];
     int j = blockIdx.x;
     int lane = threadIdx.x;
     int t = j / g.nphi, p = j - t * g.nphi;
     double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
     double thq = g.theta[t], phq = g.phi[p];
-    double ct = cos(thq), stt = sin(thq), cp = cos(phq), sp = sin(phq);
+    const double ct = g.ring_cs[2 * t], stt = g.ring_cs[2 * t + 1];
+    const double cp = g.col_cs[2 * p], sp = g.col_cs[2 * p + 1];
     double et0 = ct * cp, et1 = ct * sp, et2 = -stt;
     double ep0 = -sp, ep1 = cp;
     const double c = thr[j], dl = delta[j];
@@ -551,10 +804,10 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
         }
     }
     int count = 0;
-    s2_ranges(g, thq, phq, dl, [&](int lo, int hi) {
-        for (int base = lo; base < hi; base += 64) {
-            int i = base + lane;
-            bool valid = i < hi;
+    s2_scan<1>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid_, const int* idx_) {
+        {
+            const bool valid = valid_[0];
+            const int i = idx_[0];
             double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
             if (valid) {
                 x0 = g.X[i];
@@ -565,7 +818,7 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
             bool in = valid && d > c;
             uint64_t mk = __ballot(in);
             int nin = __popcll(mk);
-            if (nin == 0) continue;
+            if (nin == 0) return;
             if (in) {
                 int pos = rank_below(mk);
                 double dist = acos(fmin(d, 1.0));
@@ -630,10 +883,12 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s) {
 // local solve (eq. (15)-(23))
 // ---------------------------------------------------------------------------
 
-// A centre whose normal-matrix factorisation is not trustworthy to ~1e-12 is
-// re-solved by QR: Cholesky failure, condition estimate 1/min pivot of C (unit
-// diagonal) above kCondQR, or chi above kCondQR.
-constexpr double kCondQR = 1e4;
+// A centre whose normal-matrix solve is not trustworthy to ~1e-10 is re-solved
+// by QR: Cholesky failure, a pivot of the unit-diagonal C below kPivQR
+// (condition estimate above 1e8), or a Schur denominator below kDenQR
+// (regularized chi_tau above 1e4, where 1 - sum d^2/(1 + tau mu) cancels).
+constexpr double kPivQR = 1e-8;
+constexpr double kDenQR = 1e-4;
 // |R_jj| of the unit-column V at or below which V is taken as rank deficient.
 constexpr double kRankTol = 1e-11;
 
@@ -781,20 +1036,25 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
                 r0 += d2[r];
             }
             chi = 1.0 / (1.0 - r0);
-            if (!(chi >= 1.0) || chi > kCondQR || 1.0 / minpiv > kCondQR) ill = true;
+            if (!(chi >= 1.0) || minpiv < kPivQR) ill = true;
+        }
+        double den = 1.0;
+        double fac[NC > 0 ? NC : 1];
+        if (!ill) {
+            tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
+#pragma unroll
+            for (int r = 0; r < NC; r++) {
+                fac[r] = d[r] / (1.0 + tau * A.mu[r]);
+                den -= fac[r] * d[r];
+            }
+            // the Schur denominator 1 - sum d^2/(1 + tau mu) cancels when the
+            // regularized chi_tau = 1/den is large
+            if (!(den > kDenQR)) ill = true;
         }
         if (ill) {
             int slot = atomicAdd(A.qr_count, 1);
             A.qr_list[slot] = (int32_t)j;
             return;
-        }
-        tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
-        double den = 1.0;
-        double fac[NC > 0 ? NC : 1];
-#pragma unroll
-        for (int r = 0; r < NC; r++) {
-            fac[r] = d[r] / (1.0 + tau * A.mu[r]);
-            den -= fac[r] * d[r];
         }
         for (int f = 0; f < A.F; f++) {
             double z[NC > 0 ? NC : 1];
@@ -851,6 +1111,7 @@ __global__ __launch_bounds__(64) void k_s2_qr(S2Geom g, const double* __restrict
     constexpr int NC = m - 1;
     constexpr int LD = m + 1 + kMaxFieldsPerPass;
     __shared__ double T[(m + 64) * LD];
+    __shared__ int sh[kScanLds];
     const int lane = threadIdx.x;
     const int F = A.F;
     const int cols = m + F;
@@ -862,7 +1123,8 @@ __global__ __launch_bounds__(64) void k_s2_qr(S2Geom g, const double* __restrict
         const int t = j / g.nphi, p = j - t * g.nphi;
         const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
         const double thq = g.theta[t], phq = g.phi[p];
-        const double ct = cos(thq), stt = sin(thq), cp = cos(phq), sp = sin(phq);
+        const double ct = g.ring_cs[2 * t], stt = g.ring_cs[2 * t + 1];
+        const double cp = g.col_cs[2 * p], sp = g.col_cs[2 * p + 1];
         const double et0 = ct * cp, et1 = ct * sp, et2 = -stt, ep0 = -sp, ep1 = cp;
         const double c = thr[j], dl = delta[j], idl = 1.0 / dl;
         const double W = A.entries[j];
@@ -871,10 +1133,10 @@ __global__ __launch_bounds__(64) void k_s2_qr(S2Geom g, const double* __restrict
         for (int a = 0; a < m; a++) isc[a] = 1.0 / sqrt(A.entries[(int64_t)gidx(a, a) * MQ + j] / W);
         for (int e = lane; e < m * LD; e += 64) T[e] = 0.0;
         __syncthreads();
-        s2_ranges(g, thq, phq, dl, [&](int lo, int hi) {
-            for (int base = lo; base < hi; base += 64) {
-                int i = base + lane;
-                bool valid = i < hi;
+        s2_scan<1>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid_, const int* idx_) {
+            {
+                const bool valid = valid_[0];
+                const int i = idx_[0];
                 double x0 = 0.0, x1 = 0.0, x2 = 0.0, dd = -2.0;
                 if (valid) {
                     x0 = g.X[i];
@@ -885,7 +1147,7 @@ __global__ __launch_bounds__(64) void k_s2_qr(S2Geom g, const double* __restrict
                 bool in = valid && dd > c;
                 uint64_t mk = __ballot(in);
                 int nin = __popcll(mk);
-                if (nin == 0) continue;
+                if (nin == 0) return;
                 if (in) {
                     double w = wendland_phi(wendland, acos(fmin(dd, 1.0)) * idl);
                     if (g.nu) w *= g.nu[i];
@@ -1067,15 +1329,16 @@ __global__ __launch_bounds__(64) void k_s2_list(S2Geom g, const double* __restri
     double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
     double c = thr[j];
     int count = 0;
-    s2_ranges(g, g.theta[t], g.phi[p], delta[j], [&](int lo, int hi) {
-        for (int base = lo; base < hi; base += 64) {
-            int i = base + lane;
-            bool in = false;
-            if (i < hi) in = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2) > c;
-            uint64_t mk = __ballot(in);
-            if (in && idx) idx[row_ptr[j] + count + rank_below(mk)] = perm[i];
-            count += __popcll(mk);
-        }
+    __shared__ int sh[kScanLds];
+    s2_scan<1>(g, g.theta[t], g.ring_cs[2 * t], g.ring_cs[2 * t + 1], g.phi[p], delta[j], sh,
+               [&](const bool* valid_, const int* idx_) {
+        const bool valid = valid_[0];
+        const int i = idx_[0];
+        bool in = false;
+        if (valid) in = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2) > c;
+        uint64_t mk = __ballot(in);
+        if (in && idx) idx[row_ptr[j] + count + rank_below(mk)] = perm[i];
+        count += __popcll(mk);
     });
     if (lane == 0 && counts) counts[j] = count;
 }

@@ -320,6 +320,8 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     HAMLS_TRY(dalloc(P, &P.d_grid, 3 * P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_theta, nt));
     HAMLS_TRY(dalloc(P, &P.d_phi, np));
+    HAMLS_TRY(dalloc(P, &P.d_ring_cs, 2 * (size_t)nt));
+    HAMLS_TRY(dalloc(P, &P.d_col_cs, 2 * (size_t)np));
     HAMLS_TRY(dalloc(P, &P.d_x, 3 * P.cap));
     HAMLS_TRY(dalloc(P, &P.d_nu, P.cap));
     HAMLS_TRY(dalloc(P, &P.d_perm, P.cap));
@@ -368,6 +370,17 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     HAMLS_HIP(hipMemcpyAsync(P.d_theta, P.h_theta.data(), sizeof(double) * nt,
                              hipMemcpyHostToDevice, s));
     HAMLS_HIP(hipMemcpyAsync(P.d_phi, P.h_phi.data(), sizeof(double) * np, hipMemcpyHostToDevice, s));
+    std::vector<double> rcs(2 * (size_t)nt), ccs(2 * (size_t)np);
+    for (int t = 0; t < nt; t++) {
+        rcs[2 * t] = P.h_glx[t];
+        rcs[2 * t + 1] = sqrt((1.0 - P.h_glx[t]) * (1.0 + P.h_glx[t]));
+    }
+    for (int q = 0; q < np; q++) {
+        ccs[2 * q] = cphi[q];
+        ccs[2 * q + 1] = sphi[q];
+    }
+    HAMLS_HIP(hipMemcpyAsync(P.d_ring_cs, rcs.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipMemcpyAsync(P.d_col_cs, ccs.data(), sizeof(double) * 2 * np, hipMemcpyHostToDevice, s));
     HAMLS_HIP(hipMemcpyAsync(P.d_band_off, P.bins.band_off.data(), sizeof(int32_t) * (P.bins.nb + 1),
                              hipMemcpyHostToDevice, s));
     HAMLS_HIP(hipMemcpyAsync(P.d_ptab, tab.data(), sizeof(double) * P.ptab_len,
