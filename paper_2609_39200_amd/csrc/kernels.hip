@@ -39,6 +39,17 @@ __device__ __forceinline__ int rank_below(uint64_t mask) {
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Workgroups are dealt round-robin over the 8 XCDs (each with its own L2).
+// Within every group of 512 workgroups, XCD x takes the 64 consecutive work
+// items [64x, 64x + 64): neighbouring grid nodes (sharing candidate records)
+// stay on one L2, while expensive regions (holes) still spread over all XCDs.
+// A trailing partial group keeps the identity order.
+__device__ __forceinline__ int xcd_block(int bid, int nblk) {
+    const int g = bid >> 9;
+    if ((g + 1) << 9 > nblk) return bid;
+    return (g << 9) + ((bid & 7) << 6) + ((bid >> 3) & 63);
+}
+
 __device__ __forceinline__ double wendland_phi(int which, double r) {
     if (r >= 1.0) return 0.0;
     double s = 1.0 - r;
@@ -503,7 +514,7 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
     __shared__ double buf[kCandCap];
     __shared__ double binbuf[kBinCap];
     __shared__ int sh[kScanLds];
-    const int j = blockIdx.x;
+    const int j = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     const int t = j / g.nphi, p = j - t * g.nphi;
     const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
@@ -753,10 +764,11 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
 // ---------------------------------------------------------------------------
 
 // Entries per grid node: G_ab = sum_i w_i g_a g_b for a <= b (row-major upper
-// triangle, G_00 = sum w), then h_af = sum_i w_i g_a y_if.  Rows of
-// (sqrt(w) g, sqrt(w) y) are staged in LDS 64 at a time; each lane owns a few
-// entries and sums them over the staged rows.
-template <int K>
+// triangle, G_00 = sum w), then h_af = sum_i w_i g_a y_if.  Candidates are
+// fetched 64*U per step (U record loads per lane in flight); member rows of
+// (sqrt(w) g, sqrt(w) y) are staged in LDS 64 at a time and each lane owns a
+// few entries, summed over the staged rows.  FM bounds the fields of one pass.
+template <int K, int FM>
 __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __restrict__ vals,
                                                    int F, int wendland,
                                                    const double* __restrict__ thr,
@@ -765,22 +777,23 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
                                                    int32_t* __restrict__ nj) {
     constexpr int m = (K + 1) * (K + 2) / 2;
     constexpr int EG = m * (m + 1) / 2;
-    constexpr int ROW = m + kMaxFieldsPerPass + 1;
-    constexpr int KE = (EG + m * kMaxFieldsPerPass + 63) / 64;
+    constexpr int ROW = m + FM + 1;
+    constexpr int KE = (EG + m * FM + 63) / 64;
+    constexpr int U = FM == 1 ? 4 : 1;
     __shared__ double rows[64 * ROW];
     __shared__ int sh[kScanLds];
-    int j = blockIdx.x;
-    int lane = threadIdx.x;
-    int t = j / g.nphi, p = j - t * g.nphi;
-    double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
-    double thq = g.theta[t], phq = g.phi[p];
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    const int t = j / g.nphi, p = j - t * g.nphi;
+    const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+    const double thq = g.theta[t], phq = g.phi[p];
     const double ct = g.ring_cs[2 * t], stt = g.ring_cs[2 * t + 1];
     const double cp = g.col_cs[2 * p], sp = g.col_cs[2 * p + 1];
-    double et0 = ct * cp, et1 = ct * sp, et2 = -stt;
-    double ep0 = -sp, ep1 = cp;
+    const double et0 = ct * cp, et1 = ct * sp, et2 = -stt;
+    const double ep0 = -sp, ep1 = cp;
     const double c = thr[j], dl = delta[j];
     const double idl = 1.0 / dl;
-    int E = EG + m * F;
+    const int E = EG + m * F;
     int ca[KE], cb[KE];
     double acc[KE];
 #pragma unroll
@@ -804,44 +817,65 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
         }
     }
     int count = 0;
-    s2_scan<1>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid_, const int* idx_) {
-        {
-            const bool valid = valid_[0];
-            const int i = idx_[0];
-            double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
-            if (valid) {
-                x0 = g.X[i];
-                x1 = g.X[g.cap + i];
-                x2 = g.X[2 * g.cap + i];
-                d = s2_dot(x0, x1, x2, q0, q1, q2);
+    s2_scan<U>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
+        double x0[U], x1[U], x2[U], d[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            x0[u] = 0.0;
+            x1[u] = 0.0;
+            x2[u] = 0.0;
+            d[u] = -2.0;
+            if (valid[u]) {
+                int i = idx[u];
+                x0[u] = g.X[i];
+                x1[u] = g.X[g.cap + i];
+                x2[u] = g.X[2 * g.cap + i];
             }
-            bool in = valid && d > c;
-            uint64_t mk = __ballot(in);
-            int nin = __popcll(mk);
-            if (nin == 0) return;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (valid[u]) d[u] = s2_dot(x0[u], x1[u], x2[u], q0, q1, q2);
+        // field values and node weights of the members, all loads in flight
+        double y1[U], nw[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            y1[u] = 0.0;
+            nw[u] = 1.0;
+            if (d[u] > c) {
+                if (FM == 1) y1[u] = vals[idx[u]];
+                if (g.nu) nw[u] = g.nu[idx[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const bool in = d[u] > c;
+            const uint64_t mk = __ballot(in);
+            const int nin = __popcll(mk);
+            if (nin == 0) continue;
             if (in) {
-                int pos = rank_below(mk);
-                double dist = acos(fmin(d, 1.0));
-                double w = wendland_phi(wendland, dist * idl);
-                if (g.nu) w *= g.nu[i];
+                const int i = idx[u];
+                double w = wendland_phi(wendland, acos(fmin(d[u], 1.0)) * idl) * nw[u];
                 double sw = sqrt(w);
-                double u = (x0 * et0 + x1 * et1 + x2 * et2) * idl;
-                double v = (x0 * ep0 + x1 * ep1) * idl;
+                double uu = (x0[u] * et0 + x1[u] * et1 + x2[u] * et2) * idl;
+                double vv = (x0[u] * ep0 + x1[u] * ep1) * idl;
                 double pu[K + 1], pv[K + 1];
                 pu[0] = 1.0;
                 pv[0] = 1.0;
 #pragma unroll
                 for (int a = 1; a <= K; a++) {
-                    pu[a] = pu[a - 1] * u;
-                    pv[a] = pv[a - 1] * v;
+                    pu[a] = pu[a - 1] * uu;
+                    pv[a] = pv[a - 1] * vv;
                 }
-                double* row = rows + pos * ROW;
+                double* row = rows + rank_below(mk) * ROW;
                 int cidx = 0;
 #pragma unroll
                 for (int l = 0; l <= K; l++)
 #pragma unroll
-                    for (int b = 0; b <= l; b++) row[cidx++] = sw * pu[l - b] * pv[b];
-                for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
+                    for (int b2 = 0; b2 <= l; b2++) row[cidx++] = sw * pu[l - b2] * pv[b2];
+                if (FM == 1)
+                    row[m] = sw * y1[u];
+                else
+                    for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
             }
             __syncthreads();
             for (int r = 0; r < nin; r++) {
@@ -867,14 +901,22 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s) {
     S2Geom g = make_geom(P);
     dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
+#define HAMLS_ASM(KK)                                                                             \
+    if (F == 1)                                                                                   \
+        hipLaunchKernelGGL((k_s2_assemble<KK, 1>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
+                           P.d_delta, P.d_entries, P.MQ, P.d_nj);                                 \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass>), grid, block, 0, s, g, P.d_vals, \
+                           F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj);
     switch (P.K) {
-        case 0: hipLaunchKernelGGL(k_s2_assemble<0>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
-        case 1: hipLaunchKernelGGL(k_s2_assemble<1>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
-        case 2: hipLaunchKernelGGL(k_s2_assemble<2>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
-        case 3: hipLaunchKernelGGL(k_s2_assemble<3>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
-        case 4: hipLaunchKernelGGL(k_s2_assemble<4>, grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj); break;
+        case 0: HAMLS_ASM(0) break;
+        case 1: HAMLS_ASM(1) break;
+        case 2: HAMLS_ASM(2) break;
+        case 3: HAMLS_ASM(3) break;
+        case 4: HAMLS_ASM(4) break;
         default: set_error("degree %d unsupported on S2", P.K); return HAMLS_ERR_UNSUPPORTED;
     }
+#undef HAMLS_ASM
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
