@@ -33,6 +33,38 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble", "solve": "k_solve",
+                "ring_dft": "k_s2_ring_dft", "contract": "k_s2_legendre", "gather": "k_gather_values"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "s2_c2_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_2609_39200_amd", "csrc", "kernels.hip")
+    if kernel is None or not os.path.exists(path):
+        return None
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    info = {}
+    kern = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "kernel":
+            kern[f[1]] = dict(zip(f[2::2], f[3::2]))
+        else:
+            info[f[0]] = f[1]
+    if info.get("source_sha256") != cur or kernel not in kern:
+        return None
+    k = kern[kernel]
+    fs, ws = float(info["fetch_scale"]), float(info["write_scale"])
+    return (float(k["fetch_kib"]) * fs + float(k["write_kib"]) * ws) * 1024.0
+
+
 def flops_per_pair(m, F):
     """Algorithmic FLOPs of one (grid node, neighbour) pair in the fused MLS
     step: predicate 5, tangent coordinates 12, weight 10 (distance, Wendland,
@@ -49,6 +81,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy a 256 MiB buffer three times (known-size traffic for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU design is "
@@ -115,11 +150,12 @@ def main():
     m = info.m
     dom = max(phases, key=lambda k: phases[k]["avg_ms"])
     roof = None
+    traffic = measured_traffic(PHASE_KERNEL.get(dom))
     if dom == "assemble":
         fl = pairs * flops_per_pair(m, F)
         ach = fl / (phases[dom]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "assemble", "bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
                 "units_per_launch": {"pairs": pairs, "flop_per_pair": flops_per_pair(m, F)}}
     else:
         # other phases are priced on their algorithmic HBM bytes
@@ -140,7 +176,7 @@ def main():
         b = bytes_by_phase.get(dom, 0)
         ach = b / (phases[dom]["avg_ms"] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None, "units_per_launch": {"bytes": b}}
+                "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "units_per_launch": {"bytes": b}}
 
     out = {
         "metric": "MLS grid nodes solved/s (whole fit: binning + radii + local solves + quadrature)",
@@ -172,6 +208,13 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = cpu_baseline(wl, plan, gv, H, args.cpu_seconds)
     H.hamls_plan_destroy(plan)
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel() * 8
     print(json.dumps(out), flush=True)
 
 
