@@ -45,6 +45,17 @@ struct S2Bins {
     int key_bits = 0;
 };
 
+// Uniform cell grid of the SO3 and T3 domains: nc cells of width h per axis,
+// axis cell i covering [lo + i h, lo + (i+1) h); D = 4 (SO3 quaternions) or
+// 3 (T3, periodic).  Cell key = row-major index over the D axes.
+struct GridBins {
+    int D = 0;
+    int nc = 0;
+    double lo = 0.0, h = 0.0;
+    int64_t ncells = 0;
+    int key_bits = 0;
+};
+
 struct DeviceBuf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -56,21 +67,27 @@ struct Plan {
     int dom = 0, N = 0, K = 0, m = 1, D = 2;
     int32_t dims[3] = {0, 0, 0};
     int64_t MQ = 0, ncoef = 0;
-    int64_t M = 0, cap = 0;
+    int64_t M = 0;      // bound nodes
+    int64_t nrec = 0;   // sorted records (SO3 stores q and -q: 2M)
+    int64_t mcap = 0;   // node capacity of the plan
+    int64_t cap = 0;    // record capacity
     bool has_nu = false;
     S2Bins bins;
+    GridBins gbins;
+    int64_t ncells = 0;
+    int key_bits = 0;
 
     // host copies
     std::vector<double> h_grid, h_wts, h_theta, h_phi, h_glx, h_glw;
 
     // device allocations (owned)
     std::vector<DeviceBuf> owned;
-    double* d_grid = nullptr;       // MQ x 3
+    double* d_grid = nullptr;       // MQ x 3 (S2, T3) or MQ x 4 (SO3)
     double* d_theta = nullptr;      // per ring
     double* d_phi = nullptr;        // per column
     double* d_ring_cs = nullptr;    // per ring cos(theta), sin(theta)
     double* d_col_cs = nullptr;     // per column cos(phi), sin(phi)
-    double* d_x = nullptr;          // sorted node coordinates, SoA 3 x cap
+    double* d_x = nullptr;          // sorted node coordinates, SoA dim x cap
     double* d_nu = nullptr;         // sorted node weights (cap) or null
     int32_t* d_perm = nullptr;      // cap
     uint32_t* d_key[2] = {nullptr, nullptr};
@@ -96,6 +113,13 @@ struct Plan {
     double* d_tw = nullptr;         // 2 x n_phi twiddles
     double* d_G = nullptr;          // ring spectra, F x nt x (N+1) x 2
     int64_t G_fields = 0;
+    // SO3 / T3 quadrature: per-axis twiddles, two complex work buffers, the
+    // Wigner table [beta ring][coefficient] (weights and c_n folded in)
+    double* d_tw_ax[3] = {nullptr, nullptr, nullptr};
+    double* d_work[2] = {nullptr, nullptr};
+    int64_t work_len = 0;           // doubles per work buffer
+    double* d_wtab = nullptr;
+    double* d_ring_w = nullptr;     // SO3 Gauss-Legendre weight per beta ring
     int64_t resident = 0;
 
     // per-phase timing
@@ -123,10 +147,33 @@ class PhaseTimer {
     hipEvent_t b_ = nullptr;
 };
 
+// Arguments of the local solve kernels (one set per field pass).
+struct SolveArgs {
+    const double* entries;
+    int64_t MQ;
+    int F;
+    int f0;
+    const int32_t* nj;
+    const uint8_t* rstatus;
+    int reg;
+    double tau_fixed, chi_t, chi_f;
+    double mu[34];       // degree multipliers of the non-constant monomials
+    double* out;         // F_total x MQ
+    double* chi;
+    double* tau;
+    uint8_t* status;
+    int write_diag;
+    int32_t* qr_list;    // centres handed to the QR path
+    int32_t* qr_count;
+};
+
+
+SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values);
+
 // --- kernels (kernels.hip) -------------------------------------------------
 hamls_status launch_s2_keys(const Plan& P, const double* nodes, int64_t M, hipStream_t s);
-hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf);
-hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t M, hipStream_t s);
+hamls_status radix_sort(Plan& P, int64_t n, hipStream_t s, int* final_buf);
+hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t n, hipStream_t s);
 hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double* nodes,
                                  const double* nu, int64_t M, hipStream_t s);
 hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
@@ -140,6 +187,30 @@ hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx,
 hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStream_t s);
 hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s);
 hamls_status launch_s2_eval(const Plan& P, const double* coeffs, int F, const double* pts,
+                            int64_t npts, double* out, hipStream_t s);
+
+// --- kernels (grid.hip): SO3 and T3 ----------------------------------------
+hamls_status launch_grid_keys(const Plan& P, const double* nodes, int64_t M, hipStream_t s);
+hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double* nodes,
+                                const double* nu, int64_t M, hipStream_t s);
+hamls_status launch_grid_radius(const Plan& P, hipStream_t s);
+hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_grid_qr(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_grid_list(const Plan& P, const int64_t* row_ptr, int32_t* counts, int32_t* idx,
+                              hipStream_t s);
+
+// --- kernels (transform.hip): SO3 and T3 quadrature and synthesis ----------
+// out[a][k][b] = scale sum_i in[a][i][b] exp(sign 2 pi i (k - koff) i / nin),
+// complex (re, im) pairs, in real when real_in.
+hamls_status launch_dft_axis(const double* in, bool real_in, double* out, int64_t A, int nin,
+                             int64_t B, int nout, int koff, double sign, double scale,
+                             const double* tw, hipStream_t s);
+hamls_status launch_wigner_table(const Plan& P, const double* beta, const double* wts, hipStream_t s);
+hamls_status launch_so3_contract(const Plan& P, const double* G, int F, double* coeffs,
+                                 hipStream_t s);
+hamls_status launch_so3_eval(const Plan& P, const double* coeffs, int F, const double* pts,
+                             int64_t npts, double* out, hipStream_t s);
+hamls_status launch_t3_eval(const Plan& P, const double* coeffs, int F, const double* pts,
                             int64_t npts, double* out, hipStream_t s);
 
 inline int n_monomials(int D, int K) {

@@ -1,0 +1,1027 @@
+// grid.hip -- step 2 of Alg. 1 on SO(3) and T3 (gfx950).
+//
+// Both domains bin their nodes on a uniform D-dimensional cell grid:
+//   T3   D = 3, [0,1)^3, periodic; key -d^2 with d the min-image distance
+//   SO3  D = 4, [-1,1]^4 in quaternion space; every node is stored twice,
+//        as q and -q, so that the plain dot product finds exactly the copy on
+//        the centre's hemisphere and equals |q.p| bit for bit (negation is
+//        exact); key = dot, member iff dot > cos(delta/2) (rotation angle
+//        2 arccos|q.p|, Sec. 2.2)
+// The cover of a search ball is a box of cells; its rows along the last axis
+// are contiguous runs of sorted records, enumerated one row per lane and
+// scanned flattened, 64*U slots per step.
+#include <math.h>
+
+#include "common.h"
+#include "device_common.h"
+
+namespace hamls {
+
+struct GridGeom {
+    int dom;             // HAMLS_SO3 or HAMLS_T3
+    int nc;              // cells per axis
+    double lo, h;        // cell i of an axis covers [lo + i h, lo + (i+1) h)
+    const double* grid;  // M_Q x D (quaternions for SO3, points for T3)
+    const double* X;     // sorted records, SoA D x cap
+    const double* nu;    // sorted node weights or null
+    const int32_t* perm; // sorted record -> original node
+    int64_t cap;
+    const int32_t* cs;   // cell_start
+};
+
+GridGeom make_grid_geom(const Plan& P) {
+    GridGeom g;
+    g.dom = P.dom;
+    g.nc = P.gbins.nc;
+    g.lo = P.gbins.lo;
+    g.h = P.gbins.h;
+    g.grid = P.d_grid;
+    g.X = P.d_x;
+    g.nu = P.has_nu ? P.d_nu : nullptr;
+    g.perm = P.d_perm;
+    g.cap = P.cap;
+    g.cs = P.d_cell_start;
+    return g;
+}
+
+// Closeness key (larger is closer), in a fixed association without fused
+// operations: SO3 the 4-D dot product, T3 minus the squared min-image distance.
+template <int D>
+__device__ __forceinline__ double grid_key(const GridGeom& g, int64_t i, const double* q) {
+#pragma clang fp contract(off)
+    if (D == 4) {
+        double a = g.X[i] * q[0];
+        double b = g.X[g.cap + i] * q[1];
+        double c = g.X[2 * g.cap + i] * q[2];
+        double e = g.X[3 * g.cap + i] * q[3];
+        double s = a + b;
+        s = s + c;
+        s = s + e;
+        return s;
+    }
+    double s = 0.0;
+    for (int d = 0; d < 3; d++) {
+        double dl = g.X[d * g.cap + i] - q[d];
+        dl = dl - rint(dl);
+        double sq = dl * dl;
+        s = s + sq;
+    }
+    return -s;
+}
+
+// Box half-width (embedding coordinates) and key threshold of a search
+// radius r (rotation angle for SO3, distance for T3).
+template <int D>
+__device__ __forceinline__ double grid_rho(const GridGeom& g, double r) {
+    return D == 4 ? 2.0 * sin(0.25 * fmin(r, kPi)) : r;
+}
+template <int D>
+__device__ __forceinline__ double grid_key_of_radius(const GridGeom& g, double r) {
+    return D == 4 ? cos(0.5 * fmin(r, kPi)) : -(r * r);
+}
+// Largest search radius: SO3 the rotation angle pi; T3 0.87, beyond the
+// largest min-image distance sqrt(3)/2, so that the ball holds every node.
+template <int D>
+__device__ __forceinline__ double grid_rmax(const GridGeom& g) {
+    return D == 4 ? kPi : 0.87;
+}
+
+struct BoxGeo {
+    int a[4], n[4];  // per axis first cell and cell count
+    bool full[4];
+    int rows;        // rows over the first D-1 axes
+};
+
+template <int D>
+__device__ __forceinline__ BoxGeo box_geo(const GridGeom& g, const double* q, double rho) {
+    const double margin = 1e-9;
+    BoxGeo B;
+    B.rows = 1;
+    for (int d = 0; d < D; d++) {
+        int a = (int)floor((q[d] - rho - margin - g.lo) / g.h);
+        int b = (int)floor((q[d] + rho + margin - g.lo) / g.h);
+        if (D == 3) {
+            if (b - a + 1 >= g.nc) {
+                a = 0;
+                b = g.nc - 1;
+                B.full[d] = true;
+            } else {
+                B.full[d] = false;
+            }
+        } else {
+            a = a < 0 ? 0 : a;
+            b = b > g.nc - 1 ? g.nc - 1 : b;
+            B.full[d] = false;
+        }
+        B.a[d] = a;
+        B.n[d] = b - a + 1;
+        if (d < D - 1) B.rows *= B.n[d];
+    }
+    return B;
+}
+
+// Record ranges of one row of the box.
+template <int D>
+__device__ __forceinline__ void box_row_ranges(const GridGeom& g, const BoxGeo& B, int row, int& lo1,
+                                               int& len1, int& lo2, int& len2) {
+    const int nc = g.nc, L = D - 1;
+    int64_t base = 0, mul = nc;
+    int rem = row;
+#pragma unroll
+    for (int d = L - 1; d >= 0; d--) {
+        int c = B.a[d] + rem % B.n[d];
+        rem /= B.n[d];
+        c = c < 0 ? c + nc : (c >= nc ? c - nc : c);
+        base += (int64_t)c * mul;
+        mul *= nc;
+    }
+    const int a = B.a[L], b = B.a[L] + B.n[L] - 1;
+    // the run [a, b] of the last axis, split in two where it wraps (T3)
+    const int a1 = a < 0 ? a + nc : a;
+    const int e1 = (a < 0 || b >= nc) ? nc : b + 1;
+    const int e2 = a < 0 ? b + 1 : (b >= nc ? b - nc + 1 : 0);
+    const int l1 = g.cs[base + a1];
+    const int l2 = g.cs[base];
+    lo1 = l1;
+    len1 = g.cs[base + e1] - l1;
+    lo2 = l2;
+    len2 = g.cs[base + e2] - l2;
+}
+
+template <int D>
+__device__ __forceinline__ int grid_cover_count(const GridGeom& g, const double* q, double rho) {
+    BoxGeo B = box_geo<D>(g, q, rho);
+    const int lane = threadIdx.x & 63;
+    int tot = 0;
+    for (int rb = 0; rb < B.rows; rb += 64) {
+        int r = rb + lane, lo1 = 0, len1 = 0, lo2 = 0, len2 = 0;
+        if (r < B.rows) box_row_ranges<D>(g, B, r, lo1, len1, lo2, len2);
+        tot += wave_sum_int(len1 + len2);
+    }
+    return tot;
+}
+
+// Visits every record in the box cover, 64*U slots per step (see s2_scan).
+template <int D, int U, class Fn>
+__device__ __forceinline__ void grid_scan(const GridGeom& g, const double* q, double rho, int* sh,
+                                          Fn&& body) {
+    BoxGeo B = box_geo<D>(g, q, rho);
+    const int lane = threadIdx.x & 63;
+    int* s_lo1 = sh;
+    int* s_len1 = sh + 64;
+    int* s_lo2 = sh + 128;
+    int* s_pre = sh + 192;
+    for (int rb = 0; rb < B.rows; rb += 64) {
+        int r = rb + lane, lo1 = 0, len1 = 0, lo2 = 0, len2 = 0;
+        if (r < B.rows) box_row_ranges<D>(g, B, r, lo1, len1, lo2, len2);
+        int len = len1 + len2;
+        int incl = wave_incl_scan_int(len);
+        int total = __shfl(incl, 63, 64);
+        s_lo1[lane] = lo1;
+        s_len1[lane] = len1;
+        s_lo2[lane] = lo2;
+        s_pre[lane] = incl - len;
+        if (lane == 63) s_pre[64] = incl;
+        __syncthreads();
+        int kc = 0;
+        for (int base = 0; base < total; base += 64 * U) {
+            while (s_pre[kc + 1] <= base) kc++;
+            bool valid[U];
+            int idx[U];
+            int k = kc;
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                int sl = base + 64 * u + lane;
+                valid[u] = sl < total;
+                idx[u] = 0;
+                if (valid[u]) {
+                    while (s_pre[k + 1] <= sl) k++;
+                    int o = sl - s_pre[k];
+                    idx[u] = o < s_len1[k] ? s_lo1[k] + o : s_lo2[k] + (o - s_len1[k]);
+                }
+            }
+            body(valid, idx);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// binning
+// ---------------------------------------------------------------------------
+
+// One key per record: T3 one record per node; SO3 two (q and -q, the second
+// encoded as index M + i).
+__global__ void k_grid_keys(const double* __restrict__ nodes, int64_t M, int dom, int D, int nc,
+                            double lo, double h, uint32_t* __restrict__ keys,
+                            int32_t* __restrict__ idx) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t nrec = dom == HAMLS_SO3 ? 2 * M : M;
+    if (r >= nrec) return;
+    int64_t i = r < M ? r : r - M;
+    double sg = r < M ? 1.0 : -1.0;
+    uint32_t key = 0;
+    for (int d = 0; d < D; d++) {
+        double x = sg * nodes[(int64_t)D * i + d];
+        int c;
+        if (dom == HAMLS_T3) {
+            double y = x - floor(x);
+            c = (int)(y * nc);
+            c = c >= nc ? nc - 1 : (c < 0 ? 0 : c);
+        } else {
+            c = (int)floor((x - lo) / h);
+            c = c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+        }
+        key = key * (uint32_t)nc + (uint32_t)c;
+    }
+    keys[r] = key;
+    idx[r] = (int32_t)r;
+}
+
+__global__ void k_grid_gather(const int32_t* __restrict__ idx, const double* __restrict__ nodes,
+                              const double* __restrict__ nu, int64_t nrec, int64_t M, int D,
+                              int64_t cap, double* __restrict__ X, double* __restrict__ NU,
+                              int32_t* __restrict__ perm) {
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrec) return;
+    int64_t j = idx[r];
+    int64_t i = j < M ? j : j - M;
+    double sg = j < M ? 1.0 : -1.0;
+    for (int d = 0; d < D; d++) X[d * cap + r] = sg * nodes[(int64_t)D * i + d];
+    perm[r] = (int32_t)i;
+    if (nu) NU[r] = nu[i];
+}
+
+hamls_status launch_grid_keys(const Plan& P, const double* nodes, int64_t M, hipStream_t s) {
+    int64_t nrec = P.dom == HAMLS_SO3 ? 2 * M : M;
+    int bs = 256;
+    hipLaunchKernelGGL(k_grid_keys, dim3((unsigned)((nrec + bs - 1) / bs)), dim3(bs), 0, s, nodes, M,
+                       P.dom, P.gbins.D, P.gbins.nc, P.gbins.lo, P.gbins.h, P.d_key[0], P.d_idx[0]);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double* nodes,
+                                const double* nu, int64_t M, hipStream_t s) {
+    int64_t nrec = P.dom == HAMLS_SO3 ? 2 * M : M;
+    int bs = 256;
+    hipLaunchKernelGGL(k_grid_gather, dim3((unsigned)((nrec + bs - 1) / bs)), dim3(bs), 0, s, idx,
+                       nodes, nu, nrec, M, P.gbins.D, P.cap, P.d_x, P.d_nu, P.d_perm);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// support radius (eq. (5), (6), (12))
+// ---------------------------------------------------------------------------
+
+// n-th largest of buf[0..count) (count >= n), keys in (klo, khi]: rank count
+// for small sets, else a 256-bin histogram narrowing (bins monotone in the
+// key) and a rank count inside the selected bin.
+__device__ double select_nth_largest(double* buf, int count, int knn, double klo, double khi, int* hist,
+                                     double* binbuf, int bincap) {
+    const int lane = threadIdx.x & 63;
+    double found = -1e300;
+    if (count <= 256) {
+        double v[4];
+        int gt[4] = {0, 0, 0, 0}, ge[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < 4; q++) v[q] = lane + 64 * q < count ? buf[lane + 64 * q] : 1e300;
+#pragma unroll 4
+        for (int b = 0; b < count; b++) {
+            double u = buf[b];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                gt[q] += u > v[q];
+                ge[q] += u >= v[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (lane + 64 * q < count && gt[q] < knn && knn <= ge[q]) found = v[q];
+        return wave_max(found);
+    }
+    const double scale = 256.0 / (khi - klo);
+#pragma unroll
+    for (int q = 0; q < 4; q++) hist[4 * lane + q] = 0;
+    __syncthreads();
+    for (int a = lane; a < count; a += 64) {
+        int bin = (int)((khi - buf[a]) * scale);
+        bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
+        atomicAdd(&hist[bin], 1);
+    }
+    __syncthreads();
+    int h4[4], s4 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        h4[q] = hist[4 * lane + q];
+        s4 += h4[q];
+    }
+    int incl = wave_incl_scan_int(s4);
+    int before = incl - s4, bsel = -1, bbefore = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (bsel < 0 && before < knn && knn <= before + h4[q]) {
+            bsel = 4 * lane + q;
+            bbefore = before;
+        }
+        before += h4[q];
+    }
+    uint64_t owner = __ballot(bsel >= 0);
+    int src = __ffsll((unsigned long long)owner) - 1;
+    const int B = __shfl(bsel, src, 64);
+    const int kth = knn - __shfl(bbefore, src, 64);
+    const int nB = hist[B];
+    __syncthreads();
+    if (nB <= bincap) {
+        int m = 0;
+        for (int base = 0; base < count; base += 64) {
+            int a = base + lane;
+            bool inb = false;
+            double v = 0.0;
+            if (a < count) {
+                v = buf[a];
+                int bin = (int)((khi - v) * scale);
+                bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
+                inb = bin == B;
+            }
+            uint64_t mk = __ballot(inb);
+            if (inb) binbuf[m + rank_below(mk)] = v;
+            m += __popcll(mk);
+        }
+        __syncthreads();
+        for (int a = lane; a < nB; a += 64) {
+            double v = binbuf[a];
+            int gt = 0, ge = 0;
+            for (int b = 0; b < nB; b++) {
+                double u = binbuf[b];
+                gt += u > v;
+                ge += u >= v;
+            }
+            if (gt < kth && kth <= ge) found = v;
+        }
+    } else {
+        for (int a = lane; a < count; a += 64) {
+            double v = buf[a];
+            int gt = 0, ge = 0;
+            for (int b = 0; b < count; b++) {
+                double u = buf[b];
+                gt += u > v;
+                ge += u >= v;
+            }
+            if (gt < knn && knn <= ge) found = v;
+        }
+    }
+    return wave_max(found);
+}
+
+// One grid node per block (one wave).  Adaptive radius: bracket a search
+// radius on the cell-cover count (cell table only), scan the box keeping the
+// keys of the ball, resize until it holds between n and kCandCap nodes, take
+// the n-th largest key exactly.  SO3: delta = (1+eps) 2 arccos(t_n), clamped
+// below pi, threshold cos(delta/2).  T3: threshold c = (1+eps)^2 d_n^2 on d^2
+// (no transcendental), delta = sqrt(c).  A fixed delta_0 is merged (larger
+// radius wins).  Thresholds are stored on the key: SO3 c, T3 -c.
+template <int D>
+__global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int knn, double eps,
+                                                   double delta0, double* thr, double* delta,
+                                                   uint8_t* rstatus) {
+    constexpr int U = 4;
+    constexpr int kBinCap = 128;
+    __shared__ double buf[kCandCap];
+    __shared__ double binbuf[kBinCap];
+    __shared__ int sh[kScanLds];
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
+    uint8_t st = 0;
+    double dl = delta0;
+    if (knn > 0) {
+        const double rmax = grid_rmax<D>(g);
+        double r = D == 4 ? cbrt(6.0 * kPi * knn / (double)M) : cbrt(3.0 * knn / (4.0 * kPi * M));
+        r = fmin(r, rmax);
+        // bracket the cover count into [3n, 16n]
+        double rl = 0.0, rh = 0.0;
+        for (int it = 0; it < 20; it++) {
+            int cov = grid_cover_count<D>(g, q, grid_rho<D>(g, r));
+            if (cov < 3 * knn) {
+                if (r >= rmax) break;
+                rl = r;
+                r = rh > 0.0 ? sqrt(r * rh) : fmin(rmax, r * (cov < knn / 2 ? 1.6 : 1.25));
+            } else if (cov > 16 * knn && r > 1e-6) {
+                rh = r;
+                r = rl > 0.0 ? sqrt(r * rl) : r * 0.7;
+            } else {
+                break;
+            }
+        }
+        double r_lo = 0.0, r_hi = 0.0;
+        double tn = -1e300;
+        bool done = false, hemi = false;
+        for (int it = 0; it < 40 && !done; it++) {
+            const double kr = grid_key_of_radius<D>(g, r);
+            int count = 0;
+            grid_scan<D, U>(g, q, grid_rho<D>(g, r), sh, [&](const bool* valid, const int* idx) {
+                double kv[U];
+#pragma unroll
+                for (int u = 0; u < U; u++) kv[u] = valid[u] ? grid_key<D>(g, idx[u], q) : -1e300;
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    bool in = valid[u] && kv[u] > kr;
+                    uint64_t mk = __ballot(in);
+                    int pos = count + rank_below(mk);
+                    if (in && pos < kCandCap) buf[pos] = kv[u];
+                    count += __popcll(mk);
+                }
+            });
+            __syncthreads();
+            if (count >= knn && count <= kCandCap) {
+                tn = select_nth_largest(buf, count, knn, kr, D == 4 ? 1.0 : 0.0, sh, binbuf,
+                                        kBinCap);
+                done = true;
+            } else if (count < knn) {
+                if (r >= rmax) {
+                    hemi = true;
+                    done = true;
+                } else {
+                    r_lo = r;
+                    double grow = 1.15 * cbrt((double)knn / (double)(count > 0 ? count : 1));
+                    grow = grow < 1.2 ? 1.2 : (grow > 2.0 ? 2.0 : grow);
+                    double nr = r * grow;
+                    if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(r * r_hi);
+                    r = fmin(nr, rmax);
+                }
+            } else {
+                r_hi = r;
+                double shrink = 1.2 * cbrt((double)knn / (double)count);
+                double nr = r * (shrink < 0.9 ? shrink : 0.9);
+                if (nr <= r_lo) nr = sqrt(r * (r_lo > 0.0 ? r_lo : 0.5 * r));
+                r = nr;
+            }
+            __syncthreads();
+        }
+        if (!done) {
+            // exact fallback: bitwise binary search for the largest key v with
+            // #(key >= v) >= n among the keys of the ball of radius r
+            const double kr = grid_key_of_radius<D>(g, r);
+            uint64_t lo = ordered_bits(kr), hi = ordered_bits(D == 4 ? 1.0 : 0.0);
+            while (lo < hi) {
+                uint64_t mid = lo + (hi - lo + 1) / 2;
+                double v = from_ordered_bits(mid);
+                int count = 0;
+                grid_scan<D, 1>(g, q, grid_rho<D>(g, r), sh, [&](const bool* valid, const int* idx) {
+                    bool in = valid[0] && grid_key<D>(g, idx[0], q) >= v;
+                    count += __popcll(__ballot(in));
+                });
+                if (count >= knn)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            tn = from_ordered_bits(lo);
+        }
+        if (D == 4) {
+            double dk = hemi ? kPi : (1.0 + eps) * (2.0 * acos(fmin(1.0, fmax(-1.0, tn))));
+            if (!(delta0 > 0.0 && delta0 > dk)) dl = dk;
+        } else {
+            // T3: the threshold is (1+eps)^2 d_n^2 on d^2; a fixed radius wins
+            // when it is larger than the adaptive one
+            double e = 1.0 + eps;
+            double e2 = e * e;
+            double ck = hemi ? 3.0 : e2 * (-tn);
+            double dk = sqrt(ck);
+            double cc = ck;
+            dl = dk;
+            if (delta0 > 0.0 && delta0 > dk) {
+                dl = delta0;
+                cc = delta0 * delta0;
+            }
+            if (lane == 0) {
+                thr[j] = -cc;
+                delta[j] = dl;
+                rstatus[j] = st;
+            }
+            return;
+        }
+    }
+    if (D == 4) {
+        if (dl >= kPi) {
+            dl = kPi;
+            st |= HAMLS_ST_HEMISPHERE;
+        }
+        const double c = cos(0.5 * dl);
+        if (lane == 0) {
+            thr[j] = c;
+            delta[j] = dl;
+            rstatus[j] = st;
+        }
+    } else if (lane == 0) {
+        thr[j] = -(delta0 * delta0);
+        delta[j] = delta0;
+        rstatus[j] = st;
+    }
+}
+
+hamls_status launch_grid_radius(const Plan& P, hipStream_t s) {
+    GridGeom g = make_grid_geom(P);
+    double d0 = P.prm.support_radius > 0.0 ? P.prm.support_radius : 0.0;
+    int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
+    auto kern = P.dom == HAMLS_SO3 ? k_grid_radius<4> : k_grid_radius<3>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn, P.prm.knn_eps,
+                       d0, P.d_thr, P.d_delta, P.d_rstatus);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// local problem rows (Sec. 2.3) and assembly (eq. (14))
+// ---------------------------------------------------------------------------
+
+// Weight, tangent coordinates (divided by the scale) of record i for centre q.
+// SO3: Im(conj(q) p) with p the stored copy (dot > 0), scale delta/2, distance
+// 2 arccos(dot).  T3: min-image difference, scale delta, distance |d|.
+template <int D>
+__device__ __forceinline__ void grid_local(const GridGeom& g, int64_t i, const double* q, double key,
+                                           double dl, int wendland, double* u, double& w) {
+    if (D == 4) {
+        const double x0 = g.X[i], x1 = g.X[g.cap + i], x2 = g.X[2 * g.cap + i], x3 = g.X[3 * g.cap + i];
+        const double is = 2.0 / dl;
+        u[0] = (q[0] * x1 - x0 * q[1] - (q[2] * x3 - q[3] * x2)) * is;
+        u[1] = (q[0] * x2 - x0 * q[2] - (q[3] * x1 - q[1] * x3)) * is;
+        u[2] = (q[0] * x3 - x0 * q[3] - (q[1] * x2 - q[2] * x1)) * is;
+        w = wendland_phi(wendland, 2.0 * acos(fmin(key, 1.0)) / dl);
+    } else {
+        const double is = 1.0 / dl;
+        for (int d = 0; d < 3; d++) {
+            double t = g.X[d * g.cap + i] - q[d];
+            u[d] = (t - rint(t)) * is;
+        }
+        w = wendland_phi(wendland, sqrt(-key) / dl);
+    }
+    if (g.nu) w *= g.nu[i];
+}
+
+// Monomials of degree <= K in 3 variables, by degree, first variable's power
+// descending, then the second's.
+template <int K>
+__device__ __forceinline__ void monomials3(const double* u, double s, double* row) {
+    double p0[K + 1], p1[K + 1], p2[K + 1];
+    p0[0] = p1[0] = p2[0] = 1.0;
+#pragma unroll
+    for (int a = 1; a <= K; a++) {
+        p0[a] = p0[a - 1] * u[0];
+        p1[a] = p1[a - 1] * u[1];
+        p2[a] = p2[a - 1] * u[2];
+    }
+    int c = 0;
+#pragma unroll
+    for (int l = 0; l <= K; l++)
+#pragma unroll
+        for (int a = l; a >= 0; a--)
+#pragma unroll
+            for (int b = l - a; b >= 0; b--) row[c++] = s * p0[a] * p1[b] * p2[l - a - b];
+}
+
+// Fused assembly and local solve, one grid node per block (one wave).
+//  1. scan the cover; member rows (sqrt(w) g, sqrt(w) y) are staged in LDS 64
+//     at a time and each lane owns a few Gram / right-hand-side entries;
+//  2. the entries go to LDS, normalised (unit weight sum, unit-norm columns)
+//     and reordered to [V | v1 | y]: the Cholesky factor of the Gram matrix of
+//     [V | v1] is [[L, 0], [d^T, rho]] with L L^T = C, d = L^{-1} b and
+//     rho^2 = 1 - |d|^2 = 1/chi (eq. (19), (20)); the right-hand-side rows,
+//     eliminated alongside, give z = L^{-1} r[1:] and omega = (r_1 - d.z)/rho;
+//  3. with tau from eq. (23),
+//       c_1 = (rho omega + sum_j d_j z_j t_j) / (rho^2 + sum_j d_j^2 t_j),
+//     t_j = tau mu_j / (1 + tau mu_j), the Schur complement of the first
+//     unknown of eq. (22).
+// Centres whose normal-matrix solve is not trustworthy (pivot, chi < 1 or a
+// small Schur denominator) store their raw entries and go to the QR list.
+template <int D, int K, int FM>
+__global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __restrict__ vals, int F,
+                                                int wendland, const double* __restrict__ thr,
+                                                const double* __restrict__ delta, SolveArgs A,
+                                                int32_t* __restrict__ nj,
+                                                double* __restrict__ entries_out) {
+    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
+    constexpr int NC = m - 1;
+    constexpr int EG = m * (m + 1) / 2;
+    constexpr int ROW = m + FM + 1;
+    constexpr int KE = (EG + m * FM + 63) / 64;
+    constexpr int U = FM == 1 ? 2 : 1;
+    constexpr int LDM = NC + 2;                 // leading dimension of the factor
+    constexpr int RMAX = NC + 1 + FM;           // rows of [V | v1] and the fields
+    static_assert(EG + m * FM + RMAX * LDM + m <= 64 * ROW, "LDS reuse");
+    __shared__ double rows[64 * ROW];
+    __shared__ int sh[kScanLds];
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    const int64_t MQ = A.MQ;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
+    const double c = thr[j], dl = delta[j];
+    const int E = EG + m * F;
+    int ca[KE], cb[KE];
+    double acc[KE];
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        int e = lane + 64 * k;
+        acc[k] = 0.0;
+        ca[k] = -1;
+        cb[k] = 0;
+        if (e < EG) {
+            int a = 0, rem = e;
+            while (rem >= m - a) {
+                rem -= m - a;
+                a++;
+            }
+            ca[k] = a;
+            cb[k] = a + rem;
+        } else if (e < E) {
+            int r = e - EG;
+            ca[k] = r / F;
+            cb[k] = m + r % F;
+        }
+    }
+    int count = 0;
+    grid_scan<D, U>(g, q, grid_rho<D>(g, dl), sh, [&](const bool* valid, const int* idx) {
+        double kv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) kv[u] = valid[u] ? grid_key<D>(g, idx[u], q) : -1e300;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const bool in = kv[u] > c;
+            const uint64_t mk = __ballot(in);
+            const int nin = __popcll(mk);
+            if (nin == 0) continue;
+            if (in) {
+                const int i = idx[u];
+                double uu[3], w;
+                grid_local<D>(g, i, q, kv[u], dl, wendland, uu, w);
+                const double sw = sqrt(w);
+                double* row = rows + rank_below(mk) * ROW;
+                monomials3<K>(uu, sw, row);
+                for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
+            }
+            __syncthreads();
+            for (int r = 0; r < nin; r++) {
+                const double* row = rows + r * ROW;
+#pragma unroll
+                for (int k = 0; k < KE; k++)
+                    if (ca[k] >= 0) acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+            }
+            __syncthreads();
+            count += nin;
+        }
+    });
+    // entries to LDS: Gram packed upper [gidx(a, b)], then right-hand sides [a F + f]
+    double* Gs = rows;
+    double* Mx = rows + EG + m * FM;
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        int e = lane + 64 * k;
+        if (e < E) Gs[e] = acc[k];
+    }
+    __syncthreads();
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    const uint8_t rst = A.rstatus[j];
+    const double W = Gs[0];
+    if (lane == 0) nj[j] = count;
+    if (count == 0 || !(W > 0.0)) {
+        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = __builtin_nan("");
+        if (lane == 0 && A.write_diag) {
+            A.chi[j] = __builtin_nan("");
+            A.tau[j] = __builtin_nan("");
+            A.status[j] = rst | HAMLS_ST_EMPTY;
+        }
+        return;
+    }
+    // inverse column scales 1/sqrt(g_a^T W g_a / W) (unit discrete norm)
+    double* isc = Mx + RMAX * LDM;
+    bool degen = count < m;
+    {
+        double v = 1.0;
+        if (lane < m) v = sqrt(Gs[gidx(lane, lane)] / W);
+        if (__ballot(lane < m && !(v > 0.0))) degen = true;
+        if (lane < m) isc[lane] = 1.0 / v;
+    }
+    if (degen) {
+        // the tau -> infinity limit: the weighted mean
+        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = Gs[EG + lane] / W;
+        if (lane == 0 && A.write_diag) {
+            A.chi[j] = __builtin_inf();
+            A.tau[j] = __builtin_inf();
+            A.status[j] = rst | HAMLS_ST_UNDERDETERMINED;
+        }
+        return;
+    }
+    __syncthreads();
+    // normalised, reordered system: position p(0) = NC (v1), p(a) = a - 1
+    const int R = NC + 1 + F;
+    for (int e = lane; e < R * (NC + 1); e += 64) {
+        const int r = e / (NC + 1), cc = e - r * (NC + 1);
+        double v = 0.0;
+        if (r <= NC) {
+            if (cc <= r) {
+                const int a = r == NC ? 0 : r + 1, b = cc == NC ? 0 : cc + 1;
+                const int lo = a < b ? a : b, hi = a < b ? b : a;
+                v = Gs[gidx(lo, hi)] / W * (isc[a] * isc[b]);
+            }
+        } else {
+            const int f = r - NC - 1, a = cc == NC ? 0 : cc + 1;
+            v = Gs[EG + a * F + f] / W * isc[a];
+        }
+        Mx[r * LDM + cc] = v;
+    }
+    __syncthreads();
+    bool ill = false;
+    double minpiv = 1.0, s_last = 1.0;
+    for (int k = 0; k <= NC; k++) {
+        const double s = Mx[k * LDM + k];
+        if (k < NC) {
+            minpiv = fmin(minpiv, s);
+            if (!(s > 1e-300)) {
+                ill = true;
+                break;
+            }
+        } else {
+            s_last = s;
+            if (!(s > 0.0)) {
+                ill = true;
+                break;
+            }
+        }
+        const double lkk = sqrt(s);
+        const double il = 1.0 / lkk;
+        __syncthreads();
+        if (lane == 0) Mx[k * LDM + k] = lkk;
+        for (int r = k + 1 + lane; r < R; r += 64) Mx[r * LDM + k] *= il;
+        __syncthreads();
+        const int nr = R - k - 1, ncl = NC - k;
+        for (int e = lane; e < nr * ncl; e += 64) {
+            const int r = k + 1 + e / ncl, cc = k + 1 + e % ncl;
+            if (cc <= r) Mx[r * LDM + cc] -= Mx[r * LDM + k] * Mx[cc * LDM + k];
+        }
+        __syncthreads();
+    }
+    double dv[NC > 0 ? NC : 1], d2[NC > 0 ? NC : 1], tf[NC > 0 ? NC : 1];
+    double chi = 1.0, tau = 0.0, den = 1.0;
+    if (!ill) {
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            dv[k] = Mx[NC * LDM + k];
+            d2[k] = dv[k] * dv[k];
+        }
+        chi = 1.0 / s_last;
+        if (minpiv < kPivQR) ill = true;
+    }
+    if (!ill) {
+        tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
+        den = s_last;
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const double tm = tau * A.mu[k];
+            tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
+            den += d2[k] * tf[k];
+        }
+        if (!(den > kDenQR)) ill = true;
+    }
+    if (ill) {
+        for (int e = lane; e < E; e += 64) entries_out[(int64_t)e * MQ + j] = Gs[e];
+        if (lane == 0) {
+            const int slot = atomicAdd(A.qr_count, 1);
+            A.qr_list[slot] = j;
+        }
+        return;
+    }
+    if (lane < F) {
+        const double rho = Mx[NC * LDM + NC];
+        const double* zr = Mx + (NC + 1 + lane) * LDM;
+        double num = rho * zr[NC];
+#pragma unroll
+        for (int k = 0; k < NC; k++) num += dv[k] * zr[k] * tf[k];
+        A.out[(int64_t)(A.f0 + lane) * MQ + j] = num / den;
+    }
+    if (lane == 0 && A.write_diag) {
+        A.chi[j] = chi;
+        A.tau[j] = tau;
+        A.status[j] = rst | (tau > 0.0 ? HAMLS_ST_REGULARIZED : 0);
+    }
+}
+
+hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+    GridGeom g = make_grid_geom(P);
+    SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    dim3 grid((unsigned)P.MQ), block(64);
+    int wl = P.prm.wendland;
+#define HAMLS_GMLS(DD, KK)                                                                       \
+    if (F == 1)                                                                                  \
+        hipLaunchKernelGGL((k_grid_mls<DD, KK, 1>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
+                           P.d_delta, A, P.d_nj, P.d_entries);                                   \
+    else                                                                                         \
+        hipLaunchKernelGGL((k_grid_mls<DD, KK, kMaxFieldsPerPass>), grid, block, 0, s, g, P.d_vals, \
+                           F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
+#define HAMLS_GMLS_D(KK)     \
+    if (P.dom == HAMLS_SO3) { \
+        HAMLS_GMLS(4, KK)     \
+    } else {                  \
+        HAMLS_GMLS(3, KK)     \
+    }
+    switch (P.K) {
+        case 0: HAMLS_GMLS_D(0) break;
+        case 1: HAMLS_GMLS_D(1) break;
+        case 2: HAMLS_GMLS_D(2) break;
+        case 3: HAMLS_GMLS_D(3) break;
+        default: set_error("degree %d unsupported on SO(3)/T3", P.K); return HAMLS_ERR_UNSUPPORTED;
+    }
+#undef HAMLS_GMLS_D
+#undef HAMLS_GMLS
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// QR path (see k_s2_qr): streaming Householder on the rows (V | v1 | y_w)
+// ---------------------------------------------------------------------------
+
+template <int D, int K>
+__global__ __launch_bounds__(64) void k_grid_qr(GridGeom g, const double* __restrict__ vals, int wendland,
+                                               const double* __restrict__ thr,
+                                               const double* __restrict__ delta, SolveArgs A) {
+    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
+    constexpr int NC = m - 1;
+    constexpr int LD = m + 1 + kMaxFieldsPerPass;
+    __shared__ double T[(m + 64) * LD];
+    __shared__ int sh[kScanLds];
+    const int lane = threadIdx.x;
+    const int F = A.F;
+    const int cols = m + F;
+    const int64_t MQ = A.MQ;
+    const int total = *A.qr_count;
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    for (int li = blockIdx.x; li < total; li += gridDim.x) {
+        const int j = A.qr_list[li];
+        double q[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
+        const double c = thr[j], dl = delta[j];
+        const double W = A.entries[j];
+        double isc[m];
+#pragma unroll
+        for (int a = 0; a < m; a++) isc[a] = 1.0 / sqrt(A.entries[(int64_t)gidx(a, a) * MQ + j] / W);
+        for (int e = lane; e < m * LD; e += 64) T[e] = 0.0;
+        __syncthreads();
+        grid_scan<D, 1>(g, q, grid_rho<D>(g, dl), sh, [&](const bool* valid_, const int* idx_) {
+            const int i = idx_[0];
+            const double kv = valid_[0] ? grid_key<D>(g, i, q) : -1e300;
+            const bool in = kv > c;
+            const uint64_t mk = __ballot(in);
+            const int nin = __popcll(mk);
+            if (nin == 0) return;
+            if (in) {
+                double uu[3], w;
+                grid_local<D>(g, i, q, kv, dl, wendland, uu, w);
+                const double b = sqrt(w / W);
+                double mono[m];
+                monomials3<K>(uu, 1.0, mono);
+                double* row = T + (m + rank_below(mk)) * LD;
+#pragma unroll
+                for (int a = 1; a < m; a++) row[a - 1] = b * mono[a] * isc[a];
+                row[NC] = b;
+                for (int f = 0; f < F; f++) row[m + f] = b * vals[(int64_t)f * g.cap + i];
+            }
+            __syncthreads();
+            const int R = m + nin;
+            for (int k = 0; k < m; k++) {
+                double part = 0.0;
+                for (int r = k + lane; r < R; r += 64) {
+                    double v = T[r * LD + k];
+                    part += v * v;
+                }
+                double nrm2 = wave_sum(part);
+                double x0k = T[k * LD + k];
+                __syncthreads();
+                // columns have unit discrete norm; a residual below 1e-100 is
+                // rounding noise, nothing to eliminate
+                if (!(nrm2 > 1e-200)) continue;
+                double nrm = sqrt(nrm2);
+                double alpha = x0k > 0.0 ? -nrm : nrm;
+                double v0 = x0k - alpha;
+                double vv = nrm2 - x0k * x0k + v0 * v0;
+                for (int jc = k + 1 + lane; jc < cols; jc += 64) {
+                    double sdot = v0 * T[k * LD + jc];
+                    for (int r = k + 1; r < R; r++) sdot += T[r * LD + k] * T[r * LD + jc];
+                    sdot *= 2.0 / vv;
+                    T[k * LD + jc] -= sdot * v0;
+                    for (int r = k + 1; r < R; r++) T[r * LD + jc] -= sdot * T[r * LD + k];
+                }
+                __syncthreads();
+                if (lane == 0) T[k * LD + k] = alpha;
+                for (int r = k + 1 + lane; r < R; r += 64) T[r * LD + k] = 0.0;
+                __syncthreads();
+            }
+        });
+        if (lane == 0) {
+            uint8_t st = A.rstatus[j] | HAMLS_ST_ILLCOND;
+            double rmin = 1e300;
+            for (int k = 0; k < NC; k++) rmin = fmin(rmin, fabs(T[k * LD + k]));
+            double chi, tau;
+            if (!(rmin > kRankTol)) {
+                for (int f = 0; f < F; f++)
+                    A.out[(int64_t)(A.f0 + f) * MQ + j] = A.entries[(int64_t)(m * (m + 1) / 2 + f) * MQ + j] / W;
+                chi = __builtin_inf();
+                tau = __builtin_inf();
+                st |= HAMLS_ST_UNDERDETERMINED;
+            } else {
+                double dv[NC], d2[NC], sg[NC];
+#pragma unroll
+                for (int k = 0; k < NC; k++) {
+                    sg[k] = T[k * LD + k] < 0.0 ? -1.0 : 1.0;
+                    dv[k] = sg[k] * T[k * LD + NC];
+                    d2[k] = dv[k] * dv[k];
+                }
+                const double rho = T[NC * LD + NC];
+                chi = 1.0 / (rho * rho);
+                tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
+                double den = rho * rho;
+                double fac[NC];
+#pragma unroll
+                for (int k = 0; k < NC; k++) {
+                    double tm = tau * A.mu[k];
+                    fac[k] = tm > 0.0 ? dv[k] * (tm / (1.0 + tm)) : 0.0;
+                    den += fac[k] * dv[k];
+                }
+                for (int f = 0; f < F; f++) {
+                    double num = rho * T[NC * LD + m + f];
+                    for (int k = 0; k < NC; k++) num += fac[k] * sg[k] * T[k * LD + m + f];
+                    A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
+                }
+                if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
+            }
+            if (A.write_diag) {
+                A.chi[j] = chi;
+                A.tau[j] = tau;
+                A.status[j] = st;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hamls_status launch_grid_qr(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+    if (P.m <= 1) return HAMLS_OK;
+    GridGeom g = make_grid_geom(P);
+    SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    dim3 qg((unsigned)(P.MQ < 2048 ? P.MQ : 2048)), qb(64);
+    int wl = P.prm.wendland;
+    switch (P.K) {
+#define HAMLS_GQR(KK)                                                                                \
+    {                                                                                                \
+        auto kq = P.dom == HAMLS_SO3 ? k_grid_qr<4, KK> : k_grid_qr<3, KK>;                        \
+        hipLaunchKernelGGL(kq, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A);               \
+    }
+        case 1: HAMLS_GQR(1) break;
+        case 2: HAMLS_GQR(2) break;
+        case 3: HAMLS_GQR(3) break;
+#undef HAMLS_GQR
+        default: break;
+    }
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// neighbour export (introspection)
+// ---------------------------------------------------------------------------
+
+template <int D>
+__global__ __launch_bounds__(64) void k_grid_list(GridGeom g, const double* __restrict__ thr,
+                                                 const double* __restrict__ delta,
+                                                 const int64_t* __restrict__ row_ptr,
+                                                 int32_t* __restrict__ counts, int32_t* __restrict__ idx) {
+    __shared__ int sh[kScanLds];
+    const int j = blockIdx.x;
+    const int lane = threadIdx.x;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
+    const double c = thr[j];
+    int count = 0;
+    grid_scan<D, 1>(g, q, grid_rho<D>(g, delta[j]), sh, [&](const bool* valid, const int* id) {
+        bool in = valid[0] && grid_key<D>(g, id[0], q) > c;
+        uint64_t mk = __ballot(in);
+        if (in && idx) idx[row_ptr[j] + count + rank_below(mk)] = g.perm[id[0]];
+        count += __popcll(mk);
+    });
+    if (lane == 0 && counts) counts[j] = count;
+}
+
+hamls_status launch_grid_list(const Plan& P, const int64_t* row_ptr, int32_t* counts, int32_t* idx,
+                              hipStream_t s) {
+    GridGeom g = make_grid_geom(P);
+    auto kern = P.dom == HAMLS_SO3 ? k_grid_list<4> : k_grid_list<3>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.d_thr, P.d_delta, row_ptr,
+                       counts, idx);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+}  // namespace hamls

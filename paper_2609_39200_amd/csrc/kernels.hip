@@ -15,53 +15,13 @@
 #include <math.h>
 
 #include "common.h"
+#include "device_common.h"
 
 namespace hamls {
 
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------
-
-// Membership key x.q in a fixed association without fused operations, so that
-// the neighbour sets do not depend on instruction selection.
-__device__ __forceinline__ double s2_dot(double x0, double x1, double x2, double q0, double q1,
-                                         double q2) {
-#pragma clang fp contract(off)
-    double a = x0 * q0;
-    double b = x1 * q1;
-    double c = x2 * q2;
-    double s = a + b;
-    return s + c;
-}
-
-__device__ __forceinline__ int rank_below(uint64_t mask) {
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-// Workgroups are dealt round-robin over the 8 XCDs (each with its own L2).
-// Within every group of 512 workgroups, XCD x takes the 64 consecutive work
-// items [64x, 64x + 64): neighbouring grid nodes (sharing candidate records)
-// stay on one L2, while expensive regions (holes) still spread over all XCDs.
-// A trailing partial group keeps the identity order.
-__device__ __forceinline__ int xcd_block(int bid, int nblk) {
-    const int g = bid >> 9;
-    if ((g + 1) << 9 > nblk) return bid;
-    return (g << 9) + ((bid & 7) << 6) + ((bid >> 3) & 63);
-}
-
-__device__ __forceinline__ double wendland_phi(int which, double r) {
-    if (r >= 1.0) return 0.0;
-    double s = 1.0 - r;
-    double s2 = s * s;
-    if (which == 2) return s2 * s2 * s2 * (35.0 * r * r + 18.0 * r + 3.0);
-    return s2 * s2 * (4.0 * r + 1.0);
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
 
 // Geometry handed to the per-grid-node kernels.
 struct S2Geom {
@@ -172,20 +132,6 @@ __device__ __forceinline__ void band_ranges(const S2Geom& g, const CapGeo& G, in
     }
 }
 
-__device__ __forceinline__ int wave_sum_int(int v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ int wave_incl_scan_int(int v) {
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
 // Number of sorted records in the cell cover of a cap (an upper bound on the
 // nodes inside it), from the cell table alone, one band per lane.
 __device__ __forceinline__ int s2_cover_count(const S2Geom& g, double thq, double cq, double sq,
@@ -200,9 +146,6 @@ __device__ __forceinline__ int s2_cover_count(const S2Geom& g, double thq, doubl
     }
     return tot;
 }
-
-// Ints of LDS one wave needs for s2_scan.
-constexpr int kScanLds = 4 * 64 + 1;
 
 // Visits every sorted record in the cell cover of the cap, 64*U per step: the
 // lanes first enumerate up to 64 bands at once, a wave prefix sum flattens
@@ -376,7 +319,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
 }
 
 hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf) {
-    int bits = P.bins.key_bits;
+    int bits = P.key_bits;
     int passes = (bits + 7) / 8;
     int nblocks = (int)((M + RS_TILE - 1) / RS_TILE);
     if ((int64_t)nblocks * 256 > P.hist_len) {
@@ -414,7 +357,7 @@ hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t M, h
     int bs = 256;
     int64_t nbk = (M + 1 + bs - 1) / bs;
     hipLaunchKernelGGL(k_cell_start, dim3((unsigned)nbk), dim3(bs), 0, s, keys, M,
-                       P.bins.ncells, P.d_cell_start);
+                       P.ncells, P.d_cell_start);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -456,9 +399,9 @@ __global__ void k_gather_values(const int32_t* __restrict__ perm, const double* 
 hamls_status launch_gather_values(const Plan& P, const double* values, int F, int f0, int64_t ld,
                                   hipStream_t s) {
     int bs = 256;
-    int64_t nbk = (P.M + bs - 1) / bs;
+    int64_t nbk = (P.nrec + bs - 1) / bs;
     hipLaunchKernelGGL(k_gather_values, dim3((unsigned)nbk), dim3(bs), 0, s, P.d_perm,
-                       values + (int64_t)f0 * ld, F, ld, P.M, P.cap, P.d_vals, P.d_qr_count);
+                       values + (int64_t)f0 * ld, F, ld, P.nrec, P.cap, P.d_vals, P.d_qr_count);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -484,17 +427,6 @@ S2Geom make_geom(const Plan& P) {
 // ---------------------------------------------------------------------------
 // support radius (eq. (5), (6), (12))
 // ---------------------------------------------------------------------------
-
-// Order-preserving map of doubles to unsigned integers.
-__device__ __forceinline__ uint64_t ordered_bits(double v) {
-    uint64_t b = (uint64_t)__double_as_longlong(v);
-    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double from_ordered_bits(uint64_t u) {
-    uint64_t b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
-    return __longlong_as_double((long long)b);
-}
-
 
 // Support radius, one grid node per block (one wave):
 //  1. an initial radius from the cell density around the node; only where the
@@ -925,72 +857,6 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s) {
 // local solve (eq. (15)-(23))
 // ---------------------------------------------------------------------------
 
-// A centre whose normal-matrix solve is not trustworthy to ~1e-10 is re-solved
-// by QR: Cholesky failure, a pivot of the unit-diagonal C below kPivQR
-// (condition estimate above 1e8), or a Schur denominator below kDenQR
-// (regularized chi_tau above 1e4, where 1 - sum d^2/(1 + tau mu) cancels).
-constexpr double kPivQR = 1e-8;
-constexpr double kDenQR = 1e-4;
-// |R_jj| of the unit-column V at or below which V is taken as rank deficient.
-constexpr double kRankTol = 1e-11;
-
-struct SolveArgs {
-    const double* entries;
-    int64_t MQ;
-    int F;
-    int f0;
-    const int32_t* nj;
-    const uint8_t* rstatus;
-    int reg;
-    double tau_fixed, chi_t, chi_f;
-    double mu[34];       // degree multipliers of the non-constant monomials
-    double* out;         // F_total x MQ
-    double* chi;
-    double* tau;
-    uint8_t* status;
-    int write_diag;
-    int32_t* qr_list;    // centres handed to the QR path
-    int32_t* qr_count;
-};
-
-__device__ __forceinline__ double coupling_tau(const double* d2, const double* mu, int n, double tau) {
-    double r = 0.0;
-    for (int j = 0; j < n; j++) r += d2[j] / (1.0 + tau * mu[j]);
-    return r;
-}
-
-// tau of eq. (22).  Chi-target: 0 for chi <= chi_T; otherwise the tau with
-// chi_tau = chi_T (eq. (23)) by bisection on log tau (64 halvings between 1e-16
-// and the first power of two that overshoots), times the C^3 smoothstep
-// S(t) = 35t^4 - 84t^5 + 70t^6 - 20t^7 of t = (chi - chi_T)/(chi_full - chi_T).
-__device__ double choose_tau(int reg, double chi, const double* d2, const double* mu, int n,
-                             double tau_fixed, double chi_t, double chi_f) {
-    if (reg == HAMLS_REG_FIXED) return tau_fixed;
-    if (reg != HAMLS_REG_CHI_TARGET || !(chi > chi_t)) return 0.0;
-    double target = 1.0 - 1.0 / chi_t;
-    double hi = 1.0;
-    int guard = 0;
-    while (coupling_tau(d2, mu, n, hi) > target && guard < 2000) {
-        hi *= 2.0;
-        guard++;
-    }
-    double a = log(1e-16), b = log(hi);
-    for (int it = 0; it < 64; it++) {
-        double mid = 0.5 * (a + b);
-        if (coupling_tau(d2, mu, n, exp(mid)) > target)
-            a = mid;
-        else
-            b = mid;
-    }
-    double tt = (chi - chi_t) / (chi_f - chi_t);
-    double sm = 1.0;
-    if (tt < 1.0) {
-        double t4 = tt * tt * tt * tt;
-        sm = t4 * (35.0 - 84.0 * tt + 70.0 * tt * tt - 20.0 * tt * tt * tt);
-    }
-    return sm * exp(0.5 * (a + b));
-}
-
 // One thread per grid node: normalise (unit weights sum, unit-norm columns),
 // Cholesky of C, d = L^{-1} b, chi = 1/(1 - |d|^2), tau, and
 //   c_1 = (r_1 - sum_j d_j z_j / (1 + tau mu_j)) / (1 - sum_j d_j^2 / (1 + tau mu_j)),
@@ -1128,11 +994,6 @@ __global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
         A.tau[j] = tau;
         A.status[j] = st;
     }
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
 }
 
 // QR path for the centres flagged by k_solve: the rows (V_i | v1_i | y_w,i) of
@@ -1298,9 +1159,7 @@ __global__ __launch_bounds__(64) void k_s2_qr(S2Geom g, const double* __restrict
     }
 }
 
-hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int Ftotal,
-                          hipStream_t s) {
-    (void)Ftotal;
+SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     SolveArgs A;
     A.entries = P.d_entries;
     A.MQ = P.MQ;
@@ -1313,13 +1172,16 @@ hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int
     A.chi_t = P.prm.chi_target;
     A.chi_f = P.prm.chi_full;
     for (int i = 0; i < 34; i++) A.mu[i] = 0.0;
-    {
-        int c = 0;
-        for (int l = 0; l <= P.K; l++)
-            for (int b = 0; b <= l; b++) {
-                if (c > 0) A.mu[c - 1] = (double)l * (l + 1);
-                c++;
-            }
+    // degree multipliers of eq. (21) in monomial order (by degree): S2 and
+    // SO3 l(l+1), T3 l^2; one per monomial of degree l in D variables
+    int c = 0;
+    for (int l = 0; l <= P.K; l++) {
+        int cnt = P.D == 2 ? l + 1 : (l + 1) * (l + 2) / 2;
+        double mu = P.dom == HAMLS_T3 ? (double)l * l : (double)l * (l + 1);
+        for (int b = 0; b < cnt; b++) {
+            if (c > 0 && c - 1 < 34) A.mu[c - 1] = mu;
+            c++;
+        }
     }
     A.out = grid_values;
     A.chi = P.d_chi;
@@ -1328,6 +1190,13 @@ hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int
     A.write_diag = f0 == 0;
     A.qr_list = P.d_qr_list;
     A.qr_count = P.d_qr_count;
+    return A;
+}
+
+hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int Ftotal,
+                          hipStream_t s) {
+    (void)Ftotal;
+    SolveArgs A = make_solve_args(P, F, f0, grid_values);
     int bs = 256;
     dim3 grid((unsigned)((P.MQ + bs - 1) / bs)), block(bs);
     switch (P.m) {

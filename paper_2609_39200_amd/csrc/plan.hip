@@ -142,24 +142,27 @@ static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
         set_error("params: struct_size mismatch (call hamls_params_init)");
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (p->domain != HAMLS_S2) {
-        set_error("domain %d not built in this library version", p->domain);
-        return HAMLS_ERR_UNSUPPORTED;
+    const int dom = p->domain;
+    if (dom != HAMLS_S2 && dom != HAMLS_SO3 && dom != HAMLS_T3) {
+        set_error("unknown domain %d", dom);
+        return HAMLS_ERR_INVALID_ARG;
     }
     if (p->precision != HAMLS_FP64) {
         set_error("precision %d not built in this library version", p->precision);
         return HAMLS_ERR_UNSUPPORTED;
     }
     int N = p->bandwidth;
-    if (N < 0 || N > 1024) {
-        set_error("bandwidth %d outside [0, 1024]", N);
+    const int Nmax = dom == HAMLS_S2 ? 1024 : (dom == HAMLS_SO3 ? 128 : 511);
+    if (N < 0 || N > Nmax) {
+        set_error("bandwidth %d outside [0, %d]", N, Nmax);
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (p->degree < 0 || p->degree > 4) {
-        set_error("degree %d outside [0, 4]", p->degree);
+    const int Kmax = dom == HAMLS_S2 ? 4 : 3;
+    if (p->degree < 0 || p->degree > Kmax) {
+        set_error("degree %d outside [0, %d]", p->degree, Kmax);
         return HAMLS_ERR_INVALID_ARG;
     }
-    int m = n_monomials(2, p->degree);
+    int m = n_monomials(dom == HAMLS_S2 ? 2 : 3, p->degree);
     if (!(p->support_radius > 0.0) && p->knn_count <= 0) {
         set_error("need a fixed support radius or knn_count");
         return HAMLS_ERR_INVALID_ARG;
@@ -168,13 +171,25 @@ static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
         set_error("support_radius must be >= 0");
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (p->support_radius >= 0.5 * kPi) {
+    if (dom == HAMLS_S2 && p->support_radius >= 0.5 * kPi) {
         set_error("S2 support radius must be < pi/2 (tangent projection)");
+        return HAMLS_ERR_DOMAIN;
+    }
+    if (dom == HAMLS_SO3 && p->support_radius > kPi) {
+        set_error("SO3 support radius (rotation angle) must be <= pi");
+        return HAMLS_ERR_DOMAIN;
+    }
+    if (dom == HAMLS_T3 && p->support_radius >= 0.5) {
+        set_error("T3 support radius must be < 1/2 (minimum-image chart)");
         return HAMLS_ERR_DOMAIN;
     }
     if (p->knn_count > 0 && (p->knn_count < m || !(p->knn_eps > 0.0))) {
         set_error("knn_count must be >= m = %d and knn_eps > 0", m);
         return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->knn_count > kCandCap) {
+        set_error("knn_count %d above %d", p->knn_count, kCandCap);
+        return HAMLS_ERR_UNSUPPORTED;
     }
     if (p->wendland != 1 && p->wendland != 2) {
         set_error("wendland must be 1 or 2");
@@ -192,12 +207,41 @@ static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
         set_error("need 1 < chi_target < chi_full");
         return HAMLS_ERR_INVALID_ARG;
     }
-    dims[0] = p->grid_shape[0] > 0 ? p->grid_shape[0] : N + 1;
-    dims[1] = p->grid_shape[1] > 0 ? p->grid_shape[1] : 2 * N + 2;
-    dims[2] = 1;
-    if (dims[0] < N + 1 || dims[1] < 2 * N + 1) {
-        set_error("grid %d x %d is not exact on Pi_2N for N = %d", dims[0], dims[1], N);
-        return HAMLS_ERR_NOT_EXACT_GRID;
+    if (dom == HAMLS_S2) {
+        dims[0] = p->grid_shape[0] > 0 ? p->grid_shape[0] : N + 1;
+        dims[1] = p->grid_shape[1] > 0 ? p->grid_shape[1] : 2 * N + 2;
+        dims[2] = 1;
+        if (dims[0] < N + 1 || dims[1] < 2 * N + 1) {
+            set_error("grid %d x %d is not exact on Pi_2N for N = %d", dims[0], dims[1], N);
+            return HAMLS_ERR_NOT_EXACT_GRID;
+        }
+        if (dims[0] > 8192 || dims[1] > 16384) {
+            set_error("grid %d x %d too large", dims[0], dims[1]);
+            return HAMLS_ERR_UNSUPPORTED;
+        }
+    } else if (dom == HAMLS_SO3) {
+        dims[0] = p->grid_shape[0] > 0 ? p->grid_shape[0] : N + 1;
+        dims[1] = p->grid_shape[1] > 0 ? p->grid_shape[1] : 2 * N + 1;
+        dims[2] = p->grid_shape[2] > 0 ? p->grid_shape[2] : 2 * N + 1;
+        if (dims[0] < N + 1 || dims[1] < 2 * N + 1 || dims[2] < 2 * N + 1) {
+            set_error("grid %d x %d x %d is not exact for N = %d", dims[0], dims[1], dims[2], N);
+            return HAMLS_ERR_NOT_EXACT_GRID;
+        }
+        if (dims[0] > 1024 || dims[1] > 1024 || dims[2] > 1024) {
+            set_error("grid %d x %d x %d too large", dims[0], dims[1], dims[2]);
+            return HAMLS_ERR_UNSUPPORTED;
+        }
+    } else {
+        int n = p->grid_shape[0] > 0 ? p->grid_shape[0] : 2 * N + 1;
+        dims[0] = dims[1] = dims[2] = n;
+        if (n < 2 * N || n < 1) {
+            set_error("grid %d^3 is not exact for N = %d (need n >= 2N)", n, N);
+            return HAMLS_ERR_NOT_EXACT_GRID;
+        }
+        if (n > 1024) {
+            set_error("grid %d^3 too large", n);
+            return HAMLS_ERR_UNSUPPORTED;
+        }
     }
     return HAMLS_OK;
 }
@@ -258,23 +302,193 @@ static void s2_bins(Plan& P, int64_t M) {
     int bits = 1;
     while ((1ll << bits) < B.ncells) bits++;
     B.key_bits = bits;
+    P.ncells = B.ncells;
+    P.key_bits = bits;
+}
+
+// SO3 / T3 cell grid.  T3: cells of about half the expected radius (uniform
+// density: n nodes in a ball of radius (3n/(4 pi M))^(1/3)), an integer number
+// per unit period.  SO3: records live on the unit 3-sphere in R^4 (2M of them);
+// cells of about the expected chordal radius 2 sin(r/4), r = (6 pi n/M)^(1/3)
+// the rotation angle holding n of M Haar-uniform rotations.  At most 2^24 cells.
+static void grid_bins(Plan& P, int64_t M) {
+    GridBins& B = P.gbins;
+    const double knn = (double)P.prm.knn_count;
+    const double d0 = P.prm.support_radius;
+    if (P.dom == HAMLS_T3) {
+        double r = knn > 0 ? cbrt(3.0 * knn / (4.0 * kPi * (double)M)) : d0;
+        if (d0 > 0.0 && knn > 0) r = std::min(r, d0);
+        double h = 0.5 * r;
+        int nc = (int)floor(1.0 / std::max(h, 1e-6));
+        nc = std::max(1, std::min(nc, 256));
+        B.D = 3;
+        B.nc = nc;
+        B.lo = 0.0;
+        B.h = 1.0 / nc;
+    } else {
+        double r = knn > 0 ? cbrt(6.0 * kPi * knn / (double)M) : d0;
+        if (d0 > 0.0 && knn > 0) r = std::min(r, d0);
+        r = std::min(r, kPi);
+        double rho = 2.0 * sin(0.25 * r);
+        int nc = (int)ceil(2.0 / std::max(rho, 1e-6));
+        nc = std::max(2, std::min(nc, 64));
+        B.D = 4;
+        B.nc = nc;
+        B.lo = -1.0;
+        B.h = 2.0 / nc;
+    }
+    int64_t nc = 1;
+    for (int d = 0; d < B.D; d++) nc *= B.nc;
+    B.ncells = nc;
+    int bits = 1;
+    while ((1ll << bits) < nc) bits++;
+    B.key_bits = bits;
+    P.ncells = nc;
+    P.key_bits = bits;
 }
 
 static hamls_status bind_nodes(Plan& P, const double* nodes, int64_t M, const double* nu,
                                hipStream_t s) {
     P.M = M;
+    P.nrec = P.dom == HAMLS_SO3 ? 2 * M : M;
     P.has_nu = nu != nullptr;
+    const bool s2 = P.dom == HAMLS_S2;
     {
         PhaseTimer pt(P, HAMLS_PHASE_BINNING, s);
-        HAMLS_TRY(launch_s2_keys(P, nodes, M, s));
+        HAMLS_TRY(s2 ? launch_s2_keys(P, nodes, M, s) : launch_grid_keys(P, nodes, M, s));
         int fin = 0;
-        HAMLS_TRY(radix_sort(P, M, s, &fin));
-        HAMLS_TRY(launch_cell_start(P, P.d_key[fin], M, s));
-        HAMLS_TRY(launch_gather_nodes(P, P.d_idx[fin], nodes, nu, M, s));
+        HAMLS_TRY(radix_sort(P, P.nrec, s, &fin));
+        HAMLS_TRY(launch_cell_start(P, P.d_key[fin], P.nrec, s));
+        HAMLS_TRY(s2 ? launch_gather_nodes(P, P.d_idx[fin], nodes, nu, M, s)
+                     : launch_grid_gather(P, P.d_idx[fin], nodes, nu, M, s));
     }
     PhaseTimer pt(P, HAMLS_PHASE_RADIUS, s);
-    HAMLS_TRY(launch_s2_radius(P, s));
+    HAMLS_TRY(s2 ? launch_s2_radius(P, s) : launch_grid_radius(P, s));
     return HAMLS_OK;
+}
+
+// Node-side buffers of a plan (sorted records, keys, cells) and the per-centre
+// state, shared by all domains.
+static hamls_status alloc_common(Plan& P, int dimx) {
+    HAMLS_TRY(dalloc(P, &P.d_grid, (size_t)dimx * P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_x, (size_t)dimx * P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_nu, P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_perm, P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_key[0], P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_key[1], P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_idx[0], P.cap));
+    HAMLS_TRY(dalloc(P, &P.d_idx[1], P.cap));
+    P.hist_len = 256 * ((P.cap + 4095) / 4096 + 1);
+    HAMLS_TRY(dalloc(P, &P.d_hist, P.hist_len));
+    HAMLS_TRY(dalloc(P, &P.d_cell_start, P.ncells + 1));
+    HAMLS_TRY(dalloc(P, &P.d_delta, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_thr, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_status, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_rstatus, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_nj, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_chi, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_tau, P.MQ));
+    int EG = P.m * (P.m + 1) / 2;
+    P.n_entries_cap = EG + (int64_t)P.m * kMaxFieldsPerPass;
+    HAMLS_TRY(dalloc(P, &P.d_entries, P.n_entries_cap * P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_qr_list, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_qr_count, 64));
+    HAMLS_TRY(dalloc(P, &P.d_vals, (size_t)kMaxFieldsPerPass * P.cap));
+    return HAMLS_OK;
+}
+
+static void twiddles(int n, std::vector<double>& tw) {
+    tw.assign(2 * (size_t)n, 0.0);
+    for (int e = 0; e < n; e++) {
+        double a = 2.0 * kPi * e / n;
+        tw[e] = cos(a);
+        tw[n + e] = sin(a);
+    }
+}
+
+// unit quaternion of the rotation R_z(a) R_y(b) R_z(g) (Euler ZYZ)
+static void euler_quaternion(double a, double b, double g, double* q) {
+    double cb = cos(0.5 * b), sb = sin(0.5 * b);
+    double sp = 0.5 * (a + g), dm = 0.5 * (a - g);
+    q[0] = cb * cos(sp);
+    q[1] = -sb * sin(dm);
+    q[2] = sb * cos(dm);
+    q[3] = cb * sin(sp);
+}
+
+// SO3 and T3 plans: the product grid of Sec. 2.1 (SO3: Gauss-Legendre in
+// cos(beta) x trapezoid in alpha and gamma; T3: the equispaced periodic grid),
+// the cell grid, and the quadrature tables (axis twiddles; SO3 Wigner table).
+static hamls_status build_grid_plan(Plan& P, const double* nodes, int64_t M, const double* nu,
+                                    hipStream_t s) {
+    const bool so3 = P.dom == HAMLS_SO3;
+    const int dimx = so3 ? 4 : 3;
+    P.D = 3;
+    P.m = n_monomials(3, P.K);
+    P.MQ = (int64_t)P.dims[0] * P.dims[1] * P.dims[2];
+    const int N = P.N;
+    if (so3)
+        P.ncoef = (int64_t)(N + 1) * (2 * N + 1) * (2 * N + 3) / 3;
+    else
+        P.ncoef = (int64_t)P.dims[0] * P.dims[0] * P.dims[0];
+    P.mcap = M;
+    P.cap = so3 ? 2 * M : M;
+    P.h_grid.resize((size_t)dimx * P.MQ);
+    P.h_wts.resize(P.MQ);
+    std::vector<double> tw0, tw1;
+    if (so3) {
+        const int nb = P.dims[0], na = P.dims[1], ng = P.dims[2];
+        gauss_legendre(nb, P.h_glx, P.h_glw);
+        P.h_theta.resize(nb);
+        for (int t = 0; t < nb; t++) {
+            const double beta = acos(P.h_glx[t]);
+            P.h_theta[t] = beta;
+            for (int a = 0; a < na; a++)
+                for (int g = 0; g < ng; g++) {
+                    const int64_t j = ((int64_t)t * na + a) * ng + g;
+                    euler_quaternion(2.0 * kPi * a / na, beta, 2.0 * kPi * g / ng, &P.h_grid[4 * j]);
+                    P.h_wts[j] = P.h_glw[t] * (2.0 * kPi / na) * (2.0 * kPi / ng);
+                }
+        }
+        twiddles(na, tw0);
+        twiddles(ng, tw1);
+    } else {
+        const int n = P.dims[0];
+        const double w = 1.0 / ((double)n * n * n);
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++)
+                for (int c = 0; c < n; c++) {
+                    const int64_t j = ((int64_t)a * n + b) * n + c;
+                    P.h_grid[3 * j + 0] = (double)a / n;
+                    P.h_grid[3 * j + 1] = (double)b / n;
+                    P.h_grid[3 * j + 2] = (double)c / n;
+                    P.h_wts[j] = w;
+                }
+        twiddles(n, tw0);
+    }
+    grid_bins(P, M);
+    HAMLS_TRY(alloc_common(P, dimx));
+    HAMLS_TRY(dalloc(P, &P.d_tw_ax[0], tw0.size()));
+    HAMLS_HIP(hipMemcpyAsync(P.d_tw_ax[0], tw0.data(), sizeof(double) * tw0.size(),
+                             hipMemcpyHostToDevice, s));
+    if (so3) {
+        const int nb = P.dims[0];
+        HAMLS_TRY(dalloc(P, &P.d_tw_ax[1], tw1.size()));
+        HAMLS_TRY(dalloc(P, &P.d_theta, nb));
+        HAMLS_TRY(dalloc(P, &P.d_ring_w, nb));
+        HAMLS_TRY(dalloc(P, &P.d_wtab, (size_t)nb * P.ncoef));
+        HAMLS_HIP(hipMemcpyAsync(P.d_tw_ax[1], tw1.data(), sizeof(double) * tw1.size(),
+                                 hipMemcpyHostToDevice, s));
+        HAMLS_HIP(hipMemcpyAsync(P.d_theta, P.h_theta.data(), sizeof(double) * nb,
+                                 hipMemcpyHostToDevice, s));
+        HAMLS_HIP(hipMemcpyAsync(P.d_ring_w, P.h_glw.data(), sizeof(double) * nb,
+                                 hipMemcpyHostToDevice, s));
+        HAMLS_TRY(launch_wigner_table(P, P.d_theta, P.d_ring_w, s));
+    }
+    HAMLS_HIP(hipMemcpyAsync(P.d_grid, P.h_grid.data(), sizeof(double) * dimx * P.MQ,
+                             hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipStreamSynchronize(s));
+    return bind_nodes(P, nodes, M, nu, s);
 }
 
 static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nodes, int64_t M,
@@ -284,11 +498,13 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     P.dom = p->domain;
     P.N = p->bandwidth;
     P.K = p->degree;
+    if (P.dom != HAMLS_S2) return build_grid_plan(P, nodes, M, nu, s);
     P.D = 2;
     P.m = n_monomials(2, P.K);
     int nt = P.dims[0], np = P.dims[1];
     P.MQ = (int64_t)nt * np;
     P.ncoef = (int64_t)(P.N + 1) * (P.N + 1);
+    P.mcap = M;
     P.cap = M;
 
     // grid: GL in cos(theta) x trapezoid in phi
@@ -317,35 +533,12 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     }
     s2_bins(P, M);
 
-    HAMLS_TRY(dalloc(P, &P.d_grid, 3 * P.MQ));
+    HAMLS_TRY(alloc_common(P, 3));
     HAMLS_TRY(dalloc(P, &P.d_theta, nt));
     HAMLS_TRY(dalloc(P, &P.d_phi, np));
     HAMLS_TRY(dalloc(P, &P.d_ring_cs, 2 * (size_t)nt));
     HAMLS_TRY(dalloc(P, &P.d_col_cs, 2 * (size_t)np));
-    HAMLS_TRY(dalloc(P, &P.d_x, 3 * P.cap));
-    HAMLS_TRY(dalloc(P, &P.d_nu, P.cap));
-    HAMLS_TRY(dalloc(P, &P.d_perm, P.cap));
-    HAMLS_TRY(dalloc(P, &P.d_key[0], P.cap));
-    HAMLS_TRY(dalloc(P, &P.d_key[1], P.cap));
-    HAMLS_TRY(dalloc(P, &P.d_idx[0], P.cap));
-    HAMLS_TRY(dalloc(P, &P.d_idx[1], P.cap));
-    P.hist_len = 256 * ((P.cap + 4095) / 4096 + 1);
-    HAMLS_TRY(dalloc(P, &P.d_hist, P.hist_len));
     HAMLS_TRY(dalloc(P, &P.d_band_off, P.bins.nb + 1));
-    HAMLS_TRY(dalloc(P, &P.d_cell_start, P.bins.ncells + 1));
-    HAMLS_TRY(dalloc(P, &P.d_delta, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_thr, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_status, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_rstatus, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_nj, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_chi, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_tau, P.MQ));
-    int EG = P.m * (P.m + 1) / 2;
-    P.n_entries_cap = EG + (int64_t)P.m * kMaxFieldsPerPass;
-    HAMLS_TRY(dalloc(P, &P.d_entries, P.n_entries_cap * P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_qr_list, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_qr_count, 64));
-    HAMLS_TRY(dalloc(P, &P.d_vals, (size_t)kMaxFieldsPerPass * P.cap));
 
     // step-3 tables: Legendre table of the northern rings with the GL weights
     // folded in, and the ring twiddles
@@ -429,8 +622,11 @@ hamls_status hamls_plan(const hamls_params* p, const double* nodes, int64_t M,
     *out = nullptr;
     int32_t dims[3];
     HAMLS_TRY(check_params(p, dims));
-    if (M < 1 || M > ((int64_t)1 << 31) - 4096 || (p->knn_count > 0 && M < p->knn_count)) {
-        set_error("node count %lld invalid (need 1 <= M < 2^31, M >= knn_count)", (long long)M);
+    // sorted records are indexed by int32 (SO3 stores two per node)
+    const int64_t rec_max = (((int64_t)1 << 31) - 4096) / (p->domain == HAMLS_SO3 ? 2 : 1);
+    if (M < 1 || M > rec_max || (p->knn_count > 0 && M < p->knn_count)) {
+        set_error("node count %lld invalid (need 1 <= M <= %lld, M >= knn_count)", (long long)M,
+                  (long long)rec_max);
         return HAMLS_ERR_INVALID_ARG;
     }
     Plan* P = new (std::nothrow) Plan();
@@ -456,9 +652,9 @@ hamls_status hamls_plan_rebind(hamls_plan_t plan, const double* nodes, int64_t M
         set_error("null argument");
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (M < 1 || M > P->cap || (P->prm.knn_count > 0 && M < P->prm.knn_count)) {
+    if (M < 1 || M > P->mcap || (P->prm.knn_count > 0 && M < P->prm.knn_count)) {
         set_error("node count %lld outside [max(1, knn_count), capacity %lld]", (long long)M,
-                  (long long)P->cap);
+                  (long long)P->mcap);
         return HAMLS_ERR_INVALID_ARG;
     }
     return bind_nodes(*P, nodes, M, node_weights, (hipStream_t)stream);
@@ -482,12 +678,23 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
             PhaseTimer pt(*P, HAMLS_PHASE_GATHER, s);
             HAMLS_TRY(launch_gather_values(*P, values, Fc, f0, ld, s));
         }
-        {
-            PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
-            HAMLS_TRY(launch_s2_assemble(*P, Fc, f0, s));
+        if (P->dom == HAMLS_S2) {
+            {
+                PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
+                HAMLS_TRY(launch_s2_assemble(*P, Fc, f0, s));
+            }
+            PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
+            HAMLS_TRY(launch_solve(*P, Fc, f0, grid_values, F, s));
+        } else {
+            // assembly and the normal-matrix solve are fused; the QR re-solve
+            // of the flagged centres is the solve phase
+            {
+                PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
+                HAMLS_TRY(launch_grid_mls(*P, Fc, f0, grid_values, s));
+            }
+            PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
+            HAMLS_TRY(launch_grid_qr(*P, Fc, f0, grid_values, s));
         }
-        PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
-        HAMLS_TRY(launch_solve(*P, Fc, f0, grid_values, F, s));
     }
     return HAMLS_OK;
 }
@@ -504,27 +711,71 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
         return HAMLS_ERR_INVALID_ARG;
     }
     hipStream_t s = (hipStream_t)stream;
+    // work memory grows with the field count of the largest call
     if (F > P->G_fields) {
-        if (P->d_G) {
-            HAMLS_HIP(hipStreamSynchronize(s));
+        int64_t len0 = 0, len1 = 0;
+        const int N = P->N, K2 = 2 * N + 1;
+        if (P->dom == HAMLS_S2) {
+            len0 = (int64_t)F * P->dims[0] * (N + 1) * 2;
+        } else if (P->dom == HAMLS_SO3) {
+            len0 = (int64_t)F * P->dims[0] * K2 * P->dims[2] * 2;
+            len1 = (int64_t)F * P->dims[0] * K2 * K2 * 2;
+        } else {
+            len0 = len1 = (int64_t)F * P->MQ * 2;
+        }
+        HAMLS_HIP(hipStreamSynchronize(s));
+        for (double** slot : {&P->d_G, &P->d_work[0], &P->d_work[1]}) {
+            if (!*slot) continue;
             for (auto it = P->owned.begin(); it != P->owned.end(); ++it)
-                if (it->p == P->d_G) {
+                if (it->p == *slot) {
                     (void)hipFree(it->p);
                     P->resident -= (int64_t)it->bytes;
                     P->owned.erase(it);
                     break;
                 }
-            P->d_G = nullptr;
+            *slot = nullptr;
         }
-        HAMLS_TRY(dalloc(*P, &P->d_G, (size_t)F * P->dims[0] * (P->N + 1) * 2));
+        P->G_fields = 0;
+        if (P->dom == HAMLS_S2) {
+            HAMLS_TRY(dalloc(*P, &P->d_G, len0));
+        } else {
+            HAMLS_TRY(dalloc(*P, &P->d_work[0], len0));
+            HAMLS_TRY(dalloc(*P, &P->d_work[1], len1));
+        }
         P->G_fields = F;
     }
-    {
-        PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
-        HAMLS_TRY(launch_s2_ring_dft(*P, grid_values, F, s));
+    if (P->dom == HAMLS_S2) {
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
+            HAMLS_TRY(launch_s2_ring_dft(*P, grid_values, F, s));
+        }
+        PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s);
+        HAMLS_TRY(launch_s2_legendre(*P, F, coeffs, s));
+        return HAMLS_OK;
     }
-    PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s);
-    HAMLS_TRY(launch_s2_legendre(*P, F, coeffs, s));
+    if (P->dom == HAMLS_SO3) {
+        const int nb = P->dims[0], na = P->dims[1], ng = P->dims[2], N = P->N, K2 = 2 * N + 1;
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
+            // [f][t][a][g] -> [f][t][k][g] -> [f][t][k][k']
+            HAMLS_TRY(launch_dft_axis(grid_values, true, P->d_work[0], (int64_t)F * nb, na, ng, K2, N,
+                                      1.0, 2.0 * kPi / na, P->d_tw_ax[0], s));
+            HAMLS_TRY(launch_dft_axis(P->d_work[0], false, P->d_work[1], (int64_t)F * nb * K2, ng, 1, K2,
+                                      N, 1.0, 2.0 * kPi / ng, P->d_tw_ax[1], s));
+        }
+        PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s);
+        HAMLS_TRY(launch_so3_contract(*P, P->d_work[1], F, coeffs, s));
+        return HAMLS_OK;
+    }
+    const int n = P->dims[0], h = n / 2;
+    const int64_t n2 = (int64_t)n * n;
+    PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
+    HAMLS_TRY(launch_dft_axis(grid_values, true, P->d_work[0], F, n, n2, n, h, -1.0, 1.0,
+                              P->d_tw_ax[0], s));
+    HAMLS_TRY(launch_dft_axis(P->d_work[0], false, P->d_work[1], (int64_t)F * n, n, n, n, h, -1.0, 1.0,
+                              P->d_tw_ax[0], s));
+    HAMLS_TRY(launch_dft_axis(P->d_work[1], false, coeffs, (int64_t)F * n2, n, 1, n, h, -1.0,
+                              1.0 / ((double)n * n2), P->d_tw_ax[0], s));
     return HAMLS_OK;
 }
 
@@ -540,6 +791,12 @@ hamls_status hamls_eval(hamls_plan_t plan, const double* coeffs, int32_t F, cons
         return HAMLS_ERR_INVALID_ARG;
     }
     if (npts == 0) return HAMLS_OK;
+    if (npts > 0x7fffffff) {
+        set_error("too many points");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (P->dom == HAMLS_SO3) return launch_so3_eval(*P, coeffs, F, points, npts, out, (hipStream_t)stream);
+    if (P->dom == HAMLS_T3) return launch_t3_eval(*P, coeffs, F, points, npts, out, (hipStream_t)stream);
     return launch_s2_eval(*P, coeffs, F, points, npts, out, (hipStream_t)stream);
 }
 
@@ -567,9 +824,9 @@ hamls_status hamls_plan_info_get(hamls_plan_t plan, hamls_plan_info* o) {
     o->num_grid = P->MQ;
     o->num_coeffs = P->ncoef;
     o->num_nodes = P->M;
-    o->node_capacity = P->cap;
+    o->node_capacity = P->mcap;
     o->resident_bytes = P->resident;
-    o->num_cells = P->bins.ncells;
+    o->num_cells = P->ncells;
     return HAMLS_OK;
 }
 
@@ -594,7 +851,8 @@ hamls_status hamls_plan_neighbors(hamls_plan_t plan, int64_t* row_ptr, int32_t* 
     HAMLS_HIP(hipDeviceSynchronize());
     int32_t* d_cnt = nullptr;
     HAMLS_HIP(hipMalloc(&d_cnt, sizeof(int32_t) * P->MQ));
-    hamls_status st = launch_s2_count(*P, d_cnt, s);
+    hamls_status st = P->dom == HAMLS_S2 ? launch_s2_count(*P, d_cnt, s)
+                                         : launch_grid_list(*P, nullptr, d_cnt, nullptr, s);
     std::vector<int32_t> cnt(P->MQ);
     if (st == HAMLS_OK) {
         hipError_t e = hipMemcpy(cnt.data(), d_cnt, sizeof(int32_t) * P->MQ, hipMemcpyDeviceToHost);
@@ -616,7 +874,8 @@ hamls_status hamls_plan_neighbors(hamls_plan_t plan, int64_t* row_ptr, int32_t* 
     }
     e = hipMemcpy(d_rp, row_ptr, sizeof(int64_t) * (P->MQ + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        st = launch_s2_list(*P, d_rp, d_idx, s);
+        st = P->dom == HAMLS_S2 ? launch_s2_list(*P, d_rp, d_idx, s)
+                                : launch_grid_list(*P, d_rp, nullptr, d_idx, s);
         if (st == HAMLS_OK) e = hipMemcpy(idx, d_idx, sizeof(int32_t) * tot, hipMemcpyDeviceToHost);
     }
     (void)hipFree(d_rp);
