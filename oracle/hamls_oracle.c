@@ -28,8 +28,8 @@
  *   T3   [0,1)^3, grid x = i/n laid out [i0][i1][i2], basis e^{2 pi i k.x},
  *        coefficients centred-lexicographic k_d in [-(n/2), n-1-(n/2)].
  *
- * Readings of places where the paper is silent are listed in the design doc and
- * repeated at the routine that takes them.
+ * Where the paper is silent, the reading taken is stated at the routine that
+ * takes it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -645,7 +645,8 @@ static void work_free(orc_work* wk)
  *  4. B = (v_1 V); the Cholesky factor L of C = V^T V is obtained as R^T
  *     from a Householder QR of V (eq. (20)); d = L^{-1} b with b = V^T v_1
  *     equals S Q^T v_1, S = sign(diag R)
- *  5. chi = 1/(1 - |d|^2)  (eq. (19))
+ *  5. chi = 1/(1 - |d|^2)  (eq. (19)), with 1 - |d|^2 taken as the squared
+ *     residual of v_1 off span(V)
  *  6. tau: none / fixed / chi-target by bisection + smooth transition
  *  7. c_1 = first coefficient of the minimiser of (22), obtained by a second
  *     Householder QR of the augmented least-squares matrix
@@ -737,10 +738,13 @@ static void mls_centre(const orc_params* p, const double* q, double delta, int n
                 d[j] = sgn[j] * wk->E[j];
                 mu[j] = degree_multiplier(dom, degs[j + 1]);
             }
-            /* step 5 */
-            double r0 = 0.0;
-            for (int j = 0; j < mv; j++) r0 += d[j] * d[j];
-            double chi = 1.0 / (1.0 - r0);
+            /* step 5: since |v_1| = 1 (weights normalised to sum 1),
+             * 1 - |d|^2 = |(I - P_V) v_1|^2, the squared norm of the entries
+             * of Q^T v_1 below the first m-1; summed directly, without the
+             * cancellation of 1 - |d|^2 when v_1 is close to span(V) */
+            double res = 0.0;
+            for (int i = mv; i < n; i++) res += wk->E[i] * wk->E[i];
+            double chi = 1.0 / res;
             /* step 6 */
             double tau = 0.0;
             if (p->reg == ORC_REG_FIXED) {
