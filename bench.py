@@ -1,15 +1,19 @@
 #!/usr/bin/env python
 """Benchmark of the HAMLS hot path on one MI355X.
 
-Workload: S2 ill-distributed nodes, M = 200,000 (8 von Mises-Fisher clusters
-with kappa = 20 plus 20 % uniform, five 20-degree caps removed), bandwidth
-N = 128, MLS degree K = 3 (m = 10), Gauss-Legendre grid 129 x 258 (33,282
-local solves), adaptive radius with n = 40, eps = 0.05, chi-target
-regularization (chi_T = 10, chi_full = 20), one field, FP64.
+Default workload (--workload c2): S2 ill-distributed nodes, M = 200,000 (8
+von Mises-Fisher clusters with kappa = 20 plus 20 % uniform, five 20-degree
+caps removed), bandwidth N = 128, MLS degree K = 3 (m = 10), Gauss-Legendre
+grid 129 x 258 (33,282 local solves), adaptive radius with n = 40, eps = 0.05,
+chi-target regularization (chi_T = 10, chi_full = 20), one field, FP64.
+Other workloads: c3 (S2, M = 4e6, N = 512, K = 4, grid 513 x 1026, n = 60),
+so3 (M = 1e6 rotations, N = 64, K = 2, Euler grid 130^3, n = 40), t3 (M = 2e6
+points, N = 64, K = 3, grid 128^3, n = 80).
 
 One step = one whole fit with the inputs resident in device memory:
 node binning + sort + support radii (plan rebind), the MLS value at every grid
-node (Gram assembly + regularized solve), ring DFTs + Legendre contraction.
+node (Gram assembly + regularized solve), the quadrature (ring DFTs + Legendre
+contraction on S2; axis DFTs + Wigner contraction on SO(3); 3-D DFT on T3).
 value = grid nodes solved per second = M_Q * F * steps / wall time of the
 timed steps.  Prints one JSON line.
 """
@@ -35,6 +39,17 @@ def pct(a, q):
 
 PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble", "solve": "k_solve",
                 "ring_dft": "k_s2_ring_dft", "contract": "k_s2_legendre", "gather": "k_gather_values"}
+
+WORKLOADS = {
+    "c2": ("s2_clusters", "S2 ill-distributed, M=200000 (8 vMF clusters kappa=20 + 20% uniform, 5 caps of 20 deg "
+                          "removed), N=128, K=3, grid 129x258, kNN n=40 eps=0.05, chi_T=10 chi_full=20, F=1, FP64"),
+    "c3": ("s2_large", "S2 ill-distributed, M=4000000 (8 vMF clusters kappa=20 + 20% uniform, 12 caps of 10-25 deg "
+                       "removed), N=512, K=4, grid 513x1026, kNN n=60 eps=0.05, chi_T=10 chi_full=20, F=1, FP64"),
+    "so3": ("so3_clusters", "SO(3), M=1000000 rotations (50% Haar + 4 clusters sigma=0.15), N=64, K=2, Euler grid "
+                            "130^3, kNN n=40 eps=0.05, chi_T=10 chi_full=20, F=1, FP64"),
+    "t3": ("t3_clusters", "T3, M=2000000 (8 periodic Gaussian clusters sigma=0.05 + 20% uniform, 6 balls removed), "
+                          "N=64, K=3, grid 128^3, kNN n=80 eps=0.05, chi_T=10 chi_full=20, F=1, FP64"),
+}
 
 
 def measured_traffic(kernel):
@@ -65,12 +80,15 @@ def measured_traffic(kernel):
     return (float(k["fetch_kib"]) * fs + float(k["write_kib"]) * ws) * 1024.0
 
 
-def flops_per_pair(m, F):
-    """Algorithmic FLOPs of one (grid node, neighbour) pair in the fused MLS
-    step: predicate 5, tangent coordinates 12, weight 10 (distance, Wendland,
-    node weight, square root), monomials and weighting 2m, Gram m(m+1),
-    right-hand sides 2mF."""
-    return 5 + 12 + 10 + 2 * m + m * (m + 1) + 2 * m * F
+def flops_per_pair(domain, m, F):
+    """Algorithmic FLOPs of one (grid node, neighbour) pair in the MLS step:
+    membership key (S2 dot 5, SO3 dot 7, T3 min-image distance 12), tangent
+    coordinates (S2 12, SO3 24, T3 3), weight 10 (distance, Wendland, node
+    weight, square root), monomials and weighting 2m, Gram m(m+1), right-hand
+    sides 2mF."""
+    key = {"s2": 5, "so3": 7, "t3": 12}[domain]
+    crd = {"s2": 12, "so3": 24, "t3": 3}[domain]
+    return key + crd + 10 + 2 * m + m * (m + 1) + 2 * m * F
 
 
 def main():
@@ -79,6 +97,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -86,8 +105,8 @@ def main():
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the multi-GPU design is "
-                          "described in DESIGN.md and is not built"}), flush=True)
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; a multi-GPU path is "
+                          "not built"}), flush=True)
         sys.exit(2)
 
     import torch
@@ -96,7 +115,9 @@ def main():
     from paper_2609_39200_amd import workloads as W
 
     t_gen = time.time()
-    wl = W.s2_clusters()
+    builder, wl_desc = WORKLOADS[args.workload]
+    wl = getattr(W, builder)()
+    domain = wl.domain
     F = wl.values.shape[0]
     dev = torch.device("cuda:0")
     nodes = torch.as_tensor(wl.nodes, dtype=torch.float64, device=dev).contiguous()
@@ -150,29 +171,45 @@ def main():
     m = info.m
     dom = max(phases, key=lambda k: phases[k]["avg_ms"])
     roof = None
-    traffic = measured_traffic(PHASE_KERNEL.get(dom))
+    traffic = measured_traffic(PHASE_KERNEL.get(dom)) if args.workload == "c2" else None
     if dom == "assemble":
-        fl = pairs * flops_per_pair(m, F)
+        fpp = flops_per_pair(domain, m, F)
+        fl = pairs * fpp
         ach = fl / (phases[dom]["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": "assemble", "bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
-                "units_per_launch": {"pairs": pairs, "flop_per_pair": flops_per_pair(m, F)}}
+                "units_per_launch": {"pairs": pairs, "flop_per_pair": fpp}}
     else:
         # other phases are priced on their algorithmic HBM bytes
         Mn = info.num_nodes
         nt, npf = info.grid_dims[0], info.grid_dims[1]
         N = info.bandwidth
+        dimx = 4 if domain == "so3" else 3
+        nrec = 2 * Mn if domain == "so3" else Mn
+        rec = 8 * dimx
         bytes_by_phase = {
-            # keys: read 24 B + write 4+4 B; per pass 16 B (2 keys+2 indices, r+w)
-            # x 2 passes; cell table; gather 4+24 B read, 24+4 B write
-            "binning": Mn * (24 + 8 + 2 * 16 + 8 + 56),
-            # every candidate record read once (24 B), radius writes
-            "radius": pairs * 24 + MQ * 17,
+            # keys: read coordinates + write key and index; per radix pass
+            # 16 B (key + index, read + write); cell table; gather: index and
+            # coordinates read, coordinates and permutation written
+            "binning": Mn * 8 * dimx + nrec * (8 + 2 * 16 + 8 + 2 * (4 + rec)),
+            # every candidate record read once, radius writes
+            "radius": pairs * rec + MQ * 17,
             "solve": MQ * (8 * (m * (m + 1) // 2 + m * F) + 4 + 8 * F + 17),
-            "ring_dft": MQ * 8 * F + nt * (N + 1) * 16 * F,
-            "contract": ((nt + 1) // 2) * ((N + 1) * (N + 2) // 2) * 8 + (N + 1) ** 2 * 16 * F,
-            "gather": Mn * (4 + 16 * F),
+            "gather": nrec * (4 + 16 * F),
         }
+        if domain == "s2":
+            bytes_by_phase["ring_dft"] = MQ * 8 * F + nt * (N + 1) * 16 * F
+            bytes_by_phase["contract"] = (((nt + 1) // 2) * ((N + 1) * (N + 2) // 2) * 8
+                                          + (N + 1) ** 2 * 16 * F)
+        elif domain == "so3":
+            K2 = 2 * N + 1
+            nb, na, ng = info.grid_dims[0], info.grid_dims[1], info.grid_dims[2]
+            # alpha pass: real grid in, (k, gamma) spectra out; gamma pass
+            bytes_by_phase["ring_dft"] = F * nb * (na * ng * 8 + 2 * K2 * ng * 16 + K2 * K2 * 16)
+            bytes_by_phase["contract"] = nb * info.num_coeffs * 8 + F * (nb * K2 * K2 + info.num_coeffs) * 16
+        else:
+            # three axis passes: real in / complex out, then complex in / out twice
+            bytes_by_phase["ring_dft"] = F * MQ * (8 + 16 + 4 * 16)
         b = bytes_by_phase.get(dom, 0)
         ach = b / (phases[dom]["avg_ms"] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -192,8 +229,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "S2 ill-distributed, M=200000 (8 vMF clusters kappa=20 + 20% uniform, 5 caps of 20 deg "
-                        "removed), N=128, K=3, grid 129x258, kNN n=40 eps=0.05, chi_T=10 chi_full=20, F=1, FP64",
+            "workload": wl_desc,
             "grid_nodes": MQ,
             "nodes": int(info.num_nodes),
             "fields": F,

@@ -25,6 +25,7 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
 constexpr int kMaxFieldsPerPass = 16;  // fields handled by one assembly pass
 constexpr int kCandCap = 1024;         // LDS candidate buffer of the radius search
+constexpr int kResolveBlocks = 131072; // blocks of the double-double re-solve (grid-stride)
 
 void set_error(const char* fmt, ...);
 hamls_status hip_status(hipError_t e, const char* what);
@@ -104,8 +105,8 @@ struct Plan {
     double* d_chi = nullptr;        // MQ
     double* d_tau = nullptr;        // MQ
     double* d_entries = nullptr;    // n_entries x MQ
-    int32_t* d_qr_list = nullptr;   // MQ, centres re-solved by QR
-    int32_t* d_qr_count = nullptr;  // 1
+    int32_t* d_rs_list = nullptr;   // MQ, centres re-solved by QR
+    int32_t* d_rs_count = nullptr;  // 1
     int64_t n_entries_cap = 0;
     double* d_vals = nullptr;       // sorted values, kMaxFieldsPerPass x cap
     double* d_ptab = nullptr;       // Legendre table
@@ -163,8 +164,8 @@ struct SolveArgs {
     double* tau;
     uint8_t* status;
     int write_diag;
-    int32_t* qr_list;    // centres handed to the QR path
-    int32_t* qr_count;
+    int32_t* rs_list;    // centres handed to the double-double re-solve
+    int32_t* rs_count;
 };
 
 
@@ -177,9 +178,8 @@ hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t n, h
 hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double* nodes,
                                  const double* nu, int64_t M, hipStream_t s);
 hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
-hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s);
-hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int Ftotal,
-                          hipStream_t s);
+hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 hamls_status launch_gather_values(const Plan& P, const double* values, int F, int f0, int64_t ld,
                                   hipStream_t s);
 hamls_status launch_s2_count(const Plan& P, int32_t* counts, hipStream_t s);
@@ -195,7 +195,7 @@ hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double*
                                 const double* nu, int64_t M, hipStream_t s);
 hamls_status launch_grid_radius(const Plan& P, hipStream_t s);
 hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
-hamls_status launch_grid_qr(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 hamls_status launch_grid_list(const Plan& P, const int64_t* row_ptr, int32_t* counts, int32_t* idx,
                               hipStream_t s);
 

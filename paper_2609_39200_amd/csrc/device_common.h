@@ -77,43 +77,61 @@ __device__ __forceinline__ double from_ordered_bits(uint64_t u) {
 }
 
 
-// A centre whose normal-matrix solve is not trustworthy to ~1e-10 is re-solved
-// by QR: Cholesky failure, a pivot of the unit-diagonal C below kPivQR
-// (condition estimate above 1e8), or a Schur denominator below kDenQR
-// (regularized chi_tau above 1e4, where 1 - sum d^2/(1 + tau mu) cancels).
-constexpr double kPivQR = 1e-8;
-constexpr double kDenQR = 1e-4;
-// |R_jj| of the unit-column V at or below which V is taken as rank deficient.
+// A centre whose FP64 normal-matrix solve is not trustworthy to ~1e-10 is
+// re-solved with the Gram matrix in double-double precision: Cholesky
+// failure, a pivot of the unit-diagonal C below kPivResolve (condition estimate
+// above 1e8), or a Schur denominator below kDenResolve.
+constexpr double kPivResolve = 1e-8;
+constexpr double kDenResolve = 1e-4;
+// |R_jj| of the unit-column V at or below which V is taken as rank deficient
+// (compared as the squared pivot of the unit-diagonal C).
 constexpr double kRankTol = 1e-11;
 
-__device__ __forceinline__ double coupling_tau(const double* d2, const double* mu, int n, double tau) {
-    double r = 0.0;
-    for (int j = 0; j < n; j++) r += d2[j] / (1.0 + tau * mu[j]);
-    return r;
-}
-
-// tau of eq. (22).  Chi-target: 0 for chi <= chi_T; otherwise the tau with
-// chi_tau = chi_T (eq. (23)) by bisection on log tau (64 halvings between 1e-16
-// and the first power of two that overshoots), times the C^3 smoothstep
-// S(t) = 35t^4 - 84t^5 + 70t^6 - 20t^7 of t = (chi - chi_T)/(chi_full - chi_T).
-__device__ inline double choose_tau(int reg, double chi, const double* d2, const double* mu, int n,
-                             double tau_fixed, double chi_t, double chi_f) {
+// tau of eq. (22), evaluated by a whole wave (all 64 lanes active, uniform
+// inputs).  Chi-target: 0 for chi <= chi_T; otherwise the tau with chi_tau =
+// chi_T (eq. (23)), times the C^3 smoothstep S(t) = 35t^4 - 84t^5 + 70t^6 -
+// 20t^7 of t = (chi - chi_T)/(chi_full - chi_T).  The root of r_tau = 1 -
+// 1/chi_T is bracketed between 1e-16 and the first power of two where r_tau
+// falls below the target (r_tau decreases in tau), then located on log tau by
+// a 64-way search: each round the lanes evaluate r_tau at 64 interior points
+// and the bracket shrinks to the sub-interval of the crossing, 65x per round;
+// 11 rounds resolve the root beyond 64 halvings.  mu is constant over the
+// monomials of one degree: one division per degree.
+__device__ __forceinline__ double choose_tau(int reg, double chi, const double* d2, const double* mu,
+                                         int n, double tau_fixed, double chi_t, double chi_f) {
     if (reg == HAMLS_REG_FIXED) return tau_fixed;
     if (reg != HAMLS_REG_CHI_TARGET || !(chi > chi_t)) return 0.0;
-    double target = 1.0 - 1.0 / chi_t;
-    double hi = 1.0;
-    int guard = 0;
-    while (coupling_tau(d2, mu, n, hi) > target && guard < 2000) {
-        hi *= 2.0;
-        guard++;
+    const int lane = threadIdx.x & 63;
+    // one division per run of equal mu (mu is sorted by degree)
+    auto coupling = [&](double tau) {
+        double r = 0.0, cur = -1.0, inv = 0.0;
+        for (int j = 0; j < n; j++) {
+            if (mu[j] != cur) {
+                cur = mu[j];
+                inv = 1.0 / (1.0 + tau * cur);
+            }
+            r += d2[j] * inv;
+        }
+        return r;
+    };
+    const double target = 1.0 - 1.0 / chi_t;
+    // upper end: the first power of two 2^e with r <= target
+    double hi = 0.0;
+    for (int e0 = 0; e0 < 2048 && hi == 0.0; e0 += 64) {
+        const double t = ldexp(1.0, e0 + lane);
+        const uint64_t over = __ballot(coupling(t) > target);
+        if (over != ~0ull) hi = ldexp(1.0, e0 + __ffsll((unsigned long long)~over) - 1);
     }
+    if (hi == 0.0) hi = ldexp(1.0, 2047);
     double a = log(1e-16), b = log(hi);
-    for (int it = 0; it < 64; it++) {
-        double mid = 0.5 * (a + b);
-        if (coupling_tau(d2, mu, n, exp(mid)) > target)
-            a = mid;
-        else
-            b = mid;
+    for (int round = 0; round < 11; round++) {
+        const double step = (b - a) / 65.0;
+        const double x = a + step * (lane + 1);
+        const int cnt = __popcll(__ballot(coupling(exp(x)) > target));
+        const double na = cnt == 0 ? a : a + step * cnt;
+        const double nb = cnt == 64 ? b : a + step * (cnt + 1);
+        a = na;
+        b = nb;
     }
     double tt = (chi - chi_t) / (chi_f - chi_t);
     double sm = 1.0;
@@ -129,5 +147,355 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+
+// ---------------------------------------------------------------------------
+// double-double arithmetic (unevaluated sums hi + lo, |lo| <= ulp(hi)/2), from
+// the error-free transformations TwoSum (Knuth), FastTwoSum (Dekker) and the
+// FMA form of TwoProduct; written with contraction off so that the compiler
+// keeps every rounding step.
+// ---------------------------------------------------------------------------
+struct dd {
+    double hi, lo;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+#pragma clang fp contract(off)
+    const double s = a + b;
+    const double bb = s - a;
+    const double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+    const double s = a + b;
+    return {s, b - (s - a)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+#pragma clang fp contract(off)
+    const dd s = two_sum(a.hi, b.hi);
+    return fast_two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+__device__ __forceinline__ dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ dd dd_mul(dd a, dd b) {
+#pragma clang fp contract(off)
+    const double p = a.hi * b.hi;
+    double e = fma(a.hi, b.hi, -p);
+    e = fma(a.hi, b.lo, e);
+    e = fma(a.lo, b.hi, e);
+    return fast_two_sum(p, e);
+}
+__device__ __forceinline__ dd dd_mul_d(dd a, double b) {
+#pragma clang fp contract(off)
+    const double p = a.hi * b;
+    double e = fma(a.hi, b, -p);
+    e = fma(a.lo, b, e);
+    return fast_two_sum(p, e);
+}
+// 1/b: the double reciprocal and one Newton correction
+__device__ __forceinline__ dd dd_recip(dd b) {
+#pragma clang fp contract(off)
+    const double q = 1.0 / b.hi;
+    const dd r = dd_add({1.0, 0.0}, dd_neg(dd_mul_d(b, q)));
+    return fast_two_sum(q, r.hi * q);
+}
+__device__ __forceinline__ dd dd_sqrt(dd a) {
+#pragma clang fp contract(off)
+    const double x = sqrt(a.hi);
+    const double p = x * x;
+    const dd xx = {p, fma(x, x, -p)};
+    const dd r = dd_add(a, dd_neg(xx));
+    return fast_two_sum(x, r.hi / (2.0 * x));
+}
+// acc += a b for doubles a, b (the product exactly, the sum to ~1e-32)
+__device__ __forceinline__ void dd_acc(dd& acc, double a, double b) {
+#pragma clang fp contract(off)
+    const double p = a * b;
+    const double e = fma(a, b, -p);
+    const dd s = two_sum(acc.hi, p);
+    acc.hi = s.hi;
+    acc.lo = acc.lo + (s.lo + e);
+}
+__device__ __forceinline__ dd readlane_dd(dd v, int l);
+
+// Value of lane l (wave-uniform l) of every lane's v.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ dd readlane_dd(dd v, int l) {
+    return {readlane_f64(v.hi, l), readlane_f64(v.lo, l)};
+}
+
+// Local solve of one grid node by one wave, from its assembled entries
+// (eq. (15)-(23)).  Gs (LDS) holds the Gram matrix of the m weighted
+// monomial columns, packed upper [a m - a(a-1)/2 + (b - a)], then the right-hand
+// sides [m(m+1)/2 + a F + f]; isc (LDS, m doubles) is scratch.
+//  1. normalise: unit weight sum (divide by W = G_00) and unit-norm columns;
+//  2. reorder to [V | v1] and append the F right-hand-side rows; lane r holds
+//     row r.  The Cholesky factor of the Gram matrix of [V | v1] is
+//     [[L, 0], [d^T, rho]] with L L^T = C, d = L^{-1} b and rho^2 = 1 - |d|^2
+//     = 1/chi (eq. (19), (20)); eliminated alongside, the right-hand-side rows
+//     become z = L^{-1} r[1:] and omega = (r_1 - d.z)/rho.  Columns are
+//     broadcast with readlane: no LDS traffic, no barriers;
+//  3. with tau from eq. (23),
+//       c_1 = (rho omega + sum_j d_j z_j t_j) / (rho^2 + sum_j d_j^2 t_j),
+//     t_j = tau mu_j/(1 + tau mu_j): the Schur complement of the first
+//     unknown of eq. (22), without the cancellation of 1 - sum d^2/(1 + tau mu).
+// Fewer than m neighbours or a zero column: the tau -> infinity limit (the
+// weighted mean).  A pivot of C below kPivResolve, chi < 1 by rounding or a Schur
+// denominator below kDenResolve: the raw entries go to entries_out and the node to
+// the re-solve list.
+template <int m>
+__device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int F, int j,
+                                   const SolveArgs& A, double* entries_out) {
+    constexpr int NC = m - 1;
+    constexpr int EG = m * (m + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t MQ = A.MQ;
+    const uint8_t rst = A.rstatus[j];
+    const double W = Gs[0];
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    if (count == 0 || !(W > 0.0)) {
+        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = __builtin_nan("");
+        if (lane == 0 && A.write_diag) {
+            A.chi[j] = __builtin_nan("");
+            A.tau[j] = __builtin_nan("");
+            A.status[j] = rst | HAMLS_ST_EMPTY;
+        }
+        return;
+    }
+    bool degen = count < m;
+    {
+        double v = 1.0;
+        if (lane < m) v = sqrt(Gs[gidx(lane, lane)] / W);
+        if (__ballot(lane < m && !(v > 0.0))) degen = true;
+        if (lane < m) isc[lane] = 1.0 / v;
+    }
+    if (degen) {
+        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = Gs[EG + lane] / W;
+        if (lane == 0 && A.write_diag) {
+            A.chi[j] = __builtin_inf();
+            A.tau[j] = __builtin_inf();
+            A.status[j] = rst | HAMLS_ST_UNDERDETERMINED;
+        }
+        return;
+    }
+    __syncthreads();
+    // row `lane` of the normalised, reordered system; p(0) = NC, p(a) = a - 1
+    double a[NC + 1];
+    {
+        const int r = lane;
+        const int ar = r >= NC ? 0 : r + 1;
+        const double sr = r <= NC ? isc[ar] : 0.0;
+#pragma unroll
+        for (int c = 0; c <= NC; c++) {
+            const int bc = c == NC ? 0 : c + 1;
+            double v = 0.0;
+            if (r <= NC) {
+                const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
+                v = Gs[gidx(lo, hi)] / W * (sr * isc[bc]);
+            } else if (r < NC + 1 + F) {
+                v = Gs[EG + bc * F + (r - NC - 1)] / W * isc[bc];
+            }
+            a[c] = v;
+        }
+    }
+    bool ill = false;
+    double minpiv = 1.0, s_last = 1.0;
+#pragma unroll
+    for (int k = 0; k <= NC; k++) {
+        const double s = readlane_f64(a[k], k);
+        if (k < NC) {
+            minpiv = fmin(minpiv, s);
+            if (!(s > 1e-300)) {
+                ill = true;
+                break;
+            }
+        } else {
+            s_last = s;
+            if (!(s > 0.0)) {
+                ill = true;
+                break;
+            }
+        }
+        const double lkk = sqrt(s);
+        const double il = 1.0 / lkk;
+        a[k] = lane == k ? lkk : a[k] * il;
+#pragma unroll
+        for (int c = k + 1; c <= NC; c++) a[c] = fma(-a[k], readlane_f64(a[k], c), a[c]);
+    }
+    double dv[NC > 0 ? NC : 1], d2[NC > 0 ? NC : 1], tf[NC > 0 ? NC : 1];
+    double chi = 1.0, tau = 0.0, den = 1.0;
+    if (!ill) {
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            dv[k] = readlane_f64(a[k], NC);
+            d2[k] = dv[k] * dv[k];
+        }
+        chi = 1.0 / s_last;
+        if (minpiv < kPivResolve) ill = true;
+    }
+    if (!ill) {
+        tau = NC > 0 ? choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f) : 0.0;
+        den = s_last;
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const double tm = tau * A.mu[k];
+            tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
+            den += d2[k] * tf[k];
+        }
+        if (!(den > kDenResolve)) ill = true;
+    }
+    if (ill) {
+        for (int e = lane; e < EG + m * F; e += 64) entries_out[(int64_t)e * MQ + j] = Gs[e];
+        if (lane == 0) {
+            const int slot = atomicAdd(A.rs_count, 1);
+            A.rs_list[slot] = j;
+        }
+        return;
+    }
+    const double rho = readlane_f64(a[NC], NC);
+    if (lane > NC && lane < NC + 1 + F) {
+        double num = rho * a[NC];
+#pragma unroll
+        for (int k = 0; k < NC; k++) num += dv[k] * a[k] * tf[k];
+        A.out[(int64_t)(A.f0 + lane - NC - 1) * MQ + j] = num / den;
+    }
+    if (lane == 0 && A.write_diag) {
+        A.chi[j] = chi;
+        A.tau[j] = tau;
+        A.status[j] = rst | (tau > 0.0 ? HAMLS_ST_REGULARIZED : 0);
+    }
+}
+
+// Re-solve of a node flagged by mls_solve_epilogue, from its Gram matrix and
+// right-hand sides accumulated in double-double precision (Gh + Gl, same
+// packing as the FP64 entries).  The same steps in double-double: the
+// normalised system (scales rounded to doubles: d, z, rho and omega do not
+// depend on column scaling), the Cholesky factor of [V | v1 | y] in
+// registers, then d, 1 - |d|^2 = rho^2 (the last pivot, free of cancellation
+// at this precision), z and omega rounded to doubles for tau and c_1.  A
+// pivot of the unit-diagonal C at or below kRankTol^2 (|R_jj| of the
+// unit-column V at or below kRankTol) or fewer than m neighbours: the weighted
+// mean (tau -> infinity).
+template <int m>
+__device__ void mls_dd_epilogue(const double* Gh, const double* Gl, double* isc, int count, int F,
+                                int j, const SolveArgs& A) {
+    constexpr int NC = m - 1;
+    constexpr int EG = m * (m + 1) / 2;
+    const int lane = threadIdx.x & 63;
+    const int64_t MQ = A.MQ;
+    const uint8_t rst = A.rstatus[j] | HAMLS_ST_ILLCOND;
+    const double W = Gh[0] + Gl[0];
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    if (count == 0 || !(W > 0.0)) {
+        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = __builtin_nan("");
+        if (lane == 0 && A.write_diag) {
+            A.chi[j] = __builtin_nan("");
+            A.tau[j] = __builtin_nan("");
+            A.status[j] = rst | HAMLS_ST_EMPTY;
+        }
+        return;
+    }
+    // column factors f_a = 1/sqrt(G_aa), applied entry by entry as two exact
+    // double-double scalings, so that the normalised matrix is exactly the
+    // congruence diag(f) G diag(f) of the accumulated one
+    bool degen = count < m;
+    {
+        double v = 1.0;
+        if (lane < m) v = sqrt(Gh[gidx(lane, lane)] + Gl[gidx(lane, lane)]);
+        if (__ballot(lane < m && !(v > 0.0))) degen = true;
+        if (lane < m) isc[lane] = 1.0 / v;
+    }
+    const double ws = 1.0 / sqrt(W);
+    __syncthreads();
+    dd a[NC + 1];
+    bool ill = degen;
+    double s_last = 1.0;
+    if (!ill) {
+        const int r = lane;
+        const int ar = r >= NC ? 0 : r + 1;
+        const double sr = r <= NC ? isc[ar] : ws;
+#pragma unroll
+        for (int c = 0; c <= NC; c++) {
+            const int bc = c == NC ? 0 : c + 1;
+            dd v = {0.0, 0.0};
+            if (r <= NC) {
+                const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
+                const int e = gidx(lo, hi);
+                v = dd_mul_d(dd_mul_d({Gh[e], Gl[e]}, sr), isc[bc]);
+            } else if (r < NC + 1 + F) {
+                // right-hand sides of the unit-sum weights: the data scaled by 1/sqrt(W)
+                const int e = EG + bc * F + (r - NC - 1);
+                v = dd_mul_d(dd_mul_d({Gh[e], Gl[e]}, sr), isc[bc]);
+            }
+            a[c] = v;
+        }
+        const double rank2 = kRankTol * kRankTol;
+#pragma unroll
+        for (int k = 0; k <= NC; k++) {
+            const dd s = readlane_dd(a[k], k);
+            if (k < NC) {
+                if (!(s.hi > rank2)) {
+                    ill = true;
+                    break;
+                }
+            } else {
+                s_last = s.hi;
+                if (!(s.hi > 0.0)) {
+                    s_last = 0.0;
+                    break;
+                }
+            }
+            const dd lkk = dd_sqrt(s);
+            const dd il = dd_recip(lkk);
+            a[k] = lane == k ? lkk : dd_mul(a[k], il);
+#pragma unroll
+            for (int c = k + 1; c <= NC; c++)
+                a[c] = dd_add(a[c], dd_neg(dd_mul(a[k], readlane_dd(a[k], c))));
+        }
+    }
+    if (ill) {
+        // rank deficient: the tau -> infinity limit
+        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = (Gh[EG + lane] + Gl[EG + lane]) / W;
+        if (lane == 0 && A.write_diag) {
+            A.chi[j] = __builtin_inf();
+            A.tau[j] = __builtin_inf();
+            A.status[j] = rst | HAMLS_ST_UNDERDETERMINED;
+        }
+        return;
+    }
+    double dv[NC > 0 ? NC : 1], d2[NC > 0 ? NC : 1], tf[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+        dv[k] = readlane_f64(a[k].hi, NC);
+        d2[k] = dv[k] * dv[k];
+    }
+    const double chi = 1.0 / s_last;
+    const double tau = NC > 0 ? choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f) : 0.0;
+    double den = s_last;
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+        const double tm = tau * A.mu[k];
+        tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
+        den += d2[k] * tf[k];
+    }
+    const double rho = sqrt(s_last);
+    if (lane > NC && lane < NC + 1 + F) {
+        // rho omega = r_1 - d.z (omega = 0 where rho = 0)
+        double num = s_last > 0.0 ? rho * a[NC].hi : 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; k++) num += dv[k] * a[k].hi * tf[k];
+        A.out[(int64_t)(A.f0 + lane - NC - 1) * MQ + j] = num / den;
+    }
+    if (lane == 0 && A.write_diag) {
+        A.chi[j] = chi;
+        A.tau[j] = tau;
+        A.status[j] = rst | (tau > 0.0 ? HAMLS_ST_REGULARIZED : 0);
+    }
+}
 
 }  // namespace hamls

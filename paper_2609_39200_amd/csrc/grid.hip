@@ -20,7 +20,7 @@ namespace hamls {
 struct GridGeom {
     int dom;             // HAMLS_SO3 or HAMLS_T3
     int nc;              // cells per axis
-    double lo, h;        // cell i of an axis covers [lo + i h, lo + (i+1) h)
+    double lo, h, ih;    // cell i of an axis covers [lo + i h, lo + (i+1) h); ih = 1/h
     const double* grid;  // M_Q x D (quaternions for SO3, points for T3)
     const double* X;     // sorted records, SoA D x cap
     const double* nu;    // sorted node weights or null
@@ -35,6 +35,8 @@ GridGeom make_grid_geom(const Plan& P) {
     g.nc = P.gbins.nc;
     g.lo = P.gbins.lo;
     g.h = P.gbins.h;
+    // exact reciprocal of the cell width: nc per unit length (T3), nc/2 (SO3)
+    g.ih = P.dom == HAMLS_T3 ? (double)P.gbins.nc : 0.5 * P.gbins.nc;
     g.grid = P.d_grid;
     g.X = P.d_x;
     g.nu = P.has_nu ? P.d_nu : nullptr;
@@ -98,8 +100,8 @@ __device__ __forceinline__ BoxGeo box_geo(const GridGeom& g, const double* q, do
     BoxGeo B;
     B.rows = 1;
     for (int d = 0; d < D; d++) {
-        int a = (int)floor((q[d] - rho - margin - g.lo) / g.h);
-        int b = (int)floor((q[d] + rho + margin - g.lo) / g.h);
+        int a = (int)floor((q[d] - rho - margin - g.lo) * g.ih);
+        int b = (int)floor((q[d] + rho + margin - g.lo) * g.ih);
         if (D == 3) {
             if (b - a + 1 >= g.nc) {
                 a = 0;
@@ -213,7 +215,7 @@ __device__ __forceinline__ void grid_scan(const GridGeom& g, const double* q, do
 // One key per record: T3 one record per node; SO3 two (q and -q, the second
 // encoded as index M + i).
 __global__ void k_grid_keys(const double* __restrict__ nodes, int64_t M, int dom, int D, int nc,
-                            double lo, double h, uint32_t* __restrict__ keys,
+                            double lo, double ih, uint32_t* __restrict__ keys,
                             int32_t* __restrict__ idx) {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t nrec = dom == HAMLS_SO3 ? 2 * M : M;
@@ -229,7 +231,7 @@ __global__ void k_grid_keys(const double* __restrict__ nodes, int64_t M, int dom
             c = (int)(y * nc);
             c = c >= nc ? nc - 1 : (c < 0 ? 0 : c);
         } else {
-            c = (int)floor((x - lo) / h);
+            c = (int)floor((x - lo) * ih);
             c = c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
         }
         key = key * (uint32_t)nc + (uint32_t)c;
@@ -256,7 +258,7 @@ hamls_status launch_grid_keys(const Plan& P, const double* nodes, int64_t M, hip
     int64_t nrec = P.dom == HAMLS_SO3 ? 2 * M : M;
     int bs = 256;
     hipLaunchKernelGGL(k_grid_keys, dim3((unsigned)((nrec + bs - 1) / bs)), dim3(bs), 0, s, nodes, M,
-                       P.dom, P.gbins.D, P.gbins.nc, P.gbins.lo, P.gbins.h, P.d_key[0], P.d_idx[0]);
+                       P.dom, P.gbins.D, P.gbins.nc, P.gbins.lo, 0.5 * P.gbins.nc, P.d_key[0], P.d_idx[0]);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -583,51 +585,39 @@ __device__ __forceinline__ void monomials3(const double* u, double s, double* ro
             for (int b = l - a; b >= 0; b--) row[c++] = s * p0[a] * p1[b] * p2[l - a - b];
 }
 
-// Fused assembly and local solve, one grid node per block (one wave).
-//  1. scan the cover; member rows (sqrt(w) g, sqrt(w) y) are staged in LDS 64
-//     at a time and each lane owns a few Gram / right-hand-side entries;
-//  2. the entries go to LDS, normalised (unit weight sum, unit-norm columns)
-//     and reordered to [V | v1 | y]: the Cholesky factor of the Gram matrix of
-//     [V | v1] is [[L, 0], [d^T, rho]] with L L^T = C, d = L^{-1} b and
-//     rho^2 = 1 - |d|^2 = 1/chi (eq. (19), (20)); the right-hand-side rows,
-//     eliminated alongside, give z = L^{-1} r[1:] and omega = (r_1 - d.z)/rho;
-//  3. with tau from eq. (23),
-//       c_1 = (rho omega + sum_j d_j z_j t_j) / (rho^2 + sum_j d_j^2 t_j),
-//     t_j = tau mu_j / (1 + tau mu_j), the Schur complement of the first
-//     unknown of eq. (22).
-// Centres whose normal-matrix solve is not trustworthy (pivot, chi < 1 or a
-// small Schur denominator) store their raw entries and go to the QR list.
-template <int D, int K, int FM>
-__global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __restrict__ vals, int F,
+// Fused assembly and local solve, one grid node per block (one wave): the
+// cover is scanned 64*U records per step; member rows (sqrt(w) g, sqrt(w) y)
+// are staged in LDS 64 at a time and each lane owns a few Gram /
+// right-hand-side entries (every lane reads valid row positions, so the
+// accumulation has no branches); the entries then go to LDS for the solve
+// epilogue (normalisation, Cholesky in registers, tau, c_1).
+template <int D, int K, int FM, bool DD>
+__device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const GridGeom& g, const double* __restrict__ vals, int F,
                                                 int wendland, const double* __restrict__ thr,
-                                                const double* __restrict__ delta, SolveArgs A,
+                                                const double* __restrict__ delta, const SolveArgs& A,
                                                 int32_t* __restrict__ nj,
                                                 double* __restrict__ entries_out) {
     constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
-    constexpr int NC = m - 1;
     constexpr int EG = m * (m + 1) / 2;
     constexpr int ROW = m + FM + 1;
     constexpr int KE = (EG + m * FM + 63) / 64;
     constexpr int U = FM == 1 ? 2 : 1;
-    constexpr int LDM = NC + 2;                 // leading dimension of the factor
-    constexpr int RMAX = NC + 1 + FM;           // rows of [V | v1] and the fields
-    static_assert(EG + m * FM + RMAX * LDM + m <= 64 * ROW, "LDS reuse");
-    __shared__ double rows[64 * ROW];
-    __shared__ int sh[kScanLds];
-    const int j = xcd_block(blockIdx.x, gridDim.x);
+    static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
     const int lane = threadIdx.x;
-    const int64_t MQ = A.MQ;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
     for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
     const double c = thr[j], dl = delta[j];
     const int E = EG + m * F;
     int ca[KE], cb[KE];
     double acc[KE];
+    dd accd[KE];
 #pragma unroll
     for (int k = 0; k < KE; k++) {
         int e = lane + 64 * k;
         acc[k] = 0.0;
-        ca[k] = -1;
+        accd[k] = {0.0, 0.0};
+        ca[k] = 0;
         cb[k] = 0;
         if (e < EG) {
             int a = 0, rem = e;
@@ -645,9 +635,11 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
     }
     int count = 0;
     grid_scan<D, U>(g, q, grid_rho<D>(g, dl), sh, [&](const bool* valid, const int* idx) {
-        double kv[U];
+        double kv[U], y1[U];
 #pragma unroll
         for (int u = 0; u < U; u++) kv[u] = valid[u] ? grid_key<D>(g, idx[u], q) : -1e300;
+#pragma unroll
+        for (int u = 0; u < U; u++) y1[u] = (FM == 1 && kv[u] > c) ? vals[idx[u]] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const bool in = kv[u] > c;
@@ -661,151 +653,78 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
                 const double sw = sqrt(w);
                 double* row = rows + rank_below(mk) * ROW;
                 monomials3<K>(uu, sw, row);
-                for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
+                if (FM == 1)
+                    row[m] = sw * y1[u];
+                else
+                    for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
             }
             __syncthreads();
+#pragma unroll 2
             for (int r = 0; r < nin; r++) {
                 const double* row = rows + r * ROW;
 #pragma unroll
-                for (int k = 0; k < KE; k++)
-                    if (ca[k] >= 0) acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                for (int k = 0; k < KE; k++) {
+                    if (DD)
+                        dd_acc(accd[k], row[ca[k]], row[cb[k]]);
+                    else
+                        acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                }
             }
             __syncthreads();
             count += nin;
         }
     });
-    // entries to LDS: Gram packed upper [gidx(a, b)], then right-hand sides [a F + f]
+    if (DD) {
+        double* Gh = rows;
+        double* Gl = rows + EG + m * FM;
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            int e = lane + 64 * k;
+            if (e < E) {
+                const dd v = fast_two_sum(accd[k].hi, accd[k].lo);
+                Gh[e] = v.hi;
+                Gl[e] = v.lo;
+            }
+        }
+        __syncthreads();
+        mls_dd_epilogue<m>(Gh, Gl, rows + 2 * (EG + m * FM), count, F, j, A);
+        return;
+    }
+    if (lane == 0) nj[j] = count;
     double* Gs = rows;
-    double* Mx = rows + EG + m * FM;
 #pragma unroll
     for (int k = 0; k < KE; k++) {
         int e = lane + 64 * k;
         if (e < E) Gs[e] = acc[k];
     }
     __syncthreads();
-    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
-    const uint8_t rst = A.rstatus[j];
-    const double W = Gs[0];
-    if (lane == 0) nj[j] = count;
-    if (count == 0 || !(W > 0.0)) {
-        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = __builtin_nan("");
-        if (lane == 0 && A.write_diag) {
-            A.chi[j] = __builtin_nan("");
-            A.tau[j] = __builtin_nan("");
-            A.status[j] = rst | HAMLS_ST_EMPTY;
+    mls_solve_epilogue<m>(Gs, rows + EG + m * FM, count, F, j, A, entries_out);
+}
+
+
+template <int D, int K, int FM, bool DD>
+__global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __restrict__ vals, int F,
+                                                int wendland, const double* __restrict__ thr,
+                                                const double* __restrict__ delta, SolveArgs A,
+                                                int32_t* __restrict__ nj,
+                                                double* __restrict__ entries_out) {
+    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
+    constexpr int EG = m * (m + 1) / 2;
+    constexpr int ROW = m + FM + 1;
+    constexpr int KE = (EG + m * FM + 63) / 64;
+    constexpr int U = FM == 1 ? 2 : 1;
+    static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
+    __shared__ double rows[64 * ROW];
+    __shared__ int sh[kScanLds];
+    if (DD) {
+        // the re-solve list: a grid-stride loop over the listed nodes
+        const int n = *A.rs_count;
+        for (int li = blockIdx.x; li < n; li += gridDim.x) {
+            grid_node<D, K, FM, DD>(A.rs_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+            __syncthreads();
         }
-        return;
-    }
-    // inverse column scales 1/sqrt(g_a^T W g_a / W) (unit discrete norm)
-    double* isc = Mx + RMAX * LDM;
-    bool degen = count < m;
-    {
-        double v = 1.0;
-        if (lane < m) v = sqrt(Gs[gidx(lane, lane)] / W);
-        if (__ballot(lane < m && !(v > 0.0))) degen = true;
-        if (lane < m) isc[lane] = 1.0 / v;
-    }
-    if (degen) {
-        // the tau -> infinity limit: the weighted mean
-        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = Gs[EG + lane] / W;
-        if (lane == 0 && A.write_diag) {
-            A.chi[j] = __builtin_inf();
-            A.tau[j] = __builtin_inf();
-            A.status[j] = rst | HAMLS_ST_UNDERDETERMINED;
-        }
-        return;
-    }
-    __syncthreads();
-    // normalised, reordered system: position p(0) = NC (v1), p(a) = a - 1
-    const int R = NC + 1 + F;
-    for (int e = lane; e < R * (NC + 1); e += 64) {
-        const int r = e / (NC + 1), cc = e - r * (NC + 1);
-        double v = 0.0;
-        if (r <= NC) {
-            if (cc <= r) {
-                const int a = r == NC ? 0 : r + 1, b = cc == NC ? 0 : cc + 1;
-                const int lo = a < b ? a : b, hi = a < b ? b : a;
-                v = Gs[gidx(lo, hi)] / W * (isc[a] * isc[b]);
-            }
-        } else {
-            const int f = r - NC - 1, a = cc == NC ? 0 : cc + 1;
-            v = Gs[EG + a * F + f] / W * isc[a];
-        }
-        Mx[r * LDM + cc] = v;
-    }
-    __syncthreads();
-    bool ill = false;
-    double minpiv = 1.0, s_last = 1.0;
-    for (int k = 0; k <= NC; k++) {
-        const double s = Mx[k * LDM + k];
-        if (k < NC) {
-            minpiv = fmin(minpiv, s);
-            if (!(s > 1e-300)) {
-                ill = true;
-                break;
-            }
-        } else {
-            s_last = s;
-            if (!(s > 0.0)) {
-                ill = true;
-                break;
-            }
-        }
-        const double lkk = sqrt(s);
-        const double il = 1.0 / lkk;
-        __syncthreads();
-        if (lane == 0) Mx[k * LDM + k] = lkk;
-        for (int r = k + 1 + lane; r < R; r += 64) Mx[r * LDM + k] *= il;
-        __syncthreads();
-        const int nr = R - k - 1, ncl = NC - k;
-        for (int e = lane; e < nr * ncl; e += 64) {
-            const int r = k + 1 + e / ncl, cc = k + 1 + e % ncl;
-            if (cc <= r) Mx[r * LDM + cc] -= Mx[r * LDM + k] * Mx[cc * LDM + k];
-        }
-        __syncthreads();
-    }
-    double dv[NC > 0 ? NC : 1], d2[NC > 0 ? NC : 1], tf[NC > 0 ? NC : 1];
-    double chi = 1.0, tau = 0.0, den = 1.0;
-    if (!ill) {
-#pragma unroll
-        for (int k = 0; k < NC; k++) {
-            dv[k] = Mx[NC * LDM + k];
-            d2[k] = dv[k] * dv[k];
-        }
-        chi = 1.0 / s_last;
-        if (minpiv < kPivQR) ill = true;
-    }
-    if (!ill) {
-        tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
-        den = s_last;
-#pragma unroll
-        for (int k = 0; k < NC; k++) {
-            const double tm = tau * A.mu[k];
-            tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
-            den += d2[k] * tf[k];
-        }
-        if (!(den > kDenQR)) ill = true;
-    }
-    if (ill) {
-        for (int e = lane; e < E; e += 64) entries_out[(int64_t)e * MQ + j] = Gs[e];
-        if (lane == 0) {
-            const int slot = atomicAdd(A.qr_count, 1);
-            A.qr_list[slot] = j;
-        }
-        return;
-    }
-    if (lane < F) {
-        const double rho = Mx[NC * LDM + NC];
-        const double* zr = Mx + (NC + 1 + lane) * LDM;
-        double num = rho * zr[NC];
-#pragma unroll
-        for (int k = 0; k < NC; k++) num += dv[k] * zr[k] * tf[k];
-        A.out[(int64_t)(A.f0 + lane) * MQ + j] = num / den;
-    }
-    if (lane == 0 && A.write_diag) {
-        A.chi[j] = chi;
-        A.tau[j] = tau;
-        A.status[j] = rst | (tau > 0.0 ? HAMLS_ST_REGULARIZED : 0);
+    } else {
+        grid_node<D, K, FM, DD>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
     }
 }
 
@@ -814,12 +733,12 @@ hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, 
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
-#define HAMLS_GMLS(DD, KK)                                                                       \
+#define HAMLS_GMLS(DDIM, KK)                                                                       \
     if (F == 1)                                                                                  \
-        hipLaunchKernelGGL((k_grid_mls<DD, KK, 1>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
+        hipLaunchKernelGGL((k_grid_mls<DDIM, KK, 1, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
                            P.d_delta, A, P.d_nj, P.d_entries);                                   \
     else                                                                                         \
-        hipLaunchKernelGGL((k_grid_mls<DD, KK, kMaxFieldsPerPass>), grid, block, 0, s, g, P.d_vals, \
+        hipLaunchKernelGGL((k_grid_mls<DDIM, KK, kMaxFieldsPerPass, false>), grid, block, 0, s, g, P.d_vals, \
                            F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
 #define HAMLS_GMLS_D(KK)     \
     if (P.dom == HAMLS_SO3) { \
@@ -840,151 +759,35 @@ hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, 
     return HAMLS_OK;
 }
 
-// ---------------------------------------------------------------------------
-// QR path (see k_s2_qr): streaming Householder on the rows (V | v1 | y_w)
-// ---------------------------------------------------------------------------
-
-template <int D, int K>
-__global__ __launch_bounds__(64) void k_grid_qr(GridGeom g, const double* __restrict__ vals, int wendland,
-                                               const double* __restrict__ thr,
-                                               const double* __restrict__ delta, SolveArgs A) {
-    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
-    constexpr int NC = m - 1;
-    constexpr int LD = m + 1 + kMaxFieldsPerPass;
-    __shared__ double T[(m + 64) * LD];
-    __shared__ int sh[kScanLds];
-    const int lane = threadIdx.x;
-    const int F = A.F;
-    const int cols = m + F;
-    const int64_t MQ = A.MQ;
-    const int total = *A.qr_count;
-    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
-    for (int li = blockIdx.x; li < total; li += gridDim.x) {
-        const int j = A.qr_list[li];
-        double q[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
-        const double c = thr[j], dl = delta[j];
-        const double W = A.entries[j];
-        double isc[m];
-#pragma unroll
-        for (int a = 0; a < m; a++) isc[a] = 1.0 / sqrt(A.entries[(int64_t)gidx(a, a) * MQ + j] / W);
-        for (int e = lane; e < m * LD; e += 64) T[e] = 0.0;
-        __syncthreads();
-        grid_scan<D, 1>(g, q, grid_rho<D>(g, dl), sh, [&](const bool* valid_, const int* idx_) {
-            const int i = idx_[0];
-            const double kv = valid_[0] ? grid_key<D>(g, i, q) : -1e300;
-            const bool in = kv > c;
-            const uint64_t mk = __ballot(in);
-            const int nin = __popcll(mk);
-            if (nin == 0) return;
-            if (in) {
-                double uu[3], w;
-                grid_local<D>(g, i, q, kv, dl, wendland, uu, w);
-                const double b = sqrt(w / W);
-                double mono[m];
-                monomials3<K>(uu, 1.0, mono);
-                double* row = T + (m + rank_below(mk)) * LD;
-#pragma unroll
-                for (int a = 1; a < m; a++) row[a - 1] = b * mono[a] * isc[a];
-                row[NC] = b;
-                for (int f = 0; f < F; f++) row[m + f] = b * vals[(int64_t)f * g.cap + i];
-            }
-            __syncthreads();
-            const int R = m + nin;
-            for (int k = 0; k < m; k++) {
-                double part = 0.0;
-                for (int r = k + lane; r < R; r += 64) {
-                    double v = T[r * LD + k];
-                    part += v * v;
-                }
-                double nrm2 = wave_sum(part);
-                double x0k = T[k * LD + k];
-                __syncthreads();
-                // columns have unit discrete norm; a residual below 1e-100 is
-                // rounding noise, nothing to eliminate
-                if (!(nrm2 > 1e-200)) continue;
-                double nrm = sqrt(nrm2);
-                double alpha = x0k > 0.0 ? -nrm : nrm;
-                double v0 = x0k - alpha;
-                double vv = nrm2 - x0k * x0k + v0 * v0;
-                for (int jc = k + 1 + lane; jc < cols; jc += 64) {
-                    double sdot = v0 * T[k * LD + jc];
-                    for (int r = k + 1; r < R; r++) sdot += T[r * LD + k] * T[r * LD + jc];
-                    sdot *= 2.0 / vv;
-                    T[k * LD + jc] -= sdot * v0;
-                    for (int r = k + 1; r < R; r++) T[r * LD + jc] -= sdot * T[r * LD + k];
-                }
-                __syncthreads();
-                if (lane == 0) T[k * LD + k] = alpha;
-                for (int r = k + 1 + lane; r < R; r += 64) T[r * LD + k] = 0.0;
-                __syncthreads();
-            }
-        });
-        if (lane == 0) {
-            uint8_t st = A.rstatus[j] | HAMLS_ST_ILLCOND;
-            double rmin = 1e300;
-            for (int k = 0; k < NC; k++) rmin = fmin(rmin, fabs(T[k * LD + k]));
-            double chi, tau;
-            if (!(rmin > kRankTol)) {
-                for (int f = 0; f < F; f++)
-                    A.out[(int64_t)(A.f0 + f) * MQ + j] = A.entries[(int64_t)(m * (m + 1) / 2 + f) * MQ + j] / W;
-                chi = __builtin_inf();
-                tau = __builtin_inf();
-                st |= HAMLS_ST_UNDERDETERMINED;
-            } else {
-                double dv[NC], d2[NC], sg[NC];
-#pragma unroll
-                for (int k = 0; k < NC; k++) {
-                    sg[k] = T[k * LD + k] < 0.0 ? -1.0 : 1.0;
-                    dv[k] = sg[k] * T[k * LD + NC];
-                    d2[k] = dv[k] * dv[k];
-                }
-                const double rho = T[NC * LD + NC];
-                chi = 1.0 / (rho * rho);
-                tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
-                double den = rho * rho;
-                double fac[NC];
-#pragma unroll
-                for (int k = 0; k < NC; k++) {
-                    double tm = tau * A.mu[k];
-                    fac[k] = tm > 0.0 ? dv[k] * (tm / (1.0 + tm)) : 0.0;
-                    den += fac[k] * dv[k];
-                }
-                for (int f = 0; f < F; f++) {
-                    double num = rho * T[NC * LD + m + f];
-                    for (int k = 0; k < NC; k++) num += fac[k] * sg[k] * T[k * LD + m + f];
-                    A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
-                }
-                if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
-            }
-            if (A.write_diag) {
-                A.chi[j] = chi;
-                A.tau[j] = tau;
-                A.status[j] = st;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-hamls_status launch_grid_qr(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+// Re-solve of the nodes flagged by the FP64 epilogue: the same assembly in
+// double-double precision, blocks striding over the list.
+hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
     if (P.m <= 1) return HAMLS_OK;
     GridGeom g = make_grid_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    dim3 qg((unsigned)(P.MQ < 2048 ? P.MQ : 2048)), qb(64);
+    dim3 grid((unsigned)(P.MQ < kResolveBlocks ? P.MQ : kResolveBlocks)), block(64);
     int wl = P.prm.wendland;
-    switch (P.K) {
-#define HAMLS_GQR(KK)                                                                                \
-    {                                                                                                \
-        auto kq = P.dom == HAMLS_SO3 ? k_grid_qr<4, KK> : k_grid_qr<3, KK>;                        \
-        hipLaunchKernelGGL(kq, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A);               \
+#define HAMLS_GDD(DDIM, KK)                                                                          \
+    if (F == 1)                                                                                      \
+        hipLaunchKernelGGL((k_grid_mls<DDIM, KK, 1, true>), grid, block, 0, s, g, P.d_vals, F, wl,      \
+                           P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);                              \
+    else                                                                                             \
+        hipLaunchKernelGGL((k_grid_mls<DDIM, KK, kMaxFieldsPerPass, true>), grid, block, 0, s, g,       \
+                           P.d_vals, F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
+#define HAMLS_GDD_D(KK)       \
+    if (P.dom == HAMLS_SO3) { \
+        HAMLS_GDD(4, KK)      \
+    } else {                  \
+        HAMLS_GDD(3, KK)      \
     }
-        case 1: HAMLS_GQR(1) break;
-        case 2: HAMLS_GQR(2) break;
-        case 3: HAMLS_GQR(3) break;
-#undef HAMLS_GQR
+    switch (P.K) {
+        case 1: HAMLS_GDD_D(1) break;
+        case 2: HAMLS_GDD_D(2) break;
+        case 3: HAMLS_GDD_D(3) break;
         default: break;
     }
+#undef HAMLS_GDD_D
+#undef HAMLS_GDD
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

@@ -249,29 +249,48 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_count(const uint32_t* __re
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// In-place exclusive scan of a[0..len) by one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_exclusive_scan(uint32_t* __restrict__ a, int64_t len) {
-    __shared__ uint32_t part[1024];
-    int t = threadIdx.x;
-    int64_t chunk = (len + 1023) / 1024;
-    int64_t lo = t * chunk;
-    int64_t hi = lo + chunk < len ? lo + chunk : len;
-    uint32_t s = 0;
-    for (int64_t i = lo; i < hi; i++) s += a[i];
-    part[t] = s;
+// Exclusive scan of the digit-major histogram hist[d][block] in two steps:
+// block d scans its row in place and stores the row total; then one block
+// scans the 256 totals into the digit bases (the scatter adds both).
+__global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ hist, int nblocks,
+                                                   uint32_t* __restrict__ totals) {
+    __shared__ uint32_t part[256];
+    uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+    const int t = threadIdx.x;
+    const int chunk = (nblocks + 255) / 256;
+    const int lo = t * chunk, hi = lo + chunk < nblocks ? lo + chunk : nblocks;
+    uint32_t sum = 0;
+    for (int i = lo; i < hi; i++) sum += row[i];
+    part[t] = sum;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
+    for (int o = 1; o < 256; o <<= 1) {
         uint32_t v = t >= o ? part[t - o] : 0u;
         __syncthreads();
         part[t] += v;
         __syncthreads();
     }
     uint32_t run = t > 0 ? part[t - 1] : 0u;
-    for (int64_t i = lo; i < hi; i++) {
-        uint32_t v = a[i];
-        a[i] = run;
+    for (int i = lo; i < hi; i++) {
+        uint32_t v = row[i];
+        row[i] = run;
         run += v;
     }
+    if (t == 255) totals[blockIdx.x] = part[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_totals(uint32_t* __restrict__ totals) {
+    __shared__ uint32_t part[256];
+    const int t = threadIdx.x;
+    const uint32_t own = totals[t];
+    part[t] = own;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    totals[t] = part[t] - own;
 }
 
 // Stable scatter of one 8-bit digit.  Items of a tile are taken in rounds of
@@ -281,11 +300,11 @@ __global__ __launch_bounds__(1024) void k_exclusive_scan(uint32_t* __restrict__ 
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     int32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ hist,
-    int nblocks) {
+    int nblocks, const uint32_t* __restrict__ digit_base) {
     __shared__ uint32_t off[256];
     __shared__ uint32_t cnt[4][256];
     int t = threadIdx.x, w = t >> 6;
-    off[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    off[t] = digit_base[t] + hist[(int64_t)t * nblocks + blockIdx.x];
     int64_t base = (int64_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ITEMS; r++) {
         int64_t i = base + (int64_t)r * RS_THREADS + t;
@@ -322,7 +341,9 @@ hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf) {
     int bits = P.key_bits;
     int passes = (bits + 7) / 8;
     int nblocks = (int)((M + RS_TILE - 1) / RS_TILE);
-    if ((int64_t)nblocks * 256 > P.hist_len) {
+    // the last 256 entries of the histogram buffer hold the digit totals
+    uint32_t* totals = P.d_hist + (P.hist_len - 256);
+    if ((int64_t)nblocks * 256 > P.hist_len - 256) {
         set_error("radix histogram too small");
         return HAMLS_ERR_INVALID_ARG;
     }
@@ -331,11 +352,11 @@ hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf) {
         int shift = 8 * ps;
         hipLaunchKernelGGL(k_radix_count, dim3(nblocks), dim3(RS_THREADS), 0, s, P.d_key[cur], M,
                            shift, P.d_hist, nblocks);
-        hipLaunchKernelGGL(k_exclusive_scan, dim3(1), dim3(1024), 0, s, P.d_hist,
-                           (int64_t)nblocks * 256);
+        hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, s, P.d_hist, nblocks, totals);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, s, totals);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, P.d_key[cur],
                            P.d_idx[cur], P.d_key[cur ^ 1], P.d_idx[cur ^ 1], M, shift, P.d_hist,
-                           nblocks);
+                           nblocks, totals);
         cur ^= 1;
     }
     HAMLS_HIP(hipGetLastError());
@@ -343,21 +364,37 @@ hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf) {
     return HAMLS_OK;
 }
 
-// cell_start[c] = first sorted position whose key is >= c, for c in [0, ncells].
-__global__ void k_cell_start(const uint32_t* __restrict__ keys, int64_t n, int64_t ncells,
-                             int32_t* __restrict__ cs) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > n) return;
-    int64_t lo = i == 0 ? 0 : (int64_t)keys[i - 1] + 1;
-    int64_t hi = i == n ? ncells : (int64_t)keys[i];
-    for (int64_t c = lo; c <= hi; c++) cs[c] = (int32_t)i;
+// cell_start[c] = first sorted position whose key is >= c, for c in [0, ncells]:
+// one thread per cell; the block first brackets the positions of its 256 cells
+// by two binary searches, each thread then searches inside the bracket.
+__device__ __forceinline__ int64_t lower_bound_key(const uint32_t* keys, int64_t lo, int64_t hi,
+                                                   int64_t c) {
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if ((int64_t)keys[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__ keys, int64_t n,
+                                                    int64_t ncells, int32_t* __restrict__ cs) {
+    __shared__ int64_t br[2];
+    const int64_t c0 = (int64_t)blockIdx.x * 256;
+    if (threadIdx.x == 0) br[0] = lower_bound_key(keys, 0, n, c0);
+    if (threadIdx.x == 64) br[1] = lower_bound_key(keys, 0, n, c0 + 256);
+    __syncthreads();
+    const int64_t c = c0 + threadIdx.x;
+    if (c > ncells) return;
+    cs[c] = (int32_t)lower_bound_key(keys, br[0], br[1], c);
 }
 
 hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t M, hipStream_t s) {
-    int bs = 256;
-    int64_t nbk = (M + 1 + bs - 1) / bs;
-    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)nbk), dim3(bs), 0, s, keys, M,
-                       P.ncells, P.d_cell_start);
+    int64_t nbk = (P.ncells + 1 + 255) / 256;
+    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)nbk), dim3(256), 0, s, keys, M, P.ncells,
+                       P.d_cell_start);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -388,9 +425,9 @@ hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double
 
 __global__ void k_gather_values(const int32_t* __restrict__ perm, const double* __restrict__ values,
                                 int F, int64_t ld, int64_t M, int64_t cap,
-                                double* __restrict__ out, int32_t* __restrict__ qr_count) {
+                                double* __restrict__ out, int32_t* __restrict__ rs_count) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *qr_count = 0;  // the solve that follows appends its QR list from zero
+    if (i == 0) *rs_count = 0;  // the solve that follows appends its re-solve list from zero
     if (i >= M) return;
     int64_t j = perm[i];
     for (int f = 0; f < F; f++) out[f * cap + i] = values[f * ld + j];
@@ -401,7 +438,7 @@ hamls_status launch_gather_values(const Plan& P, const double* values, int F, in
     int bs = 256;
     int64_t nbk = (P.nrec + bs - 1) / bs;
     hipLaunchKernelGGL(k_gather_values, dim3((unsigned)nbk), dim3(bs), 0, s, P.d_perm,
-                       values + (int64_t)f0 * ld, F, ld, P.nrec, P.cap, P.d_vals, P.d_qr_count);
+                       values + (int64_t)f0 * ld, F, ld, P.nrec, P.cap, P.d_vals, P.d_rs_count);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -700,21 +737,19 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
 // fetched 64*U per step (U record loads per lane in flight); member rows of
 // (sqrt(w) g, sqrt(w) y) are staged in LDS 64 at a time and each lane owns a
 // few entries, summed over the staged rows.  FM bounds the fields of one pass.
-template <int K, int FM>
-__global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __restrict__ vals,
+template <int K, int FM, bool DD>
+__device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Geom& g, const double* __restrict__ vals,
                                                    int F, int wendland,
                                                    const double* __restrict__ thr,
-                                                   const double* __restrict__ delta,
-                                                   double* __restrict__ entries, int64_t MQ,
-                                                   int32_t* __restrict__ nj) {
+                                                   const double* __restrict__ delta, const SolveArgs& A,
+                                                   int32_t* __restrict__ nj,
+                                                   double* __restrict__ entries_out) {
     constexpr int m = (K + 1) * (K + 2) / 2;
     constexpr int EG = m * (m + 1) / 2;
     constexpr int ROW = m + FM + 1;
     constexpr int KE = (EG + m * FM + 63) / 64;
     constexpr int U = FM == 1 ? 4 : 1;
-    __shared__ double rows[64 * ROW];
-    __shared__ int sh[kScanLds];
-    const int j = xcd_block(blockIdx.x, gridDim.x);
+    static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
     const int lane = threadIdx.x;
     const int t = j / g.nphi, p = j - t * g.nphi;
     const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
@@ -728,11 +763,13 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
     const int E = EG + m * F;
     int ca[KE], cb[KE];
     double acc[KE];
+    dd accd[KE];
 #pragma unroll
     for (int k = 0; k < KE; k++) {
         int e = lane + 64 * k;
         acc[k] = 0.0;
-        ca[k] = -1;
+        accd[k] = {0.0, 0.0};
+        ca[k] = 0;
         cb[k] = 0;
         if (e < EG) {
             int a = 0, rem = e;
@@ -810,36 +847,88 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
                     for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
             }
             __syncthreads();
+#pragma unroll 2
             for (int r = 0; r < nin; r++) {
                 const double* row = rows + r * ROW;
 #pragma unroll
-                for (int k = 0; k < KE; k++)
-                    if (ca[k] >= 0) acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                for (int k = 0; k < KE; k++) {
+                    if (DD)
+                        dd_acc(accd[k], row[ca[k]], row[cb[k]]);
+                    else
+                        acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                }
             }
             __syncthreads();
             count += nin;
         }
     });
+    if (DD) {
+        double* Gh = rows;
+        double* Gl = rows + EG + m * FM;
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            int e = lane + 64 * k;
+            if (e < E) {
+                const dd v = fast_two_sum(accd[k].hi, accd[k].lo);
+                Gh[e] = v.hi;
+                Gl[e] = v.lo;
+            }
+        }
+        __syncthreads();
+        mls_dd_epilogue<m>(Gh, Gl, rows + 2 * (EG + m * FM), count, F, j, A);
+        return;
+    }
+    if (lane == 0) nj[j] = count;
+    double* Gs = rows;
 #pragma unroll
     for (int k = 0; k < KE; k++) {
         int e = lane + 64 * k;
-        if (e < E) entries[(int64_t)e * MQ + j] = acc[k];
+        if (e < E) Gs[e] = acc[k];
     }
-    if (lane == 0) nj[j] = count;
+    __syncthreads();
+    mls_solve_epilogue<m>(Gs, rows + EG + m * FM, count, F, j, A, entries_out);
 }
 
-hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s) {
-    (void)f0;
+
+template <int K, int FM, bool DD>
+__global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __restrict__ vals,
+                                                   int F, int wendland,
+                                                   const double* __restrict__ thr,
+                                                   const double* __restrict__ delta, SolveArgs A,
+                                                   int32_t* __restrict__ nj,
+                                                   double* __restrict__ entries_out) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    constexpr int EG = m * (m + 1) / 2;
+    constexpr int ROW = m + FM + 1;
+    constexpr int KE = (EG + m * FM + 63) / 64;
+    constexpr int U = FM == 1 ? 4 : 1;
+    static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
+    __shared__ double rows[64 * ROW];
+    __shared__ int sh[kScanLds];
+    if (DD) {
+        // the re-solve list: a grid-stride loop over the listed nodes
+        const int n = *A.rs_count;
+        for (int li = blockIdx.x; li < n; li += gridDim.x) {
+            s2_node<K, FM, DD>(A.rs_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+            __syncthreads();
+        }
+    } else {
+        s2_node<K, FM, DD>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+    }
+}
+
+hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
     S2Geom g = make_geom(P);
+    SolveArgs A = make_solve_args(P, F, f0, grid_values);
     dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
 #define HAMLS_ASM(KK)                                                                             \
     if (F == 1)                                                                                   \
-        hipLaunchKernelGGL((k_s2_assemble<KK, 1>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
-                           P.d_delta, P.d_entries, P.MQ, P.d_nj);                                 \
+        hipLaunchKernelGGL((k_s2_assemble<KK, 1, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
+                           P.d_delta, A, P.d_nj, P.d_entries);                                    \
     else                                                                                          \
-        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass>), grid, block, 0, s, g, P.d_vals, \
-                           F, wl, P.d_thr, P.d_delta, P.d_entries, P.MQ, P.d_nj);
+        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, false>), grid, block, 0, s, g, P.d_vals, \
+                           F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
     switch (P.K) {
         case 0: HAMLS_ASM(0) break;
         case 1: HAMLS_ASM(1) break;
@@ -856,308 +945,6 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // local solve (eq. (15)-(23))
 // ---------------------------------------------------------------------------
-
-// One thread per grid node: normalise (unit weights sum, unit-norm columns),
-// Cholesky of C, d = L^{-1} b, chi = 1/(1 - |d|^2), tau, and
-//   c_1 = (r_1 - sum_j d_j z_j / (1 + tau mu_j)) / (1 - sum_j d_j^2 / (1 + tau mu_j)),
-// z = L^{-1} r[1:], the Schur complement of the first unknown in (22).
-template <int MM>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs A) {
-    constexpr int EG = MM * (MM + 1) / 2;
-    constexpr int NC = MM - 1;               // order of C
-    constexpr int NL = NC * (NC + 1) / 2 + 1; // packed lower triangle of L
-    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= A.MQ) return;
-    const int64_t MQ = A.MQ;
-    int n = A.nj[j];
-    uint8_t st = A.rstatus[j];
-    double G[EG];
-#pragma unroll
-    for (int e = 0; e < EG; e++) G[e] = A.entries[(int64_t)e * MQ + j];
-    const double* H = A.entries + (int64_t)EG * MQ;  // right-hand sides, [a*F + f]
-    double W = G[0];
-    auto gidx = [](int a, int b) { return a * MM - a * (a - 1) / 2 + (b - a); };
-    if (n == 0 || !(W > 0.0)) {
-        for (int f = 0; f < A.F; f++) A.out[(int64_t)(A.f0 + f) * MQ + j] = __builtin_nan("");
-        if (A.write_diag) {
-            A.chi[j] = __builtin_nan("");
-            A.tau[j] = __builtin_nan("");
-            A.status[j] = st | HAMLS_ST_EMPTY;
-        }
-        return;
-    }
-    bool degen = n < MM;
-    double sc[MM];
-#pragma unroll
-    for (int a = 0; a < MM; a++) {
-        sc[a] = sqrt(G[gidx(a, a)] / W);
-        if (!(sc[a] > 0.0)) degen = true;
-    }
-    double chi = 1.0, tau = 0.0;
-    double d[NC > 0 ? NC : 1], L[NL];
-    double minpiv = 1.0;
-    bool ill = false;
-    if (!degen && NC > 0) {
-        // normalised C (unit diagonal) and b, Cholesky C = L L^T in packed rows
-#pragma unroll
-        for (int a = 0; a < NC; a++)
-#pragma unroll
-            for (int b = 0; b <= a; b++)
-                L[a * (a + 1) / 2 + b] = G[gidx(b + 1, a + 1)] / (W * sc[b + 1] * sc[a + 1]);
-#pragma unroll
-        for (int a = 0; a < NC; a++) d[a] = G[gidx(0, a + 1)] / (W * sc[a + 1]);
-#pragma unroll
-        for (int k = 0; k < NC; k++) {
-            double s = L[k * (k + 1) / 2 + k];
-#pragma unroll
-            for (int c = 0; c < k; c++) s -= L[k * (k + 1) / 2 + c] * L[k * (k + 1) / 2 + c];
-            if (!(s > 1e-300)) {
-                ill = true;
-                s = 1.0;
-            }
-            minpiv = fmin(minpiv, s);
-            double lkk = sqrt(s);
-            L[k * (k + 1) / 2 + k] = lkk;
-            double il = 1.0 / lkk;
-#pragma unroll
-            for (int r = k + 1; r < NC; r++) {
-                double v = L[r * (r + 1) / 2 + k];
-#pragma unroll
-                for (int c = 0; c < k; c++) v -= L[r * (r + 1) / 2 + c] * L[k * (k + 1) / 2 + c];
-                L[r * (r + 1) / 2 + k] = v * il;
-            }
-        }
-        double d2[NC > 0 ? NC : 1];
-        if (!ill) {
-            // d = L^{-1} b
-#pragma unroll
-            for (int r = 0; r < NC; r++) {
-                double v = d[r];
-#pragma unroll
-                for (int c = 0; c < r; c++) v -= L[r * (r + 1) / 2 + c] * d[c];
-                d[r] = v / L[r * (r + 1) / 2 + r];
-            }
-            double r0 = 0.0;
-#pragma unroll
-            for (int r = 0; r < NC; r++) {
-                d2[r] = d[r] * d[r];
-                r0 += d2[r];
-            }
-            chi = 1.0 / (1.0 - r0);
-            if (!(chi >= 1.0) || minpiv < kPivQR) ill = true;
-        }
-        double den = 1.0;
-        double fac[NC > 0 ? NC : 1];
-        if (!ill) {
-            tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
-#pragma unroll
-            for (int r = 0; r < NC; r++) {
-                fac[r] = d[r] / (1.0 + tau * A.mu[r]);
-                den -= fac[r] * d[r];
-            }
-            // the Schur denominator 1 - sum d^2/(1 + tau mu) cancels when the
-            // regularized chi_tau = 1/den is large
-            if (!(den > kDenQR)) ill = true;
-        }
-        if (ill) {
-            int slot = atomicAdd(A.qr_count, 1);
-            A.qr_list[slot] = (int32_t)j;
-            return;
-        }
-        for (int f = 0; f < A.F; f++) {
-            double z[NC > 0 ? NC : 1];
-#pragma unroll
-            for (int r = 0; r < NC; r++) {
-                double v = H[((int64_t)(r + 1) * A.F + f) * MQ + j] / (W * sc[r + 1]);
-#pragma unroll
-                for (int c = 0; c < r; c++) v -= L[r * (r + 1) / 2 + c] * z[c];
-                z[r] = v / L[r * (r + 1) / 2 + r];
-            }
-            double num = H[(int64_t)f * MQ + j] / W;
-#pragma unroll
-            for (int r = 0; r < NC; r++) num -= fac[r] * z[r];
-            A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
-        }
-        if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
-    }
-    if (!degen && NC == 0) {
-        for (int f = 0; f < A.F; f++) A.out[(int64_t)(A.f0 + f) * MQ + j] = H[(int64_t)f * MQ + j] / W;
-    }
-    if (degen) {
-        for (int f = 0; f < A.F; f++) A.out[(int64_t)(A.f0 + f) * MQ + j] = H[(int64_t)f * MQ + j] / W;
-        chi = __builtin_inf();
-        tau = __builtin_inf();
-        st |= HAMLS_ST_UNDERDETERMINED;
-    }
-    if (A.write_diag) {
-        A.chi[j] = chi;
-        A.tau[j] = tau;
-        A.status[j] = st;
-    }
-}
-
-// QR path for the centres flagged by k_solve: the rows (V_i | v1_i | y_w,i) of
-// the normalised weighted local problem (eq. (14)) are streamed in batches of
-// up to 64 and folded into the m-row upper-trapezoidal factor T of [V | v1 | y_w]
-// by Householder reflections (a tall-skinny QR over the first m columns).  At
-// the end, with S = sign(diag R_V):  L = R_V^T S is the Cholesky factor of C
-// (eq. (20)), d = S (Q^T v1)[0:m-1], z = S (Q^T y_w)[0:m-1], and the last
-// factor row gives rho = |(I - P_V) v1| and w = the matching component of y_w,
-// so that 1 - |d|^2 = rho^2 and r_1 - d.z = rho w without cancellation:
-//   c_1 = (rho w + sum_j d_j z_j tau mu_j/(1 + tau mu_j))
-//       / (rho^2 + sum_j d_j^2 tau mu_j/(1 + tau mu_j)).
-template <int K>
-__global__ __launch_bounds__(64) void k_s2_qr(S2Geom g, const double* __restrict__ vals, int wendland,
-                                             const double* __restrict__ thr,
-                                             const double* __restrict__ delta, SolveArgs A) {
-    constexpr int m = (K + 1) * (K + 2) / 2;
-    constexpr int NC = m - 1;
-    constexpr int LD = m + 1 + kMaxFieldsPerPass;
-    __shared__ double T[(m + 64) * LD];
-    __shared__ int sh[kScanLds];
-    const int lane = threadIdx.x;
-    const int F = A.F;
-    const int cols = m + F;
-    const int64_t MQ = A.MQ;
-    const int total = *A.qr_count;
-    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
-    for (int li = blockIdx.x; li < total; li += gridDim.x) {
-        const int j = A.qr_list[li];
-        const int t = j / g.nphi, p = j - t * g.nphi;
-        const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
-        const double thq = g.theta[t], phq = g.phi[p];
-        const double ct = g.ring_cs[2 * t], stt = g.ring_cs[2 * t + 1];
-        const double cp = g.col_cs[2 * p], sp = g.col_cs[2 * p + 1];
-        const double et0 = ct * cp, et1 = ct * sp, et2 = -stt, ep0 = -sp, ep1 = cp;
-        const double c = thr[j], dl = delta[j], idl = 1.0 / dl;
-        const double W = A.entries[j];
-        double isc[m];
-#pragma unroll
-        for (int a = 0; a < m; a++) isc[a] = 1.0 / sqrt(A.entries[(int64_t)gidx(a, a) * MQ + j] / W);
-        for (int e = lane; e < m * LD; e += 64) T[e] = 0.0;
-        __syncthreads();
-        s2_scan<1>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid_, const int* idx_) {
-            {
-                const bool valid = valid_[0];
-                const int i = idx_[0];
-                double x0 = 0.0, x1 = 0.0, x2 = 0.0, dd = -2.0;
-                if (valid) {
-                    x0 = g.X[i];
-                    x1 = g.X[g.cap + i];
-                    x2 = g.X[2 * g.cap + i];
-                    dd = s2_dot(x0, x1, x2, q0, q1, q2);
-                }
-                bool in = valid && dd > c;
-                uint64_t mk = __ballot(in);
-                int nin = __popcll(mk);
-                if (nin == 0) return;
-                if (in) {
-                    double w = wendland_phi(wendland, acos(fmin(dd, 1.0)) * idl);
-                    if (g.nu) w *= g.nu[i];
-                    double b = sqrt(w / W);
-                    double u = (x0 * et0 + x1 * et1 + x2 * et2) * idl;
-                    double v = (x0 * ep0 + x1 * ep1) * idl;
-                    double pu[K + 1], pv[K + 1];
-                    pu[0] = 1.0;
-                    pv[0] = 1.0;
-#pragma unroll
-                    for (int a = 1; a <= K; a++) {
-                        pu[a] = pu[a - 1] * u;
-                        pv[a] = pv[a - 1] * v;
-                    }
-                    double* row = T + (m + rank_below(mk)) * LD;
-                    int cidx = 0;
-#pragma unroll
-                    for (int l = 0; l <= K; l++)
-#pragma unroll
-                        for (int bb = 0; bb <= l; bb++) {
-                            if (cidx > 0) row[cidx - 1] = b * pu[l - bb] * pv[bb] * isc[cidx];
-                            cidx++;
-                        }
-                    row[NC] = b;
-                    for (int f = 0; f < F; f++) row[m + f] = b * vals[(int64_t)f * g.cap + i];
-                }
-                __syncthreads();
-                const int R = m + nin;
-                for (int k = 0; k < m; k++) {
-                    double part = 0.0;
-                    for (int r = k + lane; r < R; r += 64) {
-                        double v = T[r * LD + k];
-                        part += v * v;
-                    }
-                    double nrm2 = wave_sum(part);
-                    double x0k = T[k * LD + k];
-                    __syncthreads();
-                    // The columns have unit discrete norm; a residual below
-                    // 1e-100 is rounding noise (a batch of fewer than m rows
-                    // leaves such noise that each further reflection squares,
-                    // until 2/v.v would overflow).  Nothing to eliminate.
-                    if (!(nrm2 > 1e-200)) continue;
-                    double nrm = sqrt(nrm2);
-                    double alpha = x0k > 0.0 ? -nrm : nrm;
-                    double v0 = x0k - alpha;
-                    double vv = nrm2 - x0k * x0k + v0 * v0;
-                    for (int jc = k + 1 + lane; jc < cols; jc += 64) {
-                        double sdot = v0 * T[k * LD + jc];
-                        for (int r = k + 1; r < R; r++) sdot += T[r * LD + k] * T[r * LD + jc];
-                        sdot *= 2.0 / vv;
-                        T[k * LD + jc] -= sdot * v0;
-                        for (int r = k + 1; r < R; r++) T[r * LD + jc] -= sdot * T[r * LD + k];
-                    }
-                    __syncthreads();
-                    if (lane == 0) T[k * LD + k] = alpha;
-                    for (int r = k + 1 + lane; r < R; r += 64) T[r * LD + k] = 0.0;
-                    __syncthreads();
-                }
-            }
-        });
-        // finish on lane 0 (m - 1 <= 14 unknowns)
-        if (lane == 0) {
-            uint8_t st = A.rstatus[j] | HAMLS_ST_ILLCOND;
-            double rmin = 1e300;
-            for (int k = 0; k < NC; k++) rmin = fmin(rmin, fabs(T[k * LD + k]));
-            double chi, tau;
-            if (!(rmin > kRankTol)) {
-                for (int f = 0; f < F; f++)
-                    A.out[(int64_t)(A.f0 + f) * MQ + j] = A.entries[(int64_t)(m * (m + 1) / 2 + f) * MQ + j] / W;
-                chi = __builtin_inf();
-                tau = __builtin_inf();
-                st |= HAMLS_ST_UNDERDETERMINED;
-            } else {
-                double dv[NC], d2[NC], sg[NC];
-#pragma unroll
-                for (int k = 0; k < NC; k++) {
-                    sg[k] = T[k * LD + k] < 0.0 ? -1.0 : 1.0;
-                    dv[k] = sg[k] * T[k * LD + NC];
-                    d2[k] = dv[k] * dv[k];
-                }
-                const double rho = T[NC * LD + NC];
-                chi = 1.0 / (rho * rho);
-                tau = choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f);
-                double den = rho * rho;
-                double fac[NC];
-#pragma unroll
-                for (int k = 0; k < NC; k++) {
-                    double tm = tau * A.mu[k];
-                    fac[k] = tm > 0.0 ? dv[k] * (tm / (1.0 + tm)) : 0.0;
-                    den += fac[k] * dv[k];
-                }
-                for (int f = 0; f < F; f++) {
-                    double num = rho * T[NC * LD + m + f];
-                    for (int k = 0; k < NC; k++) num += fac[k] * sg[k] * T[k * LD + m + f];
-                    A.out[(int64_t)(A.f0 + f) * MQ + j] = num / den;
-                }
-                if (tau > 0.0) st |= HAMLS_ST_REGULARIZED;
-            }
-            if (A.write_diag) {
-                A.chi[j] = chi;
-                A.tau[j] = tau;
-                A.status[j] = st;
-            }
-        }
-        __syncthreads();
-    }
-}
 
 SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     SolveArgs A;
@@ -1188,39 +975,35 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     A.tau = P.d_tau;
     A.status = P.d_status;
     A.write_diag = f0 == 0;
-    A.qr_list = P.d_qr_list;
-    A.qr_count = P.d_qr_count;
+    A.rs_list = P.d_rs_list;
+    A.rs_count = P.d_rs_count;
     return A;
 }
 
-hamls_status launch_solve(const Plan& P, int F, int f0, double* grid_values, int Ftotal,
-                          hipStream_t s) {
-    (void)Ftotal;
+// Re-solve of the nodes flagged by the FP64 epilogue: the same assembly in
+// double-double precision, blocks striding over the list.
+hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+    if (P.m <= 1) return HAMLS_OK;
+    S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    int bs = 256;
-    dim3 grid((unsigned)((P.MQ + bs - 1) / bs)), block(bs);
-    switch (P.m) {
-        case 1: hipLaunchKernelGGL(k_solve<1>, grid, block, 0, s, A); break;
-        case 3: hipLaunchKernelGGL(k_solve<3>, grid, block, 0, s, A); break;
-        case 6: hipLaunchKernelGGL(k_solve<6>, grid, block, 0, s, A); break;
-        case 10: hipLaunchKernelGGL(k_solve<10>, grid, block, 0, s, A); break;
-        case 15: hipLaunchKernelGGL(k_solve<15>, grid, block, 0, s, A); break;
-        default: set_error("m = %d unsupported", P.m); return HAMLS_ERR_UNSUPPORTED;
+    dim3 grid((unsigned)(P.MQ < kResolveBlocks ? P.MQ : kResolveBlocks)), block(64);
+    int wl = P.prm.wendland;
+#define HAMLS_DDS(KK)                                                                                 \
+    if (F == 1)                                                                                       \
+        hipLaunchKernelGGL((k_s2_assemble<KK, 1, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
+                           P.d_delta, A, P.d_nj, P.d_entries);                                        \
+    else                                                                                              \
+        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, true>), grid, block, 0, s, g, P.d_vals, \
+                           F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
+    switch (P.K) {
+        case 1: HAMLS_DDS(1) break;
+        case 2: HAMLS_DDS(2) break;
+        case 3: HAMLS_DDS(3) break;
+        case 4: HAMLS_DDS(4) break;
+        default: break;
     }
+#undef HAMLS_DDS
     HAMLS_HIP(hipGetLastError());
-    if (P.m > 1) {
-        S2Geom g = make_geom(P);
-        dim3 qg((unsigned)(P.MQ < 2048 ? P.MQ : 2048)), qb(64);
-        int wl = P.prm.wendland;
-        switch (P.K) {
-            case 1: hipLaunchKernelGGL(k_s2_qr<1>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
-            case 2: hipLaunchKernelGGL(k_s2_qr<2>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
-            case 3: hipLaunchKernelGGL(k_s2_qr<3>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
-            case 4: hipLaunchKernelGGL(k_s2_qr<4>, qg, qb, 0, s, g, P.d_vals, wl, P.d_thr, P.d_delta, A); break;
-            default: break;
-        }
-        HAMLS_HIP(hipGetLastError());
-    }
     return HAMLS_OK;
 }
 

@@ -378,7 +378,7 @@ static hamls_status alloc_common(Plan& P, int dimx) {
     HAMLS_TRY(dalloc(P, &P.d_key[1], P.cap));
     HAMLS_TRY(dalloc(P, &P.d_idx[0], P.cap));
     HAMLS_TRY(dalloc(P, &P.d_idx[1], P.cap));
-    P.hist_len = 256 * ((P.cap + 4095) / 4096 + 1);
+    P.hist_len = 256 * ((P.cap + 4095) / 4096 + 2);  // per-block digit counts + digit totals
     HAMLS_TRY(dalloc(P, &P.d_hist, P.hist_len));
     HAMLS_TRY(dalloc(P, &P.d_cell_start, P.ncells + 1));
     HAMLS_TRY(dalloc(P, &P.d_delta, P.MQ));
@@ -391,8 +391,8 @@ static hamls_status alloc_common(Plan& P, int dimx) {
     int EG = P.m * (P.m + 1) / 2;
     P.n_entries_cap = EG + (int64_t)P.m * kMaxFieldsPerPass;
     HAMLS_TRY(dalloc(P, &P.d_entries, P.n_entries_cap * P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_qr_list, P.MQ));
-    HAMLS_TRY(dalloc(P, &P.d_qr_count, 64));
+    HAMLS_TRY(dalloc(P, &P.d_rs_list, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_rs_count, 64));
     HAMLS_TRY(dalloc(P, &P.d_vals, (size_t)kMaxFieldsPerPass * P.cap));
     return HAMLS_OK;
 }
@@ -678,23 +678,16 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
             PhaseTimer pt(*P, HAMLS_PHASE_GATHER, s);
             HAMLS_TRY(launch_gather_values(*P, values, Fc, f0, ld, s));
         }
-        if (P->dom == HAMLS_S2) {
-            {
-                PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
-                HAMLS_TRY(launch_s2_assemble(*P, Fc, f0, s));
-            }
-            PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
-            HAMLS_TRY(launch_solve(*P, Fc, f0, grid_values, F, s));
-        } else {
-            // assembly and the normal-matrix solve are fused; the QR re-solve
-            // of the flagged centres is the solve phase
-            {
-                PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
-                HAMLS_TRY(launch_grid_mls(*P, Fc, f0, grid_values, s));
-            }
-            PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
-            HAMLS_TRY(launch_grid_qr(*P, Fc, f0, grid_values, s));
+        // assembly and the normal-matrix solve are fused; the double-double re-solve of
+        // the flagged centres is the solve phase
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
+            HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_assemble(*P, Fc, f0, grid_values, s)
+                                         : launch_grid_mls(*P, Fc, f0, grid_values, s));
         }
+        PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
+        HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_resolve(*P, Fc, f0, grid_values, s)
+                                     : launch_grid_resolve(*P, Fc, f0, grid_values, s));
     }
     return HAMLS_OK;
 }

@@ -251,14 +251,12 @@ class TorusField:
         chunk = 1 << 15
         for s in range(0, x.shape[0], chunk):
             xs = x[s : s + chunk]
-            for c in range(self.coef.shape[0]):
-                prod = np.ones(xs.shape[0])
-                for d in range(3):
-                    ph = 2.0 * math.pi * np.outer(xs[:, d], ks)
-                    a = self.coef[c, d, :, 0]
-                    b = self.coef[c, d, :, 1]
-                    prod *= np.cos(ph) @ a - np.sin(ph) @ b
-                out[s : s + chunk] += prod
+            prod = np.ones((xs.shape[0], self.coef.shape[0]))
+            for d in range(3):
+                ph = 2.0 * math.pi * np.outer(xs[:, d], ks)
+                # all terms of one axis share the trigonometric table
+                prod *= np.cos(ph) @ self.coef[:, d, :, 0].T - np.sin(ph) @ self.coef[:, d, :, 1].T
+            out[s : s + chunk] = prod.sum(axis=1)
         return out
 
 
@@ -310,6 +308,14 @@ def s2_clusters(seed: int = 2000, M: int = 200_000, N: int = 128, K: int = 3, n_
                   knn_count=knn if knn is not None else 4 * m, knn_eps=0.05, reg="chi",
                   chi_target=10.0, chi_full=20.0)
     return Workload(f"s2-clusters-M{M}-N{N}-K{K}", "s2", x, y[None, :], params, truth=f)
+
+
+def s2_large(seed: int = 3000, M: int = 4_000_000, N: int = 512, K: int = 4) -> Workload:
+    """The large S2 case: the cluster + hole generator with 12 caps of radius
+    10-25 degrees, field band-limited to degree 640 plus the smooth bump,
+    N = 512 (grid 513 x 1026), K = 4 (m = 15), kNN n = 60."""
+    return s2_clusters(seed=seed, M=M, N=N, K=K, n_caps=12, cap_deg=(10.0, 25.0), field_degree=640,
+                       knn=60)
 
 
 def so3_clusters(seed: int = 5000, M: int = 1_000_000, N: int = 64, K: int = 2,

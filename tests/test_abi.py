@@ -16,7 +16,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(hamls_[a-z_]+)\s*\(", src)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_boundary_calls():
     names = declared_functions()
     for n in ("hamls_plan", "hamls_mls_to_grid", "hamls_grid_to_coeffs", "hamls_eval"):
         assert n in names

@@ -106,7 +106,14 @@ def _check(H, wl, rows=None, nu=None, label=""):
         near = fin & (om["chi"] <= 2 * chi_f)
         far = fin & ~near
         np.testing.assert_allclose(dg["chi"][sel][near], om["chi"][near], rtol=1e-8)
-        np.testing.assert_allclose(dg["chi"][sel][far], om["chi"][far], rtol=1e-3)
+        # beyond, the normal-matrix pivot 1/chi carries an absolute error of
+        # a few eps: chi to 1e-3, or to ~1e-12 chi^2 where chi passes 1e9
+        gchi, ochi = dg["chi"][sel][far], om["chi"][far]
+        badc = np.abs(gchi - ochi) > np.maximum(1e-3, 1e-12 * ochi) * ochi
+        for i in np.nonzero(badc)[0][:5]:
+            _say(f"  chi mismatch: gpu {gchi[i]:.6e} oracle {ochi[i]:.6e} "
+                 f"status {dg['status'][sel][far][i]} n {om['n'][far][i]}")
+        assert not badc.any()
         tn = near & (om["tau"] > 0)
         np.testing.assert_allclose(dg["tau"][sel][tn], om["tau"][tn], rtol=1e-6)
         n_ill = int(np.sum(dg["status"][sel] & H.ST_ILLCOND != 0))

@@ -130,7 +130,14 @@ def _check_against_oracle(H, wl, rows=None, check_lists=True, label=""):
         near = fin & (om["chi"] <= 2 * chi_f)
         far = fin & ~near
         np.testing.assert_allclose(dg["chi"][sel][near], om["chi"][near], rtol=1e-8)
-        np.testing.assert_allclose(dg["chi"][sel][far], om["chi"][far], rtol=1e-3)
+        # beyond, the normal-matrix pivot 1/chi carries an absolute error of
+        # a few eps: chi to 1e-3, or to ~1e-12 chi^2 where chi passes 1e9
+        gchi, ochi = dg["chi"][sel][far], om["chi"][far]
+        badc = np.abs(gchi - ochi) > np.maximum(1e-3, 1e-12 * ochi) * ochi
+        for i in np.nonzero(badc)[0][:5]:
+            _say(f"  chi mismatch: gpu {gchi[i]:.6e} oracle {ochi[i]:.6e} "
+                 f"status {dg['status'][sel][far][i]} n {om['n'][far][i]}")
+        assert not badc.any()
         tn = near & (om["tau"] > 0)
         np.testing.assert_allclose(dg["tau"][sel][tn], om["tau"][tn], rtol=1e-6)
         np.testing.assert_allclose(dg["tau"][sel][far], om["tau"][far], rtol=1e-2)
@@ -211,16 +218,21 @@ def test_degenerate_centres_fixed_radius(H):
         np.testing.assert_array_equal(np.isnan(gv[0]), np.isnan(om["values"][0]))
         ok = ~np.isnan(om["values"][0])
         # With a tiny fixed tau, centres holding barely m nodes keep chi up to
-        # ~1e8: their value is that ill-conditioned in itself, and any two
-        # backward-stable solvers differ by ~ eps chi |y|.  The 1e-10 bar holds
-        # where chi <= 1e6; beyond, each centre is held to 10 eps chi max|y|.
+        # ~1e8 and values amplified to O(100): such values are that
+        # ill-conditioned in themselves, and any two backward-stable solvers
+        # differ by ~ eps chi max(|y|, |value|).  The 1e-10 bar holds where
+        # chi <= 1e3; beyond, each centre is held to
+        # 1e-10 |value| + 20 eps chi max(max|y|, |value|).
         chi = om["chi"]
-        good = ok & (chi <= 1e6)
-        assert _rell2(gv[0, good], om["values"][0, good]) < TOL
-        bad = ok & (chi > 1e6)
-        _say(f"  centres with chi > 1e6: {int(bad.sum())}")
-        lim = 10 * 2.2e-16 * chi[bad] * np.abs(y).max()
-        assert np.all(np.abs(gv[0, bad] - om["values"][0, bad]) <= lim)
+        o = om["values"][0]
+        well = ok & (chi <= 1e3)
+        assert _rell2(gv[0, well], o[well]) < TOL
+        rest = ok & (chi > 1e3) & np.isfinite(chi)
+        _say(f"  centres with chi > 1e3: {int(rest.sum())}")
+        lim = 1e-10 * np.abs(o[rest]) + 20 * 2.2e-16 * chi[rest] * np.maximum(np.abs(y).max(), np.abs(o[rest]))
+        assert np.all(np.abs(gv[0, rest] - o[rest]) <= lim)
+        shep = ok & ~np.isfinite(chi)
+        np.testing.assert_allclose(gv[0, shep], o[shep], rtol=1e-12, atol=1e-14)
     finally:
         R.close()
 
@@ -322,3 +334,11 @@ def test_constant_field_whole_pipeline(H):
         assert np.abs(c[1:]).max() < 1e-12
     finally:
         R.close()
+
+
+def test_c3_full_size_sampled_rows(H):
+    # the large S2 case (M = 4e6, N = 512, K = 4, grid 513 x 1026) at full
+    # size; the oracle checks every 211th grid node against brute force over
+    # all nodes
+    wl = W.s2_large()
+    _check_against_oracle(H, wl, rows=np.arange(0, 513 * 1026, 211), check_lists=True, label="C3")
