@@ -50,9 +50,11 @@ typedef enum { HAMLS_REG_NONE = 0, HAMLS_REG_FIXED = 1, HAMLS_REG_CHI_TARGET = 2
 
 /* Arithmetic of step 2 (and step 3):
  *  FP64   every step in double precision
- *  MIXED  Gram assembly in FP32 with an FP64 residual refinement, FP64
- *         factorization of ill-conditioned centres; step 3 contraction in FP32
- *         (tables generated in FP64). */
+ *  MIXED  (S2) Gram assembly in FP32 with one FP64 residual refinement; centres
+ *         that are regularized, ill-conditioned (condition above ~1e4) or
+ *         degenerate are solved in FP64; step 3 contraction in FP32 on the
+ *         matrix cores (tables generated in FP64).  Within 1e-6 relative L2 of
+ *         FP64. */
 typedef enum { HAMLS_FP64 = 0, HAMLS_MIXED = 1 } hamls_precision;
 
 /* Per-centre status bits returned by hamls_diagnostics. */
@@ -112,8 +114,9 @@ hamls_status hamls_params_init(hamls_params* p);
  *  node_weights device, M (e.g. Voronoi areas, Sec. 2.2) or NULL for all ones
  *  M            >= 1 and >= knn_count; capacity for later rebinds is M
  * The plan copies what it needs; nodes are not referenced after return.
- * Errors: INVALID_ARG (bad parameters), NOT_EXACT_GRID, DOMAIN (S2 fixed
- * radius >= pi/2), OUT_OF_MEMORY, DEVICE. */
+ * Errors: INVALID_ARG (bad parameters), NOT_EXACT_GRID, DOMAIN (fixed
+ * radius: S2 >= pi/2, SO3 > pi, T3 >= 1/2), UNSUPPORTED (mixed precision
+ * outside S2, degree above 4 on S2 or 3 on SO3 / T3), OUT_OF_MEMORY, DEVICE. */
 hamls_status hamls_plan(const hamls_params* p, const double* nodes, int64_t M,
                         const double* node_weights, void* stream, hamls_plan_t* out);
 
@@ -124,7 +127,8 @@ hamls_status hamls_plan_rebind(hamls_plan_t plan, const double* nodes, int64_t M
 
 /* Step 2 of Alg. 1: the MLS value at every grid node (eq. (4), (14)-(23)).
  *  values       device, F rows of M node values; row f starts at values + f*ld
- *  F            1 <= F <= 64 real fields (complex data: two fields)
+ *  F            1 <= F <= 4096 real fields (complex data: two fields),
+ *               solved 16 per pass over the neighbours
  *  ld           >= M
  *  grid_values  device, F x M_Q (row-major, grid order of hamls_plan_grid)
  * Per-centre diagnostics are kept for hamls_diagnostics. */

@@ -105,8 +105,9 @@ struct Plan {
     double* d_chi = nullptr;        // MQ
     double* d_tau = nullptr;        // MQ
     double* d_entries = nullptr;    // n_entries x MQ
-    int32_t* d_rs_list = nullptr;   // MQ, centres re-solved by QR
-    int32_t* d_rs_count = nullptr;  // 1
+    int32_t* d_rs_list = nullptr;   // MQ, centres re-solved in double-double
+    int32_t* d_rs_count = nullptr;  // [0] re-solve list, [1] FP64 list of the mixed path
+    int32_t* d_mx_list = nullptr;   // MQ, nodes the mixed path hands to FP64
     int64_t n_entries_cap = 0;
     double* d_vals = nullptr;       // sorted values, kMaxFieldsPerPass x cap
     double* d_ptab = nullptr;       // Legendre table
@@ -121,6 +122,14 @@ struct Plan {
     int64_t work_len = 0;           // doubles per work buffer
     double* d_wtab = nullptr;
     double* d_ring_w = nullptr;     // SO3 Gauss-Legendre weight per beta ring
+    // S2 mixed precision: FP32 contraction table in MFMA blocks, block offsets,
+    // work items (k, parity, row tile), folded FP32 spectra
+    float* d_ptab32 = nullptr;
+    int64_t* d_tab_off = nullptr;
+    int32_t* d_leg_items = nullptr;
+    int64_t leg_items = 0;
+    float* d_x32 = nullptr;
+    int64_t x32_len = 0;
     int64_t resident = 0;
 
     // per-phase timing
@@ -164,8 +173,10 @@ struct SolveArgs {
     double* tau;
     uint8_t* status;
     int write_diag;
-    int32_t* rs_list;    // centres handed to the double-double re-solve
+    int32_t* rs_list;    // centres handed on (appended by the FP64 epilogue)
     int32_t* rs_count;
+    const int32_t* in_list;   // centres a list-mode kernel works on
+    const int32_t* in_count;
 };
 
 
@@ -179,6 +190,7 @@ hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double
                                  const double* nu, int64_t M, hipStream_t s);
 hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
 hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 hamls_status launch_gather_values(const Plan& P, const double* values, int F, int f0, int64_t ld,
                                   hipStream_t s);
@@ -186,6 +198,9 @@ hamls_status launch_s2_count(const Plan& P, int32_t* counts, hipStream_t s);
 hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx, hipStream_t s);
 hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStream_t s);
 hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s);
+hamls_status launch_s2_legendre_mfma(const Plan& P, int F, double* coeffs, hipStream_t s);
+hamls_status build_s2_mfma_table(Plan& P, std::vector<float>& tab, std::vector<int64_t>& off,
+                                 std::vector<int32_t>& items, const std::vector<double>& ptab_fp64);
 hamls_status launch_s2_eval(const Plan& P, const double* coeffs, int F, const double* pts,
                             int64_t npts, double* out, hipStream_t s);
 

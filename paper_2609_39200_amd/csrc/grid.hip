@@ -718,9 +718,9 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
     __shared__ int sh[kScanLds];
     if (DD) {
         // the re-solve list: a grid-stride loop over the listed nodes
-        const int n = *A.rs_count;
+        const int n = *A.in_count;
         for (int li = blockIdx.x; li < n; li += gridDim.x) {
-            grid_node<D, K, FM, DD>(A.rs_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+            grid_node<D, K, FM, DD>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
             __syncthreads();
         }
     } else {

@@ -427,7 +427,7 @@ __global__ void k_gather_values(const int32_t* __restrict__ perm, const double* 
                                 int F, int64_t ld, int64_t M, int64_t cap,
                                 double* __restrict__ out, int32_t* __restrict__ rs_count) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) *rs_count = 0;  // the solve that follows appends its re-solve list from zero
+    if (i < 2) rs_count[i] = 0;  // the solves that follow append their lists from zero
     if (i >= M) return;
     int64_t j = perm[i];
     for (int f = 0; f < F; f++) out[f * cap + i] = values[f * ld + j];
@@ -890,7 +890,7 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
 }
 
 
-template <int K, int FM, bool DD>
+template <int K, int FM, bool DD, bool LIST>
 __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __restrict__ vals,
                                                    int F, int wendland,
                                                    const double* __restrict__ thr,
@@ -905,16 +905,401 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
     __shared__ double rows[64 * ROW];
     __shared__ int sh[kScanLds];
-    if (DD) {
-        // the re-solve list: a grid-stride loop over the listed nodes
-        const int n = *A.rs_count;
+    if (LIST) {
+        // a list of nodes (the re-solve list, or the FP64 list of the mixed
+        // path): a grid-stride loop over the listed nodes
+        const int n = *A.in_count;
         for (int li = blockIdx.x; li < n; li += gridDim.x) {
-            s2_node<K, FM, DD>(A.rs_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+            s2_node<K, FM, DD>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
             __syncthreads();
         }
     } else {
         s2_node<K, FM, DD>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
     }
+}
+
+// Mixed precision, one S2 node per wave (the benchmark spec's FP32 policy, Rem. 2.4):
+//  1. FP32 pass: member rows (sqrt(w) g, sqrt(w) y) in FP32 (membership and
+//     coordinates in FP64), Gram and right-hand sides accumulated in FP32;
+//  2. FP64 factorisation of the FP32 system (as in the FP64 epilogue).  A node
+//     goes to the FP64 list if it is empty of structure (fewer than m members,
+//     a zero column), ill-conditioned (a pivot of the unit-diagonal C below
+//     1e-4, condition above ~1e4) or regularized (chi-target with chi above
+//     chi_T / 2, or a fixed tau > 0): these are solved from scratch in FP64;
+//  3. otherwise the FP32 solution c of the normal equations is refined once in
+//     FP64: a second pass over the members forms the residual e = y_w - B c and
+//     B^T e with FP64 rows, and the correction solves with the same factor.
+//     The error contracts by ~ cond * 6e-8 per refinement, so one step meets
+//     1e-6 for cond <= 1e4.
+template <int K, int FM>
+struct MixedLds {
+    static constexpr int m = (K + 1) * (K + 2) / 2;
+    static constexpr int EG = m * (m + 1) / 2;
+    static constexpr int E = EG + m * FM;
+    static constexpr int ROW32 = m + FM + 1;
+    static constexpr int ROW64 = m + FM;
+    static constexpr int oIsc = E, oL = oIsc + m, oC = oL + m * m, oRow = oC + FM * m;
+    static constexpr int size = oRow + 64 * ROW64;  // doubles
+    static_assert(64 * ROW32 <= 2 * size, "FP32 rows fit");
+};
+
+template <int K>
+__device__ __forceinline__ void s2_monomials(double uu, double vv, double s, double* out) {
+    double pu[K + 1], pv[K + 1];
+    pu[0] = 1.0;
+    pv[0] = 1.0;
+#pragma unroll
+    for (int a = 1; a <= K; a++) {
+        pu[a] = pu[a - 1] * uu;
+        pv[a] = pv[a - 1] * vv;
+    }
+    int c = 0;
+#pragma unroll
+    for (int l = 0; l <= K; l++)
+#pragma unroll
+        for (int b = 0; b <= l; b++) out[c++] = s * pu[l - b] * pv[b];
+}
+
+template <int K, int FM>
+__device__ __forceinline__ void s2_mixed_node(int j, double* lds, int* sh, const S2Geom& g,
+                                              const double* __restrict__ vals, int F, int wendland,
+                                              const double* __restrict__ thr,
+                                              const double* __restrict__ delta, const SolveArgs& A,
+                                              int32_t* __restrict__ nj) {
+    using L_ = MixedLds<K, FM>;
+    constexpr int m = L_::m, NC = m - 1, EG = L_::EG, ROW32 = L_::ROW32, ROW64 = L_::ROW64;
+    constexpr int KE = (EG + m * FM + 63) / 64;
+    constexpr int KG = (m * FM + 63) / 64;
+    constexpr int U = FM == 1 ? 4 : 1;
+    float* rows32 = (float*)lds;
+    double* Gs = lds;
+    double* isc = lds + L_::oIsc;
+    double* Lm = lds + L_::oL;
+    double* cv = lds + L_::oC;
+    double* rows64 = lds + L_::oRow;
+    const int lane = threadIdx.x;
+    const int64_t MQ = A.MQ;
+    const int t = j / g.nphi, p = j - t * g.nphi;
+    const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+    const double thq = g.theta[t], phq = g.phi[p];
+    const double ct = g.ring_cs[2 * t], stt = g.ring_cs[2 * t + 1];
+    const double cp = g.col_cs[2 * p], sp = g.col_cs[2 * p + 1];
+    const double et0 = ct * cp, et1 = ct * sp, et2 = -stt;
+    const double ep0 = -sp, ep1 = cp;
+    const double c = thr[j], dl = delta[j];
+    const double idl = 1.0 / dl;
+    const int E = EG + m * F;
+    int ca[KE], cb[KE];
+    float acc[KE];
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        int e = lane + 64 * k;
+        acc[k] = 0.0f;
+        ca[k] = 0;
+        cb[k] = 0;
+        if (e < EG) {
+            int a = 0, rem = e;
+            while (rem >= m - a) {
+                rem -= m - a;
+                a++;
+            }
+            ca[k] = a;
+            cb[k] = a + rem;
+        } else if (e < E) {
+            int r = e - EG;
+            ca[k] = r / F;
+            cb[k] = m + r % F;
+        }
+    }
+    // member row in FP64: sqrt(w) g (m values); returns sqrt(w)
+    auto member = [&](double x0, double x1, double x2, double d, double nw, double* row) {
+        const double w = wendland_phi(wendland, acos(fmin(d, 1.0)) * idl) * nw;
+        const double sw = sqrt(w);
+        const double uu = (x0 * et0 + x1 * et1 + x2 * et2) * idl;
+        const double vv = (x0 * ep0 + x1 * ep1) * idl;
+        s2_monomials<K>(uu, vv, sw, row);
+        return sw;
+    };
+    // ---------------- pass 1: FP32 Gram
+    int count = 0;
+    s2_scan<U>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
+            if (valid[u]) {
+                x0 = g.X[idx[u]];
+                x1 = g.X[g.cap + idx[u]];
+                x2 = g.X[2 * g.cap + idx[u]];
+                d = s2_dot(x0, x1, x2, q0, q1, q2);
+            }
+            const bool in = d > c;
+            const uint64_t mk = __ballot(in);
+            const int nin = __popcll(mk);
+            if (nin == 0) continue;
+            if (in) {
+                const int i = idx[u];
+                double r64[m];
+                const double sw = member(x0, x1, x2, d, g.nu ? g.nu[i] : 1.0, r64);
+                float* row = rows32 + rank_below(mk) * ROW32;
+#pragma unroll
+                for (int a = 0; a < m; a++) row[a] = (float)r64[a];
+                for (int f = 0; f < F; f++) row[m + f] = (float)(sw * vals[(int64_t)f * g.cap + i]);
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int r = 0; r < nin; r++) {
+                const float* row = rows32 + r * ROW32;
+#pragma unroll
+                for (int k = 0; k < KE; k++) acc[k] = fmaf(row[ca[k]], row[cb[k]], acc[k]);
+            }
+            __syncthreads();
+            count += nin;
+        }
+    });
+    if (lane == 0) nj[j] = count;
+#pragma unroll
+    for (int k = 0; k < KE; k++) {
+        int e = lane + 64 * k;
+        if (e < E) Gs[e] = (double)acc[k];
+    }
+    __syncthreads();
+    // ---------------- FP64 factorisation of the FP32 system
+    const uint8_t rst = A.rstatus[j];
+    const double W = Gs[0];
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    auto to_fp64 = [&]() {
+        if (lane == 0) {
+            const int slot = atomicAdd(A.rs_count, 1);
+            A.rs_list[slot] = j;
+        }
+    };
+    if (count == 0 || !(W > 0.0)) {
+        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = __builtin_nan("");
+        if (lane == 0 && A.write_diag) {
+            A.chi[j] = __builtin_nan("");
+            A.tau[j] = __builtin_nan("");
+            A.status[j] = rst | HAMLS_ST_EMPTY;
+        }
+        return;
+    }
+    bool degen = count < m;
+    {
+        double v = 1.0;
+        if (lane < m) v = sqrt(Gs[gidx(lane, lane)] / W);
+        if (__ballot(lane < m && !(v > 0.0))) degen = true;
+        if (lane < m) isc[lane] = 1.0 / v;
+    }
+    if (degen) {
+        to_fp64();
+        return;
+    }
+    __syncthreads();
+    double a[NC + 1];
+    {
+        const int r = lane;
+        const int ar = r >= NC ? 0 : r + 1;
+        const double sr = r <= NC ? isc[ar] : 0.0;
+#pragma unroll
+        for (int cc = 0; cc <= NC; cc++) {
+            const int bc = cc == NC ? 0 : cc + 1;
+            double v = 0.0;
+            if (r <= NC) {
+                const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
+                v = Gs[gidx(lo, hi)] / W * (sr * isc[bc]);
+            } else if (r < NC + 1 + F) {
+                v = Gs[EG + bc * F + (r - NC - 1)] / W * isc[bc];
+            }
+            a[cc] = v;
+        }
+    }
+    bool ill = false;
+    double minpiv = 1.0, s_last = 1.0;
+#pragma unroll
+    for (int k = 0; k <= NC; k++) {
+        const double sk = readlane_f64(a[k], k);
+        if (k < NC)
+            minpiv = fmin(minpiv, sk);
+        else
+            s_last = sk;
+        if (!(sk > 1e-300)) {
+            ill = true;
+            break;
+        }
+        const double lkk = sqrt(sk);
+        const double il = 1.0 / lkk;
+        a[k] = lane == k ? lkk : a[k] * il;
+#pragma unroll
+        for (int cc = k + 1; cc <= NC; cc++) a[cc] = fma(-a[k], readlane_f64(a[k], cc), a[cc]);
+    }
+    const double chi = ill ? 0.0 : 1.0 / s_last;
+    const bool regularized = (A.reg == HAMLS_REG_CHI_TARGET && chi > 0.5 * A.chi_t) ||
+                             (A.reg == HAMLS_REG_FIXED && A.tau_fixed > 0.0);
+    if (ill || minpiv < 1e-4 || regularized) {
+        to_fp64();
+        return;
+    }
+    // L (rows of the permuted order [V | v1]) to LDS; the field rows hold
+    // y' = L^{-1} r_perm: back substitution gives the FP32-data solution
+    if (lane <= NC) {
+#pragma unroll
+        for (int cc = 0; cc <= NC; cc++) Lm[lane * m + cc] = cc <= lane ? a[cc] : 0.0;
+    }
+    __syncthreads();
+    auto back_subst = [&](double* x) {
+        // x (permuted order) := L^{-T} x
+#pragma unroll
+        for (int i = NC; i >= 0; i--) {
+            double v = x[i];
+#pragma unroll
+            for (int k2 = i + 1; k2 <= NC; k2++) v -= Lm[k2 * m + i] * x[k2];
+            x[i] = v / Lm[i * m + i];
+        }
+    };
+    auto fwd_subst = [&](double* x) {
+#pragma unroll
+        for (int i = 0; i <= NC; i++) {
+            double v = x[i];
+#pragma unroll
+            for (int k2 = 0; k2 < i; k2++) v -= Lm[i * m + k2] * x[k2];
+            x[i] = v / Lm[i * m + i];
+        }
+    };
+    if (lane > NC && lane < NC + 1 + F) {
+        double x[NC + 1];
+#pragma unroll
+        for (int i = 0; i <= NC; i++) x[i] = a[i];
+        back_subst(x);
+        const int f = lane - NC - 1;
+        cv[f * m + 0] = x[NC];
+#pragma unroll
+        for (int i = 0; i < NC; i++) cv[f * m + i + 1] = x[i];
+    }
+    __syncthreads();
+    // ---------------- pass 2: FP64 residual B^T (y_w - B c)
+    const double ws = 1.0 / sqrt(W);
+    double sc[m];
+#pragma unroll
+    for (int i = 0; i < m; i++) sc[i] = isc[i] * ws;
+    int ga[KG], gf[KG];
+    double gacc[KG];
+#pragma unroll
+    for (int k = 0; k < KG; k++) {
+        const int e = lane + 64 * k;
+        ga[k] = e < m * F ? e / F : 0;
+        gf[k] = e < m * F ? m + e % F : m;
+        gacc[k] = 0.0;
+    }
+    s2_scan<U>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
+            if (valid[u]) {
+                x0 = g.X[idx[u]];
+                x1 = g.X[g.cap + idx[u]];
+                x2 = g.X[2 * g.cap + idx[u]];
+                d = s2_dot(x0, x1, x2, q0, q1, q2);
+            }
+            const bool in = d > c;
+            const uint64_t mk = __ballot(in);
+            const int nin = __popcll(mk);
+            if (nin == 0) continue;
+            if (in) {
+                const int i = idx[u];
+                double b[m];
+                const double sw = member(x0, x1, x2, d, g.nu ? g.nu[i] : 1.0, b);
+                double* row = rows64 + rank_below(mk) * ROW64;
+#pragma unroll
+                for (int a2 = 0; a2 < m; a2++) {
+                    b[a2] *= sc[a2];
+                    row[a2] = b[a2];
+                }
+                for (int f = 0; f < F; f++) {
+                    double e = sw * ws * vals[(int64_t)f * g.cap + i];
+#pragma unroll
+                    for (int a2 = 0; a2 < m; a2++) e -= b[a2] * cv[f * m + a2];
+                    row[m + f] = e;
+                }
+            }
+            __syncthreads();
+            for (int r = 0; r < nin; r++) {
+                const double* row = rows64 + r * ROW64;
+#pragma unroll
+                for (int k = 0; k < KG; k++) gacc[k] = fma(row[ga[k]], row[gf[k]], gacc[k]);
+            }
+            __syncthreads();
+        }
+    });
+    // correction: solve with the same factor, value = c_0 + delta_0
+    double* gs = rows64;
+#pragma unroll
+    for (int k = 0; k < KG; k++) {
+        const int e = lane + 64 * k;
+        if (e < m * F) gs[e] = gacc[k];
+    }
+    __syncthreads();
+    if (lane < F) {
+        double x[NC + 1];
+#pragma unroll
+        for (int i = 0; i < NC; i++) x[i] = gs[(i + 1) * F + lane];
+        x[NC] = gs[lane];
+        fwd_subst(x);
+        back_subst(x);
+        A.out[(int64_t)(A.f0 + lane) * MQ + j] = cv[lane * m] + x[NC];
+    }
+    if (lane == 0 && A.write_diag) {
+        A.chi[j] = chi;
+        A.tau[j] = 0.0;
+        A.status[j] = rst;
+    }
+}
+
+template <int K, int FM>
+__global__ __launch_bounds__(64) void k_s2_mixed(S2Geom g, const double* __restrict__ vals, int F,
+                                                int wendland, const double* __restrict__ thr,
+                                                const double* __restrict__ delta, SolveArgs A,
+                                                int32_t* __restrict__ nj) {
+    __shared__ double lds[MixedLds<K, FM>::size];
+    __shared__ int sh[kScanLds];
+    s2_mixed_node<K, FM>(xcd_block(blockIdx.x, gridDim.x), lds, sh, g, vals, F, wendland, thr, delta, A, nj);
+}
+
+// Mixed precision: the FP32 pass over every node (flagging nodes for FP64),
+// then the FP64 assembly over the flagged list (which flags its own
+// ill-conditioned nodes for the double-double re-solve).
+hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+    S2Geom g = make_geom(P);
+    SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    SolveArgs B = A;
+    A.rs_list = P.d_mx_list;
+    A.rs_count = P.d_rs_count + 1;
+    B.in_list = P.d_mx_list;
+    B.in_count = P.d_rs_count + 1;
+    dim3 grid((unsigned)P.MQ), block(64);
+    dim3 lgrid((unsigned)(P.MQ < kResolveBlocks ? P.MQ : kResolveBlocks));
+    int wl = P.prm.wendland;
+#define HAMLS_MIX(KK)                                                                                  \
+    if (F == 1) {                                                                                      \
+        hipLaunchKernelGGL((k_s2_mixed<KK, 1>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, A, \
+                           P.d_nj);                                                                    \
+        hipLaunchKernelGGL((k_s2_assemble<KK, 1, false, true>), lgrid, block, 0, s, g, P.d_vals, F, wl,     \
+                           P.d_thr, P.d_delta, B, P.d_nj, P.d_entries);                                \
+    } else {                                                                                           \
+        hipLaunchKernelGGL((k_s2_mixed<KK, kMaxFieldsPerPass>), grid, block, 0, s, g, P.d_vals, F, wl,     \
+                           P.d_thr, P.d_delta, A, P.d_nj);                                             \
+        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, false, true>), lgrid, block, 0, s, g,   \
+                           P.d_vals, F, wl, P.d_thr, P.d_delta, B, P.d_nj, P.d_entries);               \
+    }
+    switch (P.K) {
+        case 0: HAMLS_MIX(0) break;
+        case 1: HAMLS_MIX(1) break;
+        case 2: HAMLS_MIX(2) break;
+        case 3: HAMLS_MIX(3) break;
+        case 4: HAMLS_MIX(4) break;
+        default: set_error("degree %d unsupported on S2", P.K); return HAMLS_ERR_UNSUPPORTED;
+    }
+#undef HAMLS_MIX
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
 }
 
 hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
@@ -924,10 +1309,10 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_value
     int wl = P.prm.wendland;
 #define HAMLS_ASM(KK)                                                                             \
     if (F == 1)                                                                                   \
-        hipLaunchKernelGGL((k_s2_assemble<KK, 1, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
+        hipLaunchKernelGGL((k_s2_assemble<KK, 1, false, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
                            P.d_delta, A, P.d_nj, P.d_entries);                                    \
     else                                                                                          \
-        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, false>), grid, block, 0, s, g, P.d_vals, \
+        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, false, false>), grid, block, 0, s, g, P.d_vals, \
                            F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
     switch (P.K) {
         case 0: HAMLS_ASM(0) break;
@@ -977,6 +1362,8 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     A.write_diag = f0 == 0;
     A.rs_list = P.d_rs_list;
     A.rs_count = P.d_rs_count;
+    A.in_list = P.d_rs_list;
+    A.in_count = P.d_rs_count;
     return A;
 }
 
@@ -990,10 +1377,10 @@ hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values
     int wl = P.prm.wendland;
 #define HAMLS_DDS(KK)                                                                                 \
     if (F == 1)                                                                                       \
-        hipLaunchKernelGGL((k_s2_assemble<KK, 1, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
+        hipLaunchKernelGGL((k_s2_assemble<KK, 1, true, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
                            P.d_delta, A, P.d_nj, P.d_entries);                                        \
     else                                                                                              \
-        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, true>), grid, block, 0, s, g, P.d_vals, \
+        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, true, true>), grid, block, 0, s, g, P.d_vals, \
                            F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
     switch (P.K) {
         case 1: HAMLS_DDS(1) break;

@@ -147,8 +147,12 @@ static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
         set_error("unknown domain %d", dom);
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (p->precision != HAMLS_FP64) {
-        set_error("precision %d not built in this library version", p->precision);
+    if (p->precision != HAMLS_FP64 && p->precision != HAMLS_MIXED) {
+        set_error("unknown precision %d", p->precision);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->precision == HAMLS_MIXED && dom != HAMLS_S2) {
+        set_error("mixed precision is built for S2 only");
         return HAMLS_ERR_UNSUPPORTED;
     }
     int N = p->bandwidth;
@@ -393,6 +397,7 @@ static hamls_status alloc_common(Plan& P, int dimx) {
     HAMLS_TRY(dalloc(P, &P.d_entries, P.n_entries_cap * P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_rs_list, P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_rs_count, 64));
+    HAMLS_TRY(dalloc(P, &P.d_mx_list, P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_vals, (size_t)kMaxFieldsPerPass * P.cap));
     return HAMLS_OK;
 }
@@ -579,6 +584,21 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     HAMLS_HIP(hipMemcpyAsync(P.d_ptab, tab.data(), sizeof(double) * P.ptab_len,
                              hipMemcpyHostToDevice, s));
     HAMLS_HIP(hipMemcpyAsync(P.d_tw, tw.data(), sizeof(double) * 2 * np, hipMemcpyHostToDevice, s));
+    std::vector<float> tab32;
+    std::vector<int64_t> toff;
+    std::vector<int32_t> titems;
+    if (P.prm.precision == HAMLS_MIXED) {
+        HAMLS_TRY(build_s2_mfma_table(P, tab32, toff, titems, tab));
+        HAMLS_TRY(dalloc(P, &P.d_ptab32, tab32.size()));
+        HAMLS_TRY(dalloc(P, &P.d_tab_off, toff.size()));
+        HAMLS_TRY(dalloc(P, &P.d_leg_items, titems.size()));
+        HAMLS_HIP(hipMemcpyAsync(P.d_ptab32, tab32.data(), sizeof(float) * tab32.size(),
+                                 hipMemcpyHostToDevice, s));
+        HAMLS_HIP(hipMemcpyAsync(P.d_tab_off, toff.data(), sizeof(int64_t) * toff.size(),
+                                 hipMemcpyHostToDevice, s));
+        HAMLS_HIP(hipMemcpyAsync(P.d_leg_items, titems.data(), sizeof(int32_t) * titems.size(),
+                                 hipMemcpyHostToDevice, s));
+    }
     // the host vectors above are pageable: make the copies complete before
     // they go out of scope
     HAMLS_HIP(hipStreamSynchronize(s));
@@ -667,8 +687,8 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
         set_error("null argument");
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (F < 1 || F > 64 || ld < P->M) {
-        set_error("need 1 <= F <= 64 and ld >= M");
+    if (F < 1 || F > 4096 || ld < P->M) {
+        set_error("need 1 <= F <= 4096 and ld >= M");
         return HAMLS_ERR_INVALID_ARG;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -682,8 +702,11 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
         // the flagged centres is the solve phase
         {
             PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
-            HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_assemble(*P, Fc, f0, grid_values, s)
-                                         : launch_grid_mls(*P, Fc, f0, grid_values, s));
+            if (P->dom == HAMLS_S2 && P->prm.precision == HAMLS_MIXED)
+                HAMLS_TRY(launch_s2_mixed(*P, Fc, f0, grid_values, s));
+            else
+                HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_assemble(*P, Fc, f0, grid_values, s)
+                                             : launch_grid_mls(*P, Fc, f0, grid_values, s));
         }
         PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
         HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_resolve(*P, Fc, f0, grid_values, s)
@@ -717,7 +740,7 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
             len0 = len1 = (int64_t)F * P->MQ * 2;
         }
         HAMLS_HIP(hipStreamSynchronize(s));
-        for (double** slot : {&P->d_G, &P->d_work[0], &P->d_work[1]}) {
+        for (void** slot : {(void**)&P->d_G, (void**)&P->d_work[0], (void**)&P->d_work[1], (void**)&P->d_x32}) {
             if (!*slot) continue;
             for (auto it = P->owned.begin(); it != P->owned.end(); ++it)
                 if (it->p == *slot) {
@@ -728,9 +751,16 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
                 }
             *slot = nullptr;
         }
+        P->x32_len = 0;
         P->G_fields = 0;
         if (P->dom == HAMLS_S2) {
             HAMLS_TRY(dalloc(*P, &P->d_G, len0));
+            if (P->prm.precision == HAMLS_MIXED) {
+                const int th_pad = (((P->dims[0] + 1) / 2) + 3) & ~3;
+                const int64_t C_pad = ((2 * (int64_t)F + 15) / 16) * 16;
+                P->x32_len = (int64_t)(N + 1) * 2 * th_pad * C_pad;
+                HAMLS_TRY(dalloc(*P, &P->d_x32, P->x32_len));
+            }
         } else {
             HAMLS_TRY(dalloc(*P, &P->d_work[0], len0));
             HAMLS_TRY(dalloc(*P, &P->d_work[1], len1));
@@ -743,7 +773,10 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
             HAMLS_TRY(launch_s2_ring_dft(*P, grid_values, F, s));
         }
         PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s);
-        HAMLS_TRY(launch_s2_legendre(*P, F, coeffs, s));
+        if (P->prm.precision == HAMLS_MIXED)
+            HAMLS_TRY(launch_s2_legendre_mfma(*P, F, coeffs, s));
+        else
+            HAMLS_TRY(launch_s2_legendre(*P, F, coeffs, s));
         return HAMLS_OK;
     }
     if (P->dom == HAMLS_SO3) {
