@@ -38,8 +38,10 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble", "solve": "k_solve",
-                "ring_dft": "k_s2_ring_dft", "contract": "k_s2_legendre", "gather": "k_gather_values"}
+# kernel (name prefix) of each phase's main launch, for the counter summary
+PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble<",
+                "solve": None, "ring_dft": "k_s2_ring_dft", "contract": "k_s2_legendre",
+                "gather": "k_gather_values"}
 
 WORKLOADS = {
     "c2": ("s2_clusters", "S2 ill-distributed, M=200000 (8 vMF clusters kappa=20 + 20% uniform, 5 caps of 20 deg "
@@ -53,32 +55,43 @@ WORKLOADS = {
 }
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
-    None when the kernel source changed since the counters were taken."""
+def source_sha256():
+    import glob
     import hashlib
 
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2609_39200_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the kernel whose name starts with `kernel` (the
+    FP64 variant) from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy calibration), or None when the HIP sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "s2_c2_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_2609_39200_amd", "csrc", "kernels.hip")
     if kernel is None or not os.path.exists(path):
         return None
-    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
     info = {}
     kern = {}
     for line in open(path):
         if line.startswith("#") or not line.strip():
             continue
-        f = line.split()
-        if f[0] == "kernel":
-            kern[f[1]] = dict(zip(f[2::2], f[3::2]))
+        if line.startswith("kernel "):
+            name, rest = line[7:].split(" fetch_kib ")
+            f = ("fetch_kib " + rest).split()
+            kern[name] = dict(zip(f[0::2], f[1::2]))
         else:
+            f = line.split()
             info[f[0]] = f[1]
-    if info.get("source_sha256") != cur or kernel not in kern:
+    if info.get("source_sha256") != source_sha256():
         return None
-    k = kern[kernel]
-    fs, ws = float(info["fetch_scale"]), float(info["write_scale"])
-    return (float(k["fetch_kib"]) * fs + float(k["write_kib"]) * ws) * 1024.0
+    for name, k in kern.items():
+        if name.startswith(kernel) and "true" not in name:
+            return float(k["bytes"])
+    return None
 
 
 def flops_per_pair(domain, m, F):
@@ -99,6 +112,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--fields", type=int, default=1,
+                    help="fields per fit: the workload's field plus seeded N(0,1) node values")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -117,10 +132,15 @@ def main():
 
     t_gen = time.time()
     builder, wl_desc = WORKLOADS[args.workload]
+    if args.fields > 1:
+        wl_desc = wl_desc.replace(", F=1,", f", F={args.fields} (the field + N(0,1) node values),")
     if args.precision == "mixed":
         wl_desc = wl_desc.replace(", FP64", ", mixed (FP32 Gram + FP64 refinement/fallback, FP32 MFMA contraction)")
     wl = getattr(W, builder)()
     domain = wl.domain
+    if args.fields > 1:
+        extra = np.random.default_rng(77).standard_normal((args.fields - 1, wl.nodes.shape[0]))
+        wl.values = np.concatenate([wl.values, extra], axis=0)
     F = wl.values.shape[0]
     dev = torch.device("cuda:0")
     nodes = torch.as_tensor(wl.nodes, dtype=torch.float64, device=dev).contiguous()
@@ -174,7 +194,8 @@ def main():
     m = info.m
     dom = max(phases, key=lambda k: phases[k]["avg_ms"])
     roof = None
-    traffic = measured_traffic(PHASE_KERNEL.get(dom)) if args.workload == "c2" else None
+    traffic = (measured_traffic(PHASE_KERNEL.get(dom))
+               if args.workload == "c2" and args.precision == "fp64" and F == 1 else None)
     if dom == "assemble":
         fpp = flops_per_pair(domain, m, F)
         fl = pairs * fpp
@@ -238,6 +259,7 @@ def main():
             "grid_nodes": MQ,
             "nodes": int(info.num_nodes),
             "fields": F,
+            "precision": args.precision,
         },
         "fits_per_s": K / wall,
         "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "min": float(min(lat))},
