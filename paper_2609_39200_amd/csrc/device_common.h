@@ -49,6 +49,17 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Record i of a coordinate array: a 32-bit byte offset from a wave-uniform
+// base (one offset register serves every coordinate array).
+__device__ __forceinline__ double ld_rec(const double* base, int i) {
+    return *(const double*)((const char*)base + (uint32_t)i * 8u);
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 __device__ __forceinline__ int wave_sum_int(int v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -65,6 +76,126 @@ __device__ __forceinline__ int wave_incl_scan_int(int v) {
 
 // Ints of LDS one wave needs for s2_scan.
 constexpr int kScanLds = 4 * 64 + 1;
+
+__device__ __forceinline__ double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// n-th largest of the keys buf[0..count) (LDS, n <= count <= 64 NQ), by rank
+// counting with the keys held in registers, NQ per lane.  The n-th largest
+// t_n is the smallest key v with fewer than n keys strictly above it: a key at
+// or above t_n has at most #(u > t_n) < n keys above it, a key below t_n has
+// all the n or more keys at or above t_n above it.  One comparison per pair.
+// Slots past count hold -1e300, which has count >= n keys above it.
+template <int NQ>
+__device__ __forceinline__ double nth_largest_regs(const double* buf, int count, int knn) {
+    const int lane = threadIdx.x & 63;
+    double v[NQ];
+    int gt[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        v[q] = lane + 64 * q < count ? buf[lane + 64 * q] : -1e300;
+        gt[q] = 0;
+    }
+#pragma unroll 8
+    for (int b = 0; b < count; b++) {
+        const double u = buf[b];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) gt[q] += u > v[q];
+    }
+    double found = 1e300;
+#pragma unroll
+    for (int q = 0; q < NQ; q++)
+        if (gt[q] < knn) found = fmin(found, v[q]);
+    return wave_min(found);
+}
+
+// The bin of a 256-bin histogram (LDS, bins in decreasing key order, `above`
+// keys beyond bin 0) that holds the n-th largest key: the B with
+// above + C(B-1) < n <= above + C(B), C the cumulative count; before =
+// above + C(B-1).  Needs above < n <= above + C(255).  Called by a whole wave.
+__device__ __forceinline__ int hist_select_bin(const int* hist, int above, int knn, int& before_out) {
+    const int lane = threadIdx.x & 63;
+    int h4[4], s4 = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        h4[q] = hist[4 * lane + q];
+        s4 += h4[q];
+    }
+    const int incl = wave_incl_scan_int(s4);
+    int before = above + incl - s4, bsel = -1, bbefore = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (bsel < 0 && before < knn && knn <= before + h4[q]) {
+            bsel = 4 * lane + q;
+            bbefore = before;
+        }
+        before += h4[q];
+    }
+    const uint64_t owner = __ballot(bsel >= 0);
+    const int src = __ffsll((unsigned long long)owner) - 1;
+    before_out = __shfl(bbefore, src, 64);
+    return __shfl(bsel, src, 64);
+}
+
+// n-th largest of buf[0..count) (LDS, n <= count), keys in [klo, khi]: rank
+// count in registers for up to 256 keys; beyond, a 256-bin histogram on
+// khi - key (bins monotone in the key) selects the bin holding the n-th key
+// and the rank count runs inside it (a quadratic rank count over all keys if
+// that bin holds more than bincap, i.e. heavy duplication).  hist: 256 ints,
+// binbuf: bincap <= 128 doubles, both LDS.  Called by a whole wave.
+__device__ __forceinline__ double nth_largest(double* buf, int count, int knn, double klo, double khi,
+                                              int* hist, double* binbuf, int bincap) {
+    const int lane = threadIdx.x & 63;
+    if (count <= 64) return nth_largest_regs<1>(buf, count, knn);
+    if (count <= 128) return nth_largest_regs<2>(buf, count, knn);
+    if (count <= 192) return nth_largest_regs<3>(buf, count, knn);
+    if (count <= 256) return nth_largest_regs<4>(buf, count, knn);
+    const double scale = 256.0 / (khi - klo);
+#pragma unroll
+    for (int q = 0; q < 4; q++) hist[4 * lane + q] = 0;
+    __syncthreads();
+    for (int a = lane; a < count; a += 64) {
+        int bin = (int)((khi - buf[a]) * scale);
+        bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
+        atomicAdd(&hist[bin], 1);
+    }
+    __syncthreads();
+    int bbefore;
+    const int B = hist_select_bin(hist, 0, knn, bbefore);
+    const int kth = knn - bbefore;  // rank inside bin B
+    const int nB = hist[B];
+    __syncthreads();
+    if (nB <= bincap) {
+        int m = 0;
+        for (int base = 0; base < count; base += 64) {
+            const int a = base + lane;
+            bool inb = false;
+            double v = 0.0;
+            if (a < count) {
+                v = buf[a];
+                int bin = (int)((khi - v) * scale);
+                bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
+                inb = bin == B;
+            }
+            const uint64_t mk = __ballot(inb);
+            if (inb) binbuf[m + rank_below(mk)] = v;
+            m += __popcll(mk);
+        }
+        __syncthreads();
+        return nB <= 64 ? nth_largest_regs<1>(binbuf, nB, kth) : nth_largest_regs<2>(binbuf, nB, kth);
+    }
+    double found = 1e300;
+    for (int a = lane; a < count; a += 64) {
+        const double v = buf[a];
+        int gt = 0;
+#pragma unroll 8
+        for (int b = 0; b < count; b++) gt += buf[b] > v;
+        if (gt < knn) found = fmin(found, v);
+    }
+    return wave_min(found);
+}
 
 // Order-preserving map of doubles to unsigned integers.
 __device__ __forceinline__ uint64_t ordered_bits(double v) {

@@ -81,6 +81,16 @@ template <int D>
 __device__ __forceinline__ double grid_key_of_radius(const GridGeom& g, double r) {
     return D == 4 ? cos(0.5 * fmin(r, kPi)) : -(r * r);
 }
+// Key threshold of the box half-width rho (SO3 chordal distance in R^4:
+// |p - q|^2 = 2 - 2 p.q; T3 Euclidean) and back.
+template <int D>
+__device__ __forceinline__ double grid_key_of_rho(double rho) {
+    return D == 4 ? 1.0 - 0.5 * rho * rho : -(rho * rho);
+}
+template <int D>
+__device__ __forceinline__ double grid_rho_of_key(double k) {
+    return D == 4 ? sqrt(fmax(2.0 - 2.0 * k, 0.0)) : sqrt(fmax(-k, 0.0));
+}
 // Largest search radius: SO3 the rotation angle pi; T3 0.87, beyond the
 // largest min-image distance sqrt(3)/2, so that the ball holds every node.
 template <int D>
@@ -277,106 +287,6 @@ hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double*
 // support radius (eq. (5), (6), (12))
 // ---------------------------------------------------------------------------
 
-// n-th largest of buf[0..count) (count >= n), keys in (klo, khi]: rank count
-// for small sets, else a 256-bin histogram narrowing (bins monotone in the
-// key) and a rank count inside the selected bin.
-__device__ double select_nth_largest(double* buf, int count, int knn, double klo, double khi, int* hist,
-                                     double* binbuf, int bincap) {
-    const int lane = threadIdx.x & 63;
-    double found = -1e300;
-    if (count <= 256) {
-        double v[4];
-        int gt[4] = {0, 0, 0, 0}, ge[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < 4; q++) v[q] = lane + 64 * q < count ? buf[lane + 64 * q] : 1e300;
-#pragma unroll 4
-        for (int b = 0; b < count; b++) {
-            double u = buf[b];
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                gt[q] += u > v[q];
-                ge[q] += u >= v[q];
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; q++)
-            if (lane + 64 * q < count && gt[q] < knn && knn <= ge[q]) found = v[q];
-        return wave_max(found);
-    }
-    const double scale = 256.0 / (khi - klo);
-#pragma unroll
-    for (int q = 0; q < 4; q++) hist[4 * lane + q] = 0;
-    __syncthreads();
-    for (int a = lane; a < count; a += 64) {
-        int bin = (int)((khi - buf[a]) * scale);
-        bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
-        atomicAdd(&hist[bin], 1);
-    }
-    __syncthreads();
-    int h4[4], s4 = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        h4[q] = hist[4 * lane + q];
-        s4 += h4[q];
-    }
-    int incl = wave_incl_scan_int(s4);
-    int before = incl - s4, bsel = -1, bbefore = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        if (bsel < 0 && before < knn && knn <= before + h4[q]) {
-            bsel = 4 * lane + q;
-            bbefore = before;
-        }
-        before += h4[q];
-    }
-    uint64_t owner = __ballot(bsel >= 0);
-    int src = __ffsll((unsigned long long)owner) - 1;
-    const int B = __shfl(bsel, src, 64);
-    const int kth = knn - __shfl(bbefore, src, 64);
-    const int nB = hist[B];
-    __syncthreads();
-    if (nB <= bincap) {
-        int m = 0;
-        for (int base = 0; base < count; base += 64) {
-            int a = base + lane;
-            bool inb = false;
-            double v = 0.0;
-            if (a < count) {
-                v = buf[a];
-                int bin = (int)((khi - v) * scale);
-                bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
-                inb = bin == B;
-            }
-            uint64_t mk = __ballot(inb);
-            if (inb) binbuf[m + rank_below(mk)] = v;
-            m += __popcll(mk);
-        }
-        __syncthreads();
-        for (int a = lane; a < nB; a += 64) {
-            double v = binbuf[a];
-            int gt = 0, ge = 0;
-            for (int b = 0; b < nB; b++) {
-                double u = binbuf[b];
-                gt += u > v;
-                ge += u >= v;
-            }
-            if (gt < kth && kth <= ge) found = v;
-        }
-    } else {
-        for (int a = lane; a < count; a += 64) {
-            double v = buf[a];
-            int gt = 0, ge = 0;
-            for (int b = 0; b < count; b++) {
-                double u = buf[b];
-                gt += u > v;
-                ge += u >= v;
-            }
-            if (gt < knn && knn <= ge) found = v;
-        }
-    }
-    return wave_max(found);
-}
-
 // One grid node per block (one wave).  Adaptive radius: bracket a search
 // radius on the cell-cover count (cell table only), scan the box keeping the
 // keys of the ball, resize until it holds between n and kCandCap nodes, take
@@ -390,8 +300,9 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                                                    uint8_t* rstatus) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
-    __shared__ double buf[kCandCap];
-    __shared__ double binbuf[kBinCap];
+    __shared__ __align__(16) double buf[kCandCap];
+    __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
+    __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
     const int j = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
@@ -418,61 +329,116 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                 break;
             }
         }
-        double r_lo = 0.0, r_hi = 0.0;
-        double tn = -1e300;
+        // Keys at or above ktop are only counted (`above`).  With u = khi - key
+        // (khi the largest key: SO3 1, T3 0): a scan that overflows the buffer
+        // narrows the kept range to the bin of the n-th key in a 256-bin
+        // histogram of u over [khi - ktop, khi - key(r)); a scan with fewer
+        // than n keys in the ball grows it from a histogram of the records of
+        // the box outside the ball (u over [u0, 16 u0), u0 = khi - key(r)): the
+        // smallest bin edge with n records of the box inside holds at least n.
+        const double khi = D == 4 ? 1.0 : 0.0;
+        const double rhomax = grid_rho<D>(g, rmax);
+        double rho = grid_rho<D>(g, r);  // the search runs on the box half-width
+        double r_hi = 0.0;  // half-width of a box known to overflow the buffer
+        double tn = -1e300, ktop = 2.0;
         bool done = false, hemi = false;
+        int* hist = (int*)binbuf;  // 256 ints
         for (int it = 0; it < 40 && !done; it++) {
-            const double kr = grid_key_of_radius<D>(g, r);
-            int count = 0;
-            grid_scan<D, U>(g, q, grid_rho<D>(g, r), sh, [&](const bool* valid, const int* idx) {
+            const double kr = grid_key_of_rho<D>(rho);
+            const double ulo = ktop < 2.0 ? khi - ktop : 0.0;
+            const double hs = 256.0 / fmax((khi - kr) - ulo, 1e-300);
+            const double u0 = khi - kr, ohs = 256.0 / fmax(15.0 * u0, 1e-300);
+#pragma unroll
+            for (int qq = 0; qq < 4; qq++) {
+                hist[4 * lane + qq] = 0;
+                ohist[4 * lane + qq] = 0;
+            }
+            __syncthreads();
+            int count = 0, above = 0, nout = 0;
+            grid_scan<D, U>(g, q, rho, sh, [&](const bool* valid, const int* idx) {
                 double kv[U];
 #pragma unroll
                 for (int u = 0; u < U; u++) kv[u] = valid[u] ? grid_key<D>(g, idx[u], q) : -1e300;
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    bool in = valid[u] && kv[u] > kr;
-                    uint64_t mk = __ballot(in);
-                    int pos = count + rank_below(mk);
-                    if (in && pos < kCandCap) buf[pos] = kv[u];
+                    const bool up = valid[u] && kv[u] >= ktop;
+                    const bool in = valid[u] && kv[u] > kr && !up;
+                    const bool out = valid[u] && kv[u] <= kr;
+                    above += __popcll(__ballot(up));
+                    nout += __popcll(__ballot(out));
+                    if (out) {
+                        int bin = (int)((khi - kv[u] - u0) * ohs);
+                        atomicAdd(&ohist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                    }
+                    const uint64_t mk = __ballot(in);
+                    const int pos = count + rank_below(mk);
+                    if (in) {
+                        if (pos < kCandCap) {
+                            buf[pos] = kv[u];
+                        } else {
+                            int bin = (int)((khi - kv[u] - ulo) * hs);
+                            atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                        }
+                    }
                     count += __popcll(mk);
                 }
             });
             __syncthreads();
-            if (count >= knn && count <= kCandCap) {
-                tn = select_nth_largest(buf, count, knn, kr, D == 4 ? 1.0 : 0.0, sh, binbuf,
-                                        kBinCap);
-                done = true;
-            } else if (count < knn) {
-                if (r >= rmax) {
+            if (above >= knn) {
+                // rounding put the n-th key at or above ktop: drop the bound
+                rho = fmin(grid_rho_of_key<D>(ktop), rhomax);
+                r_hi = 0.0;
+                ktop = 2.0;
+            } else if (above + count < knn) {
+                if (rho >= rhomax) {
                     hemi = true;
                     done = true;
                 } else {
-                    r_lo = r;
-                    double grow = 1.15 * cbrt((double)knn / (double)(count > 0 ? count : 1));
-                    grow = grow < 1.2 ? 1.2 : (grow > 2.0 ? 2.0 : grow);
-                    double nr = r * grow;
-                    if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(r * r_hi);
-                    r = fmin(nr, rmax);
+                    const int have = above + count;
+                    double nr = -1.0;
+                    if (have + nout >= knn) {
+                        int before;
+                        const int B = hist_select_bin(ohist, have, knn, before);
+                        if (B < 255) nr = grid_rho_of_key<D>(khi - u0 * (1.0 + 15.0 * (B + 1) / 256.0));
+                    }
+                    if (nr <= rho) {
+                        double grow = 1.15 * cbrt((double)knn / (double)(have > 0 ? have : 1));
+                        grow = grow < 1.2 ? 1.2 : (grow > 2.0 ? 2.0 : grow);
+                        nr = rho * grow;
+                        if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(rho * r_hi);
+                    } else if (r_hi > 0.0) {
+                        nr = fmin(nr, r_hi);
+                    }
+                    rho = fmin(nr, rhomax);
                 }
+            } else if (count <= kCandCap) {
+                tn = nth_largest(buf, count, knn - above, kr, fmin(ktop, khi), sh, binbuf, kBinCap);
+                done = true;
             } else {
-                r_hi = r;
-                double shrink = 1.2 * cbrt((double)knn / (double)count);
-                double nr = r * (shrink < 0.9 ? shrink : 0.9);
-                if (nr <= r_lo) nr = sqrt(r * (r_lo > 0.0 ? r_lo : 0.5 * r));
-                r = nr;
+                // bin in the histogram of every key of (key(r), ktop)
+                for (int a = lane; a < kCandCap; a += 64) {
+                    int bin = (int)((khi - buf[a] - ulo) * hs);
+                    atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                }
+                __syncthreads();
+                int before;
+                const int B = hist_select_bin(hist, above, knn, before);
+                r_hi = rho;
+                if (B < 255) rho = fmin(grid_rho_of_key<D>(khi - (ulo + (B + 1) / hs)), rhomax);
+                if (B > 0) ktop = khi - (ulo + B / hs);
             }
             __syncthreads();
         }
         if (!done) {
             // exact fallback: bitwise binary search for the largest key v with
             // #(key >= v) >= n among the keys of the ball of radius r
-            const double kr = grid_key_of_radius<D>(g, r);
+            const double kr = grid_key_of_rho<D>(rho);
             uint64_t lo = ordered_bits(kr), hi = ordered_bits(D == 4 ? 1.0 : 0.0);
             while (lo < hi) {
                 uint64_t mid = lo + (hi - lo + 1) / 2;
                 double v = from_ordered_bits(mid);
                 int count = 0;
-                grid_scan<D, 1>(g, q, grid_rho<D>(g, r), sh, [&](const bool* valid, const int* idx) {
+                grid_scan<D, 1>(g, q, rho, sh, [&](const bool* valid, const int* idx) {
                     bool in = valid[0] && grid_key<D>(g, idx[0], q) >= v;
                     count += __popcll(__ballot(in));
                 });

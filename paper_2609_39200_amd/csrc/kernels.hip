@@ -80,17 +80,13 @@ __device__ __forceinline__ CapGeo cap_geo(const S2Geom& g, double thq, double cq
     return G;
 }
 
-// The (at most two) record ranges [lo1, lo1+len1), [lo2, lo2+len2) of band b
-// inside the cover.
-__device__ __forceinline__ void band_ranges(const S2Geom& g, const CapGeo& G, int b, double phq,
-                                            int& lo1, int& len1, int& lo2, int& len2) {
+// The (at most two) sector ranges [sa, sb], [sc, sd] (the second empty when
+// sd < sc) of band b, ns cells, inside the cover.
+__device__ __forceinline__ void band_sectors(const S2Geom& g, const CapGeo& G, int b, int ns, double phq,
+                                             int& sa, int& sb, int& sc, int& sd) {
     const double margin = 1e-7;
-    int off = g.band_off[b];
-    int ns = g.band_off[b + 1] - off;
     bool fullb = G.full;
     double dphi = G.dphi;
-    lo2 = 0;
-    len2 = 0;
     if (G.pole) {
         double te = G.north ? b * g.dtheta : (b + 1) * g.dtheta;  // edge nearest the pole
         fullb = true;
@@ -102,7 +98,10 @@ __device__ __forceinline__ void band_ranges(const S2Geom& g, const CapGeo& G, in
             }
         }
     }
-    int sa = 0, sb = ns - 1, sc = 0, sd = -1;  // sector ranges [sa, sb], [sc, sd]
+    sa = 0;
+    sb = ns - 1;
+    sc = 0;
+    sd = -1;
     if (!fullb) {
         double wdt = 2.0 * kPi / ns;
         int s0 = (int)floor((phq - dphi) / wdt);
@@ -124,27 +123,127 @@ __device__ __forceinline__ void band_ranges(const S2Geom& g, const CapGeo& G, in
             }
         }
     }
+}
+
+// The (at most two) record ranges [lo1, lo1+len1), [lo2, lo2+len2) of band b
+// inside the cover; off, ns: the band's first cell and cell count.
+__device__ __forceinline__ void band_ranges_at(const S2Geom& g, const CapGeo& G, int b, int off, int ns,
+                                               double phq, int& lo1, int& len1, int& lo2, int& len2) {
+    int sa, sb, sc, sd;
+    band_sectors(g, G, b, ns, phq, sa, sb, sc, sd);
     lo1 = g.cs[off + sa];
     len1 = g.cs[off + sb + 1] - lo1;
+    lo2 = 0;
+    len2 = 0;
     if (sd >= sc) {
         lo2 = g.cs[off + sc];
         len2 = g.cs[off + sd + 1] - lo2;
     }
 }
 
-// Number of sorted records in the cell cover of a cap (an upper bound on the
-// nodes inside it), from the cell table alone, one band per lane.
-__device__ __forceinline__ int s2_cover_count(const S2Geom& g, double thq, double cq, double sq,
-                                              double phq, double r) {
-    CapGeo G = cap_geo(g, thq, cq, sq, r);
+__device__ __forceinline__ void band_ranges(const S2Geom& g, const CapGeo& G, int b, double phq,
+                                            int& lo1, int& len1, int& lo2, int& len2) {
+    const int off = g.band_off[b];
+    band_ranges_at(g, G, b, off, g.band_off[b + 1] - off, phq, lo1, len1, lo2, len2);
+}
+
+// Radius k of the guess ladder r_k = min(base fac^k, pi/2).
+__device__ __forceinline__ double ladder_radius(double base, double fac, int k) {
+    double r = base;
+    for (int i = 0; i < k; i++) r *= fac;
+    return fmin(r, 0.5 * kPi);
+}
+
+// Approximate cover counts and cover areas of the caps of the R <= 64 radii of
+// a ladder around one node, in one pass of the cell table.  They only seed
+// the radius search (which is exact for whatever cap it scans), so the cover
+// is simplified: the bands the cap spans, each over the sectors within the
+// cap's widest longitude half-width asin(sin r / sin theta_q) of the node,
+// whole bands for caps that reach a pole, no rounding margin, FP32 areas.
+// Lane k first works out rung k's band range and half-width (broadcast by
+// readlane); then the bands of the largest cap go one per lane, each lane
+// staging its band's cell ranges for every rung in LDS (16 R bytes per lane)
+// and then reading all their cell starts at once.
+template <int R>
+__device__ __forceinline__ void s2_ladder_counts(const S2Geom& g, double thq, double sq, double phq,
+                                                 double base, double fac, int* lds, int (&cov)[R],
+                                                 float (&area)[R]) {
     const int lane = threadIdx.x & 63;
-    int tot = 0;
-    for (int bb = G.b0; bb <= G.b1; bb += 64) {
-        int b = bb + lane, lo1 = 0, len1 = 0, lo2 = 0, len2 = 0;
-        if (b <= G.b1) band_ranges(g, G, b, phq, lo1, len1, lo2, len2);
-        tot += wave_sum_int(len1 + len2);
+    const double ih = 1.0 / g.dtheta;
+    // rung geometry, lane k < R: bands [kb0, kb1], half-width kdp (< 0: whole bands)
+    int kb0 = 0, kb1 = -1;
+    double kdp = -1.0;
+    {
+        const double rk = ladder_radius(base, fac, lane < R ? lane : R - 1);
+        kb0 = (int)floor((thq - rk) * ih);
+        kb1 = (int)floor((thq + rk) * ih);
+        const float sr = sinf((float)rk) * (1.0f / (float)sq);
+        if (thq - rk > 0.0 && thq + rk < kPi && sr < 1.0f) kdp = (double)asinf(sr);
     }
-    return tot;
+    int bl = __shfl(kb0, R - 1, 64), bh = __shfl(kb1, R - 1, 64);
+    bl = bl < 0 ? 0 : bl;
+    bh = bh > g.nb - 1 ? g.nb - 1 : bh;
+    int4* cells = (int4*)lds + lane * R;
+    int part[R];
+    float pa[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        part[k] = 0;
+        pa[k] = 0.0f;
+    }
+    for (int bb = bl; bb <= bh; bb += 64) {
+        const int b = bb + lane;
+        const bool valid = b <= bh;
+        int off = 0, ns = 1;
+        if (valid) {
+            off = g.band_off[b];
+            ns = g.band_off[b + 1] - off;
+        }
+        const double spr = ns * (0.5 / kPi);  // sectors per radian of longitude
+#pragma unroll 1
+        for (int k = 0; k < R; k++) {
+            const int b0 = __builtin_amdgcn_readlane(kb0, k), b1 = __builtin_amdgcn_readlane(kb1, k);
+            const double dphi = readlane_f64(kdp, k);
+            int4 c = make_int4(off, off, off, off);  // empty ranges
+            if (valid && b >= b0 && b <= b1) {
+                c.y = off + ns;  // whole band
+                if (dphi >= 0.0) {
+                    const int s0 = (int)floor((phq - dphi) * spr), s1 = (int)floor((phq + dphi) * spr);
+                    if (s1 - s0 + 1 < ns) {
+                        if (s0 < 0) {
+                            c.x = off + s0 + ns;
+                            c.z = off;
+                            c.w = off + s1 + 1;
+                        } else if (s1 >= ns) {
+                            c.x = off + s0;
+                            c.z = off;
+                            c.w = off + s1 - ns + 1;
+                        } else {
+                            c.x = off + s0;
+                            c.y = off + s1 + 1;
+                        }
+                    }
+                }
+            }
+            cells[k] = c;
+        }
+        if (valid) {
+            // area of one cell of band b: (2 pi / ns) 2 sin(th_mid) sin(h / 2)
+            const float ca = (float)(4.0 * kPi) / (float)ns * sinf((float)((b + 0.5) * g.dtheta)) *
+                             sinf((float)(0.5 * g.dtheta));
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const int4 c = cells[k];
+                part[k] += (g.cs[c.y] - g.cs[c.x]) + (g.cs[c.w] - g.cs[c.z]);
+                pa[k] += (float)((c.y - c.x) + (c.w - c.z)) * ca;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        cov[k] = wave_sum_int(part[k]);
+        area[k] = wave_sum_f32(pa[k]);
+    }
 }
 
 // Visits every sorted record in the cell cover of the cap, 64*U per step: the
@@ -466,13 +565,13 @@ S2Geom make_geom(const Plan& P) {
 // ---------------------------------------------------------------------------
 
 // Support radius, one grid node per block (one wave):
-//  1. an initial radius from the cell density around the node; only where the
-//     surroundings are sparse (holes), grow it on the cell-cover count (cell
-//     table only, no record reads) until the cover holds 3n nodes;
-//  2. scan the cap, keeping the keys dot > cos r in LDS; if fewer than n or
-//     more than kCandCap, resize (bracketed) and rescan;
+//  1. an initial radius from approximate cover counts of a ladder of caps
+//     (cell table only, no record reads);
+//  2. scan the cap, keeping the keys dot > cos r in LDS; if fewer than n,
+//     grow (bracketed) and rescan; if more than kCandCap, narrow the kept key
+//     range to the histogram bin of the n-th key and rescan;
 //  3. the n-th largest key t_n exactly (rank count); if the search cannot be
-//     sized (duplicates), a bitwise binary search over the key instead.
+//     narrowed (duplicates), a bitwise binary search over the key instead.
 // delta = (1+eps) arccos(t_n), merged with a fixed delta_0 if both are set,
 // clamped to pi/2 (the tangent projection needs delta < pi/2).
 __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
@@ -480,8 +579,9 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
                                                  double* delta, uint8_t* rstatus) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
-    __shared__ double buf[kCandCap];
-    __shared__ double binbuf[kBinCap];
+    __shared__ __align__(16) double buf[kCandCap];
+    __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
+    __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
     const int j = xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
@@ -492,49 +592,112 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
     uint8_t st = 0;
     double dl = delta0, c = c_fixed;
     if (knn > 0) {
-        int bq = (int)(thq / g.dtheta);
-        bq = bq > g.nb - 1 ? g.nb - 1 : bq;
-        int off = g.band_off[bq], ns = g.band_off[bq + 1] - off;
-        int sc0 = (int)(phq * (ns / (2.0 * kPi)));
-        sc0 = sc0 > ns - 1 ? ns - 1 : sc0;
-        int cnt3 = 0, nsec = 3;
-        if (ns <= 3) {
-            cnt3 = g.cs[off + ns] - g.cs[off];
-            nsec = ns;
-        } else {
-            int a0 = (sc0 + ns - 1) % ns, a2 = (sc0 + 1) % ns;
-            cnt3 = (g.cs[off + a0 + 1] - g.cs[off + a0]) + (g.cs[off + sc0 + 1] - g.cs[off + sc0]) +
-                   (g.cs[off + a2 + 1] - g.cs[off + a2]);
-        }
-        double r;
-        if (cnt3 >= 4) {
-            double area = (2.0 * kPi / ns) * nsec * (cos(bq * g.dtheta) - cos((bq + 1) * g.dtheta));
-            r = fmin(1.2 * sqrt((double)knn * area / (kPi * cnt3)), 0.5 * kPi);
-        } else {
-            // grow on the cover count to a bracket [rl, r] around 3n covered
-            // nodes, then bisect it three times
-            r = fmin(2.0 * sqrt((double)knn / (double)M), 0.5 * kPi);
-            double rl = 0.0;
-            for (int it = 0; it < 24 && r < 0.5 * kPi; it++) {
-                int cov = s2_cover_count(g, thq, cq, sq, phq, r);
-                if (cov >= 3 * knn) break;
-                rl = r;
-                r = fmin(0.5 * kPi, r * (cov < knn / 2 ? 1.6 : 1.25));
+        // initial radius from the density of the 3 x 3 cells around the node
+        // (lanes 0-8, one cell each): the cap holding 1.44n at that density.
+        // Where they hold fewer than 4 records (sparse surroundings, holes),
+        // from the approximate cover counts of a ladder of caps r_k = r_0 1.6^k
+        // (one pass of the cell table per 8 radii), r_0 one cell: at the first
+        // cap whose cover holds 3n records, the cap that holds 1.5n at the
+        // cover's mean density, at most r_k.  Where the count jumps across that
+        // step (the edge of a hole), a finer ladder between r_k-1 and r_k first.
+        const double* Xy = g.X + g.cap;
+        const double* Xz = g.X + 2 * g.cap;
+        double r = 0.5 * kPi;
+        int cnt9 = 0;
+        float a9 = 0.0f;
+        {
+            int cnt = 0;
+            float ar = 0.0f;
+            int bq = (int)(thq * (1.0 / g.dtheta));
+            bq = bq > g.nb - 1 ? g.nb - 1 : bq;
+            const int b = bq + lane / 3 - 1, ds = lane % 3 - 1;
+            if (lane < 9 && b >= 0 && b < g.nb) {
+                const int off = g.band_off[b], ns = g.band_off[b + 1] - off;
+                const float ca = (float)(4.0 * kPi) / (float)ns * sinf((float)((b + 0.5) * g.dtheta)) *
+                                 sinf((float)(0.5 * g.dtheta));
+                if (ns <= 3) {
+                    if (ds == 0) {
+                        cnt = g.cs[off + ns] - g.cs[off];
+                        ar = ns * ca;
+                    }
+                } else {
+                    int sc = (int)(phq * (ns * (0.5 / kPi)));
+                    sc = sc > ns - 1 ? ns - 1 : sc;
+                    const int c = (sc + ds + ns) % ns;
+                    cnt = g.cs[off + c + 1] - g.cs[off + c];
+                    ar = ca;
+                }
             }
-            for (int it = 0; it < 3 && rl > 0.0; it++) {
-                double rm = sqrt(rl * r);
-                if (s2_cover_count(g, thq, cq, sq, phq, rm) >= 3 * knn)
-                    r = rm;
-                else
-                    rl = rm;
-            }
+            cnt9 = wave_sum_int(cnt);
+            a9 = wave_sum_f32(ar);
         }
-        double r_lo = 0.0, r_hi = 0.0;  // known too small / too large
-        double tn = -2.0;
+        if (cnt9 >= 4) {
+            r = fmin(1.2 * sqrt((double)knn * a9 / (kPi * cnt9)), 0.5 * kPi);
+        } else {
+            constexpr int R = 8;
+            double base = g.dtheta, fac = 1.6;
+            for (int pass = 0; pass < 6; pass++) {
+                float ak[R];
+                int ck[R];
+                s2_ladder_counts<R>(g, thq, sq, phq, base, fac, (int*)buf, ck, ak);
+                // the first radius whose cover holds 3n (counts grow with r)
+                int kh = R;
+                float as = 0.0f;
+                int cs3 = 1;
+#pragma unroll
+                for (int k = R - 1; k >= 0; k--)
+                    if (ck[k] >= 3 * knn) {
+                        kh = k;
+                        as = ak[k];
+                        cs3 = ck[k];
+                    }
+                if (kh == R) {
+                    const double rtop = ladder_radius(base, fac, R - 1);
+                    if (rtop >= 0.5 * kPi) break;
+                    base = rtop * fac;
+                    continue;
+                }
+                const double rh = ladder_radius(base, fac, kh);
+                if (cs3 > 16 * knn && fac > 1.1 && rh < 0.5 * kPi) {
+                    // refine between the previous rung and this one
+                    base = kh > 0 ? ladder_radius(base, fac, kh - 1) : base / fac;
+                    fac = pow(rh / base, 1.0 / R);
+                    base *= fac;
+                    continue;
+                }
+                // cap area 2 pi (1 - cos r) holding 1.5 n at density cs3 / as
+                const double cr = 1.0 - 1.5 * knn * as / (2.0 * kPi * cs3);
+                r = fmin(rh, acos(fmax(cr, -1.0)));
+                break;
+            }
+            __syncthreads();
+        }
+        // Keys at or above ktop are only counted (`above`): after a scan that
+        // overflows the buffer, a 256-bin histogram of u = 1 - key over
+        // [1 - ktop, 1 - cos r) locates the bin of the n-th key, and the next
+        // scan keeps only that bin's keys (the range shrinks 256-fold a step).
+        // A scan that finds fewer than n keys in the cap grows it from a
+        // histogram of the records of the cover outside the cap (u over
+        // [1 - cos r, 16 (1 - cos r))): the smallest bin edge with n records
+        // of the cover inside is a radius that holds at least n.
+        // The search runs on the key threshold cr = cos r of the cap.
+        double cr = cos(r);
+        double uh = 0.0;  // 1 - cos of a cap known to overflow the buffer
+        double tn = -2.0, ktop = 2.0;
         bool done = false, hemi = false;
+        int* hist = (int*)binbuf;  // 256 ints
         for (int it = 0; it < 40 && !done; it++) {
-            const double cr = cos(r);
-            int count = 0;
+            r = acos(cr);
+            const double ulo = ktop < 2.0 ? 1.0 - ktop : 0.0;
+            const double hs = 256.0 / fmax((1.0 - cr) - ulo, 1e-300);
+            const double u0 = 1.0 - cr, ohs = 256.0 / fmax(15.0 * u0, 1e-300);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                hist[4 * lane + q] = 0;
+                ohist[4 * lane + q] = 0;
+            }
+            __syncthreads();
+            int count = 0, above = 0, nout = 0;
             s2_scan<U>(g, thq, cq, sq, phq, r, sh, [&](const bool* valid, const int* idx) {
                 double d[U];
 #pragma unroll
@@ -542,144 +705,84 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
                     d[u] = -2.0;
                     if (valid[u]) {
                         int i = idx[u];
-                        d[u] = s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2);
+                        d[u] = s2_dot(ld_rec(g.X, i), ld_rec(Xy, i), ld_rec(Xz, i), q0, q1, q2);
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++) {
-                    bool in = d[u] > cr;
-                    uint64_t mk = __ballot(in);
-                    int pos = count + rank_below(mk);
-                    if (in && pos < kCandCap) buf[pos] = d[u];
+                    const bool up = d[u] >= ktop;
+                    const bool in = d[u] > cr && !up;
+                    const bool out = valid[u] && d[u] <= cr;
+                    above += __popcll(__ballot(up));
+                    nout += __popcll(__ballot(out));
+                    if (out) {
+                        int bin = (int)((1.0 - d[u] - u0) * ohs);
+                        atomicAdd(&ohist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                    }
+                    const uint64_t mk = __ballot(in);
+                    const int pos = count + rank_below(mk);
+                    if (in) {
+                        if (pos < kCandCap) {
+                            buf[pos] = d[u];
+                        } else {
+                            int bin = (int)((1.0 - d[u] - ulo) * hs);
+                            atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                        }
+                    }
                     count += __popcll(mk);
                 }
             });
             __syncthreads();
-            if (count >= knn && count <= kCandCap) {
-                // n-th largest key: the value with fewer than n keys above it
-                // and at least n at or above it
-                double found = -3.0;
-                if (count <= 256) {
-                    double v[4];
-                    int gt[4] = {0, 0, 0, 0}, ge[4] = {0, 0, 0, 0};
-#pragma unroll
-                    for (int q = 0; q < 4; q++) v[q] = lane + 64 * q < count ? buf[lane + 64 * q] : 3.0;
-#pragma unroll 4
-                    for (int b = 0; b < count; b++) {
-                        double u = buf[b];
-#pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            gt[q] += u > v[q];
-                            ge[q] += u >= v[q];
-                        }
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; q++)
-                        if (lane + 64 * q < count && gt[q] < knn && knn <= ge[q]) found = v[q];
-                } else {
-                    // histogram select: bins of 1 - key (monotone in the key)
-                    // over [0, 1 - cos r); keys of lower bins are larger
-                    int* hist = sh;
-                    const double scale = 256.0 / (1.0 - cr);
-#pragma unroll
-                    for (int q = 0; q < 4; q++) hist[4 * lane + q] = 0;
-                    __syncthreads();
-                    for (int a = lane; a < count; a += 64) {
-                        int bin = (int)((1.0 - buf[a]) * scale);
-                        bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
-                        atomicAdd(&hist[bin], 1);
-                    }
-                    __syncthreads();
-                    int h4[4], s4 = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        h4[q] = hist[4 * lane + q];
-                        s4 += h4[q];
-                    }
-                    int incl = wave_incl_scan_int(s4);
-                    int before = incl - s4, bsel = -1, bbefore = 0;
-#pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        if (bsel < 0 && before < knn && knn <= before + h4[q]) {
-                            bsel = 4 * lane + q;
-                            bbefore = before;
-                        }
-                        before += h4[q];
-                    }
-                    uint64_t owner = __ballot(bsel >= 0);
-                    int src = __ffsll((unsigned long long)owner) - 1;
-                    const int B = __shfl(bsel, src, 64);
-                    const int kth = knn - __shfl(bbefore, src, 64);  // rank inside bin B
-                    const int nB = hist[B];
-                    __syncthreads();
-                    if (nB <= kBinCap) {
-                        int m = 0;
-                        for (int base = 0; base < count; base += 64) {
-                            int a = base + lane;
-                            bool inb = false;
-                            double v = 0.0;
-                            if (a < count) {
-                                v = buf[a];
-                                int bin = (int)((1.0 - v) * scale);
-                                bin = bin < 0 ? 0 : (bin > 255 ? 255 : bin);
-                                inb = bin == B;
-                            }
-                            uint64_t mk = __ballot(inb);
-                            if (inb) binbuf[m + rank_below(mk)] = v;
-                            m += __popcll(mk);
-                        }
-                        __syncthreads();
-                        for (int a = lane; a < nB; a += 64) {
-                            double v = binbuf[a];
-                            int gt = 0, ge = 0;
-                            for (int b = 0; b < nB; b++) {
-                                double u = binbuf[b];
-                                gt += u > v;
-                                ge += u >= v;
-                            }
-                            if (gt < kth && kth <= ge) found = v;
-                        }
-                    } else {
-                        for (int a = lane; a < count; a += 64) {
-                            double v = buf[a];
-                            int gt = 0, ge = 0;
-#pragma unroll 4
-                            for (int b = 0; b < count; b++) {
-                                double u = buf[b];
-                                gt += u > v;
-                                ge += u >= v;
-                            }
-                            if (gt < knn && knn <= ge) found = v;
-                        }
-                    }
-                }
-                tn = wave_max(found);
-                done = true;
-            } else if (count < knn) {
-                if (r >= 0.5 * kPi) {
+            if (above >= knn) {
+                // rounding put the n-th key at or above ktop: drop the bound
+                cr = fmin(ktop, 1.0);
+                uh = 0.0;
+                ktop = 2.0;
+            } else if (above + count < knn) {
+                if (cr <= 0.0) {
                     hemi = true;
                     done = true;
                 } else {
-                    r_lo = r;
-                    double grow = 1.25 * sqrt((double)knn / (double)(count > 0 ? count : 1));
-                    grow = grow < 1.25 ? 1.25 : (grow > 2.0 ? 2.0 : grow);
-                    double nr = r * grow;
-                    if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(r * r_hi);
-                    r = fmin(nr, 0.5 * kPi);
+                    const int have = above + count;
+                    double nu = -1.0;  // 1 - cos of the next cap
+                    if (have + nout >= knn) {
+                        int before;
+                        const int B = hist_select_bin(ohist, have, knn, before);
+                        if (B < 255) nu = u0 * (1.0 + 15.0 * (B + 1) / 256.0);
+                    }
+                    if (nu < 0.0) {
+                        // radius times 1.25 to 2 (u ~ r^2 / 2)
+                        double grow = 1.5625 * (double)knn / (double)(have > 0 ? have : 1);
+                        grow = grow < 1.5625 ? 1.5625 : (grow > 4.0 ? 4.0 : grow);
+                        nu = u0 * grow;
+                        if (uh > 0.0 && nu >= uh) nu = sqrt(u0 * uh);
+                    } else if (uh > 0.0) {
+                        nu = fmin(nu, uh);
+                    }
+                    cr = fmax(1.0 - nu, 0.0);
                 }
+            } else if (count <= kCandCap) {
+                tn = nth_largest(buf, count, knn - above, cr, fmin(ktop, 1.0), sh, binbuf, kBinCap);
+                done = true;
             } else {
-                r_hi = r;
-                double shrink = 1.3 * sqrt((double)knn / (double)count);
-                double nr = r * (shrink < 0.9 ? shrink : 0.9);
-                if (nr <= r_lo) nr = sqrt(r * (r_lo > 0.0 ? r_lo : 0.5 * r));
-                r = nr;
+                // bin in the histogram of every key of (cos r, ktop)
+                for (int a = lane; a < kCandCap; a += 64) {
+                    int bin = (int)((1.0 - buf[a] - ulo) * hs);
+                    atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                }
+                __syncthreads();
+                int before;
+                const int B = hist_select_bin(hist, above, knn, before);
+                uh = u0;
+                if (B < 255) cr = 1.0 - (ulo + (B + 1) / hs);
+                if (B > 0) ktop = 1.0 - (ulo + B / hs);
             }
             __syncthreads();
         }
         if (!done) {
             // exact fallback: largest key value v with #(dot >= v) >= n, by
             // binary search over the ordered bit patterns in [cos r, 1]
-            double cr = cos(r);
+            r = acos(cr);
             uint64_t lo = ordered_bits(cr), hi = ordered_bits(1.0);
             while (lo < hi) {
                 uint64_t mid = lo + (hi - lo + 1) / 2;
