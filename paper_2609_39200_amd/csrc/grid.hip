@@ -77,10 +77,6 @@ template <int D>
 __device__ __forceinline__ double grid_rho(const GridGeom& g, double r) {
     return D == 4 ? 2.0 * sin(0.25 * fmin(r, kPi)) : r;
 }
-template <int D>
-__device__ __forceinline__ double grid_key_of_radius(const GridGeom& g, double r) {
-    return D == 4 ? cos(0.5 * fmin(r, kPi)) : -(r * r);
-}
 // Key threshold of the box half-width rho (SO3 chordal distance in R^4:
 // |p - q|^2 = 2 - 2 p.q; T3 Euclidean) and back.
 template <int D>
@@ -312,23 +308,32 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
     double dl = delta0;
     if (knn > 0) {
         const double rmax = grid_rmax<D>(g);
+        const double rhomax = grid_rho<D>(g, rmax);
+        // initial half-width: bracket the box cover count into [3n, 12n], from
+        // the radius holding n nodes at the mean density (SO3: the box around
+        // the ball on the 3-sphere is the larger part of its cover, so the
+        // first scan often holds fewer than n; the histogram-guided second
+        // scan is cheaper than a first scan of a box sized to hold n)
         double r = D == 4 ? cbrt(6.0 * kPi * knn / (double)M) : cbrt(3.0 * knn / (4.0 * kPi * M));
         r = fmin(r, rmax);
-        // bracket the cover count into [3n, 16n]
-        double rl = 0.0, rh = 0.0;
-        for (int it = 0; it < 20; it++) {
-            int cov = grid_cover_count<D>(g, q, grid_rho<D>(g, r));
-            if (cov < 3 * knn) {
-                if (r >= rmax) break;
-                rl = r;
-                r = rh > 0.0 ? sqrt(r * rh) : fmin(rmax, r * (cov < knn / 2 ? 1.6 : 1.25));
-            } else if (cov > 16 * knn && r > 1e-6) {
-                rh = r;
-                r = rl > 0.0 ? sqrt(r * rl) : r * 0.7;
-            } else {
-                break;
+        {
+            const int target = 3 * knn;
+            double rl = 0.0, rh = 0.0;
+            for (int it = 0; it < 20; it++) {
+                const int cov = grid_cover_count<D>(g, q, grid_rho<D>(g, r));
+                if (cov < target) {
+                    if (r >= rmax) break;
+                    rl = r;
+                    r = rh > 0.0 ? sqrt(r * rh) : fmin(rmax, r * (cov < target / 6 ? 1.6 : 1.25));
+                } else if (cov > 4 * target && r > 1e-6) {
+                    rh = r;
+                    r = rl > 0.0 ? sqrt(r * rl) : r * 0.7;
+                } else {
+                    break;
+                }
             }
         }
+        double rho = grid_rho<D>(g, r);  // the search runs on the box half-width
         // Keys at or above ktop are only counted (`above`).  With u = khi - key
         // (khi the largest key: SO3 1, T3 0): a scan that overflows the buffer
         // narrows the kept range to the bin of the n-th key in a 256-bin
@@ -337,8 +342,6 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
         // the box outside the ball (u over [u0, 16 u0), u0 = khi - key(r)): the
         // smallest bin edge with n records of the box inside holds at least n.
         const double khi = D == 4 ? 1.0 : 0.0;
-        const double rhomax = grid_rho<D>(g, rmax);
-        double rho = grid_rho<D>(g, r);  // the search runs on the box half-width
         double r_hi = 0.0;  // half-width of a box known to overflow the buffer
         double tn = -1e300, ktop = 2.0;
         bool done = false, hemi = false;

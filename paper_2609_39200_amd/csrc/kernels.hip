@@ -154,20 +154,19 @@ __device__ __forceinline__ double ladder_radius(double base, double fac, int k) 
     return fmin(r, 0.5 * kPi);
 }
 
-// Approximate cover counts and cover areas of the caps of the R <= 64 radii of
-// a ladder around one node, in one pass of the cell table.  They only seed
+// Approximate cover counts of the caps of the R <= 64 radii of a ladder
+// around one node, in one pass of the cell table.  They only seed
 // the radius search (which is exact for whatever cap it scans), so the cover
 // is simplified: the bands the cap spans, each over the sectors within the
 // cap's widest longitude half-width asin(sin r / sin theta_q) of the node,
-// whole bands for caps that reach a pole, no rounding margin, FP32 areas.
+// whole bands for caps that reach a pole, no rounding margin.
 // Lane k first works out rung k's band range and half-width (broadcast by
 // readlane); then the bands of the largest cap go one per lane, each lane
 // staging its band's cell ranges for every rung in LDS (16 R bytes per lane)
 // and then reading all their cell starts at once.
 template <int R>
 __device__ __forceinline__ void s2_ladder_counts(const S2Geom& g, double thq, double sq, double phq,
-                                                 double base, double fac, int* lds, int (&cov)[R],
-                                                 float (&area)[R]) {
+                                                 double base, double fac, int* lds, int (&cov)[R]) {
     const int lane = threadIdx.x & 63;
     const double ih = 1.0 / g.dtheta;
     // rung geometry, lane k < R: bands [kb0, kb1], half-width kdp (< 0: whole bands)
@@ -185,12 +184,8 @@ __device__ __forceinline__ void s2_ladder_counts(const S2Geom& g, double thq, do
     bh = bh > g.nb - 1 ? g.nb - 1 : bh;
     int4* cells = (int4*)lds + lane * R;
     int part[R];
-    float pa[R];
 #pragma unroll
-    for (int k = 0; k < R; k++) {
-        part[k] = 0;
-        pa[k] = 0.0f;
-    }
+    for (int k = 0; k < R; k++) part[k] = 0;
     for (int bb = bl; bb <= bh; bb += 64) {
         const int b = bb + lane;
         const bool valid = b <= bh;
@@ -228,22 +223,15 @@ __device__ __forceinline__ void s2_ladder_counts(const S2Geom& g, double thq, do
             cells[k] = c;
         }
         if (valid) {
-            // area of one cell of band b: (2 pi / ns) 2 sin(th_mid) sin(h / 2)
-            const float ca = (float)(4.0 * kPi) / (float)ns * sinf((float)((b + 0.5) * g.dtheta)) *
-                             sinf((float)(0.5 * g.dtheta));
 #pragma unroll
             for (int k = 0; k < R; k++) {
                 const int4 c = cells[k];
                 part[k] += (g.cs[c.y] - g.cs[c.x]) + (g.cs[c.w] - g.cs[c.z]);
-                pa[k] += (float)((c.y - c.x) + (c.w - c.z)) * ca;
             }
         }
     }
 #pragma unroll
-    for (int k = 0; k < R; k++) {
-        cov[k] = wave_sum_int(part[k]);
-        area[k] = wave_sum_f32(pa[k]);
-    }
+    for (int k = 0; k < R; k++) cov[k] = wave_sum_int(part[k]);
 }
 
 // Visits every sorted record in the cell cover of the cap, 64*U per step: the
@@ -596,10 +584,11 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
         // (lanes 0-8, one cell each): the cap holding 1.44n at that density.
         // Where they hold fewer than 4 records (sparse surroundings, holes),
         // from the approximate cover counts of a ladder of caps r_k = r_0 1.6^k
-        // (one pass of the cell table per 8 radii), r_0 one cell: at the first
-        // cap whose cover holds 3n records, the cap that holds 1.5n at the
-        // cover's mean density, at most r_k.  Where the count jumps across that
-        // step (the edge of a hole), a finer ladder between r_k-1 and r_k first.
+        // (one pass of the cell table per 8 radii), r_0 one cell: the first
+        // cap whose cover holds 3n records (in a hole, where the density sits
+        // at the rim, a mean-density estimate would fall short).  Where the
+        // count jumps past 8n across that step (the edge of a hole), a finer
+        // ladder between r_k-1 and r_k first.
         const double* Xy = g.X + g.cap;
         const double* Xz = g.X + 2 * g.cap;
         double r = 0.5 * kPi;
@@ -637,18 +626,14 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
             constexpr int R = 8;
             double base = g.dtheta, fac = 1.6;
             for (int pass = 0; pass < 6; pass++) {
-                float ak[R];
                 int ck[R];
-                s2_ladder_counts<R>(g, thq, sq, phq, base, fac, (int*)buf, ck, ak);
+                s2_ladder_counts<R>(g, thq, sq, phq, base, fac, (int*)buf, ck);
                 // the first radius whose cover holds 3n (counts grow with r)
-                int kh = R;
-                float as = 0.0f;
-                int cs3 = 1;
+                int kh = R, cs3 = 1;
 #pragma unroll
                 for (int k = R - 1; k >= 0; k--)
                     if (ck[k] >= 3 * knn) {
                         kh = k;
-                        as = ak[k];
                         cs3 = ck[k];
                     }
                 if (kh == R) {
@@ -658,16 +643,14 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
                     continue;
                 }
                 const double rh = ladder_radius(base, fac, kh);
-                if (cs3 > 16 * knn && fac > 1.1 && rh < 0.5 * kPi) {
+                if (cs3 > 8 * knn && fac > 1.1 && rh < 0.5 * kPi) {
                     // refine between the previous rung and this one
                     base = kh > 0 ? ladder_radius(base, fac, kh - 1) : base / fac;
                     fac = pow(rh / base, 1.0 / R);
                     base *= fac;
                     continue;
                 }
-                // cap area 2 pi (1 - cos r) holding 1.5 n at density cs3 / as
-                const double cr = 1.0 - 1.5 * knn * as / (2.0 * kPi * cs3);
-                r = fmin(rh, acos(fmax(cr, -1.0)));
+                r = rh;
                 break;
             }
             __syncthreads();
