@@ -24,6 +24,7 @@ namespace hamls {
 constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
 constexpr int kMaxFieldsPerPass = 16;  // fields handled by one assembly pass
+constexpr int kRadixTile = 1024;       // keys per block of a radix sort pass
 constexpr int kCandCap = 1024;         // LDS candidate buffer of the radius search
 constexpr int kResolveBlocks = 131072; // blocks of the double-double re-solve (grid-stride)
 

@@ -418,18 +418,19 @@ __device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int
     // row `lane` of the normalised, reordered system; p(0) = NC, p(a) = a - 1
     double a[NC + 1];
     {
+        const double iW = 1.0 / W;
         const int r = lane;
         const int ar = r >= NC ? 0 : r + 1;
-        const double sr = r <= NC ? isc[ar] : 0.0;
+        const double sr = r <= NC ? isc[ar] * iW : iW;
 #pragma unroll
         for (int c = 0; c <= NC; c++) {
             const int bc = c == NC ? 0 : c + 1;
             double v = 0.0;
             if (r <= NC) {
                 const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
-                v = Gs[gidx(lo, hi)] / W * (sr * isc[bc]);
+                v = Gs[gidx(lo, hi)] * (sr * isc[bc]);
             } else if (r < NC + 1 + F) {
-                v = Gs[EG + bc * F + (r - NC - 1)] / W * isc[bc];
+                v = Gs[EG + bc * F + (r - NC - 1)] * (sr * isc[bc]);
             }
             a[c] = v;
         }

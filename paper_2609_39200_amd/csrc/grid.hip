@@ -605,10 +605,12 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
     int count = 0;
     grid_scan<D, U>(g, q, grid_rho<D>(g, dl), sh, [&](const bool* valid, const int* idx) {
         double kv[U], y1[U];
+        // field values loaded with the coordinates, for every record of the
+        // cover (one round trip less than loading the members')
+#pragma unroll
+        for (int u = 0; u < U; u++) y1[u] = (FM == 1 && valid[u]) ? vals[idx[u]] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; u++) kv[u] = valid[u] ? grid_key<D>(g, idx[u], q) : -1e300;
-#pragma unroll
-        for (int u = 0; u < U; u++) y1[u] = (FM == 1 && kv[u] > c) ? vals[idx[u]] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const bool in = kv[u] > c;

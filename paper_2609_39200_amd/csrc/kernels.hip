@@ -317,8 +317,8 @@ hamls_status launch_s2_keys(const Plan& P, const double* nodes, int64_t M, hipSt
 }
 
 constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
-constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int RS_TILE = kRadixTile;
+constexpr int RS_ITEMS = RS_TILE / RS_THREADS;
 
 __global__ __launch_bounds__(RS_THREADS) void k_radix_count(const uint32_t* __restrict__ keys,
                                                             int64_t n, int shift,
@@ -834,7 +834,7 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
     constexpr int EG = m * (m + 1) / 2;
     constexpr int ROW = m + FM + 1;
     constexpr int KE = (EG + m * FM + 63) / 64;
-    constexpr int U = FM == 1 ? 4 : 1;
+    constexpr int U = FM == 1 ? 2 : 1;
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
     const int lane = threadIdx.x;
     const int t = j / g.nphi, p = j - t * g.nphi;
@@ -887,20 +887,21 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
                 x2[u] = g.X[2 * g.cap + i];
             }
         }
-#pragma unroll
-        for (int u = 0; u < U; u++)
-            if (valid[u]) d[u] = s2_dot(x0[u], x1[u], x2[u], q0, q1, q2);
-        // field values and node weights of the members, all loads in flight
+        // field values and node weights loaded with the coordinates, for every
+        // record of the cover (one round trip less than loading the members')
         double y1[U], nw[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             y1[u] = 0.0;
             nw[u] = 1.0;
-            if (d[u] > c) {
+            if (valid[u]) {
                 if (FM == 1) y1[u] = vals[idx[u]];
                 if (g.nu) nw[u] = g.nu[idx[u]];
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+            if (valid[u]) d[u] = s2_dot(x0[u], x1[u], x2[u], q0, q1, q2);
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const bool in = d[u] > c;
@@ -987,7 +988,7 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
     constexpr int EG = m * (m + 1) / 2;
     constexpr int ROW = m + FM + 1;
     constexpr int KE = (EG + m * FM + 63) / 64;
-    constexpr int U = FM == 1 ? 4 : 1;
+    constexpr int U = FM == 1 ? 2 : 1;
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
     __shared__ double rows[64 * ROW];
     __shared__ int sh[kScanLds];

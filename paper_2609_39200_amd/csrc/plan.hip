@@ -382,7 +382,7 @@ static hamls_status alloc_common(Plan& P, int dimx) {
     HAMLS_TRY(dalloc(P, &P.d_key[1], P.cap));
     HAMLS_TRY(dalloc(P, &P.d_idx[0], P.cap));
     HAMLS_TRY(dalloc(P, &P.d_idx[1], P.cap));
-    P.hist_len = 256 * ((P.cap + 4095) / 4096 + 2);  // per-block digit counts + digit totals
+    P.hist_len = 256 * ((P.cap + kRadixTile - 1) / kRadixTile + 2);  // per-block digit counts + digit totals
     HAMLS_TRY(dalloc(P, &P.d_hist, P.hist_len));
     HAMLS_TRY(dalloc(P, &P.d_cell_start, P.ncells + 1));
     HAMLS_TRY(dalloc(P, &P.d_delta, P.MQ));
