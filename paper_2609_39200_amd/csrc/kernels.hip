@@ -1576,46 +1576,59 @@ hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStrea
 // fhat_{n,k} = sum_{t < ceil(nt/2)} w_t P_n^k(x_t) (G_t(k) +- G_{nt-1-t}(k)),
 // the sign by the parity of n+k (P_n^k(-x) = (-1)^{n+k} P_n^k(x)); negative
 // orders from fhat_{n,-k} = (-1)^k conj(fhat_{n,k}) (real fields).
+// One coefficient per 8 adjacent lanes: lane p of the group sums the rings
+// t = p, p + 8, ... and the group adds its partial sums.
+constexpr int kLegSplit = 8;
 __global__ __launch_bounds__(256) void k_s2_legendre(const double* __restrict__ tab,
                                                     const double* __restrict__ G, int nt, int N,
                                                     int F, double* __restrict__ coeffs) {
-    int64_t na = (int64_t)(N + 1) * (N + 2) / 2;
-    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= na * F) return;
-    int f = (int)(gid / na);
-    int64_t id = gid - (int64_t)f * na;
+    const int64_t na = (int64_t)(N + 1) * (N + 2) / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int part = (int)(gid % kLegSplit);
+    const int64_t cidx = gid / kLegSplit;
+    const bool live = cidx < na * F;  // whole groups share this
+    const int f = live ? (int)(cidx / na) : 0;
+    const int64_t id = live ? cidx - (int64_t)f * na : 0;
     int n = (int)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
     while ((int64_t)n * (n + 1) / 2 > id) n--;
     while ((int64_t)(n + 1) * (n + 2) / 2 <= id) n++;
-    int k = (int)(id - (int64_t)n * (n + 1) / 2);
-    int th = (nt + 1) / 2;
-    bool even = ((n + k) & 1) == 0;
+    const int k = (int)(id - (int64_t)n * (n + 1) / 2);
+    const int th = (nt + 1) / 2;
+    const bool even = ((n + k) & 1) == 0;
     double re = 0.0, im = 0.0;
-    for (int t = 0; t < th; t++) {
-        int t2 = nt - 1 - t;
-        const double* g1 = G + (((int64_t)f * nt + t) * (N + 1) + k) * 2;
-        const double* g2 = G + (((int64_t)f * nt + t2) * (N + 1) + k) * 2;
-        double er, ei;
-        if (t == t2) {
-            er = g1[0];
-            ei = g1[1];
-        } else if (even) {
-            er = g1[0] + g2[0];
-            ei = g1[1] + g2[1];
-        } else {
-            er = g1[0] - g2[0];
-            ei = g1[1] - g2[1];
+    if (live) {
+        for (int t = part; t < th; t += kLegSplit) {
+            const int t2 = nt - 1 - t;
+            const double* g1 = G + (((int64_t)f * nt + t) * (N + 1) + k) * 2;
+            const double* g2 = G + (((int64_t)f * nt + t2) * (N + 1) + k) * 2;
+            double er, ei;
+            if (t == t2) {
+                er = g1[0];
+                ei = g1[1];
+            } else if (even) {
+                er = g1[0] + g2[0];
+                ei = g1[1] + g2[1];
+            } else {
+                er = g1[0] - g2[0];
+                ei = g1[1] - g2[1];
+            }
+            const double pv = tab[(int64_t)t * na + id];
+            re = fma(pv, er, re);
+            im = fma(pv, ei, im);
         }
-        double pv = tab[(int64_t)t * na + id];
-        re = fma(pv, er, re);
-        im = fma(pv, ei, im);
     }
-    int64_t nc = (int64_t)(N + 1) * (N + 1);
+#pragma unroll
+    for (int o = 1; o < kLegSplit; o <<= 1) {
+        re += __shfl_xor(re, o, 64);
+        im += __shfl_xor(im, o, 64);
+    }
+    if (!live || part != 0) return;
+    const int64_t nc = (int64_t)(N + 1) * (N + 1);
     double* o = coeffs + ((int64_t)f * nc + (int64_t)n * n + n + k) * 2;
     o[0] = re;
     o[1] = im;
     if (k > 0) {
-        double sg = (k & 1) ? -1.0 : 1.0;
+        const double sg = (k & 1) ? -1.0 : 1.0;
         double* o2 = coeffs + ((int64_t)f * nc + (int64_t)n * n + n - k) * 2;
         o2[0] = sg * re;
         o2[1] = -sg * im;
@@ -1623,9 +1636,9 @@ __global__ __launch_bounds__(256) void k_s2_legendre(const double* __restrict__ 
 }
 
 hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s) {
-    int64_t na = (int64_t)(P.N + 1) * (P.N + 2) / 2;
-    int64_t tot = na * F;
-    int bs = 256;
+    const int64_t na = (int64_t)(P.N + 1) * (P.N + 2) / 2;
+    const int64_t tot = na * F * kLegSplit;
+    const int bs = 256;
     hipLaunchKernelGGL(k_s2_legendre, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s,
                        P.d_ptab, P.d_G, P.dims[0], P.N, F, coeffs);
     HAMLS_HIP(hipGetLastError());
