@@ -503,6 +503,217 @@ __device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int
     }
 }
 
+// ---- the same solve for a group of GS lanes (GS = 16 or 32: 64 / GS nodes
+// per wave; GS = 64 is mls_solve_epilogue) ---------------------------------
+
+// The value of x on lane k of this lane's group.
+template <int GS>
+__device__ __forceinline__ double grp_bcast(double x, int k) {
+    if (GS == 64) return readlane_f64(x, k);
+    return __shfl(x, (int)((threadIdx.x & 63) & ~(GS - 1)) + k, 64);
+}
+
+// This group's bits of a wave ballot, group lane 0 in bit 0.
+template <int GS>
+__device__ __forceinline__ uint64_t grp_ballot(bool p) {
+    const uint64_t b = __ballot(p);
+    if (GS == 64) return b;
+    return (b >> ((threadIdx.x & 63) & ~(GS - 1))) & ((1ull << GS) - 1);
+}
+
+// choose_tau evaluated by one group (inputs uniform over the group): a
+// GS-way search, GS + 1 sub-intervals a round, enough rounds for the same
+// resolution of log tau (17 for GS = 16, 14 for GS = 32).
+template <int GS>
+__device__ __forceinline__ double choose_tau_grp(int reg, double chi, const double* d2, const double* mu,
+                                                 int n, double tau_fixed, double chi_t, double chi_f) {
+    if (reg == HAMLS_REG_FIXED) return tau_fixed;
+    if (reg != HAMLS_REG_CHI_TARGET || !(chi > chi_t)) return 0.0;
+    const int r = threadIdx.x & (GS - 1);
+    auto coupling = [&](double tau) {
+        double acc = 0.0, cur = -1.0, inv = 0.0;
+        for (int q = 0; q < n; q++) {
+            if (mu[q] != cur) {
+                cur = mu[q];
+                inv = 1.0 / (1.0 + tau * cur);
+            }
+            acc += d2[q] * inv;
+        }
+        return acc;
+    };
+    const double target = 1.0 - 1.0 / chi_t;
+    const uint64_t all = GS == 64 ? ~0ull : ((1ull << GS) - 1);
+    double hi = 0.0;
+    for (int e0 = 0; e0 < 2048 && hi == 0.0; e0 += GS) {
+        const uint64_t over = grp_ballot<GS>(coupling(ldexp(1.0, e0 + r)) > target);
+        if (over != all) hi = ldexp(1.0, e0 + __ffsll((unsigned long long)(~over & all)) - 1);
+    }
+    if (hi == 0.0) hi = ldexp(1.0, 2047);
+    double a = log(1e-16), b = log(hi);
+    constexpr int rounds = GS == 64 ? 11 : (GS == 32 ? 14 : 17);
+    for (int round = 0; round < rounds; round++) {
+        const double step = (b - a) / (GS + 1.0);
+        const int cnt = __popcll(grp_ballot<GS>(coupling(exp(a + step * (r + 1))) > target));
+        const double na = cnt == 0 ? a : a + step * cnt;
+        const double nb = cnt == GS ? b : a + step * (cnt + 1);
+        a = na;
+        b = nb;
+    }
+    const double tt = (chi - chi_t) / (chi_f - chi_t);
+    double sm = 1.0;
+    if (tt < 1.0) {
+        const double t4 = tt * tt * tt * tt;
+        sm = t4 * (35.0 - 84.0 * tt + 70.0 * tt * tt - 20.0 * tt * tt * tt);
+    }
+    return sm * exp(0.5 * (a + b));
+}
+
+// mls_solve_epilogue for one node per group of GS lanes (m + F <= GS), one
+// field (F = 1): Gs the node's packed Gram matrix and right-hand side in LDS,
+// group lane r holds row r of the normalised, reordered system.  The column
+// scales and every pivot go round the group by broadcasts; no barrier, so the
+// groups of a wave may take different branches.
+template <int m, int GS>
+__device__ void mls_solve_group(const double* Gs, int count, int64_t j, const SolveArgs& A) {
+    constexpr int NC = m - 1;
+    constexpr int EG = m * (m + 1) / 2;
+    constexpr int F = 1;
+    static_assert(m + F <= GS, "group too small");
+    const int r = threadIdx.x & (GS - 1);
+    const int base = (threadIdx.x & 63) & ~(GS - 1);
+    const int64_t MQ = A.MQ;
+    const uint8_t rst = A.rstatus[j];
+    const double W = Gs[0];
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    if (count == 0 || !(W > 0.0)) {
+        if (r < F) A.out[(int64_t)(A.f0 + r) * MQ + j] = __builtin_nan("");
+        if (r == 0 && A.write_diag) {
+            A.chi[j] = __builtin_nan("");
+            A.tau[j] = __builtin_nan("");
+            A.status[j] = rst | HAMLS_ST_EMPTY;
+        }
+        return;
+    }
+    bool degen = count < m;
+    double inv = 1.0;  // 1 / sqrt(G_rr / W) on group lanes r < m
+    {
+        double v = 1.0;
+        if (r < m) v = sqrt(Gs[gidx(r, r)] / W);
+        if (grp_ballot<GS>(r < m && !(v > 0.0))) degen = true;
+        inv = 1.0 / v;
+    }
+    if (degen) {
+        if (r < F) A.out[(int64_t)(A.f0 + r) * MQ + j] = Gs[EG + r] / W;
+        if (r == 0 && A.write_diag) {
+            A.chi[j] = __builtin_inf();
+            A.tau[j] = __builtin_inf();
+            A.status[j] = rst | HAMLS_ST_UNDERDETERMINED;
+        }
+        return;
+    }
+    // row r of the normalised, reordered system; p(0) = NC, p(a) = a - 1
+    double a[NC + 1];
+    {
+        const double iW = 1.0 / W;
+        const int ar = r >= NC ? 0 : r + 1;
+        const double sr = (r <= NC ? __shfl(inv, base + ar, 64) : 1.0) * iW;
+#pragma unroll
+        for (int c = 0; c <= NC; c++) {
+            const int bc = c == NC ? 0 : c + 1;
+            const double ib = grp_bcast<GS>(inv, bc);
+            double v = 0.0;
+            if (r <= NC) {
+                const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
+                v = Gs[gidx(lo, hi)] * (sr * ib);
+            } else if (r < NC + 1 + F) {
+                v = Gs[EG + bc * F + (r - NC - 1)] * (sr * ib);
+            }
+            a[c] = v;
+        }
+    }
+    bool ill = false;
+    double minpiv = 1.0, s_last = 1.0;
+#pragma unroll
+    for (int k = 0; k <= NC; k++) {
+        const double sk = grp_bcast<GS>(a[k], k);
+        if (k < NC) {
+            minpiv = fmin(minpiv, sk);
+            if (!(sk > 1e-300)) {
+                ill = true;
+                break;
+            }
+        } else {
+            s_last = sk;
+            if (!(sk > 0.0)) {
+                ill = true;
+                break;
+            }
+        }
+        const double lkk = sqrt(sk);
+        const double il = 1.0 / lkk;
+        a[k] = r == k ? lkk : a[k] * il;
+#pragma unroll
+        for (int c = k + 1; c <= NC; c++) a[c] = fma(-a[k], grp_bcast<GS>(a[k], c), a[c]);
+    }
+    double dv[NC > 0 ? NC : 1], d2[NC > 0 ? NC : 1], tf[NC > 0 ? NC : 1];
+    double chi = 1.0, tau = 0.0, den = 1.0;
+    if (!ill) {
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            dv[k] = grp_bcast<GS>(a[k], NC);
+            d2[k] = dv[k] * dv[k];
+        }
+        chi = 1.0 / s_last;
+        if (minpiv < kPivResolve) ill = true;
+    }
+    if (!ill) {
+        tau = NC > 0 ? choose_tau_grp<GS>(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f) : 0.0;
+        den = s_last;
+#pragma unroll
+        for (int k = 0; k < NC; k++) {
+            const double tm = tau * A.mu[k];
+            tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
+            den += d2[k] * tf[k];
+        }
+        if (!(den > kDenResolve)) ill = true;
+    }
+    if (ill) {
+        if (r == 0) {
+            const int slot = atomicAdd(A.rs_count, 1);
+            A.rs_list[slot] = (int32_t)j;
+        }
+        return;
+    }
+    const double rho = grp_bcast<GS>(a[NC], NC);
+    if (r > NC && r < NC + 1 + F) {
+        double num = rho * a[NC];
+#pragma unroll
+        for (int k = 0; k < NC; k++) num += dv[k] * a[k] * tf[k];
+        A.out[(int64_t)(A.f0 + r - NC - 1) * MQ + j] = num / den;
+    }
+    if (r == 0 && A.write_diag) {
+        A.chi[j] = chi;
+        A.tau[j] = tau;
+        A.status[j] = rst | (tau > 0.0 ? HAMLS_ST_REGULARIZED : 0);
+    }
+}
+
+// One node per group of GS lanes: the packed Gram matrices gram[j][E]
+// (E = m(m+1)/2 + m, one field) of an assembly pass that stopped before the
+// solve, and its neighbour counts.
+template <int m, int GS>
+__global__ __launch_bounds__(64) void k_mls_solve(const double* __restrict__ gram, SolveArgs A) {
+    constexpr int NG = 64 / GS;
+    constexpr int E = m * (m + 1) / 2 + m;
+    __shared__ double gl[NG * E];
+    const int g = threadIdx.x / GS, r = threadIdx.x % GS;
+    const int64_t j = (int64_t)blockIdx.x * NG + g;
+    const bool live = j < A.MQ;
+    for (int e = r; e < E; e += GS) gl[g * E + e] = live ? gram[j * E + e] : 0.0;
+    __syncthreads();
+    if (live) mls_solve_group<m, GS>(gl + g * E, A.nj[j], j, A);
+}
+
 // Re-solve of a node flagged by mls_solve_epilogue, from its Gram matrix and
 // right-hand sides accumulated in double-double precision (Gh + Gl, same
 // packing as the FP64 entries).  The same steps in double-double: the

@@ -823,7 +823,7 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
 // fetched 64*U per step (U record loads per lane in flight); member rows of
 // (sqrt(w) g, sqrt(w) y) are staged in LDS 64 at a time and each lane owns a
 // few entries, summed over the staged rows.  FM bounds the fields of one pass.
-template <int K, int FM, bool DD>
+template <int K, int FM, bool DD, bool SPLIT = false>
 __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Geom& g, const double* __restrict__ vals,
                                                    int F, int wendland,
                                                    const double* __restrict__ thr,
@@ -966,6 +966,16 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
         return;
     }
     if (lane == 0) nj[j] = count;
+    if (SPLIT) {
+        // the solve runs in its own kernel, several nodes per wave: hand on
+        // the packed Gram matrix and right-hand side (one field)
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            int e = lane + 64 * k;
+            if (e < E) entries_out[(int64_t)j * E + e] = acc[k];
+        }
+        return;
+    }
     double* Gs = rows;
 #pragma unroll
     for (int k = 0; k < KE; k++) {
@@ -977,7 +987,7 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
 }
 
 
-template <int K, int FM, bool DD, bool LIST>
+template <int K, int FM, bool DD, bool LIST, bool SPLIT = false>
 __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __restrict__ vals,
                                                    int F, int wendland,
                                                    const double* __restrict__ thr,
@@ -1001,7 +1011,8 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
             __syncthreads();
         }
     } else {
-        s2_node<K, FM, DD>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+        s2_node<K, FM, DD, SPLIT>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj,
+                                  entries_out);
     }
 }
 
@@ -1394,11 +1405,16 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_value
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
+    // one field: the assembly hands the Gram matrices to a solve kernel that
+    // takes 64 / 16 = 4 nodes per wave (m + 1 <= 16 for K <= 4)
 #define HAMLS_ASM(KK)                                                                             \
-    if (F == 1)                                                                                   \
-        hipLaunchKernelGGL((k_s2_assemble<KK, 1, false, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
-                           P.d_delta, A, P.d_nj, P.d_entries);                                    \
-    else                                                                                          \
+    if (F == 1) {                                                                                 \
+        constexpr int mm = (KK + 1) * (KK + 2) / 2;                                               \
+        hipLaunchKernelGGL((k_s2_assemble<KK, 1, false, false, true>), grid, block, 0, s, g, P.d_vals, F, wl, \
+                           P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);                           \
+        hipLaunchKernelGGL((k_mls_solve<mm, 16>), dim3((unsigned)((P.MQ + 3) / 4)), block, 0, s,   \
+                           (const double*)P.d_entries, A);                                        \
+    } else                                                                                        \
         hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, false, false>), grid, block, 0, s, g, P.d_vals, \
                            F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
     switch (P.K) {
