@@ -560,7 +560,7 @@ __device__ __forceinline__ void monomials3(const double* u, double s, double* ro
 // right-hand-side entries (every lane reads valid row positions, so the
 // accumulation has no branches); the entries then go to LDS for the solve
 // epilogue (normalisation, Cholesky in registers, tau, c_1).
-template <int D, int K, int FM, bool DD>
+template <int D, int K, int FM, bool DD, bool SPLIT = false>
 __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const GridGeom& g, const double* __restrict__ vals, int F,
                                                 int wendland, const double* __restrict__ thr,
                                                 const double* __restrict__ delta, const SolveArgs& A,
@@ -662,6 +662,16 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
         return;
     }
     if (lane == 0) nj[j] = count;
+    if (SPLIT) {
+        // the solve runs in its own kernel, several nodes per wave: hand on
+        // the packed Gram matrix and right-hand side (one field)
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            int e = lane + 64 * k;
+            if (e < E) entries_out[(int64_t)j * E + e] = acc[k];
+        }
+        return;
+    }
     double* Gs = rows;
 #pragma unroll
     for (int k = 0; k < KE; k++) {
@@ -673,7 +683,7 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
 }
 
 
-template <int D, int K, int FM, bool DD>
+template <int D, int K, int FM, bool DD, bool SPLIT = false>
 __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __restrict__ vals, int F,
                                                 int wendland, const double* __restrict__ thr,
                                                 const double* __restrict__ delta, SolveArgs A,
@@ -695,28 +705,44 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
             __syncthreads();
         }
     } else {
-        grid_node<D, K, FM, DD>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+        grid_node<D, K, FM, DD, SPLIT>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta,
+                                       A, nj, entries_out);
     }
+}
+
+// One field with m + 1 <= 16 (K <= 2): the assembly hands the Gram matrices
+// to a solve kernel that takes four nodes per wave.  K = 3 (m = 20) solves in
+// place: handing on 230 entries a node costs more than it saves.
+template <int D, int K>
+static void grid_mls_launch(const Plan& P, const GridGeom& g, const SolveArgs& A, int F, int wl, hipStream_t s) {
+    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
+    const dim3 grid((unsigned)P.MQ), block(64);
+    if constexpr (m + 1 <= 16) {
+        if (F == 1) {
+            hipLaunchKernelGGL((k_grid_mls<D, K, 1, false, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr,
+                               P.d_delta, A, P.d_nj, P.d_entries);
+            hipLaunchKernelGGL((k_mls_solve<m, 16>), dim3((unsigned)((P.MQ + 3) / 4)), block, 0, s,
+                               (const double*)P.d_entries, A);
+            return;
+        }
+    }
+    if (F == 1)
+        hipLaunchKernelGGL((k_grid_mls<D, K, 1, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta,
+                           A, P.d_nj, P.d_entries);
+    else
+        hipLaunchKernelGGL((k_grid_mls<D, K, kMaxFieldsPerPass, false>), grid, block, 0, s, g, P.d_vals, F, wl,
+                           P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
 }
 
 hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
     GridGeom g = make_grid_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
-#define HAMLS_GMLS(DDIM, KK)                                                                       \
-    if (F == 1)                                                                                  \
-        hipLaunchKernelGGL((k_grid_mls<DDIM, KK, 1, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
-                           P.d_delta, A, P.d_nj, P.d_entries);                                   \
-    else                                                                                         \
-        hipLaunchKernelGGL((k_grid_mls<DDIM, KK, kMaxFieldsPerPass, false>), grid, block, 0, s, g, P.d_vals, \
-                           F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
-#define HAMLS_GMLS_D(KK)     \
-    if (P.dom == HAMLS_SO3) { \
-        HAMLS_GMLS(4, KK)     \
-    } else {                  \
-        HAMLS_GMLS(3, KK)     \
-    }
+#define HAMLS_GMLS_D(KK)                                \
+    if (P.dom == HAMLS_SO3)                             \
+        grid_mls_launch<4, KK>(P, g, A, F, wl, s);      \
+    else                                                \
+        grid_mls_launch<3, KK>(P, g, A, F, wl, s);
     switch (P.K) {
         case 0: HAMLS_GMLS_D(0) break;
         case 1: HAMLS_GMLS_D(1) break;
@@ -725,7 +751,6 @@ hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, 
         default: set_error("degree %d unsupported on SO(3)/T3", P.K); return HAMLS_ERR_UNSUPPORTED;
     }
 #undef HAMLS_GMLS_D
-#undef HAMLS_GMLS
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
