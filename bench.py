@@ -40,7 +40,7 @@ def pct(a, q):
 
 # kernel (name prefix) of each phase's main launch, for the counter summary
 PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble<",
-                "solve": None, "ring_dft": "k_s2_ring_dft", "contract": "k_s2_legendre",
+                "solve": "k_mls_solve<", "ring_dft": "k_s2_ring_dft", "contract": "k_s2_legendre",
                 "gather": "k_gather_values"}
 
 WORKLOADS = {
@@ -89,7 +89,9 @@ def measured_traffic(kernel):
     if info.get("source_sha256") != source_sha256():
         return None
     for name, k in kern.items():
-        if name.startswith(kernel) and "true" not in name:
+        # the FP64 pass, not the double-double re-solve (third template argument)
+        targs = name[name.index("<") + 1:].rstrip(">").split(", ") if "<" in name else []
+        if name.startswith(kernel) and not (len(targs) > 2 and targs[2] == "true"):
             return float(k["bytes"])
     return None
 

@@ -182,6 +182,10 @@ struct SolveArgs {
 
 
 SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values);
+// one-field FP64 passes whose assembly hands its Gram matrices to a separate
+// solve kernel, and that kernel
+bool split_solve(const Plan& P, int F);
+hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 
 // --- kernels (kernels.hip) -------------------------------------------------
 hamls_status launch_s2_keys(const Plan& P, const double* nodes, int64_t M, hipStream_t s);

@@ -506,10 +506,39 @@ __device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int
 // ---- the same solve for a group of GS lanes (GS = 16 or 32: 64 / GS nodes
 // per wave; GS = 64 is mls_solve_epilogue) ---------------------------------
 
-// The value of x on lane k of this lane's group.
+// Lane K of each row of 16 lanes, to the whole row (DPP row_newbcast).
+template <int K>
+__device__ __forceinline__ double row_bcast(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + K, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + K, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The value of x on lane k of this lane's group (k a constant after
+// unrolling: the switch folds to one broadcast).
 template <int GS>
 __device__ __forceinline__ double grp_bcast(double x, int k) {
     if (GS == 64) return readlane_f64(x, k);
+    if (GS == 16) {
+        switch (k) {
+            case 0: return row_bcast<0>(x);
+            case 1: return row_bcast<1>(x);
+            case 2: return row_bcast<2>(x);
+            case 3: return row_bcast<3>(x);
+            case 4: return row_bcast<4>(x);
+            case 5: return row_bcast<5>(x);
+            case 6: return row_bcast<6>(x);
+            case 7: return row_bcast<7>(x);
+            case 8: return row_bcast<8>(x);
+            case 9: return row_bcast<9>(x);
+            case 10: return row_bcast<10>(x);
+            case 11: return row_bcast<11>(x);
+            case 12: return row_bcast<12>(x);
+            case 13: return row_bcast<13>(x);
+            case 14: return row_bcast<14>(x);
+            default: return row_bcast<15>(x);
+        }
+    }
     return __shfl(x, (int)((threadIdx.x & 63) & ~(GS - 1)) + k, 64);
 }
 

@@ -711,7 +711,7 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
 }
 
 // One field with m + 1 <= 16 (K <= 2): the assembly hands the Gram matrices
-// to a solve kernel that takes four nodes per wave.  K = 3 (m = 20) solves in
+// to launch_split_solve (four nodes per wave).  K = 3 (m = 20) solves in
 // place: handing on 230 entries a node costs more than it saves.
 template <int D, int K>
 static void grid_mls_launch(const Plan& P, const GridGeom& g, const SolveArgs& A, int F, int wl, hipStream_t s) {
@@ -721,8 +721,6 @@ static void grid_mls_launch(const Plan& P, const GridGeom& g, const SolveArgs& A
         if (F == 1) {
             hipLaunchKernelGGL((k_grid_mls<D, K, 1, false, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr,
                                P.d_delta, A, P.d_nj, P.d_entries);
-            hipLaunchKernelGGL((k_mls_solve<m, 16>), dim3((unsigned)((P.MQ + 3) / 4)), block, 0, s,
-                               (const double*)P.d_entries, A);
             return;
         }
     }

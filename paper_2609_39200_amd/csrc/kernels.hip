@@ -1405,16 +1405,12 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_value
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
-    // one field: the assembly hands the Gram matrices to a solve kernel that
-    // takes 64 / 16 = 4 nodes per wave (m + 1 <= 16 for K <= 4)
+    // one field: the assembly hands the Gram matrices to launch_split_solve
 #define HAMLS_ASM(KK)                                                                             \
-    if (F == 1) {                                                                                 \
-        constexpr int mm = (KK + 1) * (KK + 2) / 2;                                               \
+    if (F == 1)                                                                                   \
         hipLaunchKernelGGL((k_s2_assemble<KK, 1, false, false, true>), grid, block, 0, s, g, P.d_vals, F, wl, \
                            P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);                           \
-        hipLaunchKernelGGL((k_mls_solve<mm, 16>), dim3((unsigned)((P.MQ + 3) / 4)), block, 0, s,   \
-                           (const double*)P.d_entries, A);                                        \
-    } else                                                                                        \
+    else                                                                                          \
         hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, false, false>), grid, block, 0, s, g, P.d_vals, \
                            F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
     switch (P.K) {
@@ -1433,6 +1429,32 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_value
 // ---------------------------------------------------------------------------
 // local solve (eq. (15)-(23))
 // ---------------------------------------------------------------------------
+// The solve of an assembly pass that handed on its Gram matrices (one field,
+// FP64; S2 any degree, SO3/T3 m + 1 <= 16): four nodes per wave.  Nothing to
+// do for the other passes, which solve in place.
+bool split_solve(const Plan& P, int F) {
+    if (F != 1 || P.prm.precision != HAMLS_FP64) return false;
+    return P.dom == HAMLS_S2 || P.m + 1 <= 16;
+}
+
+hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+    if (!split_solve(P, F)) return HAMLS_OK;
+    SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    const dim3 grid((unsigned)((P.MQ + 3) / 4)), block(64);
+    const double* G = P.d_entries;
+    switch (P.m) {
+        case 1: hipLaunchKernelGGL((k_mls_solve<1, 16>), grid, block, 0, s, G, A); break;
+        case 3: hipLaunchKernelGGL((k_mls_solve<3, 16>), grid, block, 0, s, G, A); break;
+        case 4: hipLaunchKernelGGL((k_mls_solve<4, 16>), grid, block, 0, s, G, A); break;
+        case 6: hipLaunchKernelGGL((k_mls_solve<6, 16>), grid, block, 0, s, G, A); break;
+        case 10: hipLaunchKernelGGL((k_mls_solve<10, 16>), grid, block, 0, s, G, A); break;
+        case 15: hipLaunchKernelGGL((k_mls_solve<15, 16>), grid, block, 0, s, G, A); break;
+        default: set_error("no split solve for m = %d", P.m); return HAMLS_ERR_UNSUPPORTED;
+    }
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
 
 SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     SolveArgs A;

@@ -698,8 +698,9 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
             PhaseTimer pt(*P, HAMLS_PHASE_GATHER, s);
             HAMLS_TRY(launch_gather_values(*P, values, Fc, f0, ld, s));
         }
-        // assembly and the normal-matrix solve are fused; the double-double re-solve of
-        // the flagged centres is the solve phase
+        // assembly (for one FP64 field the solve runs in its own kernel, in the
+        // solve phase; otherwise fused with the assembly), then the double-double
+        // re-solve of the flagged centres
         {
             PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
             if (P->dom == HAMLS_S2 && P->prm.precision == HAMLS_MIXED)
@@ -709,6 +710,7 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
                                              : launch_grid_mls(*P, Fc, f0, grid_values, s));
         }
         PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
+        HAMLS_TRY(launch_split_solve(*P, Fc, f0, grid_values, s));
         HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_resolve(*P, Fc, f0, grid_values, s)
                                      : launch_grid_resolve(*P, Fc, f0, grid_values, s));
     }
