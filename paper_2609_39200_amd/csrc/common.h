@@ -25,7 +25,8 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
 constexpr int kMaxFieldsPerPass = 16;  // fields handled by one assembly pass
 constexpr int kRadixTile = 1024;       // keys per block of a radix sort pass
-constexpr int kCandCap = 1024;         // LDS candidate buffer of the radius search
+constexpr int kCandCap = 512;          // LDS candidate buffer of the radius search
+constexpr int kListCap = 128;          // S2 member list of a grid node (radius -> assembly)
 constexpr int kResolveBlocks = 131072; // blocks of the double-double re-solve (grid-stride)
 
 void set_error(const char* fmt, ...);
@@ -103,6 +104,8 @@ struct Plan {
     uint8_t* d_status = nullptr;    // MQ (radius flags, then solve flags)
     uint8_t* d_rstatus = nullptr;   // MQ radius flags kept across solves
     int32_t* d_nj = nullptr;        // MQ
+    int32_t* d_mlist = nullptr;     // S2 adaptive radius: MQ x kListCap member records
+    int32_t* d_mcnt = nullptr;      // MQ: member count, or -1 (the assembly scans)
     double* d_chi = nullptr;        // MQ
     double* d_tau = nullptr;        // MQ
     double* d_entries = nullptr;    // n_entries x MQ

@@ -36,6 +36,8 @@ struct S2Geom {
     int64_t cap;
     const int32_t* band_off; // nb + 1
     const int32_t* cs;       // cell_start
+    const int32_t* mlist;    // member lists of the radius search (kListCap per node) or null
+    const int32_t* mcnt;     // their lengths, -1 where the assembly scans the cap
     int nb;
     double dtheta;
 };
@@ -282,6 +284,24 @@ __device__ __forceinline__ void s2_scan(const S2Geom& g, double thq, double cq, 
             body(valid, idx);
         }
         __syncthreads();
+    }
+}
+
+// Visits the records of a member list (n entries), 64*U per step, with the
+// calling convention of s2_scan.
+template <int U, class Fn>
+__device__ __forceinline__ void s2_list_scan(const int32_t* list, int n, Fn&& body) {
+    const int lane = threadIdx.x & 63;
+    for (int base = 0; base < n; base += 64 * U) {
+        bool valid[U];
+        int idx[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int sl = base + 64 * u + lane;
+            valid[u] = sl < n;
+            idx[u] = valid[u] ? list[sl] : 0;
+        }
+        body(valid, idx);
     }
 }
 
@@ -543,6 +563,8 @@ S2Geom make_geom(const Plan& P) {
     g.cap = P.cap;
     g.band_off = P.d_band_off;
     g.cs = P.d_cell_start;
+    g.mlist = P.d_mlist;
+    g.mcnt = P.d_mcnt;
     g.nb = P.bins.nb;
     g.dtheta = P.bins.dtheta;
     return g;
@@ -564,10 +586,12 @@ S2Geom make_geom(const Plan& P) {
 // clamped to pi/2 (the tangent projection needs delta < pi/2).
 __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
                                                  double delta0, double c_fixed, double* thr,
-                                                 double* delta, uint8_t* rstatus) {
+                                                 double* delta, uint8_t* rstatus, int32_t* mlist,
+                                                 int32_t* mcnt) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
     __shared__ __align__(16) double buf[kCandCap];
+    __shared__ int ibuf[kCandCap];  // record of each kept key
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
@@ -668,6 +692,8 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
         double uh = 0.0;  // 1 - cos of a cap known to overflow the buffer
         double tn = -2.0, ktop = 2.0;
         bool done = false, hemi = false;
+        int lcount = -1;  // kept keys of the final scan when it kept them all
+        double lcr = 2.0;
         int* hist = (int*)binbuf;  // 256 ints
         for (int it = 0; it < 40 && !done; it++) {
             r = acos(cr);
@@ -707,6 +733,7 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
                     if (in) {
                         if (pos < kCandCap) {
                             buf[pos] = d[u];
+                            ibuf[pos] = idx[u];
                         } else {
                             int bin = (int)((1.0 - d[u] - ulo) * hs);
                             atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
@@ -747,6 +774,10 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
             } else if (count <= kCandCap) {
                 tn = nth_largest(buf, count, knn - above, cr, fmin(ktop, 1.0), sh, binbuf, kBinCap);
                 done = true;
+                if (ktop >= 2.0) {
+                    lcount = count;  // every key above cos r is kept
+                    lcr = cr;
+                }
             } else {
                 // bin in the histogram of every key of (cos r, ktop)
                 for (int a = lane; a < kCandCap; a += 64) {
@@ -795,6 +826,25 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
             }
             c = cos(dl);
         }
+        // member list for the assembly: when the final scan kept every key of
+        // a cap that holds the support (c >= cos r), the members are its kept
+        // keys above c, in scan order
+        if (mcnt) {
+            int nm = -1;
+            if (lcount >= 0 && c >= lcr && !(st & HAMLS_ST_HEMISPHERE)) {
+                nm = 0;
+                for (int base = 0; base < lcount; base += 64) {
+                    const int a = base + lane;
+                    const bool in = a < lcount && buf[a] > c;
+                    const uint64_t mk = __ballot(in);
+                    const int pos = nm + rank_below(mk);
+                    if (in && pos < kListCap) mlist[(int64_t)j * kListCap + pos] = ibuf[a];
+                    nm += __popcll(mk);
+                }
+                if (nm > kListCap) nm = -1;
+            }
+            if (lane == 0) mcnt[j] = nm;
+        }
     }
     if (lane == 0) {
         thr[j] = c;
@@ -809,7 +859,7 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
     double cf = d0 > 0.0 ? cos(d0) : 2.0;
     int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
     hipLaunchKernelGGL(k_s2_radius, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
-                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus);
+                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -872,7 +922,7 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
         }
     }
     int count = 0;
-    s2_scan<U>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
+    auto body = [&](const bool* valid, const int* idx) {
         double x0[U], x1[U], x2[U], d[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -948,7 +998,14 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
             __syncthreads();
             count += nin;
         }
-    });
+    };
+    // the members from the radius search's list where it left one, else a
+    // scan of the cap's cell cover
+    const int nl = (!DD && g.mcnt) ? g.mcnt[j] : -1;
+    if (nl >= 0)
+        s2_list_scan<U>(g.mlist + (int64_t)j * kListCap, nl, body);
+    else
+        s2_scan<U>(g, thq, ct, stt, phq, dl, sh, body);
     if (DD) {
         double* Gh = rows;
         double* Gl = rows + EG + m * FM;

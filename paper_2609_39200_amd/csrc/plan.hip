@@ -544,6 +544,10 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     HAMLS_TRY(dalloc(P, &P.d_ring_cs, 2 * (size_t)nt));
     HAMLS_TRY(dalloc(P, &P.d_col_cs, 2 * (size_t)np));
     HAMLS_TRY(dalloc(P, &P.d_band_off, P.bins.nb + 1));
+    if (P.prm.knn_count > 0) {
+        HAMLS_TRY(dalloc(P, &P.d_mlist, (size_t)kListCap * P.MQ));
+        HAMLS_TRY(dalloc(P, &P.d_mcnt, P.MQ));
+    }
 
     // step-3 tables: Legendre table of the northern rings with the GL weights
     // folded in, and the ring twiddles
