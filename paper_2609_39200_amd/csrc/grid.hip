@@ -27,6 +27,8 @@ struct GridGeom {
     const int32_t* perm; // sorted record -> original node
     int64_t cap;
     const int32_t* cs;   // cell_start
+    const int32_t* mlist;  // member lists of the radius search (kListCap per node) or null
+    const int32_t* mcnt;   // their lengths, -1 where the assembly scans the box
 };
 
 GridGeom make_grid_geom(const Plan& P) {
@@ -43,6 +45,8 @@ GridGeom make_grid_geom(const Plan& P) {
     g.perm = P.d_perm;
     g.cap = P.cap;
     g.cs = P.d_cell_start;
+    g.mlist = P.d_mlist;
+    g.mcnt = P.d_mcnt;
     return g;
 }
 
@@ -214,6 +218,24 @@ __device__ __forceinline__ void grid_scan(const GridGeom& g, const double* q, do
     }
 }
 
+// Visits the records of a member list (n entries), 64*U per step, with the
+// calling convention of grid_scan.
+template <int U, class Fn>
+__device__ __forceinline__ void grid_list_scan(const int32_t* list, int n, Fn&& body) {
+    const int lane = threadIdx.x & 63;
+    for (int base = 0; base < n; base += 64 * U) {
+        bool valid[U];
+        int idx[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int sl = base + 64 * u + lane;
+            valid[u] = sl < n;
+            idx[u] = valid[u] ? list[sl] : 0;
+        }
+        body(valid, idx);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------
@@ -293,10 +315,11 @@ hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double*
 template <int D>
 __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int knn, double eps,
                                                    double delta0, double* thr, double* delta,
-                                                   uint8_t* rstatus) {
+                                                   uint8_t* rstatus, int32_t* mlist, int32_t* mcnt) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
     __shared__ __align__(16) double buf[kCandCap];
+    __shared__ int ibuf[kCandCap];  // record of each kept key
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
@@ -345,6 +368,8 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
         double r_hi = 0.0;  // half-width of a box known to overflow the buffer
         double tn = -1e300, ktop = 2.0;
         bool done = false, hemi = false;
+        int lcount = -1;  // kept keys of the final scan when it kept them all
+        double lkr = 2.0;
         int* hist = (int*)binbuf;  // 256 ints
         for (int it = 0; it < 40 && !done; it++) {
             const double kr = grid_key_of_rho<D>(rho);
@@ -378,6 +403,7 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                     if (in) {
                         if (pos < kCandCap) {
                             buf[pos] = kv[u];
+                            ibuf[pos] = idx[u];
                         } else {
                             int bin = (int)((khi - kv[u] - ulo) * hs);
                             atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
@@ -417,6 +443,10 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
             } else if (count <= kCandCap) {
                 tn = nth_largest(buf, count, knn - above, kr, fmin(ktop, khi), sh, binbuf, kBinCap);
                 done = true;
+                if (ktop >= 2.0) {
+                    lcount = count;  // every key above key(r) is kept
+                    lkr = kr;
+                }
             } else {
                 // bin in the histogram of every key of (key(r), ktop)
                 for (int a = lane; a < kCandCap; a += 64) {
@@ -452,9 +482,15 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
             }
             tn = from_ordered_bits(lo);
         }
+        double tv;  // key threshold of the support
         if (D == 4) {
             double dk = hemi ? kPi : (1.0 + eps) * (2.0 * acos(fmin(1.0, fmax(-1.0, tn))));
             if (!(delta0 > 0.0 && delta0 > dk)) dl = dk;
+            if (dl >= kPi) {
+                dl = kPi;
+                st |= HAMLS_ST_HEMISPHERE;
+            }
+            tv = cos(0.5 * dl);
         } else {
             // T3: the threshold is (1+eps)^2 d_n^2 on d^2; a fixed radius wins
             // when it is larger than the adaptive one
@@ -468,13 +504,33 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                 dl = delta0;
                 cc = delta0 * delta0;
             }
-            if (lane == 0) {
-                thr[j] = -cc;
-                delta[j] = dl;
-                rstatus[j] = st;
-            }
-            return;
+            tv = -cc;
         }
+        // member list for the assembly: when the final scan kept every key of
+        // a ball that holds the support (tv >= key(r)), the members are its
+        // kept keys above tv, in scan order
+        if (mcnt) {
+            int nm = -1;
+            if (lcount >= 0 && tv >= lkr && !(st & HAMLS_ST_HEMISPHERE)) {
+                nm = 0;
+                for (int base = 0; base < lcount; base += 64) {
+                    const int a = base + lane;
+                    const bool in = a < lcount && buf[a] > tv;
+                    const uint64_t mk = __ballot(in);
+                    const int pos = nm + rank_below(mk);
+                    if (in && pos < kListCap) mlist[(int64_t)j * kListCap + pos] = ibuf[a];
+                    nm += __popcll(mk);
+                }
+                if (nm > kListCap) nm = -1;
+            }
+            if (lane == 0) mcnt[j] = nm;
+        }
+        if (lane == 0) {
+            thr[j] = tv;
+            delta[j] = dl;
+            rstatus[j] = st;
+        }
+        return;
     }
     if (D == 4) {
         if (dl >= kPi) {
@@ -500,7 +556,7 @@ hamls_status launch_grid_radius(const Plan& P, hipStream_t s) {
     int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
     auto kern = P.dom == HAMLS_SO3 ? k_grid_radius<4> : k_grid_radius<3>;
     hipLaunchKernelGGL(kern, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn, P.prm.knn_eps,
-                       d0, P.d_thr, P.d_delta, P.d_rstatus);
+                       d0, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -603,7 +659,7 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
         }
     }
     int count = 0;
-    grid_scan<D, U>(g, q, grid_rho<D>(g, dl), sh, [&](const bool* valid, const int* idx) {
+    auto body = [&](const bool* valid, const int* idx) {
         double kv[U], y1[U];
         // field values loaded with the coordinates, for every record of the
         // cover (one round trip less than loading the members')
@@ -644,7 +700,14 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
             __syncthreads();
             count += nin;
         }
-    });
+    };
+    // the members from the radius search's list where it left one, else a
+    // scan of the ball's box cover
+    const int nl = (!DD && g.mcnt) ? g.mcnt[j] : -1;
+    if (nl >= 0)
+        grid_list_scan<U>(g.mlist + (int64_t)j * kListCap, nl, body);
+    else
+        grid_scan<D, U>(g, q, grid_rho<D>(g, dl), sh, body);
     if (DD) {
         double* Gh = rows;
         double* Gl = rows + EG + m * FM;

@@ -390,6 +390,11 @@ static hamls_status alloc_common(Plan& P, int dimx) {
     HAMLS_TRY(dalloc(P, &P.d_status, P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_rstatus, P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_nj, P.MQ));
+    if (P.prm.knn_count > 0) {
+        // member lists handed from the adaptive-radius search to the assembly
+        HAMLS_TRY(dalloc(P, &P.d_mlist, (size_t)kListCap * P.MQ));
+        HAMLS_TRY(dalloc(P, &P.d_mcnt, P.MQ));
+    }
     HAMLS_TRY(dalloc(P, &P.d_chi, P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_tau, P.MQ));
     int EG = P.m * (P.m + 1) / 2;
@@ -544,10 +549,6 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     HAMLS_TRY(dalloc(P, &P.d_ring_cs, 2 * (size_t)nt));
     HAMLS_TRY(dalloc(P, &P.d_col_cs, 2 * (size_t)np));
     HAMLS_TRY(dalloc(P, &P.d_band_off, P.bins.nb + 1));
-    if (P.prm.knn_count > 0) {
-        HAMLS_TRY(dalloc(P, &P.d_mlist, (size_t)kListCap * P.MQ));
-        HAMLS_TRY(dalloc(P, &P.d_mcnt, P.MQ));
-    }
 
     // step-3 tables: Legendre table of the northern rings with the GL weights
     // folded in, and the ring twiddles
