@@ -314,8 +314,9 @@ hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double*
 // radius wins).  Thresholds are stored on the key: SO3 c, T3 -c.
 template <int D>
 __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int knn, double eps,
-                                                   double delta0, double* thr, double* delta,
-                                                   uint8_t* rstatus, int32_t* mlist, int32_t* mcnt) {
+                                                   double wfac, double delta0, double* thr,
+                                                   double* delta, uint8_t* rstatus, int32_t* mlist,
+                                                   int32_t* mcnt) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
     __shared__ __align__(16) double buf[kCandCap];
@@ -428,7 +429,9 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                     if (have + nout >= knn) {
                         int before;
                         const int B = hist_select_bin(ohist, have, knn, before);
-                        if (B < 255) nr = grid_rho_of_key<D>(khi - u0 * (1.0 + 15.0 * (B + 1) / 256.0));
+                        // widened by wfac = 1.005 (1 + eps) so that the scan also
+                        // holds the support and can hand on its members
+                        if (B < 255) nr = grid_rho_of_key<D>(khi - u0 * (1.0 + 15.0 * (B + 1) / 256.0)) * wfac;
                     }
                     if (nr <= rho) {
                         double grow = 1.15 * cbrt((double)knn / (double)(have > 0 ? have : 1));
@@ -556,7 +559,8 @@ hamls_status launch_grid_radius(const Plan& P, hipStream_t s) {
     int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
     auto kern = P.dom == HAMLS_SO3 ? k_grid_radius<4> : k_grid_radius<3>;
     hipLaunchKernelGGL(kern, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn, P.prm.knn_eps,
-                       d0, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt);
+                       1.005 * (1.0 + P.prm.knn_eps), d0, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist,
+                       P.d_mcnt);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
