@@ -220,8 +220,9 @@ def main():
             # 16 B (key + index, read + write); cell table; gather: index and
             # coordinates read, coordinates and permutation written
             "binning": Mn * 8 * dimx + nrec * (8 + 2 * 16 + 8 + 2 * (4 + rec)),
-            # every candidate record read once, radius writes
-            "radius": pairs * rec + MQ * 17,
+            # every member record read once; radius, threshold, status, list
+            # length and the member lists written
+            "radius": pairs * (rec + 4) + MQ * 21,
             "solve": MQ * (8 * (m * (m + 1) // 2 + m * F) + 4 + 8 * F + 17),
             "gather": nrec * (4 + 16 * F),
         }
