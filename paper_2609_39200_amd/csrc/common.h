@@ -27,7 +27,16 @@ constexpr int kMaxFieldsPerPass = 16;  // fields handled by one assembly pass
 constexpr int kRadixTile = 1024;       // keys per block of a radix sort pass
 constexpr int kCandCap = 512;          // LDS candidate buffer of the radius search
 constexpr int kListCap = 128;          // S2 member list of a grid node (radius -> assembly)
-constexpr int kResolveBlocks = 131072; // blocks of the double-double re-solve (grid-stride)
+constexpr int kResolveBlocks = 131072; // most blocks of a list kernel (grid-stride)
+
+// Blocks of a list kernel over at most MQ nodes: one per listed node up to
+// kResolveBlocks, but no more than max(MQ / 4, 8192), so that a short or empty
+// list does not pay for launching a block per grid node.
+inline unsigned list_blocks(int64_t MQ) {
+    int64_t b = MQ / 4 > 8192 ? MQ / 4 : 8192;
+    b = b < MQ ? b : MQ;
+    return (unsigned)(b < kResolveBlocks ? b : kResolveBlocks);
+}
 
 void set_error(const char* fmt, ...);
 hamls_status hip_status(hipError_t e, const char* what);

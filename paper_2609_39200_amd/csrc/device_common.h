@@ -473,11 +473,16 @@ __device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int
     if (!ill) {
         tau = NC > 0 ? choose_tau(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f) : 0.0;
         den = s_last;
+        if (tau > 0.0) {
 #pragma unroll
-        for (int k = 0; k < NC; k++) {
-            const double tm = tau * A.mu[k];
-            tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
-            den += d2[k] * tf[k];
+            for (int k = 0; k < NC; k++) {
+                const double tm = tau * A.mu[k];
+                tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
+                den += d2[k] * tf[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC; k++) tf[k] = 0.0;
         }
         if (!(den > kDenResolve)) ill = true;
     }
@@ -698,11 +703,16 @@ __device__ void mls_solve_group(const double* Gs, int count, int64_t j, const So
     if (!ill) {
         tau = NC > 0 ? choose_tau_grp<GS>(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f) : 0.0;
         den = s_last;
+        if (tau > 0.0) {
 #pragma unroll
-        for (int k = 0; k < NC; k++) {
-            const double tm = tau * A.mu[k];
-            tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
-            den += d2[k] * tf[k];
+            for (int k = 0; k < NC; k++) {
+                const double tm = tau * A.mu[k];
+                tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
+                den += d2[k] * tf[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC; k++) tf[k] = 0.0;
         }
         if (!(den > kDenResolve)) ill = true;
     }

@@ -826,7 +826,7 @@ hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_valu
     if (P.m <= 1) return HAMLS_OK;
     GridGeom g = make_grid_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    dim3 grid((unsigned)(P.MQ < kResolveBlocks ? P.MQ : kResolveBlocks)), block(64);
+    dim3 grid(list_blocks(P.MQ)), block(64);
     int wl = P.prm.wendland;
 #define HAMLS_GDD(DDIM, KK)                                                                          \
     if (F == 1)                                                                                      \

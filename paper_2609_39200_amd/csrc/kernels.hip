@@ -1430,7 +1430,7 @@ hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, 
     B.in_list = P.d_mx_list;
     B.in_count = P.d_rs_count + 1;
     dim3 grid((unsigned)P.MQ), block(64);
-    dim3 lgrid((unsigned)(P.MQ < kResolveBlocks ? P.MQ : kResolveBlocks));
+    dim3 lgrid(list_blocks(P.MQ));
     int wl = P.prm.wendland;
 #define HAMLS_MIX(KK)                                                                                  \
     if (F == 1) {                                                                                      \
@@ -1555,7 +1555,7 @@ hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values
     if (P.m <= 1) return HAMLS_OK;
     S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    dim3 grid((unsigned)(P.MQ < kResolveBlocks ? P.MQ : kResolveBlocks)), block(64);
+    dim3 grid(list_blocks(P.MQ)), block(64);
     int wl = P.prm.wendland;
 #define HAMLS_DDS(KK)                                                                                 \
     if (F == 1)                                                                                       \
