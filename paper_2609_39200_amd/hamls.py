@@ -272,7 +272,7 @@ def params_from_workload(wp: dict, **over) -> hamls_params:
     """hamls_params from a workloads.Workload.params dict (plus overrides)."""
     kw = dict(domain=wp["domain"], bandwidth=wp["bandwidth"], degree=wp["degree"],
               support_radius=float(wp.get("support_radius", 0.0)), knn_count=int(wp.get("knn_count", 0)),
-              knn_eps=float(wp.get("knn_eps", 0.05)) or 0.05, reg=wp.get("reg", "chi"),
+              knn_eps=float(wp.get("knn_eps", 0.05)), reg=wp.get("reg", "chi"),
               tau_fixed=float(wp.get("tau_fixed", 0.0)), chi_target=float(wp.get("chi_target", 10.0)),
               chi_full=float(wp.get("chi_full", 20.0)), grid_shape=tuple(wp.get("grid_shape", (0, 0, 0))))
     kw.update(over)

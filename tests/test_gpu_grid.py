@@ -206,6 +206,23 @@ def test_t3_degrees(H, K):
     _check(H, wl, label=f"t3-K{K}")
 
 
+@pytest.mark.parametrize("knn,eps", [(20, 0.01), (100, 0.3)])
+def test_t3_member_lists_and_scan_fallback(H, knn, eps):
+    # member lists (at most 128) from the radius search, or the box scan when
+    # the support holds more (n = 100, eps = 0.3: ~220 members)
+    wl = W.t3_clusters(seed=5230 + knn, M=12000, N=5, K=2, grid=10, kmax=5)
+    wl.params["knn_count"] = knn
+    wl.params["knn_eps"] = eps
+    _check(H, wl, label=f"t3 lists n={knn} eps={eps}")
+
+
+def test_so3_member_lists_scan_fallback(H):
+    wl = W.so3_clusters(seed=5140, M=15000, N=6, K=1, grid=(0, 0, 0), field_degree=5)
+    wl.params["knn_count"] = 110
+    wl.params["knn_eps"] = 0.3
+    _check(H, wl, label="so3 lists fallback")
+
+
 def test_t3_fixed_radius_weights_fields(H):
     rng = np.random.default_rng(52)
     x = W.clustered_torus(10000, rng)

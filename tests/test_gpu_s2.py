@@ -172,6 +172,16 @@ def test_degrees_knn(H, K):
     _check_against_oracle(H, wl, label=f"K{K}")
 
 
+@pytest.mark.parametrize("knn,eps", [(30, 0.01), (120, 0.25)])
+def test_member_lists_and_scan_fallback(H, knn, eps):
+    # the radius search hands each node its members (at most 128) when its
+    # final scan holds the support; n = 120 with eps = 0.25 gives ~190
+    # members, so every node falls back to scanning its cap in the assembly
+    wl = W.s2_clusters(seed=2250 + knn, M=15000, N=20, K=3, n_caps=3, field_degree=30, knn=knn)
+    wl.params["knn_eps"] = eps
+    _check_against_oracle(H, wl, label=f"lists n={knn} eps={eps}")
+
+
 def test_multi_field_and_weights(H):
     import torch
 
