@@ -707,7 +707,7 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
     };
     // the members from the radius search's list where it left one, else a
     // scan of the ball's box cover
-    const int nl = (!DD && g.mcnt) ? g.mcnt[j] : -1;
+    const int nl = g.mcnt ? g.mcnt[j] : -1;
     if (nl >= 0)
         grid_list_scan<U>(g.mlist + (int64_t)j * kListCap, nl, body);
     else

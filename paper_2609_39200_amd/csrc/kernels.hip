@@ -305,6 +305,18 @@ __device__ __forceinline__ void s2_list_scan(const int32_t* list, int n, Fn&& bo
     }
 }
 
+// The members of grid node j: the radius search's list where it left one,
+// else a scan of the cap's cell cover (body sees every record of the cover).
+template <int U, class Fn>
+__device__ __forceinline__ void s2_members(const S2Geom& g, int j, double thq, double cq, double sq,
+                                           double phq, double r, int* sh, Fn&& body) {
+    const int nl = g.mcnt ? g.mcnt[j] : -1;
+    if (nl >= 0)
+        s2_list_scan<U>(g.mlist + (int64_t)j * kListCap, nl, body);
+    else
+        s2_scan<U>(g, thq, cq, sq, phq, r, sh, body);
+}
+
 // ---------------------------------------------------------------------------
 // binning
 // ---------------------------------------------------------------------------
@@ -999,13 +1011,7 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
             count += nin;
         }
     };
-    // the members from the radius search's list where it left one, else a
-    // scan of the cap's cell cover
-    const int nl = (!DD && g.mcnt) ? g.mcnt[j] : -1;
-    if (nl >= 0)
-        s2_list_scan<U>(g.mlist + (int64_t)j * kListCap, nl, body);
-    else
-        s2_scan<U>(g, thq, ct, stt, phq, dl, sh, body);
+    s2_members<U>(g, j, thq, ct, stt, phq, dl, sh, body);
     if (DD) {
         double* Gh = rows;
         double* Gl = rows + EG + m * FM;
@@ -1177,7 +1183,7 @@ __device__ __forceinline__ void s2_mixed_node(int j, double* lds, int* sh, const
     };
     // ---------------- pass 1: FP32 Gram
     int count = 0;
-    s2_scan<U>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
+    s2_members<U>(g, j, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
@@ -1344,7 +1350,7 @@ __device__ __forceinline__ void s2_mixed_node(int j, double* lds, int* sh, const
         gf[k] = e < m * F ? m + e % F : m;
         gacc[k] = 0.0;
     }
-    s2_scan<U>(g, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
+    s2_members<U>(g, j, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
 #pragma unroll
         for (int u = 0; u < U; u++) {
             double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
