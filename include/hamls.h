@@ -189,6 +189,10 @@ hamls_status hamls_diagnostics(hamls_plan_t plan, int32_t* n, double* chi, doubl
 #define HAMLS_PHASE_GATHER 6    /* value gather into sorted order */
 #define HAMLS_NUM_PHASES 7
 hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable);
+/* Restricts the timing to the phases whose bit (1 << phase) is set in mask
+ * (every phase by default): events are recorded around those phases only,
+ * since each event pair costs a few microseconds of GPU time. */
+hamls_status hamls_timing_phases(hamls_plan_t plan, uint32_t mask);
 hamls_status hamls_timing_read(hamls_plan_t plan, int32_t phase, int64_t* launches,
                                double* total_ms);
 

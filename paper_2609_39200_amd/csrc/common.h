@@ -147,6 +147,7 @@ struct Plan {
 
     // per-phase timing
     bool timing = false;
+    uint32_t timing_mask = ~0u;  // phases timed while timing is on (bit 1 << phase)
     struct Rec {
         int phase;
         hipEvent_t a, b;

@@ -39,7 +39,7 @@ static hipEvent_t take_event(Plan& P) {
 }
 
 PhaseTimer::PhaseTimer(Plan& P, int phase, hipStream_t s) : P_(P), phase_(phase), s_(s) {
-    if (!P_.timing) return;
+    if (!P_.timing || !((P_.timing_mask >> phase) & 1u)) return;
     b_ = take_event(P_);
     if (b_) (void)hipEventRecord(b_, s_);
 }
@@ -955,6 +955,16 @@ hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable) {
         return HAMLS_ERR_INVALID_ARG;
     }
     P->timing = enable != 0;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_timing_phases(hamls_plan_t plan, uint32_t mask) {
+    Plan* P = (Plan*)plan;
+    if (!P) {
+        set_error("null plan");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    P->timing_mask = mask;
     return HAMLS_OK;
 }
 

@@ -90,6 +90,7 @@ _SIGS = {
     "hamls_plan_radii": [_vp, _vp, _vp],
     "hamls_diagnostics": [_vp, _vp, _vp, _vp, _vp],
     "hamls_timing_enable": [_vp, _i32],
+    "hamls_timing_phases": [_vp, C.c_uint32],
     "hamls_timing_read": [_vp, _i32, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
@@ -249,6 +250,12 @@ PHASES = {"binning": 0, "radius": 1, "assemble": 2, "solve": 3, "ring_dft": 4, "
 
 def hamls_timing_enable(plan: int, enable: bool = True):
     _check(_lib.hamls_timing_enable(C.c_void_p(plan), int(bool(enable))), "hamls_timing_enable")
+
+
+def hamls_timing_phases(plan: int, phases=None):
+    """Time only the named phases (all when None)."""
+    mask = 0xFFFFFFFF if phases is None else sum(1 << (PHASES[p] if isinstance(p, str) else int(p)) for p in phases)
+    _check(_lib.hamls_timing_phases(C.c_void_p(plan), C.c_uint32(mask)), "hamls_timing_phases")
 
 
 def hamls_timing_read(plan: int, phase) -> tuple:
