@@ -510,10 +510,30 @@ __global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__
     cs[c] = (int32_t)lower_bound_key(keys, br[0], br[1], c);
 }
 
+// S2 cell table from the key boundaries: position i starts the cells
+// keys[i-1]+1 .. keys[i] (cells before the first key start at 0, cells after
+// the last at n); every cell is written once.  S2 cells along a band are few
+// between two records, so the loops stay short (the 4-D SO3 grid is mostly
+// empty and keeps the per-cell search).
+__global__ __launch_bounds__(256) void k_cell_start_bounds(const uint32_t* __restrict__ keys, int64_t n,
+                                                           int64_t ncells, int32_t* __restrict__ cs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const int64_t lo = i == 0 ? 0 : (int64_t)keys[i - 1] + 1;
+    const int64_t hi = i == n ? ncells : (int64_t)keys[i];
+    for (int64_t c = lo; c <= hi; c++) cs[c] = (int32_t)i;
+}
+
 hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t M, hipStream_t s) {
-    int64_t nbk = (P.ncells + 1 + 255) / 256;
-    hipLaunchKernelGGL(k_cell_start, dim3((unsigned)nbk), dim3(256), 0, s, keys, M, P.ncells,
-                       P.d_cell_start);
+    if (P.dom == HAMLS_S2) {
+        const int64_t nbk = (M + 1 + 255) / 256;
+        hipLaunchKernelGGL(k_cell_start_bounds, dim3((unsigned)nbk), dim3(256), 0, s, keys, M, P.ncells,
+                           P.d_cell_start);
+    } else {
+        const int64_t nbk = (P.ncells + 1 + 255) / 256;
+        hipLaunchKernelGGL(k_cell_start, dim3((unsigned)nbk), dim3(256), 0, s, keys, M, P.ncells,
+                           P.d_cell_start);
+    }
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -898,6 +918,17 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
     constexpr int KE = (EG + m * FM + 63) / 64;
     constexpr int U = FM == 1 ? 2 : 1;
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
+    // One FP64 field: lanes own 2x2 blocks of the upper triangle of the Gram
+    // matrix of [V | y] (PB column pairs, NB blocks), and GB groups of lanes
+    // take interleaved members: two 16-byte LDS reads feed four FMAs, and GB
+    // members share each instruction.  The groups' partial sums are added in
+    // group order at the end.
+    constexpr int PB = (m + 2) / 2;
+    constexpr int NB = PB * (PB + 1) / 2;
+    constexpr int GB = 64 / NB > 8 ? 8 : 64 / NB;
+    constexpr bool BLK = FM == 1 && !DD && GB >= 1;
+    constexpr int RS = BLK ? 2 * PB : ROW;  // LDS row stride
+    static_assert(!BLK || (RS <= ROW && RS % 2 == 0 && m * (m + 1) / 2 + 2 * m <= 64 * ROW - GB * NB * 4), "blocked LDS");
     const int lane = threadIdx.x;
     const int t = j / g.nphi, p = j - t * g.nphi;
     const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
@@ -933,6 +964,17 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
             cb[k] = m + r % F;
         }
     }
+    const int grp = lane / NB, blk = lane - (lane / NB) * NB;
+    int bI = 0, bJ = 0;
+    {
+        int rem = blk;
+        while (rem >= PB - bI) {
+            rem -= PB - bI;
+            bI++;
+        }
+        bJ = bI + rem;
+    }
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
     int count = 0;
     auto body = [&](const bool* valid, const int* idx) {
         double x0[U], x1[U], x2[U], d[U];
@@ -984,7 +1026,8 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
                     pu[a] = pu[a - 1] * uu;
                     pv[a] = pv[a - 1] * vv;
                 }
-                double* row = rows + rank_below(mk) * ROW;
+                double* row = rows + rank_below(mk) * RS;
+                if (BLK && RS > m + 1) row[m + 1] = 0.0;
                 int cidx = 0;
 #pragma unroll
                 for (int l = 0; l <= K; l++)
@@ -996,15 +1039,28 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
                     for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
             }
             __syncthreads();
+            if (BLK) {
+                if (grp < GB) {
+                    for (int r = grp; r < nin; r += GB) {
+                        const double2 x = *(const double2*)(rows + r * RS + 2 * bI);
+                        const double2 y = *(const double2*)(rows + r * RS + 2 * bJ);
+                        a4[0] = fma(x.x, y.x, a4[0]);
+                        a4[1] = fma(x.x, y.y, a4[1]);
+                        a4[2] = fma(x.y, y.x, a4[2]);
+                        a4[3] = fma(x.y, y.y, a4[3]);
+                    }
+                }
+            } else {
 #pragma unroll 2
-            for (int r = 0; r < nin; r++) {
-                const double* row = rows + r * ROW;
+                for (int r = 0; r < nin; r++) {
+                    const double* row = rows + r * ROW;
 #pragma unroll
-                for (int k = 0; k < KE; k++) {
-                    if (DD)
-                        dd_acc(accd[k], row[ca[k]], row[cb[k]]);
-                    else
-                        acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                    for (int k = 0; k < KE; k++) {
+                        if (DD)
+                            dd_acc(accd[k], row[ca[k]], row[cb[k]]);
+                        else
+                            acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                    }
                 }
             }
             __syncthreads();
@@ -1029,6 +1085,38 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
         return;
     }
     if (lane == 0) nj[j] = count;
+    if (BLK) {
+        // sum the groups' blocks (lanes < NB), then each block's entries of
+        // the upper triangle go to their packed places (y.y is not needed)
+        double* part = rows + 64 * ROW - GB * NB * 4;
+        if (grp < GB) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) part[(grp * NB + blk) * 4 + q] = a4[q];
+        }
+        __syncthreads();
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (lane < NB) {
+            for (int g2 = 0; g2 < GB; g2++) {
+#pragma unroll
+                for (int q = 0; q < 4; q++) s4[q] += part[(g2 * NB + lane) * 4 + q];
+            }
+        }
+        double* dst = SPLIT ? entries_out + (int64_t)j * E : rows;
+        if (lane < NB) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int a = 2 * bI + (q >> 1), b = 2 * bJ + (q & 1);
+                if (a <= b && b <= m && a < m) {
+                    const int e = b < m ? a * m - a * (a - 1) / 2 + (b - a) : EG + a;
+                    dst[e] = s4[q];
+                }
+            }
+        }
+        if (SPLIT) return;
+        __syncthreads();
+        mls_solve_epilogue<m>(rows, rows + EG + m * FM, count, F, j, A, entries_out);
+        return;
+    }
     if (SPLIT) {
         // the solve runs in its own kernel, several nodes per wave: hand on
         // the packed Gram matrix and right-hand side (one field)
@@ -1063,7 +1151,7 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
     constexpr int KE = (EG + m * FM + 63) / 64;
     constexpr int U = FM == 1 ? 2 : 1;
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
-    __shared__ double rows[64 * ROW];
+    __shared__ __align__(16) double rows[64 * ROW];
     __shared__ int sh[kScanLds];
     if (LIST) {
         // a list of nodes (the re-solve list, or the FP64 list of the mixed
