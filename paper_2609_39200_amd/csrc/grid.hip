@@ -632,6 +632,14 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
     constexpr int KE = (EG + m * FM + 63) / 64;
     constexpr int U = FM == 1 ? 2 : 1;
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
+    // One FP64 field with at most 64 2x2 blocks (K <= 2): blocked Gram
+    // accumulation with interleaved member groups, as on S2
+    constexpr int PB = (m + 2) / 2;
+    constexpr int NB = PB * (PB + 1) / 2;
+    constexpr int GB = 64 / NB > 8 ? 8 : 64 / NB;
+    constexpr bool BLK = FM == 1 && !DD && GB >= 1;
+    constexpr int RS = BLK ? 2 * PB : ROW;  // LDS row stride
+    static_assert(!BLK || (RS <= ROW && RS % 2 == 0 && EG + 2 * m <= 64 * ROW - GB * NB * 4), "blocked LDS");
     const int lane = threadIdx.x;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -662,6 +670,17 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
             cb[k] = m + r % F;
         }
     }
+    const int grp = lane / NB, blk = lane - (lane / NB) * NB;
+    int bI = 0, bJ = 0;
+    {
+        int rem = blk;
+        while (rem >= PB - bI) {
+            rem -= PB - bI;
+            bI++;
+        }
+        bJ = bI + rem;
+    }
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
     int count = 0;
     auto body = [&](const bool* valid, const int* idx) {
         double kv[U], y1[U];
@@ -682,7 +701,8 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
                 double uu[3], w;
                 grid_local<D>(g, i, q, kv[u], dl, wendland, uu, w);
                 const double sw = sqrt(w);
-                double* row = rows + rank_below(mk) * ROW;
+                double* row = rows + rank_below(mk) * RS;
+                if (BLK && RS > m + 1) row[m + 1] = 0.0;
                 monomials3<K>(uu, sw, row);
                 if (FM == 1)
                     row[m] = sw * y1[u];
@@ -690,15 +710,28 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
                     for (int f = 0; f < F; f++) row[m + f] = sw * vals[(int64_t)f * g.cap + i];
             }
             __syncthreads();
+            if (BLK) {
+                if (grp < GB) {
+                    for (int r = grp; r < nin; r += GB) {
+                        const double2 x = *(const double2*)(rows + r * RS + 2 * bI);
+                        const double2 y = *(const double2*)(rows + r * RS + 2 * bJ);
+                        a4[0] = fma(x.x, y.x, a4[0]);
+                        a4[1] = fma(x.x, y.y, a4[1]);
+                        a4[2] = fma(x.y, y.x, a4[2]);
+                        a4[3] = fma(x.y, y.y, a4[3]);
+                    }
+                }
+            } else {
 #pragma unroll 2
-            for (int r = 0; r < nin; r++) {
-                const double* row = rows + r * ROW;
+                for (int r = 0; r < nin; r++) {
+                    const double* row = rows + r * ROW;
 #pragma unroll
-                for (int k = 0; k < KE; k++) {
-                    if (DD)
-                        dd_acc(accd[k], row[ca[k]], row[cb[k]]);
-                    else
-                        acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                    for (int k = 0; k < KE; k++) {
+                        if (DD)
+                            dd_acc(accd[k], row[ca[k]], row[cb[k]]);
+                        else
+                            acc[k] = fma(row[ca[k]], row[cb[k]], acc[k]);
+                    }
                 }
             }
             __syncthreads();
@@ -729,6 +762,38 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
         return;
     }
     if (lane == 0) nj[j] = count;
+    if (BLK) {
+        // sum the groups' blocks (lanes < NB), then each block's entries of
+        // the upper triangle go to their packed places (y.y is not needed)
+        double* part = rows + 64 * ROW - GB * NB * 4;
+        if (grp < GB) {
+#pragma unroll
+            for (int qq = 0; qq < 4; qq++) part[(grp * NB + blk) * 4 + qq] = a4[qq];
+        }
+        __syncthreads();
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (lane < NB) {
+            for (int g2 = 0; g2 < GB; g2++) {
+#pragma unroll
+                for (int qq = 0; qq < 4; qq++) s4[qq] += part[(g2 * NB + lane) * 4 + qq];
+            }
+        }
+        double* dst = SPLIT ? entries_out + (int64_t)j * E : rows;
+        if (lane < NB) {
+#pragma unroll
+            for (int qq = 0; qq < 4; qq++) {
+                const int a = 2 * bI + (qq >> 1), b = 2 * bJ + (qq & 1);
+                if (a <= b && b <= m && a < m) {
+                    const int e = b < m ? a * m - a * (a - 1) / 2 + (b - a) : EG + a;
+                    dst[e] = s4[qq];
+                }
+            }
+        }
+        if (SPLIT) return;
+        __syncthreads();
+        mls_solve_epilogue<m>(rows, rows + EG + m * FM, count, F, j, A, entries_out);
+        return;
+    }
     if (SPLIT) {
         // the solve runs in its own kernel, several nodes per wave: hand on
         // the packed Gram matrix and right-hand side (one field)
@@ -762,7 +827,7 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
     constexpr int KE = (EG + m * FM + 63) / 64;
     constexpr int U = FM == 1 ? 2 : 1;
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
-    __shared__ double rows[64 * ROW];
+    __shared__ __align__(16) double rows[64 * ROW];
     __shared__ int sh[kScanLds];
     if (DD) {
         // the re-solve list: a grid-stride loop over the listed nodes
