@@ -824,8 +824,6 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
     constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
     constexpr int EG = m * (m + 1) / 2;
     constexpr int ROW = m + FM + 1;
-    constexpr int KE = (EG + m * FM + 63) / 64;
-    constexpr int U = FM == 1 ? 2 : 1;
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
     __shared__ __align__(16) double rows[64 * ROW];
     __shared__ int sh[kScanLds];

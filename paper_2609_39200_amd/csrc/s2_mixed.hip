@@ -79,7 +79,6 @@ __global__ __launch_bounds__(64) void k_s2_legendre_mfma(const float* __restrict
     f32x4 acc[NCT];
 #pragma unroll
     for (int c = 0; c < NCT; c++) acc[c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 4
     for (int t0 = 0; t0 < th_pad; t0 += 4) {
         const float a = A[(int64_t)(t0 + kk) * R_pad + row];
 #pragma unroll
