@@ -39,7 +39,7 @@ struct S2Geom {
     const int32_t* mlist;    // member lists of the radius search (kListCap per node) or null
     const int32_t* mcnt;     // their lengths, -1 where the assembly scans the cap
     int nb;
-    double dtheta;
+    double dtheta, idtheta;  // band height and its reciprocal
 };
 
 // Geometry of the cell cover of a geodesic cap (thq, phq, r): the bands it
@@ -55,8 +55,8 @@ __device__ __forceinline__ CapGeo cap_geo(const S2Geom& g, double thq, double cq
     const double margin = 1e-7;
     CapGeo G;
     double rr = r + margin;
-    int b0 = (int)floor((thq - rr) / g.dtheta);
-    int b1 = (int)floor((thq + rr) / g.dtheta);
+    int b0 = (int)floor((thq - rr) * g.idtheta);
+    int b1 = (int)floor((thq + rr) * g.idtheta);
     G.b0 = b0 < 0 ? 0 : b0;
     G.b1 = b1 > g.nb - 1 ? g.nb - 1 : b1;
     const bool north = thq - rr <= 0.0, south = thq + rr >= kPi;
@@ -105,9 +105,9 @@ __device__ __forceinline__ void band_sectors(const S2Geom& g, const CapGeo& G, i
     sc = 0;
     sd = -1;
     if (!fullb) {
-        double wdt = 2.0 * kPi / ns;
-        int s0 = (int)floor((phq - dphi) / wdt);
-        int s1 = (int)floor((phq + dphi) / wdt);
+        const double spr = ns * (0.5 / kPi);  // sectors per radian
+        int s0 = (int)floor((phq - dphi) * spr);
+        int s1 = (int)floor((phq + dphi) * spr);
         if (s1 - s0 + 1 < ns) {
             if (s0 < 0) {
                 sa = s0 + ns;
@@ -599,6 +599,7 @@ S2Geom make_geom(const Plan& P) {
     g.mcnt = P.d_mcnt;
     g.nb = P.bins.nb;
     g.dtheta = P.bins.dtheta;
+    g.idtheta = 1.0 / P.bins.dtheta;
     return g;
 }
 
@@ -728,7 +729,10 @@ __global__ __launch_bounds__(64, 4) void k_s2_radius(S2Geom g, int64_t M, int kn
         double lcr = 2.0;
         int* hist = (int*)binbuf;  // 256 ints
         for (int it = 0; it < 40 && !done; it++) {
-            r = acos(cr);
+            // cap radius for the cover: an upper bound on arccos(cr) from
+            // u = 1 - cr, r = 2 asin(sqrt(u / 2)), in FP32 widened past its
+            // error (the cover only has to contain the cap)
+            r = (double)(2.0f * asinf(sqrtf((float)(0.5 * (1.0 - cr))))) * (1.0 + 4e-6) + 1e-7;
             const double ulo = ktop < 2.0 ? 1.0 - ktop : 0.0;
             const double hs = 256.0 / fmax((1.0 - cr) - ulo, 1e-300);
             const double u0 = 1.0 - cr, ohs = 256.0 / fmax(15.0 * u0, 1e-300);
