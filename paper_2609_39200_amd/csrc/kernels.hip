@@ -617,7 +617,7 @@ S2Geom make_geom(const Plan& P) {
 //     narrowed (duplicates), a bitwise binary search over the key instead.
 // delta = (1+eps) arccos(t_n), merged with a fixed delta_0 if both are set,
 // clamped to pi/2 (the tangent projection needs delta < pi/2).
-__global__ __launch_bounds__(64, 4) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
+__global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
                                                  double delta0, double c_fixed, double* thr,
                                                  double* delta, uint8_t* rstatus, int32_t* mlist,
                                                  int32_t* mcnt) {
