@@ -228,49 +228,13 @@ constexpr double kRankTol = 1e-11;
 // and the bracket shrinks to the sub-interval of the crossing, 65x per round;
 // 11 rounds resolve the root beyond 64 halvings.  mu is constant over the
 // monomials of one degree: one division per degree.
+template <int GS>
+__device__ __forceinline__ double choose_tau_grp(int reg, double chi, const double* d2, const double* mu,
+                                                 int n, double tau_fixed, double chi_t, double chi_f);
+
 __device__ __forceinline__ double choose_tau(int reg, double chi, const double* d2, const double* mu,
                                          int n, double tau_fixed, double chi_t, double chi_f) {
-    if (reg == HAMLS_REG_FIXED) return tau_fixed;
-    if (reg != HAMLS_REG_CHI_TARGET || !(chi > chi_t)) return 0.0;
-    const int lane = threadIdx.x & 63;
-    // one division per run of equal mu (mu is sorted by degree)
-    auto coupling = [&](double tau) {
-        double r = 0.0, cur = -1.0, inv = 0.0;
-        for (int j = 0; j < n; j++) {
-            if (mu[j] != cur) {
-                cur = mu[j];
-                inv = 1.0 / (1.0 + tau * cur);
-            }
-            r += d2[j] * inv;
-        }
-        return r;
-    };
-    const double target = 1.0 - 1.0 / chi_t;
-    // upper end: the first power of two 2^e with r <= target
-    double hi = 0.0;
-    for (int e0 = 0; e0 < 2048 && hi == 0.0; e0 += 64) {
-        const double t = ldexp(1.0, e0 + lane);
-        const uint64_t over = __ballot(coupling(t) > target);
-        if (over != ~0ull) hi = ldexp(1.0, e0 + __ffsll((unsigned long long)~over) - 1);
-    }
-    if (hi == 0.0) hi = ldexp(1.0, 2047);
-    double a = log(1e-16), b = log(hi);
-    for (int round = 0; round < 11; round++) {
-        const double step = (b - a) / 65.0;
-        const double x = a + step * (lane + 1);
-        const int cnt = __popcll(__ballot(coupling(exp(x)) > target));
-        const double na = cnt == 0 ? a : a + step * cnt;
-        const double nb = cnt == 64 ? b : a + step * (cnt + 1);
-        a = na;
-        b = nb;
-    }
-    double tt = (chi - chi_t) / (chi_f - chi_t);
-    double sm = 1.0;
-    if (tt < 1.0) {
-        double t4 = tt * tt * tt * tt;
-        sm = t4 * (35.0 - 84.0 * tt + 70.0 * tt * tt - 20.0 * tt * tt * tt);
-    }
-    return sm * exp(0.5 * (a + b));
+    return choose_tau_grp<64>(reg, chi, d2, mu, n, tau_fixed, chi_t, chi_f);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -583,8 +547,13 @@ __device__ __forceinline__ double choose_tau_grp(int reg, double chi, const doub
         if (over != all) hi = ldexp(1.0, e0 + __ffsll((unsigned long long)(~over & all)) - 1);
     }
     if (hi == 0.0) hi = ldexp(1.0, 2047);
+    // a few rounds of the group search narrow log tau to a relative width of
+    // ~1e-4 (65^3, 33^3 or 17^4 sub-intervals) with r_tau > target at the left
+    // end a; then Newton steps on tau from exp(a).  r_tau is convex and
+    // decreasing in tau, so the steps stay left of the root and rise to it
+    // monotonically (quadratic convergence: three steps reach rounding).
     double a = log(1e-16), b = log(hi);
-    constexpr int rounds = GS == 64 ? 11 : (GS == 32 ? 14 : 17);
+    constexpr int rounds = GS == 64 ? 3 : (GS == 32 ? 3 : 4);
     for (int round = 0; round < rounds; round++) {
         const double step = (b - a) / (GS + 1.0);
         const int cnt = __popcll(grp_ballot<GS>(coupling(exp(a + step * (r + 1))) > target));
@@ -593,13 +562,30 @@ __device__ __forceinline__ double choose_tau_grp(int reg, double chi, const doub
         a = na;
         b = nb;
     }
+    double t = exp(a);
+    const double tmax = exp(b);
+    for (int it = 0; it < 5; it++) {
+        double f = -target, fp = 0.0, cur = -1.0, inv = 0.0;
+        for (int q = 0; q < n; q++) {
+            if (mu[q] != cur) {
+                cur = mu[q];
+                inv = 1.0 / (1.0 + t * cur);
+            }
+            f += d2[q] * inv;
+            fp -= d2[q] * cur * inv * inv;
+        }
+        if (!(f > 0.0) || !(fp < 0.0)) break;
+        const double tn = fmin(t - f / fp, tmax);
+        if (!(tn > t)) break;
+        t = tn;
+    }
     const double tt = (chi - chi_t) / (chi_f - chi_t);
     double sm = 1.0;
     if (tt < 1.0) {
         const double t4 = tt * tt * tt * tt;
         sm = t4 * (35.0 - 84.0 * tt + 70.0 * tt * tt - 20.0 * tt * tt * tt);
     }
-    return sm * exp(0.5 * (a + b));
+    return sm * t;
 }
 
 // mls_solve_epilogue for one node per group of GS lanes (m + F <= GS), one
