@@ -113,7 +113,11 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["serve"],
+                    help="serve: the request loop (continuous batching) on the serving trace")
+    ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
+    ap.add_argument("--slots", type=int, default=4, help="serve: worker streams of the server")
     ap.add_argument("--fields", type=int, default=1,
                     help="fields per fit: the workload's field plus seeded N(0,1) node values")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
@@ -131,6 +135,10 @@ def main():
 
     from paper_2609_39200_amd import hamls as H
     from paper_2609_39200_amd import workloads as W
+
+    if args.workload == "serve":
+        print(json.dumps(serve_bench(args, H, W, torch)), flush=True)
+        return
 
     t_gen = time.time()
     builder, wl_desc = WORKLOADS[args.workload]
@@ -299,6 +307,123 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 8
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(args, H, W, torch):
+    """The serving trace through the request loop, then through the plain
+    one-request-at-a-time FP64 path (plan, step 2, step 3, destroy per
+    request) with the same arrivals.  Latency = completion - arrival."""
+    import threading
+
+    tr = W.serving_trace(n=args.requests, rate=args.rate)
+    n = len(tr.arrival)
+    dev = torch.device("cuda:0")
+    pools = [torch.as_tensor(x, dtype=torch.float64, device=dev).contiguous() for x in tr.pools]
+    fields = [torch.as_tensor(f, dtype=torch.float64, device=dev).contiguous() for f in tr.fields]
+    reqs = []
+    for i in range(n):
+        M, k = int(tr.M[i]), int(tr.pool[i])
+        p = H.params_from_workload(W.serving_params(tr.N[i], tr.K[i]))
+        cf = torch.empty((1, (int(tr.N[i]) + 1) ** 2, 2), dtype=torch.float64, device=dev)
+        reqs.append((p, pools[k][:M], fields[k][:M].view(1, M), cf))
+    torch.cuda.synchronize()
+
+    def summarize(lat, t_first, t_last):
+        lat = sorted(lat)
+        return {"fits_per_s": n / (t_last - t_first), "p50_ms": 1e3 * pct(lat, 50),
+                "p99_ms": 1e3 * pct(lat, 99), "makespan_s": t_last - t_first}
+
+    def serve(arrival):
+        """The request loop, starting with no resident plan."""
+        srv = H.hamls_server_create(args.slots, 0)
+        t0 = H.hamls_server_clock() + 0.05
+
+        def submitter():
+            for i, (p, x, v, cf) in enumerate(reqs):
+                dt = t0 + arrival[i] - H.hamls_server_clock()
+                if dt > 0:
+                    time.sleep(dt)
+                H.hamls_server_submit(srv, p, x, v, cf, tag=i)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        done = {}
+        while len(done) < n:
+            for c in H.hamls_server_wait(srv, 256, 1.0):
+                done[c["tag"]] = c
+        th.join()
+        _, committed, nplans = H.hamls_server_load(srv)
+        H.hamls_server_destroy(srv)
+        lat = [done[i]["t_done"] - (t0 + arrival[i]) for i in range(n)]
+        out = summarize(lat, t0, max(c["t_done"] for c in done.values()))
+        out["plans_reused"] = sum(c["plan_reused"] for c in done.values())
+        out["resident_plans_at_end"] = nplans
+        out["resident_bytes_at_end"] = committed
+        out["failed"] = sum(c["status"] != 0 for c in done.values())
+        return out
+
+    # all requests at once: the loop's capacity
+    burst = serve(np.zeros(n))
+    print(f"burst of {n} requests: {burst}", file=sys.stderr, flush=True)
+    # the trace's arrivals
+    served = serve(tr.arrival)
+    print(f"served {n} requests: {served}", file=sys.stderr, flush=True)
+    served_cf = [r[3].clone() for r in reqs]
+
+    # the plain path, one request at a time, same arrivals
+    stream = torch.cuda.current_stream()
+    t0 = H.hamls_server_clock()
+    lat = []
+    max_err = 0.0
+    for i, (p, x, v, cf) in enumerate(reqs):
+        dt = t0 + tr.arrival[i] - H.hamls_server_clock()
+        if dt > 0:
+            time.sleep(dt)
+        plan = H.hamls_plan(p, x, stream=stream)
+        info = H.hamls_plan_info_get(plan)
+        gv = torch.empty((1, info.num_grid), dtype=torch.float64, device=dev)
+        H.hamls_mls_to_grid(plan, v, gv, stream=stream)
+        H.hamls_grid_to_coeffs(plan, gv, cf, stream=stream)
+        torch.cuda.synchronize()
+        H.hamls_plan_destroy(plan)
+        lat.append(H.hamls_server_clock() - (t0 + tr.arrival[i]))
+        a, b = served_cf[i], cf
+        max_err = max(max_err, float(torch.linalg.norm(a - b) / torch.linalg.norm(b)))
+    seq = summarize(lat, t0, H.hamls_server_clock())
+    print(f"sequential: {seq}", file=sys.stderr, flush=True)
+
+    return {
+        "metric": "fits/s + p50/p99 latency, serving (continuous batching) vs the plain "
+                  "one-request-at-a-time FP64 path",
+        "value": served["fits_per_s"],
+        "unit": "fits/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": 0,
+        "ms_per_step": 1e3 * served["makespan_s"] / n,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"S2 serving trace: {n} requests, Poisson arrivals at {args.rate:g}/s, N uniform "
+                        f"in {{32,64,128,256}}, K uniform in {{2,3,4}}, M log-uniform in [1e4, 1e6] from "
+                        f"the cluster + hole generator, kNN n = 4m, chi-target regularization, F = 1",
+            "slots": args.slots,
+            "hbm_budget": "80% of free device memory",
+        },
+        "latency_ms": {"p50": served["p50_ms"], "p99": served["p99_ms"]},
+        "serving": served,
+        "serving_burst": burst,
+        "sequential_fp64": seq,
+        "vs_sequential": {"fits_per_s": served["fits_per_s"] / seq["fits_per_s"],
+                          "p99": served["p99_ms"] / seq["p99_ms"]},
+        "max_rel_l2_served_vs_sequential": max_err,
+        "timing": "host monotonic clock from each request's scheduled arrival to its completion; "
+                  "every run starts with no resident plan; serving_burst submits all requests at "
+                  "once (the loop's capacity)",
+    }
 
 
 def cpu_baseline(wl, plan, gv, H, budget_s):

@@ -154,6 +154,12 @@ hamls_status hamls_eval(hamls_plan_t plan, const double* coeffs, int32_t F, cons
 
 hamls_status hamls_plan_destroy(hamls_plan_t plan);
 
+/* Device bytes a plan of these parameters holds for M nodes after a
+ * hamls_grid_to_coeffs call with F fields: the sum of its allocations (the
+ * capacity of a serving-loop plan, below, counts as M).  Host only; no device
+ * call.  Errors: INVALID_ARG, NOT_EXACT_GRID, UNSUPPORTED as for hamls_plan. */
+hamls_status hamls_plan_footprint(const hamls_params* p, int64_t M, int32_t F, int64_t* bytes);
+
 /* ---- introspection (host outputs; these calls synchronize the stream) ---- */
 hamls_status hamls_plan_info_get(hamls_plan_t plan, hamls_plan_info* out);
 
@@ -195,6 +201,76 @@ hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable);
 hamls_status hamls_timing_phases(hamls_plan_t plan, uint32_t mask);
 hamls_status hamls_timing_read(hamls_plan_t plan, int32_t phase, int64_t* launches,
                                double* total_ms);
+
+/* ---- serving loop: continuous batching over resident plans ----
+ * The serving extension of Alg. 1: many independent fits (requests), each
+ * steps 2 and 3 (hamls_mls_to_grid then hamls_grid_to_coeffs) on its own
+ * nodes and parameters, arriving while others run.
+ *
+ * A server owns `slots` worker threads on the HIP device that is current at
+ * creation, each with its own stream (default priority), so the device work of
+ * up to `slots` requests overlaps.  Requests wait in arrival order; a free
+ * worker admits the oldest one as soon as its device footprint
+ * (hamls_plan_footprint at the plan's capacity, plus F x M_Q doubles of grid
+ * values) fits within hbm_budget next to the plans of running requests and
+ * the idle resident plans; idle plans are evicted, least recently used first,
+ * to make room.  A request whose parameters equal those of an idle resident
+ * plan with enough node capacity (at most four times what a new plan would
+ * get, since the cell grid follows a plan's first node set) rebinds it (hamls_plan_rebind: no allocation,
+ * no grid or table generation); otherwise a plan is built with its capacity
+ * rounded up to a power of two (at least 16384 nodes) and stays resident, with
+ * its Legendre / Wigner tables, after the request.  A request whose footprint
+ * alone exceeds the budget completes with OUT_OF_MEMORY.
+ *
+ * Inputs (nodes, weights, values) must be complete in device memory when the
+ * request is submitted (the workers' streams do not wait for other streams),
+ * and must stay valid and unchanged, and coeffs must not be read, until the
+ * request's completion is returned.  Results
+ * equal those of the plain one-request calls up to rounding of the summation
+ * order (a rebound plan keeps the cell grid of its first node set). */
+typedef struct hamls_request {
+    int32_t struct_size;         /* = sizeof(hamls_request) */
+    int32_t F;                   /* fields, 1 <= F <= 4096 */
+    hamls_params params;         /* as for hamls_plan */
+    const double* nodes;         /* device, as for hamls_plan */
+    const double* node_weights;  /* device, M, or NULL */
+    int64_t M;
+    const double* values;        /* device, F x M (ld = M) */
+    double* coeffs;              /* device, F x num_coeffs x 2 (as hamls_grid_to_coeffs) */
+    uint64_t tag;                /* returned with the completion */
+} hamls_request;
+
+typedef struct hamls_completion {
+    uint64_t tag;
+    int32_t status;       /* hamls_status of the request */
+    int32_t plan_reused;  /* 1: an idle resident plan was rebound */
+    double t_submit;      /* seconds on hamls_server_clock: queued */
+    double t_admit;       /* admitted by a worker */
+    double t_done;        /* coefficients complete in device memory */
+} hamls_completion;
+
+typedef struct hamls_server_s* hamls_server_t;
+
+/* slots in [1, 64]; hbm_budget in bytes, <= 0 for 80% of the device memory
+ * free at creation. */
+hamls_status hamls_server_create(int32_t slots, int64_t hbm_budget, hamls_server_t* out);
+/* Queue a request (copied; never blocks on the device).  INVALID_ARG for a
+ * malformed request (null pointers, F or M out of range); parameter errors
+ * come back in the completion. */
+hamls_status hamls_server_submit(hamls_server_t server, const hamls_request* request);
+/* Up to max completions, oldest first, into out; *count receives how many.
+ * Blocks until at least one is available or timeout_s seconds have passed
+ * (timeout_s <= 0: do not block). */
+hamls_status hamls_server_wait(hamls_server_t server, hamls_completion* out, int32_t max,
+                               int32_t* count, double timeout_s);
+/* Requests queued or running, and device bytes committed to plans. */
+hamls_status hamls_server_load(hamls_server_t server, int32_t* in_flight, int64_t* committed_bytes,
+                               int32_t* resident_plans);
+/* Finishes every queued request, then frees the plans, streams and threads.
+ * Completions not yet collected are discarded. */
+hamls_status hamls_server_destroy(hamls_server_t server);
+/* Monotonic clock (seconds) of the completion time stamps. */
+double hamls_server_clock(void);
 
 const char* hamls_status_string(hamls_status s);
 const char* hamls_last_error(void);

@@ -200,6 +200,13 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values);
 bool split_solve(const Plan& P, int F);
 hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 
+// Plan construction with a node capacity above the first bind, and the device
+// bytes such a plan holds after a coefficient pass of F fields.
+hamls_status plan_create(const hamls_params* p, const double* nodes, int64_t M, int64_t mcap,
+                         const double* node_weights, void* stream, hamls_plan_t* out);
+hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int32_t F,
+                            int64_t* bytes, int64_t* num_grid);
+
 // --- kernels (kernels.hip) -------------------------------------------------
 hamls_status launch_s2_keys(const Plan& P, const double* nodes, int64_t M, hipStream_t s);
 hamls_status radix_sort(Plan& P, int64_t n, hipStream_t s, int* final_buf);

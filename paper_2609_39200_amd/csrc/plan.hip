@@ -429,8 +429,8 @@ static void euler_quaternion(double a, double b, double g, double* q) {
 // SO3 and T3 plans: the product grid of Sec. 2.1 (SO3: Gauss-Legendre in
 // cos(beta) x trapezoid in alpha and gamma; T3: the equispaced periodic grid),
 // the cell grid, and the quadrature tables (axis twiddles; SO3 Wigner table).
-static hamls_status build_grid_plan(Plan& P, const double* nodes, int64_t M, const double* nu,
-                                    hipStream_t s) {
+static hamls_status build_grid_plan(Plan& P, const double* nodes, int64_t M, int64_t mcap,
+                                    const double* nu, hipStream_t s) {
     const bool so3 = P.dom == HAMLS_SO3;
     const int dimx = so3 ? 4 : 3;
     P.D = 3;
@@ -441,8 +441,8 @@ static hamls_status build_grid_plan(Plan& P, const double* nodes, int64_t M, con
         P.ncoef = (int64_t)(N + 1) * (2 * N + 1) * (2 * N + 3) / 3;
     else
         P.ncoef = (int64_t)P.dims[0] * P.dims[0] * P.dims[0];
-    P.mcap = M;
-    P.cap = so3 ? 2 * M : M;
+    P.mcap = mcap;
+    P.cap = so3 ? 2 * mcap : mcap;
     P.h_grid.resize((size_t)dimx * P.MQ);
     P.h_wts.resize(P.MQ);
     std::vector<double> tw0, tw1;
@@ -502,20 +502,20 @@ static hamls_status build_grid_plan(Plan& P, const double* nodes, int64_t M, con
 }
 
 static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nodes, int64_t M,
-                               const double* nu, hipStream_t s) {
+                               int64_t mcap, const double* nu, hipStream_t s) {
     P.prm = *p;
     HAMLS_HIP(hipGetDevice(&P.device));
     P.dom = p->domain;
     P.N = p->bandwidth;
     P.K = p->degree;
-    if (P.dom != HAMLS_S2) return build_grid_plan(P, nodes, M, nu, s);
+    if (P.dom != HAMLS_S2) return build_grid_plan(P, nodes, M, mcap, nu, s);
     P.D = 2;
     P.m = n_monomials(2, P.K);
     int nt = P.dims[0], np = P.dims[1];
     P.MQ = (int64_t)nt * np;
     P.ncoef = (int64_t)(P.N + 1) * (P.N + 1);
-    P.mcap = M;
-    P.cap = M;
+    P.mcap = mcap;
+    P.cap = mcap;
 
     // grid: GL in cos(theta) x trapezoid in phi
     gauss_legendre(nt, P.h_glx, P.h_glw);
@@ -610,6 +610,140 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     return bind_nodes(P, nodes, M, nu, s);
 }
 
+// A plan whose node buffers hold up to mcap >= M nodes (later rebinds up to
+// mcap allocate nothing); the binning geometry follows the first M.
+hamls_status plan_create(const hamls_params* p, const double* nodes, int64_t M, int64_t mcap,
+                         const double* node_weights, void* stream, hamls_plan_t* out) {
+    if (!out || !nodes) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    int32_t dims[3];
+    HAMLS_TRY(check_params(p, dims));
+    // sorted records are indexed by int32 (SO3 stores two per node)
+    const int64_t rec_max = (((int64_t)1 << 31) - 4096) / (p->domain == HAMLS_SO3 ? 2 : 1);
+    if (M < 1 || mcap < M || mcap > rec_max || (p->knn_count > 0 && M < p->knn_count)) {
+        set_error("node count %lld / capacity %lld invalid (need 1 <= M <= capacity <= %lld, "
+                  "M >= knn_count)", (long long)M, (long long)mcap, (long long)rec_max);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    Plan* P = new (std::nothrow) Plan();
+    if (!P) {
+        set_error("host allocation failed");
+        return HAMLS_ERR_OUT_OF_MEMORY;
+    }
+    memcpy(P->dims, dims, sizeof(dims));
+    hamls_status st = build_plan(*P, p, nodes, M, mcap, node_weights, (hipStream_t)stream);
+    if (st != HAMLS_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        free_plan(P);
+        return st;
+    }
+    *out = (hamls_plan_t)P;
+    return HAMLS_OK;
+}
+
+// Device bytes a plan of capacity mcap allocates (first bind M) once
+// hamls_grid_to_coeffs has run with F fields: the same sizes as the
+// allocations of alloc_common, build_plan / build_grid_plan and the
+// coefficient work buffers, each at least one element.
+hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int32_t F,
+                            int64_t* bytes, int64_t* num_grid) {
+    int32_t dims[3];
+    HAMLS_TRY(check_params(p, dims));
+    if (M < 1 || mcap < M || F < 1 || F > 4096) {
+        set_error("need 1 <= M <= capacity and 1 <= F <= 4096");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    Plan P;
+    P.prm = *p;
+    P.dom = p->domain;
+    P.N = p->bandwidth;
+    P.K = p->degree;
+    memcpy(P.dims, dims, sizeof(dims));
+    const bool s2 = P.dom == HAMLS_S2, so3 = P.dom == HAMLS_SO3;
+    const int dimx = so3 ? 4 : 3;
+    P.m = n_monomials(s2 ? 2 : 3, P.K);
+    P.MQ = (int64_t)dims[0] * dims[1] * (s2 ? 1 : dims[2]);
+    P.cap = so3 ? 2 * mcap : mcap;
+    if (s2)
+        s2_bins(P, M);
+    else
+        grid_bins(P, M);
+    int64_t b = 0;
+    auto add = [&b](int64_t count, int64_t elem) { b += elem * (count > 0 ? count : 1); };
+    const int64_t MQ = P.MQ, cap = P.cap;
+    add(dimx * MQ, 8);
+    add(dimx * cap, 8);
+    add(cap, 8);
+    for (int k = 0; k < 5; k++) add(cap, 4);  // perm, two key and two index buffers
+    add(256 * ((cap + kRadixTile - 1) / kRadixTile + 2), 4);
+    add(P.ncells + 1, 4);
+    add(MQ, 8);
+    add(MQ, 8);
+    add(MQ, 1);
+    add(MQ, 1);
+    add(MQ, 4);
+    if (p->knn_count > 0) {
+        add((int64_t)kListCap * MQ, 4);
+        add(MQ, 4);
+    }
+    add(MQ, 8);
+    add(MQ, 8);
+    add(((int64_t)P.m * (P.m + 1) / 2 + (int64_t)P.m * kMaxFieldsPerPass) * MQ, 8);
+    add(MQ, 4);
+    add(64, 4);
+    add(MQ, 4);
+    add((int64_t)kMaxFieldsPerPass * cap, 8);
+    const int N = P.N, K2 = 2 * N + 1;
+    if (s2) {
+        const int nt = dims[0], np = dims[1], th = (nt + 1) / 2;
+        const int64_t na = (int64_t)(N + 1) * (N + 2) / 2;
+        add(nt, 8);
+        add(np, 8);
+        add(2 * (int64_t)nt, 8);
+        add(2 * (int64_t)np, 8);
+        add(P.bins.nb + 1, 4);
+        add((int64_t)th * na, 8);
+        add(2 * (int64_t)np, 8);
+        add((int64_t)F * nt * (N + 1) * 2, 8);
+        if (p->precision == HAMLS_MIXED) {
+            const int th_pad = (th + 3) & ~3;
+            int64_t total = 0, items = 0;
+            for (int k = 0; k <= N; k++)
+                for (int q = 0; q < 2; q++) {
+                    const int R = N >= k + q ? (N - k - q) / 2 + 1 : 0;
+                    const int R_pad = (R + 15) & ~15;
+                    total += (int64_t)th_pad * R_pad;
+                    items += R_pad / 16;
+                }
+            add(total, 4);
+            add(2 * (int64_t)(N + 1), 8);
+            add(4 * items, 4);
+            const int64_t C_pad = ((2 * (int64_t)F + 15) / 16) * 16;
+            add((int64_t)(N + 1) * 2 * th_pad * C_pad, 4);
+        }
+    } else if (so3) {
+        const int nb = dims[0], na = dims[1], ng = dims[2];
+        const int64_t ncoef = (int64_t)(N + 1) * (2 * N + 1) * (2 * N + 3) / 3;
+        add(2 * (int64_t)na, 8);
+        add(2 * (int64_t)ng, 8);
+        add(nb, 8);
+        add(nb, 8);
+        add((int64_t)nb * ncoef, 8);
+        add((int64_t)F * nb * K2 * ng * 2, 8);
+        add((int64_t)F * nb * K2 * K2 * 2, 8);
+    } else {
+        add(2 * (int64_t)dims[0], 8);
+        add((int64_t)F * MQ * 2, 8);
+        add((int64_t)F * MQ * 2, 8);
+    }
+    *bytes = b;
+    if (num_grid) *num_grid = MQ;
+    return HAMLS_OK;
+}
+
 }  // namespace hamls
 
 using namespace hamls;
@@ -640,34 +774,15 @@ hamls_status hamls_params_init(hamls_params* p) {
 
 hamls_status hamls_plan(const hamls_params* p, const double* nodes, int64_t M,
                         const double* node_weights, void* stream, hamls_plan_t* out) {
-    if (!out || !nodes) {
+    return hamls::plan_create(p, nodes, M, M, node_weights, stream, out);
+}
+
+hamls_status hamls_plan_footprint(const hamls_params* p, int64_t M, int32_t F, int64_t* bytes) {
+    if (!bytes) {
         set_error("null argument");
         return HAMLS_ERR_INVALID_ARG;
     }
-    *out = nullptr;
-    int32_t dims[3];
-    HAMLS_TRY(check_params(p, dims));
-    // sorted records are indexed by int32 (SO3 stores two per node)
-    const int64_t rec_max = (((int64_t)1 << 31) - 4096) / (p->domain == HAMLS_SO3 ? 2 : 1);
-    if (M < 1 || M > rec_max || (p->knn_count > 0 && M < p->knn_count)) {
-        set_error("node count %lld invalid (need 1 <= M <= %lld, M >= knn_count)", (long long)M,
-                  (long long)rec_max);
-        return HAMLS_ERR_INVALID_ARG;
-    }
-    Plan* P = new (std::nothrow) Plan();
-    if (!P) {
-        set_error("host allocation failed");
-        return HAMLS_ERR_OUT_OF_MEMORY;
-    }
-    memcpy(P->dims, dims, sizeof(dims));
-    hamls_status st = build_plan(*P, p, nodes, M, node_weights, (hipStream_t)stream);
-    if (st != HAMLS_OK) {
-        (void)hipStreamSynchronize((hipStream_t)stream);
-        free_plan(P);
-        return st;
-    }
-    *out = (hamls_plan_t)P;
-    return HAMLS_OK;
+    return hamls::plan_footprint(p, M, M, F, bytes, nullptr);
 }
 
 hamls_status hamls_plan_rebind(hamls_plan_t plan, const double* nodes, int64_t M,

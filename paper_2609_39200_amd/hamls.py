@@ -73,6 +73,31 @@ class hamls_plan_info(C.Structure):
     ]
 
 
+class hamls_request(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_int32),
+        ("F", C.c_int32),
+        ("params", hamls_params),
+        ("nodes", C.c_void_p),
+        ("node_weights", C.c_void_p),
+        ("M", C.c_int64),
+        ("values", C.c_void_p),
+        ("coeffs", C.c_void_p),
+        ("tag", C.c_uint64),
+    ]
+
+
+class hamls_completion(C.Structure):
+    _fields_ = [
+        ("tag", C.c_uint64),
+        ("status", C.c_int32),
+        ("plan_reused", C.c_int32),
+        ("t_submit", C.c_double),
+        ("t_admit", C.c_double),
+        ("t_done", C.c_double),
+    ]
+
+
 _vp = C.c_void_p
 _i32, _i64 = C.c_int32, C.c_int64
 _P = C.POINTER
@@ -92,6 +117,12 @@ _SIGS = {
     "hamls_timing_enable": [_vp, _i32],
     "hamls_timing_phases": [_vp, C.c_uint32],
     "hamls_timing_read": [_vp, _i32, _vp, _vp],
+    "hamls_plan_footprint": [_P(hamls_params), _i64, _i32, _P(_i64)],
+    "hamls_server_create": [_i32, _i64, _P(_vp)],
+    "hamls_server_submit": [_vp, _P(hamls_request)],
+    "hamls_server_wait": [_vp, _P(hamls_completion), _i32, _P(_i32), C.c_double],
+    "hamls_server_load": [_vp, _P(_i32), _P(_i64), _P(_i32)],
+    "hamls_server_destroy": [_vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -99,6 +130,8 @@ for _name, _args in _SIGS.items():
     _f.restype = C.c_int
 _lib.hamls_status_string.argtypes = [C.c_int]
 _lib.hamls_status_string.restype = C.c_char_p
+_lib.hamls_server_clock.argtypes = []
+_lib.hamls_server_clock.restype = C.c_double
 _lib.hamls_last_error.argtypes = []
 _lib.hamls_last_error.restype = C.c_char_p
 
@@ -284,3 +317,59 @@ def params_from_workload(wp: dict, **over) -> hamls_params:
               chi_full=float(wp.get("chi_full", 20.0)), grid_shape=tuple(wp.get("grid_shape", (0, 0, 0))))
     kw.update(over)
     return hamls_params_init(**kw)
+
+
+def hamls_plan_footprint(params: hamls_params, M: int, F: int = 1) -> int:
+    out = C.c_int64(0)
+    _check(_lib.hamls_plan_footprint(C.byref(params), int(M), int(F), C.byref(out)), "hamls_plan_footprint")
+    return int(out.value)
+
+
+def hamls_server_create(slots: int = 4, hbm_budget: int = 0) -> int:
+    out = C.c_void_p()
+    _check(_lib.hamls_server_create(int(slots), int(hbm_budget), C.byref(out)), "hamls_server_create")
+    return out.value
+
+
+def hamls_server_submit(server: int, params: hamls_params, nodes, values, coeffs, node_weights=None,
+                        tag: int = 0):
+    """Queue one fit; the tensors must stay alive and unchanged until its completion."""
+    M = nodes.shape[0]
+    F = values.shape[0] if values.dim() == 2 else 1
+    r = hamls_request()
+    r.struct_size = C.sizeof(hamls_request)
+    r.F = F
+    r.params = params
+    r.nodes = _dev(nodes, "nodes").value
+    r.node_weights = None if node_weights is None else _dev(node_weights, "node_weights", (M,)).value
+    r.M = M
+    r.values = _dev(values, "values").value
+    r.coeffs = _dev(coeffs, "coeffs").value
+    r.tag = int(tag)
+    if values.numel() != F * M:
+        raise ValueError("values must hold F x M entries")
+    _check(_lib.hamls_server_submit(C.c_void_p(server), C.byref(r)), "hamls_server_submit")
+
+
+def hamls_server_wait(server: int, max_count: int = 64, timeout_s: float = 1.0) -> list:
+    """Completions as dicts (tag, status, plan_reused, t_submit, t_admit, t_done)."""
+    buf = (hamls_completion * max_count)()
+    n = C.c_int32(0)
+    _check(_lib.hamls_server_wait(C.c_void_p(server), buf, int(max_count), C.byref(n), float(timeout_s)),
+           "hamls_server_wait")
+    return [dict(tag=int(c.tag), status=int(c.status), plan_reused=bool(c.plan_reused), t_submit=c.t_submit,
+                 t_admit=c.t_admit, t_done=c.t_done) for c in buf[:n.value]]
+
+
+def hamls_server_load(server: int) -> tuple:
+    a, b, c = C.c_int32(0), C.c_int64(0), C.c_int32(0)
+    _check(_lib.hamls_server_load(C.c_void_p(server), C.byref(a), C.byref(b), C.byref(c)), "hamls_server_load")
+    return int(a.value), int(b.value), int(c.value)
+
+
+def hamls_server_destroy(server: int):
+    _check(_lib.hamls_server_destroy(C.c_void_p(server)), "hamls_server_destroy")
+
+
+def hamls_server_clock() -> float:
+    return float(_lib.hamls_server_clock())

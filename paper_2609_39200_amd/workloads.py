@@ -339,3 +339,53 @@ def t3_clusters(seed: int = 5100, M: int = 2_000_000, N: int = 64, K: int = 3,
                   knn_eps=0.05, reg="chi", chi_target=10.0, chi_full=20.0,
                   grid_shape=(grid, grid, grid))
     return Workload(f"t3-clusters-M{M}-N{N}-K{K}", "t3", x, f(x)[None, :], params, truth=f)
+
+
+# ------------------------------------------------------------------- serving
+@dataclass
+class ServingTrace:
+    """Requests of the serving workload: arrival times (s, Poisson process),
+    per-request bandwidth N, degree K and node count M, and the node pool each
+    request takes its first M nodes from (pools are cluster + hole node sets
+    in random order, so every prefix is a sample of the same distribution)."""
+    arrival: np.ndarray
+    N: np.ndarray
+    K: np.ndarray
+    M: np.ndarray
+    pool: np.ndarray
+    pools: list  # node arrays (Mmax x 3)
+    fields: list  # values on each pool (Mmax,)
+
+
+def serving_trace(n: int = 512, rate: float = 200.0, seed: int = 7000, Ns=(32, 64, 128, 256),
+                  Ks=(2, 3, 4), M_range=(1e4, 1e6), n_pools: int = 4) -> ServingTrace:
+    """n requests arriving at `rate` per second; N uniform over Ns, K uniform
+    over Ks, M log-uniform over M_range, nodes from the cluster + hole
+    generator (8 vMF clusters, kappa = 20, 20 % uniform, 5 caps of 20 deg)."""
+    rng = np.random.default_rng(seed)
+    arrival = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    arrival -= arrival[0]
+    N = rng.choice(np.asarray(Ns), size=n)
+    K = rng.choice(np.asarray(Ks), size=n)
+    lo, hi = np.log(M_range[0]), np.log(M_range[1])
+    M = np.exp(rng.uniform(lo, hi, size=n)).astype(np.int64)
+    pool = rng.integers(0, n_pools, size=n)
+    Mmax = int(M.max())
+    pools, fields = [], []
+    for k in range(n_pools):
+        prng = np.random.default_rng(seed + 1 + k)
+        caps = random_caps(5, 20.0, 20.0, prng)
+        x = cluster_hole_s2(Mmax, prng, caps=caps)
+        x = x[prng.permutation(Mmax)]
+        f = zonal_field(64, prng, n_centres=6, bump=1.0)
+        pools.append(np.ascontiguousarray(x))
+        fields.append(f(x))
+    return ServingTrace(arrival, N, K, M, pool, pools, fields)
+
+
+def serving_params(N: int, K: int) -> dict:
+    """Parameters of one serving request: kNN radius n = 4m, eps = 0.05,
+    chi-target regularization (chi_T = 10, chi_full = 20)."""
+    m = (K + 1) * (K + 2) // 2
+    return dict(domain="s2", bandwidth=int(N), degree=int(K), support_radius=0.0, knn_count=4 * m,
+                knn_eps=0.05, reg="chi", chi_target=10.0, chi_full=20.0)

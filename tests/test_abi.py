@@ -48,9 +48,11 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "hamls.h"
 int main(void){
- printf("%zu %zu %zu %zu %zu %zu\n", sizeof(hamls_params), sizeof(hamls_plan_info),
+ printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hamls_params), sizeof(hamls_plan_info),
    offsetof(hamls_params, knn_eps), offsetof(hamls_params, grid_shape),
-   offsetof(hamls_plan_info, num_grid), offsetof(hamls_plan_info, num_cells));
+   offsetof(hamls_plan_info, num_grid), offsetof(hamls_plan_info, num_cells),
+   sizeof(hamls_request), offsetof(hamls_request, nodes), offsetof(hamls_request, tag),
+   sizeof(hamls_completion), offsetof(hamls_completion, t_submit), offsetof(hamls_completion, t_done));
  return 0; }
 """
     with tempfile.TemporaryDirectory() as d:
@@ -61,7 +63,9 @@ int main(void){
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     got = [int(v) for v in out]
     ref = [C.sizeof(H.hamls_params), C.sizeof(H.hamls_plan_info), H.hamls_params.knn_eps.offset,
-           H.hamls_params.grid_shape.offset, H.hamls_plan_info.num_grid.offset, H.hamls_plan_info.num_cells.offset]
+           H.hamls_params.grid_shape.offset, H.hamls_plan_info.num_grid.offset, H.hamls_plan_info.num_cells.offset,
+           C.sizeof(H.hamls_request), H.hamls_request.nodes.offset, H.hamls_request.tag.offset,
+           C.sizeof(H.hamls_completion), H.hamls_completion.t_submit.offset, H.hamls_completion.t_done.offset]
     assert got == ref
 
 
@@ -95,3 +99,36 @@ def test_status_strings():
 
     for c in (0, -1, -2, -3, -4, -5, -6):
         assert H.hamls_status_string(c) == H.STATUS[c]
+
+
+def test_footprint_host_only():
+    """hamls_plan_footprint needs no device: it grows with M and F, it holds
+    at least the member lists of the adaptive radius (128 int32 per grid node)
+    and the per-node buffers (coordinates, weight, sort keys and indices, 16
+    value slots), and bad
+    parameters are rejected with the same codes as hamls_plan."""
+    from paper_2609_39200_amd import hamls as H
+
+    p = H.hamls_params_init(bandwidth=32, degree=3, knn_count=40)
+    a = H.hamls_plan_footprint(p, 50000, 1)
+    assert a > 0
+    assert H.hamls_plan_footprint(p, 100000, 1) > a
+    assert H.hamls_plan_footprint(p, 50000, 4) > a
+    MQ = 33 * 66
+    assert a >= 128 * 4 * MQ + 50000 * (3 * 8 + 8 + 5 * 4 + 16 * 8)
+    for over, code in ((dict(degree=7), -1), (dict(grid_shape=(10, 34, 0), bandwidth=16), -6)):
+        with pytest.raises(H.HamlsError) as e:
+            H.hamls_plan_footprint(H.hamls_params_init(**over), 1000, 1)
+        assert e.value.code == code
+
+
+def test_server_calls_reject_null_handles():
+    from paper_2609_39200_amd import hamls as H
+
+    buf = (H.hamls_completion * 4)()
+    n = C.c_int32(0)
+    assert H._lib.hamls_server_submit(None, None) == -1
+    assert H._lib.hamls_server_wait(None, buf, 4, C.byref(n), 0.0) == -1
+    assert H._lib.hamls_server_load(None, None, None, None) == -1
+    assert H._lib.hamls_server_destroy(None) == 0
+    assert H.hamls_server_clock() >= 0.0
