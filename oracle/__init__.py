@@ -61,6 +61,7 @@ def lib():
         L.orc_neighbors.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
         L.orc_neighbor_lists.argtypes = [P(OrcParams), vp, vp, i64, vp, i64, vp, vp, vp]
         L.orc_mls.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, i32, i64, vp, vp, vp, vp, vp]
+        L.orc_generating.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_alf.argtypes = [C.c_int, d, vp]
         L.orc_alf.restype = None
         L.orc_wigner_d.argtypes = [C.c_int, d, vp]
@@ -178,6 +179,32 @@ def mls(p: OrcParams, grid_pts, nodes, values, node_weights=None, rows=None):
     if rc:
         raise ValueError("orc_mls failed")
     return dict(values=out, n=nj, chi=chi, tau=tau, status=st)
+
+
+def generating(p: OrcParams, grid_pts, nodes, node_weights=None, rows=None):
+    """Generating functions of MLS at the requested centres (Rem. 2.5): CSR
+    row_ptr / idx (ascending original index) / val with M_y(q_r) =
+    sum_e val[e] y[idx[e]] over row r; plus chi, tau, status per centre."""
+    grid_pts = np.ascontiguousarray(grid_pts, dtype=np.float64)
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    nu = None if node_weights is None else np.ascontiguousarray(node_weights, dtype=np.float64)
+    rows = _rows(rows)
+    nb = neighbors(p, grid_pts, nodes, rows=rows)
+    R = nb["count"].shape[0]
+    rp = np.zeros(R + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(nb["count"])
+    idx = np.zeros(max(int(rp[-1]), 1), dtype=np.int32)
+    val = np.zeros(max(int(rp[-1]), 1))
+    chi = np.zeros(R)
+    tau = np.zeros(R)
+    st = np.zeros(R, dtype=np.uint8)
+    rc = lib().orc_generating(C.byref(p), _ptr(grid_pts), grid_pts.shape[0], _ptr(rows), R, _ptr(nodes),
+                              nodes.shape[0], _ptr(nu), _ptr(rp), _ptr(idx), _ptr(val), _ptr(chi), _ptr(tau),
+                              _ptr(st))
+    if rc:
+        raise ValueError("orc_generating failed")
+    n = int(rp[-1])
+    return dict(row_ptr=rp, idx=idx[:n], val=val[:n], chi=chi, tau=tau, status=st)
 
 
 def num_coeffs(p: OrcParams) -> int:

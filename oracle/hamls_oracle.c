@@ -614,12 +614,14 @@ typedef struct {
     double* g;    /* n x m raw monomial values */
     int32_t* nb;
     int cap;
+    int fcap; /* fields E and Rhs hold */
 } orc_work;
 
 static void work_reserve(orc_work* wk, int n, int m, int F)
 {
-    if (n <= wk->cap) return;
-    int cap = n + 64;
+    if (n <= wk->cap && F <= wk->fcap) return;
+    int cap = n + 64 > wk->cap ? n + 64 : wk->cap;
+    if (F < wk->fcap) F = wk->fcap;
     free(wk->B); free(wk->E); free(wk->Aug); free(wk->Rhs); free(wk->w); free(wk->g); free(wk->nb);
     wk->B = malloc(sizeof(double) * (size_t)cap * m);
     wk->E = malloc(sizeof(double) * (size_t)cap * (1 + F));
@@ -629,6 +631,7 @@ static void work_reserve(orc_work* wk, int n, int m, int F)
     wk->g = malloc(sizeof(double) * (size_t)cap * m);
     wk->nb = malloc(sizeof(int32_t) * (size_t)cap);
     wk->cap = cap;
+    wk->fcap = F;
 }
 
 static void work_free(orc_work* wk)
@@ -653,12 +656,15 @@ static void work_free(orc_work* wk)
  *        [ v_1  V ; 0  sqrt(tau) D^{1/2} L^T ],  right side [ y_w ; 0 ].
  * Degenerate centres: no neighbour -> NaN and EMPTY; fewer than m neighbours,
  * a zero monomial column or |R_jj| <= 1e-11 -> the tau -> infinity limit
- * (Shepard mean, Sec. 2.3) and UNDERDETERMINED. */
+ * (Shepard mean, Sec. 2.3) and UNDERDETERMINED.
+ * unit = 1: the data are the n unit vectors of the neighbourhood (field f has
+ * y = 1 at neighbour f, 0 elsewhere; F = n, vals unused), so that out[f] is
+ * the generating function a*_f of Rem. 2.5. */
 static void mls_centre(const orc_params* p, const double* q, double delta, int n,
                        const double* nodes, const double* nu, const double* vals, int F,
                        int64_t ld, const int* exps, const int* degs, int m, orc_work* wk,
                        double* out, int64_t out_stride, double* chi_out, double* tau_out,
-                       uint8_t* st)
+                       uint8_t* st, int unit)
 {
     int dom = p->domain;
     int D = tangent_dim(dom);
@@ -719,11 +725,12 @@ static void mls_centre(const orc_params* p, const double* q, double delta, int n
             for (int i = 0; i < n; i++)
                 wk->B[(size_t)(a - 1) * n + i] = sqrt(wk->w[i]) * wk->g[(size_t)a * n + i] / colscale[a];
         for (int i = 0; i < n; i++) wk->E[i] = sqrt(wk->w[i]);
-        for (int f = 0; f < F; f++)
+        const int FE = unit ? 0 : F; /* the data columns of E are not used below */
+        for (int f = 0; f < FE; f++)
             for (int i = 0; i < n; i++)
                 wk->E[(size_t)(1 + f) * n + i] = sqrt(wk->w[i]) * vals[f * ld + nb[i]];
         /* step 4 */
-        householder_qr(n, mv, wk->B, n, 1 + F, wk->E, n);
+        householder_qr(n, mv, wk->B, n, 1 + FE, wk->E, n);
         double rmax = 0.0, rmin = INFINITY;
         for (int j = 0; j < mv; j++) {
             double r = fabs(wk->B[(size_t)j * n + j]);
@@ -772,7 +779,8 @@ static void mls_centre(const orc_params* p, const double* q, double delta, int n
             }
             for (int f = 0; f < F; f++) {
                 for (int i = 0; i < n; i++)
-                    Rh[(size_t)f * na + i] = sqrt(wk->w[i]) * vals[f * ld + nb[i]];
+                    Rh[(size_t)f * na + i] =
+                        unit ? (i == f ? sqrt(wk->w[i]) : 0.0) : sqrt(wk->w[i]) * vals[f * ld + nb[i]];
                 for (int i = n; i < na; i++) Rh[(size_t)f * na + i] = 0.0;
             }
             householder_qr(na, m, A, na, F, Rh, na);
@@ -795,7 +803,7 @@ static void mls_centre(const orc_params* p, const double* q, double delta, int n
         /* K = 0: c_1 is the weighted mean itself, chi = 1 */
         for (int f = 0; f < F; f++) {
             double s = 0.0;
-            for (int i = 0; i < n; i++) s += wk->w[i] * vals[f * ld + nb[i]];
+            for (int i = 0; i < n; i++) s += wk->w[i] * (unit ? (double)(i == f) : vals[f * ld + nb[i]]);
             out[f * out_stride] = s;
         }
         *chi_out = 1.0;
@@ -804,7 +812,7 @@ static void mls_centre(const orc_params* p, const double* q, double delta, int n
     }
     for (int f = 0; f < F; f++) {
         double s = 0.0;
-        for (int i = 0; i < n; i++) s += wk->w[i] * vals[f * ld + nb[i]];
+        for (int i = 0; i < n; i++) s += wk->w[i] * (unit ? (double)(i == f) : vals[f * ld + nb[i]]);
         out[f * out_stride] = s;
     }
     *chi_out = INFINITY;
@@ -851,7 +859,7 @@ int orc_mls(const orc_params* p, const double* grid, int64_t MQ, const int64_t* 
             for (int64_t i = 0; i < M; i++)
                 if (key_inside(dom, prox_key(dom, nodes + dimq * i, q), c)) wk.nb[n++] = (int32_t)i;
             mls_centre(p, q, dl, n, nodes, nu, vals, F, ld, exps, degs, m, &wk, out + r, R,
-                       chi + r, tau + r, &st);
+                       chi + r, tau + r, &st, 0);
             nj[r] = n;
             status[r] = st;
         }
@@ -859,6 +867,65 @@ int orc_mls(const orc_params* p, const double* grid, int64_t MQ, const int64_t* 
         free(kb);
     }
     return 0;
+}
+
+/* Generating functions of MLS at the requested centres (Rem. 2.5).  The MLS
+ * value is linear in the data, M_y(q) = sum_i a*_i y_i, and a*_i is, by that
+ * definition, the MLS value of the data vector that is 1 at neighbour i and 0
+ * elsewhere: computed exactly so, by the local solve above with the n unit
+ * vectors as its fields.  row_ptr (R + 1) comes from the counts of
+ * orc_neighbors; idx receives the neighbours (ascending original index) and
+ * val the a*_i, row by row; chi, tau and status as for orc_mls. */
+int orc_generating(const orc_params* p, const double* grid, int64_t MQ, const int64_t* rows,
+                   int64_t nrows, const double* nodes, int64_t M, const double* nu,
+                   const int64_t* row_ptr, int32_t* idx, double* val, double* chi, double* tau,
+                   uint8_t* status)
+{
+    if (p->knn_count > M) return -1;
+    if (p->support_radius <= 0.0 && p->knn_count <= 0) return -1;
+    int dom = p->domain;
+    int D = tangent_dim(dom);
+    int K = p->degree;
+    if (K < 0 || K > 6) return -1;
+    int m = n_monomials(D, K);
+    int exps[3 * 128], degs[128];
+    monomial_exponents(D, K, exps, degs);
+    int dimq = dom == ORC_SO3 ? 4 : 3;
+    int64_t R = rows ? nrows : MQ;
+    int bad = 0;
+#pragma omp parallel
+    {
+        orc_work wk;
+        memset(&wk, 0, sizeof(wk));
+        double* kb = malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t r = 0; r < R; r++) {
+            int64_t j = rows ? rows[r] : r;
+            const double* q = grid + dimq * j;
+            double dl, c;
+            uint8_t st;
+            centre_radius(p, q, nodes, M, kb, &dl, &c, &st);
+            int n = 0;
+            for (int64_t i = 0; i < M; i++)
+                if (key_inside(dom, prox_key(dom, nodes + dimq * i, q), c)) n++;
+            if (n != row_ptr[r + 1] - row_ptr[r]) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+            }
+            work_reserve(&wk, n > 0 ? n : 1, m, n > 0 ? n : 1);
+            n = 0;
+            for (int64_t i = 0; i < M; i++)
+                if (key_inside(dom, prox_key(dom, nodes + dimq * i, q), c)) wk.nb[n++] = (int32_t)i;
+            for (int k = 0; k < n; k++) idx[row_ptr[r] + k] = wk.nb[k];
+            mls_centre(p, q, dl, n, nodes, nu, NULL, n, 0, exps, degs, m, &wk, val + row_ptr[r], 1,
+                       chi + r, tau + r, &st, 1);
+            status[r] = st;
+        }
+        work_free(&wk);
+        free(kb);
+    }
+    return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------ */

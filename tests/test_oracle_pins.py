@@ -597,3 +597,98 @@ def test_whole_pipeline_constant_s2():
     c = oracle.coeffs(p, r["values"])[0]
     assert abs(c[0] - math.sqrt(4 * math.pi)) < 1e-12
     assert np.abs(c[1:]).max() < 1e-12
+
+
+# ------------------------------------------------------------------ generating functions (Rem. 2.5)
+
+
+def _gen_rows(G, r):
+    a, b = G["row_ptr"][r], G["row_ptr"][r + 1]
+    return G["idx"][a:b], G["val"][a:b]
+
+
+@pytest.mark.parametrize("K", [2, 4])
+def test_generating_reproduce_tangent_polynomials_unregularized(K):
+    """Without regularization, sum_i a*_i p(x_i) = p(x) for p in Pi_K^tan
+    (polynomial reproduction, Sec. 2.3) -- in particular sum_i a*_i = 1 --
+    and a*_i = sqrt(w_i) [B^+]_{1i} (the least-squares pseudo-inverse)."""
+    rng = np.random.default_rng(40 + K)
+    nodes = W.cluster_hole_s2(5000, rng, caps=W.random_caps(3, 15, 25, rng))
+    m = (K + 1) * (K + 2) // 2
+    p = oracle.params(domain="s2", bandwidth=6, degree=K, knn_count=4 * m, knn_eps=0.05, reg="none")
+    g, _ = oracle.grid(p)
+    rows = np.arange(0, g.shape[0], 9)
+    G = oracle.generating(p, g, nodes, rows=rows)
+    nb = oracle.neighbors(p, g, nodes, rows=rows, lists=True)
+    coefs = rng.standard_normal(m)
+    for r, j in enumerate(rows):
+        idx, a = _gen_rows(G, r)
+        assert np.array_equal(idx, nb["idx"][nb["row_ptr"][r] : nb["row_ptr"][r + 1]])
+        y = _tangent_poly_values(g[j], nodes[idx], coefs, K)
+        assert abs(a @ y - coefs[0]) < 1e-9 * (1 + np.abs(coefs).sum())
+        assert abs(a.sum() - 1.0) < 1e-12
+        B, _ = oracle.local_system(p, g[j], nb["delta"][r], idx, nodes, np.zeros((1, nodes.shape[0])))
+        ref = B[:, 0] * np.linalg.pinv(B)[0]
+        assert np.max(np.abs(a - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_generating_regularized_normal_equations_and_bounds():
+    """Regularized: a*_i = sqrt(w_i) [B H_tau^-1 e_1]_i with H_tau = H but the
+    lower block C replaced by L (I + tau D) L^T (eq. (22)-(23)); constants are
+    still reproduced (sum a* = 1); the Lebesgue constant sum |a*_i| stays
+    below sqrt(chi) (Rem. 2.5; H <= H_tau, so the bound holds with the smaller
+    regularized amplification), and below sqrt(chi_T) where the regularization
+    is full (chi >= chi_full)."""
+    rng = np.random.default_rng(47)
+    K = 3
+    nodes = W.cluster_hole_s2(8000, rng, caps=W.random_caps(4, 15, 30, rng))
+    m = (K + 1) * (K + 2) // 2
+    chi_t, chi_f = 3.0, 4.0
+    p = oracle.params(domain="s2", bandwidth=12, degree=K, knn_count=int(2.5 * m), knn_eps=0.05, reg="chi",
+                      chi_target=chi_t, chi_full=chi_f)
+    g, _ = oracle.grid(p)
+    rows = np.arange(0, g.shape[0], 3)
+    G = oracle.generating(p, g, nodes, rows=rows)
+    nb = oracle.neighbors(p, g, nodes, rows=rows, lists=True)
+    mu = (_degrees(K) * (_degrees(K) + 1))[1:].astype(float)
+    n_full = n_reg = 0
+    for r, j in enumerate(rows):
+        if G["status"][r] & (oracle.ST_UNDERDETERMINED | oracle.ST_EMPTY):
+            continue
+        idx, a = _gen_rows(G, r)
+        assert abs(a.sum() - 1.0) < 1e-11
+        lam = np.abs(a).sum()
+        assert lam <= math.sqrt(G["chi"][r]) * (1 + 1e-10)
+        if G["chi"][r] >= chi_f:
+            n_full += 1
+            assert lam <= math.sqrt(chi_t) * (1 + 1e-9)
+        B, _ = oracle.local_system(p, g[j], nb["delta"][r], idx, nodes, np.zeros((1, nodes.shape[0])))
+        H = B.T @ B
+        ev = np.linalg.eigvalsh(H)
+        tol = 1e-14 * ev[-1] / ev[0] + 1e-12
+        L = np.linalg.cholesky(H[1:, 1:])
+        Ht = H.copy()
+        Ht[1:, 1:] = L @ np.diag(1 + G["tau"][r] * mu) @ L.T
+        ref = B[:, 0] * (B @ np.linalg.solve(Ht, np.eye(m)[:, 0]))
+        assert np.max(np.abs(a - ref)) < tol * max(1.0, np.max(np.abs(ref))), (j, tol)
+        n_reg += G["tau"][r] > 0
+    assert n_full > 0 and n_reg > 5
+
+
+def test_generating_applied_equals_fit():
+    """sum_i a*_i y_i equals the MLS value computed from the data directly
+    (chi-target regularization, node weights)."""
+    rng = np.random.default_rng(49)
+    nodes = W.cluster_hole_s2(4000, rng)
+    nu = rng.uniform(0.5, 2.0, 4000)
+    y = rng.standard_normal((2, 4000))
+    p = oracle.params(domain="s2", bandwidth=8, degree=4, knn_count=60, knn_eps=0.05, reg="chi")
+    g, _ = oracle.grid(p)
+    G = oracle.generating(p, g, nodes, node_weights=nu)
+    fit = oracle.mls(p, g, nodes, y, node_weights=nu)
+    rp = G["row_ptr"]
+    for f in range(2):
+        app = np.add.reduceat(G["val"] * y[f][G["idx"]], rp[:-1]) if rp[-1] else np.zeros(0)
+        ok = np.diff(rp) > 0
+        np.testing.assert_allclose(app[ok], fit["values"][f][ok], rtol=0, atol=1e-12 * np.abs(y).max() * 50)
+    np.testing.assert_array_equal(G["status"], fit["status"])
