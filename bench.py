@@ -296,6 +296,9 @@ def main():
         "roofline": roof,
     }
 
+    if domain == "s2":
+        out["generating_functions"] = gen_bench(H, torch, plan, info, vals, gv, stream, K, 1e3 * wall / K)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = cpu_baseline(wl, plan, gv, H, args.cpu_seconds)
     H.hamls_plan_destroy(plan)
@@ -307,6 +310,48 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 8
     print(json.dumps(out), flush=True)
+
+
+def gen_bench(H, torch, plan, info, vals, gv, stream, K, fit_ms):
+    """Generating functions (Rem. 2.5) on the same plan: one build, then K
+    fits through the sparse product (value gather + product), timed like the
+    main loop; the product kernel's events give its roofline (HBM: every
+    entry's 12 bytes, the row pointers, the grid values written, the sorted
+    values read once)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H.hamls_gen_build(plan, stream=stream)
+    torch.cuda.synchronize()
+    build_ms = 1e3 * (time.perf_counter() - t0)
+    ref = gv.clone()
+    H.hamls_mls_to_grid(plan, vals, ref, stream=stream)
+    H.hamls_gen_apply(plan, vals, gv, stream=stream)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(gv - ref) / torch.linalg.norm(ref))
+    rp, _, _ = H.hamls_gen_get(plan)
+    nnz = int(rp[-1])
+    H.hamls_timing_phases(plan, ["gen_apply"])
+    H.hamls_timing_enable(plan, True)
+    H.hamls_timing_read(plan, "gen_apply")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        H.hamls_gen_apply(plan, vals, gv, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n, ms = H.hamls_timing_read(plan, "gen_apply")
+    H.hamls_timing_enable(plan, False)
+    H.hamls_timing_phases(plan, None)
+    gv.copy_(ref)  # the main path's grid values for what follows
+    F = vals.shape[0]
+    MQ = info.num_grid
+    nbytes = nnz * 12 + (MQ + 1) * 8 + MQ * 8 * F + int(info.num_nodes) * 8 * F
+    kms = ms / n
+    ach = nbytes / (kms * 1e-3) / 1e9
+    return {"build_ms": build_ms, "nnz": nnz, "ms_per_fit": 1e3 * wall / K,
+            "speedup_vs_full_fit": fit_ms / (1e3 * wall / K), "rel_l2_vs_fit": err,
+            "apply_kernel": {"kernel": "k_gen_apply", "avg_ms": kms, "bytes": nbytes, "achieved": ach,
+                             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS}}
 
 
 def serve_bench(args, H, W, torch):

@@ -135,6 +135,31 @@ hamls_status hamls_plan_rebind(hamls_plan_t plan, const double* nodes, int64_t M
 hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
                                double* grid_values, void* stream);
 
+/* Generating functions of MLS (Rem. 2.5), S2 plans.  The MLS value at a grid
+ * node is a linear functional of the data, M_y(q_j) = sum_i a*_ji y_i, whose
+ * weights a*_ji depend on the nodes, the radius rule and the regularization
+ * only (tau is chosen from the geometry, eq. (23)).  hamls_gen_build computes
+ * them for the bound node set (FP64, ill-conditioned nodes in double-double
+ * as in hamls_mls_to_grid; also refreshes hamls_diagnostics) and keeps them in
+ * the plan as CSR over the grid (one entry per (grid node, neighbour) pair, 12
+ * bytes); it synchronizes the stream once (the entry count sizes the
+ * storage) and allocates on first use or growth.  A rebind invalidates them.
+ * Errors: UNSUPPORTED for SO3 / T3 plans, OUT_OF_MEMORY, DEVICE. */
+hamls_status hamls_gen_build(hamls_plan_t plan, void* stream);
+
+/* hamls_mls_to_grid through the generating functions: grid_values[f][j] =
+ * sum_i a*_ji values[f][i] (NaN where X(q_j) is empty), one sparse product per
+ * 16 fields; same arguments and layouts as hamls_mls_to_grid, equal to it up
+ * to rounding (the sums run in another order).  INVALID_ARG if
+ * hamls_gen_build has not run since the last bind. */
+hamls_status hamls_gen_apply(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
+                             double* grid_values, void* stream);
+
+/* The generating functions as host CSR over the grid: row_ptr (M_Q + 1, equal
+ * to that of hamls_plan_neighbors), idx (original node indices ascending per
+ * row) and val (a*_ji); idx and val may be NULL.  Synchronizes the device. */
+hamls_status hamls_gen_get(hamls_plan_t plan, int64_t* row_ptr, int32_t* idx, double* val);
+
 /* Step 3 of Alg. 1: fhat = F^H W f by the quadrature rule (eq. (25)).
  *  grid_values  device, F x M_Q real
  *  coeffs       device, F x num_coeffs x 2 (re, im).  Index of a coefficient:
@@ -193,7 +218,8 @@ hamls_status hamls_diagnostics(hamls_plan_t plan, int32_t* n, double* chi, doubl
 #define HAMLS_PHASE_RING_DFT 4  /* step 3: periodic-angle transforms */
 #define HAMLS_PHASE_CONTRACT 5  /* step 3: Legendre / Wigner contraction */
 #define HAMLS_PHASE_GATHER 6    /* value gather into sorted order */
-#define HAMLS_NUM_PHASES 7
+#define HAMLS_PHASE_GEN_APPLY 7 /* sparse product with the generating functions */
+#define HAMLS_NUM_PHASES 8
 hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable);
 /* Restricts the timing to the phases whose bit (1 << phase) is set in mask
  * (every phase by default): events are recorded around those phases only,

@@ -123,6 +123,16 @@ struct Plan {
     int32_t* d_mx_list = nullptr;   // MQ, nodes the mixed path hands to FP64
     int64_t n_entries_cap = 0;
     double* d_vals = nullptr;       // sorted values, kMaxFieldsPerPass x cap
+    // generating functions (Rem. 2.5): per grid node the coefficients gamma
+    // (m x MQ) of a*_i = w_i sum_a gamma_a g_a(x_i), and a*_i as CSR over the
+    // grid (row_ptr MQ + 1, sorted record index and value per entry)
+    double* d_gamma = nullptr;
+    int64_t* d_grow = nullptr;
+    int32_t* d_gcol = nullptr;
+    double* d_gval = nullptr;
+    int64_t gen_cap = 0;            // entries the CSR buffers hold
+    int64_t gen_nnz = 0;
+    bool gen_ready = false;         // built for the bound node set
     double* d_ptab = nullptr;       // Legendre table
     int64_t ptab_len = 0;
     double* d_tw = nullptr;         // 2 x n_phi twiddles
@@ -191,6 +201,7 @@ struct SolveArgs {
     int32_t* rs_count;
     const int32_t* in_list;   // centres a list-mode kernel works on
     const int32_t* in_count;
+    int unit_rhs;             // double-double re-solve: unit right-hand sides (F = m)
 };
 
 
@@ -199,6 +210,14 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values);
 // solve kernel, and that kernel
 bool split_solve(const Plan& P, int F);
 hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+
+// generating functions (Rem. 2.5): gamma by a unit-right-hand-side solve,
+// CSR row pointers from the neighbour counts, the values a*_i, and the sparse
+// product with gathered values
+hamls_status launch_gen_solve(const Plan& P, hipStream_t s);
+hamls_status launch_gen_rowptr(const Plan& P, hipStream_t s);
+hamls_status launch_s2_gen_values(const Plan& P, hipStream_t s);
+hamls_status launch_gen_apply(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 
 // Plan construction with a node capacity above the first bind, and the device
 // bytes such a plan holds after a coefficient pass of F fields.
@@ -216,7 +235,8 @@ hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double
 hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
 hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
-hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                               int unit_rhs = 0);
 hamls_status launch_gather_values(const Plan& P, const double* values, int F, int f0, int64_t ld,
                                   hipStream_t s);
 hamls_status launch_s2_count(const Plan& P, int32_t* counts, hipStream_t s);

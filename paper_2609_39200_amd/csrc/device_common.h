@@ -588,17 +588,20 @@ __device__ __forceinline__ double choose_tau_grp(int reg, double chi, const doub
     return sm * t;
 }
 
-// mls_solve_epilogue for one node per group of GS lanes (m + F <= GS), one
-// field (F = 1): Gs the node's packed Gram matrix and right-hand side in LDS,
-// group lane r holds row r of the normalised, reordered system.  The column
-// scales and every pivot go round the group by broadcasts; no barrier, so the
-// groups of a wave may take different branches.
-template <int m, int GS>
+// mls_solve_epilogue for one node per group of GS lanes (m + F <= GS): Gs the
+// node's packed Gram matrix and right-hand sides in LDS, group lane r holds
+// row r of the normalised, reordered system.  The column scales and every
+// pivot go round the group by broadcasts; no barrier, so the groups of a wave
+// may take different branches.  UNIT: the F = m right-hand sides are the unit
+// vectors e_f instead of those in Gs, so that output f is the derivative of
+// c_1 with respect to the right-hand-side entry f (the coefficients of the
+// generating functions in the monomial basis, Rem. 2.5).
+template <int m, int GS, int F = 1, bool UNIT = false>
 __device__ void mls_solve_group(const double* Gs, int count, int64_t j, const SolveArgs& A) {
     constexpr int NC = m - 1;
     constexpr int EG = m * (m + 1) / 2;
-    constexpr int F = 1;
     static_assert(m + F <= GS, "group too small");
+    static_assert(!UNIT || F == m, "unit right-hand sides: one per monomial");
     const int r = threadIdx.x & (GS - 1);
     const int base = (threadIdx.x & 63) & ~(GS - 1);
     const int64_t MQ = A.MQ;
@@ -623,7 +626,7 @@ __device__ void mls_solve_group(const double* Gs, int count, int64_t j, const So
         inv = 1.0 / v;
     }
     if (degen) {
-        if (r < F) A.out[(int64_t)(A.f0 + r) * MQ + j] = Gs[EG + r] / W;
+        if (r < F) A.out[(int64_t)(A.f0 + r) * MQ + j] = (UNIT ? (r == 0 ? 1.0 : 0.0) : Gs[EG + r]) / W;
         if (r == 0 && A.write_diag) {
             A.chi[j] = __builtin_inf();
             A.tau[j] = __builtin_inf();
@@ -646,7 +649,7 @@ __device__ void mls_solve_group(const double* Gs, int count, int64_t j, const So
                 const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
                 v = Gs[gidx(lo, hi)] * (sr * ib);
             } else if (r < NC + 1 + F) {
-                v = Gs[EG + bc * F + (r - NC - 1)] * (sr * ib);
+                v = (UNIT ? (bc == r - NC - 1 ? 1.0 : 0.0) : Gs[EG + bc * F + (r - NC - 1)]) * (sr * ib);
             }
             a[c] = v;
         }
@@ -796,9 +799,11 @@ __device__ void mls_dd_epilogue(const double* Gh, const double* Gl, double* isc,
                 const int e = gidx(lo, hi);
                 v = dd_mul_d(dd_mul_d({Gh[e], Gl[e]}, sr), isc[bc]);
             } else if (r < NC + 1 + F) {
-                // right-hand sides of the unit-sum weights: the data scaled by 1/sqrt(W)
+                // right-hand sides of the unit-sum weights: the data scaled by
+                // 1/sqrt(W) (unit vectors for the generating functions)
                 const int e = EG + bc * F + (r - NC - 1);
-                v = dd_mul_d(dd_mul_d({Gh[e], Gl[e]}, sr), isc[bc]);
+                const dd rhs = A.unit_rhs ? dd{bc == r - NC - 1 ? 1.0 : 0.0, 0.0} : dd{Gh[e], Gl[e]};
+                v = dd_mul_d(dd_mul_d(rhs, sr), isc[bc]);
             }
             a[c] = v;
         }
@@ -828,7 +833,9 @@ __device__ void mls_dd_epilogue(const double* Gh, const double* Gl, double* isc,
     }
     if (ill) {
         // rank deficient: the tau -> infinity limit
-        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = (Gh[EG + lane] + Gl[EG + lane]) / W;
+        if (lane < F)
+            A.out[(int64_t)(A.f0 + lane) * MQ + j] =
+                (A.unit_rhs ? (lane == 0 ? 1.0 : 0.0) : Gh[EG + lane] + Gl[EG + lane]) / W;
         if (lane == 0 && A.write_diag) {
             A.chi[j] = __builtin_inf();
             A.tau[j] = __builtin_inf();

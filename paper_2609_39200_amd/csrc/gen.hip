@@ -1,0 +1,134 @@
+// Generating functions of MLS (Rem. 2.5): the value at grid node x is the
+// linear functional M_y(x) = sum_i a*_i y_i of the data, with a*_i depending
+// on the geometry only.  With R_a = sum_i w_i g_a(x_i) y_i the right-hand side
+// of the (regularized) normal equations, c_1 is linear in R, so
+//   a*_i = w_i sum_a gamma_a g_a(x_i),   gamma_a = d c_1 / d R_a,
+// and gamma is c_1 of the solve with the unit vectors e_a as right-hand sides.
+// Built once per node set, the values a*_i turn every later fit on the same
+// nodes into one sparse product (grid node rows, member columns).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "device_common.h"
+
+namespace hamls {
+
+// gamma of GS-lane groups, 64 / GS nodes per wave, from the packed Gram
+// matrices of a one-field assembly pass ([j][m(m+1)/2 + m]); the pass's
+// right-hand side is not used.
+template <int m, int GS>
+__global__ __launch_bounds__(64) void k_gen_solve(const double* __restrict__ gram, SolveArgs A) {
+    constexpr int NG = 64 / GS;
+    constexpr int E = m * (m + 1) / 2 + m;
+    __shared__ double gl[NG * E];
+    const int g = threadIdx.x / GS, r = threadIdx.x % GS;
+    const int64_t j = (int64_t)blockIdx.x * NG + g;
+    const bool live = j < A.MQ;
+    for (int e = r; e < E; e += GS) gl[g * E + e] = live ? gram[j * E + e] : 0.0;
+    __syncthreads();
+    if (live) mls_solve_group<m, GS, m, true>(gl + g * E, A.nj[j], j, A);
+}
+
+// row_ptr = exclusive prefix sum of the neighbour counts (one block).
+__global__ __launch_bounds__(1024) void k_gen_rowptr(const int32_t* __restrict__ nj, int64_t MQ,
+                                                     int64_t* __restrict__ row_ptr) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (MQ + 1023) / 1024;
+    const int64_t lo = t * chunk, hi = lo + chunk < MQ ? lo + chunk : MQ;
+    int64_t own = 0;
+    for (int64_t i = lo; i < hi; i++) own += nj[i];
+    part[t] = own;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int64_t v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t run = part[t] - own;
+    for (int64_t i = lo; i < hi; i++) {
+        row_ptr[i] = run;
+        run += nj[i];
+    }
+    if (t == 1023) row_ptr[MQ] = part[1023];
+}
+
+// out[f0 + f][j] = sum_e val[e] vals[f][col[e]] over row j: 16 lanes per grid
+// node (four per wave), each lane a strided share of the row, then a 16-lane
+// butterfly.  Rows without entries (no node in the support) give NaN, as the
+// fit does.  vals: the sorted values, row f at vals + f * ldv.
+template <int FM>
+__global__ __launch_bounds__(64) void k_gen_apply(const int64_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ vals, int64_t ldv, int F,
+                                                  int f0, int64_t MQ, double* __restrict__ out) {
+    constexpr int GS = 16;
+    const int g = threadIdx.x / GS, r = threadIdx.x % GS;
+    const int64_t j = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (64 / GS) + g;
+    if (j >= MQ) return;  // whole groups: the butterfly stays within live lanes
+    const int64_t b = row_ptr[j], e = row_ptr[j + 1];
+    double acc[FM];
+#pragma unroll
+    for (int f = 0; f < FM; f++) acc[f] = 0.0;
+    for (int64_t k = b + r; k < e; k += GS) {
+        const double a = val[k];
+        const int64_t i = col[k];
+#pragma unroll
+        for (int f = 0; f < FM; f++)
+            if (f < F) acc[f] = fma(a, vals[f * ldv + i], acc[f]);
+    }
+#pragma unroll
+    for (int f = 0; f < FM; f++) {
+#pragma unroll
+        for (int o = GS / 2; o > 0; o >>= 1) acc[f] += __shfl_xor(acc[f], o, GS);
+    }
+    if (r == 0) {
+        const double nan = __builtin_nan("");
+#pragma unroll
+        for (int f = 0; f < FM; f++)
+            if (f < F) out[(int64_t)(f0 + f) * MQ + j] = e > b ? acc[f] : nan;
+    }
+}
+
+hamls_status launch_gen_solve(const Plan& P, hipStream_t s) {
+    SolveArgs A = make_solve_args(P, P.m, 0, P.d_gamma);
+    const double* G = P.d_entries;
+    // m + m lanes per node: groups of 16 up to m = 8, else 32
+#define HAMLS_GS(MM, GS)                                                                   \
+    hipLaunchKernelGGL((k_gen_solve<MM, GS>), dim3((unsigned)((P.MQ + 64 / GS - 1) / (64 / GS))), \
+                       dim3(64), 0, s, G, A);
+    switch (P.m) {
+        case 1: HAMLS_GS(1, 16) break;
+        case 3: HAMLS_GS(3, 16) break;
+        case 4: HAMLS_GS(4, 16) break;
+        case 6: HAMLS_GS(6, 16) break;
+        case 10: HAMLS_GS(10, 32) break;
+        case 15: HAMLS_GS(15, 32) break;
+        default: set_error("no generating-function solve for m = %d", P.m); return HAMLS_ERR_UNSUPPORTED;
+    }
+#undef HAMLS_GS
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+hamls_status launch_gen_rowptr(const Plan& P, hipStream_t s) {
+    hipLaunchKernelGGL(k_gen_rowptr, dim3(1), dim3(1024), 0, s, P.d_nj, P.MQ, P.d_grow);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+hamls_status launch_gen_apply(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+    const dim3 grid((unsigned)((P.MQ + 3) / 4)), block(64);
+    if (F == 1)
+        hipLaunchKernelGGL((k_gen_apply<1>), grid, block, 0, s, P.d_grow, P.d_gcol, P.d_gval, P.d_vals,
+                           P.cap, F, f0, P.MQ, grid_values);
+    else
+        hipLaunchKernelGGL((k_gen_apply<kMaxFieldsPerPass>), grid, block, 0, s, P.d_grow, P.d_gcol,
+                           P.d_gval, P.d_vals, P.cap, F, f0, P.MQ, grid_values);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+}  // namespace hamls

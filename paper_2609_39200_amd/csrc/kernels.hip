@@ -1642,15 +1642,18 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     A.rs_count = P.d_rs_count;
     A.in_list = P.d_rs_list;
     A.in_count = P.d_rs_count;
+    A.unit_rhs = 0;
     return A;
 }
 
 // Re-solve of the nodes flagged by the FP64 epilogue: the same assembly in
 // double-double precision, blocks striding over the list.
-hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                               int unit_rhs) {
     if (P.m <= 1) return HAMLS_OK;
     S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    A.unit_rhs = unit_rhs;
     dim3 grid(list_blocks(P.MQ)), block(64);
     int wl = P.prm.wendland;
 #define HAMLS_DDS(KK)                                                                                 \
@@ -1714,6 +1717,97 @@ hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx,
     S2Geom g = make_geom(P);
     hipLaunchKernelGGL(k_s2_list, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.d_thr, P.d_delta,
                        P.d_perm, row_ptr, (int32_t*)nullptr, idx);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// generating functions (Rem. 2.5)
+// ---------------------------------------------------------------------------
+
+// Values a*_i = w_i sum_a gamma_a g_a(x_i) of the generating functions at the
+// members of grid node j, with the weight w_i and the monomials g_a formed as
+// in the assembly; entries in member order from row_ptr[j] (sorted record
+// index and value).  gamma: m x MQ (the derivatives of c_1 with respect to the
+// right-hand side of the normal equations).
+template <int K>
+__global__ __launch_bounds__(64) void k_s2_gen_values(S2Geom g, int wendland, const double* __restrict__ thr,
+                                                     const double* __restrict__ delta,
+                                                     const double* __restrict__ gamma, int64_t MQ,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     int32_t* __restrict__ col, double* __restrict__ val) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    __shared__ int sh[kScanLds];
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    const int t = j / g.nphi, p = j - t * g.nphi;
+    const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
+    const double thq = g.theta[t], phq = g.phi[p];
+    const double ct = g.ring_cs[2 * t], stt = g.ring_cs[2 * t + 1];
+    const double cp = g.col_cs[2 * p], sp = g.col_cs[2 * p + 1];
+    const double et0 = ct * cp, et1 = ct * sp, et2 = -stt;
+    const double ep0 = -sp, ep1 = cp;
+    const double c = thr[j], dl = delta[j];
+    const double idl = 1.0 / dl;
+    double gm[m];
+#pragma unroll
+    for (int a = 0; a < m; a++) gm[a] = gamma[(int64_t)a * MQ + j];
+    const int64_t base = row_ptr[j], end = row_ptr[j + 1];
+    int count = 0;
+    s2_members<1>(g, j, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
+        const int i = idx[0];
+        double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
+        if (valid[0]) {
+            x0 = g.X[i];
+            x1 = g.X[g.cap + i];
+            x2 = g.X[2 * g.cap + i];
+            d = s2_dot(x0, x1, x2, q0, q1, q2);
+        }
+        const bool in = d > c;
+        const uint64_t mk = __ballot(in);
+        if (in) {
+            const double w = wendland_phi(wendland, acos(fmin(d, 1.0)) * idl) * (g.nu ? g.nu[i] : 1.0);
+            const double uu = (x0 * et0 + x1 * et1 + x2 * et2) * idl;
+            const double vv = (x0 * ep0 + x1 * ep1) * idl;
+            double pu[K + 1], pv[K + 1];
+            pu[0] = 1.0;
+            pv[0] = 1.0;
+#pragma unroll
+            for (int a = 1; a <= K; a++) {
+                pu[a] = pu[a - 1] * uu;
+                pv[a] = pv[a - 1] * vv;
+            }
+            double sum = 0.0;
+            int cidx = 0;
+#pragma unroll
+            for (int l = 0; l <= K; l++)
+#pragma unroll
+                for (int b2 = 0; b2 <= l; b2++) sum = fma(gm[cidx++], pu[l - b2] * pv[b2], sum);
+            const int64_t e = base + count + rank_below(mk);
+            if (e < end) {
+                col[e] = i;
+                val[e] = w * sum;
+            }
+        }
+        count += __popcll(mk);
+    });
+}
+
+hamls_status launch_s2_gen_values(const Plan& P, hipStream_t s) {
+    S2Geom g = make_geom(P);
+    const dim3 grid((unsigned)P.MQ), block(64);
+    const int wl = P.prm.wendland;
+#define HAMLS_GENV(KK)                                                                                 \
+    hipLaunchKernelGGL((k_s2_gen_values<KK>), grid, block, 0, s, g, wl, P.d_thr, P.d_delta, P.d_gamma, \
+                       P.MQ, P.d_grow, P.d_gcol, P.d_gval);
+    switch (P.K) {
+        case 0: HAMLS_GENV(0) break;
+        case 1: HAMLS_GENV(1) break;
+        case 2: HAMLS_GENV(2) break;
+        case 3: HAMLS_GENV(3) break;
+        case 4: HAMLS_GENV(4) break;
+        default: set_error("degree %d unsupported on S2", P.K); return HAMLS_ERR_UNSUPPORTED;
+    }
+#undef HAMLS_GENV
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

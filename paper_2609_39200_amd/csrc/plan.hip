@@ -353,6 +353,7 @@ static void grid_bins(Plan& P, int64_t M) {
 
 static hamls_status bind_nodes(Plan& P, const double* nodes, int64_t M, const double* nu,
                                hipStream_t s) {
+    P.gen_ready = false;  // generating functions belong to the previous node set
     P.M = M;
     P.nrec = P.dom == HAMLS_SO3 ? 2 * M : M;
     P.has_nu = nu != nullptr;
@@ -833,6 +834,118 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
         HAMLS_TRY(launch_split_solve(*P, Fc, f0, grid_values, s));
         HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_resolve(*P, Fc, f0, grid_values, s)
                                      : launch_grid_resolve(*P, Fc, f0, grid_values, s));
+    }
+    return HAMLS_OK;
+}
+
+hamls_status hamls_gen_build(hamls_plan_t plan, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P) {
+        set_error("null plan");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (P->dom != HAMLS_S2) {
+        set_error("generating functions are built for S2 plans only");
+        return HAMLS_ERR_UNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!P->d_gamma) {
+        HAMLS_TRY(dalloc(*P, &P->d_gamma, (size_t)P->m * P->MQ));
+        HAMLS_TRY(dalloc(*P, &P->d_grow, P->MQ + 1));
+    }
+    P->gen_ready = false;
+    // the assembly pass reads one field of sorted values and the double-double
+    // re-solve m of them: zeros (their right-hand sides are replaced by unit
+    // vectors); the re-solve list starts empty
+    HAMLS_HIP(hipMemsetAsync(P->d_vals, 0, sizeof(double) * (size_t)P->m * P->cap, s));
+    HAMLS_HIP(hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 2, s));
+    HAMLS_TRY(launch_s2_assemble(*P, 1, 0, nullptr, s));
+    HAMLS_TRY(launch_gen_solve(*P, s));
+    HAMLS_TRY(launch_s2_resolve(*P, P->m, 0, P->d_gamma, s, 1));
+    HAMLS_TRY(launch_gen_rowptr(*P, s));
+    int64_t nnz = 0;
+    HAMLS_HIP(hipMemcpyAsync(&nnz, P->d_grow + P->MQ, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HAMLS_HIP(hipStreamSynchronize(s));
+    if (nnz > P->gen_cap || !P->d_gval) {
+        for (void* q : {(void*)P->d_gcol, (void*)P->d_gval}) {
+            if (!q) continue;
+            for (auto it = P->owned.begin(); it != P->owned.end(); ++it)
+                if (it->p == q) {
+                    (void)hipFree(it->p);
+                    P->resident -= (int64_t)it->bytes;
+                    P->owned.erase(it);
+                    break;
+                }
+        }
+        P->d_gcol = nullptr;
+        P->d_gval = nullptr;
+        P->gen_cap = 0;
+        HAMLS_TRY(dalloc(*P, &P->d_gcol, nnz));
+        HAMLS_TRY(dalloc(*P, &P->d_gval, nnz));
+        P->gen_cap = nnz;
+    }
+    HAMLS_TRY(launch_s2_gen_values(*P, s));
+    P->gen_nnz = nnz;
+    P->gen_ready = true;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_gen_apply(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
+                             double* grid_values, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P || !values || !grid_values) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (!P->gen_ready) {
+        set_error("no generating functions for the bound node set (call hamls_gen_build)");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (F < 1 || F > 4096 || ld < P->M) {
+        set_error("need 1 <= F <= 4096 and ld >= M");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int f0 = 0; f0 < F; f0 += kMaxFieldsPerPass) {
+        const int Fc = std::min(kMaxFieldsPerPass, F - f0);
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_GATHER, s);
+            HAMLS_TRY(launch_gather_values(*P, values, Fc, f0, ld, s));
+        }
+        PhaseTimer pt(*P, HAMLS_PHASE_GEN_APPLY, s);
+        HAMLS_TRY(launch_gen_apply(*P, Fc, f0, grid_values, s));
+    }
+    return HAMLS_OK;
+}
+
+hamls_status hamls_gen_get(hamls_plan_t plan, int64_t* row_ptr, int32_t* idx, double* val) {
+    Plan* P = (Plan*)plan;
+    if (!P || !row_ptr) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (!P->gen_ready) {
+        set_error("no generating functions for the bound node set (call hamls_gen_build)");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    HAMLS_HIP(hipDeviceSynchronize());
+    HAMLS_HIP(hipMemcpy(row_ptr, P->d_grow, sizeof(int64_t) * (P->MQ + 1), hipMemcpyDeviceToHost));
+    if (!idx && !val) return HAMLS_OK;
+    const int64_t nnz = P->gen_nnz;
+    std::vector<int32_t> col(nnz), perm(P->nrec);
+    std::vector<double> v(nnz);
+    HAMLS_HIP(hipMemcpy(col.data(), P->d_gcol, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+    HAMLS_HIP(hipMemcpy(v.data(), P->d_gval, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+    HAMLS_HIP(hipMemcpy(perm.data(), P->d_perm, sizeof(int32_t) * P->nrec, hipMemcpyDeviceToHost));
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t j = 0; j < P->MQ; j++) {
+        row.clear();
+        for (int64_t e = row_ptr[j]; e < row_ptr[j + 1]; e++) row.push_back({perm[col[e]], v[e]});
+        std::sort(row.begin(), row.end());
+        for (size_t k = 0; k < row.size(); k++) {
+            if (idx) idx[row_ptr[j] + k] = row[k].first;
+            if (val) val[row_ptr[j] + k] = row[k].second;
+        }
     }
     return HAMLS_OK;
 }

@@ -118,6 +118,9 @@ _SIGS = {
     "hamls_timing_phases": [_vp, C.c_uint32],
     "hamls_timing_read": [_vp, _i32, _vp, _vp],
     "hamls_plan_footprint": [_P(hamls_params), _i64, _i32, _P(_i64)],
+    "hamls_gen_build": [_vp, _vp],
+    "hamls_gen_apply": [_vp, _vp, _i32, _i64, _vp, _vp],
+    "hamls_gen_get": [_vp, _vp, _vp, _vp],
     "hamls_server_create": [_i32, _i64, _P(_vp)],
     "hamls_server_submit": [_vp, _P(hamls_request)],
     "hamls_server_wait": [_vp, _P(hamls_completion), _i32, _P(_i32), C.c_double],
@@ -278,7 +281,8 @@ def hamls_diagnostics(plan: int):
     return dict(n=n, chi=chi, tau=tau, status=st)
 
 
-PHASES = {"binning": 0, "radius": 1, "assemble": 2, "solve": 3, "ring_dft": 4, "contract": 5, "gather": 6}
+PHASES = {"binning": 0, "radius": 1, "assemble": 2, "solve": 3, "ring_dft": 4, "contract": 5, "gather": 6,
+          "gen_apply": 7}
 
 
 def hamls_timing_enable(plan: int, enable: bool = True):
@@ -373,3 +377,25 @@ def hamls_server_destroy(server: int):
 
 def hamls_server_clock() -> float:
     return float(_lib.hamls_server_clock())
+
+
+def hamls_gen_build(plan: int, stream=None):
+    _check(_lib.hamls_gen_build(C.c_void_p(plan), _stream(stream)), "hamls_gen_build")
+
+
+def hamls_gen_apply(plan: int, values, grid_values, stream=None):
+    """values: (F, M) contiguous; grid_values: (F, M_Q)."""
+    F = values.shape[0]
+    _check(_lib.hamls_gen_apply(C.c_void_p(plan), _dev(values, "values"), F, values.shape[1],
+                                _dev(grid_values, "grid_values"), _stream(stream)), "hamls_gen_apply")
+
+
+def hamls_gen_get(plan: int):
+    """(row_ptr, idx, val) numpy arrays: the generating functions per grid node."""
+    info = hamls_plan_info_get(plan)
+    rp = np.zeros(info.num_grid + 1, dtype=np.int64)
+    _check(_lib.hamls_gen_get(C.c_void_p(plan), _np_ptr(rp), None, None), "hamls_gen_get")
+    idx = np.zeros(max(int(rp[-1]), 1), dtype=np.int32)
+    val = np.zeros(max(int(rp[-1]), 1))
+    _check(_lib.hamls_gen_get(C.c_void_p(plan), _np_ptr(rp), _np_ptr(idx), _np_ptr(val)), "hamls_gen_get")
+    return rp, idx[: rp[-1]], val[: rp[-1]]

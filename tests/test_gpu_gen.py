@@ -1,0 +1,173 @@
+"""Generating functions (Rem. 2.5) on the GPU, through the C ABI, against the
+FP64 oracle.
+
+Bars: the CSR structure (row pointers, neighbour indices) bit-exact against
+the oracle's neighbour sets; the values a*_ji within 1e-10 relative L2 of the
+oracle's (a*_i = the MLS value of the unit data vector e_i); the sparse
+product within 1e-10 relative L2 of the oracle's fit and of the plan's own
+hamls_mls_to_grid (both FP64 routes to the same functional, whose rounding
+differences grow with the local amplification chi: ~1e-12 seen at K = 1
+without regularization)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_39200_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch  # noqa: F401
+
+    from paper_2609_39200_amd import hamls
+
+    return hamls
+
+
+def _dev(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _rell2(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def _fit(H, plan, vals, use_gen):
+    import torch
+
+    info = H.hamls_plan_info_get(plan)
+    gv = torch.empty((vals.shape[0], info.num_grid), dtype=torch.float64, device="cuda")
+    (H.hamls_gen_apply if use_gen else H.hamls_mls_to_grid)(plan, vals, gv)
+    torch.cuda.synchronize()
+    return gv.cpu().numpy()
+
+
+CASES = [
+    # (label, workload builder kwargs, parameter overrides, node weights)
+    ("clusters-K2", dict(M=6000, N=12, K=2), {}, False),
+    ("clusters-K3-weights", dict(M=8000, N=16, K=3), {}, True),
+    ("clusters-K4-chi-low", dict(M=8000, N=16, K=4), dict(chi_target=2.0, chi_full=3.0), False),
+    ("clusters-K1-none", dict(M=5000, N=10, K=1), dict(reg="none"), False),
+    # kNN barely above m: ill-conditioned supports, gamma from the double-double re-solve
+    ("clusters-K4-knn16-ill", dict(M=8000, N=16, K=4, knn=16), {}, False),
+]
+
+
+@pytest.mark.parametrize("label,kw,over,weights", CASES, ids=[c[0] for c in CASES])
+def test_generating_functions_match_oracle(H, label, kw, over, weights):
+    wl = W.s2_clusters(seed=600 + kw["K"], **kw)
+    wp = dict(wl.params, **over)
+    rng = np.random.default_rng(5)
+    nu = rng.uniform(0.5, 2.0, wl.nodes.shape[0]) if weights else None
+    _say("gen", label)
+    p = H.params_from_workload(wp)
+    plan = H.hamls_plan(p, _dev(wl.nodes), None if nu is None else _dev(nu))
+    try:
+        H.hamls_gen_build(plan)
+        rp, idx, val = H.hamls_gen_get(plan)
+        po = oracle.params(**wp)
+        g, _ = oracle.grid(po)
+        G = oracle.generating(po, g, wl.nodes, node_weights=nu)
+        assert np.array_equal(rp, G["row_ptr"])
+        assert np.array_equal(idx, G["idx"])
+        err = _rell2(val, G["val"])
+        worst = max((np.max(np.abs(val[a:b] - G["val"][a:b])) / max(1.0, np.max(np.abs(G["val"][a:b])))
+                     for a, b in zip(rp[:-1], rp[1:]) if b > a), default=0.0)
+        dg = H.hamls_diagnostics(plan)
+        _say(label, "nnz", int(rp[-1]), "rel l2", err, "worst row", worst,
+             "regularized", int(np.sum(dg["status"] & H.ST_REGULARIZED != 0)),
+             "ill", int(np.sum(dg["status"] & H.ST_ILLCOND != 0)))
+        assert err <= TOL
+        if "ill" in label:
+            assert np.any(dg["status"] & H.ST_ILLCOND)
+        # the product with the data: oracle fit, and the plan's own fit
+        vals = _dev(np.concatenate([wl.values, rng.standard_normal((2, wl.nodes.shape[0]))]))
+        a = _fit(H, plan, vals, True)
+        b = _fit(H, plan, vals, False)
+        fit = oracle.mls(po, g, wl.nodes, vals.cpu().numpy(), node_weights=nu)
+        ok = np.isfinite(fit["values"][0])
+        assert np.array_equal(np.isfinite(a), np.isfinite(fit["values"]))
+        assert _rell2(a[:, ok], fit["values"][:, ok]) <= TOL
+        assert _rell2(a[:, ok], b[:, ok]) <= TOL
+    finally:
+        H.hamls_plan_destroy(plan)
+
+
+def test_generating_functions_fixed_radius_holes(H):
+    """A fixed radius over holes leaves empty supports (NaN rows without
+    entries) and underdetermined ones (Shepard weights w_i / sum w)."""
+    rng = np.random.default_rng(9)
+    caps = W.random_caps(6, 20.0, 30.0, rng)
+    x = W.cluster_hole_s2(6000, rng, caps=caps)
+    wp = dict(domain="s2", bandwidth=12, degree=2, support_radius=0.12, knn_count=0, reg="chi")
+    p = H.params_from_workload(wp)
+    plan = H.hamls_plan(p, _dev(x))
+    try:
+        H.hamls_gen_build(plan)
+        rp, idx, val = H.hamls_gen_get(plan)
+        po = oracle.params(**wp)
+        g, _ = oracle.grid(po)
+        G = oracle.generating(po, g, x)
+        assert np.array_equal(rp, G["row_ptr"]) and np.array_equal(idx, G["idx"])
+        assert np.any(np.diff(rp) == 0)
+        assert np.any(G["status"] & oracle.ST_UNDERDETERMINED)
+        assert _rell2(val, G["val"]) <= TOL
+        vals = _dev(rng.standard_normal((1, x.shape[0])))
+        a = _fit(H, plan, vals, True)
+        b = _fit(H, plan, vals, False)
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        assert np.array_equal(np.isnan(a[0]), np.diff(rp) == 0)
+        ok = ~np.isnan(b)
+        assert _rell2(a[ok], b[ok]) <= TOL
+    finally:
+        H.hamls_plan_destroy(plan)
+
+
+def test_generating_functions_full_size_and_rebind(H):
+    """The S2 cluster workload at full size (M = 200,000, N = 128, K = 3):
+    the product equals the plan's fit, and sampled grid nodes equal the
+    oracle's; a rebind invalidates the weights until they are rebuilt."""
+    import torch
+
+    wl = W.s2_clusters()
+    p = H.params_from_workload(wl.params)
+    nodes = _dev(wl.nodes)
+    plan = H.hamls_plan(p, nodes)
+    try:
+        _say("gen full size build")
+        H.hamls_gen_build(plan)
+        vals = _dev(np.concatenate([wl.values, np.random.default_rng(3).standard_normal((16, wl.nodes.shape[0]))]))
+        a = _fit(H, plan, vals, True)
+        b = _fit(H, plan, vals, False)
+        err = _rell2(a, b)
+        _say("gen full size vs fit", err)
+        assert err <= TOL
+        po = oracle.params(**wl.params)
+        g, _ = oracle.grid(po)
+        rows = np.random.default_rng(4).choice(g.shape[0], 48, replace=False)
+        fit = oracle.mls(po, g, wl.nodes, vals[:2].cpu().numpy(), rows=rows)
+        assert _rell2(a[:2, rows], fit["values"]) <= TOL
+        # rebind to a subset: stale weights are refused, then rebuilt
+        H.hamls_plan_rebind(plan, nodes[:150000].contiguous())
+        gv = torch.empty((1, g.shape[0]), dtype=torch.float64, device="cuda")
+        with pytest.raises(H.HamlsError):
+            H.hamls_gen_apply(plan, vals[:1, :150000].contiguous(), gv)
+        H.hamls_gen_build(plan)
+        v2 = vals[:1, :150000].contiguous()
+        assert _rell2(_fit(H, plan, v2, True), _fit(H, plan, v2, False)) <= TOL
+    finally:
+        H.hamls_plan_destroy(plan)
