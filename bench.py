@@ -316,7 +316,7 @@ def gen_bench(H, torch, plan, info, vals, gv, stream, K, fit_ms):
     """Generating functions (Rem. 2.5) on the same plan: one build, then K
     fits through the sparse product (value gather + product), timed like the
     main loop; the product kernel's events give its roofline (HBM: every
-    entry's 12 bytes, the row pointers, the grid values written, the sorted
+    entry's 12 bytes, the row pointers, the grid values written, the node
     values read once)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -149,8 +149,9 @@ hamls_status hamls_gen_build(hamls_plan_t plan, void* stream);
 
 /* hamls_mls_to_grid through the generating functions: grid_values[f][j] =
  * sum_i a*_ji values[f][i] (NaN where X(q_j) is empty), one sparse product per
- * 16 fields; same arguments and layouts as hamls_mls_to_grid, equal to it up
- * to rounding (the sums run in another order).  INVALID_ARG if
+ * 16 fields that reads values in place; same arguments and layouts as
+ * hamls_mls_to_grid, equal to it up to rounding (the sums run in another
+ * order).  INVALID_ARG if
  * hamls_gen_build has not run since the last bind. */
 hamls_status hamls_gen_apply(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
                              double* grid_values, void* stream);

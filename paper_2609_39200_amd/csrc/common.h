@@ -125,7 +125,7 @@ struct Plan {
     double* d_vals = nullptr;       // sorted values, kMaxFieldsPerPass x cap
     // generating functions (Rem. 2.5): per grid node the coefficients gamma
     // (m x MQ) of a*_i = w_i sum_a gamma_a g_a(x_i), and a*_i as CSR over the
-    // grid (row_ptr MQ + 1, sorted record index and value per entry)
+    // grid (row_ptr MQ + 1, original node index and value per entry)
     double* d_gamma = nullptr;
     int64_t* d_grow = nullptr;
     int32_t* d_gcol = nullptr;
@@ -217,7 +217,8 @@ hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_value
 hamls_status launch_gen_solve(const Plan& P, hipStream_t s);
 hamls_status launch_gen_rowptr(const Plan& P, hipStream_t s);
 hamls_status launch_s2_gen_values(const Plan& P, hipStream_t s);
-hamls_status launch_gen_apply(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_gen_apply(const Plan& P, const double* values, int64_t ld, int F, int f0,
+                              double* grid_values, hipStream_t s);
 
 // Plan construction with a node capacity above the first bind, and the device
 // bytes such a plan holds after a coefficient pass of F fields.

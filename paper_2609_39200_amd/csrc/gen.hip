@@ -54,30 +54,46 @@ __global__ __launch_bounds__(1024) void k_gen_rowptr(const int32_t* __restrict__
     if (t == 1023) row_ptr[MQ] = part[1023];
 }
 
-// out[f0 + f][j] = sum_e val[e] vals[f][col[e]] over row j: 16 lanes per grid
-// node (four per wave), each lane a strided share of the row, then a 16-lane
-// butterfly.  Rows without entries (no node in the support) give NaN, as the
-// fit does.  vals: the sorted values, row f at vals + f * ldv.
-template <int FM>
-__global__ __launch_bounds__(64) void k_gen_apply(const int64_t* __restrict__ row_ptr,
-                                                  const int32_t* __restrict__ col,
-                                                  const double* __restrict__ val,
-                                                  const double* __restrict__ vals, int64_t ldv, int F,
-                                                  int f0, int64_t MQ, double* __restrict__ out) {
-    constexpr int GS = 16;
+// out[f0 + f][j] = sum_e val[e] vals[f][col[e]] over row j, col the original
+// node index (the caller's values are read in place, no gather pass): 32 lanes
+// per grid node, 8 nodes per 256-thread block; each lane takes U entries of
+// its row at once (entries are read once: non-temporal loads; the values stay
+// in L2), then a 32-lane butterfly.  Measured on the S2 cluster workload (47
+// entries a row): 16 lanes a row took 1.6x as long, a whole wave 1.2x.  Rows
+// without entries (no node in the support) give NaN, as the fit does.  vals:
+// row f at vals + f * ldv.
+template <int FM, int U>
+__global__ __launch_bounds__(256) void k_gen_apply(const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ vals, int64_t ldv, int F,
+                                                   int f0, int64_t MQ, double* __restrict__ out) {
+    constexpr int GS = 32;
     const int g = threadIdx.x / GS, r = threadIdx.x % GS;
-    const int64_t j = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (64 / GS) + g;
+    const int64_t j = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (256 / GS) + g;
     if (j >= MQ) return;  // whole groups: the butterfly stays within live lanes
     const int64_t b = row_ptr[j], e = row_ptr[j + 1];
     double acc[FM];
 #pragma unroll
     for (int f = 0; f < FM; f++) acc[f] = 0.0;
-    for (int64_t k = b + r; k < e; k += GS) {
-        const double a = val[k];
-        const int64_t i = col[k];
+    for (int64_t k0 = b + r; k0 < e; k0 += GS * U) {
+        double a[U];
+        int64_t i[U];
 #pragma unroll
-        for (int f = 0; f < FM; f++)
-            if (f < F) acc[f] = fma(a, vals[f * ldv + i], acc[f]);
+        for (int u = 0; u < U; u++) {
+            const int64_t k = k0 + GS * u;
+            a[u] = 0.0;
+            i[u] = 0;
+            if (k < e) {
+                a[u] = __builtin_nontemporal_load(val + k);
+                i[u] = __builtin_nontemporal_load(col + k);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int f = 0; f < FM; f++)
+                if (f < F) acc[f] = fma(a[u], vals[f * ldv + i[u]], acc[f]);
     }
 #pragma unroll
     for (int f = 0; f < FM; f++) {
@@ -119,14 +135,16 @@ hamls_status launch_gen_rowptr(const Plan& P, hipStream_t s) {
     return HAMLS_OK;
 }
 
-hamls_status launch_gen_apply(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
-    const dim3 grid((unsigned)((P.MQ + 3) / 4)), block(64);
+hamls_status launch_gen_apply(const Plan& P, const double* values, int64_t ld, int F, int f0,
+                              double* grid_values, hipStream_t s) {
+    const dim3 grid((unsigned)((P.MQ + 7) / 8)), block(256);
+    const double* v = values + (int64_t)f0 * ld;
     if (F == 1)
-        hipLaunchKernelGGL((k_gen_apply<1>), grid, block, 0, s, P.d_grow, P.d_gcol, P.d_gval, P.d_vals,
-                           P.cap, F, f0, P.MQ, grid_values);
+        hipLaunchKernelGGL((k_gen_apply<1, 2>), grid, block, 0, s, P.d_grow, P.d_gcol, P.d_gval, v, ld, F,
+                           f0, P.MQ, grid_values);
     else
-        hipLaunchKernelGGL((k_gen_apply<kMaxFieldsPerPass>), grid, block, 0, s, P.d_grow, P.d_gcol,
-                           P.d_gval, P.d_vals, P.cap, F, f0, P.MQ, grid_values);
+        hipLaunchKernelGGL((k_gen_apply<kMaxFieldsPerPass, 2>), grid, block, 0, s, P.d_grow, P.d_gcol,
+                           P.d_gval, v, ld, F, f0, P.MQ, grid_values);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

@@ -1727,14 +1727,15 @@ hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx,
 
 // Values a*_i = w_i sum_a gamma_a g_a(x_i) of the generating functions at the
 // members of grid node j, with the weight w_i and the monomials g_a formed as
-// in the assembly; entries in member order from row_ptr[j] (sorted record
-// index and value).  gamma: m x MQ (the derivatives of c_1 with respect to the
+// in the assembly; entries in member order from row_ptr[j] (original node
+// index perm[i] and value).  gamma: m x MQ (the derivatives of c_1 with respect to the
 // right-hand side of the normal equations).
 template <int K>
 __global__ __launch_bounds__(64) void k_s2_gen_values(S2Geom g, int wendland, const double* __restrict__ thr,
                                                      const double* __restrict__ delta,
                                                      const double* __restrict__ gamma, int64_t MQ,
                                                      const int64_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ perm,
                                                      int32_t* __restrict__ col, double* __restrict__ val) {
     constexpr int m = (K + 1) * (K + 2) / 2;
     __shared__ int sh[kScanLds];
@@ -1784,7 +1785,7 @@ __global__ __launch_bounds__(64) void k_s2_gen_values(S2Geom g, int wendland, co
                 for (int b2 = 0; b2 <= l; b2++) sum = fma(gm[cidx++], pu[l - b2] * pv[b2], sum);
             const int64_t e = base + count + rank_below(mk);
             if (e < end) {
-                col[e] = i;
+                col[e] = perm[i];
                 val[e] = w * sum;
             }
         }
@@ -1798,7 +1799,7 @@ hamls_status launch_s2_gen_values(const Plan& P, hipStream_t s) {
     const int wl = P.prm.wendland;
 #define HAMLS_GENV(KK)                                                                                 \
     hipLaunchKernelGGL((k_s2_gen_values<KK>), grid, block, 0, s, g, wl, P.d_thr, P.d_delta, P.d_gamma, \
-                       P.MQ, P.d_grow, P.d_gcol, P.d_gval);
+                       P.MQ, P.d_grow, P.d_perm, P.d_gcol, P.d_gval);
     switch (P.K) {
         case 0: HAMLS_GENV(0) break;
         case 1: HAMLS_GENV(1) break;

@@ -908,12 +908,8 @@ hamls_status hamls_gen_apply(hamls_plan_t plan, const double* values, int32_t F,
     hipStream_t s = (hipStream_t)stream;
     for (int f0 = 0; f0 < F; f0 += kMaxFieldsPerPass) {
         const int Fc = std::min(kMaxFieldsPerPass, F - f0);
-        {
-            PhaseTimer pt(*P, HAMLS_PHASE_GATHER, s);
-            HAMLS_TRY(launch_gather_values(*P, values, Fc, f0, ld, s));
-        }
         PhaseTimer pt(*P, HAMLS_PHASE_GEN_APPLY, s);
-        HAMLS_TRY(launch_gen_apply(*P, Fc, f0, grid_values, s));
+        HAMLS_TRY(launch_gen_apply(*P, values, ld, Fc, f0, grid_values, s));
     }
     return HAMLS_OK;
 }
@@ -932,15 +928,14 @@ hamls_status hamls_gen_get(hamls_plan_t plan, int64_t* row_ptr, int32_t* idx, do
     HAMLS_HIP(hipMemcpy(row_ptr, P->d_grow, sizeof(int64_t) * (P->MQ + 1), hipMemcpyDeviceToHost));
     if (!idx && !val) return HAMLS_OK;
     const int64_t nnz = P->gen_nnz;
-    std::vector<int32_t> col(nnz), perm(P->nrec);
+    std::vector<int32_t> col(nnz);
     std::vector<double> v(nnz);
     HAMLS_HIP(hipMemcpy(col.data(), P->d_gcol, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
     HAMLS_HIP(hipMemcpy(v.data(), P->d_gval, sizeof(double) * nnz, hipMemcpyDeviceToHost));
-    HAMLS_HIP(hipMemcpy(perm.data(), P->d_perm, sizeof(int32_t) * P->nrec, hipMemcpyDeviceToHost));
     std::vector<std::pair<int32_t, double>> row;
     for (int64_t j = 0; j < P->MQ; j++) {
         row.clear();
-        for (int64_t e = row_ptr[j]; e < row_ptr[j + 1]; e++) row.push_back({perm[col[e]], v[e]});
+        for (int64_t e = row_ptr[j]; e < row_ptr[j + 1]; e++) row.push_back({col[e], v[e]});
         std::sort(row.begin(), row.end());
         for (size_t k = 0; k < row.size(); k++) {
             if (idx) idx[row_ptr[j] + k] = row[k].first;
