@@ -296,6 +296,7 @@ def main():
         "roofline": roof,
     }
 
+    out["captured_fit"] = graph_bench(H, torch, plan, info, vals, K)
     if domain == "s2":
         out["generating_functions"] = gen_bench(H, torch, plan, info, vals, gv, stream, K, 1e3 * wall / K)
 
@@ -310,6 +311,39 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 8
     print(json.dumps(out), flush=True)
+
+
+def graph_bench(H, torch, plan, info, vals, K):
+    """Steps 2 + 3 on the bound nodes (no rebind), K times eagerly and K times
+    as replays of one captured graph, on a side stream (capture needs a
+    stream other than the default one)."""
+    s = torch.cuda.Stream()
+    F = vals.shape[0]
+    gv = torch.empty((F, info.num_grid), dtype=torch.float64, device=vals.device)
+    cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=vals.device)
+    torch.cuda.synchronize()
+    g = H.hamls_fit_capture(plan, vals, gv, cf, s)
+    try:
+        def eager():
+            H.hamls_mls_to_grid(plan, vals, gv, stream=s)
+            H.hamls_grid_to_coeffs(plan, gv, cf, stream=s)
+
+        def replay():
+            H.hamls_graph_launch(g, s)
+
+        res = {}
+        for name, fn in (("eager", eager), ("graph", replay)):
+            fn()
+            s.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(K):
+                fn()
+            s.synchronize()
+            res[f"{name}_ms"] = 1e3 * (time.perf_counter() - t0) / K
+    finally:
+        H.hamls_graph_destroy(g)
+    res["note"] = "steps 2 + 3 only (no rebind), wall clock per fit"
+    return res
 
 
 def gen_bench(H, torch, plan, info, vals, gv, stream, K, fit_ms):

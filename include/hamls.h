@@ -180,6 +180,26 @@ hamls_status hamls_eval(hamls_plan_t plan, const double* coeffs, int32_t F, cons
 
 hamls_status hamls_plan_destroy(hamls_plan_t plan);
 
+/* ---- captured fits (HIP graphs) ----
+ * Steps 2 and 3 on a resident plan have fixed shapes: a fit whose buffers do
+ * not change between calls (repeated fields on one node set, a served plan)
+ * can be captured once and replayed as one graph launch instead of ~15 kernel
+ * launches.  hamls_fit_capture records hamls_mls_to_grid(values, F, ld,
+ * grid_values) followed by hamls_grid_to_coeffs(grid_values, F, coeffs) on
+ * `stream`, which must not be the default stream, and instantiates the graph
+ * (it synchronizes the stream first; step-3 work buffers for F fields are
+ * allocated before the capture, and the captured work records no memset).
+ * Each hamls_graph_launch reads what values holds when it runs and rewrites
+ * grid_values, coeffs and the diagnostics, with the same results as the
+ * eager calls.  The graph refers to the plan's buffers: a rebind to the same
+ * M keeps it valid; after a rebind to another M hamls_graph_launch returns
+ * INVALID_ARG.  Destroy graphs before their plan. */
+typedef struct hamls_graph_s* hamls_graph_t;
+hamls_status hamls_fit_capture(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
+                               double* grid_values, double* coeffs, void* stream, hamls_graph_t* out);
+hamls_status hamls_graph_launch(hamls_graph_t graph, void* stream);
+hamls_status hamls_graph_destroy(hamls_graph_t graph);
+
 /* Device bytes a plan of these parameters holds for M nodes after a
  * hamls_grid_to_coeffs call with F fields: the sum of its allocations (the
  * capacity of a serving-loop plan, below, counts as M).  Host only; no device

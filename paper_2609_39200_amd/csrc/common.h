@@ -201,7 +201,6 @@ struct SolveArgs {
     int32_t* rs_count;
     const int32_t* in_list;   // centres a list-mode kernel works on
     const int32_t* in_count;
-    int unit_rhs;             // double-double re-solve: unit right-hand sides (F = m)
 };
 
 

@@ -909,7 +909,7 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
 // fetched 64*U per step (U record loads per lane in flight); member rows of
 // (sqrt(w) g, sqrt(w) y) are staged in LDS 64 at a time and each lane owns a
 // few entries, summed over the staged rows.  FM bounds the fields of one pass.
-template <int K, int FM, bool DD, bool SPLIT = false>
+template <int K, int FM, bool DD, bool SPLIT = false, bool UNIT = false>
 __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Geom& g, const double* __restrict__ vals,
                                                    int F, int wendland,
                                                    const double* __restrict__ thr,
@@ -1085,7 +1085,7 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
             }
         }
         __syncthreads();
-        mls_dd_epilogue<m>(Gh, Gl, rows + 2 * (EG + m * FM), count, F, j, A);
+        mls_dd_epilogue<m, UNIT>(Gh, Gl, rows + 2 * (EG + m * FM), count, F, j, A);
         return;
     }
     if (lane == 0) nj[j] = count;
@@ -1142,7 +1142,7 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
 }
 
 
-template <int K, int FM, bool DD, bool LIST, bool SPLIT = false>
+template <int K, int FM, bool DD, bool LIST, bool SPLIT = false, bool UNIT = false>
 __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __restrict__ vals,
                                                    int F, int wendland,
                                                    const double* __restrict__ thr,
@@ -1160,7 +1160,8 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
         // path): a grid-stride loop over the listed nodes
         const int n = *A.in_count;
         for (int li = blockIdx.x; li < n; li += gridDim.x) {
-            s2_node<K, FM, DD>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+            s2_node<K, FM, DD, false, UNIT>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj,
+                                            entries_out);
             __syncthreads();
         }
     } else {
@@ -1642,7 +1643,6 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     A.rs_count = P.d_rs_count;
     A.in_list = P.d_rs_list;
     A.in_count = P.d_rs_count;
-    A.unit_rhs = 0;
     return A;
 }
 
@@ -1653,11 +1653,13 @@ hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values
     if (P.m <= 1) return HAMLS_OK;
     S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    A.unit_rhs = unit_rhs;
     dim3 grid(list_blocks(P.MQ)), block(64);
     int wl = P.prm.wendland;
 #define HAMLS_DDS(KK)                                                                                 \
-    if (F == 1)                                                                                       \
+    if (unit_rhs)                                                                                     \
+        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, true, true, false, true>), grid, block, 0, s, g, \
+                           P.d_vals, F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);             \
+    else if (F == 1)                                                                                  \
         hipLaunchKernelGGL((k_s2_assemble<KK, 1, true, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
                            P.d_delta, A, P.d_nj, P.d_entries);                                        \
     else                                                                                              \

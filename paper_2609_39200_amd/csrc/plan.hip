@@ -945,19 +945,9 @@ hamls_status hamls_gen_get(hamls_plan_t plan, int64_t* row_ptr, int32_t* idx, do
     return HAMLS_OK;
 }
 
-hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, int32_t F,
-                                  double* coeffs, void* stream) {
-    Plan* P = (Plan*)plan;
-    if (!P || !grid_values || !coeffs) {
-        set_error("null argument");
-        return HAMLS_ERR_INVALID_ARG;
-    }
-    if (F < 1 || F > 4096) {
-        set_error("F outside [1, 4096]");
-        return HAMLS_ERR_INVALID_ARG;
-    }
-    hipStream_t s = (hipStream_t)stream;
-    // work memory grows with the field count of the largest call
+// Step-3 work memory for F fields (grows with the largest call; the growth
+// synchronizes the stream and reallocates).
+static hamls_status ensure_coeff_work(Plan* P, int32_t F, hipStream_t s) {
     if (F > P->G_fields) {
         int64_t len0 = 0, len1 = 0;
         const int N = P->N, K2 = 2 * N + 1;
@@ -997,6 +987,22 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
         }
         P->G_fields = F;
     }
+    return HAMLS_OK;
+}
+
+hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, int32_t F,
+                                  double* coeffs, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P || !grid_values || !coeffs) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (F < 1 || F > 4096) {
+        set_error("F outside [1, 4096]");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HAMLS_TRY(ensure_coeff_work(P, F, s));
     if (P->dom == HAMLS_S2) {
         {
             PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
@@ -1032,6 +1038,86 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
                               P->d_tw_ax[0], s));
     HAMLS_TRY(launch_dft_axis(P->d_work[1], false, coeffs, (int64_t)F * n2, n, 1, n, h, -1.0,
                               1.0 / ((double)n * n2), P->d_tw_ax[0], s));
+    return HAMLS_OK;
+}
+
+// A captured fit: steps 2 and 3 on one plan with fixed buffers, replayed as
+// one graph launch.
+struct hamls_graph_s {
+    Plan* P;
+    int64_t M;
+    hipGraph_t g;
+    hipGraphExec_t x;
+};
+
+hamls_status hamls_fit_capture(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
+                               double* grid_values, double* coeffs, void* stream, hamls_graph_t* out) {
+    Plan* P = (Plan*)plan;
+    if (!P || !values || !grid_values || !coeffs || !out) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (!stream) {
+        set_error("capture needs a stream other than the default stream");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (F < 1 || F > 4096 || ld < P->M) {
+        set_error("need 1 <= F <= 4096 and ld >= M");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    // everything that allocates or synchronizes happens before the capture
+    HAMLS_TRY(ensure_coeff_work(P, F, s));
+    HAMLS_HIP(hipStreamSynchronize(s));
+    const bool timing = P->timing;
+    P->timing = false;
+    HAMLS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hamls_status st = hamls_mls_to_grid(plan, values, F, ld, grid_values, stream);
+    if (st == HAMLS_OK) st = hamls_grid_to_coeffs(plan, grid_values, F, coeffs, stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    P->timing = timing;
+    if (st != HAMLS_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != HAMLS_OK ? st : hip_status(e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_status(e, "hipGraphInstantiate");
+    }
+    hamls_graph_s* G = new (std::nothrow) hamls_graph_s{P, P->M, g, x};
+    if (!G) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        set_error("host allocation failed");
+        return HAMLS_ERR_OUT_OF_MEMORY;
+    }
+    *out = G;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_graph_launch(hamls_graph_t graph, void* stream) {
+    if (!graph) {
+        set_error("null graph");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (graph->P->M != graph->M) {
+        set_error("the plan was rebound to %lld nodes since the capture (%lld)", (long long)graph->P->M,
+                  (long long)graph->M);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    HAMLS_HIP(hipGraphLaunch(graph->x, (hipStream_t)stream));
+    return HAMLS_OK;
+}
+
+hamls_status hamls_graph_destroy(hamls_graph_t graph) {
+    if (!graph) return HAMLS_OK;
+    (void)hipGraphExecDestroy(graph->x);
+    (void)hipGraphDestroy(graph->g);
+    delete graph;
     return HAMLS_OK;
 }
 

@@ -118,6 +118,9 @@ _SIGS = {
     "hamls_timing_phases": [_vp, C.c_uint32],
     "hamls_timing_read": [_vp, _i32, _vp, _vp],
     "hamls_plan_footprint": [_P(hamls_params), _i64, _i32, _P(_i64)],
+    "hamls_fit_capture": [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _P(_vp)],
+    "hamls_graph_launch": [_vp, _vp],
+    "hamls_graph_destroy": [_vp],
     "hamls_gen_build": [_vp, _vp],
     "hamls_gen_apply": [_vp, _vp, _i32, _i64, _vp, _vp],
     "hamls_gen_get": [_vp, _vp, _vp, _vp],
@@ -399,3 +402,21 @@ def hamls_gen_get(plan: int):
     val = np.zeros(max(int(rp[-1]), 1))
     _check(_lib.hamls_gen_get(C.c_void_p(plan), _np_ptr(rp), _np_ptr(idx), _np_ptr(val)), "hamls_gen_get")
     return rp, idx[: rp[-1]], val[: rp[-1]]
+
+
+def hamls_fit_capture(plan: int, values, grid_values, coeffs, stream) -> int:
+    """Capture step 2 + step 3 on `stream` (not the default stream); returns a graph handle."""
+    out = C.c_void_p()
+    F = values.shape[0]
+    _check(_lib.hamls_fit_capture(C.c_void_p(plan), _dev(values, "values"), F, values.shape[1],
+                                  _dev(grid_values, "grid_values"), _dev(coeffs, "coeffs"), _stream(stream),
+                                  C.byref(out)), "hamls_fit_capture")
+    return out.value
+
+
+def hamls_graph_launch(graph: int, stream=None):
+    _check(_lib.hamls_graph_launch(C.c_void_p(graph), _stream(stream)), "hamls_graph_launch")
+
+
+def hamls_graph_destroy(graph: int):
+    _check(_lib.hamls_graph_destroy(C.c_void_p(graph)), "hamls_graph_destroy")
