@@ -44,6 +44,9 @@ PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_asse
                 "gather": "k_gather_values"}
 
 WORKLOADS = {
+    "c2fixed": ("s2_clusters_fixed", "S2 ill-distributed under a fixed radius (skewed neighbour counts 0-2400, "
+                "median 196), M=200000 (C2 nodes), N=128, K=3, grid 129x258, delta0=0.1 rad, chi_T=10 "
+                "chi_full=20, F=1, FP64"),
     "c2": ("s2_clusters", "S2 ill-distributed, M=200000 (8 vMF clusters kappa=20 + 20% uniform, 5 caps of 20 deg "
                           "removed), N=128, K=3, grid 129x258, kNN n=40 eps=0.05, chi_T=10 chi_full=20, F=1, FP64"),
     "c3": ("s2_large", "S2 ill-distributed, M=4000000 (8 vMF clusters kappa=20 + 20% uniform, 12 caps of 10-25 deg "
@@ -163,6 +166,14 @@ def main():
     gv = torch.empty((F, MQ), dtype=torch.float64, device=dev)
     cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=dev)
     gen_s = time.time() - t_gen
+
+    # launch form of the one-field FP64 S2 assembly (grid order or the work
+    # queue), measured on these nodes and kept by the plan
+    tune = None
+    if domain == "s2" and args.precision == "fp64" and F == 1:
+        q, t = H.hamls_plan_tune(plan, stream=stream)
+        tune = {"form": q, "grid_order_ms": t[0], "cost_order_dispatch_ms": t[1],
+                "queue_ms": {"8/CU": t[2], "12/CU": t[3]}}
 
     def step():
         H.hamls_plan_rebind(plan, nodes, stream=stream)
@@ -295,6 +306,8 @@ def main():
         "stats": {"pairs": pairs, "mean_neighbours": pairs / MQ, "regularized": n_reg, "illcond": n_ill},
         "roofline": roof,
     }
+    if tune is not None:
+        out["assembly_launch"] = tune
 
     out["captured_fit"] = graph_bench(H, torch, plan, info, vals, K)
     if domain == "s2":

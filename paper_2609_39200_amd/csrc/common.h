@@ -130,6 +130,11 @@ struct Plan {
     int64_t* d_grow = nullptr;
     int32_t* d_gcol = nullptr;
     double* d_gval = nullptr;
+    // launch form of the one-field FP64 S2 assembly chosen by hamls_plan_tune:
+    // 0 = grid order, 1 = dispatch in cost order, > 1 = work queue of that many
+    // blocks over d_order (grid nodes by decreasing member count at tuning time)
+    int asm_queue_blocks = 0;
+    int32_t* d_order = nullptr;
     int64_t gen_cap = 0;            // entries the CSR buffers hold
     int64_t gen_nnz = 0;
     bool gen_ready = false;         // built for the bound node set
@@ -233,7 +238,11 @@ hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t n, h
 hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double* nodes,
                                  const double* nu, int64_t M, hipStream_t s);
 hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
-hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+// queue_blocks: < 0 the plan's tuned launch form, 0 grid order, 1 cost-ordered
+// dispatch, > 1 the work queue with that many blocks (one FP64 field)
+hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                                int queue_blocks = -1);
+hamls_status launch_cost_order(const Plan& P, hipStream_t s);
 hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
                                int unit_rhs = 0);

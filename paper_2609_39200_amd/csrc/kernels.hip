@@ -566,7 +566,9 @@ __global__ void k_gather_values(const int32_t* __restrict__ perm, const double* 
                                 int F, int64_t ld, int64_t M, int64_t cap,
                                 double* __restrict__ out, int32_t* __restrict__ rs_count) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 2) rs_count[i] = 0;  // the solves that follow append their lists from zero
+    // the solves that follow append their lists from zero ([0], [1]);
+    // [2, 10) are the per-XCD node counters of the work-queue assembly
+    if (i < 10) rs_count[i] = 0;
     if (i >= M) return;
     int64_t j = perm[i];
     for (int f = 0; f < F; f++) out[f * cap + i] = values[f * ld + j];
@@ -620,7 +622,7 @@ S2Geom make_geom(const Plan& P) {
 __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
                                                  double delta0, double c_fixed, double* thr,
                                                  double* delta, uint8_t* rstatus, int32_t* mlist,
-                                                 int32_t* mcnt) {
+                                                 int32_t* mcnt, const int32_t* __restrict__ order) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
     __shared__ __align__(16) double buf[kCandCap];
@@ -628,7 +630,8 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
-    const int j = xcd_block(blockIdx.x, gridDim.x);
+    // grid order over the XCDs, or the plan's cost order (heaviest first)
+    const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     const int t = j / g.nphi, p = j - t * g.nphi;
     const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
@@ -894,8 +897,11 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
     double d0 = P.prm.support_radius > 0.0 ? P.prm.support_radius : 0.0;
     double cf = d0 > 0.0 ? cos(d0) : 2.0;
     int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
+    // the cost order of the assembly (member counts at tuning) also puts the
+    // search's costly nodes (large covers, holes) first
+    const int32_t* order = P.asm_queue_blocks == 1 ? P.d_order : nullptr;
     hipLaunchKernelGGL(k_s2_radius, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
-                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt);
+                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt, order);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -1168,6 +1174,93 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
         s2_node<K, FM, DD, SPLIT>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj,
                                   entries_out);
     }
+}
+
+// Work-queue form of the one-field FP64 assembly pass (split solve): a fixed
+// grid of blocks takes grid nodes, heaviest first, from the cost order.  The
+// order is dealt over the 8 XCDs (node k of the order to XCD k mod 8; blocks
+// are dispatched round-robin over the XCDs, so block b serves XCD b mod 8),
+// with one counter per XCD: a single counter for the whole chip serialized
+// its atomics (4.6x slower at C2).  The node code is the grid-order kernel's;
+// each node's entries do not depend on the order.  counters[0..8) start at
+// zero (reset by the value gather that precedes every pass); every block
+// leaves once its XCD's share is handed out.
+template <int K>
+__global__ __launch_bounds__(64) void k_s2_assemble_queue(S2Geom g, const double* __restrict__ vals,
+                                                         int wendland, const double* __restrict__ thr,
+                                                         const double* __restrict__ delta, SolveArgs A,
+                                                         int32_t* __restrict__ nj,
+                                                         double* __restrict__ entries_out,
+                                                         const int32_t* __restrict__ order,
+                                                         int32_t* __restrict__ counters) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    constexpr int ROW = m + 1 + 1;
+    __shared__ __align__(16) double rows[64 * ROW];
+    __shared__ int sh[kScanLds];
+    __shared__ int next;
+    const int64_t MQ = A.MQ;
+    const int x = blockIdx.x & 7;
+    const int64_t share = (MQ - x + 7) / 8;  // nodes x, x + 8, ... of the order
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(counters + x, 1);
+        __syncthreads();
+        const int64_t k = next;
+        __syncthreads();
+        if (k >= share) break;
+        s2_node<K, 1, false, true>(order[8 * k + x], rows, sh, g, vals, 1, wendland, thr, delta, A, nj,
+                                   entries_out);
+        __syncthreads();
+    }
+}
+
+// Cost-ordered dispatch of the same pass: block b assembles grid node
+// order[b]; the hardware dispatcher starts blocks in index order as slots free
+// up, so the heaviest nodes start first, with no atomics.
+template <int K>
+__global__ __launch_bounds__(64) void k_s2_assemble_ordered(S2Geom g, const double* __restrict__ vals,
+                                                           int wendland, const double* __restrict__ thr,
+                                                           const double* __restrict__ delta, SolveArgs A,
+                                                           int32_t* __restrict__ nj,
+                                                           double* __restrict__ entries_out,
+                                                           const int32_t* __restrict__ order) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    constexpr int ROW = m + 1 + 1;
+    __shared__ __align__(16) double rows[64 * ROW];
+    __shared__ int sh[kScanLds];
+    s2_node<K, 1, false, true>(order[blockIdx.x], rows, sh, g, vals, 1, wendland, thr, delta, A, nj, entries_out);
+}
+
+// Grid nodes ordered by decreasing cost for the work queue: buckets of
+// floor(log2(n_j + 1)) (coarse is enough for scheduling), heaviest bucket
+// first; one block.  Within a bucket the order follows the LDS atomics.
+__global__ __launch_bounds__(1024) void k_cost_order(const int32_t* __restrict__ nj, int64_t MQ,
+                                                     int32_t* __restrict__ order) {
+    __shared__ int hist[33];
+    __shared__ int base[33];
+    const int t = threadIdx.x;
+    if (t < 33) hist[t] = 0;
+    __syncthreads();
+    auto bucket = [&](int64_t j) {
+        const uint32_t v = (uint32_t)max(nj[j], 0) + 1u;
+        return 32 - (31 - __builtin_clz(v));  // heavier nodes get smaller bucket numbers
+    };
+    for (int64_t j = t; j < MQ; j += 1024) atomicAdd(&hist[bucket(j)], 1);
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int b = 0; b < 33; b++) {
+            base[b] = run;
+            run += hist[b];
+        }
+    }
+    __syncthreads();
+    for (int64_t j = t; j < MQ; j += 1024) order[atomicAdd(&base[bucket(j)], 1)] = (int32_t)j;
+}
+
+hamls_status launch_cost_order(const Plan& P, hipStream_t s) {
+    hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, s, P.d_nj, P.MQ, P.d_order);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
 }
 
 // Mixed precision, one S2 node per wave (the benchmark spec's FP32 policy, Rem. 2.4):
@@ -1554,11 +1647,36 @@ hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, 
     return HAMLS_OK;
 }
 
-hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                                int queue_blocks) {
     S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
+    if (queue_blocks < 0) queue_blocks = P.asm_queue_blocks;
+    if (queue_blocks > 1 && queue_blocks < 8) queue_blocks = 8;  // one block per XCD partition at least
+    if (F == 1 && queue_blocks > 0 && P.d_order) {
+        // one FP64 field in cost order: dispatch order (1) or the work queue
+        // (that many blocks); the order is set by hamls_plan_tune
+#define HAMLS_ASQ(KK)                                                                                   \
+    if (queue_blocks == 1)                                                                              \
+        hipLaunchKernelGGL((k_s2_assemble_ordered<KK>), grid, block, 0, s, g, P.d_vals, wl, P.d_thr,   \
+                           P.d_delta, A, P.d_nj, P.d_entries, P.d_order);                              \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_s2_assemble_queue<KK>), dim3((unsigned)queue_blocks), block, 0, s, g, P.d_vals, \
+                           wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries, P.d_order, P.d_rs_count + 2);
+        switch (P.K) {
+            case 0: HAMLS_ASQ(0) break;
+            case 1: HAMLS_ASQ(1) break;
+            case 2: HAMLS_ASQ(2) break;
+            case 3: HAMLS_ASQ(3) break;
+            case 4: HAMLS_ASQ(4) break;
+            default: set_error("degree %d unsupported on S2", P.K); return HAMLS_ERR_UNSUPPORTED;
+        }
+#undef HAMLS_ASQ
+        HAMLS_HIP(hipGetLastError());
+        return HAMLS_OK;
+    }
     // one field: the assembly hands the Gram matrices to launch_split_solve
 #define HAMLS_ASM(KK)                                                                             \
     if (F == 1)                                                                                   \

@@ -838,6 +838,96 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
     return HAMLS_OK;
 }
 
+// The work queue's node order: the member counts of the bound nodes (one
+// grid-order assembly pass on zero values), then grid nodes by decreasing count.
+static hamls_status queue_order(Plan* P, hipStream_t s) {
+    if (!P->d_order) HAMLS_TRY(dalloc(*P, &P->d_order, P->MQ));
+    HAMLS_HIP(hipMemsetAsync(P->d_vals, 0, sizeof(double) * (size_t)P->cap, s));
+    HAMLS_HIP(hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s));
+    HAMLS_TRY(launch_s2_assemble(*P, 1, 0, nullptr, s, 0));
+    return launch_cost_order(*P, s);
+}
+
+hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t queue_blocks) {
+    Plan* P = (Plan*)plan;
+    if (!P || queue_blocks < 0 || (queue_blocks > 1 && queue_blocks < 8) || queue_blocks > (1 << 20)) {
+        // the queue needs a block on each of the 8 XCD partitions
+        set_error("null plan or form not 0, 1 or a block count in [8, 2^20]");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (queue_blocks > 0 && (P->dom != HAMLS_S2 || P->prm.precision != HAMLS_FP64)) {
+        set_error("the work-queue assembly exists for FP64 S2 plans only");
+        return HAMLS_ERR_UNSUPPORTED;
+    }
+    if (queue_blocks > 0) HAMLS_TRY(queue_order(P, (hipStream_t)stream));
+    P->asm_queue_blocks = queue_blocks;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blocks, float* times_ms) {
+    Plan* P = (Plan*)plan;
+    if (!P) {
+        set_error("null plan");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (times_ms)
+        for (int k = 0; k < 4; k++) times_ms[k] = -1.0f;
+    if (P->dom != HAMLS_S2 || P->prm.precision != HAMLS_FP64) {
+        // only the one-field FP64 S2 pass has two launch forms
+        P->asm_queue_blocks = 0;
+        if (queue_blocks) *queue_blocks = 0;
+        return HAMLS_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int ncu = 0;
+    HAMLS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device));
+    HAMLS_TRY(queue_order(P, s));
+    // candidates: grid order, dispatch in cost order, and the queue at 8 and
+    // 12 blocks per CU (the queue kernel holds 12 one-wave blocks per CU at a
+    // time: three waves per SIMD; bounding it to four spills); best of three
+    const int cand[4] = {0, 1, 8 * ncu, 12 * ncu};
+    hipEvent_t a = nullptr, b = nullptr;
+    HAMLS_HIP(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_status(e, "hipEventCreate");
+    }
+    float best[4];
+    hamls_status st = HAMLS_OK;
+    for (int c = 0; c < 4 && st == HAMLS_OK; c++) {
+        best[c] = 1e30f;
+        for (int rep = 0; rep < 3 && st == HAMLS_OK; rep++) {
+            e = hipMemsetAsync(P->d_rs_count + 2, 0, sizeof(int32_t) * 8, s);
+            if (e == hipSuccess) e = hipEventRecord(a, s);
+            if (e != hipSuccess) {
+                st = hip_status(e, "tune");
+                break;
+            }
+            st = launch_s2_assemble(*P, 1, 0, nullptr, s, cand[c]);
+            float ms = 0.0f;
+            if (st == HAMLS_OK) {
+                e = hipEventRecord(b, s);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                if (e != hipSuccess) st = hip_status(e, "tune");
+            }
+            if (st == HAMLS_OK && ms < best[c]) best[c] = ms;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != HAMLS_OK) return st;
+    int pick = 0;
+    for (int c = 1; c < 4; c++)
+        if (best[c] < best[pick]) pick = c;
+    P->asm_queue_blocks = cand[pick];
+    if (queue_blocks) *queue_blocks = cand[pick];
+    if (times_ms)
+        for (int c = 0; c < 4; c++) times_ms[c] = best[c];
+    return HAMLS_OK;
+}
+
 hamls_status hamls_gen_build(hamls_plan_t plan, void* stream) {
     Plan* P = (Plan*)plan;
     if (!P) {
@@ -858,7 +948,7 @@ hamls_status hamls_gen_build(hamls_plan_t plan, void* stream) {
     // re-solve m of them: zeros (their right-hand sides are replaced by unit
     // vectors); the re-solve list starts empty
     HAMLS_HIP(hipMemsetAsync(P->d_vals, 0, sizeof(double) * (size_t)P->m * P->cap, s));
-    HAMLS_HIP(hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 2, s));
+    HAMLS_HIP(hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s));
     HAMLS_TRY(launch_s2_assemble(*P, 1, 0, nullptr, s));
     HAMLS_TRY(launch_gen_solve(*P, s));
     HAMLS_TRY(launch_s2_resolve(*P, P->m, 0, P->d_gamma, s, 1));

@@ -118,6 +118,8 @@ _SIGS = {
     "hamls_timing_phases": [_vp, C.c_uint32],
     "hamls_timing_read": [_vp, _i32, _vp, _vp],
     "hamls_plan_footprint": [_P(hamls_params), _i64, _i32, _P(_i64)],
+    "hamls_plan_tune": [_vp, _vp, _P(_i32), _vp],
+    "hamls_plan_assembly_form": [_vp, _vp, _i32],
     "hamls_fit_capture": [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _P(_vp)],
     "hamls_graph_launch": [_vp, _vp],
     "hamls_graph_destroy": [_vp],
@@ -420,3 +422,17 @@ def hamls_graph_launch(graph: int, stream=None):
 
 def hamls_graph_destroy(graph: int):
     _check(_lib.hamls_graph_destroy(C.c_void_p(graph)), "hamls_graph_destroy")
+
+
+def hamls_plan_tune(plan: int, stream=None) -> tuple:
+    """(form, [grid order ms, cost-ordered dispatch ms, queue 8/CU ms, queue 12/CU ms]);
+    form 0 = grid order, 1 = cost-ordered dispatch, else the queue's block count."""
+    q = C.c_int32(0)
+    t = (C.c_float * 4)()
+    _check(_lib.hamls_plan_tune(C.c_void_p(plan), _stream(stream), C.byref(q), t), "hamls_plan_tune")
+    return int(q.value), [float(v) for v in t]
+
+
+def hamls_plan_assembly_form(plan: int, queue_blocks: int, stream=None):
+    _check(_lib.hamls_plan_assembly_form(C.c_void_p(plan), _stream(stream), int(queue_blocks)),
+           "hamls_plan_assembly_form")

@@ -310,6 +310,17 @@ def s2_clusters(seed: int = 2000, M: int = 200_000, N: int = 128, K: int = 3, n_
     return Workload(f"s2-clusters-M{M}-N{N}-K{K}", "s2", x, y[None, :], params, truth=f)
 
 
+def s2_clusters_fixed(seed: int = 2000, M: int = 200_000, N: int = 128, K: int = 3,
+                      delta0: float = 0.1) -> Workload:
+    """The S2 cluster + hole nodes under a fixed support radius delta0 (rad):
+    no node in the holes, ~100 in the uniform part, ~2000 at the cluster
+    modes -- the skewed neighbour counts of ill-distributed data."""
+    wl = s2_clusters(seed=seed, M=M, N=N, K=K)
+    wl.params = dict(wl.params, support_radius=float(delta0), knn_count=0)
+    wl.name = f"s2-clusters-fixed{delta0:g}-M{M}-N{N}-K{K}"
+    return wl
+
+
 def s2_large(seed: int = 3000, M: int = 4_000_000, N: int = 512, K: int = 4) -> Workload:
     """The large S2 case: the cluster + hole generator with 12 caps of radius
     10-25 degrees, field band-limited to degree 640 plus the smooth bump,
