@@ -170,10 +170,11 @@ def main():
     # launch form of the one-field FP64 S2 assembly (grid order or the work
     # queue), measured on these nodes and kept by the plan
     tune = None
-    if domain == "s2" and args.precision == "fp64" and F == 1:
+    if args.precision == "fp64":
         q, t = H.hamls_plan_tune(plan, stream=stream)
-        tune = {"form": q, "grid_order_ms": t[0], "cost_order_dispatch_ms": t[1],
-                "queue_ms": {"8/CU": t[2], "12/CU": t[3]}}
+        tune = {"form": q, "grid_order_ms": t[0], "cost_order_dispatch_ms": t[1]}
+        if domain == "s2":
+            tune["queue_ms"] = {"8/CU": t[2], "12/CU": t[3]}
 
     def step():
         H.hamls_plan_rebind(plan, nodes, stream=stream)

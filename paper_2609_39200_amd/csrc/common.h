@@ -263,7 +263,9 @@ hamls_status launch_grid_keys(const Plan& P, const double* nodes, int64_t M, hip
 hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double* nodes,
                                 const double* nu, int64_t M, hipStream_t s);
 hamls_status launch_grid_radius(const Plan& P, hipStream_t s);
-hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+// form: < 0 the plan's tuned launch form, 0 grid order, 1 cost-ordered dispatch
+hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                             int form = -1);
 hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
 hamls_status launch_grid_list(const Plan& P, const int64_t* row_ptr, int32_t* counts, int32_t* idx,
                               hipStream_t s);

@@ -316,7 +316,7 @@ template <int D>
 __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int knn, double eps,
                                                    double wfac, double delta0, double* thr,
                                                    double* delta, uint8_t* rstatus, int32_t* mlist,
-                                                   int32_t* mcnt) {
+                                                   int32_t* mcnt, const int32_t* __restrict__ order) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
     __shared__ __align__(16) double buf[kCandCap];
@@ -324,7 +324,8 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
-    const int j = xcd_block(blockIdx.x, gridDim.x);
+    // grid order over the XCDs, or the plan's cost order (heaviest first)
+    const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
@@ -558,9 +559,10 @@ hamls_status launch_grid_radius(const Plan& P, hipStream_t s) {
     double d0 = P.prm.support_radius > 0.0 ? P.prm.support_radius : 0.0;
     int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
     auto kern = P.dom == HAMLS_SO3 ? k_grid_radius<4> : k_grid_radius<3>;
+    const int32_t* order = P.asm_queue_blocks == 1 ? P.d_order : nullptr;
     hipLaunchKernelGGL(kern, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn, P.prm.knn_eps,
                        1.005 * (1.0 + P.prm.knn_eps), d0, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist,
-                       P.d_mcnt);
+                       P.d_mcnt, order);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -820,7 +822,8 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
                                                 int wendland, const double* __restrict__ thr,
                                                 const double* __restrict__ delta, SolveArgs A,
                                                 int32_t* __restrict__ nj,
-                                                double* __restrict__ entries_out) {
+                                                double* __restrict__ entries_out,
+                                                const int32_t* __restrict__ order) {
     constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
     constexpr int EG = m * (m + 1) / 2;
     constexpr int ROW = m + FM + 1;
@@ -835,8 +838,9 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
             __syncthreads();
         }
     } else {
-        grid_node<D, K, FM, DD, SPLIT>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta,
-                                       A, nj, entries_out);
+        // grid order over the XCDs, or the plan's cost order (heaviest first)
+        const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
+        grid_node<D, K, FM, DD, SPLIT>(j, rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
     }
 }
 
@@ -844,33 +848,36 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
 // to launch_split_solve (four nodes per wave).  K = 3 (m = 20) solves in
 // place: handing on 230 entries a node costs more than it saves.
 template <int D, int K>
-static void grid_mls_launch(const Plan& P, const GridGeom& g, const SolveArgs& A, int F, int wl, hipStream_t s) {
+static void grid_mls_launch(const Plan& P, const GridGeom& g, const SolveArgs& A, int F, int wl, hipStream_t s,
+                            const int32_t* order) {
     constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
     const dim3 grid((unsigned)P.MQ), block(64);
     if constexpr (m + 1 <= 16) {
         if (F == 1) {
             hipLaunchKernelGGL((k_grid_mls<D, K, 1, false, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr,
-                               P.d_delta, A, P.d_nj, P.d_entries);
+                               P.d_delta, A, P.d_nj, P.d_entries, order);
             return;
         }
     }
     if (F == 1)
         hipLaunchKernelGGL((k_grid_mls<D, K, 1, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta,
-                           A, P.d_nj, P.d_entries);
+                           A, P.d_nj, P.d_entries, order);
     else
         hipLaunchKernelGGL((k_grid_mls<D, K, kMaxFieldsPerPass, false>), grid, block, 0, s, g, P.d_vals, F, wl,
-                           P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
+                           P.d_thr, P.d_delta, A, P.d_nj, P.d_entries, order);
 }
 
-hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s, int form) {
     GridGeom g = make_grid_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     int wl = P.prm.wendland;
-#define HAMLS_GMLS_D(KK)                                \
-    if (P.dom == HAMLS_SO3)                             \
-        grid_mls_launch<4, KK>(P, g, A, F, wl, s);      \
-    else                                                \
-        grid_mls_launch<3, KK>(P, g, A, F, wl, s);
+    if (form < 0) form = P.asm_queue_blocks;
+    const int32_t* order = form == 1 ? P.d_order : nullptr;
+#define HAMLS_GMLS_D(KK)                                       \
+    if (P.dom == HAMLS_SO3)                                    \
+        grid_mls_launch<4, KK>(P, g, A, F, wl, s, order);      \
+    else                                                       \
+        grid_mls_launch<3, KK>(P, g, A, F, wl, s, order);
     switch (P.K) {
         case 0: HAMLS_GMLS_D(0) break;
         case 1: HAMLS_GMLS_D(1) break;
@@ -894,10 +901,10 @@ hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_valu
 #define HAMLS_GDD(DDIM, KK)                                                                          \
     if (F == 1)                                                                                      \
         hipLaunchKernelGGL((k_grid_mls<DDIM, KK, 1, true>), grid, block, 0, s, g, P.d_vals, F, wl,      \
-                           P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);                              \
+                           P.d_thr, P.d_delta, A, P.d_nj, P.d_entries, (const int32_t*)nullptr);     \
     else                                                                                             \
         hipLaunchKernelGGL((k_grid_mls<DDIM, KK, kMaxFieldsPerPass, true>), grid, block, 0, s, g,       \
-                           P.d_vals, F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
+                           P.d_vals, F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries, (const int32_t*)nullptr);
 #define HAMLS_GDD_D(KK)       \
     if (P.dom == HAMLS_SO3) { \
         HAMLS_GDD(4, KK)      \

@@ -838,14 +838,29 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
     return HAMLS_OK;
 }
 
-// The work queue's node order: the member counts of the bound nodes (one
-// grid-order assembly pass on zero values), then grid nodes by decreasing count.
-static hamls_status queue_order(Plan* P, hipStream_t s) {
+// One one-field FP64 assembly pass on the zero values of the tuning in a given
+// launch form (S2: 0 grid order, 1 cost order, > 1 queue; SO3 / T3: 0 or 1).
+// out: M_Q doubles for the passes that solve in place (SO3 / T3, m > 15).
+static hamls_status tune_pass(Plan* P, hipStream_t s, int form, double* out) {
+    return P->dom == HAMLS_S2 ? launch_s2_assemble(*P, 1, 0, out, s, form)
+                              : launch_grid_mls(*P, 1, 0, out, s, form);
+}
+
+// The cost order: the member counts of the bound nodes (one grid-order
+// assembly pass on zero values), then grid nodes by decreasing count.
+static hamls_status queue_order(Plan* P, hipStream_t s, double* out) {
     if (!P->d_order) HAMLS_TRY(dalloc(*P, &P->d_order, P->MQ));
     HAMLS_HIP(hipMemsetAsync(P->d_vals, 0, sizeof(double) * (size_t)P->cap, s));
     HAMLS_HIP(hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s));
-    HAMLS_TRY(launch_s2_assemble(*P, 1, 0, nullptr, s, 0));
+    HAMLS_TRY(tune_pass(P, s, 0, out));
     return launch_cost_order(*P, s);
+}
+
+// M_Q doubles of grid values for the tuning passes (freed by the caller)
+static hamls_status tune_out(Plan* P, double** out) {
+    *out = nullptr;
+    HAMLS_HIP(hipMalloc(out, sizeof(double) * (size_t)P->MQ));
+    return HAMLS_OK;
 }
 
 hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t queue_blocks) {
@@ -855,11 +870,23 @@ hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t q
         set_error("null plan or form not 0, 1 or a block count in [8, 2^20]");
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (queue_blocks > 0 && (P->dom != HAMLS_S2 || P->prm.precision != HAMLS_FP64)) {
-        set_error("the work-queue assembly exists for FP64 S2 plans only");
+    if (queue_blocks > 0 && P->prm.precision != HAMLS_FP64) {
+        set_error("the cost-ordered forms exist for FP64 plans only");
         return HAMLS_ERR_UNSUPPORTED;
     }
-    if (queue_blocks > 0) HAMLS_TRY(queue_order(P, (hipStream_t)stream));
+    if (queue_blocks > 1 && P->dom != HAMLS_S2) {
+        set_error("the work-queue assembly exists for S2 plans only");
+        return HAMLS_ERR_UNSUPPORTED;
+    }
+    if (queue_blocks > 0) {
+        hipStream_t s = (hipStream_t)stream;
+        double* out = nullptr;
+        HAMLS_TRY(tune_out(P, &out));
+        hamls_status st = queue_order(P, s, out);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(out);
+        HAMLS_TRY(st);
+    }
     P->asm_queue_blocks = queue_blocks;
     return HAMLS_OK;
 }
@@ -872,8 +899,8 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
     }
     if (times_ms)
         for (int k = 0; k < 4; k++) times_ms[k] = -1.0f;
-    if (P->dom != HAMLS_S2 || P->prm.precision != HAMLS_FP64) {
-        // only the one-field FP64 S2 pass has two launch forms
+    if (P->prm.precision != HAMLS_FP64) {
+        // the mixed pass has one launch form
         P->asm_queue_blocks = 0;
         if (queue_blocks) *queue_blocks = 0;
         return HAMLS_OK;
@@ -881,30 +908,41 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
     hipStream_t s = (hipStream_t)stream;
     int ncu = 0;
     HAMLS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device));
-    HAMLS_TRY(queue_order(P, s));
-    // candidates: grid order, dispatch in cost order, and the queue at 8 and
-    // 12 blocks per CU (the queue kernel holds 12 one-wave blocks per CU at a
-    // time: three waves per SIMD; bounding it to four spills); best of three
+    double* out = nullptr;
+    HAMLS_TRY(tune_out(P, &out));
+    hamls_status st0 = queue_order(P, s, out);
+    if (st0 != HAMLS_OK) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(out);
+        return st0;
+    }
+    // candidates: grid order, dispatch in cost order, and (S2) the queue at 8
+    // and 12 blocks per CU (the queue kernel holds 12 one-wave blocks per CU at
+    // a time: three waves per SIMD; bounding it to four spills); best of three
     const int cand[4] = {0, 1, 8 * ncu, 12 * ncu};
+    const int ncand = P->dom == HAMLS_S2 ? 4 : 2;
     hipEvent_t a = nullptr, b = nullptr;
-    HAMLS_HIP(hipEventCreate(&a));
-    hipError_t e = hipEventCreate(&b);
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
     if (e != hipSuccess) {
-        (void)hipEventDestroy(a);
+        if (a) (void)hipEventDestroy(a);
+        (void)hipFree(out);
         return hip_status(e, "hipEventCreate");
     }
-    float best[4];
+    float best[4] = {-1.0f, -1.0f, -1.0f, -1.0f};
     hamls_status st = HAMLS_OK;
-    for (int c = 0; c < 4 && st == HAMLS_OK; c++) {
+    for (int c = 0; c < ncand && st == HAMLS_OK; c++) {
         best[c] = 1e30f;
         for (int rep = 0; rep < 3 && st == HAMLS_OK; rep++) {
-            e = hipMemsetAsync(P->d_rs_count + 2, 0, sizeof(int32_t) * 8, s);
+            // every pass starts with empty re-solve lists (the in-place passes
+            // append to them) and zero queue counters
+            e = hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s);
             if (e == hipSuccess) e = hipEventRecord(a, s);
             if (e != hipSuccess) {
                 st = hip_status(e, "tune");
                 break;
             }
-            st = launch_s2_assemble(*P, 1, 0, nullptr, s, cand[c]);
+            st = tune_pass(P, s, cand[c], out);
             float ms = 0.0f;
             if (st == HAMLS_OK) {
                 e = hipEventRecord(b, s);
@@ -915,11 +953,13 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
             if (st == HAMLS_OK && ms < best[c]) best[c] = ms;
         }
     }
+    (void)hipStreamSynchronize(s);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    (void)hipFree(out);
     if (st != HAMLS_OK) return st;
     int pick = 0;
-    for (int c = 1; c < 4; c++)
+    for (int c = 1; c < ncand; c++)
         if (best[c] < best[pick]) pick = c;
     P->asm_queue_blocks = cand[pick];
     if (queue_blocks) *queue_blocks = cand[pick];

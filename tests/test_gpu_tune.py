@@ -96,7 +96,7 @@ def test_queue_and_tuned_forms_equal_grid_order(H):
         H.hamls_plan_destroy(plan)
 
 
-def test_forms_outside_fp64_s2(H):
+def test_forms_of_mixed_plans(H):
     wl = W.s2_clusters_fixed(M=20000, N=16, K=2, delta0=0.2)
     p = H.params_from_workload(wl.params, precision="mixed")
     plan = H.hamls_plan(p, _dev(wl.nodes))
@@ -108,5 +108,41 @@ def test_forms_outside_fp64_s2(H):
         with pytest.raises(H.HamlsError):
             H.hamls_plan_assembly_form(plan, 5)
         H.hamls_plan_assembly_form(plan, 0)
+    finally:
+        H.hamls_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("domain", ["so3", "t3"])
+def test_cost_order_on_grid_domains(H, domain):
+    """SO(3) / T3: grid order and cost-ordered dispatch (assembly, and the
+    radius search of later binds) give identical results; no queue form."""
+    rng = np.random.default_rng(17)
+    if domain == "so3":
+        x = W.clustered_rotations(40000, rng)
+        wp = dict(domain="so3", bandwidth=10, degree=2, knn_count=40, knn_eps=0.05, reg="chi")
+    else:
+        x = W.clustered_torus(40000, rng)
+        wp = dict(domain="t3", bandwidth=10, degree=3, knn_count=80, knn_eps=0.05, reg="chi",
+                  grid_shape=(20, 20, 20))
+    p = H.params_from_workload(wp)
+    nodes = _dev(x)
+    plan = H.hamls_plan(p, nodes)
+    try:
+        vals = _dev(rng.standard_normal((2, x.shape[0])))
+        gv0, cf0, d0 = _fit(H, plan, vals)
+        H.hamls_plan_assembly_form(plan, 1)
+        gv, cf, d = _fit(H, plan, vals)
+        assert _same(gv, gv0) and _same(cf, cf0)
+        H.hamls_plan_rebind(plan, nodes)  # the radius search in cost order
+        gv, cf, d = _fit(H, plan, vals)
+        assert _same(gv, gv0) and _same(cf, cf0)
+        assert np.array_equal(d["n"], d0["n"]) and np.array_equal(d["status"], d0["status"])
+        choice, times = H.hamls_plan_tune(plan)
+        _say(domain, "tuned", choice, times)
+        assert choice in (0, 1) and times[0] > 0 and times[1] > 0 and times[2:] == [-1.0, -1.0]
+        gv, cf, _ = _fit(H, plan, vals)
+        assert _same(gv, gv0) and _same(cf, cf0)
+        with pytest.raises(H.HamlsError):
+            H.hamls_plan_assembly_form(plan, 256)
     finally:
         H.hamls_plan_destroy(plan)
