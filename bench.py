@@ -167,14 +167,13 @@ def main():
     cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=dev)
     gen_s = time.time() - t_gen
 
-    # launch form of the one-field FP64 S2 assembly (grid order or the work
+    # launch form of the assembly pass (grid order, cost order, S2 FP64 work
     # queue), measured on these nodes and kept by the plan
     tune = None
-    if args.precision == "fp64":
-        q, t = H.hamls_plan_tune(plan, stream=stream)
-        tune = {"form": q, "grid_order_ms": t[0], "cost_order_dispatch_ms": t[1]}
-        if domain == "s2":
-            tune["queue_ms"] = {"8/CU": t[2], "12/CU": t[3]}
+    q, t = H.hamls_plan_tune(plan, stream=stream)
+    tune = {"form": q, "grid_order_ms": t[0], "cost_order_dispatch_ms": t[1]}
+    if domain == "s2" and args.precision == "fp64":
+        tune["queue_ms"] = {"8/CU": t[2], "12/CU": t[3]}
 
     def step():
         H.hamls_plan_rebind(plan, nodes, stream=stream)

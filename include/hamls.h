@@ -183,9 +183,10 @@ hamls_status hamls_plan_destroy(hamls_plan_t plan);
 /* Skewed neighbour counts (ill-distributed nodes under a fixed or hybrid
  * radius: from none in holes to thousands at cluster modes) make a few grid
  * nodes far costlier than the rest; in grid order they can trail at the end
- * of a launch.  hamls_plan_tune measures the one-field FP64 assembly pass on
- * the bound nodes in its launch forms -- grid order (0); blocks dispatched in
- * order of decreasing member count (1); on S2 also a persistent work queue
+ * of a launch.  hamls_plan_tune measures the one-field assembly pass (FP64,
+ * or the mixed FP32 pass with its FP64 list) on the bound nodes in its launch
+ * forms -- grid order (0); blocks dispatched in order of decreasing member
+ * count (1); on FP64 S2 also a persistent work queue
  * with per-XCD counters handing out grid nodes in that order, at 8 and 12
  * blocks per CU (the block count) -- and keeps the fastest for the plan's
  * later passes (best of three timings each, HIP events on `stream`;
@@ -194,13 +195,13 @@ hamls_status hamls_plan_destroy(hamls_plan_t plan);
  * keep it (any order gives the same results, only the balance changes).
  * Results are identical in every form.  *queue_blocks receives the choice and
  * times_ms, if not NULL, the four timings in milliseconds (-1 for forms the
- * plan lacks).  Mixed-precision plans have one form: choice 0. */
+ * plan lacks). */
 hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blocks, float* times_ms);
 /* Sets the launch form directly: 0 = grid order, 1 = cost-ordered dispatch,
  * >= 8 = the work queue with that many blocks (the order computed from the
  * bound nodes as in hamls_plan_tune).  INVALID_ARG for 2..7 (the queue needs a
- * block for each of its 8 partitions); UNSUPPORTED for forms other than 0 on
- * mixed plans and for the queue on SO3 / T3. */
+ * block for each of its 8 partitions); UNSUPPORTED for the queue on SO3, T3
+ * and mixed plans. */
 hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t queue_blocks);
 
 /* ---- captured fits (HIP graphs) ----

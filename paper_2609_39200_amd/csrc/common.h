@@ -243,7 +243,8 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
 hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
                                 int queue_blocks = -1);
 hamls_status launch_cost_order(const Plan& P, hipStream_t s);
-hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                             int form = -1);
 hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
                                int unit_rhs = 0);
 hamls_status launch_gather_values(const Plan& P, const double* values, int F, int f0, int64_t ld,

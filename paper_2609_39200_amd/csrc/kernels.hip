@@ -1602,17 +1602,21 @@ template <int K, int FM>
 __global__ __launch_bounds__(64) void k_s2_mixed(S2Geom g, const double* __restrict__ vals, int F,
                                                 int wendland, const double* __restrict__ thr,
                                                 const double* __restrict__ delta, SolveArgs A,
-                                                int32_t* __restrict__ nj) {
+                                                int32_t* __restrict__ nj, const int32_t* __restrict__ order) {
     __shared__ double lds[MixedLds<K, FM>::size];
     __shared__ int sh[kScanLds];
-    s2_mixed_node<K, FM>(xcd_block(blockIdx.x, gridDim.x), lds, sh, g, vals, F, wendland, thr, delta, A, nj);
+    // grid order over the XCDs, or the plan's cost order (heaviest first)
+    const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
+    s2_mixed_node<K, FM>(j, lds, sh, g, vals, F, wendland, thr, delta, A, nj);
 }
 
 // Mixed precision: the FP32 pass over every node (flagging nodes for FP64),
 // then the FP64 assembly over the flagged list (which flags its own
 // ill-conditioned nodes for the double-double re-solve).
-hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s, int form) {
     S2Geom g = make_geom(P);
+    if (form < 0) form = P.asm_queue_blocks;
+    const int32_t* order = form == 1 ? P.d_order : nullptr;
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     SolveArgs B = A;
     A.rs_list = P.d_mx_list;
@@ -1625,12 +1629,12 @@ hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, 
 #define HAMLS_MIX(KK)                                                                                  \
     if (F == 1) {                                                                                      \
         hipLaunchKernelGGL((k_s2_mixed<KK, 1>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, A, \
-                           P.d_nj);                                                                    \
+                           P.d_nj, order);                                                             \
         hipLaunchKernelGGL((k_s2_assemble<KK, 1, false, true>), lgrid, block, 0, s, g, P.d_vals, F, wl,     \
                            P.d_thr, P.d_delta, B, P.d_nj, P.d_entries);                                \
     } else {                                                                                           \
         hipLaunchKernelGGL((k_s2_mixed<KK, kMaxFieldsPerPass>), grid, block, 0, s, g, P.d_vals, F, wl,     \
-                           P.d_thr, P.d_delta, A, P.d_nj);                                             \
+                           P.d_thr, P.d_delta, A, P.d_nj, order);                                      \
         hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, false, true>), lgrid, block, 0, s, g,   \
                            P.d_vals, F, wl, P.d_thr, P.d_delta, B, P.d_nj, P.d_entries);               \
     }

@@ -842,8 +842,9 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
 // launch form (S2: 0 grid order, 1 cost order, > 1 queue; SO3 / T3: 0 or 1).
 // out: M_Q doubles for the passes that solve in place (SO3 / T3, m > 15).
 static hamls_status tune_pass(Plan* P, hipStream_t s, int form, double* out) {
-    return P->dom == HAMLS_S2 ? launch_s2_assemble(*P, 1, 0, out, s, form)
-                              : launch_grid_mls(*P, 1, 0, out, s, form);
+    if (P->dom != HAMLS_S2) return launch_grid_mls(*P, 1, 0, out, s, form);
+    return P->prm.precision == HAMLS_MIXED ? launch_s2_mixed(*P, 1, 0, out, s, form)
+                                           : launch_s2_assemble(*P, 1, 0, out, s, form);
 }
 
 // The cost order: the member counts of the bound nodes (one grid-order
@@ -870,12 +871,8 @@ hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t q
         set_error("null plan or form not 0, 1 or a block count in [8, 2^20]");
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (queue_blocks > 0 && P->prm.precision != HAMLS_FP64) {
-        set_error("the cost-ordered forms exist for FP64 plans only");
-        return HAMLS_ERR_UNSUPPORTED;
-    }
-    if (queue_blocks > 1 && P->dom != HAMLS_S2) {
-        set_error("the work-queue assembly exists for S2 plans only");
+    if (queue_blocks > 1 && (P->dom != HAMLS_S2 || P->prm.precision != HAMLS_FP64)) {
+        set_error("the work-queue assembly exists for FP64 S2 plans only");
         return HAMLS_ERR_UNSUPPORTED;
     }
     if (queue_blocks > 0) {
@@ -899,12 +896,6 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
     }
     if (times_ms)
         for (int k = 0; k < 4; k++) times_ms[k] = -1.0f;
-    if (P->prm.precision != HAMLS_FP64) {
-        // the mixed pass has one launch form
-        P->asm_queue_blocks = 0;
-        if (queue_blocks) *queue_blocks = 0;
-        return HAMLS_OK;
-    }
     hipStream_t s = (hipStream_t)stream;
     int ncu = 0;
     HAMLS_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device));
@@ -920,7 +911,7 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
     // and 12 blocks per CU (the queue kernel holds 12 one-wave blocks per CU at
     // a time: three waves per SIMD; bounding it to four spills); best of three
     const int cand[4] = {0, 1, 8 * ncu, 12 * ncu};
-    const int ncand = P->dom == HAMLS_S2 ? 4 : 2;
+    const int ncand = P->dom == HAMLS_S2 && P->prm.precision == HAMLS_FP64 ? 4 : 2;
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);

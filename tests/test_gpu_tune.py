@@ -97,12 +97,22 @@ def test_queue_and_tuned_forms_equal_grid_order(H):
 
 
 def test_forms_of_mixed_plans(H):
+    """Mixed precision: grid order and cost order (the FP32 pass and the
+    radius search) give identical results; no queue form."""
     wl = W.s2_clusters_fixed(M=20000, N=16, K=2, delta0=0.2)
     p = H.params_from_workload(wl.params, precision="mixed")
-    plan = H.hamls_plan(p, _dev(wl.nodes))
+    nodes = _dev(wl.nodes)
+    plan = H.hamls_plan(p, nodes)
     try:
+        vals = _dev(wl.values)
+        gv0, cf0, d0 = _fit(H, plan, vals)
+        H.hamls_plan_assembly_form(plan, 1)
+        H.hamls_plan_rebind(plan, nodes)
+        gv, cf, d = _fit(H, plan, vals)
+        assert _same(gv, gv0) and _same(cf, cf0) and np.array_equal(d["status"], d0["status"])
         choice, times = H.hamls_plan_tune(plan)
-        assert choice == 0 and times == [-1.0] * 4
+        _say("mixed tuned", choice, times)
+        assert choice in (0, 1) and times[0] > 0 and times[1] > 0 and times[2:] == [-1.0, -1.0]
         with pytest.raises(H.HamlsError):
             H.hamls_plan_assembly_form(plan, 256)
         with pytest.raises(H.HamlsError):
