@@ -324,8 +324,9 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
-    // grid order over the XCDs, or the plan's cost order (heaviest first)
-    const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
+    // grid order, or the plan's cost order (heaviest first), dealt over the XCDs
+    const int jb = xcd_block(blockIdx.x, gridDim.x);
+    const int j = order ? order[jb] : jb;
     const int lane = threadIdx.x;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
@@ -838,8 +839,9 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
             __syncthreads();
         }
     } else {
-        // grid order over the XCDs, or the plan's cost order (heaviest first)
-        const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
+        // grid order, or the plan's cost order (heaviest first), dealt over the XCDs
+        const int jb = xcd_block(blockIdx.x, gridDim.x);
+        const int j = order ? order[jb] : jb;
         grid_node<D, K, FM, DD, SPLIT>(j, rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
     }
 }

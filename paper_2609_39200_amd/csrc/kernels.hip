@@ -630,8 +630,9 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
-    // grid order over the XCDs, or the plan's cost order (heaviest first)
-    const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
+    // grid order, or the plan's cost order (heaviest first), dealt over the XCDs
+    const int jb = xcd_block(blockIdx.x, gridDim.x);
+    const int j = order ? order[jb] : jb;
     const int lane = threadIdx.x;
     const int t = j / g.nphi, p = j - t * g.nphi;
     const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
@@ -1213,9 +1214,10 @@ __global__ __launch_bounds__(64) void k_s2_assemble_queue(S2Geom g, const double
     }
 }
 
-// Cost-ordered dispatch of the same pass: block b assembles grid node
-// order[b]; the hardware dispatcher starts blocks in index order as slots free
-// up, so the heaviest nodes start first, with no atomics.
+// Cost-ordered dispatch of the same pass: the blocks take the cost order
+// through the XCD-aware mapping (runs of 64 positions per XCD); the hardware
+// dispatcher starts blocks in index order as slots free up, so the heaviest
+// nodes start first, with no atomics.
 template <int K>
 __global__ __launch_bounds__(64) void k_s2_assemble_ordered(S2Geom g, const double* __restrict__ vals,
                                                            int wendland, const double* __restrict__ thr,
@@ -1227,38 +1229,43 @@ __global__ __launch_bounds__(64) void k_s2_assemble_ordered(S2Geom g, const doub
     constexpr int ROW = m + 1 + 1;
     __shared__ __align__(16) double rows[64 * ROW];
     __shared__ int sh[kScanLds];
-    s2_node<K, 1, false, true>(order[blockIdx.x], rows, sh, g, vals, 1, wendland, thr, delta, A, nj, entries_out);
+    s2_node<K, 1, false, true>(order[xcd_block(blockIdx.x, gridDim.x)], rows, sh, g, vals, 1, wendland, thr, delta, A,
+                               nj, entries_out);
 }
 
-// Grid nodes ordered by decreasing cost for the work queue: buckets of
-// floor(log2(n_j + 1)) (coarse is enough for scheduling), heaviest bucket
-// first; one block.  Within a bucket the order follows the LDS atomics.
-__global__ __launch_bounds__(1024) void k_cost_order(const int32_t* __restrict__ nj, int64_t MQ,
-                                                     int32_t* __restrict__ order) {
-    __shared__ int hist[33];
-    __shared__ int base[33];
+// Grid nodes ordered by decreasing cost: buckets of floor(log2(n_j + 1))
+// (coarse is enough for scheduling), heaviest bucket first, and grid order
+// within a bucket (a stable counting sort), so that runs of the order stay
+// spatially close for the XCD-aware block mapping.  One block of 256 threads,
+// each owning a contiguous chunk of grid nodes.
+__global__ __launch_bounds__(256) void k_cost_order(const int32_t* __restrict__ nj, int64_t MQ,
+                                                    int32_t* __restrict__ order) {
+    constexpr int NB = 33, T = 256;
+    __shared__ int cnt[NB * T];  // [bucket][thread]: counts, then offsets
     const int t = threadIdx.x;
-    if (t < 33) hist[t] = 0;
-    __syncthreads();
+    const int64_t chunk = (MQ + T - 1) / T;
+    const int64_t lo = t * chunk, hi = lo + chunk < MQ ? lo + chunk : MQ;
     auto bucket = [&](int64_t j) {
         const uint32_t v = (uint32_t)max(nj[j], 0) + 1u;
         return 32 - (31 - __builtin_clz(v));  // heavier nodes get smaller bucket numbers
     };
-    for (int64_t j = t; j < MQ; j += 1024) atomicAdd(&hist[bucket(j)], 1);
+    for (int b = 0; b < NB; b++) cnt[b * T + t] = 0;
+    for (int64_t j = lo; j < hi; j++) cnt[bucket(j) * T + t]++;
     __syncthreads();
     if (t == 0) {
         int run = 0;
-        for (int b = 0; b < 33; b++) {
-            base[b] = run;
-            run += hist[b];
+        for (int e = 0; e < NB * T; e++) {
+            const int c = cnt[e];
+            cnt[e] = run;
+            run += c;
         }
     }
     __syncthreads();
-    for (int64_t j = t; j < MQ; j += 1024) order[atomicAdd(&base[bucket(j)], 1)] = (int32_t)j;
+    for (int64_t j = lo; j < hi; j++) order[cnt[bucket(j) * T + t]++] = (int32_t)j;
 }
 
 hamls_status launch_cost_order(const Plan& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(1024), 0, s, P.d_nj, P.MQ, P.d_order);
+    hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(256), 0, s, P.d_nj, P.MQ, P.d_order);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -1605,9 +1612,9 @@ __global__ __launch_bounds__(64) void k_s2_mixed(S2Geom g, const double* __restr
                                                 int32_t* __restrict__ nj, const int32_t* __restrict__ order) {
     __shared__ double lds[MixedLds<K, FM>::size];
     __shared__ int sh[kScanLds];
-    // grid order over the XCDs, or the plan's cost order (heaviest first)
-    const int j = order ? order[blockIdx.x] : xcd_block(blockIdx.x, gridDim.x);
-    s2_mixed_node<K, FM>(j, lds, sh, g, vals, F, wendland, thr, delta, A, nj);
+    // grid order, or the plan's cost order (heaviest first), dealt over the XCDs
+    const int jb = xcd_block(blockIdx.x, gridDim.x);
+    s2_mixed_node<K, FM>(order ? order[jb] : jb, lds, sh, g, vals, F, wendland, thr, delta, A, nj);
 }
 
 // Mixed precision: the FP32 pass over every node (flagging nodes for FP64),
