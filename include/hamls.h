@@ -135,7 +135,7 @@ hamls_status hamls_plan_rebind(hamls_plan_t plan, const double* nodes, int64_t M
 hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
                                double* grid_values, void* stream);
 
-/* Generating functions of MLS (Rem. 2.5), S2 plans.  The MLS value at a grid
+/* Generating functions of MLS (Rem. 2.5), all domains.  The MLS value at a grid
  * node is a linear functional of the data, M_y(q_j) = sum_i a*_ji y_i, whose
  * weights a*_ji depend on the nodes, the radius rule and the regularization
  * only (tau is chosen from the geometry, eq. (23)).  hamls_gen_build computes
@@ -144,7 +144,7 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
  * the plan as CSR over the grid (one entry per (grid node, neighbour) pair, 12
  * bytes); it synchronizes the stream once (the entry count sizes the
  * storage) and allocates on first use or growth.  A rebind invalidates them.
- * Errors: UNSUPPORTED for SO3 / T3 plans, OUT_OF_MEMORY, DEVICE. */
+ * Errors: OUT_OF_MEMORY, DEVICE. */
 hamls_status hamls_gen_build(hamls_plan_t plan, void* stream);
 
 /* hamls_mls_to_grid through the generating functions: grid_values[f][j] =

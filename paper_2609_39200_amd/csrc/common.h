@@ -265,9 +265,12 @@ hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double*
                                 const double* nu, int64_t M, hipStream_t s);
 hamls_status launch_grid_radius(const Plan& P, hipStream_t s);
 // form: < 0 the plan's tuned launch form, 0 grid order, 1 cost-ordered dispatch
+// split_only: one field, the Gram matrices handed on (no solve) at any m
 hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
-                             int form = -1);
-hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+                             int form = -1, bool split_only = false);
+hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                                 int unit_rhs = 0);
+hamls_status launch_grid_gen_values(const Plan& P, hipStream_t s);
 hamls_status launch_grid_list(const Plan& P, const int64_t* row_ptr, int32_t* counts, int32_t* idx,
                               hipStream_t s);
 

@@ -751,9 +751,10 @@ __global__ __launch_bounds__(64) void k_mls_solve(const double* __restrict__ gra
 // at this precision), z and omega rounded to doubles for tau and c_1.  A
 // pivot of the unit-diagonal C at or below kRankTol^2 (|R_jj| of the
 // unit-column V at or below kRankTol) or fewer than m neighbours: the weighted
-// mean (tau -> infinity).  UNIT: the F = m right-hand sides are the unit
-// vectors (the generating functions' gamma); a separate instantiation, so that
-// the fit's kernels keep their own register allocation.
+// mean (tau -> infinity).  UNIT: right-hand side f is the unit vector
+// e_{f0 + f} (the generating functions' gamma, F = m split into passes of at
+// most 16); a separate instantiation, so that the fit's kernels keep their own
+// register allocation.
 template <int m, bool UNIT = false>
 __device__ void mls_dd_epilogue(const double* Gh, const double* Gl, double* isc, int count, int F,
                                 int j, const SolveArgs& A) {
@@ -804,7 +805,7 @@ __device__ void mls_dd_epilogue(const double* Gh, const double* Gl, double* isc,
                 // right-hand sides of the unit-sum weights: the data scaled by
                 // 1/sqrt(W) (unit vectors for the generating functions)
                 const int e = EG + bc * F + (r - NC - 1);
-                const dd rhs = UNIT ? dd{bc == r - NC - 1 ? 1.0 : 0.0, 0.0} : dd{Gh[e], Gl[e]};
+                const dd rhs = UNIT ? dd{bc == A.f0 + r - NC - 1 ? 1.0 : 0.0, 0.0} : dd{Gh[e], Gl[e]};
                 v = dd_mul_d(dd_mul_d(rhs, sr), isc[bc]);
             }
             a[c] = v;
@@ -837,7 +838,7 @@ __device__ void mls_dd_epilogue(const double* Gh, const double* Gl, double* isc,
         // rank deficient: the tau -> infinity limit
         if (lane < F)
             A.out[(int64_t)(A.f0 + lane) * MQ + j] =
-                (UNIT ? (lane == 0 ? 1.0 : 0.0) : Gh[EG + lane] + Gl[EG + lane]) / W;
+                (UNIT ? (A.f0 + lane == 0 ? 1.0 : 0.0) : Gh[EG + lane] + Gl[EG + lane]) / W;
         if (lane == 0 && A.write_diag) {
             A.chi[j] = __builtin_inf();
             A.tau[j] = __builtin_inf();

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_gen_apply(const int64_t* __restrict__ r
 hamls_status launch_gen_solve(const Plan& P, hipStream_t s) {
     SolveArgs A = make_solve_args(P, P.m, 0, P.d_gamma);
     const double* G = P.d_entries;
-    // m + m lanes per node: groups of 16 up to m = 8, else 32
+    // m + m lanes per node: groups of 16 up to m = 8, 32 up to 16, else 64
 #define HAMLS_GS(MM, GS)                                                                   \
     hipLaunchKernelGGL((k_gen_solve<MM, GS>), dim3((unsigned)((P.MQ + 64 / GS - 1) / (64 / GS))), \
                        dim3(64), 0, s, G, A);
@@ -122,6 +122,7 @@ hamls_status launch_gen_solve(const Plan& P, hipStream_t s) {
         case 6: HAMLS_GS(6, 16) break;
         case 10: HAMLS_GS(10, 32) break;
         case 15: HAMLS_GS(15, 32) break;
+        case 20: HAMLS_GS(20, 64) break;
         default: set_error("no generating-function solve for m = %d", P.m); return HAMLS_ERR_UNSUPPORTED;
     }
 #undef HAMLS_GS

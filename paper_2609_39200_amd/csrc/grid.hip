@@ -623,7 +623,7 @@ __device__ __forceinline__ void monomials3(const double* u, double s, double* ro
 // right-hand-side entries (every lane reads valid row positions, so the
 // accumulation has no branches); the entries then go to LDS for the solve
 // epilogue (normalisation, Cholesky in registers, tau, c_1).
-template <int D, int K, int FM, bool DD, bool SPLIT = false>
+template <int D, int K, int FM, bool DD, bool SPLIT = false, bool UNIT = false>
 __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const GridGeom& g, const double* __restrict__ vals, int F,
                                                 int wendland, const double* __restrict__ thr,
                                                 const double* __restrict__ delta, const SolveArgs& A,
@@ -761,7 +761,7 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
             }
         }
         __syncthreads();
-        mls_dd_epilogue<m>(Gh, Gl, rows + 2 * (EG + m * FM), count, F, j, A);
+        mls_dd_epilogue<m, UNIT>(Gh, Gl, rows + 2 * (EG + m * FM), count, F, j, A);
         return;
     }
     if (lane == 0) nj[j] = count;
@@ -818,7 +818,7 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
 }
 
 
-template <int D, int K, int FM, bool DD, bool SPLIT = false>
+template <int D, int K, int FM, bool DD, bool SPLIT = false, bool UNIT = false>
 __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __restrict__ vals, int F,
                                                 int wendland, const double* __restrict__ thr,
                                                 const double* __restrict__ delta, SolveArgs A,
@@ -835,7 +835,8 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
         // the re-solve list: a grid-stride loop over the listed nodes
         const int n = *A.in_count;
         for (int li = blockIdx.x; li < n; li += gridDim.x) {
-            grid_node<D, K, FM, DD>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+            grid_node<D, K, FM, DD, false, UNIT>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj,
+                                                 entries_out);
             __syncthreads();
         }
     } else {
@@ -851,15 +852,13 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
 // place: handing on 230 entries a node costs more than it saves.
 template <int D, int K>
 static void grid_mls_launch(const Plan& P, const GridGeom& g, const SolveArgs& A, int F, int wl, hipStream_t s,
-                            const int32_t* order) {
+                            const int32_t* order, bool split_only) {
     constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
     const dim3 grid((unsigned)P.MQ), block(64);
-    if constexpr (m + 1 <= 16) {
-        if (F == 1) {
-            hipLaunchKernelGGL((k_grid_mls<D, K, 1, false, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr,
-                               P.d_delta, A, P.d_nj, P.d_entries, order);
-            return;
-        }
+    if (F == 1 && (m + 1 <= 16 || split_only)) {
+        hipLaunchKernelGGL((k_grid_mls<D, K, 1, false, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr,
+                           P.d_delta, A, P.d_nj, P.d_entries, order);
+        return;
     }
     if (F == 1)
         hipLaunchKernelGGL((k_grid_mls<D, K, 1, false>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta,
@@ -869,7 +868,8 @@ static void grid_mls_launch(const Plan& P, const GridGeom& g, const SolveArgs& A
                            P.d_thr, P.d_delta, A, P.d_nj, P.d_entries, order);
 }
 
-hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s, int form) {
+hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s, int form,
+                             bool split_only) {
     GridGeom g = make_grid_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     int wl = P.prm.wendland;
@@ -877,9 +877,9 @@ hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, 
     const int32_t* order = form == 1 ? P.d_order : nullptr;
 #define HAMLS_GMLS_D(KK)                                       \
     if (P.dom == HAMLS_SO3)                                    \
-        grid_mls_launch<4, KK>(P, g, A, F, wl, s, order);      \
+        grid_mls_launch<4, KK>(P, g, A, F, wl, s, order, split_only); \
     else                                                       \
-        grid_mls_launch<3, KK>(P, g, A, F, wl, s, order);
+        grid_mls_launch<3, KK>(P, g, A, F, wl, s, order, split_only);
     switch (P.K) {
         case 0: HAMLS_GMLS_D(0) break;
         case 1: HAMLS_GMLS_D(1) break;
@@ -894,14 +894,18 @@ hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, 
 
 // Re-solve of the nodes flagged by the FP64 epilogue: the same assembly in
 // double-double precision, blocks striding over the list.
-hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                                 int unit_rhs) {
     if (P.m <= 1) return HAMLS_OK;
     GridGeom g = make_grid_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
     dim3 grid(list_blocks(P.MQ)), block(64);
     int wl = P.prm.wendland;
 #define HAMLS_GDD(DDIM, KK)                                                                          \
-    if (F == 1)                                                                                      \
+    if (unit_rhs)                                                                                    \
+        hipLaunchKernelGGL((k_grid_mls<DDIM, KK, kMaxFieldsPerPass, true, false, true>), grid, block, 0, s, g, \
+                           P.d_vals, F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries, (const int32_t*)nullptr); \
+    else if (F == 1)                                                                                 \
         hipLaunchKernelGGL((k_grid_mls<DDIM, KK, 1, true>), grid, block, 0, s, g, P.d_vals, F, wl,      \
                            P.d_thr, P.d_delta, A, P.d_nj, P.d_entries, (const int32_t*)nullptr);     \
     else                                                                                             \
@@ -956,6 +960,83 @@ hamls_status launch_grid_list(const Plan& P, const int64_t* row_ptr, int32_t* co
     auto kern = P.dom == HAMLS_SO3 ? k_grid_list<4> : k_grid_list<3>;
     hipLaunchKernelGGL(kern, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.d_thr, P.d_delta, row_ptr,
                        counts, idx);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// Values a*_i = w_i sum_a gamma_a g_a(x_i) of the generating functions
+// (Rem. 2.5) at the members of grid node j, with the key, weight and tangent
+// monomials formed as in the assembly (grid_key, grid_local, monomials3);
+// entries in member order from row_ptr[j] (original node index perm[i] and
+// value).  gamma: m x MQ.
+template <int D, int K>
+__global__ __launch_bounds__(64) void k_grid_gen_values(GridGeom g, int wendland, const double* __restrict__ thr,
+                                                       const double* __restrict__ delta,
+                                                       const double* __restrict__ gamma, int64_t MQ,
+                                                       const int64_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ perm,
+                                                       int32_t* __restrict__ col, double* __restrict__ val) {
+    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
+    __shared__ int sh[kScanLds];
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
+    const double c = thr[j], dl = delta[j];
+    double gm[m];
+#pragma unroll
+    for (int a = 0; a < m; a++) gm[a] = gamma[(int64_t)a * MQ + j];
+    const int64_t base = row_ptr[j], end = row_ptr[j + 1];
+    int count = 0;
+    auto body = [&](const bool* valid, const int* idx) {
+        const int i = idx[0];
+        const double kv = valid[0] ? grid_key<D>(g, i, q) : -1e300;
+        const bool in = kv > c;
+        const uint64_t mk = __ballot(in);
+        if (in) {
+            double uu[3], w, mono[m];
+            grid_local<D>(g, i, q, kv, dl, wendland, uu, w);
+            monomials3<K>(uu, 1.0, mono);
+            double sum = 0.0;
+#pragma unroll
+            for (int a = 0; a < m; a++) sum = fma(gm[a], mono[a], sum);
+            const int64_t e = base + count + rank_below(mk);
+            if (e < end) {
+                col[e] = perm[i];
+                val[e] = w * sum;
+            }
+        }
+        count += __popcll(mk);
+    };
+    const int nl = g.mcnt ? g.mcnt[j] : -1;
+    if (nl >= 0)
+        grid_list_scan<1>(g.mlist + (int64_t)j * kListCap, nl, body);
+    else
+        grid_scan<D, 1>(g, q, grid_rho<D>(g, dl), sh, body);
+}
+
+hamls_status launch_grid_gen_values(const Plan& P, hipStream_t s) {
+    GridGeom g = make_grid_geom(P);
+    const dim3 grid((unsigned)P.MQ), block(64);
+    const int wl = P.prm.wendland;
+#define HAMLS_GGV(DDIM, KK)                                                                          \
+    hipLaunchKernelGGL((k_grid_gen_values<DDIM, KK>), grid, block, 0, s, g, wl, P.d_thr, P.d_delta,   \
+                       P.d_gamma, P.MQ, P.d_grow, P.d_perm, P.d_gcol, P.d_gval);
+#define HAMLS_GGV_D(KK)        \
+    if (P.dom == HAMLS_SO3) {  \
+        HAMLS_GGV(4, KK)       \
+    } else {                   \
+        HAMLS_GGV(3, KK)       \
+    }
+    switch (P.K) {
+        case 0: HAMLS_GGV_D(0) break;
+        case 1: HAMLS_GGV_D(1) break;
+        case 2: HAMLS_GGV_D(2) break;
+        case 3: HAMLS_GGV_D(3) break;
+        default: set_error("degree %d unsupported on SO(3)/T3", P.K); return HAMLS_ERR_UNSUPPORTED;
+    }
+#undef HAMLS_GGV_D
+#undef HAMLS_GGV
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

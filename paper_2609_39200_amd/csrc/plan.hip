@@ -965,24 +965,28 @@ hamls_status hamls_gen_build(hamls_plan_t plan, void* stream) {
         set_error("null plan");
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (P->dom != HAMLS_S2) {
-        set_error("generating functions are built for S2 plans only");
-        return HAMLS_ERR_UNSUPPORTED;
-    }
     hipStream_t s = (hipStream_t)stream;
+    const bool s2 = P->dom == HAMLS_S2;
     if (!P->d_gamma) {
         HAMLS_TRY(dalloc(*P, &P->d_gamma, (size_t)P->m * P->MQ));
         HAMLS_TRY(dalloc(*P, &P->d_grow, P->MQ + 1));
     }
     P->gen_ready = false;
     // the assembly pass reads one field of sorted values and the double-double
-    // re-solve m of them: zeros (their right-hand sides are replaced by unit
-    // vectors); the re-solve list starts empty
-    HAMLS_HIP(hipMemsetAsync(P->d_vals, 0, sizeof(double) * (size_t)P->m * P->cap, s));
+    // re-solve up to 16 of them: zeros (their right-hand sides are replaced by
+    // unit vectors); the re-solve list starts empty
+    HAMLS_HIP(hipMemsetAsync(P->d_vals, 0, sizeof(double) * (size_t)kMaxFieldsPerPass * P->cap, s));
     HAMLS_HIP(hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s));
-    HAMLS_TRY(launch_s2_assemble(*P, 1, 0, nullptr, s));
+    if (s2)
+        HAMLS_TRY(launch_s2_assemble(*P, 1, 0, nullptr, s));
+    else
+        HAMLS_TRY(launch_grid_mls(*P, 1, 0, nullptr, s, -1, true));
     HAMLS_TRY(launch_gen_solve(*P, s));
-    HAMLS_TRY(launch_s2_resolve(*P, P->m, 0, P->d_gamma, s, 1));
+    for (int f0 = 0; f0 < P->m; f0 += kMaxFieldsPerPass) {
+        const int Fc = std::min(kMaxFieldsPerPass, P->m - f0);
+        HAMLS_TRY(s2 ? launch_s2_resolve(*P, Fc, f0, P->d_gamma, s, 1)
+                     : launch_grid_resolve(*P, Fc, f0, P->d_gamma, s, 1));
+    }
     HAMLS_TRY(launch_gen_rowptr(*P, s));
     int64_t nnz = 0;
     HAMLS_HIP(hipMemcpyAsync(&nnz, P->d_grow + P->MQ, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1005,7 +1009,7 @@ hamls_status hamls_gen_build(hamls_plan_t plan, void* stream) {
         HAMLS_TRY(dalloc(*P, &P->d_gval, nnz));
         P->gen_cap = nnz;
     }
-    HAMLS_TRY(launch_s2_gen_values(*P, s));
+    HAMLS_TRY(s2 ? launch_s2_gen_values(*P, s) : launch_grid_gen_values(*P, s));
     P->gen_nnz = nnz;
     P->gen_ready = true;
     return HAMLS_OK;

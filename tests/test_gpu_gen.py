@@ -171,3 +171,65 @@ def test_generating_functions_full_size_and_rebind(H):
         assert _rell2(_fit(H, plan, v2, True), _fit(H, plan, v2, False)) <= TOL
     finally:
         H.hamls_plan_destroy(plan)
+
+
+GRID_CASES = [
+    ("so3-K2", "so3", dict(bandwidth=8, degree=2, knn_count=40), None),
+    ("so3-K3", "so3", dict(bandwidth=6, degree=3, knn_count=60), None),
+    ("t3-K3", "t3", dict(bandwidth=8, degree=3, knn_count=80, grid_shape=(16, 16, 16)), None),
+    ("t3-K2-fixed", "t3", dict(bandwidth=8, degree=2, knn_count=0, support_radius=0.12,
+                               grid_shape=(16, 16, 16)), None),
+    # half the nodes within 1e-7 of a sphere: near the shell the cubic
+    # monomials are nearly dependent (a quadratic identity), so supports are
+    # ill-conditioned and gamma comes from the double-double unit re-solve in
+    # two passes (16 + 4 right-hand sides)
+    ("t3-K3-shell-ill", "t3", dict(bandwidth=8, degree=3, knn_count=40, grid_shape=(16, 16, 16)), "shell"),
+]
+
+
+def _shell_torus(M, rng):
+    half = M // 2
+    v = rng.standard_normal((half, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    r = 0.3 + 1e-7 * rng.standard_normal((half, 1))
+    return np.concatenate([0.5 + r * v, rng.random((M - half, 3))]) % 1.0
+
+
+@pytest.mark.parametrize("label,domain,over,nodes", GRID_CASES, ids=[c[0] for c in GRID_CASES])
+def test_generating_functions_grid_domains(H, label, domain, over, nodes):
+    """SO(3) (records q and -q, tangent coordinates Im(conj(q) p)) and T3
+    (min-image differences), m = 10 and m = 20 (the double-double unit
+    re-solve in two passes of at most 16 right-hand sides)."""
+    rng = np.random.default_rng(31)
+    if nodes == "shell":
+        x = _shell_torus(20000, rng)
+    else:
+        x = W.clustered_rotations(20000, rng) if domain == "so3" else W.clustered_torus(20000, rng)
+    wp = dict(domain=domain, knn_eps=0.05, reg="chi", **over)
+    _say("gen", label)
+    p = H.params_from_workload(wp)
+    plan = H.hamls_plan(p, _dev(x))
+    try:
+        H.hamls_gen_build(plan)
+        rp, idx, val = H.hamls_gen_get(plan)
+        po = oracle.params(**wp)
+        g, _w = oracle.grid(po)
+        G = oracle.generating(po, g, x)
+        assert np.array_equal(rp, G["row_ptr"])
+        assert np.array_equal(idx, G["idx"])
+        err = _rell2(val, G["val"])
+        dg = H.hamls_diagnostics(plan)
+        _say(label, "nnz", int(rp[-1]), "rel l2", err, "ill", int(np.sum(dg["status"] & H.ST_ILLCOND != 0)))
+        assert err <= TOL
+        if "ill" in label:
+            assert np.any(dg["status"] & H.ST_ILLCOND)
+        vals = _dev(rng.standard_normal((3, x.shape[0])))
+        a = _fit(H, plan, vals, True)
+        b = _fit(H, plan, vals, False)
+        fit = oracle.mls(po, g, x, vals.cpu().numpy())
+        ok = np.isfinite(fit["values"][0])
+        assert np.array_equal(np.isfinite(a), np.isfinite(fit["values"]))
+        assert _rell2(a[:, ok], fit["values"][:, ok]) <= TOL
+        assert _rell2(a[:, ok], b[:, ok]) <= TOL
+    finally:
+        H.hamls_plan_destroy(plan)
