@@ -36,7 +36,7 @@ class OrcParams(C.Structure):
         ("chi_target", C.c_double),
         ("chi_full", C.c_double),
         ("grid_shape", C.c_int32 * 3),
-        ("pad_", C.c_int32),
+        ("smooth_aux", C.c_int32),
     ]
 
 
@@ -61,6 +61,8 @@ def lib():
         L.orc_neighbors.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
         L.orc_neighbor_lists.argtypes = [P(OrcParams), vp, vp, i64, vp, i64, vp, vp, vp]
         L.orc_mls.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, i32, i64, vp, vp, vp, vp, vp]
+        L.orc_fibonacci.argtypes = [C.c_int, vp]
+        L.orc_fibonacci.restype = None
         L.orc_generating.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_alf.argtypes = [C.c_int, d, vp]
         L.orc_alf.restype = None
@@ -84,7 +86,7 @@ def _ptr(a):
 
 def params(domain="s2", bandwidth=16, degree=2, support_radius=0.0, knn_count=0, knn_eps=0.05,
            wendland=1, reg="chi", tau_fixed=0.0, chi_target=10.0, chi_full=20.0, grid_shape=(0, 0, 0),
-           **_ignored) -> OrcParams:
+           smooth_aux=0, **_ignored) -> OrcParams:
     p = OrcParams()
     p.domain = _DOMAINS[domain]
     p.bandwidth = int(bandwidth)
@@ -97,6 +99,7 @@ def params(domain="s2", bandwidth=16, degree=2, support_radius=0.0, knn_count=0,
     p.tau_fixed = float(tau_fixed)
     p.chi_target = float(chi_target)
     p.chi_full = float(chi_full)
+    p.smooth_aux = int(smooth_aux)
     gs = list(grid_shape) + [0] * (3 - len(grid_shape))
     for k in range(3):
         p.grid_shape[k] = int(gs[k])
@@ -205,6 +208,13 @@ def generating(p: OrcParams, grid_pts, nodes, node_weights=None, rows=None):
         raise ValueError("orc_generating failed")
     n = int(rp[-1])
     return dict(row_ptr=rp, idx=idx[:n], val=val[:n], chi=chi, tau=tau, status=st)
+
+
+def fibonacci(n: int):
+    """The auxiliary Fibonacci grid of the smoothed radius (n x 3)."""
+    pts = np.zeros((n, 3))
+    lib().orc_fibonacci(int(n), _ptr(pts))
+    return pts
 
 
 def num_coeffs(p: OrcParams) -> int:

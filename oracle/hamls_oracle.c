@@ -65,7 +65,7 @@ typedef struct {
     double chi_target;      /* chi_T of Sec. 2.3 */
     double chi_full;        /* chi_full of Sec. 2.3 */
     int32_t grid_shape[3];  /* see orc_grid_dims */
-    int32_t pad_;
+    int32_t smooth_aux;     /* S2 adaptive radius smoothed on this many Fibonacci points; 0 off */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -372,15 +372,87 @@ static double select_kth(double* a, int64_t n, int64_t k, int asc)
  * S2 requires delta < pi/2 (tangent projection, Sec. 2.3); a larger radius is
  * clamped to pi/2 and flagged.  Threshold: S2 cos(delta); SO3 cos(delta/2);
  * T3 delta^2, where for the adaptive radius c = (1+eps)^2 d_n^2 directly. */
-static void centre_radius(const orc_params* p, const double* q, const double* nodes, int64_t M,
-                          double* keybuf, double* delta, double* c, uint8_t* st)
+/* ------------------------------------------------------------------ */
+/* smoothed adaptive radius (Sec. 2.2, after eq. (12))                 */
+/* ------------------------------------------------------------------ */
+
+/* Fibonacci grid of n points on S2 (the auxiliary grid): z_k = 1 - (2k+1)/n,
+ * longitude k times the golden angle pi (3 - sqrt 5). */
+void orc_fibonacci(int n, double* pts)
+{
+    const double ga = ORC_PI * (3.0 - sqrt(5.0));
+    for (int k = 0; k < n; k++) {
+        double z = 1.0 - (2.0 * k + 1.0) / n;
+        double r = sqrt((1.0 - z) * (1.0 + z));
+        double ph = ga * k;
+        pts[3 * k] = r * cos(ph);
+        pts[3 * k + 1] = r * sin(ph);
+        pts[3 * k + 2] = z;
+    }
+}
+
+/* d_n, the distance to the n-th nearest node, at every auxiliary point (brute
+ * force, as in centre_radius). */
+typedef struct {
+    int n;
+    double* pts;  /* n x 3 */
+    double* dn;   /* n */
+    double rs;    /* Shepard support radius: three mean spacings of the grid */
+} orc_aux;
+
+static void aux_build(const orc_params* p, const double* nodes, int64_t M, orc_aux* a)
+{
+    a->n = p->smooth_aux;
+    a->pts = malloc(sizeof(double) * 3 * (size_t)a->n);
+    a->dn = malloc(sizeof(double) * (size_t)a->n);
+    a->rs = 3.0 * sqrt(4.0 * ORC_PI / a->n);
+    orc_fibonacci(a->n, a->pts);
+#pragma omp parallel
+    {
+        double* kb = malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int k = 0; k < a->n; k++) {
+            for (int64_t i = 0; i < M; i++) kb[i] = prox_key(ORC_S2, nodes + 3 * i, a->pts + 3 * k);
+            a->dn[k] = key_distance(ORC_S2, select_kth(kb, M, p->knn_count - 1, 0));
+        }
+        free(kb);
+    }
+}
+
+static void aux_free(orc_aux* a)
+{
+    free(a->pts);
+    free(a->dn);
+}
+
+/* The degree-zero MLS (Shepard) approximation of d_n at q from the auxiliary
+ * values, Wendland weights of support a->rs (the plan's profile). */
+static double aux_smooth(const orc_params* p, const orc_aux* a, const double* q)
+{
+    double sw = 0.0, sv = 0.0;
+    for (int k = 0; k < a->n; k++) {
+        double d = key_distance(ORC_S2, prox_key(ORC_S2, a->pts + 3 * k, q));
+        double w = wendland(p->wendland, d / a->rs);
+        sw += w;
+        sv += w * a->dn[k];
+    }
+    return sv / sw;
+}
+
+/* The radius of one centre: fixed, adaptive, both (the larger), or (S2,
+ * smooth_aux > 0) the smoothed adaptive radius (1 + eps) * smoothed d_n. */
+static void centre_radius(const orc_params* p, const orc_aux* aux, const double* q, const double* nodes,
+                          int64_t M, double* keybuf, double* delta, double* c, uint8_t* st)
 {
     int dom = p->domain;
     int dimx = dom == ORC_SO3 ? 4 : 3;
     double dl = 0.0, cc = 0.0;
     int have = 0;
     *st = 0;
-    if (p->knn_count > 0) {
+    if (aux) {
+        dl = (1.0 + p->knn_eps) * aux_smooth(p, aux, q);
+        have = 1;
+    } else if (p->knn_count > 0) {
         for (int64_t i = 0; i < M; i++) keybuf[i] = prox_key(dom, nodes + dimx * i, q);
         double tn = select_kth(keybuf, M, p->knn_count - 1, dom == ORC_T3);
         if (dom == ORC_T3) {
@@ -427,6 +499,13 @@ int orc_neighbors(const orc_params* p, const double* grid, int64_t MQ, const int
     int dom = p->domain;
     int dimq = dom == ORC_SO3 ? 4 : 3;
     int64_t R = rows ? nrows : MQ;
+    orc_aux aux;
+    const orc_aux* auxp = NULL;
+    if (p->smooth_aux > 0) {
+        if (p->domain != ORC_S2 || p->knn_count <= 0) return -1;
+        aux_build(p, nodes, M, &aux);
+        auxp = &aux;
+    }
 #pragma omp parallel
     {
         double* kb = malloc(sizeof(double) * (size_t)(M > 0 ? M : 1));
@@ -436,7 +515,7 @@ int orc_neighbors(const orc_params* p, const double* grid, int64_t MQ, const int
             const double* q = grid + dimq * j;
             double dl, c;
             uint8_t st;
-            centre_radius(p, q, nodes, M, kb, &dl, &c, &st);
+            centre_radius(p, auxp, q, nodes, M, kb, &dl, &c, &st);
             int32_t cnt = 0;
             for (int64_t i = 0; i < M; i++)
                 if (key_inside(dom, prox_key(dom, nodes + dimq * i, q), c)) cnt++;
@@ -447,6 +526,7 @@ int orc_neighbors(const orc_params* p, const double* grid, int64_t MQ, const int
         }
         free(kb);
     }
+    if (auxp) aux_free(&aux);
     return 0;
 }
 
@@ -839,6 +919,13 @@ int orc_mls(const orc_params* p, const double* grid, int64_t MQ, const int64_t* 
     monomial_exponents(D, K, exps, degs);
     int dimq = dom == ORC_SO3 ? 4 : 3;
     int64_t R = rows ? nrows : MQ;
+    orc_aux aux;
+    const orc_aux* auxp = NULL;
+    if (p->smooth_aux > 0) {
+        if (p->domain != ORC_S2 || p->knn_count <= 0) return -1;
+        aux_build(p, nodes, M, &aux);
+        auxp = &aux;
+    }
 #pragma omp parallel
     {
         orc_work wk;
@@ -850,7 +937,7 @@ int orc_mls(const orc_params* p, const double* grid, int64_t MQ, const int64_t* 
             const double* q = grid + dimq * j;
             double dl, c;
             uint8_t st;
-            centre_radius(p, q, nodes, M, kb, &dl, &c, &st);
+            centre_radius(p, auxp, q, nodes, M, kb, &dl, &c, &st);
             int n = 0;
             for (int64_t i = 0; i < M; i++)
                 if (key_inside(dom, prox_key(dom, nodes + dimq * i, q), c)) n++;
@@ -866,6 +953,7 @@ int orc_mls(const orc_params* p, const double* grid, int64_t MQ, const int64_t* 
         work_free(&wk);
         free(kb);
     }
+    if (auxp) aux_free(&aux);
     return 0;
 }
 
@@ -893,6 +981,13 @@ int orc_generating(const orc_params* p, const double* grid, int64_t MQ, const in
     int dimq = dom == ORC_SO3 ? 4 : 3;
     int64_t R = rows ? nrows : MQ;
     int bad = 0;
+    orc_aux aux;
+    const orc_aux* auxp = NULL;
+    if (p->smooth_aux > 0) {
+        if (p->domain != ORC_S2 || p->knn_count <= 0) return -1;
+        aux_build(p, nodes, M, &aux);
+        auxp = &aux;
+    }
 #pragma omp parallel
     {
         orc_work wk;
@@ -904,7 +999,7 @@ int orc_generating(const orc_params* p, const double* grid, int64_t MQ, const in
             const double* q = grid + dimq * j;
             double dl, c;
             uint8_t st;
-            centre_radius(p, q, nodes, M, kb, &dl, &c, &st);
+            centre_radius(p, auxp, q, nodes, M, kb, &dl, &c, &st);
             int n = 0;
             for (int64_t i = 0; i < M; i++)
                 if (key_inside(dom, prox_key(dom, nodes + dimq * i, q), c)) n++;
@@ -925,6 +1020,7 @@ int orc_generating(const orc_params* p, const double* grid, int64_t MQ, const in
         work_free(&wk);
         free(kb);
     }
+    if (auxp) aux_free(&aux);
     return bad ? -1 : 0;
 }
 

@@ -692,3 +692,62 @@ def test_generating_applied_equals_fit():
         ok = np.diff(rp) > 0
         np.testing.assert_allclose(app[ok], fit["values"][f][ok], rtol=0, atol=1e-12 * np.abs(y).max() * 50)
     np.testing.assert_array_equal(G["status"], fit["status"])
+
+
+# ------------------------------------------------------------------ smoothed adaptive radius (Sec. 2.2)
+
+
+def test_fibonacci_grid():
+    """Unit vectors; z_k equally spaced in (-1, 1); longitude steps of the
+    golden angle; nearly uniform (every random point within 1.2 mean spacings
+    of the grid)."""
+    n = 2000
+    x = oracle.fibonacci(n)
+    np.testing.assert_allclose(np.linalg.norm(x, axis=1), 1.0, atol=1e-15)
+    np.testing.assert_allclose(np.diff(x[:, 2]), -2.0 / n, atol=1e-15)
+    ph = np.unwrap(np.arctan2(x[:, 1], x[:, 0]))
+    np.testing.assert_allclose(np.diff(ph) % (2 * math.pi), (math.pi * (3 - math.sqrt(5))) % (2 * math.pi),
+                               atol=1e-9)
+    probe = W.uniform_s2(20000, np.random.default_rng(3))
+    d, _ = cKDTree(x).query(probe)
+    assert 2 * np.arcsin(d.max() / 2) <= 1.2 * math.sqrt(4 * math.pi / n)
+
+
+def _dn_at(points, nodes, n):
+    d, _ = cKDTree(nodes).query(points, k=n)
+    return 2 * np.arcsin(np.minimum(d[:, -1], 2.0) / 2)
+
+
+def test_smoothed_radius_is_a_local_average_of_dn():
+    """delta/(1+eps) is a Wendland-weighted mean (degree-zero MLS) of d_n on the
+    auxiliary grid: it lies between the smallest and largest d_n of the
+    auxiliary points within the smoothing support (three mean spacings);
+    d_n here comes from cKDTree, independently of the oracle."""
+    rng = np.random.default_rng(61)
+    nodes = W.cluster_hole_s2(6000, rng, caps=W.random_caps(4, 15, 25, rng))
+    naux = 1500
+    p = oracle.params(domain="s2", bandwidth=10, degree=2, knn_count=24, knn_eps=0.05, smooth_aux=naux)
+    g, _ = oracle.grid(p)
+    nb = oracle.neighbors(p, g, nodes)
+    aux = oracle.fibonacci(naux)
+    dn = _dn_at(aux, nodes, 24)
+    rs = 3 * math.sqrt(4 * math.pi / naux)
+    ang = np.arccos(np.clip(g @ aux.T, -1, 1))
+    sm = nb["delta"] / 1.05
+    for j in range(g.shape[0]):
+        inside = ang[j] < rs
+        assert dn[inside].min() * (1 - 1e-12) <= sm[j] <= dn[inside].max() * (1 + 1e-12)
+    # smooth across neighbouring centres, unlike the raw d_n at the centres
+    raw = _dn_at(g, nodes, 24)
+    assert np.max(np.abs(np.diff(sm))) < np.max(np.abs(np.diff(raw)))
+
+
+def test_smoothed_radius_keeps_n_neighbours_on_a_fine_grid():
+    """With the auxiliary grid fine enough, (1 + eps) times the smoothed d_n
+    still exceeds d_n, so every support holds at least n nodes."""
+    rng = np.random.default_rng(62)
+    nodes = W.uniform_s2(8000, rng)
+    p = oracle.params(domain="s2", bandwidth=10, degree=2, knn_count=24, knn_eps=0.3, smooth_aux=20000)
+    g, _ = oracle.grid(p)
+    nb = oracle.neighbors(p, g, nodes)
+    assert nb["count"].min() >= 24
