@@ -82,7 +82,12 @@ typedef struct hamls_params {
     int32_t grid_shape[3];   /* 0 = the paper's minimal exact grid; otherwise checked for
                                 exactness. S2 (n_theta, n_phi, -), SO3 (n_beta, n_alpha,
                                 n_gamma), T3 (n, n, n) */
-    int32_t reserved;
+    int32_t smooth_aux;      /* S2, knn_count > 0, no fixed radius: > 0 smooths the adaptive
+                                radius (Sec. 2.2, after eq. (12)): d_n is evaluated on a
+                                Fibonacci grid of smooth_aux points and replaced by its
+                                degree-zero MLS approximation (Wendland weights, support
+                                three mean spacings sqrt(4 pi / smooth_aux)); delta = (1+eps)
+                                times that.  0: eq. (12) as it stands */
 } hamls_params;
 
 typedef struct hamls_plan_info {

@@ -107,6 +107,15 @@ struct Plan {
     uint32_t* d_hist = nullptr;
     int64_t hist_len = 0;
     int32_t* d_band_off = nullptr;
+    // smoothed adaptive radius: the auxiliary Fibonacci points (xyz, theta,
+    // phi, cos/sin theta) and their search outputs
+    double* d_aux = nullptr;
+    double* d_aux_theta = nullptr;
+    double* d_aux_phi = nullptr;
+    double* d_aux_cs = nullptr;
+    double* d_aux_thr = nullptr;
+    double* d_aux_delta = nullptr;
+    uint8_t* d_aux_rst = nullptr;
     int32_t* d_cell_start = nullptr;
     double* d_delta = nullptr;      // MQ
     double* d_thr = nullptr;        // MQ

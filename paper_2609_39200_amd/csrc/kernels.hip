@@ -619,6 +619,7 @@ S2Geom make_geom(const Plan& P) {
 //     narrowed (duplicates), a bitwise binary search over the key instead.
 // delta = (1+eps) arccos(t_n), merged with a fixed delta_0 if both are set,
 // clamped to pi/2 (the tangent projection needs delta < pi/2).
+template <bool AUX>
 __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
                                                  double delta0, double c_fixed, double* thr,
                                                  double* delta, uint8_t* rstatus, int32_t* mlist,
@@ -634,7 +635,8 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
     const int jb = xcd_block(blockIdx.x, gridDim.x);
     const int j = order ? order[jb] : jb;
     const int lane = threadIdx.x;
-    const int t = j / g.nphi, p = j - t * g.nphi;
+    // AUX: scattered points with their own angles (theta, phi, ring_cs per point)
+    const int t = AUX ? j : j / g.nphi, p = AUX ? j : j - t * g.nphi;
     const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
     const double thq = g.theta[t], phq = g.phi[p];
     const double cq = g.ring_cs[2 * t], sq = g.ring_cs[2 * t + 1];
@@ -893,6 +895,48 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
     }
 }
 
+// Smoothed adaptive radius (Sec. 2.2, after eq. (12)): d_n at the
+// auxiliary points (delta_aux / (1 + eps)) replaced at grid node j by its
+// degree-zero MLS approximation, Wendland weights of constant support rs;
+// delta_j = (1 + eps) times that, clamped below pi/2 (HEMISPHERE), threshold
+// cos(delta_j), members found by the assembly's scan (no list).  One wave per
+// grid node runs over all auxiliary points; only those inside the support
+// (dot > cos rs) need the arc length.
+__global__ __launch_bounds__(64) void k_s2_smooth_radius(const double* __restrict__ grid, int64_t MQ,
+                                                        const double* __restrict__ aux,
+                                                        const double* __restrict__ delta_aux, int naux,
+                                                        double eps, double rs, double crs, int wendland,
+                                                        double* __restrict__ thr, double* __restrict__ delta,
+                                                        uint8_t* __restrict__ rstatus, int32_t* __restrict__ mcnt) {
+    const int j = xcd_block(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x;
+    const double q0 = grid[3 * j], q1 = grid[3 * j + 1], q2 = grid[3 * j + 2];
+    const double ie = 1.0 / (1.0 + eps);
+    double sw = 0.0, sv = 0.0;
+    for (int k = lane; k < naux; k += 64) {
+        const double d = s2_dot(aux[3 * k], aux[3 * k + 1], aux[3 * k + 2], q0, q1, q2);
+        if (d > crs) {
+            const double w = wendland_phi(wendland, acos(fmin(d, 1.0)) / rs);
+            sw += w;
+            sv += w * (delta_aux[k] * ie);
+        }
+    }
+    sw = wave_sum(sw);
+    sv = wave_sum(sv);
+    if (lane == 0) {
+        double dl = (1.0 + eps) * (sv / sw);
+        uint8_t st = 0;
+        if (dl >= 0.5 * kPi) {
+            dl = 0.5 * kPi;
+            st = HAMLS_ST_HEMISPHERE;
+        }
+        thr[j] = cos(dl);
+        delta[j] = dl;
+        rstatus[j] = st;
+        if (mcnt) mcnt[j] = -1;
+    }
+}
+
 hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
     S2Geom g = make_geom(P);
     double d0 = P.prm.support_radius > 0.0 ? P.prm.support_radius : 0.0;
@@ -901,7 +945,29 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
     // the cost order of the assembly (member counts at tuning) also puts the
     // search's costly nodes (large covers, holes) first
     const int32_t* order = P.asm_queue_blocks == 1 ? P.d_order : nullptr;
-    hipLaunchKernelGGL(k_s2_radius, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
+    if (P.prm.smooth_aux > 0) {
+        // smoothed adaptive radius: d_n on the auxiliary Fibonacci grid (the
+        // same search, no member lists), then its degree-zero MLS at the nodes
+        S2Geom ga = g;
+        ga.grid = P.d_aux;
+        ga.theta = P.d_aux_theta;
+        ga.phi = P.d_aux_phi;
+        ga.ring_cs = P.d_aux_cs;
+        ga.nphi = 1;
+        ga.mlist = nullptr;
+        ga.mcnt = nullptr;
+        const int na = P.prm.smooth_aux;
+        hipLaunchKernelGGL(k_s2_radius<true>, dim3((unsigned)na), dim3(64), 0, s, ga, P.M, knn, P.prm.knn_eps, 0.0,
+                           2.0, P.d_aux_thr, P.d_aux_delta, P.d_aux_rst, (int32_t*)nullptr, (int32_t*)nullptr,
+                           (const int32_t*)nullptr);
+        const double rs = 3.0 * sqrt(4.0 * kPi / na);
+        hipLaunchKernelGGL(k_s2_smooth_radius, dim3((unsigned)P.MQ), dim3(64), 0, s, P.d_grid, P.MQ, P.d_aux,
+                           P.d_aux_delta, na, P.prm.knn_eps, rs, cos(rs), P.prm.wendland, P.d_thr, P.d_delta,
+                           P.d_rstatus, P.d_mcnt);
+        HAMLS_HIP(hipGetLastError());
+        return HAMLS_OK;
+    }
+    hipLaunchKernelGGL(k_s2_radius<false>, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
                        P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt, order);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;

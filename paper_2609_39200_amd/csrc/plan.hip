@@ -167,6 +167,14 @@ static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
         return HAMLS_ERR_INVALID_ARG;
     }
     int m = n_monomials(dom == HAMLS_S2 ? 2 : 3, p->degree);
+    if (p->smooth_aux < 0 || p->smooth_aux > (1 << 24)) {
+        set_error("smooth_aux outside [0, 2^24]");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (p->smooth_aux > 0 && (dom != HAMLS_S2 || p->knn_count <= 0 || p->support_radius > 0.0)) {
+        set_error("the smoothed radius needs an S2 plan with knn_count > 0 and no fixed radius");
+        return HAMLS_ERR_INVALID_ARG;
+    }
     if (!(p->support_radius > 0.0) && p->knn_count <= 0) {
         set_error("need a fixed support radius or knn_count");
         return HAMLS_ERR_INVALID_ARG;
@@ -550,6 +558,41 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     HAMLS_TRY(dalloc(P, &P.d_ring_cs, 2 * (size_t)nt));
     HAMLS_TRY(dalloc(P, &P.d_col_cs, 2 * (size_t)np));
     HAMLS_TRY(dalloc(P, &P.d_band_off, P.bins.nb + 1));
+    std::vector<double> aux, aux_th, aux_ph, aux_cs;
+    if (p->smooth_aux > 0) {
+        // the auxiliary Fibonacci grid of the smoothed radius: z_k = 1 -
+        // (2k+1)/n, longitude k times the golden angle pi (3 - sqrt 5)
+        const int na = p->smooth_aux;
+        const double ga = kPi * (3.0 - sqrt(5.0));
+        aux.resize(3 * (size_t)na);
+        aux_th.resize(na);
+        aux_ph.resize(na);
+        aux_cs.resize(2 * (size_t)na);
+        for (int k = 0; k < na; k++) {
+            const double z = 1.0 - (2.0 * k + 1.0) / na;
+            const double r = sqrt((1.0 - z) * (1.0 + z));
+            const double ph = ga * k;
+            aux[3 * k] = r * cos(ph);
+            aux[3 * k + 1] = r * sin(ph);
+            aux[3 * k + 2] = z;
+            aux_th[k] = acos(z);
+            aux_ph[k] = fmod(ph, 2.0 * kPi);
+            aux_cs[2 * k] = z;
+            aux_cs[2 * k + 1] = r;
+        }
+        HAMLS_TRY(dalloc(P, &P.d_aux, aux.size()));
+        HAMLS_TRY(dalloc(P, &P.d_aux_theta, aux_th.size()));
+        HAMLS_TRY(dalloc(P, &P.d_aux_phi, aux_ph.size()));
+        HAMLS_TRY(dalloc(P, &P.d_aux_cs, aux_cs.size()));
+        HAMLS_TRY(dalloc(P, &P.d_aux_thr, na));
+        HAMLS_TRY(dalloc(P, &P.d_aux_delta, na));
+        HAMLS_TRY(dalloc(P, &P.d_aux_rst, na));
+        HAMLS_HIP(hipMemcpyAsync(P.d_aux, aux.data(), sizeof(double) * aux.size(), hipMemcpyHostToDevice, s));
+        HAMLS_HIP(hipMemcpyAsync(P.d_aux_theta, aux_th.data(), sizeof(double) * na, hipMemcpyHostToDevice, s));
+        HAMLS_HIP(hipMemcpyAsync(P.d_aux_phi, aux_ph.data(), sizeof(double) * na, hipMemcpyHostToDevice, s));
+        HAMLS_HIP(hipMemcpyAsync(P.d_aux_cs, aux_cs.data(), sizeof(double) * aux_cs.size(), hipMemcpyHostToDevice,
+                                 s));
+    }
 
     // step-3 tables: Legendre table of the northern rings with the GL weights
     // folded in, and the ring twiddles
@@ -706,6 +749,16 @@ hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int3
         add(2 * (int64_t)nt, 8);
         add(2 * (int64_t)np, 8);
         add(P.bins.nb + 1, 4);
+        if (p->smooth_aux > 0) {
+            const int64_t nx = p->smooth_aux;
+            add(3 * nx, 8);
+            add(nx, 8);
+            add(nx, 8);
+            add(2 * nx, 8);
+            add(nx, 8);
+            add(nx, 8);
+            add(nx, 1);
+        }
         add((int64_t)th * na, 8);
         add(2 * (int64_t)np, 8);
         add((int64_t)F * nt * (N + 1) * 2, 8);

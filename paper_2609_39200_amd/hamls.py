@@ -52,7 +52,7 @@ class hamls_params(C.Structure):
         ("chi_target", C.c_double),
         ("chi_full", C.c_double),
         ("grid_shape", C.c_int32 * 3),
-        ("reserved", C.c_int32),
+        ("smooth_aux", C.c_int32),
     ]
 
 
@@ -323,7 +323,8 @@ def params_from_workload(wp: dict, **over) -> hamls_params:
               support_radius=float(wp.get("support_radius", 0.0)), knn_count=int(wp.get("knn_count", 0)),
               knn_eps=float(wp.get("knn_eps", 0.05)), reg=wp.get("reg", "chi"),
               tau_fixed=float(wp.get("tau_fixed", 0.0)), chi_target=float(wp.get("chi_target", 10.0)),
-              chi_full=float(wp.get("chi_full", 20.0)), grid_shape=tuple(wp.get("grid_shape", (0, 0, 0))))
+              chi_full=float(wp.get("chi_full", 20.0)), grid_shape=tuple(wp.get("grid_shape", (0, 0, 0))),
+              smooth_aux=int(wp.get("smooth_aux", 0)))
     kw.update(over)
     return hamls_params_init(**kw)
 

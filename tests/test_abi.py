@@ -80,6 +80,9 @@ int main(void){
         (dict(chi_target=5.0, chi_full=4.0), -1),
         (dict(knn_count=3, degree=2), -1),
         (dict(wendland=3), -1),
+        (dict(smooth_aux=-1), -1),
+        (dict(smooth_aux=1000, knn_count=0, support_radius=0.2), -1),
+        (dict(smooth_aux=1000, domain="so3"), -1),
     ],
 )
 def test_plan_rejects_bad_parameters_without_a_device(over, code):

@@ -74,7 +74,8 @@ def _collect(H, srv, n, timeout=60.0):
 
 @pytest.mark.parametrize(
     "domain,over,F",
-    [("s2", {}, 1), ("s2", dict(precision="mixed"), 3), ("so3", {}, 2), ("t3", {}, 1)],
+    [("s2", {}, 1), ("s2", dict(precision="mixed"), 3), ("s2", dict(smooth_aux=3000), 1), ("so3", {}, 2),
+     ("t3", {}, 1)],
 )
 def test_footprint_equals_resident_bytes(H, domain, over, F):
     import torch
