@@ -44,6 +44,9 @@ PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_asse
                 "gather": "k_gather_values"}
 
 WORKLOADS = {
+    "c2smooth": ("s2_clusters_smooth", "S2 ill-distributed (C2 nodes, M=200000), N=128, K=3, grid 129x258, smoothed "
+                 "adaptive radius: d_n (n=40) on 65536 Fibonacci points, degree-zero MLS at the grid, eps=0.05, "
+                 "chi_T=10 chi_full=20, F=1, FP64"),
     "c2fixed": ("s2_clusters_fixed", "S2 ill-distributed under a fixed radius (skewed neighbour counts 0-2400, "
                 "median 196), M=200000 (C2 nodes), N=128, K=3, grid 129x258, delta0=0.1 rad, chi_T=10 "
                 "chi_full=20, F=1, FP64"),

@@ -900,8 +900,10 @@ __global__ __launch_bounds__(64) void k_s2_radius(S2Geom g, int64_t M, int knn, 
 // degree-zero MLS approximation, Wendland weights of constant support rs;
 // delta_j = (1 + eps) times that, clamped below pi/2 (HEMISPHERE), threshold
 // cos(delta_j), members found by the assembly's scan (no list).  One wave per
-// grid node runs over all auxiliary points; only those inside the support
-// (dot > cos rs) need the arc length.
+// grid node.  The Fibonacci points are ordered by z (z_k = 1 - (2k+1)/n), so
+// those within rs of q lie in one index range, the band of polar angles
+// theta_q -/+ rs (widened by a margin and one index each way); only points
+// inside the support (dot > cos rs) need the arc length.
 __global__ __launch_bounds__(64) void k_s2_smooth_radius(const double* __restrict__ grid, int64_t MQ,
                                                         const double* __restrict__ aux,
                                                         const double* __restrict__ delta_aux, int naux,
@@ -912,8 +914,13 @@ __global__ __launch_bounds__(64) void k_s2_smooth_radius(const double* __restric
     const int lane = threadIdx.x;
     const double q0 = grid[3 * j], q1 = grid[3 * j + 1], q2 = grid[3 * j + 2];
     const double ie = 1.0 / (1.0 + eps);
+    const double thq = acos(fmin(fmax(q2, -1.0), 1.0));
+    const double z_hi = thq - rs - 1e-9 > 0.0 ? cos(thq - rs - 1e-9) : 1.0;
+    const double z_lo = thq + rs + 1e-9 < kPi ? cos(thq + rs + 1e-9) : -1.0;
+    const int k0 = max(0, (int)floor(0.5 * (1.0 - z_hi) * naux - 0.5) - 1);
+    const int k1 = min(naux - 1, (int)ceil(0.5 * (1.0 - z_lo) * naux - 0.5) + 1);
     double sw = 0.0, sv = 0.0;
-    for (int k = lane; k < naux; k += 64) {
+    for (int k = k0 + lane; k <= k1; k += 64) {
         const double d = s2_dot(aux[3 * k], aux[3 * k + 1], aux[3 * k + 2], q0, q1, q2);
         if (d > crs) {
             const double w = wendland_phi(wendland, acos(fmin(d, 1.0)) / rs);

@@ -321,6 +321,16 @@ def s2_clusters_fixed(seed: int = 2000, M: int = 200_000, N: int = 128, K: int =
     return wl
 
 
+def s2_clusters_smooth(seed: int = 2000, M: int = 200_000, N: int = 128, K: int = 3,
+                       smooth_aux: int = 65536) -> Workload:
+    """The S2 cluster + hole workload with the smoothed adaptive radius: d_n
+    on a Fibonacci grid of smooth_aux points, degree-zero MLS at the grid."""
+    wl = s2_clusters(seed=seed, M=M, N=N, K=K)
+    wl.params = dict(wl.params, smooth_aux=int(smooth_aux))
+    wl.name = f"s2-clusters-smooth{smooth_aux}-M{M}-N{N}-K{K}"
+    return wl
+
+
 def s2_large(seed: int = 3000, M: int = 4_000_000, N: int = 512, K: int = 4) -> Workload:
     """The large S2 case: the cluster + hole generator with 12 caps of radius
     10-25 degrees, field band-limited to degree 640 plus the smooth bump,
