@@ -368,9 +368,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_count(const uint32_t* __re
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of the digit-major histogram hist[d][block] in two steps:
-// block d scans its row in place and stores the row total; then one block
-// scans the 256 totals into the digit bases (the scatter adds both).
+// Exclusive scan of the digit-major histogram hist[d][block], first step:
+// block d scans its row in place and stores the row total; each scatter block
+// then scans the 256 totals into the digit bases and adds both.
 __global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ hist, int nblocks,
                                                    uint32_t* __restrict__ totals) {
     __shared__ uint32_t part[256];
@@ -397,20 +397,6 @@ __global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ hist, 
     if (t == 255) totals[blockIdx.x] = part[255];
 }
 
-__global__ __launch_bounds__(256) void k_scan_totals(uint32_t* __restrict__ totals) {
-    __shared__ uint32_t part[256];
-    const int t = threadIdx.x;
-    const uint32_t own = totals[t];
-    part[t] = own;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        uint32_t v = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    totals[t] = part[t] - own;
-}
 
 // Stable scatter of one 8-bit digit.  Items of a tile are taken in rounds of
 // 256 in input order; the rank of an item among equal digits is its rank in
@@ -419,11 +405,22 @@ __global__ __launch_bounds__(256) void k_scan_totals(uint32_t* __restrict__ tota
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, uint32_t* __restrict__ kout,
     int32_t* __restrict__ vout, int64_t n, int shift, const uint32_t* __restrict__ hist,
-    int nblocks, const uint32_t* __restrict__ digit_base) {
+    int nblocks, const uint32_t* __restrict__ totals) {
     __shared__ uint32_t off[256];
     __shared__ uint32_t cnt[4][256];
     int t = threadIdx.x, w = t >> 6;
-    off[t] = digit_base[t] + hist[(int64_t)t * nblocks + blockIdx.x];
+    // digit bases: every block scans the 256 digit totals itself (cheaper
+    // than a kernel of its own between the row scan and the scatter)
+    const uint32_t own = totals[t];
+    off[t] = own;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t v = t >= o ? off[t - o] : 0u;
+        __syncthreads();
+        off[t] += v;
+        __syncthreads();
+    }
+    off[t] += hist[(int64_t)t * nblocks + blockIdx.x] - own;
     int64_t base = (int64_t)blockIdx.x * RS_TILE;
     for (int r = 0; r < RS_ITEMS; r++) {
         int64_t i = base + (int64_t)r * RS_THREADS + t;
@@ -472,7 +469,6 @@ hamls_status radix_sort(Plan& P, int64_t M, hipStream_t s, int* final_buf) {
         hipLaunchKernelGGL(k_radix_count, dim3(nblocks), dim3(RS_THREADS), 0, s, P.d_key[cur], M,
                            shift, P.d_hist, nblocks);
         hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, s, P.d_hist, nblocks, totals);
-        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, s, totals);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(RS_THREADS), 0, s, P.d_key[cur],
                            P.d_idx[cur], P.d_key[cur ^ 1], P.d_idx[cur ^ 1], M, shift, P.d_hist,
                            nblocks, totals);
