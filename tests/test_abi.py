@@ -135,3 +135,16 @@ def test_server_calls_reject_null_handles():
     assert H._lib.hamls_server_load(None, None, None, None) == -1
     assert H._lib.hamls_server_destroy(None) == 0
     assert H.hamls_server_clock() >= 0.0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on exactly one GPU: --gpus 2 exits with a JSON message
+    before touching a device."""
+    import json
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
