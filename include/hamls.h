@@ -31,7 +31,7 @@ extern "C" {
 typedef enum {
     HAMLS_OK = 0,
     HAMLS_ERR_INVALID_ARG = -1,   /* argument outside its documented range */
-    HAMLS_ERR_UNSUPPORTED = -2,   /* valid request this build does not handle */
+    HAMLS_ERR_UNSUPPORTED = -2,   /* valid request the library does not handle */
     HAMLS_ERR_OUT_OF_MEMORY = -3, /* device or host allocation failed */
     HAMLS_ERR_DEVICE = -4,        /* HIP runtime error (message in hamls_last_error) */
     HAMLS_ERR_DOMAIN = -5,        /* geometric precondition violated */

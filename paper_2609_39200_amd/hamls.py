@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libhamls.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
-        "or `python paper_2609_39200_amd/build.py` (there is no CPU fallback)")
+        f"{LIB_PATH} is not built; run `python paper_2609_39200_amd/build.py` "
+        "(there is no CPU fallback)")
 
 _lib = C.CDLL(LIB_PATH)
 
