@@ -641,8 +641,16 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
     constexpr int NB = PB * (PB + 1) / 2;
     constexpr int GB = 64 / NB > 8 ? 8 : 64 / NB;
     constexpr bool BLK = FM == 1 && !DD && GB >= 1;
-    constexpr int RS = BLK ? 2 * PB : ROW;  // LDS row stride
+    // One FP64 field whose 2x2 blocks do not fit 64 lanes (m = 20): 3x3 blocks
+    // of the 21 columns of [V | y] (28 blocks), two interleaved member groups:
+    // six LDS reads feed nine FMAs (the packed-entry path: two reads per FMA)
+    constexpr int P3 = (m + 3) / 3;
+    constexpr int NB3 = P3 * (P3 + 1) / 2;
+    constexpr int GB3 = 64 / NB3 > 8 ? 8 : 64 / NB3;
+    constexpr bool BLK3 = FM == 1 && !DD && !BLK && (m + 1) % 3 == 0 && GB3 >= 2;
+    constexpr int RS = BLK ? 2 * PB : (BLK3 ? m + 1 : ROW);  // LDS row stride
     static_assert(!BLK || (RS <= ROW && RS % 2 == 0 && EG + 2 * m <= 64 * ROW - GB * NB * 4), "blocked LDS");
+    static_assert(!BLK3 || EG + 2 * m <= 64 * ROW - GB3 * NB3 * 9, "3x3 blocked LDS");
     const int lane = threadIdx.x;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -684,6 +692,17 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
         bJ = bI + rem;
     }
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    const int grp3 = lane / NB3, blk3 = lane - (lane / NB3) * NB3;
+    int cI = 0, cJ = 0;
+    {
+        int rem = blk3;
+        while (rem >= P3 - cI) {
+            rem -= P3 - cI;
+            cI++;
+        }
+        cJ = cI + rem;
+    }
+    double a9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int count = 0;
     auto body = [&](const bool* valid, const int* idx) {
         double kv[U], y1[U];
@@ -722,6 +741,23 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
                         a4[1] = fma(x.x, y.y, a4[1]);
                         a4[2] = fma(x.y, y.x, a4[2]);
                         a4[3] = fma(x.y, y.y, a4[3]);
+                    }
+                }
+            } else if (BLK3) {
+                if (grp3 < GB3) {
+                    for (int r = grp3; r < nin; r += GB3) {
+                        const double* rr = rows + r * RS;
+                        const double x0 = rr[3 * cI], x1 = rr[3 * cI + 1], x2 = rr[3 * cI + 2];
+                        const double z0 = rr[3 * cJ], z1 = rr[3 * cJ + 1], z2 = rr[3 * cJ + 2];
+                        a9[0] = fma(x0, z0, a9[0]);
+                        a9[1] = fma(x0, z1, a9[1]);
+                        a9[2] = fma(x0, z2, a9[2]);
+                        a9[3] = fma(x1, z0, a9[3]);
+                        a9[4] = fma(x1, z1, a9[4]);
+                        a9[5] = fma(x1, z2, a9[5]);
+                        a9[6] = fma(x2, z0, a9[6]);
+                        a9[7] = fma(x2, z1, a9[7]);
+                        a9[8] = fma(x2, z2, a9[8]);
                     }
                 }
             } else {
@@ -765,6 +801,38 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
         return;
     }
     if (lane == 0) nj[j] = count;
+    if (BLK3) {
+        // sum the groups' 3x3 blocks (lanes < NB3), then each block's entries
+        // of the upper triangle go to their packed places (y.y is not needed)
+        double* part = rows + 64 * ROW - GB3 * NB3 * 9;
+        if (grp3 < GB3) {
+#pragma unroll
+            for (int qq = 0; qq < 9; qq++) part[(grp3 * NB3 + blk3) * 9 + qq] = a9[qq];
+        }
+        __syncthreads();
+        double s9[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (lane < NB3) {
+            for (int g2 = 0; g2 < GB3; g2++) {
+#pragma unroll
+                for (int qq = 0; qq < 9; qq++) s9[qq] += part[(g2 * NB3 + lane) * 9 + qq];
+            }
+        }
+        double* dst = SPLIT ? entries_out + (int64_t)j * E : rows;
+        if (lane < NB3) {
+#pragma unroll
+            for (int qq = 0; qq < 9; qq++) {
+                const int a = 3 * cI + qq / 3, b = 3 * cJ + qq % 3;
+                if (a <= b && b <= m && a < m) {
+                    const int e = b < m ? a * m - a * (a - 1) / 2 + (b - a) : EG + a;
+                    dst[e] = s9[qq];
+                }
+            }
+        }
+        if (SPLIT) return;
+        __syncthreads();
+        mls_solve_epilogue<m>(rows, rows + EG + m * FM, count, F, j, A, entries_out);
+        return;
+    }
     if (BLK) {
         // sum the groups' blocks (lanes < NB), then each block's entries of
         // the upper triangle go to their packed places (y.y is not needed)
