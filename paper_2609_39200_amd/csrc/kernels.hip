@@ -1339,7 +1339,7 @@ hamls_status launch_cost_order(const Plan& P, hipStream_t s) {
     return HAMLS_OK;
 }
 
-// Mixed precision, one S2 node per wave (the benchmark spec's FP32 policy, Rem. 2.4):
+// Mixed precision, one S2 node per wave (FP32 assembly with FP64 safeguards, Rem. 2.4):
 //  1. FP32 pass: member rows (sqrt(w) g, sqrt(w) y) in FP32 (membership and
 //     coordinates in FP64), Gram and right-hand sides accumulated in FP32;
 //  2. FP64 factorisation of the FP32 system (as in the FP64 epilogue).  A node
