@@ -77,6 +77,16 @@ __device__ __forceinline__ int wave_incl_scan_int(int v) {
 // Ints of LDS one wave needs for s2_scan.
 constexpr int kScanLds = 4 * 64 + 1;
 
+// A wave-uniform double moved to scalar registers (bits unchanged).  The
+// support-radius searches hold their per-node state (centre, cap, histogram
+// parameters) this way, which frees the vector registers for occupancy.
+__device__ __forceinline__ double uni_d(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
     return v;

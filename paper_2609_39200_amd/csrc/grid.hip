@@ -307,20 +307,23 @@ hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double*
 
 // One grid node per block (one wave).  Adaptive radius: bracket a search
 // radius on the cell-cover count (cell table only), scan the box keeping the
-// keys of the ball, resize until it holds between n and kCandCap nodes, take
+// keys of the ball, resize until it holds between n and kGCap nodes, take
 // the n-th largest key exactly.  SO3: delta = (1+eps) 2 arccos(t_n), clamped
 // below pi, threshold cos(delta/2).  T3: threshold c = (1+eps)^2 d_n^2 on d^2
 // (no transcendental), delta = sqrt(c).  A fixed delta_0 is merged (larger
 // radius wins).  Thresholds are stored on the key: SO3 c, T3 -c.
 template <int D>
-__global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int knn, double eps,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_grid_radius(GridGeom g, int64_t M, int knn, double eps,
                                                    double wfac, double delta0, double* thr,
                                                    double* delta, uint8_t* rstatus, int32_t* mlist,
                                                    int32_t* mcnt, const int32_t* __restrict__ order) {
     constexpr int U = 4;
+    // 416 candidates keep the LDS at 8 KB, five waves per SIMD with 96 VGPRs
+    // (the wave-uniform state in scalar registers)
+    constexpr int kGCap = 416;
     constexpr int kBinCap = 128;
-    __shared__ __align__(16) double buf[kCandCap];
-    __shared__ int ibuf[kCandCap];  // record of each kept key
+    __shared__ __align__(16) double buf[kGCap];
+    __shared__ int ibuf[kGCap];  // record of each kept key
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
@@ -329,7 +332,7 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
     const int j = order ? order[jb] : jb;
     const int lane = threadIdx.x;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
+    for (int d = 0; d < D; d++) q[d] = uni_d(g.grid[(int64_t)D * j + d]);
     uint8_t st = 0;
     double dl = delta0;
     if (knn > 0) {
@@ -376,9 +379,14 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
         int* hist = (int*)binbuf;  // 256 ints
         for (int it = 0; it < 40 && !done; it++) {
             const double kr = grid_key_of_rho<D>(rho);
-            const double ulo = ktop < 2.0 ? khi - ktop : 0.0;
-            const double hs = 256.0 / fmax((khi - kr) - ulo, 1e-300);
-            const double u0 = khi - kr, ohs = 256.0 / fmax(15.0 * u0, 1e-300);
+            const double ulo = uni_d(ktop < 2.0 ? khi - ktop : 0.0);
+            const double hs = uni_d(256.0 / fmax((khi - kr) - ulo, 1e-300));
+            const double u0 = uni_d(khi - kr), ohs = uni_d(256.0 / fmax(15.0 * u0, 1e-300));
+            rho = uni_d(rho);
+            ktop = uni_d(ktop);
+            tn = uni_d(tn);
+            r_hi = uni_d(r_hi);
+            lkr = uni_d(lkr);
 #pragma unroll
             for (int qq = 0; qq < 4; qq++) {
                 hist[4 * lane + qq] = 0;
@@ -404,7 +412,7 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                     const uint64_t mk = __ballot(in);
                     const int pos = count + rank_below(mk);
                     if (in) {
-                        if (pos < kCandCap) {
+                        if (pos < kGCap) {
                             buf[pos] = kv[u];
                             ibuf[pos] = idx[u];
                         } else {
@@ -445,7 +453,7 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                     }
                     rho = fmin(nr, rhomax);
                 }
-            } else if (count <= kCandCap) {
+            } else if (count <= kGCap) {
                 tn = nth_largest(buf, count, knn - above, kr, fmin(ktop, khi), sh, binbuf, kBinCap);
                 done = true;
                 if (ktop >= 2.0) {
@@ -454,7 +462,7 @@ __global__ __launch_bounds__(64) void k_grid_radius(GridGeom g, int64_t M, int k
                 }
             } else {
                 // bin in the histogram of every key of (key(r), ktop)
-                for (int a = lane; a < kCandCap; a += 64) {
+                for (int a = lane; a < kGCap; a += 64) {
                     int bin = (int)((khi - buf[a] - ulo) * hs);
                     atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
                 }

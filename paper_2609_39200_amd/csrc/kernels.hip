@@ -605,17 +605,9 @@ S2Geom make_geom(const Plan& P) {
 // support radius (eq. (5), (6), (12))
 // ---------------------------------------------------------------------------
 
-// A wave-uniform double moved to scalar registers (bits unchanged).  The
-// search's per-node state (the centre, its angles, the cap and histogram
-// parameters) is uniform; held in SGPRs it lowers the search from 167 to 128
-// VGPRs, four waves per SIMD, with 20 spilled bytes per lane.
-__device__ __forceinline__ double uni_d(double x) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
+// The search keeps its wave-uniform state in scalar registers (uni_d): 128
+// VGPRs, four waves per SIMD, with 20 spilled bytes per lane (167 VGPRs and
+// three waves otherwise).
 // Support radius, one grid node per block (one wave):
 //  1. an initial radius from approximate cover counts of a ladder of caps
 //     (cell table only, no record reads);
