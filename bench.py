@@ -1,19 +1,21 @@
 #!/usr/bin/env python
 """Benchmark of the HAMLS hot path on one MI355X.
 
-Default workload (--workload c2): S2 ill-distributed nodes, M = 200,000 (8
-von Mises-Fisher clusters with kappa = 20 plus 20 % uniform, five 20-degree
-caps removed), bandwidth N = 128, MLS degree K = 3 (m = 10), Gauss-Legendre
-grid 129 x 258 (33,282 local solves), adaptive radius with n = 40, eps = 0.05,
-chi-target regularization (chi_T = 10, chi_full = 20), one field, FP64.
-Other workloads: c3 (S2, M = 4e6, N = 512, K = 4, grid 513 x 1026, n = 60),
-so3 (M = 1e6 rotations, N = 64, K = 2, Euler grid 130^3, n = 40), t3 (M = 2e6
-points, N = 64, K = 3, grid 128^3, n = 80).
+Default workload (--workload c3, the largest configuration): S2 ill-distributed
+nodes, M = 4,000,000 (8 von Mises-Fisher clusters with kappa = 20 plus 20 %
+uniform, twelve caps of radius 10-25 degrees removed), bandwidth N = 512, MLS
+degree K = 4 (m = 15), Gauss-Legendre grid 513 x 1026 (526,338 local solves),
+adaptive radius with n = 60, eps = 0.05, chi-target regularization (chi_T = 10,
+chi_full = 20), one field, FP64.
+Other workloads: c2 (S2, M = 2e5, N = 128, K = 3, grid 129 x 258, n = 40), so3
+(M = 1e6 rotations, N = 64, K = 2, Euler grid 130^3, n = 40), t3 (M = 2e6
+points, N = 64, K = 3, grid 128^3, n = 80), serve (the request loop).
 
 One step = one whole fit with the inputs resident in device memory:
 node binning + sort + support radii (plan rebind), the MLS value at every grid
-node (Gram assembly + regularized solve), the quadrature (ring DFTs + Legendre
-contraction on S2; axis DFTs + Wigner contraction on SO(3); 3-D DFT on T3).
+node (Gram assembly + regularized solve + extended-precision re-solve of the
+ill-conditioned centres), the quadrature (ring DFTs + Legendre contraction on
+S2; axis DFTs + Wigner contraction on SO(3); 3-D FFT on T3).
 value = grid nodes solved per second = M_Q * F * steps / wall time of the
 timed steps.  Prints one JSON line.
 """
@@ -30,7 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
-PEAK_FP32_VALU_TFLOPS = 157.3  # published FP32 vector peak (packed)
+# FP32 vector peak without packed FP32 instructions (which this build does not
+# use): one FP32 FMA per lane per cycle, the FP64 rate
+PEAK_FP32_VALU_TFLOPS = 78.6
+PEAK_FP32_MFMA_TFLOPS = 157.3  # dense FP32 matrix-core peak
 PEAK_HBM_GBS = 8000.0
 
 
@@ -39,9 +44,17 @@ def pct(a, q):
 
 
 # kernel (name prefix) of each phase's main launch, for the counter summary
-PHASE_KERNEL = {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble<",
-                "solve": "k_mls_solve<", "ring_dft": "k_s2_ring_dft", "contract": "k_s2_legendre",
-                "gather": "k_gather_values"}
+PHASE_KERNEL = {
+    "s2": {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble",
+           "solve": "k_mls_solve<", "resolve": "k_s2_assemble", "ring_dft": "k_s2_ring_dft",
+           "contract": "k_s2_legendre", "gather": "k_gather_values"},
+    "so3": {"binning": None, "radius": "k_grid_radius<4", "assemble": "k_grid_mls<4",
+            "solve": "k_mls_solve<", "resolve": "k_grid_mls<4", "ring_dft": "k_dft_axis",
+            "contract": "k_so3_contract", "gather": "k_gather_values"},
+    "t3": {"binning": None, "radius": "k_grid_radius<3", "assemble": "k_grid_mls<3",
+           "solve": "k_mls_solve<", "resolve": "k_grid_mls<3", "ring_dft": "k_t3",
+           "contract": None, "gather": "k_gather_values"},
+}
 
 WORKLOADS = {
     "c2smooth": ("s2_clusters_smooth", "S2 ill-distributed (C2 nodes, M=200000), N=128, K=3, grid 129x258, smoothed "
@@ -72,14 +85,17 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(workload, kernel):
     """HBM bytes per launch of the kernel whose name starts with `kernel` (the
-    FP64 variant) from the committed rocprofv3 counter summary (FETCH_SIZE and
-    WRITE_SIZE scaled by the copy calibration), or None when the HIP sources
-    changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "s2_c2_hbm_traffic.txt")
+    FP64 pass; the double-double re-solve when `resolve`) from the committed
+    rocprofv3 counter summary of this workload (FETCH_SIZE and WRITE_SIZE
+    scaled by the copy calibration), or None when there is none or the HIP
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.txt")
     if kernel is None or not os.path.exists(path):
         return None
+    resolve = kernel.startswith("resolve:")
+    kernel = kernel.split(":", 1)[-1]
     info = {}
     kern = {}
     for line in open(path):
@@ -95,38 +111,49 @@ def measured_traffic(kernel):
     if info.get("source_sha256") != source_sha256():
         return None
     for name, k in kern.items():
-        # the FP64 pass, not the double-double re-solve (third template argument)
+        # the double-double re-solve instantiations carry "true" as their
+        # third template argument
         targs = name[name.index("<") + 1:].rstrip(">").split(", ") if "<" in name else []
-        if name.startswith(kernel) and not (len(targs) > 2 and targs[2] == "true"):
+        dd = len(targs) > 2 and targs[2] == "true"
+        if name.startswith(kernel) and dd == resolve:
             return float(k["bytes"])
     return None
 
 
 def flops_per_pair(domain, m, F):
-    """Algorithmic FLOPs of one (grid node, neighbour) pair in the MLS step:
+    """Algorithmic FLOPs of one (grid node, neighbour) pair of the MLS step:
     membership key (S2 dot 5, SO3 dot 7, T3 min-image distance 12), tangent
-    coordinates (S2 12, SO3 24, T3 3), weight 10 (distance, Wendland, node
-    weight, square root), monomials and weighting 2m, Gram m(m+1), right-hand
+    coordinates (S2 12, SO3 24, T3 3), distance and Wendland weight ~40,
+    monomials m - 1, Gram m(m+1) (symmetric m x m, one FMA per entry), right-hand
     sides 2mF."""
     key = {"s2": 5, "so3": 7, "t3": 12}[domain]
     crd = {"s2": 12, "so3": 24, "t3": 3}[domain]
-    return key + crd + 10 + 2 * m + m * (m + 1) + 2 * m * F
+    return key + crd + 40 + (m - 1) + m * (m + 1) + 2 * m * F
+
+
+def flops_per_solve(m, F):
+    """Algorithmic FLOPs of one local solve: Cholesky of the order m-1 block
+    ((m-1)^3/3 FMA), two triangular solves per right-hand side, and the tau
+    search (64 steps of ~3m)."""
+    return 2 * (m - 1) ** 3 // 3 + 2 * (m - 1) ** 2 * (1 + F) + 64 * 3 * m
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["serve"],
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + ["serve"],
                     help="serve: the request loop (continuous batching) on the serving trace")
     ap.add_argument("--requests", type=int, default=512, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--slots", type=int, default=4, help="serve: worker streams of the server")
     ap.add_argument("--fields", type=int, default=1,
                     help="fields per fit: the workload's field plus seeded N(0,1) node values")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0,
+                    help="budget of the CPU oracle sample (all cores; a third of it on one core)")
+    ap.add_argument("--no-mfma", action="store_true", help="skip the F = 64 contraction measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy a 256 MiB buffer three times (known-size traffic for "
@@ -229,56 +256,36 @@ def main():
     n_reg = int(np.sum(diag["status"] & H.ST_REGULARIZED != 0))
     n_ill = int(np.sum(diag["status"] & H.ST_ILLCOND != 0))
 
-    # roofline of the dominant phase
+    # roofline of the dominant phase, priced on the method's algorithmic work
     m = info.m
+    illc = (diag["status"] & H.ST_ILLCOND) != 0
+    n_ill_pairs = int(diag["n"][illc].astype(np.int64).sum())
+    work = phase_work(domain, info, m, F, pairs, MQ, n_ill, n_ill_pairs)
+    wk = work.get(dom)
+    kern = PHASE_KERNEL[domain].get(dom)
+    if dom == "resolve" and kern:
+        kern = "resolve:" + kern
+    traffic = measured_traffic(args.workload, kern) if args.precision == "fp64" and F == 1 else None
     roof = None
-    traffic = (measured_traffic(PHASE_KERNEL.get(dom))
-               if args.workload == "c2" and args.precision == "fp64" and F == 1 else None)
-    if dom == "assemble":
-        fpp = flops_per_pair(domain, m, F)
-        fl = pairs * fpp
-        ach = fl / (phases[dom]["avg_ms"] * 1e-3) / 1e12
-        # the mixed pass is priced against the FP32 vector peak
-        peak = PEAK_FP64_VALU_TFLOPS if args.precision == "fp64" else PEAK_FP32_VALU_TFLOPS
-        roof = {"kernel": "assemble", "bound": "alu", "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic,
-                "units_per_launch": {"pairs": pairs, "flop_per_pair": fpp}}
-    else:
-        # other phases are priced on their algorithmic HBM bytes
-        Mn = info.num_nodes
-        nt, npf = info.grid_dims[0], info.grid_dims[1]
-        N = info.bandwidth
-        dimx = 4 if domain == "so3" else 3
-        nrec = 2 * Mn if domain == "so3" else Mn
-        rec = 8 * dimx
-        bytes_by_phase = {
-            # keys: read coordinates + write key and index; per radix pass
-            # 16 B (key + index, read + write); cell table; gather: index and
-            # coordinates read, coordinates and permutation written
-            "binning": Mn * 8 * dimx + nrec * (8 + 2 * 16 + 8 + 2 * (4 + rec)),
-            # every member record read once; radius, threshold, status, list
-            # length and the member lists written
-            "radius": pairs * (rec + 4) + MQ * 21,
-            "solve": MQ * (8 * (m * (m + 1) // 2 + m * F) + 4 + 8 * F + 17),
-            "gather": nrec * (4 + 16 * F),
-        }
-        if domain == "s2":
-            bytes_by_phase["ring_dft"] = MQ * 8 * F + nt * (N + 1) * 16 * F
-            bytes_by_phase["contract"] = (((nt + 1) // 2) * ((N + 1) * (N + 2) // 2) * 8
-                                          + (N + 1) ** 2 * 16 * F)
-        elif domain == "so3":
-            K2 = 2 * N + 1
-            nb, na, ng = info.grid_dims[0], info.grid_dims[1], info.grid_dims[2]
-            # alpha pass: real grid in, (k, gamma) spectra out; gamma pass
-            bytes_by_phase["ring_dft"] = F * nb * (na * ng * 8 + 2 * K2 * ng * 16 + K2 * K2 * 16)
-            bytes_by_phase["contract"] = nb * info.num_coeffs * 8 + F * (nb * K2 * K2 + info.num_coeffs) * 16
+    if wk is not None:
+        bound, amount = wk
+        sec = phases[dom]["avg_ms"] * 1e-3
+        if bound == "hbm":
+            ach = amount / sec / 1e9
+            roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "units_per_launch": {"bytes": amount}}
         else:
-            # three axis passes: real in / complex out, then complex in / out twice
-            bytes_by_phase["ring_dft"] = F * MQ * (8 + 16 + 4 * 16)
-        b = bytes_by_phase.get(dom, 0)
-        ach = b / (phases[dom]["avg_ms"] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "units_per_launch": {"bytes": b}}
+            peak = PEAK_FP64_VALU_TFLOPS if args.precision == "fp64" else PEAK_FP32_VALU_TFLOPS
+            ach = amount / sec / 1e12
+            roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                    "frac": ach / peak, "traffic": traffic, "units_per_launch": {"flop": amount}}
+    # the whole MLS step (radius + assembly + solve + re-solve) against the
+    # FP64 vector peak, on its algorithmic FLOPs
+    mls_ms = sum(phases[k]["avg_ms"] for k in ("radius", "assemble", "solve", "resolve") if k in phases)
+    mls_fl = pairs * flops_per_pair(domain, m, F) + MQ * flops_per_solve(m, F)
+    mls_roof = {"phases": "radius + assemble + solve + resolve", "ms": mls_ms, "flop": mls_fl,
+                "achieved": mls_fl / (mls_ms * 1e-3) / 1e12, "peak": PEAK_FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": mls_fl / (mls_ms * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS}
 
     out = {
         "metric": "MLS grid nodes solved/s (whole fit: binning + radii + local solves + quadrature)",
@@ -308,6 +315,7 @@ def main():
                   f"percentiles come from {nc} fits outside the timed region with every phase timed",
         "stats": {"pairs": pairs, "mean_neighbours": pairs / MQ, "regularized": n_reg, "illcond": n_ill},
         "roofline": roof,
+        "mls_step_roofline": mls_roof,
     }
     if tune is not None:
         out["assembly_launch"] = tune
@@ -315,6 +323,8 @@ def main():
     out["captured_fit"] = graph_bench(H, torch, plan, info, vals, K)
     out["generating_functions"] = gen_bench(H, torch, plan, info, vals, gv, stream, K, 1e3 * wall / K)
 
+    if domain == "s2" and not args.no_mfma:
+        out["contraction_f64"] = contraction_bench(H, torch, wl, 64, K)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["accuracy"] = cpu_baseline(wl, plan, gv, H, args.cpu_seconds)
     H.hamls_plan_destroy(plan)
@@ -326,6 +336,97 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel() * 8
     print(json.dumps(out), flush=True)
+
+
+def phase_work(domain, info, m, F, pairs, MQ, n_ill, n_ill_pairs):
+    """Algorithmic work of each phase's launch: ("hbm", bytes) or ("alu",
+    FLOPs).  Bytes count what the method must move once: coordinates and keys
+    of the binning passes, each sorted record read once by the radius search
+    plus its outputs, the DFT inputs and outputs, the Legendre / Wigner table
+    read once.  FLOPs count the pair and solve arithmetic of the centres a
+    launch handles."""
+    Mn = info.num_nodes
+    nt, npf = info.grid_dims[0], info.grid_dims[1]
+    N = info.bandwidth
+    dimx = 4 if domain == "so3" else 3
+    nrec = 2 * Mn if domain == "so3" else Mn
+    rec = 8 * dimx
+    w = {
+        # keys: read coordinates + write key and index; per radix pass 16 B
+        # (key + index, read + write); cell table; gather: index and
+        # coordinates read, coordinates and permutation written
+        "binning": ("hbm", Mn * 8 * dimx + nrec * (8 + 2 * 16 + 8 + 2 * (4 + rec))),
+        # every sorted record read once; radius, threshold and status written
+        "radius": ("hbm", nrec * rec + MQ * 17),
+        "assemble": ("alu", pairs * flops_per_pair(domain, m, F)),
+        "solve": ("alu", MQ * flops_per_solve(m, F)),
+        "resolve": ("alu", n_ill_pairs * flops_per_pair(domain, m, F) + n_ill * flops_per_solve(m, F)),
+        "gather": ("hbm", nrec * (4 + 16 * F)),
+    }
+    if domain == "s2":
+        w["ring_dft"] = ("hbm", MQ * 8 * F + nt * (N + 1) * 16 * F)
+        w["contract"] = ("hbm", ((nt + 1) // 2) * ((N + 1) * (N + 2) // 2) * 8 + (N + 1) ** 2 * 16 * F)
+    elif domain == "so3":
+        K2 = 2 * N + 1
+        nb, na, ng = info.grid_dims[0], info.grid_dims[1], info.grid_dims[2]
+        # alpha pass: real grid in, (k, gamma) spectra out; gamma pass
+        w["ring_dft"] = ("hbm", F * nb * (na * ng * 8 + 2 * K2 * ng * 16 + K2 * K2 * 16))
+        w["contract"] = ("hbm", nb * info.num_coeffs * 8 + F * (nb * K2 * K2 + info.num_coeffs) * 16)
+    else:
+        # real grid values in, complex coefficients out, one pass each
+        w["ring_dft"] = ("hbm", F * MQ * (8 + 16))
+    return w
+
+
+def contraction_bench(H, torch, wl, F, K):
+    """The S2 Legendre contraction at F fields on random grid values: the FP64
+    kernel of the plain path and the FP32 matrix-core kernel of the mixed path
+    (step 3 only; the contraction phase timed with HIP events).  FLOPs: for
+    every table entry w_t P_n^k(x_t) of the northern rings (after the
+    equatorial fold) and every field, one FMA each for the real and the
+    imaginary part of the folded spectrum."""
+    res = {"fields": F}
+    dev = torch.device("cuda:0")
+    nodes = torch.as_tensor(wl.nodes[: max(wl.params["knn_count"], 1000)], dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for prec in ("fp64", "mixed"):
+        p = H.params_from_workload(wl.params, precision=prec)
+        plan = H.hamls_plan(p, nodes, stream=stream)
+        try:
+            info = H.hamls_plan_info_get(plan)
+            g = torch.randn((F, info.num_grid), dtype=torch.float64, device=dev)
+            cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=dev)
+            H.hamls_grid_to_coeffs(plan, g, cf, stream=stream)
+            torch.cuda.synchronize()
+            H.hamls_timing_phases(plan, ["contract", "ring_dft"])
+            H.hamls_timing_enable(plan, True)
+            H.hamls_timing_read(plan, "contract")
+            H.hamls_timing_read(plan, "ring_dft")
+            for _ in range(K):
+                H.hamls_grid_to_coeffs(plan, g, cf, stream=stream)
+            n, ms = H.hamls_timing_read(plan, "contract")
+            nd, msd = H.hamls_timing_read(plan, "ring_dft")
+            H.hamls_timing_enable(plan, False)
+            N = info.bandwidth
+            th = (info.grid_dims[0] + 1) // 2
+            entries = th * (N + 1) * (N + 2) // 2
+            fl = 4 * entries * F
+            avg = ms / n
+            peak = PEAK_FP32_MFMA_TFLOPS if prec == "mixed" else PEAK_FP64_VALU_TFLOPS
+            res[prec] = {"kernel": "k_s2_legendre_mfma" if prec == "mixed" else "k_s2_legendre",
+                         "avg_ms": avg, "ring_dft_ms": msd / nd, "flop": fl,
+                         "achieved": fl / (avg * 1e-3) / 1e12, "unit": "TFLOP/s", "peak": peak,
+                         "frac": fl / (avg * 1e-3) / 1e12 / peak}
+            if prec == "mixed":
+                ref = res.get("_ref")
+                if ref is not None:
+                    res["mixed_rel_l2_vs_fp64"] = float(torch.linalg.norm(cf - ref) / torch.linalg.norm(ref))
+            else:
+                res["_ref"] = cf.clone()
+        finally:
+            H.hamls_plan_destroy(plan)
+    res.pop("_ref", None)
+    return res
 
 
 def graph_bench(H, torch, plan, info, vals, K):
@@ -522,24 +623,44 @@ def serve_bench(args, H, W, torch):
     }
 
 
+def _omp_threads(n):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp)."""
+    import ctypes
+
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
 def cpu_baseline(wl, plan, gv, H, budget_s):
     """The FP64 oracle (untuned) on a bounded sample of the same workload:
-    every s-th grid node for step 2 (brute-force neighbours + QR solves), and
-    the full step-3 quadrature (direct sums).  Extrapolated to the whole grid."""
+    whole rings of the grid, every s-th ring (s chosen to fit the budget; the
+    ring subset of the large configuration), for step 2 (brute-force
+    neighbours + QR solves) with all host cores, then a smaller sample on one
+    core; the full step-3 quadrature (direct sums) with all cores.  Both
+    extrapolated to the whole grid."""
     import oracle
 
     po = oracle.params(**wl.params)
-    opts, _ = oracle.grid(po)
-    MQ = opts.shape[0]
+    gpts, _ = H.hamls_plan_grid(plan)
+    MQ = gpts.shape[0]
+    dims = oracle.grid_dims(po)
+    ring = int(np.prod([d for d in dims[1:] if d > 0]))  # grid nodes per ring (first axis)
+    nrings = MQ // ring
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    probe = np.arange(0, MQ, max(1, MQ // 256))
+    _omp_threads(threads)
+    probe = np.arange(0, MQ, max(1, MQ // 128))
     t = time.perf_counter()
-    oracle.mls(po, opts, wl.nodes, wl.values, rows=probe)
+    oracle.mls(po, gpts, wl.nodes, wl.values, rows=probe)
     per_row = (time.perf_counter() - t) / probe.size
-    n_rows = int(min(MQ, max(probe.size, budget_s / max(per_row, 1e-9))))
-    rows = np.unique(np.linspace(0, MQ - 1, n_rows).astype(np.int64))
+    want = max(1, int(budget_s / max(per_row, 1e-9) / ring))  # rings that fit the budget
+    stride = max(1, -(-nrings // want))
+    rings = np.arange(0, nrings, stride)
+    rows = (rings[:, None] * ring + np.arange(ring)[None, :]).ravel()
     t = time.perf_counter()
-    om = oracle.mls(po, opts, wl.nodes, wl.values, rows=rows)
+    om = oracle.mls(po, gpts, wl.nodes, wl.values, rows=rows)
     t_mls = time.perf_counter() - t
     t = time.perf_counter()
     gcpu = gv.cpu().numpy()
@@ -551,12 +672,25 @@ def cpu_baseline(wl, plan, gv, H, budget_s):
     got = gcpu[:, rows]
     ok = ~np.isnan(ref[0])
     err = float(np.linalg.norm(got[:, ok] - ref[:, ok]) / np.linalg.norm(ref[:, ok]))
-    return (
-        {"value": MQ * F / t_fit, "unit": "grid nodes/s", "cores": threads, "kind": "oracle",
-         "sample": f"step 2 on {rows.size} of {MQ} grid nodes ({t_mls:.1f} s, extrapolated) + full step 3 "
-                   f"({t_quad:.1f} s); FP64 C oracle, OpenMP"},
-        {"rel_l2_vs_oracle_on_sample": err, "sample_rows": int(rows.size)},
-    )
+    emax = float(np.abs(got[:, ok] - ref[:, ok]).max() / np.abs(ref[:, ok]).max())
+    base = {"value": MQ * F / t_fit, "unit": "grid nodes/s", "cores": threads, "kind": "oracle",
+            "sample": f"step 2 on {rings.size} of {nrings} grid rings (every {stride}th ring, {rows.size} "
+                      f"grid nodes, {t_mls:.1f} s, extrapolated) + full step 3 ({t_quad:.1f} s); FP64 C "
+                      f"oracle, OpenMP, {threads} threads"}
+    # one core: a third of the budget, grid nodes spread over the grid
+    if _omp_threads(1):
+        n1 = int(min(MQ, max(16, budget_s / 3.0 / max(per_row * threads, 1e-9))))
+        rows1 = np.unique(np.linspace(0, MQ - 1, n1).astype(np.int64))
+        t = time.perf_counter()
+        oracle.mls(po, gpts, wl.nodes, wl.values, rows=rows1)
+        t1 = time.perf_counter() - t
+        _omp_threads(threads)
+        base["one_core"] = {"value": MQ * F / (t1 * MQ / rows1.size + t_quad * threads),
+                            "unit": "grid nodes/s", "cores": 1,
+                            "sample": f"step 2 on {rows1.size} grid nodes spread over the grid ({t1:.1f} s, "
+                                      f"extrapolated) + step 3 taken as {threads} x its all-core time"}
+    return base, {"rel_l2_vs_oracle_on_sample": err, "max_rel_vs_oracle_on_sample": emax,
+                  "sample_rows": int(rows.size)}
 
 
 if __name__ == "__main__":

@@ -121,7 +121,8 @@ hamls_status hamls_params_init(hamls_params* p);
  * The plan copies what it needs; nodes are not referenced after return.
  * Errors: INVALID_ARG (bad parameters), NOT_EXACT_GRID, DOMAIN (fixed
  * radius: S2 >= pi/2, SO3 > pi, T3 >= 1/2), UNSUPPORTED (mixed precision
- * outside S2, degree above 4 on S2 or 3 on SO3 / T3), OUT_OF_MEMORY, DEVICE. */
+ * outside S2, degree above 4 on S2 or 3 on SO3 / T3, knn_count above 512 on
+ * S2 or 416 on SO3 / T3), OUT_OF_MEMORY, DEVICE. */
 hamls_status hamls_plan(const hamls_params* p, const double* nodes, int64_t M,
                         const double* node_weights, void* stream, hamls_plan_t* out);
 
@@ -221,8 +222,10 @@ hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t q
  * Each hamls_graph_launch reads what values holds when it runs and rewrites
  * grid_values, coeffs and the diagnostics, with the same results as the
  * eager calls.  The graph refers to the plan's buffers: a rebind to the same
- * M keeps it valid; after a rebind to another M hamls_graph_launch returns
- * INVALID_ARG.  Destroy graphs before their plan. */
+ * M that keeps node weights present (or absent) keeps it valid; after a
+ * rebind to another M, or one that adds or drops node weights,
+ * hamls_graph_launch returns INVALID_ARG.  Destroy graphs before their
+ * plan. */
 typedef struct hamls_graph_s* hamls_graph_t;
 hamls_status hamls_fit_capture(hamls_plan_t plan, const double* values, int32_t F, int64_t ld,
                                double* grid_values, double* coeffs, void* stream, hamls_graph_t* out);
@@ -269,7 +272,8 @@ hamls_status hamls_diagnostics(hamls_plan_t plan, int32_t* n, double* chi, doubl
 #define HAMLS_PHASE_CONTRACT 5  /* step 3: Legendre / Wigner contraction */
 #define HAMLS_PHASE_GATHER 6    /* value gather into sorted order */
 #define HAMLS_PHASE_GEN_APPLY 7 /* sparse product with the generating functions */
-#define HAMLS_NUM_PHASES 8
+#define HAMLS_PHASE_RESOLVE 8   /* re-solve of the ill-conditioned centres (extended precision) */
+#define HAMLS_NUM_PHASES 9
 hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable);
 /* Restricts the timing to the phases whose bit (1 << phase) is set in mask
  * (every phase by default): events are recorded around those phases only,

@@ -25,7 +25,8 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
 constexpr int kMaxFieldsPerPass = 16;  // fields handled by one assembly pass
 constexpr int kRadixTile = 1024;       // keys per block of a radix sort pass
-constexpr int kCandCap = 512;          // LDS candidate buffer of the radius search
+constexpr int kCandCap = 512;          // LDS candidate buffer of the S2 radius search
+constexpr int kGridCandCap = 416;      // LDS candidate buffer of the SO3 / T3 radius search
 constexpr int kListCap = 128;          // S2 member list of a grid node (radius -> assembly)
 constexpr int kResolveBlocks = 131072; // most blocks of a list kernel (grid-stride)
 
@@ -158,7 +159,7 @@ struct Plan {
     double* d_work[2] = {nullptr, nullptr};
     int64_t work_len = 0;           // doubles per work buffer
     double* d_wtab = nullptr;
-    double* d_ring_w = nullptr;     // SO3 Gauss-Legendre weight per beta ring
+    double* d_ring_w = nullptr;     // Gauss-Legendre weight per ring (S2 theta, SO3 beta)
     // S2 mixed precision: FP32 contraction table in MFMA blocks, block offsets,
     // work items (k, parity, row tile), folded FP32 spectra
     float* d_ptab32 = nullptr;
@@ -263,8 +264,10 @@ hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx,
 hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStream_t s);
 hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s);
 hamls_status launch_s2_legendre_mfma(const Plan& P, int F, double* coeffs, hipStream_t s);
-hamls_status build_s2_mfma_table(Plan& P, std::vector<float>& tab, std::vector<int64_t>& off,
-                                 std::vector<int32_t>& items, const std::vector<double>& ptab_fp64);
+hamls_status build_s2_mfma_layout(Plan& P, std::vector<int64_t>& off, std::vector<int32_t>& items,
+                                  int64_t* len);
+hamls_status launch_s2_mfma_table(const Plan& P, int64_t len, hipStream_t s);
+hamls_status launch_s2_legendre_table(const Plan& P, hipStream_t s);
 hamls_status launch_s2_eval(const Plan& P, const double* coeffs, int F, const double* pts,
                             int64_t npts, double* out, hipStream_t s);
 

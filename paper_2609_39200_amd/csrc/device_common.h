@@ -36,6 +36,26 @@ __device__ __forceinline__ int xcd_block(int bid, int nblk) {
     return (g << 9) + ((bid & 7) << 6) + ((bid >> 3) & 63);
 }
 
+// Normalised associated Legendre functions through the Wigner small-d
+// functions d^n_{k0}(theta): P_n^k(cos theta) = sqrt((2n+1)/(4 pi)) d^n_{k0}
+// (orthonormal on S2, Condon-Shortley phase).  The edge value is
+// d^k_{k0} = prod_{j=1..k} (-sin theta) sqrt((2j-1)/(2j)), and d obeys the
+// three-term recurrence in the degree
+//   sqrt((n+1-k)(n+1+k)) d^{n+1} = (2n+1) cos(theta) d^n - sqrt((n-k)(n+k)) d^{n-1}.
+__device__ __forceinline__ double dk0_edge(int k, double s) {
+    double d = 1.0;
+    for (int j = 1; j <= k; j++) d *= -s * sqrt((2.0 * j - 1.0) / (2.0 * j));
+    return d;
+}
+
+__device__ __forceinline__ double dk0_next(int n, int k, double x, double d, double dm) {
+    const double lo = sqrt((double)(n - k) * (double)(n + k));
+    const double hi = sqrt((double)(n + 1 - k) * (double)(n + 1 + k));
+    return ((2.0 * n + 1.0) * x * d - lo * dm) / hi;
+}
+
+__device__ __forceinline__ double sh_norm(int n) { return sqrt((2.0 * n + 1.0) / (4.0 * kPi)); }
+
 __device__ __forceinline__ double wendland_phi(int which, double r) {
     if (r >= 1.0) return 0.0;
     double s = 1.0 - r;

@@ -320,7 +320,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     constexpr int U = 4;
     // 416 candidates keep the LDS at 8 KB, five waves per SIMD with 96 VGPRs
     // (the wave-uniform state in scalar registers)
-    constexpr int kGCap = 416;
+    constexpr int kGCap = kGridCandCap;
     constexpr int kBinCap = 128;
     __shared__ __align__(16) double buf[kGCap];
     __shared__ int ibuf[kGCap];  // record of each kept key

@@ -2140,13 +2140,47 @@ hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_
     return HAMLS_OK;
 }
 
+// Step-3 table of the northern rings t < ceil(nt/2):
+//   tab[t][n(n+1)/2 + k] = w_t P_n^k(x_t),
+// generated on the device from the ring cosines/sines and GL weights: one
+// block per order k, one thread per ring, the d^n_{k0} recurrence running
+// over the degree (the same trip count on every lane of a block).
+__global__ __launch_bounds__(256) void k_s2_legendre_table(const double* __restrict__ ring_cs,
+                                                          const double* __restrict__ ring_w, int th,
+                                                          int N, double* __restrict__ tab) {
+    const int k = blockIdx.x;
+    const int t = blockIdx.y * blockDim.x + threadIdx.x;
+    if (t >= th) return;
+    const int64_t na = (int64_t)(N + 1) * (N + 2) / 2;
+    const double x = ring_cs[2 * t], s = ring_cs[2 * t + 1], w = ring_w[t];
+    double* col = tab + (int64_t)t * na + k;
+    double d = dk0_edge(k, s), dm = 0.0;
+    for (int n = k; n <= N; n++) {
+        col[(int64_t)n * (n + 1) / 2] = w * sh_norm(n) * d;
+        if (n < N) {
+            const double nx = dk0_next(n, k, x, d, dm);
+            dm = d;
+            d = nx;
+        }
+    }
+}
+
+hamls_status launch_s2_legendre_table(const Plan& P, hipStream_t s) {
+    const int th = (P.dims[0] + 1) / 2;
+    dim3 grid((unsigned)(P.N + 1), (unsigned)((th + 255) / 256));
+    hipLaunchKernelGGL(k_s2_legendre_table, grid, dim3(256), 0, s, P.d_ring_cs, P.d_ring_w, th, P.N,
+                       P.d_ptab);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // synthesis
 // ---------------------------------------------------------------------------
 
 // out[f*P + i] = Re sum_{n,k} fhat_{n,k} P_n^{|k|}(cos th) (sign) e^{ik phi};
-// the normalised associated Legendre functions are generated on the fly by the
-// sectoral start P_k^k and the three-term recurrence in n.
+// the Legendre functions come from the d^n_{k0} recurrence (dk0_edge,
+// dk0_next) for each order k.
 __global__ __launch_bounds__(128) void k_s2_eval(const double* __restrict__ coeffs, int F, int N,
                                                 const double* __restrict__ pts, int64_t np,
                                                 double* __restrict__ out) {
@@ -2160,35 +2194,25 @@ __global__ __launch_bounds__(128) void k_s2_eval(const double* __restrict__ coef
     for (int f = 0; f < F; f++) {
         const double* cf = coeffs + (int64_t)f * nc * 2;
         double acc = 0.0;
-        double pkk = 1.0 / sqrt(4.0 * kPi);
+        double edge = 1.0;  // d^k_{k0}, updated order by order
         for (int k = 0; k <= N; k++) {
-            if (k > 0) pkk = -sqrt((2.0 * k + 1.0) / (2.0 * k)) * st * pkk;
-            double ck = cos(k * ph), sk = sin(k * ph);
-            double sg = (k & 1) ? -1.0 : 1.0;
-            double pm2 = 0.0, pm1 = pkk;
+            if (k > 0) edge *= -st * sqrt((2.0 * k - 1.0) / (2.0 * k));
+            const double ck = cos(k * ph), sk = sin(k * ph);
+            const double sg = (k & 1) ? -1.0 : 1.0;
+            double d = edge, dm = 0.0;
             for (int n = k; n <= N; n++) {
-                double pn;
-                if (n == k)
-                    pn = pkk;
-                else if (n == k + 1)
-                    pn = sqrt(2.0 * k + 3.0) * ct * pkk;
-                else {
-                    double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)k * k));
-                    double b = sqrt((((double)n - 1) * (n - 1) - (double)k * k) /
-                                    (4.0 * ((double)n - 1) * (n - 1) - 1.0));
-                    pn = a * (ct * pm1 - b * pm2);
-                }
-                if (n > k) {
-                    pm2 = pm1;
-                    pm1 = pn;
-                }
                 const double* c1 = cf + ((int64_t)n * n + n + k) * 2;
                 double v = c1[0] * ck - c1[1] * sk;
                 if (k > 0) {
                     const double* c2 = cf + ((int64_t)n * n + n - k) * 2;
                     v += sg * (c2[0] * ck + c2[1] * sk);
                 }
-                acc = fma(pn, v, acc);
+                acc = fma(sh_norm(n) * d, v, acc);
+                if (n < N) {
+                    const double nx = dk0_next(n, k, ct, d, dm);
+                    dm = d;
+                    d = nx;
+                }
             }
         }
         out[(int64_t)f * np + i] = acc;

@@ -10,6 +10,7 @@
 #include <new>
 
 #include "common.h"
+#include "host_geometry.h"
 
 namespace hamls {
 
@@ -68,74 +69,6 @@ static void drain_timing(Plan& P) {
 // ---------------------------------------------------------------------------
 // host geometry (step 1 of Alg. 1, Sec. 2.1)
 // ---------------------------------------------------------------------------
-
-// Gauss-Legendre rule with n nodes on [-1, 1]: Newton iteration on P_n from the
-// Chebyshev-like guess cos(pi (i + 3/4) / (n + 1/2)); nodes returned in
-// descending order (rings by increasing polar angle), mirrored exactly.
-static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
-    x.assign(n, 0.0);
-    w.assign(n, 0.0);
-    auto eval = [n](double z, double& pn, double& dpn) {
-        double pm = 1.0, pc = z;
-        if (n == 0) {
-            pn = 1.0;
-            dpn = 0.0;
-            return;
-        }
-        for (int k = 2; k <= n; k++) {
-            double pk = ((2.0 * k - 1.0) * z * pc - (k - 1.0) * pm) / k;
-            pm = pc;
-            pc = pk;
-        }
-        pn = pc;
-        dpn = n * (z * pc - pm) / (z * z - 1.0);
-    };
-    for (int i = 0; i < (n + 1) / 2; i++) {
-        double z = cos(kPi * (i + 0.75) / (n + 0.5));
-        double pn, dpn;
-        for (int it = 0; it < 100; it++) {
-            eval(z, pn, dpn);
-            double step = pn / dpn;
-            z -= step;
-            if (fabs(step) < 1e-15) {
-                eval(z, pn, dpn);
-                z -= pn / dpn;
-                break;
-            }
-        }
-        eval(z, pn, dpn);
-        double wi = 2.0 / ((1.0 - z * z) * dpn * dpn);
-        x[i] = z;
-        x[n - 1 - i] = -z;
-        w[i] = wi;
-        w[n - 1 - i] = wi;
-    }
-    if (n % 2 == 1) x[n / 2] = 0.0;
-}
-
-// Normalised associated Legendre functions (Condon-Shortley phase) at x for
-// 0 <= k <= n <= N, at n(n+1)/2 + k: sectoral start and three-term recurrence.
-static void alf_column(int N, double x, double* out) {
-    double s = sqrt((1.0 - x) * (1.0 + x));
-    double pkk = 1.0 / sqrt(4.0 * kPi);
-    for (int k = 0; k <= N; k++) {
-        if (k > 0) pkk = -sqrt((2.0 * k + 1.0) / (2.0 * k)) * s * pkk;
-        out[(size_t)k * (k + 1) / 2 + k] = pkk;
-        if (k == N) break;
-        double p1 = sqrt(2.0 * k + 3.0) * x * pkk;
-        out[(size_t)(k + 1) * (k + 2) / 2 + k] = p1;
-        double pm2 = pkk, pm1 = p1;
-        for (int n = k + 2; n <= N; n++) {
-            double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)k * k));
-            double b = sqrt((((double)n - 1.0) * (n - 1.0) - (double)k * k) /
-                            (4.0 * ((double)n - 1.0) * (n - 1.0) - 1.0));
-            double pn = a * (x * pm1 - b * pm2);
-            out[(size_t)n * (n + 1) / 2 + k] = pn;
-            pm2 = pm1;
-            pm1 = pn;
-        }
-    }
-}
 
 static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
     if (!p || p->struct_size != (int32_t)sizeof(hamls_params)) {
@@ -199,8 +132,9 @@ static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
         set_error("knn_count must be >= m = %d and knn_eps > 0", m);
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (p->knn_count > kCandCap) {
-        set_error("knn_count %d above %d", p->knn_count, kCandCap);
+    const int knn_cap = dom == HAMLS_S2 ? kCandCap : kGridCandCap;
+    if (p->knn_count > knn_cap) {
+        set_error("knn_count %d above %d (the radius search's candidate buffer)", p->knn_count, knn_cap);
         return HAMLS_ERR_UNSUPPORTED;
     }
     if (p->wendland != 1 && p->wendland != 2) {
@@ -425,16 +359,6 @@ static void twiddles(int n, std::vector<double>& tw) {
     }
 }
 
-// unit quaternion of the rotation R_z(a) R_y(b) R_z(g) (Euler ZYZ)
-static void euler_quaternion(double a, double b, double g, double* q) {
-    double cb = cos(0.5 * b), sb = sin(0.5 * b);
-    double sp = 0.5 * (a + g), dm = 0.5 * (a - g);
-    q[0] = cb * cos(sp);
-    q[1] = -sb * sin(dm);
-    q[2] = sb * cos(dm);
-    q[3] = cb * sin(sp);
-}
-
 // SO3 and T3 plans: the product grid of Sec. 2.1 (SO3: Gauss-Legendre in
 // cos(beta) x trapezoid in alpha and gamma; T3: the equispaced periodic grid),
 // the cell grid, and the quadrature tables (axis twiddles; SO3 Wigner table).
@@ -457,17 +381,26 @@ static hamls_status build_grid_plan(Plan& P, const double* nodes, int64_t M, int
     std::vector<double> tw0, tw1;
     if (so3) {
         const int nb = P.dims[0], na = P.dims[1], ng = P.dims[2];
-        gauss_legendre(nb, P.h_glx, P.h_glw);
+        geom::gauss_legendre_rule(nb, P.h_glx, P.h_glw);
         P.h_theta.resize(nb);
+        // the rotation R_z(alpha) R_y(beta) R_z(gamma) as the quaternion
+        // product q_z(alpha) q_y(beta) q_z(gamma)
+        std::vector<double> qa(4 * (size_t)na), qg(4 * (size_t)ng);
+        for (int a = 0; a < na; a++) geom::quat_rot_z(2.0 * kPi * a / na, &qa[4 * a]);
+        for (int g = 0; g < ng; g++) geom::quat_rot_z(2.0 * kPi * g / ng, &qg[4 * g]);
         for (int t = 0; t < nb; t++) {
             const double beta = acos(P.h_glx[t]);
             P.h_theta[t] = beta;
-            for (int a = 0; a < na; a++)
+            double qb[4], qab[4];
+            geom::quat_rot_y(beta, qb);
+            for (int a = 0; a < na; a++) {
+                geom::quat_mul(&qa[4 * a], qb, qab);
                 for (int g = 0; g < ng; g++) {
                     const int64_t j = ((int64_t)t * na + a) * ng + g;
-                    euler_quaternion(2.0 * kPi * a / na, beta, 2.0 * kPi * g / ng, &P.h_grid[4 * j]);
+                    geom::quat_mul(qab, &qg[4 * g], &P.h_grid[4 * j]);
                     P.h_wts[j] = P.h_glw[t] * (2.0 * kPi / na) * (2.0 * kPi / ng);
                 }
+            }
         }
         twiddles(na, tw0);
         twiddles(ng, tw1);
@@ -527,7 +460,7 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     P.cap = mcap;
 
     // grid: GL in cos(theta) x trapezoid in phi
-    gauss_legendre(nt, P.h_glx, P.h_glw);
+    geom::gauss_legendre_rule(nt, P.h_glx, P.h_glw);
     P.h_theta.resize(nt);
     P.h_phi.resize(np);
     P.h_grid.resize(3 * P.MQ);
@@ -556,6 +489,7 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
     HAMLS_TRY(dalloc(P, &P.d_theta, nt));
     HAMLS_TRY(dalloc(P, &P.d_phi, np));
     HAMLS_TRY(dalloc(P, &P.d_ring_cs, 2 * (size_t)nt));
+    HAMLS_TRY(dalloc(P, &P.d_ring_w, nt));
     HAMLS_TRY(dalloc(P, &P.d_col_cs, 2 * (size_t)np));
     HAMLS_TRY(dalloc(P, &P.d_band_off, P.bins.nb + 1));
     std::vector<double> aux, aux_th, aux_ph, aux_cs;
@@ -594,16 +528,12 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
                                  s));
     }
 
-    // step-3 tables: Legendre table of the northern rings with the GL weights
-    // folded in, and the ring twiddles
+    // step-3 tables: the Legendre table of the northern rings with the GL
+    // weights folded in (generated on the device below), and the ring
+    // twiddles
     int th = (nt + 1) / 2;
     int64_t na = (int64_t)(P.N + 1) * (P.N + 2) / 2;
     P.ptab_len = (int64_t)th * na;
-    std::vector<double> tab(P.ptab_len);
-    for (int t = 0; t < th; t++) {
-        alf_column(P.N, P.h_glx[t], tab.data() + (size_t)t * na);
-        for (int64_t i = 0; i < na; i++) tab[(size_t)t * na + i] *= P.h_glw[t];
-    }
     std::vector<double> tw(2 * (size_t)np);
     for (int q = 0; q < np; q++) {
         tw[q] = cphi[q];
@@ -627,26 +557,25 @@ static hamls_status build_plan(Plan& P, const hamls_params* p, const double* nod
         ccs[2 * q + 1] = sphi[q];
     }
     HAMLS_HIP(hipMemcpyAsync(P.d_ring_cs, rcs.data(), sizeof(double) * 2 * nt, hipMemcpyHostToDevice, s));
+    HAMLS_HIP(hipMemcpyAsync(P.d_ring_w, P.h_glw.data(), sizeof(double) * nt, hipMemcpyHostToDevice, s));
     HAMLS_HIP(hipMemcpyAsync(P.d_col_cs, ccs.data(), sizeof(double) * 2 * np, hipMemcpyHostToDevice, s));
     HAMLS_HIP(hipMemcpyAsync(P.d_band_off, P.bins.band_off.data(), sizeof(int32_t) * (P.bins.nb + 1),
                              hipMemcpyHostToDevice, s));
-    HAMLS_HIP(hipMemcpyAsync(P.d_ptab, tab.data(), sizeof(double) * P.ptab_len,
-                             hipMemcpyHostToDevice, s));
     HAMLS_HIP(hipMemcpyAsync(P.d_tw, tw.data(), sizeof(double) * 2 * np, hipMemcpyHostToDevice, s));
-    std::vector<float> tab32;
+    HAMLS_TRY(launch_s2_legendre_table(P, s));
     std::vector<int64_t> toff;
     std::vector<int32_t> titems;
     if (P.prm.precision == HAMLS_MIXED) {
-        HAMLS_TRY(build_s2_mfma_table(P, tab32, toff, titems, tab));
-        HAMLS_TRY(dalloc(P, &P.d_ptab32, tab32.size()));
+        int64_t len32 = 0;
+        HAMLS_TRY(build_s2_mfma_layout(P, toff, titems, &len32));
+        HAMLS_TRY(dalloc(P, &P.d_ptab32, len32));
         HAMLS_TRY(dalloc(P, &P.d_tab_off, toff.size()));
         HAMLS_TRY(dalloc(P, &P.d_leg_items, titems.size()));
-        HAMLS_HIP(hipMemcpyAsync(P.d_ptab32, tab32.data(), sizeof(float) * tab32.size(),
-                                 hipMemcpyHostToDevice, s));
         HAMLS_HIP(hipMemcpyAsync(P.d_tab_off, toff.data(), sizeof(int64_t) * toff.size(),
                                  hipMemcpyHostToDevice, s));
         HAMLS_HIP(hipMemcpyAsync(P.d_leg_items, titems.data(), sizeof(int32_t) * titems.size(),
                                  hipMemcpyHostToDevice, s));
+        HAMLS_TRY(launch_s2_mfma_table(P, len32, s));
     }
     // the host vectors above are pageable: make the copies complete before
     // they go out of scope
@@ -747,6 +676,7 @@ hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int3
         add(nt, 8);
         add(np, 8);
         add(2 * (int64_t)nt, 8);
+        add(nt, 8);
         add(2 * (int64_t)np, 8);
         add(P.bins.nb + 1, 4);
         if (p->smooth_aux > 0) {
@@ -883,8 +813,11 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
                 HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_assemble(*P, Fc, f0, grid_values, s)
                                              : launch_grid_mls(*P, Fc, f0, grid_values, s));
         }
-        PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
-        HAMLS_TRY(launch_split_solve(*P, Fc, f0, grid_values, s));
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
+            HAMLS_TRY(launch_split_solve(*P, Fc, f0, grid_values, s));
+        }
+        PhaseTimer pt(*P, HAMLS_PHASE_RESOLVE, s);
         HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_resolve(*P, Fc, f0, grid_values, s)
                                      : launch_grid_resolve(*P, Fc, f0, grid_values, s));
     }
@@ -1220,10 +1153,13 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
 }
 
 // A captured fit: steps 2 and 3 on one plan with fixed buffers, replayed as
-// one graph launch.
+// one graph launch.  The launch choices the host made at capture time from
+// the plan's binding (node count, whether node weights enter the kernels)
+// are recorded: a replay after a rebind that changes them is refused.
 struct hamls_graph_s {
     Plan* P;
     int64_t M;
+    bool has_nu;
     hipGraph_t g;
     hipGraphExec_t x;
 };
@@ -1266,7 +1202,7 @@ hamls_status hamls_fit_capture(hamls_plan_t plan, const double* values, int32_t 
         (void)hipGraphDestroy(g);
         return hip_status(e, "hipGraphInstantiate");
     }
-    hamls_graph_s* G = new (std::nothrow) hamls_graph_s{P, P->M, g, x};
+    hamls_graph_s* G = new (std::nothrow) hamls_graph_s{P, P->M, P->has_nu, g, x};
     if (!G) {
         (void)hipGraphExecDestroy(x);
         (void)hipGraphDestroy(g);
@@ -1285,6 +1221,11 @@ hamls_status hamls_graph_launch(hamls_graph_t graph, void* stream) {
     if (graph->P->M != graph->M) {
         set_error("the plan was rebound to %lld nodes since the capture (%lld)", (long long)graph->P->M,
                   (long long)graph->M);
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (graph->P->has_nu != graph->has_nu) {
+        set_error("the plan was rebound %s node weights since the capture (captured %s them)",
+                  graph->P->has_nu ? "with" : "without", graph->has_nu ? "with" : "without");
         return HAMLS_ERR_INVALID_ARG;
     }
     HAMLS_HIP(hipGraphLaunch(graph->x, (hipStream_t)stream));

@@ -146,12 +146,48 @@ hamls_status launch_s2_legendre_mfma(const Plan& P, int F, double* coeffs, hipSt
     return HAMLS_OK;
 }
 
-// Host: the FP32 table blocks, their offsets and the work items.
-hamls_status build_s2_mfma_table(Plan& P, std::vector<float>& tab, std::vector<int64_t>& off,
-                                 std::vector<int32_t>& items, const std::vector<double>& ptab_fp64) {
+// FP32 table blocks from the resident FP64 table (which holds
+// w_t P_n^k(x_t) at [t][n(n+1)/2 + k]): block (k, p) at off[2k + p] is
+// [t < th_pad][row < R_pad], row r <-> degree n = k + p + 2r, zero padding.
+__global__ __launch_bounds__(256) void k_s2_mfma_table(const double* __restrict__ tab64,
+                                                      const int64_t* __restrict__ off, int th, int th_pad,
+                                                      int N, float* __restrict__ tab32) {
+    const int kp = blockIdx.y;
+    const int k = kp >> 1, p = kp & 1;
+    const int R = N >= k + p ? (N - k - p) / 2 + 1 : 0;
+    const int R_pad = (R + 15) & ~15;
+    const int64_t na = (int64_t)(N + 1) * (N + 2) / 2;
+    const int64_t len = (int64_t)th_pad * R_pad;
+    float* blk = tab32 + off[kp];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < len;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(e / R_pad), r = (int)(e - (int64_t)t * R_pad);
+        float v = 0.0f;
+        if (t < th && r < R) {
+            const int n = k + p + 2 * r;
+            v = (float)tab64[(int64_t)t * na + (int64_t)n * (n + 1) / 2 + k];
+        }
+        blk[e] = v;
+    }
+}
+
+hamls_status launch_s2_mfma_table(const Plan& P, int64_t len, hipStream_t s) {
+    (void)len;
     const int nt = P.dims[0], N = P.N;
     const int th = (nt + 1) / 2, th_pad = (th + 3) & ~3;
-    const int64_t na = (int64_t)(N + 1) * (N + 2) / 2;
+    dim3 grid(16u, (unsigned)(2 * (N + 1)));
+    hipLaunchKernelGGL(k_s2_mfma_table, grid, dim3(256), 0, s, P.d_ptab, P.d_tab_off, th, th_pad, N,
+                       P.d_ptab32);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+// Host: offsets of the FP32 table blocks, their total length and the work
+// items.
+hamls_status build_s2_mfma_layout(Plan& P, std::vector<int64_t>& off, std::vector<int32_t>& items,
+                                  int64_t* len) {
+    const int nt = P.dims[0], N = P.N;
+    const int th = (nt + 1) / 2, th_pad = (th + 3) & ~3;
     off.assign(2 * (size_t)(N + 1), 0);
     int64_t total = 0;
     items.clear();
@@ -168,20 +204,8 @@ hamls_status build_s2_mfma_table(Plan& P, std::vector<float>& tab, std::vector<i
                 items.push_back(0);
             }
         }
-    tab.assign((size_t)total, 0.0f);
-    for (int k = 0; k <= N; k++)
-        for (int p = 0; p < 2; p++) {
-            const int R = N >= k + p ? (N - k - p) / 2 + 1 : 0;
-            const int R_pad = (R + 15) & ~15;
-            float* blk = tab.data() + off[2 * k + p];
-            for (int t = 0; t < th; t++)
-                for (int r = 0; r < R; r++) {
-                    const int n = k + p + 2 * r;
-                    // the FP64 table holds w_t P_n^k(x_t) at [t][n(n+1)/2 + k]
-                    blk[(int64_t)t * R_pad + r] = (float)ptab_fp64[(size_t)t * na + (size_t)n * (n + 1) / 2 + k];
-                }
-        }
     P.leg_items = (int64_t)items.size() / 4;
+    *len = total;
     return HAMLS_OK;
 }
 

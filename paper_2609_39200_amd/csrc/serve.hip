@@ -36,16 +36,19 @@ double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// Parameters that make two plans interchangeable (grid, tables, radius rule,
-// weights, regularization, precision).
+// Parameters that make two plans interchangeable: every field of
+// hamls_params (grid, tables, radius rule including the smoothed radius,
+// weights, regularization, precision).  A field added to hamls_params must be
+// added here; the static_assert below fails when the struct changes size.
 bool same_params(const hamls_params& a, const hamls_params& b) {
+    static_assert(sizeof(hamls_params) == 88, "hamls_params changed: update same_params");
     return a.domain == b.domain && a.bandwidth == b.bandwidth && a.degree == b.degree &&
            a.support_radius == b.support_radius && a.knn_count == b.knn_count &&
            a.wendland == b.wendland && a.knn_eps == b.knn_eps && a.reg == b.reg &&
            a.precision == b.precision && a.tau_fixed == b.tau_fixed &&
            a.chi_target == b.chi_target && a.chi_full == b.chi_full &&
            a.grid_shape[0] == b.grid_shape[0] && a.grid_shape[1] == b.grid_shape[1] &&
-           a.grid_shape[2] == b.grid_shape[2];
+           a.grid_shape[2] == b.grid_shape[2] && a.smooth_aux == b.smooth_aux;
 }
 
 // Node capacity of a new plan: the next power of two, at least 16384.

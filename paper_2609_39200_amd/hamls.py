@@ -287,7 +287,7 @@ def hamls_diagnostics(plan: int):
 
 
 PHASES = {"binning": 0, "radius": 1, "assemble": 2, "solve": 3, "ring_dft": 4, "contract": 5, "gather": 6,
-          "gen_apply": 7}
+          "gen_apply": 7, "resolve": 8}
 
 
 def hamls_timing_enable(plan: int, enable: bool = True):

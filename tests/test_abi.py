@@ -83,6 +83,9 @@ int main(void){
         (dict(smooth_aux=-1), -1),
         (dict(smooth_aux=1000, knn_count=0, support_radius=0.2), -1),
         (dict(smooth_aux=1000, domain="so3"), -1),
+        (dict(knn_count=513), -2),
+        (dict(domain="so3", knn_count=417), -2),
+        (dict(domain="t3", knn_count=417, grid_shape=(33, 33, 33)), -2),
     ],
 )
 def test_plan_rejects_bad_parameters_without_a_device(over, code):

@@ -80,7 +80,7 @@ def test_generating_functions_match_oracle(H, label, kw, over, weights):
         H.hamls_gen_build(plan)
         rp, idx, val = H.hamls_gen_get(plan)
         po = oracle.params(**wp)
-        g, _ = oracle.grid(po)
+        g, _ = H.hamls_plan_grid(plan)  # the library's exported grid
         G = oracle.generating(po, g, wl.nodes, node_weights=nu)
         assert np.array_equal(rp, G["row_ptr"])
         assert np.array_equal(idx, G["idx"])
@@ -120,7 +120,7 @@ def test_generating_functions_fixed_radius_holes(H):
         H.hamls_gen_build(plan)
         rp, idx, val = H.hamls_gen_get(plan)
         po = oracle.params(**wp)
-        g, _ = oracle.grid(po)
+        g, _ = H.hamls_plan_grid(plan)  # the library's exported grid
         G = oracle.generating(po, g, x)
         assert np.array_equal(rp, G["row_ptr"]) and np.array_equal(idx, G["idx"])
         assert np.any(np.diff(rp) == 0)
@@ -157,7 +157,7 @@ def test_generating_functions_full_size_and_rebind(H):
         _say("gen full size vs fit", err)
         assert err <= TOL
         po = oracle.params(**wl.params)
-        g, _ = oracle.grid(po)
+        g, _ = H.hamls_plan_grid(plan)  # the library's exported grid
         rows = np.random.default_rng(4).choice(g.shape[0], 48, replace=False)
         fit = oracle.mls(po, g, wl.nodes, vals[:2].cpu().numpy(), rows=rows)
         assert _rell2(a[:2, rows], fit["values"]) <= TOL
@@ -213,7 +213,7 @@ def test_generating_functions_grid_domains(H, label, domain, over, nodes):
         H.hamls_gen_build(plan)
         rp, idx, val = H.hamls_gen_get(plan)
         po = oracle.params(**wp)
-        g, _w = oracle.grid(po)
+        g, _w = H.hamls_plan_grid(plan)  # the library's exported grid
         G = oracle.generating(po, g, x)
         assert np.array_equal(rp, G["row_ptr"])
         assert np.array_equal(idx, G["idx"])

@@ -12,6 +12,8 @@ import pytest
 import oracle
 from paper_2609_39200_amd import workloads as W
 
+import _parity as PAR
+
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
@@ -66,13 +68,14 @@ def _check(H, wl, rows=None, nu=None, label=""):
         gpts, gw = H.hamls_plan_grid(plan)
         po = oracle.params(**wl.params)
         opts, ow = oracle.grid(po)
-        assert gpts.shape == opts.shape
-        assert np.abs(gpts - opts).max() < 1e-15
-        assert np.abs(gw - ow).max() < 1e-15 * max(1.0, ow.max())
-        _say(f"  grid points bitwise equal: {int(np.sum(np.all(gpts == opts, axis=1)))}/{gpts.shape[0]}")
+        # the library builds the SO3 grid as quaternion products
+        # q_z(alpha) q_y(beta) q_z(gamma) over its own Gauss-Legendre rule, the
+        # oracle from the closed form; they agree to rounding, and both sides
+        # then work on the library's exported points
+        _say("  grid: " + PAR.check_grids(gpts, gw, opts, ow))
         MQ = gpts.shape[0]
         sel = np.arange(MQ) if rows is None else np.asarray(rows)
-        on = oracle.neighbors(po, opts, wl.nodes, rows=sel, lists=True)
+        on = oracle.neighbors(po, gpts, wl.nodes, rows=sel, lists=True)
         delta, thr = H.hamls_plan_radii(plan)
         rp, idx = H.hamls_plan_neighbors(plan)
         bad = 0
@@ -88,17 +91,18 @@ def _check(H, wl, rows=None, nu=None, label=""):
         np.testing.assert_allclose(delta[sel], on["delta"], rtol=1e-13)
         # thresholds: SO3 stores cos(delta/2) (as the oracle), T3 -delta^2
         # (the oracle delta^2, member iff d^2 below it)
-        othr = on["threshold"] if wl.domain == "so3" else -on["threshold"]
-        np.testing.assert_allclose(thr[sel], othr, rtol=1e-13, atol=1e-15)
-        om = oracle.mls(po, opts, wl.nodes, wl.values, node_weights=nu, rows=sel)
+        gthr = thr[sel] if wl.domain == "so3" else -thr[sel]
+        PAR.check_thresholds(wl.domain, wl.nodes, gpts, sel, gthr, on["threshold"])
+        om = oracle.mls(po, gpts, wl.nodes, wl.values, node_weights=nu, rows=sel)
         dg = H.hamls_diagnostics(plan)
         np.testing.assert_array_equal(dg["n"][sel], om["n"])
         g = gv[:, sel]
         mask = ~np.isnan(om["values"][0])
         assert np.array_equal(np.isnan(g[0]), ~mask)
         err = _rell2(g[:, mask], om["values"][:, mask])
-        _say(f"  grid values rel L2 vs oracle: {err:.3e}")
-        assert err < TOL
+        emax = PAR.maxrel(g[:, mask], om["values"][:, mask]) if mask.any() else 0.0
+        _say(f"  grid values vs oracle: rel L2 {err:.3e}, max |diff| / max |value| {emax:.3e}")
+        assert err < TOL and emax < TOL
         common = oracle.ST_REGULARIZED | oracle.ST_UNDERDETERMINED | oracle.ST_EMPTY | oracle.ST_HEMISPHERE
         np.testing.assert_array_equal(dg["status"][sel] & common, om["status"] & common)
         fin = np.isfinite(om["chi"])
@@ -118,11 +122,15 @@ def _check(H, wl, rows=None, nu=None, label=""):
         np.testing.assert_allclose(dg["tau"][sel][tn], om["tau"][tn], rtol=1e-6)
         n_ill = int(np.sum(dg["status"][sel] & H.ST_ILLCOND != 0))
         _say(f"  regularized {int(np.sum(om['status'] & 1))}/{sel.size}, ill-conditioned {n_ill}")
-        if rows is None and mask.all():
+        if np.isfinite(gv).all():
+            # step 3 at any size: the oracle's quadrature of the library's own
+            # grid values, every coefficient
             oc = oracle.coeffs(po, gv)
-            cerr = _rell2(cf, oc)
-            _say(f"  coefficients rel L2 vs oracle (same grid values): {cerr:.3e}")
-            assert cerr < TOL
+            cerr, cmax = _rell2(cf, oc), PAR.maxrel(cf, oc)
+            _say(f"  coefficients vs oracle quadrature of the GPU grid values: rel L2 {cerr:.3e}, "
+                 f"max {cmax:.3e}")
+            assert cerr < TOL and cmax < TOL
+        if rows is None and mask.all():
             oc2 = oracle.coeffs(po, om["values"])
             cerr2 = _rell2(cf, oc2)
             _say(f"  coefficients rel L2 vs oracle end to end: {cerr2:.3e}")
@@ -157,9 +165,11 @@ def test_so3_fixed_radius_weights_fields(H):
 
 
 def test_so3_oversampled_grid_sampled(H):
-    # the benchmark's SO(3) grid shape, N = 64 on a 130^3 Euler grid, with
-    # fewer nodes; every 1009th grid node against the oracle
-    wl = W.so3_clusters(seed=5120, M=200000, N=64, K=2, grid=(130, 130, 130), field_degree=20)
+    # the SO(3) benchmark workload at full size: M = 10^6 rotations, N = 64 on
+    # the 130^3 Euler grid; every 1009th grid node against the oracle's brute
+    # force over all nodes, and every coefficient against the oracle's
+    # quadrature of the GPU grid values
+    wl = W.so3_clusters()
     _check(H, wl, rows=np.arange(0, 130 ** 3, 1009), label="so3-130^3")
 
 
@@ -223,6 +233,20 @@ def test_so3_member_lists_scan_fallback(H):
     _check(H, wl, label="so3 lists fallback")
 
 
+@pytest.mark.parametrize("domain", ["so3", "t3"])
+def test_grid_knn_at_candidate_buffer_limit(H, domain):
+    # n = 400, just below the 416-entry candidate buffer of the SO3/T3
+    # search: first scans often overflow it, so the kept key range is
+    # narrowed by the histogram and rescanned; sets stay bit-exact
+    if domain == "so3":
+        wl = W.so3_clusters(seed=5150, M=30000, N=4, K=1, grid=(0, 0, 0), field_degree=4)
+    else:
+        wl = W.t3_clusters(seed=5250, M=30000, N=4, K=1, grid=8, kmax=4)
+    wl.params["knn_count"] = 400
+    wl.params["knn_eps"] = 0.05
+    _check(H, wl, label=f"{domain} n=400")
+
+
 def test_t3_fixed_radius_weights_fields(H):
     rng = np.random.default_rng(52)
     x = W.clustered_torus(10000, rng)
@@ -235,9 +259,10 @@ def test_t3_fixed_radius_weights_fields(H):
 
 
 def test_t3_power_of_two_grid_sampled(H):
-    # the benchmark's T3 grid, 128^3 with k in [-64, 63]^3, fewer nodes;
-    # every 2003rd grid node against the oracle
-    wl = W.t3_clusters(seed=5220, M=300000, N=64, K=3, grid=128, kmax=16)
+    # the T3 benchmark workload at full size: M = 2 10^6 points, the 128^3
+    # grid with k in [-64, 63]^3; every 2003rd grid node against the oracle,
+    # every coefficient against the oracle's quadrature of the GPU grid values
+    wl = W.t3_clusters()
     _check(H, wl, rows=np.arange(0, 128 ** 3, 2003), label="t3-128^3")
 
 

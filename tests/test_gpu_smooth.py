@@ -56,7 +56,7 @@ def test_smoothed_radius_matches_oracle(H, K, naux):
         delta, thr = H.hamls_plan_radii(plan)
         rp, idx = H.hamls_plan_neighbors(plan)
         po = oracle.params(**wp)
-        g, _w = oracle.grid(po)
+        g, _w = H.hamls_plan_grid(plan)  # the library's exported grid
         nb = oracle.neighbors(po, g, x, lists=True)
         derr = np.max(np.abs(delta - nb["delta"]) / nb["delta"])
         _say("delta rel", derr, "count min", int(np.diff(rp).min()))

@@ -84,7 +84,7 @@ def test_queue_and_tuned_forms_equal_grid_order(H):
         assert _same(gv, gv0) and _same(cf, cf0)
         # the oracle on sampled grid nodes, heaviest included
         po = oracle.params(**wl.params)
-        g, _ = oracle.grid(po)
+        g, _ = H.hamls_plan_grid(plan)  # the library's exported grid
         rows = np.unique(np.concatenate([np.argsort(-n)[:8], np.random.default_rng(2).choice(g.shape[0], 24)]))
         fit = oracle.mls(po, g, wl.nodes, wl.values, rows=rows)
         ok = np.isfinite(fit["values"][0])

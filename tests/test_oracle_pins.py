@@ -751,3 +751,170 @@ def test_smoothed_radius_keeps_n_neighbours_on_a_fine_grid():
     g, _ = oracle.grid(p)
     nb = oracle.neighbors(p, g, nodes)
     assert nb["count"].min() >= 24
+
+
+# ------------------------------------------------------------------ SO(3) and T3 charts and penalties
+
+
+def test_so3_grid_quaternions_are_euler_zyz_rotations():
+    """Every SO(3) grid point is the rotation R_z(alpha) R_y(beta) R_z(gamma)
+    (Sec. 2.1, Euler ZYZ), with beta = arccos of the Gauss-Legendre node and
+    alpha, gamma on the trapezoid: the rotation matrix of the oracle's
+    quaternion (scipy's conversion) equals the product of the three axis
+    rotations built here.  A swapped angle, a wrong half-angle sign or a
+    transposed factor fails."""
+    from scipy.spatial.transform import Rotation
+
+    p = oracle.params(domain="so3", bandwidth=3, degree=1, knn_count=4, grid_shape=(5, 7, 8))
+    pts, _ = oracle.grid(p)
+    nb, na, ng = oracle.grid_dims(p)
+    x, _ = oracle.gauss_legendre(nb)
+
+    def rz(a):
+        c, s = math.cos(a), math.sin(a)
+        return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+    def ry(b):
+        c, s = math.cos(b), math.sin(b)
+        return np.array([[c, 0.0, s], [0.0, 1.0, 0.0], [-s, 0.0, c]])
+
+    Rq = Rotation.from_quat(pts[:, [1, 2, 3, 0]]).as_matrix()
+    for t in range(nb):
+        for a in range(na):
+            for g in range(ng):
+                j = (t * na + a) * ng + g
+                R = rz(2 * math.pi * a / na) @ ry(math.acos(x[t])) @ rz(2 * math.pi * g / ng)
+                np.testing.assert_allclose(Rq[j], R, atol=1e-14)
+    np.testing.assert_allclose(np.linalg.norm(pts, axis=1), 1.0, atol=1e-15)
+
+
+def _so3_chart_poly(qc, nodes, coefs, K, frame):
+    """p(s) for s = sin(omega/2) n, (omega, n) the axis and angle of the
+    relative rotation R_c^T R_i computed from rotation matrices (scipy), so
+    independent of the sign of either quaternion; s is expressed in the
+    orthonormal frame given (Pi_K^tan does not depend on the frame)."""
+    from scipy.spatial.transform import Rotation
+
+    Rc = Rotation.from_quat(qc[[1, 2, 3, 0]])
+    Ri = Rotation.from_quat(nodes[:, [1, 2, 3, 0]])
+    rv = (Rc.inv() * Ri).as_rotvec()
+    om = np.linalg.norm(rv, axis=1)
+    sc = np.where(om > 1e-300, np.sin(0.5 * om) / np.where(om > 0, om, 1.0), 0.5)
+    s = (rv * sc[:, None]) @ frame
+    val = np.zeros(nodes.shape[0])
+    c = 0
+    for l in range(K + 1):
+        for a in range(l, -1, -1):
+            for b in range(l - a, -1, -1):
+                val += coefs[c] * s[:, 0] ** a * s[:, 1] ** b * s[:, 2] ** (l - a - b)
+                c += 1
+    return val
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_so3_chart_reproduces_polynomials_for_either_quaternion_sign(K):
+    """Unregularized MLS on SO(3) reproduces Pi_K^tan at the centre (Sec.
+    2.3), where the tangent coordinates of a rotation are those of its
+    representative on the centre's hemisphere.  Half of the nodes are given
+    as -q: a chart that ignores the hemisphere (the sign of q.x) sees their
+    odd monomials negated and fails."""
+    rng = np.random.default_rng(90 + K)
+    nodes = W.clustered_rotations(6000, rng)
+    flip = rng.random(6000) < 0.5
+    nodes[flip] *= -1.0
+    m = (K + 1) * (K + 2) * (K + 3) // 6
+    p = oracle.params(domain="so3", bandwidth=2, degree=K, knn_count=3 * m, knn_eps=0.05, reg="none")
+    g, _ = oracle.grid(p)
+    frame, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    coefs = rng.standard_normal(m)
+    for j in range(0, g.shape[0], 7):
+        y = _so3_chart_poly(g[j], nodes, coefs, K, frame)
+        r = oracle.mls(p, g, nodes, y[None, :], rows=[j])
+        assert abs(r["values"][0, 0] - coefs[0]) < 1e-9 * (1 + np.abs(coefs).sum()), j
+
+
+def _degrees3(K):
+    return np.array([l for l in range(K + 1) for _ in range((l + 1) * (l + 2) // 2)])
+
+
+@pytest.mark.parametrize("dom", ["so3", "t3"])
+def test_regularized_solution_vs_normal_equations_so3_t3(dom):
+    """eq. (21)-(23) on SO(3) and T3: c_1 solves the regularized normal
+    equations with C_tau = L (I + tau D) L^T, D = diag(mu) of the non-constant
+    monomials by degree l: mu = l(l+1) on SO(3), mu = l^2 on T3 (the paper's
+    choices); chi_tau = chi_T at full regularization.  Swapping the two
+    multiplier rules fails (they differ at every l >= 1)."""
+    K = 2
+    rng = np.random.default_rng(120 if dom == "so3" else 121)
+    if dom == "so3":
+        nodes = W.clustered_rotations(6000, rng)
+    else:
+        nodes = W.clustered_torus(6000, rng)
+    y = rng.standard_normal(nodes.shape[0])
+    m = 10
+    chi_t, chi_f = 1.5, 2.0
+    p = oracle.params(domain=dom, bandwidth=2, degree=K, knn_count=14, knn_eps=0.05, reg="chi",
+                      chi_target=chi_t, chi_full=chi_f)
+    g, _ = oracle.grid(p)
+    nb = oracle.neighbors(p, g, nodes, lists=True)
+    r = oracle.mls(p, g, nodes, y[None, :])
+    l = _degrees3(K)[1:].astype(float)
+    mu = l * (l + 1) if dom == "so3" else l * l
+    n_full = n_reg = 0
+    for j in range(0, g.shape[0], 3):
+        if r["status"][j] & (oracle.ST_UNDERDETERMINED | oracle.ST_EMPTY):
+            continue
+        idx = nb["idx"][nb["row_ptr"][j] : nb["row_ptr"][j + 1]]
+        B, yw = oracle.local_system(p, g[j], nb["delta"][j], idx, nodes, y[None, :])
+        H = B.T @ B
+        ev = np.linalg.eigvalsh(H)
+        tol = 1e-14 * ev[-1] / ev[0] + 1e-12
+        tau = r["tau"][j]
+        L = np.linalg.cholesky(H[1:, 1:])
+        Ht = H.copy()
+        Ht[1:, 1:] = L @ np.diag(1 + tau * mu) @ L.T
+        c_ref = np.linalg.solve(Ht, B.T @ yw[:, 0])
+        assert abs(r["values"][0, j] - c_ref[0]) < tol * (1 + np.abs(yw).sum()), (j, tau)
+        if r["chi"][j] >= chi_f:
+            n_full += 1
+            assert abs(np.linalg.inv(Ht)[0, 0] - chi_t) < 1e-8 + tol * chi_t
+        n_reg += tau > 0
+    assert n_full > 0 and n_reg > 5
+    # the penalty must matter for this pin to bite: with the other domain's
+    # multipliers the regularized values move
+    mu_other = l * l if dom == "so3" else l * (l + 1)
+    moved = 0
+    for j in range(0, g.shape[0], 3):
+        if not (r["status"][j] & oracle.ST_REGULARIZED) or r["status"][j] & oracle.ST_UNDERDETERMINED:
+            continue
+        idx = nb["idx"][nb["row_ptr"][j] : nb["row_ptr"][j + 1]]
+        B, yw = oracle.local_system(p, g[j], nb["delta"][j], idx, nodes, y[None, :])
+        H = B.T @ B
+        L = np.linalg.cholesky(H[1:, 1:])
+        Ht = H.copy()
+        Ht[1:, 1:] = L @ np.diag(1 + r["tau"][j] * mu_other) @ L.T
+        c_other = np.linalg.solve(Ht, B.T @ yw[:, 0])[0]
+        moved += abs(c_other - r["values"][0, j]) > 1e-6 * (1 + np.abs(yw).sum())
+    assert moved > 0
+
+
+def test_smoothed_radius_equals_the_wendland_mean_of_dn():
+    """The smoothed radius (Sec. 2.2, after eq. (12)) is (1 + eps) times the
+    degree-zero MLS approximation of d_n from the auxiliary Fibonacci grid:
+    sum_k phi(d(q, z_k)/rho) d_n(z_k) / sum_k phi(d(q, z_k)/rho), with
+    phi = phi_{3,1}, rho three mean spacings sqrt(4 pi / n_aux), d the arc
+    length, and d_n(z_k) the n-th nearest-node distance from cKDTree.  A wrong
+    support, profile or distance fails."""
+    rng = np.random.default_rng(63)
+    nodes = W.cluster_hole_s2(6000, rng, caps=W.random_caps(4, 15, 25, rng))
+    naux, n, eps = 1500, 24, 0.05
+    p = oracle.params(domain="s2", bandwidth=10, degree=2, knn_count=n, knn_eps=eps, smooth_aux=naux)
+    g, _ = oracle.grid(p)
+    nb = oracle.neighbors(p, g, nodes)
+    aux = oracle.fibonacci(naux)
+    dn = _dn_at(aux, nodes, n)
+    rho = 3 * math.sqrt(4 * math.pi / naux)
+    ang = np.arccos(np.clip(g @ aux.T, -1, 1))
+    w = _wendland31(ang / rho)
+    ref = (1 + eps) * (w @ dn) / w.sum(axis=1)
+    np.testing.assert_allclose(nb["delta"], np.minimum(ref, math.pi / 2), rtol=1e-11)
