@@ -389,12 +389,15 @@ def contraction_bench(H, torch, wl, F, K):
     dev = torch.device("cuda:0")
     nodes = torch.as_tensor(wl.nodes[: max(wl.params["knn_count"], 1000)], dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    g = None
     for prec in ("fp64", "mixed"):
         p = H.params_from_workload(wl.params, precision=prec)
         plan = H.hamls_plan(p, nodes, stream=stream)
         try:
             info = H.hamls_plan_info_get(plan)
-            g = torch.randn((F, info.num_grid), dtype=torch.float64, device=dev)
+            if g is None:  # the same grid values for both paths
+                gen = torch.Generator(device=dev).manual_seed(1234)
+                g = torch.randn((F, info.num_grid), dtype=torch.float64, device=dev, generator=gen)
             cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=dev)
             H.hamls_grid_to_coeffs(plan, g, cf, stream=stream)
             torch.cuda.synchronize()

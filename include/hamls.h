@@ -232,6 +232,18 @@ hamls_status hamls_fit_capture(hamls_plan_t plan, const double* values, int32_t 
 hamls_status hamls_graph_launch(hamls_graph_t graph, void* stream);
 hamls_status hamls_graph_destroy(hamls_graph_t graph);
 
+/* Node weights of the paper's ill-distributed recipe (Sec. 2.2, the remark
+ * after Thm. 2.1: the weight function rescaled by each node's Voronoi-cell
+ * volume; Sec. 3: the data weighted by Voronoi areas): the area of the
+ * spherical Voronoi cell {y : y.x_i >= y.x_j for every j} of every bound node,
+ * exact up to rounding.
+ *  areas   device, M doubles in the caller's node order (sum 4 pi); NaN for a
+ *          cell that reaches ~89.99 degrees from its node, holds more than 28
+ *          vertices, or belongs to a duplicated node
+ * Pass them back as node_weights (hamls_plan_rebind) to weight the fit.
+ * Asynchronous on stream.  Errors: INVALID_ARG, UNSUPPORTED (SO3, T3), DEVICE. */
+hamls_status hamls_plan_voronoi_areas(hamls_plan_t plan, double* areas, void* stream);
+
 /* Device bytes a plan of these parameters holds for M nodes after a
  * hamls_grid_to_coeffs call with F fields: the sum of its allocations (the
  * capacity of a serving-loop plan, below, counts as M).  Host only; no device

@@ -63,6 +63,8 @@ def lib():
         L.orc_mls.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, i32, i64, vp, vp, vp, vp, vp]
         L.orc_fibonacci.argtypes = [C.c_int, vp]
         L.orc_fibonacci.restype = None
+        L.orc_voronoi_areas.argtypes = [vp, i64, vp, i64, vp]
+        L.orc_voronoi_areas.restype = i64
         L.orc_generating.argtypes = [P(OrcParams), vp, i64, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.orc_alf.argtypes = [C.c_int, d, vp]
         L.orc_alf.restype = None
@@ -208,6 +210,21 @@ def generating(p: OrcParams, grid_pts, nodes, node_weights=None, rows=None):
         raise ValueError("orc_generating failed")
     n = int(rp[-1])
     return dict(row_ptr=rp, idx=idx[:n], val=val[:n], chi=chi, tau=tau, status=st)
+
+
+def voronoi_areas(nodes, rows=None):
+    """Spherical Voronoi cell area of every node (S2 unit vectors, M x 3), or
+    of the nodes `rows`, brute force over all nodes; NaN for a cell reaching
+    ~90 degrees from its node."""
+    x = np.ascontiguousarray(nodes, dtype=np.float64)
+    if rows is None:
+        a = np.zeros(x.shape[0])
+        lib().orc_voronoi_areas(_ptr(x), x.shape[0], None, 0, _ptr(a))
+    else:
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        a = np.zeros(r.shape[0])
+        lib().orc_voronoi_areas(_ptr(x), x.shape[0], _ptr(r), r.shape[0], _ptr(a))
+    return a
 
 
 def fibonacci(n: int):

@@ -373,6 +373,128 @@ static double select_kth(double* a, int64_t n, int64_t k, int asc)
  * clamped to pi/2 and flagged.  Threshold: S2 cos(delta); SO3 cos(delta/2);
  * T3 delta^2, where for the adaptive radius c = (1+eps)^2 d_n^2 directly. */
 /* ------------------------------------------------------------------ */
+/* Voronoi-area node weights (Sec. 2.2, the remark after Thm. 2.1;    */
+/* Sec. 3, where both methods weight the nodes by Voronoi areas)       */
+/* ------------------------------------------------------------------ */
+
+/* Area of the spherical Voronoi cell of every node, by its definition
+ *   V_i = { x in S2 : x.x_i >= x.x_j for every j },
+ * the intersection of the half-spaces x.(x_i - x_j) >= 0 over ALL other
+ * nodes (brute force, O(M^2)).  The cell is built in the gnomonic chart
+ * centred at x_i (x = x_i + u e1 + v e2, up to a positive factor), where
+ * great circles are lines and each half-space is the half-plane
+ *   (x_i.x_i - x_i.x_j) - u (e1.x_j) - v (e2.x_j) >= 0;
+ * a large square is clipped by every half-plane in turn (Sutherland-Hodgman),
+ * the vertices are mapped back to the sphere, and the area is the sum of the
+ * solid angles of the triangles (x_i, y_k, y_k+1) (Van Oosterom-Strackee).
+ * A cell that reaches the square's edge (more than ~89.99 degrees from its
+ * node) gets NaN; nodes must be distinct unit vectors.  rows (nrows of them)
+ * selects the nodes whose cells are computed, or NULL for all M; areas[r]
+ * belongs to the r-th selected node.  Returns the number of NaN cells. */
+#define ORC_VOR_W 1e4
+int64_t orc_voronoi_areas(const double* nodes, int64_t M, const int64_t* rows, int64_t nrows, double* areas)
+{
+    int64_t bad = 0;
+    int64_t nr = rows ? nrows : M;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : bad)
+    for (int64_t r = 0; r < nr; r++) {
+        const int64_t i = rows ? rows[r] : r;
+        double* out_i = areas + r;
+        const double* x = nodes + 3 * i;
+        int ax = 0;
+        for (int d = 1; d < 3; d++)
+            if (fabs(x[d]) < fabs(x[ax])) ax = d;
+        double a[3] = {0.0, 0.0, 0.0};
+        a[ax] = 1.0;
+        double ax_x = a[0] * x[0] + a[1] * x[1] + a[2] * x[2];
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; d++) e1[d] = a[d] - ax_x * x[d];
+        double n1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        for (int d = 0; d < 3; d++) e1[d] /= n1;
+        e2[0] = x[1] * e1[2] - x[2] * e1[1];
+        e2[1] = x[2] * e1[0] - x[0] * e1[2];
+        e2[2] = x[0] * e1[1] - x[1] * e1[0];
+        double xx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        /* the polygon (at most M + 4 vertices), in two ping-pong arrays */
+        int cap = 64;
+        double* pu = malloc(sizeof(double) * 4 * cap);
+        int nv = 4;
+        pu[0] = -ORC_VOR_W; pu[1] = -ORC_VOR_W;
+        pu[2] = ORC_VOR_W;  pu[3] = -ORC_VOR_W;
+        pu[4] = ORC_VOR_W;  pu[5] = ORC_VOR_W;
+        pu[6] = -ORC_VOR_W; pu[7] = ORC_VOR_W;
+        for (int64_t j = 0; j < M && nv > 0; j++) {
+            if (j == i) continue;
+            const double* y = nodes + 3 * j;
+            double b = xx - (x[0] * y[0] + x[1] * y[1] + x[2] * y[2]);
+            double cu = e1[0] * y[0] + e1[1] * y[1] + e1[2] * y[2];
+            double cv = e2[0] * y[0] + e2[1] * y[1] + e2[2] * y[2];
+            if (nv + 2 > cap) {
+                cap *= 2;
+                pu = realloc(pu, sizeof(double) * 4 * cap);
+            }
+            double* out = pu + 2 * cap;
+            int no = 0;
+            for (int k = 0; k < nv; k++) {
+                const double* p1 = pu + 2 * k;
+                const double* p2 = pu + 2 * ((k + 1) % nv);
+                double f1 = b - cu * p1[0] - cv * p1[1];
+                double f2 = b - cu * p2[0] - cv * p2[1];
+                if (f1 >= 0.0) {
+                    out[2 * no] = p1[0];
+                    out[2 * no + 1] = p1[1];
+                    no++;
+                }
+                if ((f1 >= 0.0) != (f2 >= 0.0)) {
+                    double t = f1 / (f1 - f2);
+                    out[2 * no] = p1[0] + t * (p2[0] - p1[0]);
+                    out[2 * no + 1] = p1[1] + t * (p2[1] - p1[1]);
+                    no++;
+                }
+            }
+            memcpy(pu, out, sizeof(double) * 2 * no);
+            nv = no;
+        }
+        int reach = nv < 3;
+        for (int k = 0; k < nv; k++)
+            if (fabs(pu[2 * k]) >= 0.999999 * ORC_VOR_W || fabs(pu[2 * k + 1]) >= 0.999999 * ORC_VOR_W) reach = 1;
+        if (reach) {
+            *out_i = NAN;
+            bad++;
+            free(pu);
+            continue;
+        }
+        double area = 0.0;
+        for (int k = 0; k < nv; k++) {
+            double yk[3], yl[3];
+            const double* p1 = pu + 2 * k;
+            const double* p2 = pu + 2 * ((k + 1) % nv);
+            for (int d = 0; d < 3; d++) {
+                yk[d] = x[d] + p1[0] * e1[d] + p1[1] * e2[d];
+                yl[d] = x[d] + p2[0] * e1[d] + p2[1] * e2[d];
+            }
+            double nk = sqrt(yk[0] * yk[0] + yk[1] * yk[1] + yk[2] * yk[2]);
+            double nl = sqrt(yl[0] * yl[0] + yl[1] * yl[1] + yl[2] * yl[2]);
+            for (int d = 0; d < 3; d++) {
+                yk[d] /= nk;
+                yl[d] /= nl;
+            }
+            double cr[3] = {yk[1] * yl[2] - yk[2] * yl[1], yk[2] * yl[0] - yk[0] * yl[2],
+                            yk[0] * yl[1] - yk[1] * yl[0]};
+            double xn = sqrt(xx);
+            double det = (x[0] * cr[0] + x[1] * cr[1] + x[2] * cr[2]) / xn;
+            double den = 1.0 + (x[0] * yk[0] + x[1] * yk[1] + x[2] * yk[2]) / xn +
+                         (yk[0] * yl[0] + yk[1] * yl[1] + yk[2] * yl[2]) +
+                         (yl[0] * x[0] + yl[1] * x[1] + yl[2] * x[2]) / xn;
+            area += 2.0 * atan2(fabs(det), den);
+        }
+        *out_i = area;
+        free(pu);
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ */
 /* smoothed adaptive radius (Sec. 2.2, after eq. (12))                 */
 /* ------------------------------------------------------------------ */
 

@@ -184,9 +184,11 @@ struct Plan {
 };
 
 // Records a start/end event pair around one phase when timing is enabled.
+// Records a start and an end event around a phase when the plan's timing is
+// on for it; `allowed` = false records nothing (no event is created).
 class PhaseTimer {
   public:
-    PhaseTimer(Plan& P, int phase, hipStream_t s);
+    PhaseTimer(Plan& P, int phase, hipStream_t s, bool allowed = true);
     ~PhaseTimer();
 
   private:
@@ -261,9 +263,44 @@ hamls_status launch_gather_values(const Plan& P, const double* values, int F, in
                                   hipStream_t s);
 hamls_status launch_s2_count(const Plan& P, int32_t* counts, hipStream_t s);
 hamls_status launch_s2_list(const Plan& P, const int64_t* row_ptr, int32_t* idx, hipStream_t s);
-hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStream_t s);
-hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s);
-hamls_status launch_s2_legendre_mfma(const Plan& P, int F, double* coeffs, hipStream_t s);
+// Radices of a mixed-radix FFT of length n (product of rad[0..nst-1]);
+// nst = 0: no factorization into primes up to 19 (direct sums are used).
+constexpr int kFftMaxStages = 16;
+struct FftPlan {
+    int nst = 0;
+    int rad[kFftMaxStages] = {};
+};
+FftPlan make_fft_plan(int n);
+bool fft_axis_fits(int nin);
+hamls_status launch_fft_axis(const double* in, bool real_in, double* out, int64_t A, int nin, int64_t B,
+                             int nout, int koff, double sign, double scale, const double* tw, hipStream_t s);
+bool s2_ring_fft_fits(int np);
+hamls_status launch_s2_voronoi(const Plan& P, double* areas, hipStream_t s);
+hamls_status launch_s2_ring_fft(const Plan& P, const double* gv, int F, double* G, hipStream_t s);
+
+// Work memory of step 3 for F fields: element counts and pointers.
+//   d0  S2: ring spectra G[f][ring][k] (complex); SO3 / T3: first axis pass
+//   d1  SO3 / T3: second axis pass
+//   f0  S2 mixed: folded FP32 spectra of the matrix-core contraction
+struct CoeffWorkSize {
+    int64_t d0 = 0, d1 = 0, f0 = 0;
+};
+struct CoeffWork {
+    double* d0 = nullptr;
+    double* d1 = nullptr;
+    float* f0 = nullptr;
+    int64_t f0_len = 0;
+};
+CoeffWorkSize coeff_work_size(const Plan& P, int F);
+// Step 3 (eq. (25)) of F fields with the given work memory.
+// timed = false records no timing events (the no-allocation entry point).
+hamls_status run_grid_to_coeffs(Plan* P, const double* grid_values, int F, double* coeffs,
+                                const CoeffWork& W, hipStream_t s, bool timed = true);
+
+hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, double* G, hipStream_t s);
+hamls_status launch_s2_legendre(const Plan& P, int F, const double* G, double* coeffs, hipStream_t s);
+hamls_status launch_s2_legendre_mfma(const Plan& P, int F, const double* G, float* X, int64_t xlen,
+                                     double* coeffs, hipStream_t s);
 hamls_status build_s2_mfma_layout(Plan& P, std::vector<int64_t>& off, std::vector<int32_t>& items,
                                   int64_t* len);
 hamls_status launch_s2_mfma_table(const Plan& P, int64_t len, hipStream_t s);

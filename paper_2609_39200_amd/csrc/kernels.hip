@@ -2059,11 +2059,13 @@ __global__ __launch_bounds__(256) void k_s2_ring_dft(const double* __restrict__ 
     }
 }
 
-hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, hipStream_t s) {
+hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, double* G, hipStream_t s) {
     int nt = P.dims[0], np = P.dims[1];
+    // ring lengths that factor into primes up to 19: FFTs of mirrored ring pairs
+    if (s2_ring_fft_fits(np)) return launch_s2_ring_fft(P, gv, F, G, s);
     size_t lds = sizeof(double) * 3 * (size_t)np;
     hipLaunchKernelGGL(k_s2_ring_dft, dim3(nt, F), dim3(256), lds, s, gv, P.MQ, nt, np, P.N,
-                       P.d_tw, P.d_G);
+                       P.d_tw, G);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -2130,12 +2132,12 @@ __global__ __launch_bounds__(256) void k_s2_legendre(const double* __restrict__ 
     }
 }
 
-hamls_status launch_s2_legendre(const Plan& P, int F, double* coeffs, hipStream_t s) {
+hamls_status launch_s2_legendre(const Plan& P, int F, const double* G, double* coeffs, hipStream_t s) {
     const int64_t na = (int64_t)(P.N + 1) * (P.N + 2) / 2;
     const int64_t tot = na * F * kLegSplit;
     const int bs = 256;
     hipLaunchKernelGGL(k_s2_legendre, dim3((unsigned)((tot + bs - 1) / bs)), dim3(bs), 0, s,
-                       P.d_ptab, P.d_G, P.dims[0], P.N, F, coeffs);
+                       P.d_ptab, G, P.dims[0], P.N, F, coeffs);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

@@ -39,8 +39,8 @@ static hipEvent_t take_event(Plan& P) {
     return e;
 }
 
-PhaseTimer::PhaseTimer(Plan& P, int phase, hipStream_t s) : P_(P), phase_(phase), s_(s) {
-    if (!P_.timing || !((P_.timing_mask >> phase) & 1u)) return;
+PhaseTimer::PhaseTimer(Plan& P, int phase, hipStream_t s, bool allowed) : P_(P), phase_(phase), s_(s) {
+    if (!allowed || !P_.timing || !((P_.timing_mask >> phase) & 1u)) return;
     b_ = take_event(P_);
     if (b_) (void)hipEventRecord(b_, s_);
 }
@@ -728,6 +728,112 @@ hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int3
     return HAMLS_OK;
 }
 
+CoeffWorkSize coeff_work_size(const Plan& P, int F) {
+    CoeffWorkSize z;
+    const int N = P.N, K2 = 2 * N + 1;
+    if (P.dom == HAMLS_S2) {
+        z.d0 = (int64_t)F * P.dims[0] * (N + 1) * 2;
+        if (P.prm.precision == HAMLS_MIXED) {
+            const int th_pad = (((P.dims[0] + 1) / 2) + 3) & ~3;
+            const int64_t C_pad = ((2 * (int64_t)F + 15) / 16) * 16;
+            z.f0 = (int64_t)(N + 1) * 2 * th_pad * C_pad;
+        }
+    } else if (P.dom == HAMLS_SO3) {
+        z.d0 = (int64_t)F * P.dims[0] * K2 * P.dims[2] * 2;
+        z.d1 = (int64_t)F * P.dims[0] * K2 * K2 * 2;
+    } else {
+        z.d0 = z.d1 = (int64_t)F * P.MQ * 2;
+    }
+    return z;
+}
+
+// Step-3 work memory for F fields, owned by the plan (grows with the largest
+// call; the growth synchronizes the stream).
+static hamls_status ensure_coeff_work(Plan* P, int32_t F, hipStream_t s) {
+    if (F > P->G_fields) {
+        const CoeffWorkSize z = coeff_work_size(*P, F);
+        HAMLS_HIP(hipStreamSynchronize(s));
+        for (void** slot : {(void**)&P->d_G, (void**)&P->d_work[0], (void**)&P->d_work[1], (void**)&P->d_x32}) {
+            if (!*slot) continue;
+            for (auto it = P->owned.begin(); it != P->owned.end(); ++it)
+                if (it->p == *slot) {
+                    (void)hipFree(it->p);
+                    P->resident -= (int64_t)it->bytes;
+                    P->owned.erase(it);
+                    break;
+                }
+            *slot = nullptr;
+        }
+        P->x32_len = 0;
+        P->G_fields = 0;
+        if (P->dom == HAMLS_S2) {
+            HAMLS_TRY(dalloc(*P, &P->d_G, z.d0));
+            if (z.f0 > 0) {
+                P->x32_len = z.f0;
+                HAMLS_TRY(dalloc(*P, &P->d_x32, P->x32_len));
+            }
+        } else {
+            HAMLS_TRY(dalloc(*P, &P->d_work[0], z.d0));
+            HAMLS_TRY(dalloc(*P, &P->d_work[1], z.d1));
+        }
+        P->G_fields = F;
+    }
+    return HAMLS_OK;
+}
+
+static CoeffWork plan_coeff_work(const Plan& P) {
+    CoeffWork W;
+    if (P.dom == HAMLS_S2) {
+        W.d0 = P.d_G;
+        W.f0 = P.d_x32;
+        W.f0_len = P.x32_len;
+    } else {
+        W.d0 = P.d_work[0];
+        W.d1 = P.d_work[1];
+    }
+    return W;
+}
+
+hamls_status run_grid_to_coeffs(Plan* P, const double* grid_values, int F, double* coeffs,
+                                const CoeffWork& W, hipStream_t s, bool timed) {
+    if (P->dom == HAMLS_S2) {
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s, timed);
+            HAMLS_TRY(launch_s2_ring_dft(*P, grid_values, F, W.d0, s));
+        }
+        PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s, timed);
+        if (P->prm.precision == HAMLS_MIXED)
+            HAMLS_TRY(launch_s2_legendre_mfma(*P, F, W.d0, W.f0, W.f0_len, coeffs, s));
+        else
+            HAMLS_TRY(launch_s2_legendre(*P, F, W.d0, coeffs, s));
+        return HAMLS_OK;
+    }
+    if (P->dom == HAMLS_SO3) {
+        const int nb = P->dims[0], na = P->dims[1], ng = P->dims[2], N = P->N, K2 = 2 * N + 1;
+        {
+            PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s, timed);
+            // [f][t][a][g] -> [f][t][k][g] -> [f][t][k][k']
+            HAMLS_TRY(launch_dft_axis(grid_values, true, W.d0, (int64_t)F * nb, na, ng, K2, N,
+                                      1.0, 2.0 * kPi / na, P->d_tw_ax[0], s));
+            HAMLS_TRY(launch_dft_axis(W.d0, false, W.d1, (int64_t)F * nb * K2, ng, 1, K2,
+                                      N, 1.0, 2.0 * kPi / ng, P->d_tw_ax[1], s));
+        }
+        PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s, timed);
+        HAMLS_TRY(launch_so3_contract(*P, W.d1, F, coeffs, s));
+        return HAMLS_OK;
+    }
+    const int n = P->dims[0], h = n / 2;
+    const int64_t n2 = (int64_t)n * n;
+    PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s, timed);
+    HAMLS_TRY(launch_dft_axis(grid_values, true, W.d0, F, n, n2, n, h, -1.0, 1.0,
+                              P->d_tw_ax[0], s));
+    HAMLS_TRY(launch_dft_axis(W.d0, false, W.d1, (int64_t)F * n, n, n, n, h, -1.0, 1.0,
+                              P->d_tw_ax[0], s));
+    HAMLS_TRY(launch_dft_axis(W.d1, false, coeffs, (int64_t)F * n2, n, 1, n, h, -1.0,
+                              1.0 / ((double)n * n2), P->d_tw_ax[0], s));
+    return HAMLS_OK;
+}
+
 }  // namespace hamls
 
 using namespace hamls;
@@ -1058,49 +1164,6 @@ hamls_status hamls_gen_get(hamls_plan_t plan, int64_t* row_ptr, int32_t* idx, do
 
 // Step-3 work memory for F fields (grows with the largest call; the growth
 // synchronizes the stream and reallocates).
-static hamls_status ensure_coeff_work(Plan* P, int32_t F, hipStream_t s) {
-    if (F > P->G_fields) {
-        int64_t len0 = 0, len1 = 0;
-        const int N = P->N, K2 = 2 * N + 1;
-        if (P->dom == HAMLS_S2) {
-            len0 = (int64_t)F * P->dims[0] * (N + 1) * 2;
-        } else if (P->dom == HAMLS_SO3) {
-            len0 = (int64_t)F * P->dims[0] * K2 * P->dims[2] * 2;
-            len1 = (int64_t)F * P->dims[0] * K2 * K2 * 2;
-        } else {
-            len0 = len1 = (int64_t)F * P->MQ * 2;
-        }
-        HAMLS_HIP(hipStreamSynchronize(s));
-        for (void** slot : {(void**)&P->d_G, (void**)&P->d_work[0], (void**)&P->d_work[1], (void**)&P->d_x32}) {
-            if (!*slot) continue;
-            for (auto it = P->owned.begin(); it != P->owned.end(); ++it)
-                if (it->p == *slot) {
-                    (void)hipFree(it->p);
-                    P->resident -= (int64_t)it->bytes;
-                    P->owned.erase(it);
-                    break;
-                }
-            *slot = nullptr;
-        }
-        P->x32_len = 0;
-        P->G_fields = 0;
-        if (P->dom == HAMLS_S2) {
-            HAMLS_TRY(dalloc(*P, &P->d_G, len0));
-            if (P->prm.precision == HAMLS_MIXED) {
-                const int th_pad = (((P->dims[0] + 1) / 2) + 3) & ~3;
-                const int64_t C_pad = ((2 * (int64_t)F + 15) / 16) * 16;
-                P->x32_len = (int64_t)(N + 1) * 2 * th_pad * C_pad;
-                HAMLS_TRY(dalloc(*P, &P->d_x32, P->x32_len));
-            }
-        } else {
-            HAMLS_TRY(dalloc(*P, &P->d_work[0], len0));
-            HAMLS_TRY(dalloc(*P, &P->d_work[1], len1));
-        }
-        P->G_fields = F;
-    }
-    return HAMLS_OK;
-}
-
 hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, int32_t F,
                                   double* coeffs, void* stream) {
     Plan* P = (Plan*)plan;
@@ -1114,42 +1177,7 @@ hamls_status hamls_grid_to_coeffs(hamls_plan_t plan, const double* grid_values, 
     }
     hipStream_t s = (hipStream_t)stream;
     HAMLS_TRY(ensure_coeff_work(P, F, s));
-    if (P->dom == HAMLS_S2) {
-        {
-            PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
-            HAMLS_TRY(launch_s2_ring_dft(*P, grid_values, F, s));
-        }
-        PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s);
-        if (P->prm.precision == HAMLS_MIXED)
-            HAMLS_TRY(launch_s2_legendre_mfma(*P, F, coeffs, s));
-        else
-            HAMLS_TRY(launch_s2_legendre(*P, F, coeffs, s));
-        return HAMLS_OK;
-    }
-    if (P->dom == HAMLS_SO3) {
-        const int nb = P->dims[0], na = P->dims[1], ng = P->dims[2], N = P->N, K2 = 2 * N + 1;
-        {
-            PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
-            // [f][t][a][g] -> [f][t][k][g] -> [f][t][k][k']
-            HAMLS_TRY(launch_dft_axis(grid_values, true, P->d_work[0], (int64_t)F * nb, na, ng, K2, N,
-                                      1.0, 2.0 * kPi / na, P->d_tw_ax[0], s));
-            HAMLS_TRY(launch_dft_axis(P->d_work[0], false, P->d_work[1], (int64_t)F * nb * K2, ng, 1, K2,
-                                      N, 1.0, 2.0 * kPi / ng, P->d_tw_ax[1], s));
-        }
-        PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s);
-        HAMLS_TRY(launch_so3_contract(*P, P->d_work[1], F, coeffs, s));
-        return HAMLS_OK;
-    }
-    const int n = P->dims[0], h = n / 2;
-    const int64_t n2 = (int64_t)n * n;
-    PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s);
-    HAMLS_TRY(launch_dft_axis(grid_values, true, P->d_work[0], F, n, n2, n, h, -1.0, 1.0,
-                              P->d_tw_ax[0], s));
-    HAMLS_TRY(launch_dft_axis(P->d_work[0], false, P->d_work[1], (int64_t)F * n, n, n, n, h, -1.0, 1.0,
-                              P->d_tw_ax[0], s));
-    HAMLS_TRY(launch_dft_axis(P->d_work[1], false, coeffs, (int64_t)F * n2, n, 1, n, h, -1.0,
-                              1.0 / ((double)n * n2), P->d_tw_ax[0], s));
-    return HAMLS_OK;
+    return run_grid_to_coeffs(P, grid_values, F, coeffs, plan_coeff_work(*P), s);
 }
 
 // A captured fit: steps 2 and 3 on one plan with fixed buffers, replayed as
@@ -1238,6 +1266,19 @@ hamls_status hamls_graph_destroy(hamls_graph_t graph) {
     (void)hipGraphDestroy(graph->g);
     delete graph;
     return HAMLS_OK;
+}
+
+hamls_status hamls_plan_voronoi_areas(hamls_plan_t plan, double* areas, void* stream) {
+    Plan* P = (Plan*)plan;
+    if (!P || !areas) {
+        set_error("null argument");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (P->dom != HAMLS_S2) {
+        set_error("Voronoi areas are built for S2 plans");
+        return HAMLS_ERR_UNSUPPORTED;
+    }
+    return launch_s2_voronoi(*P, areas, (hipStream_t)stream);
 }
 
 hamls_status hamls_eval(hamls_plan_t plan, const double* coeffs, int32_t F, const double* points,

@@ -108,12 +108,13 @@ __global__ __launch_bounds__(64) void k_s2_legendre_mfma(const float* __restrict
     }
 }
 
-hamls_status launch_s2_legendre_mfma(const Plan& P, int F, double* coeffs, hipStream_t s) {
+hamls_status launch_s2_legendre_mfma(const Plan& P, int F, const double* G, float* X, int64_t xcap,
+                                     double* coeffs, hipStream_t s) {
     const int nt = P.dims[0], N = P.N;
     const int th = (nt + 1) / 2, th_pad = (th + 3) & ~3;
     const int C_pad = ((2 * F + 15) / 16) * 16;
     const int64_t xlen = (int64_t)(N + 1) * 2 * th_pad * C_pad;
-    if (xlen > P.x32_len) {
+    if (xlen > xcap) {
         set_error("fold buffer too small");
         return HAMLS_ERR_INVALID_ARG;
     }
@@ -121,8 +122,7 @@ hamls_status launch_s2_legendre_mfma(const Plan& P, int F, double* coeffs, hipSt
         const int bs = 256;
         int64_t nb = (xlen + bs - 1) / bs;
         nb = nb < 65536 ? nb : 65536;
-        hipLaunchKernelGGL(k_s2_fold32, dim3((unsigned)nb), dim3(bs), 0, s, P.d_G, nt, N, F, th, th_pad, C_pad,
-                           P.d_x32);
+        hipLaunchKernelGGL(k_s2_fold32, dim3((unsigned)nb), dim3(bs), 0, s, G, nt, N, F, th, th_pad, C_pad, X);
         HAMLS_HIP(hipGetLastError());
     }
     const int nct_total = C_pad / 16;
@@ -131,7 +131,7 @@ hamls_status launch_s2_legendre_mfma(const Plan& P, int F, double* coeffs, hipSt
         dim3 grid((unsigned)P.leg_items), block(64);
 #define HAMLS_LEG(NN)                                                                                 \
     hipLaunchKernelGGL(k_s2_legendre_mfma<NN>, grid, block, 0, s, P.d_ptab32, P.d_tab_off,            \
-                       (const LegItem*)P.d_leg_items, P.d_x32, N, F, th_pad, C_pad, ct0, coeffs)
+                       (const LegItem*)P.d_leg_items, X, N, F, th_pad, C_pad, ct0, coeffs)
         if (nct <= 1)
             HAMLS_LEG(1);
         else if (nct <= 2)

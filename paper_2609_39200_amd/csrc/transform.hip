@@ -103,6 +103,9 @@ hamls_status launch_dft_axis(const double* in, bool real_in, double* out, int64_
         set_error("dft axis: empty shape");
         return HAMLS_ERR_INVALID_ARG;
     }
+    // lengths that factor into primes up to 19: the mixed-radix FFT
+    if (fft_axis_fits(nin))
+        return launch_fft_axis(in, real_in, out, A, nin, B, nout, koff, sign, scale, tw, s);
     // tile of at most 48 KiB
     int TL = (int)(49152 / (16 * (int64_t)(nin + 1)));
     TL = TL > 16 ? 16 : TL;

@@ -108,6 +108,7 @@ _SIGS = {
     "hamls_mls_to_grid": [_vp, _vp, _i32, _i64, _vp, _vp],
     "hamls_grid_to_coeffs": [_vp, _vp, _i32, _vp, _vp],
     "hamls_eval": [_vp, _vp, _i32, _vp, _i64, _vp, _vp],
+    "hamls_plan_voronoi_areas": [_vp, _vp, _vp],
     "hamls_plan_destroy": [_vp],
     "hamls_plan_info_get": [_vp, _P(hamls_plan_info)],
     "hamls_plan_grid": [_vp, _vp, _vp],
@@ -227,6 +228,13 @@ def hamls_grid_to_coeffs(plan: int, grid_values, coeffs, stream=None):
     F = grid_values.shape[0]
     _check(_lib.hamls_grid_to_coeffs(C.c_void_p(plan), _dev(grid_values, "grid_values"), F,
                                      _dev(coeffs, "coeffs"), _stream(stream)), "hamls_grid_to_coeffs")
+
+
+def hamls_plan_voronoi_areas(plan: int, areas, stream=None):
+    """areas: (M,) FP64 device tensor, the spherical Voronoi-cell area of every
+    bound node (S2 plans)."""
+    _check(_lib.hamls_plan_voronoi_areas(C.c_void_p(plan), _dev(areas, "areas"), _stream(stream)),
+           "hamls_plan_voronoi_areas")
 
 
 def hamls_eval(plan: int, coeffs, points, out, stream=None):

@@ -918,3 +918,46 @@ def test_smoothed_radius_equals_the_wendland_mean_of_dn():
     w = _wendland31(ang / rho)
     ref = (1 + eps) * (w @ dn) / w.sum(axis=1)
     np.testing.assert_allclose(nb["delta"], np.minimum(ref, math.pi / 2), rtol=1e-11)
+
+
+# ------------------------------------------------------------------ Voronoi-area node weights (Sec. 2.2, Sec. 3)
+
+
+def _platonic(name):
+    if name == "octahedron":
+        x = np.vstack([np.eye(3), -np.eye(3)])
+    elif name == "cube":
+        x = np.array([[a, b, c] for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)], float)
+    else:
+        ph = (1 + math.sqrt(5)) / 2
+        x = np.array([[0, s1, s2 * ph] for s1 in (-1, 1) for s2 in (-1, 1)]
+                     + [[s1, s2 * ph, 0] for s1 in (-1, 1) for s2 in (-1, 1)]
+                     + [[s2 * ph, 0, s1] for s1 in (-1, 1) for s2 in (-1, 1)], float)
+    return x / np.linalg.norm(x, axis=1)[:, None]
+
+
+@pytest.mark.parametrize("name,n", [("octahedron", 6), ("cube", 8), ("icosahedron", 12)])
+def test_voronoi_areas_of_regular_polyhedra(name, n):
+    """The vertices of a regular polyhedron have congruent Voronoi cells:
+    each has area 4 pi / n exactly."""
+    a = oracle.voronoi_areas(_platonic(name))
+    assert a.shape == (n,)
+    np.testing.assert_allclose(a, 4 * math.pi / n, rtol=1e-11)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clusters"])
+def test_voronoi_areas_vs_scipy(kind):
+    """Cell areas equal scipy's SphericalVoronoi (qhull's hull, an
+    independent construction) and sum to 4 pi."""
+    from scipy.spatial import SphericalVoronoi
+
+    rng = np.random.default_rng(71 if kind == "uniform" else 72)
+    if kind == "uniform":
+        x = W.uniform_s2(1500, rng)
+    else:
+        x = W.cluster_hole_s2(1500, rng, caps=W.random_caps(3, 15, 25, rng))
+    a = oracle.voronoi_areas(x)
+    b = SphericalVoronoi(x).calculate_areas()
+    assert not np.isnan(a).any()
+    np.testing.assert_allclose(a, b, rtol=1e-9)
+    assert abs(a.sum() - 4 * math.pi) < 1e-11
