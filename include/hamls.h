@@ -22,6 +22,7 @@
 #ifndef HAMLS_H
 #define HAMLS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -231,6 +232,26 @@ hamls_status hamls_fit_capture(hamls_plan_t plan, const double* values, int32_t 
                                double* grid_values, double* coeffs, void* stream, hamls_graph_t* out);
 hamls_status hamls_graph_launch(hamls_graph_t graph, void* stream);
 hamls_status hamls_graph_destroy(hamls_graph_t graph);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * hamls_grid_to_coeffs with its step-3 work memory (ring spectra, axis-pass
+ * buffers, folded FP32 spectra) taken from a static device array of
+ * hamls_noalloc_scratch_bytes() bytes (128 MiB) that each GPU the library runs
+ * on holds until the process ends, instead of the plan's own work memory,
+ * which hamls_grid_to_coeffs grows (allocates) with the largest F it sees.
+ * Arguments, layouts and results as hamls_grid_to_coeffs (the same kernels);
+ * the plan's device must be current.  Calls no hipMalloc, hipFree or other
+ * allocating routine and records no timing events.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialized by the caller.
+ * Errors: INVALID_ARG (null pointers, F outside [1, 4096], F whose work
+ * memory exceeds the array -- a clear message names the bytes needed -- or a
+ * current device other than the plan's), UNSUPPORTED (device index >= 64),
+ * DEVICE. */
+hamls_status hamls_grid_to_coeffs_noalloc(hamls_plan_t plan, const double* grid_values, int32_t F,
+                                          double* coeffs, void* stream);
+size_t hamls_noalloc_scratch_bytes(void);
 
 /* Node weights of the paper's ill-distributed recipe (Sec. 2.2, the remark
  * after Thm. 2.1: the weight function rescaled by each node's Voronoi-cell

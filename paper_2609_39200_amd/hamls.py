@@ -107,6 +107,7 @@ _SIGS = {
     "hamls_plan_rebind": [_vp, _vp, _i64, _vp, _vp],
     "hamls_mls_to_grid": [_vp, _vp, _i32, _i64, _vp, _vp],
     "hamls_grid_to_coeffs": [_vp, _vp, _i32, _vp, _vp],
+    "hamls_grid_to_coeffs_noalloc": [_vp, _vp, _i32, _vp, _vp],
     "hamls_eval": [_vp, _vp, _i32, _vp, _i64, _vp, _vp],
     "hamls_plan_voronoi_areas": [_vp, _vp, _vp],
     "hamls_plan_destroy": [_vp],
@@ -143,6 +144,8 @@ _lib.hamls_server_clock.argtypes = []
 _lib.hamls_server_clock.restype = C.c_double
 _lib.hamls_last_error.argtypes = []
 _lib.hamls_last_error.restype = C.c_char_p
+_lib.hamls_noalloc_scratch_bytes.argtypes = []
+_lib.hamls_noalloc_scratch_bytes.restype = C.c_size_t
 
 
 class HamlsError(RuntimeError):
@@ -228,6 +231,19 @@ def hamls_grid_to_coeffs(plan: int, grid_values, coeffs, stream=None):
     F = grid_values.shape[0]
     _check(_lib.hamls_grid_to_coeffs(C.c_void_p(plan), _dev(grid_values, "grid_values"), F,
                                      _dev(coeffs, "coeffs"), _stream(stream)), "hamls_grid_to_coeffs")
+
+
+def hamls_grid_to_coeffs_noalloc(plan: int, grid_values, coeffs, stream=None):
+    """As hamls_grid_to_coeffs, with the step-3 work memory in the library's
+    static device array (no allocation)."""
+    F = grid_values.shape[0]
+    _check(_lib.hamls_grid_to_coeffs_noalloc(C.c_void_p(plan), _dev(grid_values, "grid_values"), F,
+                                             _dev(coeffs, "coeffs"), _stream(stream)),
+           "hamls_grid_to_coeffs_noalloc")
+
+
+def hamls_noalloc_scratch_bytes() -> int:
+    return int(_lib.hamls_noalloc_scratch_bytes())
 
 
 def hamls_plan_voronoi_areas(plan: int, areas, stream=None):
