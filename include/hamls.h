@@ -51,11 +51,12 @@ typedef enum { HAMLS_REG_NONE = 0, HAMLS_REG_FIXED = 1, HAMLS_REG_CHI_TARGET = 2
 
 /* Arithmetic of step 2 (and step 3):
  *  FP64   every step in double precision
- *  MIXED  (S2) Gram assembly in FP32 with one FP64 residual refinement; centres
+ *  MIXED  Gram assembly in FP32 with one FP64 residual refinement; centres
  *         that are regularized, ill-conditioned (condition above ~1e4) or
- *         degenerate are solved in FP64; step 3 contraction in FP32 on the
- *         matrix cores (tables generated in FP64).  Within 1e-6 relative L2 of
- *         FP64. */
+ *         degenerate are solved in FP64 (every domain); on S2 the step-3
+ *         contraction in FP32 on the matrix cores (tables generated in FP64).
+ *         hamls_plan_tune may keep FP64 kernels for step 2 where they are
+ *         faster.  Within 1e-6 relative L2 of FP64. */
 typedef enum { HAMLS_FP64 = 0, HAMLS_MIXED = 1 } hamls_precision;
 
 /* Per-centre status bits returned by hamls_diagnostics. */
@@ -121,9 +122,9 @@ hamls_status hamls_params_init(hamls_params* p);
  *  M            >= 1 and >= knn_count; capacity for later rebinds is M
  * The plan copies what it needs; nodes are not referenced after return.
  * Errors: INVALID_ARG (bad parameters), NOT_EXACT_GRID, DOMAIN (fixed
- * radius: S2 >= pi/2, SO3 > pi, T3 >= 1/2), UNSUPPORTED (mixed precision
- * outside S2, degree above 4 on S2 or 3 on SO3 / T3, knn_count above 512 on
- * S2 or 416 on SO3 / T3), OUT_OF_MEMORY, DEVICE. */
+ * radius: S2 >= pi/2, SO3 > pi, T3 >= 1/2), UNSUPPORTED (degree above 4 on
+ * S2 or 3 on SO3 / T3, knn_count above 512 on S2 or 416 on SO3 / T3),
+ * OUT_OF_MEMORY, DEVICE. */
 hamls_status hamls_plan(const hamls_params* p, const double* nodes, int64_t M,
                         const double* node_weights, void* stream, hamls_plan_t* out);
 
@@ -202,7 +203,13 @@ hamls_status hamls_plan_destroy(hamls_plan_t plan);
  * keep it (any order gives the same results, only the balance changes).
  * Results are identical in every form.  *queue_blocks receives the choice and
  * times_ms, if not NULL, the four timings in milliseconds (-1 for forms the
- * plan lacks). */
+ * plan lacks).  On a MIXED plan it also times step 2 (one field, without the
+ * extended-precision re-solve) by the FP32-Gram pass with its FP64 list
+ * (times_ms[2]) and by the FP64 kernels (times_ms[3]), and runs later step-2
+ * calls with the faster; step 3 stays FP32 on the matrix cores.  (Without
+ * packed FP32 instructions the FP32 vector rate equals the FP64 rate, so the
+ * FP32 Gram pass pays only where it saves memory traffic.)  Both choices are
+ * within the mixed bar of the FP64 path. */
 hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blocks, float* times_ms);
 /* Sets the launch form directly: 0 = grid order, 1 = cost-ordered dispatch,
  * >= 8 = the work queue with that many blocks (the order computed from the
@@ -327,7 +334,10 @@ hamls_status hamls_timing_read(hamls_plan_t plan, int32_t phase, int64_t* launch
  * (hamls_plan_footprint at the plan's capacity, plus F x M_Q doubles of grid
  * values) fits within hbm_budget next to the plans of running requests and
  * the idle resident plans; idle plans are evicted, least recently used first,
- * to make room.  A request whose parameters equal those of an idle resident
+ * to make room.  While the oldest request cannot fit until running requests
+ * finish, a later one (among the next 32) that fits now is admitted ahead of
+ * it (backfilling), at most 8 times per waiting request, so that none is
+ * starved.  A request whose parameters equal those of an idle resident
  * plan with enough node capacity (at most four times what a new plan would
  * get, since the cell grid follows a plan's first node set) rebinds it (hamls_plan_rebind: no allocation,
  * no grid or table generation); otherwise a plan is built with its capacity

@@ -383,7 +383,7 @@ static double select_kth(double* a, int64_t n, int64_t k, int asc)
  * nodes (brute force, O(M^2)).  The cell is built in the gnomonic chart
  * centred at x_i (x = x_i + u e1 + v e2, up to a positive factor), where
  * great circles are lines and each half-space is the half-plane
- *   (x_i.x_i - x_i.x_j) - u (e1.x_j) - v (e2.x_j) >= 0;
+ *   (x_i + u e1 + v e2).(x_i - x_j) >= 0;
  * a large square is clipped by every half-plane in turn (Sutherland-Hodgman),
  * the vertices are mapped back to the sphere, and the area is the sum of the
  * solid angles of the triangles (x_i, y_k, y_k+1) (Van Oosterom-Strackee).
@@ -415,20 +415,39 @@ int64_t orc_voronoi_areas(const double* nodes, int64_t M, const int64_t* rows, i
         e2[1] = x[2] * e1[0] - x[0] * e1[2];
         e2[2] = x[0] * e1[1] - x[1] * e1[0];
         double xx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        /* the polygon (at most M + 4 vertices), in two ping-pong arrays */
+        /* the polygon (at most M + 4 vertices), in two ping-pong arrays;
+         * pass 0 clips the square of half-width ORC_VOR_W, pass 1 clips again
+         * from a square twice the extent of pass 0's cell, so that no vertex
+         * is computed from far-away corners (their rounding would swamp a
+         * small cell) */
         int cap = 64;
         double* pu = malloc(sizeof(double) * 4 * cap);
-        int nv = 4;
-        pu[0] = -ORC_VOR_W; pu[1] = -ORC_VOR_W;
-        pu[2] = ORC_VOR_W;  pu[3] = -ORC_VOR_W;
-        pu[4] = ORC_VOR_W;  pu[5] = ORC_VOR_W;
-        pu[6] = -ORC_VOR_W; pu[7] = ORC_VOR_W;
+        int nv = 0;
+        double win = ORC_VOR_W;
+        for (int pass = 0; pass < 2; pass++) {
+        if (pass == 1) {
+            double ext = 0.0;
+            for (int k = 0; k < nv; k++) {
+                if (fabs(pu[2 * k]) > ext) ext = fabs(pu[2 * k]);
+                if (fabs(pu[2 * k + 1]) > ext) ext = fabs(pu[2 * k + 1]);
+            }
+            if (nv < 3 || ext >= 0.999999 * ORC_VOR_W) break;
+            win = 2.0 * ext;
+        }
+        nv = 4;
+        pu[0] = -win; pu[1] = -win;
+        pu[2] = win;  pu[3] = -win;
+        pu[4] = win;  pu[5] = win;
+        pu[6] = -win; pu[7] = win;
         for (int64_t j = 0; j < M && nv > 0; j++) {
             if (j == i) continue;
             const double* y = nodes + 3 * j;
-            double b = xx - (x[0] * y[0] + x[1] * y[1] + x[2] * y[2]);
-            double cu = e1[0] * y[0] + e1[1] * y[1] + e1[2] * y[2];
-            double cv = e2[0] * y[0] + e2[1] * y[1] + e2[2] * y[2];
+            /* (x + u e1 + v e2).(x - y) >= 0, with the difference vector
+             * formed first (accurate for close nodes) */
+            double dl[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+            double b = x[0] * dl[0] + x[1] * dl[1] + x[2] * dl[2];
+            double cu = -(e1[0] * dl[0] + e1[1] * dl[1] + e1[2] * dl[2]);
+            double cv = -(e2[0] * dl[0] + e2[1] * dl[1] + e2[2] * dl[2]);
             if (nv + 2 > cap) {
                 cap *= 2;
                 pu = realloc(pu, sizeof(double) * 4 * cap);
@@ -455,37 +474,31 @@ int64_t orc_voronoi_areas(const double* nodes, int64_t M, const int64_t* rows, i
             memcpy(pu, out, sizeof(double) * 2 * no);
             nv = no;
         }
+        }
         int reach = nv < 3;
         for (int k = 0; k < nv; k++)
-            if (fabs(pu[2 * k]) >= 0.999999 * ORC_VOR_W || fabs(pu[2 * k + 1]) >= 0.999999 * ORC_VOR_W) reach = 1;
+            if (fabs(pu[2 * k]) >= 0.999999 * win || fabs(pu[2 * k + 1]) >= 0.999999 * win) reach = 1;
         if (reach) {
             *out_i = NAN;
             bad++;
             free(pu);
             continue;
         }
+        /* solid angle of the fan triangle (x, y_k, y_k+1), y = (x + u e1 +
+         * v e2)/n with n = |x + u e1 + v e2|: the Van Oosterom-Strackee
+         * formula with its triple product (u_k v_l - u_l v_k)/(n_k n_l) and
+         * dot products |x|/n, (x.x + u_k u_l + v_k v_l)/(n_k n_l) written in
+         * the chart (e1, e2, x/|x| orthonormal), which avoids the
+         * cancellation of the triple product of nearly parallel vectors */
         double area = 0.0;
+        double xn = sqrt(xx);
         for (int k = 0; k < nv; k++) {
-            double yk[3], yl[3];
             const double* p1 = pu + 2 * k;
             const double* p2 = pu + 2 * ((k + 1) % nv);
-            for (int d = 0; d < 3; d++) {
-                yk[d] = x[d] + p1[0] * e1[d] + p1[1] * e2[d];
-                yl[d] = x[d] + p2[0] * e1[d] + p2[1] * e2[d];
-            }
-            double nk = sqrt(yk[0] * yk[0] + yk[1] * yk[1] + yk[2] * yk[2]);
-            double nl = sqrt(yl[0] * yl[0] + yl[1] * yl[1] + yl[2] * yl[2]);
-            for (int d = 0; d < 3; d++) {
-                yk[d] /= nk;
-                yl[d] /= nl;
-            }
-            double cr[3] = {yk[1] * yl[2] - yk[2] * yl[1], yk[2] * yl[0] - yk[0] * yl[2],
-                            yk[0] * yl[1] - yk[1] * yl[0]};
-            double xn = sqrt(xx);
-            double det = (x[0] * cr[0] + x[1] * cr[1] + x[2] * cr[2]) / xn;
-            double den = 1.0 + (x[0] * yk[0] + x[1] * yk[1] + x[2] * yk[2]) / xn +
-                         (yk[0] * yl[0] + yk[1] * yl[1] + yk[2] * yl[2]) +
-                         (yl[0] * x[0] + yl[1] * x[1] + yl[2] * x[2]) / xn;
+            double nk = sqrt(xx + p1[0] * p1[0] + p1[1] * p1[1]);
+            double nl = sqrt(xx + p2[0] * p2[0] + p2[1] * p2[1]);
+            double det = (p1[0] * p2[1] - p2[0] * p1[1]) / (nk * nl);
+            double den = 1.0 + xn / nk + xn / nl + (xx + p1[0] * p2[0] + p1[1] * p2[1]) / (nk * nl);
             area += 2.0 * atan2(fabs(det), den);
         }
         *out_i = area;

@@ -144,6 +144,9 @@ struct Plan {
     // 0 = grid order, 1 = dispatch in cost order, > 1 = work queue of that many
     // blocks over d_order (grid nodes by decreasing member count at tuning time)
     int asm_queue_blocks = 0;
+    // mixed plans: step 2 runs the FP64 kernels when hamls_plan_tune measured
+    // them faster than the FP32-Gram pass (step 3 stays FP32 on MFMA)
+    bool mixed_fp64_step2 = false;
     int32_t* d_order = nullptr;
     int64_t gen_cap = 0;            // entries the CSR buffers hold
     int64_t gen_nnz = 0;
@@ -317,6 +320,7 @@ hamls_status launch_grid_radius(const Plan& P, hipStream_t s);
 // split_only: one field, the Gram matrices handed on (no solve) at any m
 hamls_status launch_grid_mls(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
                              int form = -1, bool split_only = false);
+hamls_status launch_grid_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s, int form = -1);
 hamls_status launch_grid_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
                                  int unit_rhs = 0);
 hamls_status launch_grid_gen_values(const Plan& P, hipStream_t s);

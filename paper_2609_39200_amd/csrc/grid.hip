@@ -894,7 +894,9 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
 }
 
 
-template <int D, int K, int FM, bool DD, bool SPLIT = false, bool UNIT = false>
+// LIST: the FP64 pass over the nodes the mixed-precision pass handed on
+// (A.in_list), as the re-solve does for its list.
+template <int D, int K, int FM, bool DD, bool SPLIT = false, bool UNIT = false, bool LIST = false>
 __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __restrict__ vals, int F,
                                                 int wendland, const double* __restrict__ thr,
                                                 const double* __restrict__ delta, SolveArgs A,
@@ -907,7 +909,13 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
     static_assert(2 * (EG + m * FM) + m <= 64 * ROW, "LDS reuse");
     __shared__ __align__(16) double rows[64 * ROW];
     __shared__ int sh[kScanLds];
-    if (DD) {
+    if (LIST && !DD) {
+        const int n = *A.in_count;
+        for (int li = blockIdx.x; li < n; li += gridDim.x) {
+            grid_node<D, K, FM, false>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
+            __syncthreads();
+        }
+    } else if (DD) {
         // the re-solve list: a grid-stride loop over the listed nodes
         const int n = *A.in_count;
         for (int li = blockIdx.x; li < n; li += gridDim.x) {
@@ -921,6 +929,99 @@ __global__ __launch_bounds__(64) void k_grid_mls(GridGeom g, const double* __res
         const int j = order ? order[jb] : jb;
         grid_node<D, K, FM, DD, SPLIT>(j, rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
     }
+}
+
+// Mixed precision (Rem. 2.4): FP32 Gram, FP64 refinement, or hand-off to the
+// FP64 list (mixed_node_core), the members from the radius search's list or a
+// scan of the ball's box cover.
+template <int D, int K, int FM>
+__device__ __forceinline__ void grid_mixed_node(int j, double* lds, int* sh, const GridGeom& g,
+                                                const double* __restrict__ vals, int F, int wendland,
+                                                const double* __restrict__ thr, const double* __restrict__ delta,
+                                                const SolveArgs& A, int32_t* __restrict__ nj) {
+    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
+    constexpr int U = FM == 1 ? 2 : 1;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < D; d++) q[d] = g.grid[(int64_t)D * j + d];
+    const double dl = delta[j];
+    auto scan = [&](auto&& body) {
+        const int nl = g.mcnt ? g.mcnt[j] : -1;
+        if (nl >= 0)
+            grid_list_scan<U>(g.mlist + (int64_t)j * kListCap, nl, body);
+        else
+            grid_scan<D, U>(g, q, grid_rho<D>(g, dl), sh, body);
+    };
+    auto key = [&](int i) { return grid_key<D>(g, i, q); };
+    auto row = [&](int i, double kv, double* r) {
+        double uu[3], w;
+        grid_local<D>(g, i, q, kv, dl, wendland, uu, w);
+        const double sw = sqrt(w);
+        monomials3<K>(uu, sw, r);
+        return sw;
+    };
+    mixed_node_core<m, FM, U>(j, lds, thr[j], vals, g.cap, F, A, nj, scan, key, row);
+}
+
+template <int D, int K, int FM>
+__global__ __launch_bounds__(64) void k_grid_mixed(GridGeom g, const double* __restrict__ vals, int F,
+                                                  int wendland, const double* __restrict__ thr,
+                                                  const double* __restrict__ delta, SolveArgs A,
+                                                  int32_t* __restrict__ nj, const int32_t* __restrict__ order) {
+    constexpr int m = (K + 1) * (K + 2) * (K + 3) / 6;
+    __shared__ double lds[MixedLayout<m, FM>::size];
+    __shared__ int sh[kScanLds];
+    // grid order, or the plan's cost order (heaviest first), dealt over the XCDs
+    const int jb = xcd_block(blockIdx.x, gridDim.x);
+    grid_mixed_node<D, K, FM>(order ? order[jb] : jb, lds, sh, g, vals, F, wendland, thr, delta, A, nj);
+}
+
+template <int D, int K>
+static void grid_mixed_launch(const Plan& P, const GridGeom& g, const SolveArgs& A, const SolveArgs& B, int F,
+                              int wl, hipStream_t s, const int32_t* order) {
+    const dim3 grid((unsigned)P.MQ), block(64), lgrid(list_blocks(P.MQ));
+    if (F == 1) {
+        hipLaunchKernelGGL((k_grid_mixed<D, K, 1>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, P.d_delta, A,
+                           P.d_nj, order);
+        hipLaunchKernelGGL((k_grid_mls<D, K, 1, false, false, false, true>), lgrid, block, 0, s, g, P.d_vals, F,
+                           wl, P.d_thr, P.d_delta, B, P.d_nj, P.d_entries, (const int32_t*)nullptr);
+    } else {
+        hipLaunchKernelGGL((k_grid_mixed<D, K, kMaxFieldsPerPass>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr,
+                           P.d_delta, A, P.d_nj, order);
+        hipLaunchKernelGGL((k_grid_mls<D, K, kMaxFieldsPerPass, false, false, false, true>), lgrid, block, 0, s, g,
+                           P.d_vals, F, wl, P.d_thr, P.d_delta, B, P.d_nj, P.d_entries, (const int32_t*)nullptr);
+    }
+}
+
+// Mixed precision on SO3 / T3: the FP32 pass over every node (flagging nodes
+// for FP64), then the FP64 assembly over the flagged list (which flags its
+// own ill-conditioned nodes for the double-double re-solve).
+hamls_status launch_grid_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s, int form) {
+    GridGeom g = make_grid_geom(P);
+    if (form < 0) form = P.asm_queue_blocks;
+    const int32_t* order = form == 1 ? P.d_order : nullptr;
+    SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    SolveArgs B = A;
+    A.rs_list = P.d_mx_list;
+    A.rs_count = P.d_rs_count + 1;
+    B.in_list = P.d_mx_list;
+    B.in_count = P.d_rs_count + 1;
+    const int wl = P.prm.wendland;
+#define HAMLS_GMIX_D(KK)                                               \
+    if (P.dom == HAMLS_SO3)                                            \
+        grid_mixed_launch<4, KK>(P, g, A, B, F, wl, s, order);         \
+    else                                                               \
+        grid_mixed_launch<3, KK>(P, g, A, B, F, wl, s, order);
+    switch (P.K) {
+        case 0: HAMLS_GMIX_D(0) break;
+        case 1: HAMLS_GMIX_D(1) break;
+        case 2: HAMLS_GMIX_D(2) break;
+        case 3: HAMLS_GMIX_D(3) break;
+        default: set_error("degree %d unsupported on SO(3)/T3", P.K); return HAMLS_ERR_UNSUPPORTED;
+    }
+#undef HAMLS_GMIX_D
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
 }
 
 // One field with m + 1 <= 16 (K <= 2): the assembly hands the Gram matrices

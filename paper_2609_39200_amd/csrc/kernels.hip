@@ -1362,16 +1362,7 @@ hamls_status launch_cost_order(const Plan& P, hipStream_t s) {
 //     The error contracts by ~ cond * 6e-8 per refinement, so one step meets
 //     1e-6 for cond <= 1e4.
 template <int K, int FM>
-struct MixedLds {
-    static constexpr int m = (K + 1) * (K + 2) / 2;
-    static constexpr int EG = m * (m + 1) / 2;
-    static constexpr int E = EG + m * FM;
-    static constexpr int ROW32 = m + FM + 1;
-    static constexpr int ROW64 = m + FM;
-    static constexpr int oIsc = E, oL = oIsc + m, oC = oL + m * m, oRow = oC + FM * m;
-    static constexpr int size = oRow + 64 * ROW64;  // doubles
-    static_assert(64 * ROW32 <= 2 * size, "FP32 rows fit");
-};
+using MixedLds = MixedLayout<(K + 1) * (K + 2) / 2, FM>;
 
 template <int K>
 __device__ __forceinline__ void s2_monomials(double uu, double vv, double s, double* out) {
@@ -1396,19 +1387,8 @@ __device__ __forceinline__ void s2_mixed_node(int j, double* lds, int* sh, const
                                               const double* __restrict__ thr,
                                               const double* __restrict__ delta, const SolveArgs& A,
                                               int32_t* __restrict__ nj) {
-    using L_ = MixedLds<K, FM>;
-    constexpr int m = L_::m, NC = m - 1, EG = L_::EG, ROW32 = L_::ROW32, ROW64 = L_::ROW64;
-    constexpr int KE = (EG + m * FM + 63) / 64;
-    constexpr int KG = (m * FM + 63) / 64;
+    constexpr int m = (K + 1) * (K + 2) / 2;
     constexpr int U = FM == 1 ? 4 : 1;
-    float* rows32 = (float*)lds;
-    double* Gs = lds;
-    double* isc = lds + L_::oIsc;
-    double* Lm = lds + L_::oL;
-    double* cv = lds + L_::oC;
-    double* rows64 = lds + L_::oRow;
-    const int lane = threadIdx.x;
-    const int64_t MQ = A.MQ;
     const int t = j / g.nphi, p = j - t * g.nphi;
     const double q0 = g.grid[3 * j], q1 = g.grid[3 * j + 1], q2 = g.grid[3 * j + 2];
     const double thq = g.theta[t], phq = g.phi[p];
@@ -1416,271 +1396,21 @@ __device__ __forceinline__ void s2_mixed_node(int j, double* lds, int* sh, const
     const double cp = g.col_cs[2 * p], sp = g.col_cs[2 * p + 1];
     const double et0 = ct * cp, et1 = ct * sp, et2 = -stt;
     const double ep0 = -sp, ep1 = cp;
-    const double c = thr[j], dl = delta[j];
+    const double dl = delta[j];
     const double idl = 1.0 / dl;
-    const int E = EG + m * F;
-    int ca[KE], cb[KE];
-    float acc[KE];
-#pragma unroll
-    for (int k = 0; k < KE; k++) {
-        int e = lane + 64 * k;
-        acc[k] = 0.0f;
-        ca[k] = 0;
-        cb[k] = 0;
-        if (e < EG) {
-            int a = 0, rem = e;
-            while (rem >= m - a) {
-                rem -= m - a;
-                a++;
-            }
-            ca[k] = a;
-            cb[k] = a + rem;
-        } else if (e < E) {
-            int r = e - EG;
-            ca[k] = r / F;
-            cb[k] = m + r % F;
-        }
-    }
+    auto scan = [&](auto&& body) { s2_members<U>(g, j, thq, ct, stt, phq, dl, sh, body); };
+    auto key = [&](int i) { return s2_dot(g.X[i], g.X[g.cap + i], g.X[2 * g.cap + i], q0, q1, q2); };
     // member row in FP64: sqrt(w) g (m values); returns sqrt(w)
-    auto member = [&](double x0, double x1, double x2, double d, double nw, double* row) {
-        const double w = wendland_phi(wendland, acos(fmin(d, 1.0)) * idl) * nw;
+    auto row = [&](int i, double d, double* r) {
+        const double x0 = g.X[i], x1 = g.X[g.cap + i], x2 = g.X[2 * g.cap + i];
+        const double w = wendland_phi(wendland, acos(fmin(d, 1.0)) * idl) * (g.nu ? g.nu[i] : 1.0);
         const double sw = sqrt(w);
         const double uu = (x0 * et0 + x1 * et1 + x2 * et2) * idl;
         const double vv = (x0 * ep0 + x1 * ep1) * idl;
-        s2_monomials<K>(uu, vv, sw, row);
+        s2_monomials<K>(uu, vv, sw, r);
         return sw;
     };
-    // ---------------- pass 1: FP32 Gram
-    int count = 0;
-    s2_members<U>(g, j, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
-            if (valid[u]) {
-                x0 = g.X[idx[u]];
-                x1 = g.X[g.cap + idx[u]];
-                x2 = g.X[2 * g.cap + idx[u]];
-                d = s2_dot(x0, x1, x2, q0, q1, q2);
-            }
-            const bool in = d > c;
-            const uint64_t mk = __ballot(in);
-            const int nin = __popcll(mk);
-            if (nin == 0) continue;
-            if (in) {
-                const int i = idx[u];
-                double r64[m];
-                const double sw = member(x0, x1, x2, d, g.nu ? g.nu[i] : 1.0, r64);
-                float* row = rows32 + rank_below(mk) * ROW32;
-#pragma unroll
-                for (int a = 0; a < m; a++) row[a] = (float)r64[a];
-                for (int f = 0; f < F; f++) row[m + f] = (float)(sw * vals[(int64_t)f * g.cap + i]);
-            }
-            __syncthreads();
-#pragma unroll 2
-            for (int r = 0; r < nin; r++) {
-                const float* row = rows32 + r * ROW32;
-#pragma unroll
-                for (int k = 0; k < KE; k++) acc[k] = fmaf(row[ca[k]], row[cb[k]], acc[k]);
-            }
-            __syncthreads();
-            count += nin;
-        }
-    });
-    if (lane == 0) nj[j] = count;
-#pragma unroll
-    for (int k = 0; k < KE; k++) {
-        int e = lane + 64 * k;
-        if (e < E) Gs[e] = (double)acc[k];
-    }
-    __syncthreads();
-    // ---------------- FP64 factorisation of the FP32 system
-    const uint8_t rst = A.rstatus[j];
-    const double W = Gs[0];
-    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
-    auto to_fp64 = [&]() {
-        if (lane == 0) {
-            const int slot = atomicAdd(A.rs_count, 1);
-            A.rs_list[slot] = j;
-        }
-    };
-    if (count == 0 || !(W > 0.0)) {
-        if (lane < F) A.out[(int64_t)(A.f0 + lane) * MQ + j] = __builtin_nan("");
-        if (lane == 0 && A.write_diag) {
-            A.chi[j] = __builtin_nan("");
-            A.tau[j] = __builtin_nan("");
-            A.status[j] = rst | HAMLS_ST_EMPTY;
-        }
-        return;
-    }
-    bool degen = count < m;
-    {
-        double v = 1.0;
-        if (lane < m) v = sqrt(Gs[gidx(lane, lane)] / W);
-        if (__ballot(lane < m && !(v > 0.0))) degen = true;
-        if (lane < m) isc[lane] = 1.0 / v;
-    }
-    if (degen) {
-        to_fp64();
-        return;
-    }
-    __syncthreads();
-    double a[NC + 1];
-    {
-        const int r = lane;
-        const int ar = r >= NC ? 0 : r + 1;
-        const double sr = r <= NC ? isc[ar] : 0.0;
-#pragma unroll
-        for (int cc = 0; cc <= NC; cc++) {
-            const int bc = cc == NC ? 0 : cc + 1;
-            double v = 0.0;
-            if (r <= NC) {
-                const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
-                v = Gs[gidx(lo, hi)] / W * (sr * isc[bc]);
-            } else if (r < NC + 1 + F) {
-                v = Gs[EG + bc * F + (r - NC - 1)] / W * isc[bc];
-            }
-            a[cc] = v;
-        }
-    }
-    bool ill = false;
-    double minpiv = 1.0, s_last = 1.0;
-#pragma unroll
-    for (int k = 0; k <= NC; k++) {
-        const double sk = readlane_f64(a[k], k);
-        if (k < NC)
-            minpiv = fmin(minpiv, sk);
-        else
-            s_last = sk;
-        if (!(sk > 1e-300)) {
-            ill = true;
-            break;
-        }
-        const double lkk = sqrt(sk);
-        const double il = 1.0 / lkk;
-        a[k] = lane == k ? lkk : a[k] * il;
-#pragma unroll
-        for (int cc = k + 1; cc <= NC; cc++) a[cc] = fma(-a[k], readlane_f64(a[k], cc), a[cc]);
-    }
-    const double chi = ill ? 0.0 : 1.0 / s_last;
-    const bool regularized = (A.reg == HAMLS_REG_CHI_TARGET && chi > 0.5 * A.chi_t) ||
-                             (A.reg == HAMLS_REG_FIXED && A.tau_fixed > 0.0);
-    if (ill || minpiv < 1e-4 || regularized) {
-        to_fp64();
-        return;
-    }
-    // L (rows of the permuted order [V | v1]) to LDS; the field rows hold
-    // y' = L^{-1} r_perm: back substitution gives the FP32-data solution
-    if (lane <= NC) {
-#pragma unroll
-        for (int cc = 0; cc <= NC; cc++) Lm[lane * m + cc] = cc <= lane ? a[cc] : 0.0;
-    }
-    __syncthreads();
-    auto back_subst = [&](double* x) {
-        // x (permuted order) := L^{-T} x
-#pragma unroll
-        for (int i = NC; i >= 0; i--) {
-            double v = x[i];
-#pragma unroll
-            for (int k2 = i + 1; k2 <= NC; k2++) v -= Lm[k2 * m + i] * x[k2];
-            x[i] = v / Lm[i * m + i];
-        }
-    };
-    auto fwd_subst = [&](double* x) {
-#pragma unroll
-        for (int i = 0; i <= NC; i++) {
-            double v = x[i];
-#pragma unroll
-            for (int k2 = 0; k2 < i; k2++) v -= Lm[i * m + k2] * x[k2];
-            x[i] = v / Lm[i * m + i];
-        }
-    };
-    if (lane > NC && lane < NC + 1 + F) {
-        double x[NC + 1];
-#pragma unroll
-        for (int i = 0; i <= NC; i++) x[i] = a[i];
-        back_subst(x);
-        const int f = lane - NC - 1;
-        cv[f * m + 0] = x[NC];
-#pragma unroll
-        for (int i = 0; i < NC; i++) cv[f * m + i + 1] = x[i];
-    }
-    __syncthreads();
-    // ---------------- pass 2: FP64 residual B^T (y_w - B c)
-    const double ws = 1.0 / sqrt(W);
-    double sc[m];
-#pragma unroll
-    for (int i = 0; i < m; i++) sc[i] = isc[i] * ws;
-    int ga[KG], gf[KG];
-    double gacc[KG];
-#pragma unroll
-    for (int k = 0; k < KG; k++) {
-        const int e = lane + 64 * k;
-        ga[k] = e < m * F ? e / F : 0;
-        gf[k] = e < m * F ? m + e % F : m;
-        gacc[k] = 0.0;
-    }
-    s2_members<U>(g, j, thq, ct, stt, phq, dl, sh, [&](const bool* valid, const int* idx) {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            double x0 = 0.0, x1 = 0.0, x2 = 0.0, d = -2.0;
-            if (valid[u]) {
-                x0 = g.X[idx[u]];
-                x1 = g.X[g.cap + idx[u]];
-                x2 = g.X[2 * g.cap + idx[u]];
-                d = s2_dot(x0, x1, x2, q0, q1, q2);
-            }
-            const bool in = d > c;
-            const uint64_t mk = __ballot(in);
-            const int nin = __popcll(mk);
-            if (nin == 0) continue;
-            if (in) {
-                const int i = idx[u];
-                double b[m];
-                const double sw = member(x0, x1, x2, d, g.nu ? g.nu[i] : 1.0, b);
-                double* row = rows64 + rank_below(mk) * ROW64;
-#pragma unroll
-                for (int a2 = 0; a2 < m; a2++) {
-                    b[a2] *= sc[a2];
-                    row[a2] = b[a2];
-                }
-                for (int f = 0; f < F; f++) {
-                    double e = sw * ws * vals[(int64_t)f * g.cap + i];
-#pragma unroll
-                    for (int a2 = 0; a2 < m; a2++) e -= b[a2] * cv[f * m + a2];
-                    row[m + f] = e;
-                }
-            }
-            __syncthreads();
-            for (int r = 0; r < nin; r++) {
-                const double* row = rows64 + r * ROW64;
-#pragma unroll
-                for (int k = 0; k < KG; k++) gacc[k] = fma(row[ga[k]], row[gf[k]], gacc[k]);
-            }
-            __syncthreads();
-        }
-    });
-    // correction: solve with the same factor, value = c_0 + delta_0
-    double* gs = rows64;
-#pragma unroll
-    for (int k = 0; k < KG; k++) {
-        const int e = lane + 64 * k;
-        if (e < m * F) gs[e] = gacc[k];
-    }
-    __syncthreads();
-    if (lane < F) {
-        double x[NC + 1];
-#pragma unroll
-        for (int i = 0; i < NC; i++) x[i] = gs[(i + 1) * F + lane];
-        x[NC] = gs[lane];
-        fwd_subst(x);
-        back_subst(x);
-        A.out[(int64_t)(A.f0 + lane) * MQ + j] = cv[lane * m] + x[NC];
-    }
-    if (lane == 0 && A.write_diag) {
-        A.chi[j] = chi;
-        A.tau[j] = 0.0;
-        A.status[j] = rst;
-    }
+    mixed_node_core<m, FM, U>(j, lds, thr[j], vals, g.cap, F, A, nj, scan, key, row);
 }
 
 template <int K, int FM>
@@ -1794,7 +1524,7 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_value
 // FP64; S2 any degree, SO3/T3 m + 1 <= 16): four nodes per wave.  Nothing to
 // do for the other passes, which solve in place.
 bool split_solve(const Plan& P, int F) {
-    if (F != 1 || P.prm.precision != HAMLS_FP64) return false;
+    if (F != 1 || (P.prm.precision != HAMLS_FP64 && !P.mixed_fp64_step2)) return false;
     return P.dom == HAMLS_S2 || P.m + 1 <= 16;
 }
 

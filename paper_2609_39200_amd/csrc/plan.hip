@@ -84,10 +84,6 @@ static hamls_status check_params(const hamls_params* p, int32_t dims[3]) {
         set_error("unknown precision %d", p->precision);
         return HAMLS_ERR_INVALID_ARG;
     }
-    if (p->precision == HAMLS_MIXED && dom != HAMLS_S2) {
-        set_error("mixed precision is built for S2 only");
-        return HAMLS_ERR_UNSUPPORTED;
-    }
     int N = p->bandwidth;
     const int Nmax = dom == HAMLS_S2 ? 1024 : (dom == HAMLS_SO3 ? 128 : 511);
     if (N < 0 || N > Nmax) {
@@ -700,7 +696,7 @@ hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int3
                     const int R = N >= k + q ? (N - k - q) / 2 + 1 : 0;
                     const int R_pad = (R + 15) & ~15;
                     total += (int64_t)th_pad * R_pad;
-                    items += R_pad / 16;
+                    items += (R + 63) / 64;
                 }
             add(total, 4);
             add(2 * (int64_t)(N + 1), 8);
@@ -913,8 +909,9 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
         // re-solve of the flagged centres
         {
             PhaseTimer pt(*P, HAMLS_PHASE_ASSEMBLE, s);
-            if (P->dom == HAMLS_S2 && P->prm.precision == HAMLS_MIXED)
-                HAMLS_TRY(launch_s2_mixed(*P, Fc, f0, grid_values, s));
+            if (P->prm.precision == HAMLS_MIXED && !P->mixed_fp64_step2)
+                HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_mixed(*P, Fc, f0, grid_values, s)
+                                             : launch_grid_mixed(*P, Fc, f0, grid_values, s));
             else
                 HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_assemble(*P, Fc, f0, grid_values, s)
                                              : launch_grid_mls(*P, Fc, f0, grid_values, s));
@@ -934,9 +931,19 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
 // launch form (S2: 0 grid order, 1 cost order, > 1 queue; SO3 / T3: 0 or 1).
 // out: M_Q doubles for the passes that solve in place (SO3 / T3, m > 15).
 static hamls_status tune_pass(Plan* P, hipStream_t s, int form, double* out) {
-    if (P->dom != HAMLS_S2) return launch_grid_mls(*P, 1, 0, out, s, form);
-    return P->prm.precision == HAMLS_MIXED ? launch_s2_mixed(*P, 1, 0, out, s, form)
-                                           : launch_s2_assemble(*P, 1, 0, out, s, form);
+    const bool fp32 = P->prm.precision == HAMLS_MIXED && !P->mixed_fp64_step2;
+    if (P->dom != HAMLS_S2)
+        return fp32 ? launch_grid_mixed(*P, 1, 0, out, s, form) : launch_grid_mls(*P, 1, 0, out, s, form);
+    return fp32 ? launch_s2_mixed(*P, 1, 0, out, s, form) : launch_s2_assemble(*P, 1, 0, out, s, form);
+}
+
+// Step 2 of one field on zero values without the re-solve (the assembly
+// pass, plus the split solve where the pass hands one on): the cost compared
+// when a mixed plan chooses between its FP32-Gram and FP64 kernels.
+static hamls_status tune_step2(Plan* P, hipStream_t s, int form, double* out) {
+    HAMLS_TRY(tune_pass(P, s, form, out));
+    if (split_solve(*P, 1)) HAMLS_TRY(launch_split_solve(*P, 1, 0, out, s));
+    return HAMLS_OK;
 }
 
 // The cost order: the member counts of the bound nodes (one grid-order
@@ -1046,8 +1053,45 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
         if (best[c] < best[pick]) pick = c;
     P->asm_queue_blocks = cand[pick];
     if (queue_blocks) *queue_blocks = cand[pick];
+    if (P->prm.precision == HAMLS_MIXED) {
+        // step 2 of a mixed plan: the FP32-Gram pass (with its FP64 list)
+        // against the FP64 kernels, in the chosen form; the faster is kept
+        hamls_status st2 = tune_out(P, &out);
+        if (st2 != HAMLS_OK) return st2;
+        e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        float t2[2] = {1e30f, 1e30f};
+        for (int v = 0; v < 2 && e == hipSuccess && st2 == HAMLS_OK; v++) {
+            P->mixed_fp64_step2 = v == 1;
+            for (int rep = 0; rep < 3 && e == hipSuccess && st2 == HAMLS_OK; rep++) {
+                e = hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s);
+                if (e == hipSuccess) e = hipEventRecord(a, s);
+                if (e != hipSuccess) break;
+                st2 = tune_step2(P, s, P->asm_queue_blocks, out);
+                float ms = 0.0f;
+                if (st2 == HAMLS_OK) {
+                    e = hipEventRecord(b, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(b);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+                }
+                if (e == hipSuccess && st2 == HAMLS_OK && ms < t2[v]) t2[v] = ms;
+            }
+        }
+        (void)hipStreamSynchronize(s);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        (void)hipFree(out);
+        P->mixed_fp64_step2 = false;
+        if (st2 != HAMLS_OK) return st2;
+        if (e != hipSuccess) return hip_status(e, "tune");
+        P->mixed_fp64_step2 = t2[1] < t2[0];
+        if (times_ms) {
+            times_ms[2] = t2[0];
+            times_ms[3] = t2[1];
+        }
+    }
     if (times_ms)
-        for (int c = 0; c < 4; c++) times_ms[c] = best[c];
+        for (int c = 0; c < ncand; c++) times_ms[c] = best[c];
     return HAMLS_OK;
 }
 

@@ -73,7 +73,14 @@ struct Resident {
 struct Pending {
     hamls_request req;
     double t_submit;
+    int bypassed = 0;  // times a later request was admitted ahead of this one at the head
 };
+
+// A blocked head of the queue may be passed by later requests that fit now
+// (backfilling), at most this many times per head, so that it is not starved.
+constexpr int kMaxBypass = 8;
+// Later requests examined for backfilling.
+constexpr int kBackfillScan = 32;
 
 }  // namespace
 
@@ -96,6 +103,8 @@ struct Server {
 
     void worker(int w);
     hamls_status run(Resident& e, const Pending& p, bool reuse, hipStream_t s);
+    hamls_status place(const hamls_request& r, Resident** e, int64_t* need, int64_t* mcap);
+    int64_t evictable(const Resident* keep) const;
 };
 
 namespace {
@@ -135,6 +144,39 @@ hamls_status Server::run(Resident& e, const Pending& p, bool reuse, hipStream_t 
     return HAMLS_OK;
 }
 
+// Where request r would run: an idle resident plan of equal parameters and
+// enough capacity, at most four times the capacity a new plan would get (its
+// cell grid follows its first node set), the smallest such; else a new plan.
+// Sets *e (null: new plan), the device bytes it adds (*need) and the new
+// plan's capacity (*mcap); returns the request's own error for invalid
+// parameters.
+hamls_status Server::place(const hamls_request& r, Resident** e, int64_t* need, int64_t* mcap) {
+    *e = nullptr;
+    const int64_t cap_new = capacity_for(r.M);
+    for (Resident* c : resident)
+        if (!c->busy && c->plan && c->mcap >= r.M && c->mcap <= 4 * cap_new && same_params(c->prm, r.params) &&
+            (!*e || c->mcap < (*e)->mcap))
+            *e = c;
+    if (*e) {
+        *mcap = (*e)->mcap;
+        *need = r.F > (*e)->F_grid ? 8 * (int64_t)(r.F - (*e)->F_grid) * (*e)->MQ : 0;
+        return HAMLS_OK;
+    }
+    *mcap = cap_new;
+    int64_t fp = 0, mq = 0;
+    HAMLS_TRY(plan_footprint(&r.params, r.M, cap_new, r.F, &fp, &mq));
+    *need = fp + 8 * (int64_t)r.F * mq;  // the plan and F x M_Q grid values
+    return HAMLS_OK;
+}
+
+// Bytes held by idle resident plans other than `keep` (what eviction frees).
+int64_t Server::evictable(const Resident* keep) const {
+    int64_t b = 0;
+    for (const Resident* c : resident)
+        if (!c->busy && c != keep) b += c->bytes;
+    return b;
+}
+
 void Server::worker(int w) {
     (void)hipSetDevice(device);
     hipStream_t s = streams[w];
@@ -145,34 +187,58 @@ void Server::worker(int w) {
             if (stop) return;
             continue;
         }
-        const Pending& head = queue.front();
-        const hamls_request& r = head.req;
-        // an idle resident plan of equal parameters and enough capacity, at
-        // most four times the capacity a new plan would get (its cell grid
-        // follows its first node set), the smallest such; else a new one
+        // the head of the queue, or (when it cannot fit until running requests
+        // finish) the first later request that fits now, if the head has been
+        // passed fewer than kMaxBypass times
+        size_t pick = 0;
         Resident* e = nullptr;
-        const int64_t cap_new = capacity_for(r.M);
-        for (Resident* c : resident)
-            if (!c->busy && c->plan && c->mcap >= r.M && c->mcap <= 4 * cap_new &&
-                same_params(c->prm, r.params) && (!e || c->mcap < e->mcap))
-                e = c;
-        const bool reuse = e != nullptr;
-        int64_t need = 0;
-        int64_t mcap = reuse ? e->mcap : cap_new;
-        if (reuse) {
-            need = r.F > e->F_grid ? 8 * (int64_t)(r.F - e->F_grid) * e->MQ : 0;
-        } else {
-            int64_t fp = 0, mq = 0;
-            hamls_status st = plan_footprint(&r.params, r.M, mcap, r.F, &fp, &mq);
+        int64_t need = 0, mcap = 0;
+        {
+            hamls_status st = place(queue[0].req, &e, &need, &mcap);
             if (st != HAMLS_OK) {
                 // invalid parameters: complete at once with the error
-                hamls_completion c{r.tag, (int32_t)st, 0, head.t_submit, now_s(), now_s()};
+                const Pending& head = queue.front();
+                hamls_completion c{head.req.tag, (int32_t)st, 0, head.t_submit, now_s(), now_s()};
                 queue.pop_front();
                 done.push_back(c);
                 cv_done.notify_all();
                 continue;
             }
-            need = fp + 8 * (int64_t)r.F * mq;  // the plan and F x M_Q grid values
+        }
+        bool fits = committed - evictable(e) + need <= budget;
+        if (!fits && running > 0 && queue[0].bypassed < kMaxBypass) {
+            const size_t lim = std::min(queue.size(), (size_t)kBackfillScan + 1);
+            for (size_t i = 1; i < lim && !fits; i++) {
+                Resident* e2 = nullptr;
+                int64_t need2 = 0, mcap2 = 0;
+                if (place(queue[i].req, &e2, &need2, &mcap2) != HAMLS_OK) continue;
+                if (committed - evictable(e2) + need2 <= budget) {
+                    pick = i;
+                    e = e2;
+                    need = need2;
+                    mcap = mcap2;
+                    fits = true;
+                }
+            }
+            if (fits) queue[0].bypassed++;
+        }
+        const bool reuse = e != nullptr;
+        if (!fits) {
+            const Pending& head = queue.front();
+            const uint64_t g0 = gen;
+            if (running == 0) {
+                // nothing left to finish: the head cannot fit even on an
+                // emptied server
+                hamls_completion c{head.req.tag, (int32_t)HAMLS_ERR_OUT_OF_MEMORY, 0, head.t_submit, now_s(),
+                                   now_s()};
+                queue.pop_front();
+                done.push_back(c);
+                cv_done.notify_all();
+                continue;
+            }
+            // wait until a running request finishes (its plan becomes idle)
+            cv_work.wait(lk, [&] { return stop || gen != g0; });
+            continue;
         }
         // evict idle plans, least recently used first, until the request fits
         std::vector<Resident*> evicted;
@@ -185,25 +251,8 @@ void Server::worker(int w) {
             committed -= v->bytes;
             evicted.push_back(v);
         }
-        if (committed + need > budget) {
-            const uint64_t g0 = gen;
-            if (running == 0) {
-                // nothing left to finish or evict: it cannot fit
-                hamls_completion c{r.tag, (int32_t)HAMLS_ERR_OUT_OF_MEMORY, 0, head.t_submit, now_s(),
-                                   now_s()};
-                queue.pop_front();
-                done.push_back(c);
-                cv_done.notify_all();
-            }
-            lk.unlock();
-            for (Resident* v : evicted) free_resident(v);
-            lk.lock();
-            // wait until a running request finishes (its plan becomes idle)
-            if (running > 0) cv_work.wait(lk, [&] { return stop || gen != g0; });
-            continue;
-        }
-        Pending p = head;
-        queue.pop_front();
+        Pending p = queue[pick];
+        queue.erase(queue.begin() + (std::ptrdiff_t)pick);
         if (!reuse) {
             e = new Resident();
             e->prm = p.req.params;

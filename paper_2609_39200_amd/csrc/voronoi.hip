@@ -6,9 +6,11 @@
 // One thread per sorted record x.  The cell {y : y.x >= y.x_j for all j} is
 // built in the gnomonic chart at x (y ~ x + u e1 + v e2): every other node x_j
 // bounds it by the half-plane
-//   (x.x - x.x_j) - u (e1.x_j) - v (e2.x_j) >= 0,
-// and a large square is clipped by the half-planes of the nodes of a cell
-// cover of the cap of radius rho around x (Sutherland-Hodgman).  With R the
+//   (x + u e1 + v e2).(x - x_j) >= 0,
+// and a square (half-width tan(rho), at most 1e4) is clipped by the
+// half-planes of the nodes of a cell cover of the cap of radius rho around x
+// (Sutherland-Hodgman; bands outward from x's own, nodes that cannot cut the
+// current polygon skipped).  With R the
 // largest angle from x to a vertex of the result, a node at angle d >= 2R
 // from x cannot cut the cell (its bisector lies beyond every vertex), so the
 // result is exact once 2R < rho; otherwise rho grows and the cell is rebuilt.
@@ -74,16 +76,21 @@ __global__ __launch_bounds__(kVorThreads) void k_s2_voronoi(VorGeom g, int64_t n
     double rho = sqrt(16.0 * acell / (kPi * (double)(chi - clo > 0 ? chi - clo : 1)));
     rho = fmin(fmax(rho, 1e-9), kPi);
     double result = nan("");
+    double wfix = 0.0;  // > 0: the window of a refining pass
     for (int attempt = 0; attempt < 40; attempt++) {
+        // the chart window: a cell accepted below lies within angle rho / 2
+        // of x, so a square of half-width tan(rho) holds it with room; a
+        // window near the cell's size keeps the clipped vertices accurate
+        const double W = wfix > 0.0 ? wfix : (rho < 1.5 ? tan(rho) : kVorWindow);
         int nv = 4;
-        pa[0] = -kVorWindow;
-        pa[1] = -kVorWindow;
-        pa[2] = kVorWindow;
-        pa[3] = -kVorWindow;
-        pa[4] = kVorWindow;
-        pa[5] = kVorWindow;
-        pa[6] = -kVorWindow;
-        pa[7] = kVorWindow;
+        pa[0] = -W;
+        pa[1] = -W;
+        pa[2] = W;
+        pa[3] = -W;
+        pa[4] = W;
+        pa[5] = W;
+        pa[6] = -W;
+        pa[7] = W;
         bool overflow = false;  // also set when the polygon vanishes (duplicate nodes)
         // the cells covering the cap of radius rho, widened by one band and
         // one sector on each side (rounding of the binning)
@@ -92,7 +99,15 @@ __global__ __launch_bounds__(kVorThreads) void k_s2_voronoi(VorGeom g, int64_t n
         blo = blo < 0 ? 0 : blo;
         bhi = bhi > g.nb - 1 ? g.nb - 1 : bhi;
         const double dphi = allphi ? kPi : asin(fmin(1.0, sin(rho) / sin(th0)));
-        for (int b = blo; b <= bhi && !overflow; b++) {
+        // cos of the current polygon's largest vertex angle R: a node at angle
+        // d >= 2R from x cannot cut it (nor the final cell, which lies inside)
+        double cmin_cur = 0.0;
+        // bands outward from x's own (near candidates first keep the
+        // intermediate polygons small)
+        const int nsteps = 2 * max(b0 - blo, bhi - b0) + 1;
+        for (int bs = 0; bs < nsteps && !overflow; bs++) {
+            const int b = (bs & 1) ? b0 - (bs + 1) / 2 : b0 + bs / 2;
+            if (b < blo || b > bhi) continue;
             const int ns = g.band_off[b + 1] - g.band_off[b];
             int ranges[4];
             int nr = 0;
@@ -122,9 +137,14 @@ __global__ __launch_bounds__(kVorThreads) void k_s2_voronoi(VorGeom g, int64_t n
                 for (int j = ranges[2 * q]; j < ranges[2 * q + 1]; j++) {
                     if (j == r) continue;
                     const double y0 = g.X[j], y1 = g.X[g.cap + j], y2 = g.X[2 * g.cap + j];
-                    const double bj = xx - (x0 * y0 + x1 * y1 + x2 * y2);
-                    const double cu = e10 * y0 + e11 * y1 + e12 * y2;
-                    const double cv = e20 * y0 + e21 * y1 + e22 * y2;
+                    const double dot = x0 * y0 + x1 * y1 + x2 * y2;
+                    if (dot < 2.0 * cmin_cur * cmin_cur - 1.0 - 1e-12) continue;
+                    // the half-plane (x + u e1 + v e2).(x - y) >= 0 through the
+                    // difference vector (no cancellation for close nodes)
+                    const double d0 = x0 - y0, d1 = x1 - y1, d2 = x2 - y2;
+                    const double bj = x0 * d0 + x1 * d1 + x2 * d2;
+                    const double cu = -(e10 * d0 + e11 * d1 + e12 * d2);
+                    const double cv = -(e20 * d0 + e21 * d1 + e22 * d2);
                     // clip the polygon pa (nv vertices) into pb
                     int no = 0;
                     double u1 = pa[2 * nv - 2], v1 = pa[2 * nv - 1];
@@ -159,49 +179,56 @@ __global__ __launch_bounds__(kVorThreads) void k_s2_voronoi(VorGeom g, int64_t n
                     pa = pb;
                     pb = t;
                     nv = no;
+                    double cm = 1.0;
+                    for (int k = 0; k < nv; k++)
+                        cm = fmin(cm, sqrt(xx / (xx + pa[2 * k] * pa[2 * k] + pa[2 * k + 1] * pa[2 * k + 1])));
+                    cmin_cur = cm;
                 }
             }
         }
         if (overflow || nv < 3) break;
         // largest angle from x to a vertex; the chart's edge
         bool edge = false;
-        double cmin = 1.0;
+        double cmin = 1.0, ext = 0.0;
         for (int k = 0; k < nv; k++) {
             const double u = pa[2 * k], v = pa[2 * k + 1];
-            if (fabs(u) >= 0.999999 * kVorWindow || fabs(v) >= 0.999999 * kVorWindow) edge = true;
+            if (fabs(u) >= 0.999999 * W || fabs(v) >= 0.999999 * W) edge = true;
+            ext = fmax(ext, fmax(fabs(u), fabs(v)));
             // cos of the angle between x and x + u e1 + v e2
             cmin = fmin(cmin, sqrt(xx) / sqrt(xx + u * u + v * v));
         }
         const double R = acos(fmin(1.0, cmin));
+        if (!edge && 2.0 * R < rho * (1.0 - 1e-9) && wfix == 0.0 && W > 4.0 * ext) {
+            // exact but clipped from a window much larger than the cell:
+            // once more from a square twice the cell's extent
+            wfix = 2.0 * ext;
+            continue;
+        }
         if (!edge && 2.0 * R < rho * (1.0 - 1e-9)) {
+            // Van Oosterom-Strackee in the chart: with y = (x + u e1 + v e2)/n,
+            // n = |x + u e1 + v e2|, the triple product of (x, y_k, y_l) is
+            // (u_k v_l - u_l v_k)/(n_k n_l) and the dot products are
+            // |x|/n and (x.x + u_k u_l + v_k v_l)/(n_k n_l): no cancellation
+            // for small cells
             double area = 0.0;
             const double xn = sqrt(xx);
             for (int k = 0; k < nv; k++) {
                 const int l = k + 1 < nv ? k + 1 : 0;
-                double a0 = x0 + pa[2 * k] * e10 + pa[2 * k + 1] * e20;
-                double a1 = x1 + pa[2 * k] * e11 + pa[2 * k + 1] * e21;
-                double a2 = x2 + pa[2 * k] * e12 + pa[2 * k + 1] * e22;
-                double c0 = x0 + pa[2 * l] * e10 + pa[2 * l + 1] * e20;
-                double c1 = x1 + pa[2 * l] * e11 + pa[2 * l + 1] * e21;
-                double c2 = x2 + pa[2 * l] * e12 + pa[2 * l + 1] * e22;
-                const double na = 1.0 / sqrt(a0 * a0 + a1 * a1 + a2 * a2);
-                const double nc = 1.0 / sqrt(c0 * c0 + c1 * c1 + c2 * c2);
-                a0 *= na;
-                a1 *= na;
-                a2 *= na;
-                c0 *= nc;
-                c1 *= nc;
-                c2 *= nc;
-                const double det = (x0 * (a1 * c2 - a2 * c1) + x1 * (a2 * c0 - a0 * c2) + x2 * (a0 * c1 - a1 * c0)) / xn;
-                const double den = 1.0 + (x0 * a0 + x1 * a1 + x2 * a2) / xn + (a0 * c0 + a1 * c1 + a2 * c2) +
-                                   (c0 * x0 + c1 * x1 + c2 * x2) / xn;
+                const double uk = pa[2 * k], vk = pa[2 * k + 1], ul = pa[2 * l], vl = pa[2 * l + 1];
+                const double nk = sqrt(xx + uk * uk + vk * vk), nl = sqrt(xx + ul * ul + vl * vl);
+                const double inn = 1.0 / (nk * nl);
+                const double det = (uk * vl - ul * vk) * inn;
+                const double den = 1.0 + xn / nk + xn / nl + (xx + uk * ul + vk * vl) * inn;
                 area += 2.0 * atan2(fabs(det), den);
             }
             result = area;
             break;
         }
-        if (edge || rho >= kPi) break;  // every node was in the cover: the cell reaches the chart's edge
-        rho = fmin(kPi, fmax(2.0 * rho, 2.05 * R));
+        if (wfix > 0.0) break;  // a refining pass that failed: keep NaN
+        if (rho >= kPi) break;  // every node was in the cover: the cell reaches the chart's edge
+        // a cover too small to close the cell (edge), or one that may miss a
+        // node closer than 2R: grow it
+        rho = edge ? fmin(kPi, 2.0 * rho) : fmin(kPi, fmax(2.0 * rho, 2.05 * R));
     }
     areas[g.perm[r]] = result;
 }

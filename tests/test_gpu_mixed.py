@@ -1,5 +1,6 @@
-"""GPU tests of the S2 mixed-precision path (FP32 Gram assembly with an FP64
-residual refinement and FP64 fallback; FP32 MFMA Legendre contraction).
+"""GPU tests of the mixed-precision path (FP32 Gram assembly with an FP64
+residual refinement and FP64 fallback on S2, SO(3) and T3; FP32 MFMA Legendre
+contraction on S2).
 
 Bar: within 1e-6 relative L2 of the FP64 path on the same inputs, grid values
 and coefficients; the FP64 path itself is held to the oracle elsewhere."""
@@ -113,8 +114,8 @@ def test_mixed_fixed_radius_and_degenerate(H):
 
 @pytest.mark.parametrize("F", [3, 19, 64, 70])
 def test_mixed_many_fields_mfma_tiles(H, F):
-    # F >= 8 fills whole 16-column MFMA tiles; 64 is one full launch of 8
-    # tiles, 70 needs a second launch
+    # the contraction's column chunks: F = 3 (one 32-column chunk), 19 (64),
+    # 64 (one 128-column chunk), 70 (a second 128-column chunk)
     rng = np.random.default_rng(100 + F)
     wl = W.s2_clusters(seed=2700, M=30000, N=40, K=2, field_degree=50)
     vals = np.concatenate([wl.values, rng.standard_normal((F - 1, wl.nodes.shape[0]))], axis=0)
@@ -123,3 +124,61 @@ def test_mixed_many_fields_mfma_tiles(H, F):
 
 def test_mixed_c3_full(H):
     _compare(H, W.s2_large(), "C3")
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_mixed_so3_degrees(H, K):
+    wl = W.so3_clusters(seed=5300 + K, M=20000, N=8, K=K, grid=(0, 0, 0), field_degree=6)
+    _compare(H, wl, f"so3 K{K}")
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_mixed_t3_degrees(H, K):
+    wl = W.t3_clusters(seed=5310 + K, M=20000, N=6, K=K, grid=14, kmax=6)
+    _compare(H, wl, f"t3 K{K}")
+
+
+def test_mixed_grid_fields(H):
+    rng = np.random.default_rng(5320)
+    wl = W.so3_clusters(seed=5321, M=15000, N=6, K=2, grid=(0, 0, 0), field_degree=5)
+    vals = np.concatenate([wl.values, rng.standard_normal((18, wl.nodes.shape[0]))], axis=0)
+    _compare(H, wl, "so3 F=19", values=vals)
+
+
+def test_mixed_so3_full(H):
+    # the SO(3) benchmark workload (C5a: M = 10^6, N = 64, K = 2, 130^3)
+    _compare(H, W.so3_clusters(), "so3 130^3")
+
+
+def test_mixed_t3_full(H):
+    # the T3 benchmark workload (C5b: M = 2 10^6, N = 64, K = 3, 128^3)
+    _compare(H, W.t3_clusters(), "t3 128^3")
+
+
+def test_mfma_contraction_c3_shape_64_fields(H):
+    """Step 3 at the large configuration's shape (N = 512, grid 513 x 1026)
+    with 64 fields of random grid values: the matrix-core contraction of the
+    mixed path against the FP64 path, every coefficient."""
+    import torch
+
+    wl = W.s2_clusters(seed=2800, M=20000, N=512, K=4, n_caps=3, field_degree=40)
+    gen = torch.Generator(device="cuda").manual_seed(2801)
+    out = {}
+    g = None
+    for prec in ("fp64", "mixed"):
+        p = H.params_from_workload(wl.params, precision=prec)
+        plan = H.hamls_plan(p, _dev(wl.nodes))
+        try:
+            info = H.hamls_plan_info_get(plan)
+            if g is None:
+                g = torch.randn((64, info.num_grid), dtype=torch.float64, device="cuda", generator=gen)
+            cf = torch.empty((64, info.num_coeffs, 2), dtype=torch.float64, device="cuda")
+            H.hamls_grid_to_coeffs(plan, g, cf)
+            torch.cuda.synchronize()
+            out[prec] = cf.cpu().numpy()
+        finally:
+            H.hamls_plan_destroy(plan)
+    e = _rell2(out["mixed"], out["fp64"])
+    emax = float(np.abs(out["mixed"] - out["fp64"]).max() / np.abs(out["fp64"]).max())
+    _say(f"[gpu-mixed] C3 shape, F = 64: coefficients rel L2 mixed vs FP64 {e:.3e}, max {emax:.3e}")
+    assert e < TOL_MIXED and emax < TOL_MIXED

@@ -207,3 +207,112 @@ def test_admission_budget_and_errors(H):
         assert done[i]["status"] == 0, (i, done[i])
         err = _rell2(cf.cpu().numpy(), _alone(H, p, nodes, vals))
         assert err <= (TOL if done[i]["plan_reused"] else 0.0), (i, err)
+
+
+def test_smoothed_and_plain_requests_do_not_share_plans(H):
+    """Requests equal in every parameter but the smoothed radius (Sec. 2.2,
+    after eq. (12)) must not rebind each other's resident plan: each result
+    equals its own request run alone."""
+    import torch
+
+    prng = np.random.default_rng(140)
+    x = W.cluster_hole_s2(20000, prng, caps=W.random_caps(3, 15.0, 20.0, prng))
+    v = prng.standard_normal((1, 20000))
+    base = W.serving_params(24, 3)
+    srv = H.hamls_server_create(1, 0)  # one worker: strictly sequential, plans stay resident
+    live = []
+    try:
+        for i, aux in enumerate([0, 4000, 0, 4000]):
+            p = H.params_from_workload(base, smooth_aux=aux)
+            # decreasing M: every later request fits a resident plan's capacity
+            nodes, vals = _dev(x[: 15000 - 1000 * i]), _dev(v[:, : 15000 - 1000 * i])
+            cf = torch.full((1, 25 * 25, 2), float("nan"), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            H.hamls_server_submit(srv, p, nodes, vals, cf, tag=i)
+            live.append((p, nodes, vals, cf))
+        done = _collect(H, srv, len(live))
+    finally:
+        H.hamls_server_destroy(srv)
+    assert all(c["status"] == 0 for c in done.values()), done
+    # the third and fourth reuse the plans of the first and second
+    assert [int(done[i]["plan_reused"]) for i in range(4)] == [0, 0, 1, 1]
+    for i, (p, nodes, vals, cf) in enumerate(live):
+        err = _rell2(cf.cpu().numpy(), _alone(H, p, nodes, vals))
+        _say("smooth_aux", p.smooth_aux, "reused", done[i]["plan_reused"], "rel l2", err)
+        assert err <= TOL
+
+
+def test_served_results_match_the_oracle(H):
+    """A sample of served results against the FP64 CPU oracle (steps 2 and 3
+    on the library's grid), on small requests of several N and K."""
+    import torch
+
+    import oracle
+
+    reqs = _requests()
+    sel = [0, 2, 5]  # N = 16, K = 2, M <= 5000
+    srv = H.hamls_server_create(2, 0)
+    live = []
+    try:
+        for i, r in enumerate(reqs):
+            p = H.params_from_workload(W.serving_params(r["N"], r["K"]))
+            nodes, vals = _dev(r["x"]), _dev(r["v"])
+            cf = torch.full((r["v"].shape[0], (r["N"] + 1) ** 2, 2), float("nan"), dtype=torch.float64,
+                            device="cuda")
+            torch.cuda.synchronize()
+            H.hamls_server_submit(srv, p, nodes, vals, cf, tag=i)
+            live.append(cf)
+        done = _collect(H, srv, len(reqs))
+    finally:
+        H.hamls_server_destroy(srv)
+    for i in sel:
+        assert done[i]["status"] == 0
+        r = reqs[i]
+        wp = W.serving_params(r["N"], r["K"])
+        po = oracle.params(**wp)
+        plan = H.hamls_plan(H.params_from_workload(wp), _dev(r["x"]))
+        gpts, _ = H.hamls_plan_grid(plan)
+        H.hamls_plan_destroy(plan)
+        om = oracle.mls(po, gpts, r["x"], r["v"])
+        oc = oracle.coeffs(po, om["values"])
+        c = live[i].cpu().numpy()
+        err = _rell2(c[..., 0] + 1j * c[..., 1], oc)
+        _say("served request", i, "vs oracle rel l2", err)
+        assert err < TOL
+
+
+def test_backfilling_passes_a_blocked_request(H):
+    """Under a budget with room for one large plan, a large request that waits
+    for a running one to finish is passed by a small request that fits, and
+    every result equals its request alone."""
+    import torch
+
+    prng = np.random.default_rng(150)
+    x = W.cluster_hole_s2(30000, prng, caps=W.random_caps(3, 15.0, 20.0, prng))
+    small = (16, 2, 3000)
+    large = (64, 4, 30000)
+    fp_large = H.hamls_plan_footprint(H.params_from_workload(W.serving_params(64, 4)), 32768, 1)
+    fp_small = H.hamls_plan_footprint(H.params_from_workload(W.serving_params(16, 2)), 16384, 1)
+    budget = int(1.5 * fp_large)
+    assert fp_small < budget - fp_large
+    srv = H.hamls_server_create(2, budget)
+    live = []
+    try:
+        for i, (N, K, M) in enumerate([large, large, small]):
+            p = H.params_from_workload(W.serving_params(N, K))
+            vals = _dev(prng.standard_normal((1, M)))
+            nodes = _dev(x[:M])
+            cf = torch.full((1, (N + 1) ** 2, 2), float("nan"), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            H.hamls_server_submit(srv, p, nodes, vals, cf, tag=i)
+            live.append((p, nodes, vals, cf))
+        done = _collect(H, srv, len(live))
+    finally:
+        H.hamls_server_destroy(srv)
+    assert all(c["status"] == 0 for c in done.values()), done
+    _say("admit times", [round(done[i]["t_admit"] - done[0]["t_admit"], 4) for i in range(3)])
+    # the small request was admitted before the second large one
+    assert done[2]["t_admit"] < done[1]["t_admit"]
+    for i, (p, nodes, vals, cf) in enumerate(live):
+        err = _rell2(cf.cpu().numpy(), _alone(H, p, nodes, vals))
+        assert err <= (TOL if done[i]["plan_reused"] else 0.0), (i, err)

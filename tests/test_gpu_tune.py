@@ -112,7 +112,14 @@ def test_forms_of_mixed_plans(H):
         assert _same(gv, gv0) and _same(cf, cf0) and np.array_equal(d["status"], d0["status"])
         choice, times = H.hamls_plan_tune(plan)
         _say("mixed tuned", choice, times)
-        assert choice in (0, 1) and times[0] > 0 and times[1] > 0 and times[2:] == [-1.0, -1.0]
+        # forms 0 / 1, then step 2 by the FP32-Gram pass [2] and by the FP64
+        # kernels [3]; the faster is kept, and either is within the mixed bar
+        assert choice in (0, 1) and min(times) > 0
+        H.hamls_plan_rebind(plan, nodes)
+        gv2, cf2, d2 = _fit(H, plan, vals)
+        ok = ~np.isnan(gv0)
+        assert np.array_equal(np.isnan(gv2), ~ok)
+        assert np.linalg.norm(gv2[ok] - gv0[ok]) <= 1e-6 * np.linalg.norm(gv0[ok])
         with pytest.raises(H.HamlsError):
             H.hamls_plan_assembly_form(plan, 256)
         with pytest.raises(H.HamlsError):
