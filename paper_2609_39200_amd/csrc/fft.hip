@@ -104,6 +104,11 @@ __device__ cplx<T>* fft_lines(cplx<T>* a, cplx<T>* b, int TL, int ld, int n, con
 
 // Lines (a, b) of the [A][nin][B] input (real or complex FP64), TL per
 // block: out[(a nout + k) B + b] = scale X_{(k - koff) mod nin}.
+// Real input is transformed in pairs: lines l and l + TL/2 of the block go
+// into one complex line z = x_l + i x_{l+TL/2}, and X_l(k) = (Z_k + conj
+// Z_{-k}) / 2, X_{l+TL/2}(k) = (Z_k - conj Z_{-k}) / (2i).  Strided lines
+// (B > 1) are loaded TL consecutive b at a time (128-byte segments for TL =
+// 16 real or 8 complex lines).
 __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in, int real_in,
                                                   double* __restrict__ out, int64_t A, int nin, int64_t B,
                                                   int nout, int koff, double sign, double scale,
@@ -112,7 +117,8 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in,
     double* stw = lds;  // cos [nin], sin [nin]
     cplx<double>* buf0 = (cplx<double>*)(lds + 2 * nin);
     const int ld = nin + 1;
-    cplx<double>* buf1 = buf0 + (int64_t)TL * ld;
+    const int NL = real_in ? TL / 2 : TL;  // complex lines transformed
+    cplx<double>* buf1 = buf0 + (int64_t)NL * ld;
     const int tid = threadIdx.x;
     const int64_t nlines = A * B;
     const int64_t L0 = (int64_t)blockIdx.x * TL;
@@ -138,10 +144,16 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in,
                 im = in[2 * addr + 1];
             }
         }
-        buf0[l * ld + i] = cplx<double>{re, im};
+        if (real_in) {
+            // line l < NL: real part; line l >= NL: imaginary part of line l - NL
+            double* slot = (double*)&buf0[(l % NL) * ld + i];
+            slot[l / NL] = re;
+        } else {
+            buf0[l * ld + i] = cplx<double>{re, im};
+        }
     }
     __syncthreads();
-    const cplx<double>* X = fft_lines<double>(buf0, buf1, TL, ld, nin, fp, stw, sign);
+    const cplx<double>* X = fft_lines<double>(buf0, buf1, NL, ld, nin, fp, stw, sign);
     for (int e = tid; e < TL * nout; e += blockDim.x) {
         int l, k;
         if (B > 1) {
@@ -155,7 +167,17 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in,
         if (L >= nlines) continue;
         int f = (k - koff) % nin;
         if (f < 0) f += nin;
-        const cplx<double> x = X[l * ld + f];
+        cplx<double> x;
+        if (real_in) {
+            const cplx<double> z = X[(l % NL) * ld + f];
+            const cplx<double> c = X[(l % NL) * ld + (f == 0 ? 0 : nin - f)];  // Z_{-k}
+            if (l < NL)
+                x = cplx<double>{0.5 * (z.re + c.re), 0.5 * (z.im - c.im)};
+            else
+                x = cplx<double>{0.5 * (z.im + c.im), -0.5 * (z.re - c.re)};
+        } else {
+            x = X[l * ld + f];
+        }
         const int64_t a = L / B, b = L - a * B;
         const int64_t o = (a * nout + k) * B + b;
         out[2 * o] = x.re * scale;
@@ -236,10 +258,16 @@ FftPlan make_fft_plan(int n) {
     return p;
 }
 
-bool fft_axis_fits(int nin) {
-    const FftPlan fp = make_fft_plan(nin);
-    return fp.nst > 0 && (size_t)sizeof(double) * (2 * (size_t)nin + 4 * (size_t)(nin + 1)) <= 65536;
+// Lines per block: 16 real lines (8 complex transforms) or 8 complex lines
+// when their two ping-pong buffers and the twiddles fit 64 KiB; 0 otherwise.
+static int fft_axis_lines(int nin, bool real_in) {
+    const int TL = real_in ? 16 : 8;
+    const int NL = real_in ? TL / 2 : TL;
+    const size_t bytes = sizeof(double) * 2 * (size_t)nin + 2 * 16 * (size_t)(nin + 1) * NL;
+    return bytes <= 65536 ? TL : 0;
 }
+
+bool fft_axis_fits(int nin) { return make_fft_plan(nin).nst > 0 && fft_axis_lines(nin, false) > 0; }
 
 hamls_status launch_fft_axis(const double* in, bool real_in, double* out, int64_t A, int nin, int64_t B,
                              int nout, int koff, double sign, double scale, const double* tw, hipStream_t s) {
@@ -248,21 +276,19 @@ hamls_status launch_fft_axis(const double* in, bool real_in, double* out, int64_
         set_error("fft axis: length %d has a prime factor above 19", nin);
         return HAMLS_ERR_UNSUPPORTED;
     }
-    // two ping-pong tiles of TL lines and the twiddles in at most 64 KiB
-    const int64_t per_line = 2 * 16 * (int64_t)(nin + 1);
-    int TL = (int)((65536 - 16 * (int64_t)nin) / per_line);
-    TL = TL > 16 ? 16 : TL;
+    const int TL = fft_axis_lines(nin, real_in);
     if (TL < 1) {
         set_error("fft axis: length %d too large", nin);
         return HAMLS_ERR_UNSUPPORTED;
     }
+    const int NL = real_in ? TL / 2 : TL;
     const int64_t nlines = A * B;
     const int64_t nblk = (nlines + TL - 1) / TL;
     if (nblk > 0x7fffffff) {
         set_error("fft axis: too many lines");
         return HAMLS_ERR_UNSUPPORTED;
     }
-    const size_t lds = sizeof(double) * 2 * (size_t)nin + (size_t)per_line * TL;
+    const size_t lds = sizeof(double) * 2 * (size_t)nin + 2 * 16 * (size_t)(nin + 1) * NL;
     hipLaunchKernelGGL(k_fft_axis, dim3((unsigned)nblk), dim3(256), lds, s, in, real_in ? 1 : 0, out, A, nin, B,
                        nout, koff, sign, scale, tw, TL, fp);
     HAMLS_HIP(hipGetLastError());

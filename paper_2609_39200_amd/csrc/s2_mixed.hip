@@ -18,8 +18,9 @@
 // Kernels: k_s2_fold_x transposes the FP64 ring spectra G[f][t][k] into the
 // FP32 folded spectra through an LDS tile (reads coalesced along k, writes
 // along the columns); k_s2_legendre_mfma computes a 64-row x CW-column tile
-// of one block per workgroup: the K = th_pad reduction runs in chunks of 32
-// rings staged in LDS (double-buffered, one barrier per chunk), and each of
+// of one block per workgroup: the K = th_pad reduction runs in chunks of 16
+// or 32 rings staged in LDS (double-buffered, one barrier per chunk; the next
+// chunk's global loads in flight during the current chunk's MFMAs), and each of
 // the four waves accumulates 2 x CW/32 tiles of v_mfma_f32_16x16x4f32
 // (A 16x4, B 4x16, D 16x16, FP32 accumulate: lane l holds A[l % 16][l / 16],
 // B[l / 16][l % 16] and D[4 (l / 16) + r][l % 16], r < 4).
@@ -82,7 +83,6 @@ struct LegItem {
 };
 
 constexpr int kMfmaRows = 64;  // rows per workgroup tile (4 waves: 2 x 2 row halves / column halves)
-constexpr int kMfmaTK = 32;    // rings per LDS chunk
 
 // One workgroup (256 threads) per (item, column chunk of CW): rows
 // [64 rt, 64 rt + 64) of block (k, p) against columns [cw0, cw0 + CW).
@@ -95,10 +95,11 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
                                                          const float* __restrict__ X, int N, int F, int th_pad,
                                                          int C_pad, double* __restrict__ coeffs) {
     constexpr int NCT = CW / 32;          // column tiles of 16 per wave
+    constexpr int kMfmaTK = CW == 128 ? 16 : 32;  // rings per LDS chunk (LDS for four blocks per CU)
     constexpr int LA = kMfmaRows + 16;    // LDS row strides (padded against bank conflicts)
     constexpr int LB = CW + 16;
-    __shared__ float As[2][kMfmaTK * LA];
-    __shared__ float Bs[2][kMfmaTK * LB];
+    __shared__ __align__(16) float As[2][kMfmaTK * LA];
+    __shared__ __align__(16) float Bs[2][kMfmaTK * LB];
     const LegItem it = items[blockIdx.x];
     const int k = it.k, p = it.p;
     const int cw0 = blockIdx.y * CW;
@@ -111,18 +112,44 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
     const int wr = (w >> 1) * 32, wc = (w & 1) * (CW / 2);
     const int nchunk = (th_pad + kMfmaTK - 1) / kMfmaTK;
 
-    // stage chunk q of A (kMfmaTK rings x 64 rows) and B (x CW columns)
-    auto stage = [&](int q, int buf) {
+    // chunk q of A (kMfmaTK rings x 64 rows) and B (x CW columns) in 16-byte
+    // pieces: loaded into registers one chunk ahead (in flight during the
+    // MFMAs of the current chunk), then stored to the other LDS buffer
+    constexpr int NA = kMfmaTK * kMfmaRows / 4 / 256;  // float4 of A per thread
+    constexpr int NBv = kMfmaTK * CW / 4 / 256;        // float4 of B per thread
+    static_assert(NA * 256 * 4 == kMfmaTK * kMfmaRows && NBv * 256 * 4 == kMfmaTK * CW, "chunk split");
+    float4 ra[NA], rb[NBv];
+    auto gload = [&](int q) {
         const int t0 = q * kMfmaTK;
-        for (int e = tid; e < kMfmaTK * kMfmaRows; e += 256) {
+#pragma unroll
+        for (int v = 0; v < NA; v++) {
+            const int e = (tid + 256 * v) * 4;
             const int tt = e / kMfmaRows, rr = e - tt * kMfmaRows;
             const int t = t0 + tt, r = r0 + rr;
-            As[buf][tt * LA + rr] = (t < th_pad && r < R_pad) ? A[(int64_t)t * R_pad + r] : 0.0f;
+            ra[v] = (t < th_pad && r < R_pad) ? *(const float4*)(A + (int64_t)t * R_pad + r)
+                                              : float4{0.0f, 0.0f, 0.0f, 0.0f};
         }
-        for (int e = tid; e < kMfmaTK * CW; e += 256) {
+#pragma unroll
+        for (int v = 0; v < NBv; v++) {
+            const int e = (tid + 256 * v) * 4;
             const int tt = e / CW, cc = e - tt * CW;
             const int t = t0 + tt, c = cw0 + cc;
-            Bs[buf][tt * LB + cc] = (t < th_pad && c < C_pad) ? B[(int64_t)t * C_pad + c] : 0.0f;
+            rb[v] = (t < th_pad && c < C_pad) ? *(const float4*)(B + (int64_t)t * C_pad + c)
+                                              : float4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < NA; v++) {
+            const int e = (tid + 256 * v) * 4;
+            const int tt = e / kMfmaRows, rr = e - tt * kMfmaRows;
+            *(float4*)(As[buf] + tt * LA + rr) = ra[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NBv; v++) {
+            const int e = (tid + 256 * v) * 4;
+            const int tt = e / CW, cc = e - tt * CW;
+            *(float4*)(Bs[buf] + tt * LB + cc) = rb[v];
         }
     };
 
@@ -132,11 +159,12 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
 #pragma unroll
         for (int c = 0; c < NCT; c++) acc[i][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    stage(0, 0);
+    gload(0);
+    lstore(0);
     __syncthreads();
     for (int q = 0; q < nchunk; q++) {
         const int buf = q & 1;
-        if (q + 1 < nchunk) stage(q + 1, buf ^ 1);  // the other buffer is free: read before the last barrier
+        if (q + 1 < nchunk) gload(q + 1);
         const float* as = As[buf];
         const float* bs = Bs[buf];
 #pragma unroll
@@ -151,6 +179,8 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
                 acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][c], 0, 0, 0);
             }
         }
+        // the other buffer was last read before the previous barrier
+        if (q + 1 < nchunk) lstore(buf ^ 1);
         __syncthreads();
     }
 

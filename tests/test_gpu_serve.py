@@ -261,7 +261,7 @@ def test_served_results_match_the_oracle(H):
                             device="cuda")
             torch.cuda.synchronize()
             H.hamls_server_submit(srv, p, nodes, vals, cf, tag=i)
-            live.append(cf)
+            live.append((nodes, vals, cf))  # inputs stay valid until completion
         done = _collect(H, srv, len(reqs))
     finally:
         H.hamls_server_destroy(srv)
@@ -275,7 +275,7 @@ def test_served_results_match_the_oracle(H):
         H.hamls_plan_destroy(plan)
         om = oracle.mls(po, gpts, r["x"], r["v"])
         oc = oracle.coeffs(po, om["values"])
-        c = live[i].cpu().numpy()
+        c = live[i][2].cpu().numpy()
         err = _rell2(c[..., 0] + 1j * c[..., 1], oc)
         _say("served request", i, "vs oracle rel l2", err)
         assert err < TOL
