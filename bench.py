@@ -63,6 +63,9 @@ WORKLOADS = {
     "c2fixed": ("s2_clusters_fixed", "S2 ill-distributed under a fixed radius (skewed neighbour counts 0-2400, "
                 "median 196), M=200000 (C2 nodes), N=128, K=3, grid 129x258, delta0=0.1 rad, chi_T=10 "
                 "chi_full=20, F=1, FP64"),
+    "c2hybrid": ("s2_clusters_hybrid", "S2 ill-distributed under the hybrid radius max(delta0, (1+eps) d_n) "
+                 "(neighbour counts ~44-5700, median ~630), M=200000 (C2 nodes), N=128, K=3, grid 129x258, "
+                 "delta0=0.16 rad, kNN n=40 eps=0.05, chi_T=10 chi_full=20, F=1, FP64"),
     "c2": ("s2_clusters", "S2 ill-distributed, M=200000 (8 vMF clusters kappa=20 + 20% uniform, 5 caps of 20 deg "
                           "removed), N=128, K=3, grid 129x258, kNN n=40 eps=0.05, chi_T=10 chi_full=20, F=1, FP64"),
     "c3": ("s2_large", "S2 ill-distributed, M=4000000 (8 vMF clusters kappa=20 + 20% uniform, 12 caps of 10-25 deg "

@@ -218,6 +218,14 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
  * and mixed plans. */
 hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t queue_blocks);
 
+/* Introspection of the cost order behind forms >= 1: order (host, M_Q int32)
+ * receives the grid nodes by decreasing member count -- buckets of
+ * floor(log2(n_j + 1)), heaviest first, grid order within a bucket -- as
+ * computed from the member counts of the node set at tuning.  Synchronizes
+ * the device.  INVALID_ARG for a null argument or a plan that has no order
+ * yet (never tuned nor set to a form >= 1). */
+hamls_status hamls_plan_cost_order(hamls_plan_t plan, int32_t* order);
+
 /* ---- captured fits (HIP graphs) ----
  * Steps 2 and 3 on a resident plan have fixed shapes: a fit whose buffers do
  * not change between calls (repeated fields on one node set, a served plan)

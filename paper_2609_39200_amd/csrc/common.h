@@ -25,6 +25,9 @@ constexpr double kPi = 3.141592653589793238462643383279502884;
 constexpr int kWave = 64;
 constexpr int kMaxFieldsPerPass = 16;  // fields handled by one assembly pass
 constexpr int kRadixTile = 1024;       // keys per block of a radix sort pass
+constexpr int kTileItems = 2048;       // grid nodes per block of the tiled order / row-pointer passes
+constexpr int kOrderBuckets = 33;      // cost-order buckets (floor(log2(n_j + 1)) mapped to 1..32)
+inline int tile_count(int64_t n) { return (int)((n + kTileItems - 1) / kTileItems); }
 constexpr int kCandCap = 512;          // LDS candidate buffer of the S2 radius search
 constexpr int kGridCandCap = 416;      // LDS candidate buffer of the SO3 / T3 radius search
 constexpr int kListCap = 128;          // S2 member list of a grid node (radius -> assembly)
@@ -46,6 +49,12 @@ hamls_status hip_status(hipError_t e, const char* what);
     do {                                                       \
         hipError_t e_ = (call);                                \
         if (e_ != hipSuccess) return hip_status(e_, #call);    \
+    } while (0)
+
+#define HAMLS_TRY(x)                       \
+    do {                                   \
+        hamls_status s_ = (x);             \
+        if (s_ != HAMLS_OK) return s_;     \
     } while (0)
 
 // Geometry of the S2 binning: nb equal-angle bands in theta, band b split into
@@ -131,6 +140,7 @@ struct Plan {
     int32_t* d_rs_list = nullptr;   // MQ, centres re-solved in double-double
     int32_t* d_rs_count = nullptr;  // [0] re-solve list, [1] FP64 list of the mixed path
     int32_t* d_mx_list = nullptr;   // MQ, nodes the mixed path hands to FP64
+    int32_t* d_rs_sorted = nullptr; // MQ, the re-solve list by decreasing member count
     int64_t n_entries_cap = 0;
     double* d_vals = nullptr;       // sorted values, kMaxFieldsPerPass x cap
     // generating functions (Rem. 2.5): per grid node the coefficients gamma
@@ -148,6 +158,10 @@ struct Plan {
     // them faster than the FP32-Gram pass (step 3 stays FP32 on MFMA)
     bool mixed_fp64_step2 = false;
     int32_t* d_order = nullptr;
+    // per-tile counts of the tiled cost order and row-pointer scan
+    // (kOrderBuckets x tiles uint32, or tiles int64)
+    uint32_t* d_tiles = nullptr;
+    int64_t tiles_len = 0;
     int64_t gen_cap = 0;            // entries the CSR buffers hold
     int64_t gen_nnz = 0;
     bool gen_ready = false;         // built for the bound node set

@@ -94,6 +94,43 @@ __device__ __forceinline__ int wave_incl_scan_int(int v) {
     return v;
 }
 
+__device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t v) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up((long long)v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum of v[0, n) in place by one block of 1024 threads
+// (each a contiguous chunk); *total receives the sum when not null.  For the
+// small per-tile count arrays of the multi-block sorts and scans.
+template <class T>
+__global__ __launch_bounds__(1024) void k_exclusive_scan(T* __restrict__ v, int64_t n, T* __restrict__ total) {
+    __shared__ T part[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t lo = t * chunk < n ? t * chunk : n, hi = lo + chunk < n ? lo + chunk : n;
+    T own = 0;
+    for (int64_t i = lo; i < hi; i++) own += v[i];
+    part[t] = own;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const T x = t >= o ? part[t - o] : (T)0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    T run = part[t] - own;
+    for (int64_t i = lo; i < hi; i++) {
+        const T x = v[i];
+        v[i] = run;
+        run += x;
+    }
+    if (t == 1023 && total) *total = part[1023];
+}
+
 // Ints of LDS one wave needs for s2_scan.
 constexpr int kScanLds = 4 * 64 + 1;
 
@@ -371,11 +408,10 @@ __device__ __forceinline__ dd readlane_dd(dd v, int l) {
 //     unknown of eq. (22), without the cancellation of 1 - sum d^2/(1 + tau mu).
 // Fewer than m neighbours or a zero column: the tau -> infinity limit (the
 // weighted mean).  A pivot of C below kPivResolve, chi < 1 by rounding or a Schur
-// denominator below kDenResolve: the raw entries go to entries_out and the node to
-// the re-solve list.
+// denominator below kDenResolve: the node goes to the re-solve list.
 template <int m>
 __device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int F, int j,
-                                   const SolveArgs& A, double* entries_out) {
+                                   const SolveArgs& A, double* /*unused*/) {
     constexpr int NC = m - 1;
     constexpr int EG = m * (m + 1) / 2;
     const int lane = threadIdx.x & 63;
@@ -481,7 +517,6 @@ __device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int
         if (!(den > kDenResolve)) ill = true;
     }
     if (ill) {
-        for (int e = lane; e < EG + m * F; e += 64) entries_out[(int64_t)e * MQ + j] = Gs[e];
         if (lane == 0) {
             const int slot = atomicAdd(A.rs_count, 1);
             A.rs_list[slot] = j;

@@ -29,29 +29,44 @@ __global__ __launch_bounds__(64) void k_gen_solve(const double* __restrict__ gra
     if (live) mls_solve_group<m, GS, m, true>(gl + g * E, A.nj[j], j, A);
 }
 
-// row_ptr = exclusive prefix sum of the neighbour counts (one block).
-__global__ __launch_bounds__(1024) void k_gen_rowptr(const int32_t* __restrict__ nj, int64_t MQ,
-                                                     int64_t* __restrict__ row_ptr) {
-    __shared__ int64_t part[1024];
+// row_ptr = exclusive prefix sum of the neighbour counts, over tiles of
+// kTileItems grid nodes: the tile sums, one scan of them (which also writes
+// row_ptr[MQ], the entry count), and each tile's scan from its base.
+__global__ __launch_bounds__(256) void k_tile_sums(const int32_t* __restrict__ nj, int64_t MQ,
+                                                   int64_t* __restrict__ sums) {
+    __shared__ int64_t ws[4];
     const int t = threadIdx.x;
-    const int64_t chunk = (MQ + 1023) / 1024;
-    const int64_t lo = t * chunk, hi = lo + chunk < MQ ? lo + chunk : MQ;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
     int64_t own = 0;
-    for (int64_t i = lo; i < hi; i++) own += nj[i];
-    part[t] = own;
+    for (int r = 0; r < kTileItems / 256; r++) {
+        const int64_t j = base + r * 256 + t;
+        if (j < MQ) own += nj[j];
+    }
+    own = wave_incl_scan_i64(own);
+    if ((t & 63) == 63) ws[t >> 6] = own;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        const int64_t v = t >= o ? part[t - o] : 0;
+    if (t == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void k_tile_rowptr(const int32_t* __restrict__ nj, int64_t MQ,
+                                                     const int64_t* __restrict__ bases,
+                                                     int64_t* __restrict__ row_ptr) {
+    __shared__ int64_t ws[4];
+    const int t = threadIdx.x, w = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    int64_t carry = bases[blockIdx.x];
+    for (int r = 0; r < kTileItems / 256; r++) {
+        const int64_t j = base + r * 256 + t;
+        const int64_t x = j < MQ ? (int64_t)nj[j] : 0;
+        const int64_t incl = wave_incl_scan_i64(x);
+        if ((t & 63) == 63) ws[w] = incl;
         __syncthreads();
-        part[t] += v;
+        int64_t pre = carry;
+        for (int w2 = 0; w2 < w; w2++) pre += ws[w2];
+        if (j < MQ) row_ptr[j] = pre + incl - x;
+        carry += ws[0] + ws[1] + ws[2] + ws[3];
         __syncthreads();
     }
-    int64_t run = part[t] - own;
-    for (int64_t i = lo; i < hi; i++) {
-        row_ptr[i] = run;
-        run += nj[i];
-    }
-    if (t == 1023) row_ptr[MQ] = part[1023];
 }
 
 // out[f0 + f][j] = sum_e val[e] vals[f][col[e]] over row j, col the original
@@ -131,7 +146,16 @@ hamls_status launch_gen_solve(const Plan& P, hipStream_t s) {
 }
 
 hamls_status launch_gen_rowptr(const Plan& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_gen_rowptr, dim3(1), dim3(1024), 0, s, P.d_nj, P.MQ, P.d_grow);
+    const int nt = tile_count(P.MQ);
+    if (!P.d_tiles || 2 * (int64_t)nt > P.tiles_len) {
+        set_error("tile buffer too small");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    int64_t* sums = (int64_t*)P.d_tiles;
+    hipLaunchKernelGGL(k_tile_sums, dim3(nt), dim3(256), 0, s, P.d_nj, P.MQ, sums);
+    hipLaunchKernelGGL((k_exclusive_scan<int64_t>), dim3(1), dim3(1024), 0, s, sums, (int64_t)nt,
+                       P.d_grow + P.MQ);
+    hipLaunchKernelGGL(k_tile_rowptr, dim3(nt), dim3(256), 0, s, P.d_nj, P.MQ, sums, P.d_grow);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

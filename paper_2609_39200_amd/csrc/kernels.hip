@@ -1157,6 +1157,21 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
         }
     };
     s2_members<U>(g, j, thq, ct, stt, phq, dl, sh, body);
+    if (DD && SPLIT) {
+        // hand the double-double Gram on to the solve kernel: hi parts at
+        // [0, E), lo parts at [EG + m FM, ...), the member count after them
+#pragma unroll
+        for (int k = 0; k < KE; k++) {
+            int e = lane + 64 * k;
+            if (e < E) {
+                const dd v = fast_two_sum(accd[k].hi, accd[k].lo);
+                entries_out[e] = v.hi;
+                entries_out[EG + m * FM + e] = v.lo;
+            }
+        }
+        if (lane == 0) entries_out[2 * (EG + m * FM)] = (double)count;
+        return;
+    }
     if (DD) {
         double* Gh = rows;
         double* Gl = rows + EG + m * FM;
@@ -1255,6 +1270,53 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
     }
 }
 
+// The extended-precision re-solve in two kernels over a chunk [c0, c0 + ch)
+// of the re-solve list: the double-double Gram accumulation (the member scan
+// and its rows, no solve registers: several waves per SIMD), then the
+// double-double factorization and regularized solve from the handed-on Gram
+// (per node dd_stride(m, FM) doubles of the hand-off buffer).  The same
+// arithmetic in the same order as one fused kernel.
+constexpr int dd_stride(int m, int FM) { return 2 * (m * (m + 1) / 2 + m * FM) + 2; }
+
+template <int K, int FM>
+__global__ __launch_bounds__(64) void k_s2_dd_gram(S2Geom g, const double* __restrict__ vals, int F, int wendland,
+                                                  const double* __restrict__ thr, const double* __restrict__ delta,
+                                                  SolveArgs A, int32_t* __restrict__ nj, double* __restrict__ ddg,
+                                                  int64_t c0, int64_t ch) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    __shared__ __align__(16) double rows[64 * (m + FM + 1)];
+    __shared__ int sh[kScanLds];
+    const int64_t n = *A.in_count;
+    const int64_t hi = n < c0 + ch ? n : c0 + ch;
+    for (int64_t li = c0 + blockIdx.x; li < hi; li += gridDim.x) {
+        s2_node<K, FM, true, true>(A.in_list[li], rows, sh, g, vals, F, wendland, thr, delta, A, nj,
+                                   ddg + (li - c0) * dd_stride(m, FM));
+        __syncthreads();
+    }
+}
+
+template <int m, int FM, bool UNIT>
+__global__ __launch_bounds__(64) void k_dd_solve(const double* __restrict__ ddg, SolveArgs A, int F, int64_t c0,
+                                                int64_t ch) {
+    constexpr int EF = m * (m + 1) / 2 + m * FM;
+    __shared__ __align__(16) double buf[2 * EF + m];
+    const int lane = threadIdx.x;
+    const int E = m * (m + 1) / 2 + m * F;
+    const int64_t n = *A.in_count;
+    const int64_t hi = n < c0 + ch ? n : c0 + ch;
+    for (int64_t li = c0 + blockIdx.x; li < hi; li += gridDim.x) {
+        const double* src = ddg + (li - c0) * dd_stride(m, FM);
+        for (int e = lane; e < E; e += 64) {
+            buf[e] = src[e];
+            buf[EF + e] = src[EF + e];
+        }
+        const int count = (int)src[2 * EF];
+        __syncthreads();
+        mls_dd_epilogue<m, UNIT>(buf, buf + EF, buf + 2 * EF, count, F, A.in_list[li], A);
+        __syncthreads();
+    }
+}
+
 // Work-queue form of the one-field FP64 assembly pass (split solve): a fixed
 // grid of blocks takes grid nodes, heaviest first, from the cost order.  The
 // order is dealt over the 8 XCDs (node k of the order to XCD k mod 8; blocks
@@ -1273,8 +1335,7 @@ __global__ __launch_bounds__(64) void k_s2_assemble_queue(S2Geom g, const double
                                                          const int32_t* __restrict__ order,
                                                          int32_t* __restrict__ counters) {
     constexpr int m = (K + 1) * (K + 2) / 2;
-    constexpr int ROW = m + 1 + 1;
-    __shared__ __align__(16) double rows[64 * ROW];
+    __shared__ __align__(16) double rows[64 * (m + 2)];
     __shared__ int sh[kScanLds];
     __shared__ int next;
     const int64_t MQ = A.MQ;
@@ -1297,15 +1358,14 @@ __global__ __launch_bounds__(64) void k_s2_assemble_queue(S2Geom g, const double
 // dispatcher starts blocks in index order as slots free up, so the heaviest
 // nodes start first, with no atomics.
 template <int K>
-__global__ __launch_bounds__(64) void k_s2_assemble_ordered(S2Geom g, const double* __restrict__ vals,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_s2_assemble_ordered(S2Geom g, const double* __restrict__ vals,
                                                            int wendland, const double* __restrict__ thr,
                                                            const double* __restrict__ delta, SolveArgs A,
                                                            int32_t* __restrict__ nj,
                                                            double* __restrict__ entries_out,
                                                            const int32_t* __restrict__ order) {
     constexpr int m = (K + 1) * (K + 2) / 2;
-    constexpr int ROW = m + 1 + 1;
-    __shared__ __align__(16) double rows[64 * ROW];
+    __shared__ __align__(16) double rows[64 * (m + 2)];
     __shared__ int sh[kScanLds];
     s2_node<K, 1, false, true>(order[xcd_block(blockIdx.x, gridDim.x)], rows, sh, g, vals, 1, wendland, thr, delta, A,
                                nj, entries_out);
@@ -1314,38 +1374,93 @@ __global__ __launch_bounds__(64) void k_s2_assemble_ordered(S2Geom g, const doub
 // Grid nodes ordered by decreasing cost: buckets of floor(log2(n_j + 1))
 // (coarse is enough for scheduling), heaviest bucket first, and grid order
 // within a bucket (a stable counting sort), so that runs of the order stay
-// spatially close for the XCD-aware block mapping.  One block of 256 threads,
-// each owning a contiguous chunk of grid nodes.
-__global__ __launch_bounds__(256) void k_cost_order(const int32_t* __restrict__ nj, int64_t MQ,
-                                                    int32_t* __restrict__ order) {
-    constexpr int NB = 33, T = 256;
-    __shared__ int cnt[NB * T];  // [bucket][thread]: counts, then offsets
+// spatially close for the XCD-aware block mapping.  Three launches over tiles
+// of kTileItems grid nodes: per-tile bucket counts (bucket-major), one
+// exclusive scan of that count matrix, and a stable scatter that ranks equal
+// buckets by ballot matching, round by round in grid order.
+__device__ __forceinline__ int cost_bucket(int32_t n) {
+    const uint32_t v = (uint32_t)max(n, 0) + 1u;
+    return 32 - (31 - __builtin_clz(v));  // 1..32, heavier nodes first
+}
+
+// Items i < n (n = *count when count is given, else MQ): grid node
+// j = list[i] (or i), bucket of nj[j].
+__global__ __launch_bounds__(256) void k_order_count(const int32_t* __restrict__ nj, int64_t MQ,
+                                                     const int32_t* __restrict__ list,
+                                                     const int32_t* __restrict__ count,
+                                                     uint32_t* __restrict__ hist, int ntiles) {
+    __shared__ uint32_t h[kOrderBuckets];
     const int t = threadIdx.x;
-    const int64_t chunk = (MQ + T - 1) / T;
-    const int64_t lo = t * chunk, hi = lo + chunk < MQ ? lo + chunk : MQ;
-    auto bucket = [&](int64_t j) {
-        const uint32_t v = (uint32_t)max(nj[j], 0) + 1u;
-        return 32 - (31 - __builtin_clz(v));  // heavier nodes get smaller bucket numbers
-    };
-    for (int b = 0; b < NB; b++) cnt[b * T + t] = 0;
-    for (int64_t j = lo; j < hi; j++) cnt[bucket(j) * T + t]++;
+    if (t < kOrderBuckets) h[t] = 0u;
     __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int e = 0; e < NB * T; e++) {
-            const int c = cnt[e];
-            cnt[e] = run;
-            run += c;
-        }
+    const int64_t n = count ? (int64_t)*count : MQ;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    for (int r = 0; r < kTileItems / 256; r++) {
+        const int64_t i = base + r * 256 + t;
+        if (i < n) atomicAdd(&h[cost_bucket(nj[list ? list[i] : i])], 1u);
     }
     __syncthreads();
-    for (int64_t j = lo; j < hi; j++) order[cnt[bucket(j) * T + t]++] = (int32_t)j;
+    if (t < kOrderBuckets) hist[(int64_t)t * ntiles + blockIdx.x] = h[t];
+}
+
+__global__ __launch_bounds__(256) void k_order_scatter(const int32_t* __restrict__ nj, int64_t MQ,
+                                                       const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ count,
+                                                       const uint32_t* __restrict__ hist, int ntiles,
+                                                       int32_t* __restrict__ order) {
+    __shared__ uint32_t off[kOrderBuckets];
+    __shared__ uint32_t cnt[4][kOrderBuckets];
+    const int t = threadIdx.x, w = t >> 6;
+    if (t < kOrderBuckets) off[t] = hist[(int64_t)t * ntiles + blockIdx.x];
+    const int64_t n = count ? (int64_t)*count : MQ;
+    const int64_t base = (int64_t)blockIdx.x * kTileItems;
+    for (int r = 0; r < kTileItems / 256; r++) {
+        const int64_t i = base + r * 256 + t;
+        const bool valid = i < n;
+        const int32_t j = valid ? (list ? list[i] : (int32_t)i) : 0;
+        const int d = valid ? cost_bucket(nj[j]) : 0;
+        if (t < 4 * kOrderBuckets) cnt[t / kOrderBuckets][t % kOrderBuckets] = 0u;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 6; b++) {
+            const uint64_t mb = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? mb : ~mb;
+        }
+        const int rank = rank_below(peers);
+        if (valid && rank == 0) cnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = off[d] + (uint32_t)rank;
+            for (int w2 = 0; w2 < w; w2++) pos += cnt[w2][d];
+            order[pos] = j;
+        }
+        __syncthreads();
+        if (t < kOrderBuckets) off[t] += cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+        __syncthreads();
+    }
+}
+
+// The items in cost order: list (or 0..MQ-1) by decreasing bucket of nj, the
+// list's order within a bucket; n = *count (or MQ) items, at most MQ.
+static hamls_status cost_sort(const Plan& P, const int32_t* list, const int32_t* count, int32_t* out,
+                              hipStream_t s) {
+    const int nt = tile_count(P.MQ);
+    if (!P.d_tiles || (int64_t)kOrderBuckets * nt > P.tiles_len) {
+        set_error("tile buffer too small");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL(k_order_count, dim3(nt), dim3(256), 0, s, P.d_nj, P.MQ, list, count, P.d_tiles, nt);
+    hipLaunchKernelGGL((k_exclusive_scan<uint32_t>), dim3(1), dim3(1024), 0, s, P.d_tiles,
+                       (int64_t)kOrderBuckets * nt, (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_order_scatter, dim3(nt), dim3(256), 0, s, P.d_nj, P.MQ, list, count, P.d_tiles, nt,
+                       out);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
 }
 
 hamls_status launch_cost_order(const Plan& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(256), 0, s, P.d_nj, P.MQ, P.d_order);
-    HAMLS_HIP(hipGetLastError());
-    return HAMLS_OK;
+    return cost_sort(P, nullptr, nullptr, P.d_order, s);
 }
 
 // Mixed precision, one S2 node per wave (FP32 assembly with FP64 safeguards, Rem. 2.4):
@@ -1585,23 +1700,39 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
 
 // Re-solve of the nodes flagged by the FP64 epilogue: the same assembly in
 // double-double precision, blocks striding over the list.
+// The re-solve list in chunks of the hand-off buffer (the plan's Gram
+// hand-off array d_entries, free at this point of the pass): one chunk for
+// one field, two for up to 16.
+template <int K, int FM, bool UNIT>
+static void s2_resolve_chunks(const Plan& P, const S2Geom& g, const SolveArgs& A, int F, hipStream_t s) {
+    constexpr int m = (K + 1) * (K + 2) / 2;
+    const int64_t cap = P.n_entries_cap * P.MQ;
+    int64_t ch = cap / dd_stride(m, FM);
+    ch = ch < P.MQ ? ch : P.MQ;
+    const dim3 grid(list_blocks(ch)), block(64);
+    for (int64_t c0 = 0; c0 < P.MQ; c0 += ch) {
+        hipLaunchKernelGGL((k_s2_dd_gram<K, FM>), grid, block, 0, s, g, P.d_vals, F, P.prm.wendland, P.d_thr,
+                           P.d_delta, A, P.d_nj, P.d_entries, c0, ch);
+        hipLaunchKernelGGL((k_dd_solve<m, FM, UNIT>), grid, block, 0, s, P.d_entries, A, F, c0, ch);
+    }
+}
+
 hamls_status launch_s2_resolve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
                                int unit_rhs) {
     if (P.m <= 1) return HAMLS_OK;
     S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    dim3 grid(list_blocks(P.MQ)), block(64);
-    int wl = P.prm.wendland;
-#define HAMLS_DDS(KK)                                                                                 \
-    if (unit_rhs)                                                                                     \
-        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, true, true, false, true>), grid, block, 0, s, g, \
-                           P.d_vals, F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);             \
-    else if (F == 1)                                                                                  \
-        hipLaunchKernelGGL((k_s2_assemble<KK, 1, true, true>), grid, block, 0, s, g, P.d_vals, F, wl, P.d_thr, \
-                           P.d_delta, A, P.d_nj, P.d_entries);                                        \
-    else                                                                                              \
-        hipLaunchKernelGGL((k_s2_assemble<KK, kMaxFieldsPerPass, true, true>), grid, block, 0, s, g, P.d_vals, \
-                           F, wl, P.d_thr, P.d_delta, A, P.d_nj, P.d_entries);
+    // heaviest nodes first (the list comes in the order the solve flagged
+    // them; a node with thousands of members started late would trail)
+    HAMLS_TRY(cost_sort(P, A.in_list, A.in_count, P.d_rs_sorted, s));
+    A.in_list = P.d_rs_sorted;
+#define HAMLS_DDS(KK)                                                  \
+    if (unit_rhs)                                                      \
+        s2_resolve_chunks<KK, kMaxFieldsPerPass, true>(P, g, A, F, s); \
+    else if (F == 1)                                                   \
+        s2_resolve_chunks<KK, 1, false>(P, g, A, F, s);                \
+    else                                                               \
+        s2_resolve_chunks<KK, kMaxFieldsPerPass, false>(P, g, A, F, s);
     switch (P.K) {
         case 1: HAMLS_DDS(1) break;
         case 2: HAMLS_DDS(2) break;

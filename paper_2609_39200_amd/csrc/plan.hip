@@ -200,12 +200,6 @@ static hamls_status dalloc(Plan& P, T** ptr, size_t count) {
     return HAMLS_OK;
 }
 
-#define HAMLS_TRY(x)                       \
-    do {                                   \
-        hamls_status s_ = (x);             \
-        if (s_ != HAMLS_OK) return s_;     \
-    } while (0)
-
 static void free_plan(Plan* P) {
     if (!P) return;
     for (auto& r : P->pending) {
@@ -342,6 +336,9 @@ static hamls_status alloc_common(Plan& P, int dimx) {
     HAMLS_TRY(dalloc(P, &P.d_rs_list, P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_rs_count, 64));
     HAMLS_TRY(dalloc(P, &P.d_mx_list, P.MQ));
+    HAMLS_TRY(dalloc(P, &P.d_rs_sorted, P.MQ));
+    P.tiles_len = (int64_t)kOrderBuckets * tile_count(P.MQ);
+    HAMLS_TRY(dalloc(P, &P.d_tiles, (size_t)P.tiles_len));
     HAMLS_TRY(dalloc(P, &P.d_vals, (size_t)kMaxFieldsPerPass * P.cap));
     return HAMLS_OK;
 }
@@ -664,6 +661,8 @@ hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int3
     add(MQ, 4);
     add(64, 4);
     add(MQ, 4);
+    add(MQ, 4);
+    add((int64_t)kOrderBuckets * tile_count(MQ), 4);
     add((int64_t)kMaxFieldsPerPass * cap, 8);
     const int N = P.N, K2 = 2 * N + 1;
     if (s2) {
@@ -948,8 +947,16 @@ static hamls_status tune_step2(Plan* P, hipStream_t s, int form, double* out) {
 
 // The cost order: the member counts of the bound nodes (one grid-order
 // assembly pass on zero values), then grid nodes by decreasing count.
+// The per-tile count buffer of the tiled cost order and row-pointer scan.
+static hamls_status ensure_tiles(Plan* P) {
+    if (P->d_tiles) return HAMLS_OK;  // allocated with the plan
+    P->tiles_len = (int64_t)kOrderBuckets * tile_count(P->MQ);
+    return dalloc(*P, &P->d_tiles, (size_t)P->tiles_len);
+}
+
 static hamls_status queue_order(Plan* P, hipStream_t s, double* out) {
     if (!P->d_order) HAMLS_TRY(dalloc(*P, &P->d_order, P->MQ));
+    HAMLS_TRY(ensure_tiles(P));
     HAMLS_HIP(hipMemsetAsync(P->d_vals, 0, sizeof(double) * (size_t)P->cap, s));
     HAMLS_HIP(hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s));
     HAMLS_TRY(tune_pass(P, s, 0, out));
@@ -984,6 +991,17 @@ hamls_status hamls_plan_assembly_form(hamls_plan_t plan, void* stream, int32_t q
         HAMLS_TRY(st);
     }
     P->asm_queue_blocks = queue_blocks;
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_cost_order(hamls_plan_t plan, int32_t* order) {
+    Plan* P = (Plan*)plan;
+    if (!P || !order || !P->d_order) {
+        set_error("null plan or order, or no cost order computed");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    HAMLS_HIP(hipDeviceSynchronize());
+    HAMLS_HIP(hipMemcpy(order, P->d_order, sizeof(int32_t) * (size_t)P->MQ, hipMemcpyDeviceToHost));
     return HAMLS_OK;
 }
 
@@ -1107,6 +1125,7 @@ hamls_status hamls_gen_build(hamls_plan_t plan, void* stream) {
         HAMLS_TRY(dalloc(*P, &P->d_gamma, (size_t)P->m * P->MQ));
         HAMLS_TRY(dalloc(*P, &P->d_grow, P->MQ + 1));
     }
+    HAMLS_TRY(ensure_tiles(P));
     P->gen_ready = false;
     // the assembly pass reads one field of sorted values and the double-double
     // re-solve up to 16 of them: zeros (their right-hand sides are replaced by

@@ -20,13 +20,6 @@
 
 #include "common.h"
 
-#ifndef HAMLS_TRY
-#define HAMLS_TRY(x)                       \
-    do {                                   \
-        hamls_status s_ = (x);             \
-        if (s_ != HAMLS_OK) return s_;     \
-    } while (0)
-#endif
 
 namespace hamls {
 namespace {
@@ -98,7 +91,8 @@ struct Server {
     int64_t committed = 0;
     int32_t running = 0;
     uint64_t use_clock = 0;
-    uint64_t gen = 0;  // bumped whenever a request finishes
+    uint64_t gen = 0;   // bumped whenever a request finishes
+    uint64_t qgen = 0;  // bumped whenever a request arrives
     bool stop = false;
 
     void worker(int w);
@@ -237,7 +231,9 @@ void Server::worker(int w) {
                 continue;
             }
             // wait until a running request finishes (its plan becomes idle)
-            cv_work.wait(lk, [&] { return stop || gen != g0; });
+            // or a new request arrives (it may fit where the head does not)
+            const uint64_t q0 = qgen;
+            cv_work.wait(lk, [&] { return stop || gen != g0 || qgen != q0; });
             continue;
         }
         // evict idle plans, least recently used first, until the request fits
@@ -355,7 +351,8 @@ hamls_status hamls_server_submit(hamls_server_t server, const hamls_request* r) 
         return HAMLS_ERR_INVALID_ARG;
     }
     S->queue.push_back(Pending{*r, now_s()});
-    S->cv_work.notify_one();
+    S->qgen++;
+    S->cv_work.notify_all();
     return HAMLS_OK;
 }
 

@@ -122,6 +122,7 @@ _SIGS = {
     "hamls_plan_footprint": [_P(hamls_params), _i64, _i32, _P(_i64)],
     "hamls_plan_tune": [_vp, _vp, _P(_i32), _vp],
     "hamls_plan_assembly_form": [_vp, _vp, _i32],
+    "hamls_plan_cost_order": [_vp, _vp],
     "hamls_fit_capture": [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _P(_vp)],
     "hamls_graph_launch": [_vp, _vp],
     "hamls_graph_destroy": [_vp],
@@ -461,3 +462,11 @@ def hamls_plan_tune(plan: int, stream=None) -> tuple:
 def hamls_plan_assembly_form(plan: int, queue_blocks: int, stream=None):
     _check(_lib.hamls_plan_assembly_form(C.c_void_p(plan), _stream(stream), int(queue_blocks)),
            "hamls_plan_assembly_form")
+
+
+def hamls_plan_cost_order(plan: int) -> np.ndarray:
+    """The plan's cost order (grid node indices, int32 M_Q) behind forms >= 1."""
+    info = hamls_plan_info_get(plan)
+    out = np.empty(info.num_grid, dtype=np.int32)
+    _check(_lib.hamls_plan_cost_order(C.c_void_p(plan), out.ctypes.data_as(C.c_void_p)), "hamls_plan_cost_order")
+    return out

@@ -321,6 +321,18 @@ def s2_clusters_fixed(seed: int = 2000, M: int = 200_000, N: int = 128, K: int =
     return wl
 
 
+def s2_clusters_hybrid(seed: int = 2000, M: int = 200_000, N: int = 128, K: int = 3,
+                       delta0: float = 0.16) -> Workload:
+    """The S2 cluster + hole nodes under the hybrid radius max(delta0, (1 +
+    eps) d_n) (both rules of eq. (12) and the fixed radius set, n = 4m): the
+    fixed radius holds ~250 nodes in the uniform part and up to ~5000 at the
+    cluster modes, while the adaptive one reaches across the holes."""
+    wl = s2_clusters(seed=seed, M=M, N=N, K=K)
+    wl.params = dict(wl.params, support_radius=float(delta0))
+    wl.name = f"s2-clusters-hybrid{delta0:g}-M{M}-N{N}-K{K}"
+    return wl
+
+
 def s2_clusters_smooth(seed: int = 2000, M: int = 200_000, N: int = 128, K: int = 3,
                        smooth_aux: int = 65536) -> Workload:
     """The S2 cluster + hole workload with the smoothed adaptive radius: d_n

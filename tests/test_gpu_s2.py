@@ -339,6 +339,15 @@ def test_c2_full_size_sampled_rows(H):
     R, om = _check_against_oracle(H, wl, rows=np.arange(0, 129 * 258, 97), label="C2")
 
 
+def test_c2_hybrid_radius_sampled_rows(H):
+    # both radius rules: delta = max(delta0, (1 + eps) d_n) on the C2 nodes,
+    # ~44 to ~5700 neighbours; every 97th grid node against the oracle
+    wl = W.s2_clusters_hybrid()
+    R, om = _check_against_oracle(H, wl, rows=np.arange(0, 129 * 258, 97), label="C2 hybrid")
+    _say(f"  neighbour counts of the sampled rows: {int(om['n'].min())}..{int(om['n'].max())}")
+    assert om["n"].max() > 2000 and om["n"].min() >= 40
+
+
 def test_constant_field_whole_pipeline(H):
     wl = W.s2_clusters(seed=2500, M=20000, N=32, K=3, field_degree=10)
     wl.values[:] = 1.0

@@ -295,17 +295,20 @@ def test_backfilling_passes_a_blocked_request(H):
     fp_small = H.hamls_plan_footprint(H.params_from_workload(W.serving_params(16, 2)), 16384, 1)
     budget = int(1.5 * fp_large)
     assert fp_small < budget - fp_large
-    srv = H.hamls_server_create(2, budget)
     live = []
+    for N, K, M in [large, large, small]:
+        p = H.params_from_workload(W.serving_params(N, K))
+        vals = _dev(prng.standard_normal((1, M)))
+        nodes = _dev(x[:M])
+        cf = torch.full((1, (N + 1) ** 2, 2), float("nan"), dtype=torch.float64, device="cuda")
+        live.append((p, nodes, vals, cf))
+    torch.cuda.synchronize()
+    srv = H.hamls_server_create(2, budget)
     try:
-        for i, (N, K, M) in enumerate([large, large, small]):
-            p = H.params_from_workload(W.serving_params(N, K))
-            vals = _dev(prng.standard_normal((1, M)))
-            nodes = _dev(x[:M])
-            cf = torch.full((1, (N + 1) ** 2, 2), float("nan"), dtype=torch.float64, device="cuda")
-            torch.cuda.synchronize()
+        # back to back: the small request arrives while the first large one
+        # runs and the second waits for its memory
+        for i, (p, nodes, vals, cf) in enumerate(live):
             H.hamls_server_submit(srv, p, nodes, vals, cf, tag=i)
-            live.append((p, nodes, vals, cf))
         done = _collect(H, srv, len(live))
     finally:
         H.hamls_server_destroy(srv)

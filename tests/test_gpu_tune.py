@@ -55,8 +55,23 @@ def _same(a, b):
     return np.array_equal(a, b, equal_nan=True)
 
 
-def test_queue_and_tuned_forms_equal_grid_order(H):
-    wl = W.s2_clusters_fixed(M=60000, N=48, K=3, delta0=0.15)
+def _check_cost_order(H, plan, n):
+    """The plan's cost order is the stable sort of the grid nodes by the
+    bucket floor(log2(n_j + 1)), heaviest first (bit-exact)."""
+    order = H.hamls_plan_cost_order(plan)
+    b = 32 - np.floor(np.log2(np.maximum(n, 0).astype(np.float64) + 1)).astype(np.int64)
+    expect = np.argsort(b, kind="stable").astype(np.int32)
+    _say("cost order:", order.size, "grid nodes, buckets", np.unique(b).size)
+    assert np.array_equal(order, expect)
+
+
+@pytest.mark.parametrize("rule", ["fixed", "hybrid"])
+def test_queue_and_tuned_forms_equal_grid_order(H, rule):
+    if rule == "fixed":
+        wl = W.s2_clusters_fixed(M=60000, N=48, K=3, delta0=0.15)
+    else:
+        # max(delta0, (1 + eps) d_n): no empty node, thousands at the modes
+        wl = W.s2_clusters_hybrid(M=60000, N=48, K=3, delta0=0.25)
     p = H.params_from_workload(wl.params)
     nodes = _dev(wl.nodes)
     plan = H.hamls_plan(p, nodes)
@@ -65,9 +80,14 @@ def test_queue_and_tuned_forms_equal_grid_order(H):
         gv0, cf0, d0 = _fit(H, plan, vals)
         n = d0["n"]
         _say("skew: min", int(n.min()), "median", float(np.median(n)), "max", int(n.max()))
-        assert n.min() == 0 and n.max() > 10 * np.median(n)
+        if rule == "fixed":
+            assert n.min() == 0 and n.max() > 10 * np.median(n)
+        else:
+            assert n.min() >= 40 and n.max() > 4 * np.median(n)
         for q in (1, 64, 1024, 3072):
             H.hamls_plan_assembly_form(plan, q)
+            if q == 1:
+                _check_cost_order(H, plan, n)
             gv, cf, d = _fit(H, plan, vals)
             assert _same(gv, gv0) and _same(cf, cf0), q
             for k in ("n", "status"):
@@ -147,7 +167,10 @@ def test_cost_order_on_grid_domains(H, domain):
     try:
         vals = _dev(rng.standard_normal((2, x.shape[0])))
         gv0, cf0, d0 = _fit(H, plan, vals)
+        with pytest.raises(H.HamlsError):
+            H.hamls_plan_cost_order(plan)  # no order before a form >= 1
         H.hamls_plan_assembly_form(plan, 1)
+        _check_cost_order(H, plan, d0["n"])
         gv, cf, d = _fit(H, plan, vals)
         assert _same(gv, gv0) and _same(cf, cf0)
         H.hamls_plan_rebind(plan, nodes)  # the radius search in cost order
