@@ -56,6 +56,16 @@ PHASE_KERNEL = {
            "contract": None, "gather": "k_gather_values"},
 }
 
+# file-name stem of a workload's committed rocprofv3 summaries
+PROFILE_NAME = {"c3": "s2_c3", "c2": "s2_c2", "c2fixed": "s2_c2_fixed_radius", "c2smooth": "s2_c2_smoothed_radius",
+                "c2hybrid": "s2_c2_hybrid_radius", "so3": "so3_m1e6_n64", "t3": "t3_m2e6_n64"}
+
+
+def _progress(msg):
+    """A progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 WORKLOADS = {
     "c2smooth": ("s2_clusters_smooth", "S2 ill-distributed (C2 nodes, M=200000), N=128, K=3, grid 129x258, smoothed "
                  "adaptive radius: d_n (n=40) on 65536 Fibonacci points, degree-zero MLS at the grid, eps=0.05, "
@@ -94,7 +104,7 @@ def measured_traffic(workload, kernel):
     rocprofv3 counter summary of this workload (FETCH_SIZE and WRITE_SIZE
     scaled by the copy calibration), or None when there is none or the HIP
     sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", f"{PROFILE_NAME.get(workload, workload)}_hbm_traffic.txt")
     if kernel is None or not os.path.exists(path):
         return None
     resolve = kernel.startswith("resolve:")
@@ -200,6 +210,7 @@ def main():
     cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=dev)
     gen_s = time.time() - t_gen
 
+    _progress(f"{args.workload}: inputs and plan ready ({gen_s:.1f} s)")
     # launch form of the assembly pass (grid order, cost order, S2 FP64 work
     # queue), measured on these nodes and kept by the plan
     tune = None
@@ -219,6 +230,7 @@ def main():
     for ph in H.PHASES:
         H.hamls_timing_read(plan, ph)  # clear
 
+    _progress("tuned and warmed up")
     # census (outside the timed region): every phase timed, per-fit latency;
     # each event pair costs a few microseconds of GPU time
     K = args.steps
@@ -323,6 +335,7 @@ def main():
     if tune is not None:
         out["assembly_launch"] = tune
 
+    _progress("census and timed fits done; captured fits, generating functions")
     out["captured_fit"] = graph_bench(H, torch, plan, info, vals, K)
     out["generating_functions"] = gen_bench(H, torch, plan, info, vals, gv, stream, K, 1e3 * wall / K)
 

@@ -941,6 +941,128 @@ __device__ void mls_dd_epilogue(const double* Gh, const double* Gl, double* isc,
     }
 }
 
+// mls_dd_epilogue by one group of GS lanes (GS / 64 nodes a wave): the same
+// double-double steps, row r of the system on group lane r (m + F <= GS),
+// broadcasts within the group, and the group's tau search.
+template <int GS>
+__device__ __forceinline__ dd grp_bcast_dd(dd x, int k) {
+    return {grp_bcast<GS>(x.hi, k), grp_bcast<GS>(x.lo, k)};
+}
+
+template <int m, int GS, bool UNIT>
+__device__ void mls_dd_group(const double* Gh, const double* Gl, int count, int F, int64_t j,
+                             const SolveArgs& A) {
+    constexpr int NC = m - 1;
+    constexpr int EG = m * (m + 1) / 2;
+    const int r = threadIdx.x & (GS - 1);
+    const int base = (threadIdx.x & 63) & ~(GS - 1);
+    const int64_t MQ = A.MQ;
+    const uint8_t rst = A.rstatus[j] | HAMLS_ST_ILLCOND;
+    const double W = Gh[0] + Gl[0];
+    auto gidx = [](int a, int b) { return a * m - a * (a - 1) / 2 + (b - a); };
+    if (count == 0 || !(W > 0.0)) {
+        if (r < F) A.out[(int64_t)(A.f0 + r) * MQ + j] = __builtin_nan("");
+        if (r == 0 && A.write_diag) {
+            A.chi[j] = __builtin_nan("");
+            A.tau[j] = __builtin_nan("");
+            A.status[j] = rst | HAMLS_ST_EMPTY;
+        }
+        return;
+    }
+    bool degen = count < m;
+    double inv = 1.0;  // 1 / sqrt(G_rr) on group lanes r < m
+    {
+        double v = 1.0;
+        if (r < m) v = sqrt(Gh[gidx(r, r)] + Gl[gidx(r, r)]);
+        if (grp_ballot<GS>(r < m && !(v > 0.0))) degen = true;
+        inv = 1.0 / v;
+    }
+    const double ws = 1.0 / sqrt(W);
+    dd a[NC + 1];
+    bool ill = degen;
+    double s_last = 1.0;
+    if (!ill) {
+        const int ar = r >= NC ? 0 : r + 1;
+        const double sr = r <= NC ? __shfl(inv, base + ar, 64) : ws;
+#pragma unroll
+        for (int c = 0; c <= NC; c++) {
+            const int bc = c == NC ? 0 : c + 1;
+            const double ib = grp_bcast<GS>(inv, bc);
+            dd v = {0.0, 0.0};
+            if (r <= NC) {
+                const int lo = ar < bc ? ar : bc, hi = ar < bc ? bc : ar;
+                const int e = gidx(lo, hi);
+                v = dd_mul_d(dd_mul_d({Gh[e], Gl[e]}, sr), ib);
+            } else if (r < NC + 1 + F) {
+                const int e = EG + bc * F + (r - NC - 1);
+                const dd rhs = UNIT ? dd{bc == A.f0 + r - NC - 1 ? 1.0 : 0.0, 0.0} : dd{Gh[e], Gl[e]};
+                v = dd_mul_d(dd_mul_d(rhs, sr), ib);
+            }
+            a[c] = v;
+        }
+        const double rank2 = kRankTol * kRankTol;
+#pragma unroll
+        for (int k = 0; k <= NC; k++) {
+            const dd sk = grp_bcast_dd<GS>(a[k], k);
+            if (k < NC) {
+                if (!(sk.hi > rank2)) {
+                    ill = true;
+                    break;
+                }
+            } else {
+                s_last = sk.hi;
+                if (!(sk.hi > 0.0)) {
+                    s_last = 0.0;
+                    break;
+                }
+            }
+            const dd lkk = dd_sqrt(sk);
+            const dd il = dd_recip(lkk);
+            a[k] = r == k ? lkk : dd_mul(a[k], il);
+#pragma unroll
+            for (int c = k + 1; c <= NC; c++) a[c] = dd_add(a[c], dd_neg(dd_mul(a[k], grp_bcast_dd<GS>(a[k], c))));
+        }
+    }
+    if (ill) {
+        // rank deficient: the tau -> infinity limit
+        if (r < F)
+            A.out[(int64_t)(A.f0 + r) * MQ + j] = (UNIT ? (A.f0 + r == 0 ? 1.0 : 0.0) : Gh[EG + r] + Gl[EG + r]) / W;
+        if (r == 0 && A.write_diag) {
+            A.chi[j] = __builtin_inf();
+            A.tau[j] = __builtin_inf();
+            A.status[j] = rst | HAMLS_ST_UNDERDETERMINED;
+        }
+        return;
+    }
+    double dv[NC > 0 ? NC : 1], d2[NC > 0 ? NC : 1], tf[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+        dv[k] = grp_bcast<GS>(a[k].hi, NC);
+        d2[k] = dv[k] * dv[k];
+    }
+    const double chi = 1.0 / s_last;
+    const double tau = NC > 0 ? choose_tau_grp<GS>(A.reg, chi, d2, A.mu, NC, A.tau_fixed, A.chi_t, A.chi_f) : 0.0;
+    double den = s_last;
+#pragma unroll
+    for (int k = 0; k < NC; k++) {
+        const double tm = tau * A.mu[k];
+        tf[k] = tm > 0.0 ? tm / (1.0 + tm) : 0.0;
+        den += d2[k] * tf[k];
+    }
+    const double rho = sqrt(s_last);
+    if (r > NC && r < NC + 1 + F) {
+        double num = s_last > 0.0 ? rho * a[NC].hi : 0.0;
+#pragma unroll
+        for (int k = 0; k < NC; k++) num += dv[k] * a[k].hi * tf[k];
+        A.out[(int64_t)(A.f0 + r - NC - 1) * MQ + j] = num / den;
+    }
+    if (r == 0 && A.write_diag) {
+        A.chi[j] = chi;
+        A.tau[j] = tau;
+        A.status[j] = rst | (tau > 0.0 ? HAMLS_ST_REGULARIZED : 0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // mixed precision (FP32 Gram, FP64 refinement), any domain
 // ---------------------------------------------------------------------------

@@ -1274,8 +1274,8 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
 // of the re-solve list: the double-double Gram accumulation (the member scan
 // and its rows, no solve registers: several waves per SIMD), then the
 // double-double factorization and regularized solve from the handed-on Gram
-// (per node dd_stride(m, FM) doubles of the hand-off buffer).  The same
-// arithmetic in the same order as one fused kernel.
+// (per node dd_stride(m, FM) doubles of the hand-off buffer), several nodes a
+// wave.
 constexpr int dd_stride(int m, int FM) { return 2 * (m * (m + 1) / 2 + m * FM) + 2; }
 
 template <int K, int FM>
@@ -1295,24 +1295,34 @@ __global__ __launch_bounds__(64) void k_s2_dd_gram(S2Geom g, const double* __res
     }
 }
 
+// Lanes per node of the double-double solve (m + F rows on a group).
+constexpr int dd_group_size(int m, int FM) { return m + FM <= 16 ? 16 : (m + FM <= 32 ? 32 : 64); }
+
 template <int m, int FM, bool UNIT>
 __global__ __launch_bounds__(64) void k_dd_solve(const double* __restrict__ ddg, SolveArgs A, int F, int64_t c0,
                                                 int64_t ch) {
     constexpr int EF = m * (m + 1) / 2 + m * FM;
-    __shared__ __align__(16) double buf[2 * EF + m];
-    const int lane = threadIdx.x;
+    constexpr int GS = dd_group_size(m, FM);
+    constexpr int NG = 64 / GS;
+    __shared__ __align__(16) double buf[NG][2 * EF];
+    const int g = threadIdx.x / GS, r = threadIdx.x % GS;
     const int E = m * (m + 1) / 2 + m * F;
     const int64_t n = *A.in_count;
     const int64_t hi = n < c0 + ch ? n : c0 + ch;
-    for (int64_t li = c0 + blockIdx.x; li < hi; li += gridDim.x) {
-        const double* src = ddg + (li - c0) * dd_stride(m, FM);
-        for (int e = lane; e < E; e += 64) {
-            buf[e] = src[e];
-            buf[EF + e] = src[EF + e];
+    for (int64_t b0 = c0 + (int64_t)blockIdx.x * NG; b0 < hi; b0 += (int64_t)gridDim.x * NG) {
+        const int64_t li = b0 + g;
+        const bool live = li < hi;
+        int count = 0;
+        if (live) {
+            const double* src = ddg + (li - c0) * dd_stride(m, FM);
+            for (int e = r; e < E; e += GS) {
+                buf[g][e] = src[e];
+                buf[g][EF + e] = src[EF + e];
+            }
+            count = (int)src[2 * EF];
         }
-        const int count = (int)src[2 * EF];
         __syncthreads();
-        mls_dd_epilogue<m, UNIT>(buf, buf + EF, buf + 2 * EF, count, F, A.in_list[li], A);
+        if (live) mls_dd_group<m, GS, UNIT>(buf[g], buf[g] + EF, count, F, A.in_list[li], A);
         __syncthreads();
     }
 }
@@ -1710,10 +1720,11 @@ static void s2_resolve_chunks(const Plan& P, const S2Geom& g, const SolveArgs& A
     int64_t ch = cap / dd_stride(m, FM);
     ch = ch < P.MQ ? ch : P.MQ;
     const dim3 grid(list_blocks(ch)), block(64);
+    const dim3 sgrid((grid.x + 64 / dd_group_size(m, FM) - 1) / (64 / dd_group_size(m, FM)));
     for (int64_t c0 = 0; c0 < P.MQ; c0 += ch) {
         hipLaunchKernelGGL((k_s2_dd_gram<K, FM>), grid, block, 0, s, g, P.d_vals, F, P.prm.wendland, P.d_thr,
                            P.d_delta, A, P.d_nj, P.d_entries, c0, ch);
-        hipLaunchKernelGGL((k_dd_solve<m, FM, UNIT>), grid, block, 0, s, P.d_entries, A, F, c0, ch);
+        hipLaunchKernelGGL((k_dd_solve<m, FM, UNIT>), sgrid, block, 0, s, P.d_entries, A, F, c0, ch);
     }
 }
 

@@ -92,7 +92,11 @@ def _check_against_oracle(H, wl, rows=None, check_lists=True, label=""):
         # points, so that the neighbour sets can be compared bit for bit
         _say("  grid: " + PAR.check_grids(gpts, gw, opts, ow))
         MQ = gpts.shape[0]
-        sel = np.arange(MQ) if rows is None else np.asarray(rows)
+        if callable(rows):
+            # rows chosen from the fit's diagnostics (e.g. the heaviest nodes)
+            sel = np.asarray(rows(H.hamls_diagnostics(R.plan)))
+        else:
+            sel = np.arange(MQ) if rows is None else np.asarray(rows)
         on = oracle.neighbors(po, gpts, wl.nodes, rows=sel, lists=check_lists)
         delta, thr = H.hamls_plan_radii(R.plan)
         if check_lists:
@@ -365,5 +369,13 @@ def test_c3_full_size_sampled_rows(H):
     # the large S2 case (M = 4e6, N = 512, K = 4, grid 513 x 1026) at full
     # size; the oracle checks every 211th grid node against brute force over
     # all nodes
+    # the 48 grid nodes with the most members (thousands, in the holes: the
+    # re-solve shares each of them among several waves) are checked as well
     wl = W.s2_large()
-    _check_against_oracle(H, wl, rows=np.arange(0, 513 * 1026, 211), check_lists=True, label="C3")
+
+    def rows(dg):
+        heavy = np.argsort(-dg["n"], kind="stable")[:48]
+        _say(f"  heaviest sampled nodes: {int(dg['n'][heavy].min())}..{int(dg['n'][heavy].max())} members")
+        return np.union1d(np.arange(0, 513 * 1026, 211), heavy)
+
+    _check_against_oracle(H, wl, rows=rows, check_lists=True, label="C3")
