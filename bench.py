@@ -397,7 +397,9 @@ def phase_work(domain, info, m, F, pairs, MQ, n_ill, n_ill_pairs):
 def contraction_bench(H, torch, wl, F, K):
     """The S2 Legendre contraction at F fields on random grid values: the FP64
     kernel of the plain path and the FP32 matrix-core kernel of the mixed path
-    (step 3 only; the contraction phase timed with HIP events).  FLOPs: for
+    (step 3 only; the contraction kernel timed with HIP events, and apart from
+    it the ring transforms and, on the mixed path, the fold of the spectra
+    into the FP32 blocks and the unfold into the coefficients).  FLOPs: for
     every table entry w_t P_n^k(x_t) of the northern rings (after the
     equatorial fold) and every field, one FMA each for the real and the
     imaginary part of the folded spectrum."""
@@ -417,14 +419,15 @@ def contraction_bench(H, torch, wl, F, K):
             cf = torch.empty((F, info.num_coeffs, 2), dtype=torch.float64, device=dev)
             H.hamls_grid_to_coeffs(plan, g, cf, stream=stream)
             torch.cuda.synchronize()
-            H.hamls_timing_phases(plan, ["contract", "ring_dft"])
+            H.hamls_timing_phases(plan, ["contract", "ring_dft", "fold"])
             H.hamls_timing_enable(plan, True)
-            H.hamls_timing_read(plan, "contract")
-            H.hamls_timing_read(plan, "ring_dft")
+            for ph in ("contract", "ring_dft", "fold"):
+                H.hamls_timing_read(plan, ph)
             for _ in range(K):
                 H.hamls_grid_to_coeffs(plan, g, cf, stream=stream)
             n, ms = H.hamls_timing_read(plan, "contract")
             nd, msd = H.hamls_timing_read(plan, "ring_dft")
+            _, msf = H.hamls_timing_read(plan, "fold")
             H.hamls_timing_enable(plan, False)
             N = info.bandwidth
             th = (info.grid_dims[0] + 1) // 2
@@ -433,7 +436,7 @@ def contraction_bench(H, torch, wl, F, K):
             avg = ms / n
             peak = PEAK_FP32_MFMA_TFLOPS if prec == "mixed" else PEAK_FP64_VALU_TFLOPS
             res[prec] = {"kernel": "k_s2_legendre_mfma" if prec == "mixed" else "k_s2_legendre",
-                         "avg_ms": avg, "ring_dft_ms": msd / nd, "flop": fl,
+                         "avg_ms": avg, "ring_dft_ms": msd / nd, "fold_unfold_ms": msf / K, "flop": fl,
                          "achieved": fl / (avg * 1e-3) / 1e12, "unit": "TFLOP/s", "peak": peak,
                          "frac": fl / (avg * 1e-3) / 1e12 / peak}
             if prec == "mixed":

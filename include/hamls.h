@@ -321,7 +321,9 @@ hamls_status hamls_diagnostics(hamls_plan_t plan, int32_t* n, double* chi, doubl
 #define HAMLS_PHASE_GATHER 6    /* value gather into sorted order */
 #define HAMLS_PHASE_GEN_APPLY 7 /* sparse product with the generating functions */
 #define HAMLS_PHASE_RESOLVE 8   /* re-solve of the ill-conditioned centres (extended precision) */
-#define HAMLS_NUM_PHASES 9
+#define HAMLS_PHASE_FOLD 9      /* step 3, S2 mixed: spectra folded into the FP32 contraction blocks and
+                                   the blocks unfolded into the coefficient layout */
+#define HAMLS_NUM_PHASES 10
 hamls_status hamls_timing_enable(hamls_plan_t plan, int32_t enable);
 /* Restricts the timing to the phases whose bit (1 << phase) is set in mask
  * (every phase by default): events are recorded around those phases only,

@@ -304,6 +304,7 @@ struct CoeffWorkSize {
 };
 struct CoeffWork {
     double* d0 = nullptr;
+    int64_t d0_len = 0;  // doubles
     double* d1 = nullptr;
     float* f0 = nullptr;
     int64_t f0_len = 0;
@@ -316,8 +317,14 @@ hamls_status run_grid_to_coeffs(Plan* P, const double* grid_values, int F, doubl
 
 hamls_status launch_s2_ring_dft(const Plan& P, const double* gv, int F, double* G, hipStream_t s);
 hamls_status launch_s2_legendre(const Plan& P, int F, const double* G, double* coeffs, hipStream_t s);
-hamls_status launch_s2_legendre_mfma(const Plan& P, int F, const double* G, float* X, int64_t xlen,
-                                     double* coeffs, hipStream_t s);
+// step 3 of the S2 mixed path: fold (FP64 spectra G -> FP32 blocks X), the
+// matrix-core contraction (X -> block-ordered FP32 output in G's memory),
+// unfold (-> coefficients)
+hamls_status launch_s2_fold(const Plan& P, int F, const double* G, int64_t glen, float* X, int64_t xcap,
+                            hipStream_t s);
+hamls_status launch_s2_legendre_mfma(const Plan& P, int F, const float* X, float* out, hipStream_t s);
+hamls_status launch_s2_unfold(const Plan& P, int F, const float* out, double* coeffs, hipStream_t s);
+int64_t s2_mfma_out_len(int N, int F);
 hamls_status build_s2_mfma_layout(Plan& P, std::vector<int64_t>& off, std::vector<int32_t>& items,
                                   int64_t* len);
 hamls_status launch_s2_mfma_table(const Plan& P, int64_t len, hipStream_t s);

@@ -91,6 +91,7 @@ hamls_status hamls_grid_to_coeffs_noalloc(hamls_plan_t plan, const double* grid_
     if (st != HAMLS_OK) return st;
     CoeffWork W;
     W.d0 = z.d0 > 0 ? (double*)base : nullptr;
+    W.d0_len = z.d0;
     W.d1 = z.d1 > 0 ? (double*)(base + b0) : nullptr;
     W.f0 = z.f0 > 0 ? (float*)(base + b0 + b1) : nullptr;
     W.f0_len = z.f0;

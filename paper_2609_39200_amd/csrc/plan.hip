@@ -732,6 +732,9 @@ CoeffWorkSize coeff_work_size(const Plan& P, int F) {
             const int th_pad = (((P.dims[0] + 1) / 2) + 3) & ~3;
             const int64_t C_pad = ((2 * (int64_t)F + 15) / 16) * 16;
             z.f0 = (int64_t)(N + 1) * 2 * th_pad * C_pad;
+            // the ring spectra's memory later holds the contraction's FP32
+            // block-ordered output
+            z.d0 = std::max(z.d0, (s2_mfma_out_len(N, F) + 1) / 2);
         }
     } else if (P.dom == HAMLS_SO3) {
         z.d0 = (int64_t)F * P.dims[0] * K2 * P.dims[2] * 2;
@@ -780,6 +783,7 @@ static CoeffWork plan_coeff_work(const Plan& P) {
     CoeffWork W;
     if (P.dom == HAMLS_S2) {
         W.d0 = P.d_G;
+        W.d0_len = P.G_fields > 0 ? coeff_work_size(P, P.G_fields).d0 : 0;
         W.f0 = P.d_x32;
         W.f0_len = P.x32_len;
     } else {
@@ -796,12 +800,20 @@ hamls_status run_grid_to_coeffs(Plan* P, const double* grid_values, int F, doubl
             PhaseTimer pt(*P, HAMLS_PHASE_RING_DFT, s, timed);
             HAMLS_TRY(launch_s2_ring_dft(*P, grid_values, F, W.d0, s));
         }
+        if (P->prm.precision == HAMLS_MIXED) {
+            {
+                PhaseTimer pt(*P, HAMLS_PHASE_FOLD, s, timed);
+                HAMLS_TRY(launch_s2_fold(*P, F, W.d0, W.d0_len, W.f0, W.f0_len, s));
+            }
+            {
+                PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s, timed);
+                HAMLS_TRY(launch_s2_legendre_mfma(*P, F, W.f0, (float*)W.d0, s));
+            }
+            PhaseTimer pt(*P, HAMLS_PHASE_FOLD, s, timed);
+            return launch_s2_unfold(*P, F, (const float*)W.d0, coeffs, s);
+        }
         PhaseTimer pt(*P, HAMLS_PHASE_CONTRACT, s, timed);
-        if (P->prm.precision == HAMLS_MIXED)
-            HAMLS_TRY(launch_s2_legendre_mfma(*P, F, W.d0, W.f0, W.f0_len, coeffs, s));
-        else
-            HAMLS_TRY(launch_s2_legendre(*P, F, W.d0, coeffs, s));
-        return HAMLS_OK;
+        return launch_s2_legendre(*P, F, W.d0, coeffs, s);
     }
     if (P->dom == HAMLS_SO3) {
         const int nb = P->dims[0], na = P->dims[1], ng = P->dims[2], N = P->N, K2 = 2 * N + 1;

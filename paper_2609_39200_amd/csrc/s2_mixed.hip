@@ -18,18 +18,16 @@
 // Kernels: k_s2_fold_x transposes the FP64 ring spectra G[f][t][k] into the
 // FP32 folded spectra through an LDS tile (reads coalesced along k, writes
 // along the columns); k_s2_legendre_mfma computes a 64-row x CW-column tile
-// of one block per workgroup: the K = th_pad reduction runs in chunks of 16
-// or 32 rings staged in LDS (double-buffered, one barrier per chunk; the next
+// of one block per workgroup: the K = th_pad reduction runs in chunks of 32
+// rings staged in LDS (double-buffered, one barrier per chunk; the next
 // chunk's global loads in flight during the current chunk's MFMAs), and each of
-// the four waves accumulates 2 x CW/32 tiles of v_mfma_f32_16x16x4f32
-// (A 16x4, B 4x16, D 16x16, FP32 accumulate: lane l holds A[l % 16][l / 16],
-// B[l / 16][l % 16] and D[4 (l / 16) + r][l % 16], r < 4).
+// the four waves accumulates its share in 32 x 32 tiles of
+// v_mfma_f32_32x32x2f32 (FP32 accumulate).
 #include "common.h"
 #include "device_common.h"
 
 namespace hamls {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFoldK = 32;   // orders per fold tile
 constexpr int kFoldC = 128;  // columns (64 fields) per fold tile
@@ -82,24 +80,39 @@ struct LegItem {
     int k, p, rt, pad;
 };
 
-constexpr int kMfmaRows = 64;  // rows per workgroup tile (4 waves: 2 x 2 row halves / column halves)
+constexpr int kMfmaRows = 64;  // rows per workgroup tile
+constexpr int kMfmaTK = 32;    // rings per LDS chunk
 
-// One workgroup (256 threads) per (item, column chunk of CW): rows
-// [64 rt, 64 rt + 64) of block (k, p) against columns [cw0, cw0 + CW).
-// Wave w owns rows 32 (w / 2) .. + 32 (two 16-row tiles) and columns
-// (CW / 2) (w % 2) .. + CW / 2 (CW / 32 tiles of 16).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Waves of the contraction's workgroup: two 32-row halves of the 64-row tile
+// times CW / 64 column groups (at least one).
+constexpr int mfma_waves(int CW) { return 2 * (CW >= 128 ? CW / 64 : 1); }
+
+// One workgroup (64 mfma_waves(CW) threads) per (item, column chunk of CW):
+// rows [64 rt, 64 rt + 64) of block (k, p) against columns [cw0, cw0 + CW).
+// Each wave owns one 32-row half and CW / WC columns, and accumulates
+// 1 x TC tiles of v_mfma_f32_32x32x2f32 (A 32x2, B 2x32, D 32x32 FP32: lane l
+// holds A[l % 32][l / 32], B[l / 32][l % 32] and
+// D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] in accumulator v < 16).  The
+// K = th_pad reduction runs in chunks of 32 rings staged in LDS, double
+// buffered: the next chunk's 16-byte global loads are in flight in registers
+// during the current chunk's MFMAs, then stored to the other buffer.
 template <int CW>
 __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restrict__ tab,
                                                          const int64_t* __restrict__ tab_off,
                                                          const LegItem* __restrict__ items,
                                                          const float* __restrict__ X, int N, int F, int th_pad,
-                                                         int C_pad, double* __restrict__ coeffs) {
-    constexpr int NCT = CW / 32;          // column tiles of 16 per wave
-    constexpr int kMfmaTK = CW == 128 ? 16 : 32;  // rings per LDS chunk (LDS for four blocks per CU)
-    constexpr int LA = kMfmaRows + 16;    // LDS row strides (padded against bank conflicts)
-    constexpr int LB = CW + 16;
-    __shared__ __align__(16) float As[2][kMfmaTK * LA];
-    __shared__ __align__(16) float Bs[2][kMfmaTK * LB];
+                                                         int C_pad, float* __restrict__ out) {
+    constexpr int NW = mfma_waves(CW);
+    constexpr int NT = 64 * NW;                 // threads
+    constexpr int WR = 2;                       // waves along the rows
+    constexpr int WC = NW / WR;                 // waves along the columns
+    constexpr int TR = kMfmaRows / WR / 32;     // 32-row MFMA tiles per wave
+    constexpr int TC = CW / WC / 32;            // 32-column MFMA tiles per wave
+    static_assert(TR == 1 && TC >= 1 && TC * 32 * WC == CW, "wave tile");
+    __shared__ __align__(16) float As[2][kMfmaTK * kMfmaRows];
+    __shared__ __align__(16) float Bs[2][kMfmaTK * CW];
     const LegItem it = items[blockIdx.x];
     const int k = it.k, p = it.p;
     const int cw0 = blockIdx.y * CW;
@@ -109,21 +122,18 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
     const float* A = tab + tab_off[2 * k + p];
     const float* B = X + ((int64_t)(2 * k + p) * th_pad) * C_pad;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * (CW / 2);
+    const int wr = (w / WC) * (kMfmaRows / WR), wc = (w % WC) * (CW / WC);
     const int nchunk = (th_pad + kMfmaTK - 1) / kMfmaTK;
 
-    // chunk q of A (kMfmaTK rings x 64 rows) and B (x CW columns) in 16-byte
-    // pieces: loaded into registers one chunk ahead (in flight during the
-    // MFMAs of the current chunk), then stored to the other LDS buffer
-    constexpr int NA = kMfmaTK * kMfmaRows / 4 / 256;  // float4 of A per thread
-    constexpr int NBv = kMfmaTK * CW / 4 / 256;        // float4 of B per thread
-    static_assert(NA * 256 * 4 == kMfmaTK * kMfmaRows && NBv * 256 * 4 == kMfmaTK * CW, "chunk split");
+    constexpr int NA = kMfmaTK * kMfmaRows / 4 / NT;  // float4 of A per thread
+    constexpr int NBv = kMfmaTK * CW / 4 / NT;        // float4 of B per thread
+    static_assert(NA * NT * 4 == kMfmaTK * kMfmaRows && NBv * NT * 4 == kMfmaTK * CW, "chunk split");
     float4 ra[NA], rb[NBv];
     auto gload = [&](int q) {
         const int t0 = q * kMfmaTK;
 #pragma unroll
         for (int v = 0; v < NA; v++) {
-            const int e = (tid + 256 * v) * 4;
+            const int e = (tid + NT * v) * 4;
             const int tt = e / kMfmaRows, rr = e - tt * kMfmaRows;
             const int t = t0 + tt, r = r0 + rr;
             ra[v] = (t < th_pad && r < R_pad) ? *(const float4*)(A + (int64_t)t * R_pad + r)
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
         }
 #pragma unroll
         for (int v = 0; v < NBv; v++) {
-            const int e = (tid + 256 * v) * 4;
+            const int e = (tid + NT * v) * 4;
             const int tt = e / CW, cc = e - tt * CW;
             const int t = t0 + tt, c = cw0 + cc;
             rb[v] = (t < th_pad && c < C_pad) ? *(const float4*)(B + (int64_t)t * C_pad + c)
@@ -141,23 +151,23 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int v = 0; v < NA; v++) {
-            const int e = (tid + 256 * v) * 4;
-            const int tt = e / kMfmaRows, rr = e - tt * kMfmaRows;
-            *(float4*)(As[buf] + tt * LA + rr) = ra[v];
+            const int e = (tid + NT * v) * 4;
+            *(float4*)(As[buf] + e) = ra[v];
         }
 #pragma unroll
         for (int v = 0; v < NBv; v++) {
-            const int e = (tid + 256 * v) * 4;
-            const int tt = e / CW, cc = e - tt * CW;
-            *(float4*)(Bs[buf] + tt * LB + cc) = rb[v];
+            const int e = (tid + NT * v) * 4;
+            *(float4*)(Bs[buf] + e) = rb[v];
         }
     };
 
-    f32x4 acc[2][NCT];
+    f32x16 acc[TR][TC];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < TR; i++)
 #pragma unroll
-        for (int c = 0; c < NCT; c++) acc[i][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int c = 0; c < TC; c++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) acc[i][c][v] = 0.0f;
 
     gload(0);
     lstore(0);
@@ -167,71 +177,156 @@ __global__ __launch_bounds__(256) void k_s2_legendre_mfma(const float* __restric
         if (q + 1 < nchunk) gload(q + 1);
         const float* as = As[buf];
         const float* bs = Bs[buf];
+        const int kmax = th_pad - q * kMfmaTK;  // rings of this chunk (a multiple of 4)
 #pragma unroll
-        for (int tk = 0; tk < kMfmaTK; tk += 4) {
-            const int kr = tk + (lane >> 4);
-            const float a0 = as[kr * LA + wr + (lane & 15)];
-            const float a1 = as[kr * LA + wr + 16 + (lane & 15)];
+        for (int tk = 0; tk < kMfmaTK; tk += 2) {
+            if (tk >= kmax) break;
+            const int kr = tk + (lane >> 5);
+            float a[TR], b[TC];
 #pragma unroll
-            for (int c = 0; c < NCT; c++) {
-                const float b = bs[kr * LB + wc + c * 16 + (lane & 15)];
-                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][c], 0, 0, 0);
-                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][c], 0, 0, 0);
-            }
+            for (int i = 0; i < TR; i++) a[i] = as[kr * kMfmaRows + wr + 32 * i + (lane & 31)];
+#pragma unroll
+            for (int c = 0; c < TC; c++) b[c] = bs[kr * CW + wc + 32 * c + (lane & 31)];
+#pragma unroll
+            for (int i = 0; i < TR; i++)
+#pragma unroll
+                for (int c = 0; c < TC; c++)
+                    acc[i][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[c], acc[i][c], 0, 0, 0);
         }
         // the other buffer was last read before the previous barrier
         if (q + 1 < nchunk) lstore(buf ^ 1);
         __syncthreads();
     }
 
-    const int64_t nc = (int64_t)(N + 1) * (N + 1);
-    const double sg = (k & 1) ? -1.0 : 1.0;
+    // the tile in the block's own order, [row < R_pad][2F columns] from the
+    // block's first row at tab_off / th_pad: lanes 0-31 write 32 consecutive
+    // columns of one row (k_s2_unfold scatters it into the coefficients)
+    float* o = out + tab_off[2 * k + p] / th_pad * (2 * F);
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < TR; i++)
 #pragma unroll
-        for (int c = 0; c < NCT; c++) {
-            const int col = cw0 + wc + c * 16 + (lane & 15);
+        for (int c = 0; c < TC; c++) {
+            const int col = cw0 + wc + 32 * c + (lane & 31);
             if (col >= 2 * F) continue;
-            const int f = col >> 1, part = col & 1;
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int rr = r0 + wr + 16 * i + 4 * (lane >> 4) + r;
-                if (rr >= R) continue;
-                const int n = k + p + 2 * rr;
-                const double v = (double)acc[i][c][r];
-                coeffs[((int64_t)f * nc + (int64_t)n * n + n + k) * 2 + part] = v;
-                if (k > 0)
-                    coeffs[((int64_t)f * nc + (int64_t)n * n + n - k) * 2 + part] = part == 0 ? sg * v : -sg * v;
+            for (int v = 0; v < 16; v++) {
+                const int rr = r0 + wr + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                if (rr < R) o[(int64_t)rr * (2 * F) + col] = acc[i][c][v];
             }
         }
 }
 
-hamls_status launch_s2_legendre_mfma(const Plan& P, int F, const double* G, float* X, int64_t xcap,
-                                     double* coeffs, hipStream_t s) {
-    const int nt = P.dims[0], N = P.N;
-    const int th = (nt + 1) / 2, th_pad = (th + 3) & ~3;
-    const int C_pad = ((2 * F + 15) / 16) * 16;
+// Fields per workgroup of k_s2_unfold.
+constexpr int kUnfoldF = 8;
+
+// Orders per LDS stage of k_s2_unfold.
+constexpr int kUnfoldK = 256;
+
+// The contraction's blocks (FP32, [row][2F] per (k, p), row r <-> degree
+// n = k + p + 2r) into the coefficient layout.  Workgroup (n, field chunk)
+// stages kUnfoldK orders k >= 0 of degree n at a time in LDS (one row of
+// block (k, (n - k) mod 2) each: 2 kUnfoldF consecutive floats), then
+// writes, field by field, the two contiguous runs of (n, +k) and (n, -k),
+// with fhat_{n,-k} = (-1)^k conj(fhat_{n,k}).
+__global__ __launch_bounds__(256) void k_s2_unfold(const float* __restrict__ blk, const int64_t* __restrict__ tab_off,
+                                                  int N, int F, int th_pad, double* __restrict__ coeffs) {
+    constexpr int cols = 2 * kUnfoldF;
+    __shared__ float v[kUnfoldK * cols];
+    const int n = blockIdx.x;
+    const int f0 = blockIdx.y * kUnfoldF;
+    const int nf = min(kUnfoldF, F - f0);
+    const int64_t nc = (int64_t)(N + 1) * (N + 1);
+    for (int k0 = 0; k0 <= n; k0 += kUnfoldK) {
+        const int nk = min(kUnfoldK, n + 1 - k0);
+        for (int e = threadIdx.x; e < nk * cols; e += blockDim.x) {
+            const int kl = e / cols, c = e - kl * cols;
+            const int k = k0 + kl;
+            const int p = (n - k) & 1, rr = (n - k) >> 1;
+            float x = 0.0f;
+            if (c < 2 * nf) x = blk[tab_off[2 * k + p] / th_pad * (2 * F) + (int64_t)rr * (2 * F) + 2 * f0 + c];
+            v[e] = x;
+        }
+        __syncthreads();
+        // per field: entries (k, part) for k in [k0, k0 + nk), then -k
+        for (int e = threadIdx.x; e < nf * nk * 4; e += blockDim.x) {
+            const int fl = e / (4 * nk), rem = e - fl * 4 * nk;
+            const int neg = rem >= 2 * nk;
+            const int r2 = neg ? rem - 2 * nk : rem;
+            const int kl = r2 >> 1, part = r2 & 1;
+            const int k = k0 + kl;
+            if (neg && k == 0) continue;
+            double x = (double)v[kl * cols + 2 * fl + part];
+            if (neg && (((k & 1) != 0) != (part == 1))) x = -x;
+            const int64_t idx = (int64_t)n * n + n + (neg ? -k : k);
+            coeffs[((int64_t)(f0 + fl) * nc + idx) * 2 + part] = x;
+        }
+        __syncthreads();
+    }
+}
+
+// Size (floats) of the contraction's block-ordered output: sum over the
+// (k, p) blocks of R_pad rows x 2F.
+int64_t s2_mfma_out_len(int N, int F) {
+    int64_t rows = 0;
+    for (int k = 0; k <= N; k++)
+        for (int p = 0; p < 2; p++) {
+            const int R = N >= k + p ? (N - k - p) / 2 + 1 : 0;
+            rows += (R + 15) & ~15;
+        }
+    return rows * 2 * F;
+}
+
+// Step 3 of the mixed path in three launches: the fold of the ring spectra G
+// (FP64) into X (FP32 blocks), the matrix-core contraction, whose
+// block-ordered output goes to G's memory (consumed by then; the work size
+// provides for both), and the unfold into the coefficients.
+static void mfma_dims(const Plan& P, int F, int& th, int& th_pad, int& C_pad) {
+    th = (P.dims[0] + 1) / 2;
+    th_pad = (th + 3) & ~3;
+    C_pad = ((2 * F + 15) / 16) * 16;
+}
+
+hamls_status launch_s2_fold(const Plan& P, int F, const double* G, int64_t glen, float* X, int64_t xcap,
+                            hipStream_t s) {
+    int th, th_pad, C_pad;
+    mfma_dims(P, F, th, th_pad, C_pad);
+    const int N = P.N;
     const int64_t xlen = (int64_t)(N + 1) * 2 * th_pad * C_pad;
-    if (xlen > xcap) {
-        set_error("fold buffer too small");
+    if (xlen > xcap || s2_mfma_out_len(N, F) > 2 * glen) {
+        set_error("fold or contraction buffer too small");
         return HAMLS_ERR_INVALID_ARG;
     }
-    {
-        dim3 grid((unsigned)th_pad, (unsigned)((N + 1 + kFoldK - 1) / kFoldK), (unsigned)((C_pad + kFoldC - 1) / kFoldC));
-        hipLaunchKernelGGL(k_s2_fold_x, grid, dim3(256), 0, s, G, nt, N, F, th, th_pad, C_pad, X);
-        HAMLS_HIP(hipGetLastError());
-    }
+    dim3 grid((unsigned)th_pad, (unsigned)((N + 1 + kFoldK - 1) / kFoldK), (unsigned)((C_pad + kFoldC - 1) / kFoldC));
+    hipLaunchKernelGGL(k_s2_fold_x, grid, dim3(256), 0, s, G, P.dims[0], N, F, th, th_pad, C_pad, X);
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+hamls_status launch_s2_legendre_mfma(const Plan& P, int F, const float* X, float* out, hipStream_t s) {
+    int th, th_pad, C_pad;
+    mfma_dims(P, F, th, th_pad, C_pad);
+    const int N = P.N;
     const LegItem* items = (const LegItem*)P.d_leg_items;
     if (C_pad <= 32) {
-        hipLaunchKernelGGL(k_s2_legendre_mfma<32>, dim3((unsigned)P.leg_items, 1), dim3(256), 0, s, P.d_ptab32,
-                           P.d_tab_off, items, X, N, F, th_pad, C_pad, coeffs);
+        hipLaunchKernelGGL(k_s2_legendre_mfma<32>, dim3((unsigned)P.leg_items, 1), dim3(64 * mfma_waves(32)), 0, s,
+                           P.d_ptab32, P.d_tab_off, items, X, N, F, th_pad, C_pad, out);
     } else if (C_pad <= 64) {
-        hipLaunchKernelGGL(k_s2_legendre_mfma<64>, dim3((unsigned)P.leg_items, 1), dim3(256), 0, s, P.d_ptab32,
-                           P.d_tab_off, items, X, N, F, th_pad, C_pad, coeffs);
+        hipLaunchKernelGGL(k_s2_legendre_mfma<64>, dim3((unsigned)P.leg_items, 1), dim3(64 * mfma_waves(64)), 0, s,
+                           P.d_ptab32, P.d_tab_off, items, X, N, F, th_pad, C_pad, out);
     } else {
         hipLaunchKernelGGL(k_s2_legendre_mfma<128>, dim3((unsigned)P.leg_items, (unsigned)((C_pad + 127) / 128)),
-                           dim3(256), 0, s, P.d_ptab32, P.d_tab_off, items, X, N, F, th_pad, C_pad, coeffs);
+                           dim3(64 * mfma_waves(128)), 0, s, P.d_ptab32, P.d_tab_off, items, X, N, F, th_pad, C_pad,
+                           out);
     }
+    HAMLS_HIP(hipGetLastError());
+    return HAMLS_OK;
+}
+
+hamls_status launch_s2_unfold(const Plan& P, int F, const float* out, double* coeffs, hipStream_t s) {
+    int th, th_pad, C_pad;
+    mfma_dims(P, F, th, th_pad, C_pad);
+    hipLaunchKernelGGL(k_s2_unfold, dim3((unsigned)(P.N + 1), (unsigned)((F + kUnfoldF - 1) / kUnfoldF)), dim3(256),
+                       0, s, out, P.d_tab_off, P.N, F, th_pad, coeffs);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

@@ -312,7 +312,7 @@ def hamls_diagnostics(plan: int):
 
 
 PHASES = {"binning": 0, "radius": 1, "assemble": 2, "solve": 3, "ring_dft": 4, "contract": 5, "gather": 6,
-          "gen_apply": 7, "resolve": 8}
+          "gen_apply": 7, "resolve": 8, "fold": 9}
 
 
 def hamls_timing_enable(plan: int, enable: bool = True):
