@@ -207,18 +207,17 @@ __device__ __forceinline__ int hist_select_bin(const int* hist, int above, int k
 }
 
 // n-th largest of buf[0..count) (LDS, n <= count), keys in [klo, khi]: rank
-// count in registers for up to 256 keys; beyond, a 256-bin histogram on
-// khi - key (bins monotone in the key) selects the bin holding the n-th key
-// and the rank count runs inside it (a quadratic rank count over all keys if
-// that bin holds more than bincap, i.e. heavy duplication).  hist: 256 ints,
-// binbuf: bincap <= 128 doubles, both LDS.  Called by a whole wave.
+// count in registers for up to 64 keys (one comparison per key pair); beyond,
+// a 256-bin histogram on khi - key (bins monotone in the key) selects the bin
+// holding the n-th key and the rank count runs inside it (a quadratic rank
+// count over all keys if that bin holds more than bincap, i.e. heavy
+// duplication).  The histogram costs a few instructions per key where the
+// rank count costs count / 64 per key.  hist: 256 ints, binbuf: bincap <= 128
+// doubles, both LDS.  Called by a whole wave.
 __device__ __forceinline__ double nth_largest(double* buf, int count, int knn, double klo, double khi,
                                               int* hist, double* binbuf, int bincap) {
     const int lane = threadIdx.x & 63;
     if (count <= 64) return nth_largest_regs<1>(buf, count, knn);
-    if (count <= 128) return nth_largest_regs<2>(buf, count, knn);
-    if (count <= 192) return nth_largest_regs<3>(buf, count, knn);
-    if (count <= 256) return nth_largest_regs<4>(buf, count, knn);
     const double scale = 256.0 / (khi - klo);
 #pragma unroll
     for (int q = 0; q < 4; q++) hist[4 * lane + q] = 0;
