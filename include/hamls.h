@@ -64,7 +64,10 @@ typedef enum { HAMLS_FP64 = 0, HAMLS_MIXED = 1 } hamls_precision;
 #define HAMLS_ST_UNDERDETERMINED 2u /* fewer than m nodes or singular local system: Shepard mean */
 #define HAMLS_ST_EMPTY 4u          /* no node inside the support: value NaN */
 #define HAMLS_ST_HEMISPHERE 8u     /* support radius clamped (S2: pi/2, SO3: pi) */
-#define HAMLS_ST_ILLCOND 16u       /* local system ill-conditioned (solved by the fallback path) */
+#define HAMLS_ST_ILLCOND 16u       /* solved in double-double precision: the FP64 local system was
+                                      ill-conditioned, or (one-field FP64 fits, adaptive radius on S2)
+                                      the search predicted it from the node's nearest neighbour lying
+                                      beyond 0.7 d_n */
 
 typedef struct hamls_params {
     int32_t struct_size;     /* = sizeof(hamls_params); set by hamls_params_init */

@@ -134,6 +134,9 @@ struct Plan {
     int32_t* d_nj = nullptr;        // MQ
     int32_t* d_mlist = nullptr;     // S2 adaptive radius: MQ x kListCap member records
     int32_t* d_mcnt = nullptr;      // MQ: member count, or -1 (the assembly scans)
+    uint8_t* d_route = nullptr;     // S2 adaptive radius: MQ, 1 where the search predicts an
+                                    // ill-conditioned local system (solved in double-double only)
+    bool route_valid = false;       // d_route holds the last search's predictions
     double* d_chi = nullptr;        // MQ
     double* d_tau = nullptr;        // MQ
     double* d_entries = nullptr;    // n_entries x MQ
@@ -235,6 +238,7 @@ struct SolveArgs {
     int32_t* rs_count;
     const int32_t* in_list;   // centres a list-mode kernel works on
     const int32_t* in_count;
+    const uint8_t* route;     // split solve: centres left to the re-solve (null: none)
 };
 
 
@@ -242,7 +246,8 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values);
 // one-field FP64 passes whose assembly hands its Gram matrices to a separate
 // solve kernel, and that kernel
 bool split_solve(const Plan& P, int F);
-hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s);
+hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                                bool route = false);
 
 // generating functions (Rem. 2.5): gamma by a unit-right-hand-side solve,
 // CSR row pointers from the neighbour counts, the values a*_i, and the sparse
@@ -269,8 +274,11 @@ hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double
 hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
 // queue_blocks: < 0 the plan's tuned launch form, 0 grid order, 1 cost-ordered
 // dispatch, > 1 the work queue with that many blocks (one FP64 field)
+// route: one field, a fit's pass: the centres the search predicts to be
+// ill-conditioned go to the re-solve list unassembled (a tuning or
+// generating-function pass assembles every centre)
 hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
-                                int queue_blocks = -1);
+                                int queue_blocks = -1, bool route = false);
 hamls_status launch_cost_order(const Plan& P, hipStream_t s);
 hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
                              int form = -1);

@@ -800,7 +800,8 @@ __global__ __launch_bounds__(64) void k_mls_solve(const double* __restrict__ gra
     __shared__ double gl[NG * E];
     const int g = threadIdx.x / GS, r = threadIdx.x % GS;
     const int64_t j = (int64_t)blockIdx.x * NG + g;
-    const bool live = j < A.MQ;
+    // centres the assembly left to the re-solve have no entries
+    const bool live = j < A.MQ && !(A.route && A.route[j]);
     for (int e = r; e < E; e += GS) gl[g * E + e] = live ? gram[j * E + e] : 0.0;
     __syncthreads();
     if (live) mls_solve_group<m, GS>(gl + g * E, A.nj[j], j, A);

@@ -38,6 +38,7 @@ struct S2Geom {
     const int32_t* cs;       // cell_start
     const int32_t* mlist;    // member lists of the radius search (kListCap per node) or null
     const int32_t* mcnt;     // their lengths, -1 where the assembly scans the cap
+    const uint8_t* route;    // one-field FP64 pass: nodes sent to the re-solve unassembled, or null
     int nb;
     double dtheta, idtheta;  // band height and its reciprocal
 };
@@ -595,6 +596,7 @@ S2Geom make_geom(const Plan& P) {
     g.cs = P.d_cell_start;
     g.mlist = P.d_mlist;
     g.mcnt = P.d_mcnt;
+    g.route = nullptr;
     g.nb = P.bins.nb;
     g.dtheta = P.bins.dtheta;
     g.idtheta = 1.0 / P.bins.dtheta;
@@ -604,6 +606,11 @@ S2Geom make_geom(const Plan& P) {
 // ---------------------------------------------------------------------------
 // support radius (eq. (5), (6), (12))
 // ---------------------------------------------------------------------------
+
+// Nearest-node distance, relative to d_n, beyond which the search predicts an
+// ill-conditioned local system (C3: every centre the FP64 solve flags, and
+// 17 700 of the 438 000 others, lie beyond 0.7 d_n).
+constexpr double kRouteRatio = 0.7;
 
 // The search keeps its wave-uniform state in scalar registers (uni_d): 128
 // VGPRs, four waves per SIMD, with 20 spilled bytes per lane (167 VGPRs and
@@ -622,7 +629,8 @@ template <bool AUX>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
                                                  double delta0, double c_fixed, double* thr,
                                                  double* delta, uint8_t* rstatus, int32_t* mlist,
-                                                 int32_t* mcnt, const int32_t* __restrict__ order) {
+                                                 int32_t* mcnt, const int32_t* __restrict__ order,
+                                                 uint8_t* route) {
     constexpr int U = 4;
     constexpr int kBinCap = 128;
     __shared__ __align__(16) double buf[kCandCap];
@@ -732,6 +740,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         bool done = false, hemi = false;
         int lcount = -1;  // kept keys of the final scan when it kept them all
         double lcr = 2.0;
+        double kmx = -2.0;  // largest key seen: the nearest node lies in every scanned cover that holds n
         int* hist = (int*)binbuf;  // 256 ints
         for (int it = 0; it < 40 && !done; it++) {
             // cap radius for the cover: an upper bound on arccos(cr) from
@@ -763,6 +772,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         int i = idx[u];
                         d[u] = s2_dot(ld_rec(g.X, i), ld_rec(Xy, i), ld_rec(Xz, i), q0, q1, q2);
                     }
+                    kmx = fmax(kmx, d[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++) {
@@ -892,6 +902,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
             if (lane == 0) mcnt[j] = nm;
         }
+        // Where even the nearest node lies beyond kRouteRatio d_n, the members
+        // form a thin shell about the node (inside a hole of the node set) and
+        // the local system is ill-conditioned: the one-field FP64 pass then
+        // leaves the node to the double-double re-solve without assembling it
+        // in FP64 first (a routing decision only: either path solves any node)
+        if (route) {
+            const double kmax = wave_max(kmx);
+            bool rt = false;
+            if (!hemi) {
+                const double d0 = acos(fmin(1.0, fmax(-1.0, kmax)));
+                const double dn = acos(fmin(1.0, fmax(-1.0, tn)));
+                rt = d0 > kRouteRatio * dn;
+            }
+            if (lane == 0) route[j] = rt ? 1 : 0;
+        }
     }
     if (lane == 0) {
         thr[j] = c;
@@ -971,7 +996,7 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
         const int na = P.prm.smooth_aux;
         hipLaunchKernelGGL(k_s2_radius<true>, dim3((unsigned)na), dim3(64), 0, s, ga, P.M, knn, P.prm.knn_eps, 0.0,
                            2.0, P.d_aux_thr, P.d_aux_delta, P.d_aux_rst, (int32_t*)nullptr, (int32_t*)nullptr,
-                           (const int32_t*)nullptr);
+                           (const int32_t*)nullptr, (uint8_t*)nullptr);
         const double rs = 3.0 * sqrt(4.0 * kPi / na);
         hipLaunchKernelGGL(k_s2_smooth_radius, dim3((unsigned)P.MQ), dim3(64), 0, s, P.d_grid, P.MQ, P.d_aux,
                            P.d_aux_delta, na, P.prm.knn_eps, rs, cos(rs), P.prm.wendland, P.d_thr, P.d_delta,
@@ -980,7 +1005,8 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
         return HAMLS_OK;
     }
     hipLaunchKernelGGL(k_s2_radius<false>, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
-                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt, order);
+                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt, order,
+                       knn > 0 ? P.d_route : (uint8_t*)nullptr);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -988,6 +1014,26 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // assembly of the local problems (eq. (14)), one wave per grid node
 // ---------------------------------------------------------------------------
+
+// One-field FP64 passes: a centre the search predicts to be ill-conditioned
+// is not assembled (k_route_list hands it to the re-solve list, the split
+// solve skips it, the double-double pass counts its members).  A plain early
+// exit: appending to the list here raised the assembly's register use.
+__device__ __forceinline__ bool routed(const S2Geom& g, int j) { return g.route && g.route[j]; }
+
+// The routed centres onto the re-solve list (one atomic per wave).
+__global__ __launch_bounds__(256) void k_route_list(const uint8_t* __restrict__ route, int64_t MQ,
+                                                   int32_t* __restrict__ list, int32_t* __restrict__ count) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool r = j < MQ && route[j];
+    const uint64_t mk = __ballot(r);
+    if (mk == 0) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == __ffsll((unsigned long long)mk) - 1) base = atomicAdd(count, __popcll(mk));
+    base = __shfl(base, __ffsll((unsigned long long)mk) - 1, 64);
+    if (r) list[base + rank_below(mk)] = (int32_t)j;
+}
 
 // Entries per grid node: G_ab = sum_i w_i g_a g_b for a <= b (row-major upper
 // triangle, G_00 = sum w), then h_af = sum_i w_i g_a y_if.  Candidates are
@@ -1169,7 +1215,10 @@ __device__ __forceinline__ void s2_node(int j, double* rows, int* sh, const S2Ge
                 entries_out[EG + m * FM + e] = v.lo;
             }
         }
-        if (lane == 0) entries_out[2 * (EG + m * FM)] = (double)count;
+        if (lane == 0) {
+            entries_out[2 * (EG + m * FM)] = (double)count;
+            nj[j] = count;
+        }
         return;
     }
     if (DD) {
@@ -1265,8 +1314,9 @@ __global__ __launch_bounds__(64) void k_s2_assemble(S2Geom g, const double* __re
             __syncthreads();
         }
     } else {
-        s2_node<K, FM, DD, SPLIT>(xcd_block(blockIdx.x, gridDim.x), rows, sh, g, vals, F, wendland, thr, delta, A, nj,
-                                  entries_out);
+        const int j = xcd_block(blockIdx.x, gridDim.x);
+        if (SPLIT && FM == 1 && !DD && routed(g, j)) return;
+        s2_node<K, FM, DD, SPLIT>(j, rows, sh, g, vals, F, wendland, thr, delta, A, nj, entries_out);
     }
 }
 
@@ -1357,8 +1407,9 @@ __global__ __launch_bounds__(64) void k_s2_assemble_queue(S2Geom g, const double
         const int64_t k = next;
         __syncthreads();
         if (k >= share) break;
-        s2_node<K, 1, false, true>(order[8 * k + x], rows, sh, g, vals, 1, wendland, thr, delta, A, nj,
-                                   entries_out);
+        const int j = order[8 * k + x];
+        if (!routed(g, j))
+            s2_node<K, 1, false, true>(j, rows, sh, g, vals, 1, wendland, thr, delta, A, nj, entries_out);
         __syncthreads();
     }
 }
@@ -1377,8 +1428,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     constexpr int m = (K + 1) * (K + 2) / 2;
     __shared__ __align__(16) double rows[64 * (m + 2)];
     __shared__ int sh[kScanLds];
-    s2_node<K, 1, false, true>(order[xcd_block(blockIdx.x, gridDim.x)], rows, sh, g, vals, 1, wendland, thr, delta, A,
-                               nj, entries_out);
+    const int j = order[xcd_block(blockIdx.x, gridDim.x)];
+    if (routed(g, j)) return;
+    s2_node<K, 1, false, true>(j, rows, sh, g, vals, 1, wendland, thr, delta, A, nj, entries_out);
 }
 
 // Grid nodes ordered by decreasing cost: buckets of floor(log2(n_j + 1))
@@ -1592,9 +1644,15 @@ hamls_status launch_s2_mixed(const Plan& P, int F, int f0, double* grid_values, 
 }
 
 hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
-                                int queue_blocks) {
+                                int queue_blocks, bool route) {
     S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    if (route && F == 1 && P.route_valid) {
+        g.route = P.d_route;
+        hipLaunchKernelGGL(k_route_list, dim3((unsigned)((P.MQ + 255) / 256)), dim3(256), 0, s, P.d_route, P.MQ,
+                           P.d_rs_list, P.d_rs_count);
+        HAMLS_HIP(hipGetLastError());
+    }
     dim3 grid((unsigned)P.MQ), block(64);
     int wl = P.prm.wendland;
     if (queue_blocks < 0) queue_blocks = P.asm_queue_blocks;
@@ -1653,9 +1711,11 @@ bool split_solve(const Plan& P, int F) {
     return P.dom == HAMLS_S2 || P.m + 1 <= 16;
 }
 
-hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s) {
+hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_values, hipStream_t s,
+                                bool route) {
     if (!split_solve(P, F)) return HAMLS_OK;
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
+    if (route && F == 1 && P.route_valid) A.route = P.d_route;
     const dim3 grid((unsigned)((P.MQ + 3) / 4)), block(64);
     const double* G = P.d_entries;
     switch (P.m) {
@@ -1705,6 +1765,7 @@ SolveArgs make_solve_args(const Plan& P, int F, int f0, double* grid_values) {
     A.rs_count = P.d_rs_count;
     A.in_list = P.d_rs_list;
     A.in_count = P.d_rs_count;
+    A.route = nullptr;
     return A;
 }
 

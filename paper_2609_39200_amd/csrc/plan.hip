@@ -301,6 +301,9 @@ static hamls_status bind_nodes(Plan& P, const double* nodes, int64_t M, const do
     }
     PhaseTimer pt(P, HAMLS_PHASE_RADIUS, s);
     HAMLS_TRY(s2 ? launch_s2_radius(P, s) : launch_grid_radius(P, s));
+    // the plain adaptive search of S2 predicts the ill-conditioned centres
+    // (degree 0 has no re-solve: nothing to route to)
+    P.route_valid = s2 && P.d_route && P.prm.knn_count > 0 && P.prm.smooth_aux == 0 && P.m > 1;
     return HAMLS_OK;
 }
 
@@ -327,6 +330,7 @@ static hamls_status alloc_common(Plan& P, int dimx) {
         // member lists handed from the adaptive-radius search to the assembly
         HAMLS_TRY(dalloc(P, &P.d_mlist, (size_t)kListCap * P.MQ));
         HAMLS_TRY(dalloc(P, &P.d_mcnt, P.MQ));
+        if (P.dom == HAMLS_S2) HAMLS_TRY(dalloc(P, &P.d_route, P.MQ));
     }
     HAMLS_TRY(dalloc(P, &P.d_chi, P.MQ));
     HAMLS_TRY(dalloc(P, &P.d_tau, P.MQ));
@@ -654,6 +658,7 @@ hamls_status plan_footprint(const hamls_params* p, int64_t M, int64_t mcap, int3
     if (p->knn_count > 0) {
         add((int64_t)kListCap * MQ, 4);
         add(MQ, 4);
+        if (s2) add(MQ, 1);  // route flags
     }
     add(MQ, 8);
     add(MQ, 8);
@@ -924,12 +929,12 @@ hamls_status hamls_mls_to_grid(hamls_plan_t plan, const double* values, int32_t 
                 HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_mixed(*P, Fc, f0, grid_values, s)
                                              : launch_grid_mixed(*P, Fc, f0, grid_values, s));
             else
-                HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_assemble(*P, Fc, f0, grid_values, s)
+                HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_assemble(*P, Fc, f0, grid_values, s, -1, true)
                                              : launch_grid_mls(*P, Fc, f0, grid_values, s));
         }
         {
             PhaseTimer pt(*P, HAMLS_PHASE_SOLVE, s);
-            HAMLS_TRY(launch_split_solve(*P, Fc, f0, grid_values, s));
+            HAMLS_TRY(launch_split_solve(*P, Fc, f0, grid_values, s, true));
         }
         PhaseTimer pt(*P, HAMLS_PHASE_RESOLVE, s);
         HAMLS_TRY(P->dom == HAMLS_S2 ? launch_s2_resolve(*P, Fc, f0, grid_values, s)
