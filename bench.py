@@ -218,6 +218,9 @@ def main():
     tune = {"form": q, "grid_order_ms": t[0], "cost_order_dispatch_ms": t[1]}
     if domain == "s2" and args.precision == "fp64":
         tune["queue_ms"] = {"8/CU": t[2], "12/CU": t[3]}
+    if domain == "s2":
+        en, rt = H.hamls_plan_routing(plan)
+        tune["routing"] = {"enabled": en, "step2_ms_without": rt[0], "step2_ms_with": rt[1]}
 
     def step():
         H.hamls_plan_rebind(plan, nodes, stream=stream)

@@ -214,6 +214,23 @@ hamls_status hamls_plan_destroy(hamls_plan_t plan);
  * FP32 Gram pass pays only where it saves memory traffic.)  Both choices are
  * within the mixed bar of the FP64 path. */
 hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blocks, float* times_ms);
+/* Routing of predicted ill-conditioned centres (S2, adaptive radius of eq.
+ * (12), one-field FP64 step 2, degree >= 1).  The support-radius search flags
+ * a centre whose nearest node lies beyond 0.7 d_n: its members form a thin
+ * shell (a hole of the node set), the setting in which the FP64 solve hands
+ * the centre to the double-double re-solve.  With routing on, a fit's
+ * one-field FP64 pass sends the flagged centres to the re-solve without
+ * assembling them in FP64 first; the values stay within the FP64 bar either
+ * way (only the precision in which a centre is solved changes, and such
+ * centres carry HAMLS_ST_ILLCOND).  It pays where most flagged centres need
+ * the re-solve anyway.  Off for a new plan; hamls_plan_tune times step 2
+ * without and with it on the bound nodes and keeps the faster.
+ *  set       -1 query, 0 off, 1 on
+ *  enabled   out (may be NULL): the state after the call
+ *  times_ms  out (may be NULL), 2 floats: the tuner's step-2 times without
+ *            and with routing, -1 where it did not time them
+ * INVALID_ARG for a null plan or set outside {-1, 0, 1}. */
+hamls_status hamls_plan_routing(hamls_plan_t plan, int32_t set, int32_t* enabled, float* times_ms);
 /* Sets the launch form directly: 0 = grid order, 1 = cost-ordered dispatch,
  * >= 8 = the work queue with that many blocks (the order computed from the
  * bound nodes as in hamls_plan_tune).  INVALID_ARG for 2..7 (the queue needs a

@@ -137,6 +137,8 @@ struct Plan {
     uint8_t* d_route = nullptr;     // S2 adaptive radius: MQ, 1 where the search predicts an
                                     // ill-conditioned local system (solved in double-double only)
     bool route_valid = false;       // d_route holds the last search's predictions
+    bool route_enabled = false;     // fits route (hamls_plan_tune or hamls_plan_routing)
+    float route_ms[2] = {-1.0f, -1.0f};  // tuner's step-2 times without / with routing
     double* d_chi = nullptr;        // MQ
     double* d_tau = nullptr;        // MQ
     double* d_entries = nullptr;    // n_entries x MQ

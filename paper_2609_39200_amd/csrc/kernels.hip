@@ -709,7 +709,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 if (kh == R) {
                     const double rtop = ladder_radius(base, fac, R - 1);
                     if (rtop >= 0.5 * kPi) break;
+                    // the next ladder in steps of 1.25 (spanning 4.8x): a pass
+                    // costs the bands of its largest cap, and steps of 1.6
+                    // would reach pi/2 (every band) from about 0.13 rad on
                     base = rtop * fac;
+                    fac = fmin(fac, 1.25);
                     continue;
                 }
                 const double rh = ladder_radius(base, fac, kh);
@@ -1647,7 +1651,7 @@ hamls_status launch_s2_assemble(const Plan& P, int F, int f0, double* grid_value
                                 int queue_blocks, bool route) {
     S2Geom g = make_geom(P);
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    if (route && F == 1 && P.route_valid) {
+    if (route && F == 1 && P.route_valid && P.route_enabled) {
         g.route = P.d_route;
         hipLaunchKernelGGL(k_route_list, dim3((unsigned)((P.MQ + 255) / 256)), dim3(256), 0, s, P.d_route, P.MQ,
                            P.d_rs_list, P.d_rs_count);
@@ -1715,7 +1719,7 @@ hamls_status launch_split_solve(const Plan& P, int F, int f0, double* grid_value
                                 bool route) {
     if (!split_solve(P, F)) return HAMLS_OK;
     SolveArgs A = make_solve_args(P, F, f0, grid_values);
-    if (route && F == 1 && P.route_valid) A.route = P.d_route;
+    if (route && F == 1 && P.route_valid && P.route_enabled) A.route = P.d_route;
     const dim3 grid((unsigned)((P.MQ + 3) / 4)), block(64);
     const double* G = P.d_entries;
     switch (P.m) {

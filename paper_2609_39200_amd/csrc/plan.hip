@@ -1022,6 +1022,71 @@ hamls_status hamls_plan_cost_order(hamls_plan_t plan, int32_t* order) {
     return HAMLS_OK;
 }
 
+// Routing of the centres the search predicts to be ill-conditioned (S2,
+// adaptive radius, one FP64 field): step 2 of one field -- assembly in the
+// plan's form, split solve, re-solve -- timed without and with it (best of
+// three), the faster kept.  Whether it pays depends on how many predicted
+// centres really need the re-solve (on the large S2 configuration nearly
+// all; where holes are sparsely rimmed, few).
+static hamls_status tune_routing(Plan* P, hipStream_t s) {
+    P->route_ms[0] = P->route_ms[1] = -1.0f;
+    if (!P->route_valid || !(P->prm.precision == HAMLS_FP64 || P->mixed_fp64_step2)) {
+        P->route_enabled = false;
+        return HAMLS_OK;
+    }
+    double* out = nullptr;
+    HAMLS_TRY(tune_out(P, &out));
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    hamls_status st = HAMLS_OK;
+    float t[2] = {1e30f, 1e30f};
+    for (int v = 0; v < 2 && e == hipSuccess && st == HAMLS_OK; v++) {
+        P->route_enabled = v == 1;
+        for (int rep = 0; rep < 3 && e == hipSuccess && st == HAMLS_OK; rep++) {
+            e = hipMemsetAsync(P->d_rs_count, 0, sizeof(int32_t) * 10, s);
+            if (e == hipSuccess) e = hipEventRecord(a, s);
+            if (e != hipSuccess) break;
+            st = launch_s2_assemble(*P, 1, 0, out, s, P->asm_queue_blocks, true);
+            if (st == HAMLS_OK) st = launch_split_solve(*P, 1, 0, out, s, true);
+            if (st == HAMLS_OK) st = launch_s2_resolve(*P, 1, 0, out, s);
+            float ms = 0.0f;
+            if (st == HAMLS_OK) {
+                e = hipEventRecord(b, s);
+                if (e == hipSuccess) e = hipEventSynchronize(b);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            }
+            if (e == hipSuccess && st == HAMLS_OK && ms < t[v]) t[v] = ms;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipFree(out);
+    P->route_enabled = false;
+    if (st != HAMLS_OK) return st;
+    if (e != hipSuccess) return hip_status(e, "tune");
+    P->route_enabled = t[1] < t[0];
+    P->route_ms[0] = t[0];
+    P->route_ms[1] = t[1];
+    return HAMLS_OK;
+}
+
+hamls_status hamls_plan_routing(hamls_plan_t plan, int32_t set, int32_t* enabled, float* times_ms) {
+    Plan* P = (Plan*)plan;
+    if (!P || set < -1 || set > 1) {
+        set_error("null plan or set outside {-1, 0, 1}");
+        return HAMLS_ERR_INVALID_ARG;
+    }
+    if (set >= 0) P->route_enabled = set == 1;
+    if (enabled) *enabled = P->route_enabled ? 1 : 0;
+    if (times_ms) {
+        times_ms[0] = P->route_ms[0];
+        times_ms[1] = P->route_ms[1];
+    }
+    return HAMLS_OK;
+}
+
 hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blocks, float* times_ms) {
     Plan* P = (Plan*)plan;
     if (!P) {
@@ -1127,7 +1192,7 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
     }
     if (times_ms)
         for (int c = 0; c < ncand; c++) times_ms[c] = best[c];
-    return HAMLS_OK;
+    return tune_routing(P, s);
 }
 
 hamls_status hamls_gen_build(hamls_plan_t plan, void* stream) {

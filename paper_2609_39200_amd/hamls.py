@@ -121,6 +121,7 @@ _SIGS = {
     "hamls_timing_read": [_vp, _i32, _vp, _vp],
     "hamls_plan_footprint": [_P(hamls_params), _i64, _i32, _P(_i64)],
     "hamls_plan_tune": [_vp, _vp, _P(_i32), _vp],
+    "hamls_plan_routing": [_vp, _i32, _P(_i32), _vp],
     "hamls_plan_assembly_form": [_vp, _vp, _i32],
     "hamls_plan_cost_order": [_vp, _vp],
     "hamls_fit_capture": [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _P(_vp)],
@@ -457,6 +458,15 @@ def hamls_plan_tune(plan: int, stream=None) -> tuple:
     t = (C.c_float * 4)()
     _check(_lib.hamls_plan_tune(C.c_void_p(plan), _stream(stream), C.byref(q), t), "hamls_plan_tune")
     return int(q.value), [float(v) for v in t]
+
+
+def hamls_plan_routing(plan: int, set: int = -1) -> tuple:
+    """(enabled, [step-2 ms without, with routing] from the tuner or -1);
+    set: -1 query, 0 off, 1 on."""
+    en = C.c_int32(0)
+    t = (C.c_float * 2)()
+    _check(_lib.hamls_plan_routing(C.c_void_p(plan), int(set), C.byref(en), t), "hamls_plan_routing")
+    return bool(en.value), [float(v) for v in t]
 
 
 def hamls_plan_assembly_form(plan: int, queue_blocks: int, stream=None):

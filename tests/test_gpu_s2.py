@@ -379,3 +379,54 @@ def test_c3_full_size_sampled_rows(H):
         return np.union1d(np.arange(0, 513 * 1026, 211), heavy)
 
     _check_against_oracle(H, wl, rows=rows, check_lists=True, label="C3")
+
+
+def test_routing_of_predicted_illcond_centres(H):
+    # C2 nodes (holes of 20 degrees): with routing on, the centres whose
+    # nearest node lies beyond 0.7 d_n skip the FP64 assembly and are solved
+    # in double-double directly.  Same member counts and status bits (but
+    # ILLCOND) as the FP64 route, values within the FP64 bar of it, and the
+    # routed centres against the oracle
+    import torch
+
+    wl = W.s2_clusters()
+    _say(f"[gpu] routing of predicted ill-conditioned centres, {wl.name}")
+    p = H.params_from_workload(wl.params)
+    plan = H.hamls_plan(p, _dev(wl.nodes))
+    try:
+        info = H.hamls_plan_info_get(plan)
+        vals = _dev(wl.values)
+        out = {}
+        for route in (0, 1):
+            en, _ = H.hamls_plan_routing(plan, route)
+            assert en == bool(route)
+            gv = torch.empty((1, info.num_grid), dtype=torch.float64, device="cuda")
+            H.hamls_mls_to_grid(plan, vals, gv)
+            torch.cuda.synchronize()
+            out[route] = (gv.cpu().numpy()[0], H.hamls_diagnostics(plan))
+        a, da = out[0]
+        b, db = out[1]
+        ill_off = (da["status"] & H.ST_ILLCOND) != 0
+        ill_on = (db["status"] & H.ST_ILLCOND) != 0
+        routed = ill_on & ~ill_off
+        _say(f"  ill-conditioned: {int(ill_off.sum())} (FP64 route), {int(ill_on.sum())} with routing")
+        assert routed.sum() > 100 and not (ill_off & ~ill_on).any()
+        np.testing.assert_array_equal(da["n"], db["n"])
+        common = H.ST_REGULARIZED | H.ST_UNDERDETERMINED | H.ST_EMPTY | H.ST_HEMISPHERE
+        np.testing.assert_array_equal(da["status"] & common, db["status"] & common)
+        ok = ~np.isnan(a)
+        assert np.array_equal(ok, ~np.isnan(b))
+        e, emax = _rell2(b[ok], a[ok]), PAR.maxrel(b[ok], a[ok])
+        _say(f"  routing on vs off: rel L2 {e:.3e}, max {emax:.3e}")
+        assert e < TOL and emax < TOL
+        gpts, _ = H.hamls_plan_grid(plan)
+        sel = np.nonzero(routed)[0][::max(1, int(routed.sum()) // 64)][:64]
+        po = _oracle_params(wl)
+        om = oracle.mls(po, gpts, wl.nodes, wl.values, rows=sel)
+        e2 = _rell2(b[sel], om["values"][0])
+        emax2 = PAR.maxrel(b[sel], om["values"][0])
+        _say(f"  {sel.size} routed centres vs oracle: rel L2 {e2:.3e}, max {emax2:.3e}")
+        assert e2 < TOL and emax2 < TOL
+        np.testing.assert_array_equal(db["n"][sel], om["n"])
+    finally:
+        H.hamls_plan_destroy(plan)
