@@ -46,13 +46,13 @@ def pct(a, q):
 # kernel (name prefix) of each phase's main launch, for the counter summary
 PHASE_KERNEL = {
     "s2": {"binning": None, "radius": "k_s2_radius", "assemble": "k_s2_assemble",
-           "solve": "k_mls_solve<", "resolve": "k_s2_assemble", "ring_dft": "k_s2_ring_dft",
+           "solve": "k_mls_solve<", "resolve": "k_s2_dd_gram", "ring_dft": "k_s2_ring_fft",
            "contract": "k_s2_legendre", "gather": "k_gather_values"},
     "so3": {"binning": None, "radius": "k_grid_radius<4", "assemble": "k_grid_mls<4",
-            "solve": "k_mls_solve<", "resolve": "k_grid_mls<4", "ring_dft": "k_dft_axis",
+            "solve": "k_mls_solve<", "resolve": "k_grid_mls<4", "ring_dft": "k_fft_axis",
             "contract": "k_so3_contract", "gather": "k_gather_values"},
     "t3": {"binning": None, "radius": "k_grid_radius<3", "assemble": "k_grid_mls<3",
-           "solve": "k_mls_solve<", "resolve": "k_grid_mls<3", "ring_dft": "k_t3",
+           "solve": "k_mls_solve<", "resolve": "k_grid_mls<3", "ring_dft": "k_fft_axis",
            "contract": None, "gather": "k_gather_values"},
 }
 
@@ -124,9 +124,14 @@ def measured_traffic(workload, kernel):
     if info.get("source_sha256") != source_sha256():
         return None
     for name, k in kern.items():
-        # the double-double re-solve instantiations carry "true" as their
-        # third template argument
         targs = name[name.index("<") + 1:].rstrip(">").split(", ") if "<" in name else []
+        if kernel.startswith("k_s2_dd_gram"):
+            # the S2 double-double Gram pass of one field: <K, 1>
+            if name.startswith(kernel) and len(targs) == 2 and targs[1] == "1":
+                return float(k["bytes"])
+            continue
+        # the grid domains' double-double re-solve instantiations carry
+        # "true" as their third template argument
         dd = len(targs) > 2 and targs[2] == "true"
         if name.startswith(kernel) and dd == resolve:
             return float(k["bytes"])
