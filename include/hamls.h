@@ -224,7 +224,10 @@ hamls_status hamls_plan_tune(hamls_plan_t plan, void* stream, int32_t* queue_blo
  * way (only the precision in which a centre is solved changes, and such
  * centres carry HAMLS_ST_ILLCOND).  It pays where most flagged centres need
  * the re-solve anyway.  Off for a new plan; hamls_plan_tune times step 2
- * without and with it on the bound nodes and keeps the faster.
+ * without and with it on the bound nodes and keeps the faster.  The flags
+ * come from the search, which computes them only on plans that route (it
+ * costs the search a few percent): switching routing on here takes effect
+ * from the next bind (hamls_plan_rebind), switching it off at once.
  *  set       -1 query, 0 off, 1 on
  *  enabled   out (may be NULL): the state after the call
  *  times_ms  out (may be NULL), 2 floats: the tuner's step-2 times without

@@ -273,7 +273,8 @@ hamls_status radix_sort(Plan& P, int64_t n, hipStream_t s, int* final_buf);
 hamls_status launch_cell_start(const Plan& P, const uint32_t* keys, int64_t n, hipStream_t s);
 hamls_status launch_gather_nodes(const Plan& P, const int32_t* idx, const double* nodes,
                                  const double* nu, int64_t M, hipStream_t s);
-hamls_status launch_s2_radius(const Plan& P, hipStream_t s);
+// route: also flag the centres whose nearest node lies beyond 0.7 d_n (d_route)
+hamls_status launch_s2_radius(const Plan& P, hipStream_t s, bool route = false);
 // queue_blocks: < 0 the plan's tuned launch form, 0 grid order, 1 cost-ordered
 // dispatch, > 1 the work queue with that many blocks (one FP64 field)
 // route: one field, a fit's pass: the centres the search predicts to be

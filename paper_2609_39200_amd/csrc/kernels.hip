@@ -625,7 +625,7 @@ constexpr double kRouteRatio = 0.7;
 //     narrowed (duplicates), a bitwise binary search over the key instead.
 // delta = (1+eps) arccos(t_n), merged with a fixed delta_0 if both are set,
 // clamped to pi/2 (the tangent projection needs delta < pi/2).
-template <bool AUX>
+template <bool AUX, bool ROUTE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_s2_radius(S2Geom g, int64_t M, int knn, double eps,
                                                  double delta0, double c_fixed, double* thr,
                                                  double* delta, uint8_t* rstatus, int32_t* mlist,
@@ -776,7 +776,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                         int i = idx[u];
                         d[u] = s2_dot(ld_rec(g.X, i), ld_rec(Xy, i), ld_rec(Xz, i), q0, q1, q2);
                     }
-                    kmx = fmax(kmx, d[u]);
+                    if (ROUTE) kmx = fmax(kmx, d[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < U; u++) {
@@ -911,7 +911,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         // the local system is ill-conditioned: the one-field FP64 pass then
         // leaves the node to the double-double re-solve without assembling it
         // in FP64 first (a routing decision only: either path solves any node)
-        if (route) {
+        if (ROUTE) {
             const double kmax = wave_max(kmx);
             bool rt = false;
             if (!hemi) {
@@ -978,7 +978,7 @@ __global__ __launch_bounds__(64) void k_s2_smooth_radius(const double* __restric
     }
 }
 
-hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
+hamls_status launch_s2_radius(const Plan& P, hipStream_t s, bool route) {
     S2Geom g = make_geom(P);
     double d0 = P.prm.support_radius > 0.0 ? P.prm.support_radius : 0.0;
     double cf = d0 > 0.0 ? cos(d0) : 2.0;
@@ -998,7 +998,7 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
         ga.mlist = nullptr;
         ga.mcnt = nullptr;
         const int na = P.prm.smooth_aux;
-        hipLaunchKernelGGL(k_s2_radius<true>, dim3((unsigned)na), dim3(64), 0, s, ga, P.M, knn, P.prm.knn_eps, 0.0,
+        hipLaunchKernelGGL((k_s2_radius<true, false>), dim3((unsigned)na), dim3(64), 0, s, ga, P.M, knn, P.prm.knn_eps, 0.0,
                            2.0, P.d_aux_thr, P.d_aux_delta, P.d_aux_rst, (int32_t*)nullptr, (int32_t*)nullptr,
                            (const int32_t*)nullptr, (uint8_t*)nullptr);
         const double rs = 3.0 * sqrt(4.0 * kPi / na);
@@ -1008,9 +1008,17 @@ hamls_status launch_s2_radius(const Plan& P, hipStream_t s) {
         HAMLS_HIP(hipGetLastError());
         return HAMLS_OK;
     }
-    hipLaunchKernelGGL(k_s2_radius<false>, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
-                       P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt, order,
-                       knn > 0 ? P.d_route : (uint8_t*)nullptr);
+    // the route flags (nearest-node distance against d_n) only when a fit
+    // will route or the tuner times routing: tracking the nearest key costs
+    // the search a few percent
+    if (route && knn > 0 && P.d_route)
+        hipLaunchKernelGGL((k_s2_radius<false, true>), dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
+                           P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt, order,
+                           P.d_route);
+    else
+        hipLaunchKernelGGL((k_s2_radius<false, false>), dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn,
+                           P.prm.knn_eps, d0, cf, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist, P.d_mcnt, order,
+                           (uint8_t*)nullptr);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }

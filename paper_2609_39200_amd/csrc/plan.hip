@@ -283,6 +283,12 @@ static void grid_bins(Plan& P, int64_t M) {
     P.key_bits = bits;
 }
 
+// Routing of predicted ill-conditioned centres applies to S2 plans with the
+// plain adaptive radius and degree >= 1 (the re-solve needs m > 1).
+static bool route_possible(const Plan& P) {
+    return P.dom == HAMLS_S2 && P.d_route && P.prm.knn_count > 0 && P.prm.smooth_aux == 0 && P.m > 1;
+}
+
 static hamls_status bind_nodes(Plan& P, const double* nodes, int64_t M, const double* nu,
                                hipStream_t s) {
     P.gen_ready = false;  // generating functions belong to the previous node set
@@ -300,10 +306,11 @@ static hamls_status bind_nodes(Plan& P, const double* nodes, int64_t M, const do
                      : launch_grid_gather(P, P.d_idx[fin], nodes, nu, M, s));
     }
     PhaseTimer pt(P, HAMLS_PHASE_RADIUS, s);
-    HAMLS_TRY(s2 ? launch_s2_radius(P, s) : launch_grid_radius(P, s));
     // the plain adaptive search of S2 predicts the ill-conditioned centres
-    // (degree 0 has no re-solve: nothing to route to)
-    P.route_valid = s2 && P.d_route && P.prm.knn_count > 0 && P.prm.smooth_aux == 0 && P.m > 1;
+    // when the plan routes them (degree 0 has no re-solve: nothing to route to)
+    const bool flags = s2 && P.route_enabled && route_possible(P);
+    HAMLS_TRY(s2 ? launch_s2_radius(P, s, flags) : launch_grid_radius(P, s));
+    P.route_valid = flags;
     return HAMLS_OK;
 }
 
@@ -1030,10 +1037,13 @@ hamls_status hamls_plan_cost_order(hamls_plan_t plan, int32_t* order) {
 // all; where holes are sparsely rimmed, few).
 static hamls_status tune_routing(Plan* P, hipStream_t s) {
     P->route_ms[0] = P->route_ms[1] = -1.0f;
-    if (!P->route_valid || !(P->prm.precision == HAMLS_FP64 || P->mixed_fp64_step2)) {
+    if (!route_possible(*P) || !(P->prm.precision == HAMLS_FP64 || P->mixed_fp64_step2)) {
         P->route_enabled = false;
         return HAMLS_OK;
     }
+    // the flags of the bound nodes (the search again; the radii are the same)
+    HAMLS_TRY(launch_s2_radius(*P, s, true));
+    P->route_valid = true;
     double* out = nullptr;
     HAMLS_TRY(tune_out(P, &out));
     hipEvent_t a = nullptr, b = nullptr;

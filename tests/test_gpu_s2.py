@@ -397,9 +397,12 @@ def test_routing_of_predicted_illcond_centres(H):
         info = H.hamls_plan_info_get(plan)
         vals = _dev(wl.values)
         out = {}
+        nodes = _dev(wl.nodes)
         for route in (0, 1):
             en, _ = H.hamls_plan_routing(plan, route)
             assert en == bool(route)
+            # the search computes the flags at the next bind
+            H.hamls_plan_rebind(plan, nodes)
             gv = torch.empty((1, info.num_grid), dtype=torch.float64, device="cuda")
             H.hamls_mls_to_grid(plan, vals, gv)
             torch.cuda.synchronize()
