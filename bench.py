@@ -56,6 +56,14 @@ PHASE_KERNEL = {
            "contract": None, "gather": "k_gather_values"},
 }
 
+# the kernels behind each timed phase (the phase's duration is theirs together)
+PHASE_LAUNCHES = {
+    "s2": {"radius": "k_s2_radius (one launch)",
+           "resolve": "cost sort of the list (3 short launches) + k_s2_dd_gram<K, 1> + k_dd_solve<m, 1, false>",
+           "assemble": "k_route_list (when routing) + k_s2_assemble_ordered<K> (or the tuned form)",
+           "solve": "k_mls_solve<m, 16>"},
+}
+
 # file-name stem of a workload's committed rocprofv3 summaries
 PROFILE_NAME = {"c3": "s2_c3", "c2": "s2_c2", "c2fixed": "s2_c2_fixed_radius", "c2smooth": "s2_c2_smoothed_radius",
                 "c2hybrid": "s2_c2_hybrid_radius", "so3": "so3_m1e6_n64", "t3": "t3_m2e6_n64"}
@@ -302,6 +310,7 @@ def main():
             ach = amount / sec / 1e12
             roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                     "frac": ach / peak, "traffic": traffic, "units_per_launch": {"flop": amount}}
+        roof["launches"] = PHASE_LAUNCHES.get(domain, {}).get(dom, kern)
     # the whole MLS step (radius + assembly + solve + re-solve) against the
     # FP64 vector peak, on its algorithmic FLOPs
     mls_ms = sum(phases[k]["avg_ms"] for k in ("radius", "assemble", "solve", "resolve") if k in phases)
