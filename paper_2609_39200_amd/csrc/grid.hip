@@ -305,18 +305,27 @@ hamls_status launch_grid_gather(const Plan& P, const int32_t* idx, const double*
 // support radius (eq. (5), (6), (12))
 // ---------------------------------------------------------------------------
 
-// One grid node per block (one wave).  Adaptive radius: bracket a search
-// radius on the cell-cover count (cell table only), scan the box keeping the
-// keys of the ball, resize until it holds between n and kGCap nodes, take
-// the n-th largest key exactly.  SO3: delta = (1+eps) 2 arccos(t_n), clamped
-// below pi, threshold cos(delta/2).  T3: threshold c = (1+eps)^2 d_n^2 on d^2
-// (no transcendental), delta = sqrt(c).  A fixed delta_0 is merged (larger
-// radius wins).  Thresholds are stored on the key: SO3 c, T3 -c.
+// Grid nodes per wave of the radius search.  Consecutive grid nodes are
+// neighbours on the product grid (its last axis varies fastest), so every node
+// after the first of a group starts from the previous node's n-th distance
+// widened by kSeedGrow: the first scan then nearly always holds n nodes, with
+// no sizing on the cell table and no second scan.
+constexpr int kRadGroup = 8;
+constexpr double kSeedGrow = 1.15;
+
+// One wave per group of kRadGroup consecutive grid nodes, one node at a time.
+// Adaptive radius: the first node of a group brackets a search radius on the
+// cell-cover count (cell table only), the others take the seed above; scan the
+// box keeping the keys of the ball, resize until it holds between n and kGCap
+// nodes, take the n-th largest key exactly.  SO3: delta = (1+eps) 2
+// arccos(t_n), clamped below pi, threshold cos(delta/2).  T3: threshold
+// c = (1+eps)^2 d_n^2 on d^2 (no transcendental), delta = sqrt(c).  A fixed
+// delta_0 is merged (larger radius wins).  Thresholds are stored on the key:
+// SO3 c, T3 -c.
 template <int D>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_grid_radius(GridGeom g, int64_t M, int knn, double eps,
-                                                   double wfac, double delta0, double* thr,
-                                                   double* delta, uint8_t* rstatus, int32_t* mlist,
-                                                   int32_t* mcnt, const int32_t* __restrict__ order) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(D == 4 ? 4 : 5))) void k_grid_radius(
+    GridGeom g, int64_t M, int64_t MQ, int knn, double eps, double wfac, double delta0, double* thr,
+    double* delta, uint8_t* rstatus, int32_t* mlist, int32_t* mcnt) {
     constexpr int U = 4;
     // 416 candidates keep the LDS at 8 KB, five waves per SIMD with 96 VGPRs
     // (the wave-uniform state in scalar registers)
@@ -327,239 +336,295 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
     __shared__ __align__(16) double binbuf[kBinCap];  // also the scan histogram
     __shared__ int ohist[256];
     __shared__ int sh[kScanLds];
-    // grid order, or the plan's cost order (heaviest first), dealt over the XCDs
+    // groups in grid order, dealt over the XCDs
     const int jb = xcd_block(blockIdx.x, gridDim.x);
-    const int j = order ? order[jb] : jb;
     const int lane = threadIdx.x;
-    double q[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int d = 0; d < D; d++) q[d] = uni_d(g.grid[(int64_t)D * j + d]);
-    uint8_t st = 0;
-    double dl = delta0;
-    if (knn > 0) {
-        const double rmax = grid_rmax<D>(g);
-        const double rhomax = grid_rho<D>(g, rmax);
-        // initial half-width: bracket the box cover count into [3n, 12n], from
-        // the radius holding n nodes at the mean density (SO3: the box around
-        // the ball on the 3-sphere is the larger part of its cover, so the
-        // first scan often holds fewer than n; the histogram-guided second
-        // scan is cheaper than a first scan of a box sized to hold n)
-        double r = D == 4 ? cbrt(6.0 * kPi * knn / (double)M) : cbrt(3.0 * knn / (4.0 * kPi * M));
-        r = fmin(r, rmax);
-        {
-            const int target = 3 * knn;
-            double rl = 0.0, rh = 0.0;
-            for (int it = 0; it < 20; it++) {
-                const int cov = grid_cover_count<D>(g, q, grid_rho<D>(g, r));
-                if (cov < target) {
-                    if (r >= rmax) break;
-                    rl = r;
-                    r = rh > 0.0 ? sqrt(r * rh) : fmin(rmax, r * (cov < target / 6 ? 1.6 : 1.25));
-                } else if (cov > 4 * target && r > 1e-6) {
-                    rh = r;
-                    r = rl > 0.0 ? sqrt(r * rl) : r * 0.7;
-                } else {
-                    break;
-                }
-            }
-        }
-        double rho = grid_rho<D>(g, r);  // the search runs on the box half-width
-        // Keys at or above ktop are only counted (`above`).  With u = khi - key
-        // (khi the largest key: SO3 1, T3 0): a scan that overflows the buffer
-        // narrows the kept range to the bin of the n-th key in a 256-bin
-        // histogram of u over [khi - ktop, khi - key(r)); a scan with fewer
-        // than n keys in the ball grows it from a histogram of the records of
-        // the box outside the ball (u over [u0, 16 u0), u0 = khi - key(r)): the
-        // smallest bin edge with n records of the box inside holds at least n.
-        const double khi = D == 4 ? 1.0 : 0.0;
-        double r_hi = 0.0;  // half-width of a box known to overflow the buffer
-        double tn = -1e300, ktop = 2.0;
-        bool done = false, hemi = false;
-        int lcount = -1;  // kept keys of the final scan when it kept them all
-        double lkr = 2.0;
-        int* hist = (int*)binbuf;  // 256 ints
-        for (int it = 0; it < 40 && !done; it++) {
-            const double kr = grid_key_of_rho<D>(rho);
-            const double ulo = uni_d(ktop < 2.0 ? khi - ktop : 0.0);
-            const double hs = uni_d(256.0 / fmax((khi - kr) - ulo, 1e-300));
-            const double u0 = uni_d(khi - kr), ohs = uni_d(256.0 / fmax(15.0 * u0, 1e-300));
-            rho = uni_d(rho);
-            ktop = uni_d(ktop);
-            tn = uni_d(tn);
-            r_hi = uni_d(r_hi);
-            lkr = uni_d(lkr);
-#pragma unroll
-            for (int qq = 0; qq < 4; qq++) {
-                hist[4 * lane + qq] = 0;
-                ohist[4 * lane + qq] = 0;
-            }
-            __syncthreads();
-            int count = 0, above = 0, nout = 0;
-            grid_scan<D, U>(g, q, rho, sh, [&](const bool* valid, const int* idx) {
-                double kv[U];
-#pragma unroll
-                for (int u = 0; u < U; u++) kv[u] = valid[u] ? grid_key<D>(g, idx[u], q) : -1e300;
-#pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const bool up = valid[u] && kv[u] >= ktop;
-                    const bool in = valid[u] && kv[u] > kr && !up;
-                    const bool out = valid[u] && kv[u] <= kr;
-                    above += __popcll(__ballot(up));
-                    nout += __popcll(__ballot(out));
-                    if (out) {
-                        int bin = (int)((khi - kv[u] - u0) * ohs);
-                        atomicAdd(&ohist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
-                    }
-                    const uint64_t mk = __ballot(in);
-                    const int pos = count + rank_below(mk);
-                    if (in) {
-                        if (pos < kGCap) {
-                            buf[pos] = kv[u];
-                            ibuf[pos] = idx[u];
+    // largest search radius and its box half-width
+    const double rmax = grid_rmax<D>(g);
+    const double rhomax = uni_d(grid_rho<D>(g, rmax));
+    double tprev = 0.0;   // n-th largest key of the group's previous node
+    bool seeded = false;  // tprev holds one
+    for (int gi = 0; gi < kRadGroup; gi++) {
+        const int64_t jj = (int64_t)jb * kRadGroup + gi;
+        if (jj >= MQ) break;
+        const int j = (int)jj;
+        double q[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int d = 0; d < D; d++) q[d] = uni_d(g.grid[(int64_t)D * j + d]);
+        uint8_t st = 0;
+        double dl = delta0;
+        if (knn > 0) {
+            tprev = uni_d(tprev);
+            // initial box half-width rho: the seed, or (first node of a group)
+            // the radius holding n nodes at the mean density with the box cover
+            // count bracketed into [3n, 12n]; a scan with fewer than n nodes in
+            // the ball grows it from the histogram of the records outside
+            double rho;
+            const double rs = grid_rho_of_key<D>(tprev) * kSeedGrow;
+            const bool lean = seeded && rs > 0.1 * g.h;
+            if (lean) {
+                rho = fmin(rs, rhomax);
+            } else {
+                // radius holding n nodes at the mean density
+                double r = fmin(D == 4 ? cbrt(6.0 * kPi * knn / (double)M) : cbrt(3.0 * knn / (4.0 * kPi * M)),
+                                rmax);
+                {
+                    const int target = 3 * knn;
+                    double rl = 0.0, rh = 0.0;
+                    for (int it = 0; it < 20; it++) {
+                        const int cov = grid_cover_count<D>(g, q, grid_rho<D>(g, r));
+                        if (cov < target) {
+                            if (r >= rmax) break;
+                            rl = r;
+                            r = rh > 0.0 ? sqrt(r * rh) : fmin(rmax, r * (cov < target / 6 ? 1.6 : 1.25));
+                        } else if (cov > 4 * target && r > 1e-6) {
+                            rh = r;
+                            r = rl > 0.0 ? sqrt(r * rl) : r * 0.7;
                         } else {
-                            int bin = (int)((khi - kv[u] - ulo) * hs);
-                            atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                            break;
                         }
                     }
-                    count += __popcll(mk);
                 }
-            });
-            __syncthreads();
-            if (above >= knn) {
-                // rounding put the n-th key at or above ktop: drop the bound
-                rho = fmin(grid_rho_of_key<D>(ktop), rhomax);
-                r_hi = 0.0;
-                ktop = 2.0;
-            } else if (above + count < knn) {
-                if (rho >= rhomax) {
-                    hemi = true;
+                rho = grid_rho<D>(g, r);
+            }
+            // Keys at or above ktop are only counted (`above`).  With u = khi - key
+            // (khi the largest key: SO3 1, T3 0): a scan that overflows the buffer
+            // narrows the kept range to the bin of the n-th key in a 256-bin
+            // histogram of u over [khi - ktop, khi - key(r)); a scan with fewer
+            // than n keys in the ball grows it from a histogram of the records of
+            // the box outside the ball (u over [u0, 16 u0), u0 = khi - key(r)): the
+            // smallest bin edge with n records of the box inside holds at least n.
+            const double khi = D == 4 ? 1.0 : 0.0;
+            double r_hi = 0.0;  // half-width of a box known to overflow the buffer
+            double tn = -1e300, ktop = 2.0;
+            bool done = false, hemi = false;
+            int lcount = -1;  // kept keys of the final scan when it kept them all
+            double lkr = 2.0;
+            int* hist = (int*)binbuf;  // 256 ints
+            if (lean) {
+                // seeded first scan: keep the keys of the ball, nothing else;
+                // when it holds fewer than n or overflows the buffer, the
+                // general loop below takes over (grown or at the same radius)
+                const double kr = uni_d(grid_key_of_rho<D>(rho));
+                rho = uni_d(rho);
+                int count = 0;
+                grid_scan<D, U>(g, q, rho, sh, [&](const bool* valid, const int* idx) {
+                    double kv[U];
+#pragma unroll
+                    for (int u = 0; u < U; u++) kv[u] = grid_key<D>(g, idx[u], q);
+#pragma unroll
+                    for (int u = 0; u < U; u++) kv[u] = valid[u] ? kv[u] : -1e300;
+#pragma unroll
+                    for (int u = 0; u < U; u++) {
+                        const bool in = kv[u] > kr;
+                        const uint64_t mk = __ballot(in);
+                        const int pos = count + rank_below(mk);
+                        if (in && pos < kGCap) {
+                            buf[pos] = kv[u];
+                            ibuf[pos] = idx[u];
+                        }
+                        count += __popcll(mk);
+                    }
+                });
+                __syncthreads();
+                if (count >= knn && count <= kGCap) {
+                    tn = nth_largest(buf, count, knn, kr, khi, sh, binbuf, kBinCap);
                     done = true;
-                } else {
-                    const int have = above + count;
-                    double nr = -1.0;
-                    if (have + nout >= knn) {
-                        int before;
-                        const int B = hist_select_bin(ohist, have, knn, before);
-                        // widened by wfac = 1.005 (1 + eps) so that the scan also
-                        // holds the support and can hand on its members
-                        if (B < 255) nr = grid_rho_of_key<D>(khi - u0 * (1.0 + 15.0 * (B + 1) / 256.0)) * wfac;
-                    }
-                    if (nr <= rho) {
-                        double grow = 1.15 * cbrt((double)knn / (double)(have > 0 ? have : 1));
-                        grow = grow < 1.2 ? 1.2 : (grow > 2.0 ? 2.0 : grow);
-                        nr = rho * grow;
-                        if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(rho * r_hi);
-                    } else if (r_hi > 0.0) {
-                        nr = fmin(nr, r_hi);
-                    }
-                    rho = fmin(nr, rhomax);
-                }
-            } else if (count <= kGCap) {
-                tn = nth_largest(buf, count, knn - above, kr, fmin(ktop, khi), sh, binbuf, kBinCap);
-                done = true;
-                if (ktop >= 2.0) {
-                    lcount = count;  // every key above key(r) is kept
+                    lcount = count;
                     lkr = kr;
-                }
-            } else {
-                // bin in the histogram of every key of (key(r), ktop)
-                for (int a = lane; a < kGCap; a += 64) {
-                    int bin = (int)((khi - buf[a] - ulo) * hs);
-                    atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                } else if (count < knn) {
+                    const double grow = 1.15 * cbrt((double)knn / (double)(count > 0 ? count : 1));
+                    rho = fmin(rho * fmin(fmax(grow, 1.2), 2.0), rhomax);
                 }
                 __syncthreads();
-                int before;
-                const int B = hist_select_bin(hist, above, knn, before);
-                r_hi = rho;
-                if (B < 255) rho = fmin(grid_rho_of_key<D>(khi - (ulo + (B + 1) / hs)), rhomax);
-                if (B > 0) ktop = khi - (ulo + B / hs);
             }
-            __syncthreads();
-        }
-        if (!done) {
-            // exact fallback: bitwise binary search for the largest key v with
-            // #(key >= v) >= n among the keys of the ball of radius r
-            const double kr = grid_key_of_rho<D>(rho);
-            uint64_t lo = ordered_bits(kr), hi = ordered_bits(D == 4 ? 1.0 : 0.0);
-            while (lo < hi) {
-                uint64_t mid = lo + (hi - lo + 1) / 2;
-                double v = from_ordered_bits(mid);
-                int count = 0;
-                grid_scan<D, 1>(g, q, rho, sh, [&](const bool* valid, const int* idx) {
-                    bool in = valid[0] && grid_key<D>(g, idx[0], q) >= v;
-                    count += __popcll(__ballot(in));
+            for (int it = 0; it < 40 && !done; it++) {
+                const double kr = grid_key_of_rho<D>(rho);
+                const double ulo = uni_d(ktop < 2.0 ? khi - ktop : 0.0);
+                const double hs = uni_d(256.0 / fmax((khi - kr) - ulo, 1e-300));
+                const double u0 = uni_d(khi - kr), ohs = uni_d(256.0 / fmax(15.0 * u0, 1e-300));
+                rho = uni_d(rho);
+                ktop = uni_d(ktop);
+                tn = uni_d(tn);
+                r_hi = uni_d(r_hi);
+                lkr = uni_d(lkr);
+#pragma unroll
+                for (int qq = 0; qq < 4; qq++) {
+                    hist[4 * lane + qq] = 0;
+                    ohist[4 * lane + qq] = 0;
+                }
+                __syncthreads();
+                int count = 0, above = 0, nout = 0;
+                grid_scan<D, U>(g, q, rho, sh, [&](const bool* valid, const int* idx) {
+                    double kv[U];
+#pragma unroll
+                    for (int u = 0; u < U; u++) kv[u] = grid_key<D>(g, idx[u], q);
+#pragma unroll
+                    for (int u = 0; u < U; u++) kv[u] = valid[u] ? kv[u] : -1e300;
+#pragma unroll
+                    for (int u = 0; u < U; u++) {
+                        const bool up = valid[u] && kv[u] >= ktop;
+                        const bool in = valid[u] && kv[u] > kr && !up;
+                        const bool out = valid[u] && kv[u] <= kr;
+                        above += __popcll(__ballot(up));
+                        nout += __popcll(__ballot(out));
+                        if (out) {
+                            int bin = (int)((khi - kv[u] - u0) * ohs);
+                            atomicAdd(&ohist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                        }
+                        const uint64_t mk = __ballot(in);
+                        const int pos = count + rank_below(mk);
+                        if (in) {
+                            if (pos < kGCap) {
+                                buf[pos] = kv[u];
+                                ibuf[pos] = idx[u];
+                            } else {
+                                int bin = (int)((khi - kv[u] - ulo) * hs);
+                                atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                            }
+                        }
+                        count += __popcll(mk);
+                    }
                 });
-                if (count >= knn)
-                    lo = mid;
-                else
-                    hi = mid - 1;
+                __syncthreads();
+                if (above >= knn) {
+                    // rounding put the n-th key at or above ktop: drop the bound
+                    rho = fmin(grid_rho_of_key<D>(ktop), rhomax);
+                    r_hi = 0.0;
+                    ktop = 2.0;
+                } else if (above + count < knn) {
+                    if (rho >= rhomax) {
+                        hemi = true;
+                        done = true;
+                    } else {
+                        const int have = above + count;
+                        double nr = -1.0;
+                        if (have + nout >= knn) {
+                            int before;
+                            const int B = hist_select_bin(ohist, have, knn, before);
+                            // widened by wfac = 1.005 (1 + eps) so that the scan also
+                            // holds the support and can hand on its members
+                            if (B < 255) nr = grid_rho_of_key<D>(khi - u0 * (1.0 + 15.0 * (B + 1) / 256.0)) * wfac;
+                        }
+                        if (nr <= rho) {
+                            double grow = 1.15 * cbrt((double)knn / (double)(have > 0 ? have : 1));
+                            grow = grow < 1.2 ? 1.2 : (grow > 2.0 ? 2.0 : grow);
+                            nr = rho * grow;
+                            if (r_hi > 0.0 && nr >= r_hi) nr = sqrt(rho * r_hi);
+                        } else if (r_hi > 0.0) {
+                            nr = fmin(nr, r_hi);
+                        }
+                        rho = fmin(nr, rhomax);
+                    }
+                } else if (count <= kGCap) {
+                    tn = nth_largest(buf, count, knn - above, kr, fmin(ktop, khi), sh, binbuf, kBinCap);
+                    done = true;
+                    if (ktop >= 2.0) {
+                        lcount = count;  // every key above key(r) is kept
+                        lkr = kr;
+                    }
+                } else {
+                    // bin in the histogram of every key of (key(r), ktop)
+                    for (int a = lane; a < kGCap; a += 64) {
+                        int bin = (int)((khi - buf[a] - ulo) * hs);
+                        atomicAdd(&hist[bin < 0 ? 0 : (bin > 255 ? 255 : bin)], 1);
+                    }
+                    __syncthreads();
+                    int before;
+                    const int B = hist_select_bin(hist, above, knn, before);
+                    r_hi = rho;
+                    if (B < 255) rho = fmin(grid_rho_of_key<D>(khi - (ulo + (B + 1) / hs)), rhomax);
+                    if (B > 0) ktop = khi - (ulo + B / hs);
+                }
+                __syncthreads();
             }
-            tn = from_ordered_bits(lo);
+            if (!done) {
+                // exact fallback: bitwise binary search for the largest key v with
+                // #(key >= v) >= n among the keys of the ball of radius r
+                const double kr = grid_key_of_rho<D>(rho);
+                uint64_t lo = ordered_bits(kr), hi = ordered_bits(D == 4 ? 1.0 : 0.0);
+                while (lo < hi) {
+                    uint64_t mid = lo + (hi - lo + 1) / 2;
+                    double v = from_ordered_bits(mid);
+                    int count = 0;
+                    grid_scan<D, 1>(g, q, rho, sh, [&](const bool* valid, const int* idx) {
+                        bool in = valid[0] && grid_key<D>(g, idx[0], q) >= v;
+                        count += __popcll(__ballot(in));
+                    });
+                    if (count >= knn)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                tn = from_ordered_bits(lo);
+            }
+            double tv;  // key threshold of the support
+            if (D == 4) {
+                double dk = hemi ? kPi : (1.0 + eps) * (2.0 * acos(fmin(1.0, fmax(-1.0, tn))));
+                if (!(delta0 > 0.0 && delta0 > dk)) dl = dk;
+                if (dl >= kPi) {
+                    dl = kPi;
+                    st |= HAMLS_ST_HEMISPHERE;
+                }
+                tv = cos(0.5 * dl);
+            } else {
+                // T3: the threshold is (1+eps)^2 d_n^2 on d^2; a fixed radius wins
+                // when it is larger than the adaptive one
+                double e = 1.0 + eps;
+                double e2 = e * e;
+                double ck = hemi ? 3.0 : e2 * (-tn);
+                double dk = sqrt(ck);
+                double cc = ck;
+                dl = dk;
+                if (delta0 > 0.0 && delta0 > dk) {
+                    dl = delta0;
+                    cc = delta0 * delta0;
+                }
+                tv = -cc;
+            }
+            // member list for the assembly: when the final scan kept every key of
+            // a ball that holds the support (tv >= key(r)), the members are its
+            // kept keys above tv, in scan order
+            if (mcnt) {
+                int nm = -1;
+                if (lcount >= 0 && tv >= lkr && !(st & HAMLS_ST_HEMISPHERE)) {
+                    nm = 0;
+                    for (int base = 0; base < lcount; base += 64) {
+                        const int a = base + lane;
+                        const bool in = a < lcount && buf[a] > tv;
+                        const uint64_t mk = __ballot(in);
+                        const int pos = nm + rank_below(mk);
+                        if (in && pos < kListCap) mlist[(int64_t)j * kListCap + pos] = ibuf[a];
+                        nm += __popcll(mk);
+                    }
+                    if (nm > kListCap) nm = -1;
+                }
+                if (lane == 0) mcnt[j] = nm;
+            }
+            if (lane == 0) {
+                thr[j] = tv;
+                delta[j] = dl;
+                rstatus[j] = st;
+            }
+            tprev = tn;
+            seeded = !hemi;
+            continue;
         }
-        double tv;  // key threshold of the support
         if (D == 4) {
-            double dk = hemi ? kPi : (1.0 + eps) * (2.0 * acos(fmin(1.0, fmax(-1.0, tn))));
-            if (!(delta0 > 0.0 && delta0 > dk)) dl = dk;
             if (dl >= kPi) {
                 dl = kPi;
                 st |= HAMLS_ST_HEMISPHERE;
             }
-            tv = cos(0.5 * dl);
-        } else {
-            // T3: the threshold is (1+eps)^2 d_n^2 on d^2; a fixed radius wins
-            // when it is larger than the adaptive one
-            double e = 1.0 + eps;
-            double e2 = e * e;
-            double ck = hemi ? 3.0 : e2 * (-tn);
-            double dk = sqrt(ck);
-            double cc = ck;
-            dl = dk;
-            if (delta0 > 0.0 && delta0 > dk) {
-                dl = delta0;
-                cc = delta0 * delta0;
+            const double c = cos(0.5 * dl);
+            if (lane == 0) {
+                thr[j] = c;
+                delta[j] = dl;
+                rstatus[j] = st;
             }
-            tv = -cc;
-        }
-        // member list for the assembly: when the final scan kept every key of
-        // a ball that holds the support (tv >= key(r)), the members are its
-        // kept keys above tv, in scan order
-        if (mcnt) {
-            int nm = -1;
-            if (lcount >= 0 && tv >= lkr && !(st & HAMLS_ST_HEMISPHERE)) {
-                nm = 0;
-                for (int base = 0; base < lcount; base += 64) {
-                    const int a = base + lane;
-                    const bool in = a < lcount && buf[a] > tv;
-                    const uint64_t mk = __ballot(in);
-                    const int pos = nm + rank_below(mk);
-                    if (in && pos < kListCap) mlist[(int64_t)j * kListCap + pos] = ibuf[a];
-                    nm += __popcll(mk);
-                }
-                if (nm > kListCap) nm = -1;
-            }
-            if (lane == 0) mcnt[j] = nm;
-        }
-        if (lane == 0) {
-            thr[j] = tv;
-            delta[j] = dl;
+        } else if (lane == 0) {
+            thr[j] = -(delta0 * delta0);
+            delta[j] = delta0;
             rstatus[j] = st;
         }
-        return;
-    }
-    if (D == 4) {
-        if (dl >= kPi) {
-            dl = kPi;
-            st |= HAMLS_ST_HEMISPHERE;
-        }
-        const double c = cos(0.5 * dl);
-        if (lane == 0) {
-            thr[j] = c;
-            delta[j] = dl;
-            rstatus[j] = st;
-        }
-    } else if (lane == 0) {
-        thr[j] = -(delta0 * delta0);
-        delta[j] = delta0;
-        rstatus[j] = st;
     }
 }
 
@@ -568,10 +633,10 @@ hamls_status launch_grid_radius(const Plan& P, hipStream_t s) {
     double d0 = P.prm.support_radius > 0.0 ? P.prm.support_radius : 0.0;
     int knn = P.prm.knn_count > 0 ? P.prm.knn_count : 0;
     auto kern = P.dom == HAMLS_SO3 ? k_grid_radius<4> : k_grid_radius<3>;
-    const int32_t* order = P.asm_queue_blocks == 1 ? P.d_order : nullptr;
-    hipLaunchKernelGGL(kern, dim3((unsigned)P.MQ), dim3(64), 0, s, g, P.M, knn, P.prm.knn_eps,
+    const int64_t groups = (P.MQ + kRadGroup - 1) / kRadGroup;
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(64), 0, s, g, P.M, P.MQ, knn, P.prm.knn_eps,
                        1.005 * (1.0 + P.prm.knn_eps), d0, P.d_thr, P.d_delta, P.d_rstatus, P.d_mlist,
-                       P.d_mcnt, order);
+                       P.d_mcnt);
     HAMLS_HIP(hipGetLastError());
     return HAMLS_OK;
 }
@@ -717,9 +782,11 @@ __device__ __forceinline__ void grid_node(int j, double* rows, int* sh, const Gr
         // field values loaded with the coordinates, for every record of the
         // cover (one round trip less than loading the members')
 #pragma unroll
-        for (int u = 0; u < U; u++) y1[u] = (FM == 1 && valid[u]) ? vals[idx[u]] : 0.0;
+        for (int u = 0; u < U; u++) y1[u] = FM == 1 ? vals[idx[u]] : 0.0;
 #pragma unroll
-        for (int u = 0; u < U; u++) kv[u] = valid[u] ? grid_key<D>(g, idx[u], q) : -1e300;
+        for (int u = 0; u < U; u++) kv[u] = grid_key<D>(g, idx[u], q);
+#pragma unroll
+        for (int u = 0; u < U; u++) kv[u] = valid[u] ? kv[u] : -1e300;
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const bool in = kv[u] > c;
