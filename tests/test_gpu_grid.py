@@ -247,6 +247,41 @@ def test_grid_knn_at_candidate_buffer_limit(H, domain):
     _check(H, wl, label=f"{domain} n=400")
 
 
+def test_t3_density_step_seeded_search(H):
+    # Nineteen twentieths of the points below z = 0.4.  The search runs eight
+    # consecutive grid nodes (along the last grid axis, z) a wave, each after
+    # the first starting from its neighbour's d_n widened by 1.15: crossing
+    # the step upward leaves that ball short of n nodes (the search grows it),
+    # crossing it downward and at the periodic wrap overfills the 416-key
+    # candidate buffer (the search narrows it).  Both cases are counted here
+    # on the CPU first, so that the test is known to reach them; sets stay
+    # bit-exact.
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(5260)
+    M, n, g = 20000, 40, 12
+    nd = int(0.95 * M)
+    x = rng.random((M, 3))
+    x[:nd, 2] *= 0.4
+    x[nd:, 2] = 0.4 + 0.6 * x[nd:, 2]
+    f = W.torus_field(4, rng)
+    wl = W.Workload("t3-density-step", "t3", x, f(x)[None, :],
+                    dict(domain="t3", bandwidth=4, degree=2, support_radius=0.0, knn_count=n,
+                         knn_eps=0.05, reg="chi", chi_target=10.0, chi_full=20.0,
+                         grid_shape=(g, g, g)))
+    a, b, c = np.meshgrid(np.arange(g), np.arange(g), np.arange(g), indexing="ij")
+    q = np.stack([a.ravel(), b.ravel(), c.ravel()], axis=1) / g
+    tree = cKDTree(x, boxsize=1.0)
+    dn = tree.query(q, k=n)[0][:, -1]
+    seeded = np.arange(1, g ** 3) % 8 != 0  # grid nodes after the first of their group
+    held = tree.query_ball_point(q[1:], 1.15 * dn[:-1], return_length=True)
+    short = int(np.sum(seeded & (held < n)))
+    over = int(np.sum(seeded & (held > 416)))
+    _say(f"  seeded balls short of n: {short}, over the buffer: {over}")
+    assert short > 0 and over > 0
+    _check(H, wl, label="t3 density step")
+
+
 def test_t3_fixed_radius_weights_fields(H):
     rng = np.random.default_rng(52)
     x = W.clustered_torus(10000, rng)
