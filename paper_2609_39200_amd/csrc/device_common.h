@@ -280,6 +280,20 @@ __device__ __forceinline__ double from_ordered_bits(uint64_t u) {
 // above 1e8), or a Schur denominator below kDenResolve.
 constexpr double kPivResolve = 1e-8;
 constexpr double kDenResolve = 1e-4;
+
+// sqrt(s) and 1/sqrt(s) of a Cholesky pivot s > 0: the hardware reciprocal
+// square-root estimate and two Newton steps y <- y + y (1 - s y^2) / 2 (a
+// correctly rounded square root followed by a division is twice as long a
+// dependent chain, and the factorization runs one pivot after another)
+__device__ __forceinline__ void pivot_roots(double s, double& root, double& inv) {
+    double y = __builtin_amdgcn_rsq(s);
+    double e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-s * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    inv = y;
+    root = s * y;
+}
 // |R_jj| of the unit-column V at or below which V is taken as rank deficient
 // (compared as the squared pivot of the unit-diagonal C).
 constexpr double kRankTol = 1e-11;
@@ -482,8 +496,8 @@ __device__ void mls_solve_epilogue(const double* Gs, double* isc, int count, int
                 break;
             }
         }
-        const double lkk = sqrt(s);
-        const double il = 1.0 / lkk;
+        double lkk, il;
+        pivot_roots(s, lkk, il);
         a[k] = lane == k ? lkk : a[k] * il;
 #pragma unroll
         for (int c = k + 1; c <= NC; c++) a[c] = fma(-a[k], readlane_f64(a[k], c), a[c]);
@@ -736,8 +750,8 @@ __device__ void mls_solve_group(const double* Gs, int count, int64_t j, const So
                 break;
             }
         }
-        const double lkk = sqrt(sk);
-        const double il = 1.0 / lkk;
+        double lkk, il;
+        pivot_roots(sk, lkk, il);
         a[k] = r == k ? lkk : a[k] * il;
 #pragma unroll
         for (int c = k + 1; c <= NC; c++) a[c] = fma(-a[k], grp_bcast<GS>(a[k], c), a[c]);
@@ -1233,8 +1247,8 @@ __device__ __forceinline__ void mixed_node_core(int j, double* lds, double thr, 
             ill = true;
             break;
         }
-        const double lkk = sqrt(sk);
-        const double il = 1.0 / lkk;
+        double lkk, il;
+        pivot_roots(sk, lkk, il);
         a[k] = lane == k ? lkk : a[k] * il;
 #pragma unroll
         for (int cc = k + 1; cc <= NC; cc++) a[cc] = fma(-a[k], readlane_f64(a[k], cc), a[cc]);
