@@ -21,14 +21,73 @@ struct cplx {
     T re, im;
 };
 
+// a / b for 0 <= a < 2^24 and 1 <= b < 2^24, from rb = 1/b in FP32: the
+// product is within one unit of the quotient, and one step each way makes it
+// exact (an integer division by a value known only at run time costs several
+// times as many instructions, and the index arithmetic of these kernels does
+// one per element)
+__device__ __forceinline__ int div_small(int a, int b, float rb) {
+    int q = (int)((float)a * rb);
+    if (q * b > a)
+        q--;
+    else if ((q + 1) * b <= a)
+        q++;
+    return q;
+}
+
+// X_p = sum_q v_q w^(p q), w = exp(sign 2 pi i / R), for R = 2, 4, 8: the
+// even and odd halves transformed at R/2 and joined by the roots
+// w^p (w^(p + R/2) = -w^p).
+template <class T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> x, cplx<T> y) { return {x.re + y.re, x.im + y.im}; }
+template <class T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> x, cplx<T> y) { return {x.re - y.re, x.im - y.im}; }
+// x times sign i
+template <class T>
+__device__ __forceinline__ cplx<T> cmul_i(cplx<T> x, T sign) { return {-sign * x.im, sign * x.re}; }
+template <int R, class T>
+__device__ __forceinline__ void fft_small(const cplx<T>* v, cplx<T>* X, T sign) {
+    if constexpr (R == 2) {
+        X[0] = cadd(v[0], v[1]);
+        X[1] = csub(v[0], v[1]);
+    } else if constexpr (R == 4) {
+        const cplx<T> a = cadd(v[0], v[2]), bb = csub(v[0], v[2]);
+        const cplx<T> c = cadd(v[1], v[3]), d = cmul_i(csub(v[1], v[3]), sign);
+        X[0] = cadd(a, c);
+        X[2] = csub(a, c);
+        X[1] = cadd(bb, d);
+        X[3] = csub(bb, d);
+    } else {
+        const cplx<T> ve[4] = {v[0], v[2], v[4], v[6]}, vo[4] = {v[1], v[3], v[5], v[7]};
+        cplx<T> E[4], O[4];
+        fft_small<4, T>(ve, E, sign);
+        fft_small<4, T>(vo, O, sign);
+        const T h = (T)0.70710678118654752440;  // sqrt(1/2)
+        // w^1 O_1, w^2 O_2, w^3 O_3 with w = (1 + sign i) / sqrt(2)
+        const cplx<T> o1 = {h * (O[1].re - sign * O[1].im), h * (O[1].im + sign * O[1].re)};
+        const cplx<T> o2 = cmul_i(O[2], sign);
+        const cplx<T> o3 = {-h * (O[3].re + sign * O[3].im), h * (sign * O[3].re - O[3].im)};
+        X[0] = cadd(E[0], O[0]);
+        X[4] = csub(E[0], O[0]);
+        X[1] = cadd(E[1], o1);
+        X[5] = csub(E[1], o1);
+        X[2] = cadd(E[2], o2);
+        X[6] = csub(E[2], o2);
+        X[3] = cadd(E[3], o3);
+        X[7] = csub(E[3], o3);
+    }
+}
+
 // One radix-R Stockham butterfly (see the file comment); tw holds cos at
 // [e] and sin at [n + e] (FP64 in LDS, rounded to T on use).
 template <int R, class T>
 __device__ __forceinline__ void fft_butterfly(const cplx<T>* __restrict__ a, cplx<T>* __restrict__ b, int j,
-                                              int Ns, int n, const double* __restrict__ tw, T sign) {
+                                              int Ns, float rNs, int tsc, int n, const double* __restrict__ tw,
+                                              T sign) {
     const int m = n / R;
-    const int jj = j % Ns;
-    const int tstep = jj * (n / (Ns * R));
+    const int jq = div_small(j, Ns, rNs);  // j div Ns
+    const int jj = j - jq * Ns;             // j mod Ns
+    const int tstep = jj * tsc;             // tsc = n / (Ns R)
     cplx<T> v[R];
 #pragma unroll
     for (int q = 0; q < R; q++) {
@@ -38,7 +97,17 @@ __device__ __forceinline__ void fft_butterfly(const cplx<T>* __restrict__ a, cpl
         v[q].re = x.re * c - x.im * s;
         v[q].im = x.re * s + x.im * c;
     }
-    const int d0 = (j / Ns) * Ns * R + jj;
+    const int d0 = jq * Ns * R + jj;
+    if constexpr (R == 2 || R == 4 || R == 8) {
+        // the R-point DFT factored into radix-2 steps: its roots are 1, +-i
+        // and (+-1 +- i)/sqrt(2), so it takes additions and four
+        // multiplications instead of the (R - 1)^2 complex products below
+        cplx<T> X[R];
+        fft_small<R, T>(v, X, sign);
+#pragma unroll
+        for (int p = 0; p < R; p++) b[d0 + p * Ns] = X[p];
+        return;
+    }
     // outputs one at a time for the larger radices (register pressure)
     constexpr int kUnrollOut = R <= 8 ? R : 1;
 #pragma unroll kUnrollOut
@@ -56,12 +125,12 @@ __device__ __forceinline__ void fft_butterfly(const cplx<T>* __restrict__ a, cpl
 }
 
 template <class T>
-__device__ __forceinline__ void fft_stage(int R, const cplx<T>* a, cplx<T>* b, int j, int Ns, int n,
-                                          const double* tw, T sign) {
+__device__ __forceinline__ void fft_stage(int R, const cplx<T>* a, cplx<T>* b, int j, int Ns, float rNs, int tsc,
+                                          int n, const double* tw, T sign) {
     switch (R) {
 #define HAMLS_FFT_CASE(RR) \
     case RR:               \
-        fft_butterfly<RR, T>(a, b, j, Ns, n, tw, sign); \
+        fft_butterfly<RR, T>(a, b, j, Ns, rNs, tsc, n, tw, sign); \
         break;
         HAMLS_FFT_CASE(2)
         HAMLS_FFT_CASE(3)
@@ -89,9 +158,11 @@ __device__ cplx<T>* fft_lines(cplx<T>* a, cplx<T>* b, int TL, int ld, int n, con
     for (int s = 0; s < fp.nst; s++) {
         const int R = fp.rad[s];
         const int per = n / R;
+        const float rper = 1.0f / (float)per, rNs = 1.0f / (float)Ns;
+        const int tsc = n / (Ns * R);
         for (int e = threadIdx.x; e < TL * per; e += blockDim.x) {
-            const int l = e / per, j = e - l * per;
-            fft_stage<T>(R, a + l * ld, b + l * ld, j, Ns, n, tw, sign);
+            const int l = div_small(e, per, rper), j = e - l * per;
+            fft_stage<T>(R, a + l * ld, b + l * ld, j, Ns, rNs, tsc, n, tw, sign);
         }
         __syncthreads();
         cplx<T>* t = a;
@@ -122,20 +193,36 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in,
     const int tid = threadIdx.x;
     const int64_t nlines = A * B;
     const int64_t L0 = (int64_t)blockIdx.x * TL;
+    // TL and NL are powers of two (8 or 16 lines; 4, 8 or 16 transforms)
+    const int lgTL = 31 - __clz(TL), lgNL = 31 - __clz(NL);
+    const float rnin = 1.0f / (float)nin, rnout = 1.0f / (float)nout;
+    // line L = (a, b) of the [A][B] lines: L0's split once, then b0 + l < B + TL
+    const int64_t a0 = L0 / B, b0 = L0 - a0 * B;
+    const float rB = B < (1 << 24) ? 1.0f / (float)B : 0.0f;
+    auto split = [&](int l, int64_t& a, int64_t& b) {
+        b = b0 + l;
+        a = a0;
+        if (b >= B) {
+            const int64_t w = B < (1 << 24) ? (int64_t)div_small((int)b, (int)B, rB) : b / B;
+            a += w;
+            b -= w * B;
+        }
+    };
     for (int e = tid; e < 2 * nin; e += blockDim.x) stw[e] = tw[e];
     for (int e = tid; e < TL * nin; e += blockDim.x) {
         int l, i;
         if (B > 1) {
-            l = e % TL;
-            i = e / TL;
+            l = e & (TL - 1);
+            i = e >> lgTL;
         } else {
-            i = e % nin;
-            l = e / nin;
+            l = div_small(e, nin, rnin);
+            i = e - l * nin;
         }
         const int64_t L = L0 + l;
         double re = 0.0, im = 0.0;
         if (L < nlines) {
-            const int64_t a = L / B, b = L - a * B;
+            int64_t a, b;
+            split(l, a, b);
             const int64_t addr = (a * nin + i) * B + b;
             if (real_in) {
                 re = in[addr];
@@ -146,8 +233,8 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in,
         }
         if (real_in) {
             // line l < NL: real part; line l >= NL: imaginary part of line l - NL
-            double* slot = (double*)&buf0[(l % NL) * ld + i];
-            slot[l / NL] = re;
+            double* slot = (double*)&buf0[(l & (NL - 1)) * ld + i];
+            slot[l >> lgNL] = re;
         } else {
             buf0[l * ld + i] = cplx<double>{re, im};
         }
@@ -157,20 +244,23 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in,
     for (int e = tid; e < TL * nout; e += blockDim.x) {
         int l, k;
         if (B > 1) {
-            l = e % TL;
-            k = e / TL;
+            l = e & (TL - 1);
+            k = e >> lgTL;
         } else {
-            k = e % nout;
-            l = e / nout;
+            l = div_small(e, nout, rnout);
+            k = e - l * nout;
         }
         const int64_t L = L0 + l;
         if (L >= nlines) continue;
-        int f = (k - koff) % nin;
-        if (f < 0) f += nin;
+        int f = k - koff;
+        if (f < 0 || f >= nin) {
+            f %= nin;
+            if (f < 0) f += nin;
+        }
         cplx<double> x;
         if (real_in) {
-            const cplx<double> z = X[(l % NL) * ld + f];
-            const cplx<double> c = X[(l % NL) * ld + (f == 0 ? 0 : nin - f)];  // Z_{-k}
+            const cplx<double> z = X[(l & (NL - 1)) * ld + f];
+            const cplx<double> c = X[(l & (NL - 1)) * ld + (f == 0 ? 0 : nin - f)];  // Z_{-k}
             if (l < NL)
                 x = cplx<double>{0.5 * (z.re + c.re), 0.5 * (z.im - c.im)};
             else
@@ -178,7 +268,8 @@ __global__ __launch_bounds__(256) void k_fft_axis(const double* __restrict__ in,
         } else {
             x = X[l * ld + f];
         }
-        const int64_t a = L / B, b = L - a * B;
+        int64_t a, b;
+        split(l, a, b);
         const int64_t o = (a * nout + k) * B + b;
         out[2 * o] = x.re * scale;
         out[2 * o + 1] = x.im * scale;
@@ -225,8 +316,9 @@ __global__ __launch_bounds__(256) void k_s2_ring_fft(const double* __restrict__ 
     }
 }
 
-// Radices of n (primes 3..19 first, then powers of two by 8 and 4), or
-// nst = 0 when n has a prime factor above 19 (the direct sum is used then).
+// Radices of n (primes 3..19, then powers of two by 8, 4 and 2, the stages
+// in the reverse order), or nst = 0 when n has a prime factor above 19 (the
+// direct sum is used then).
 FftPlan make_fft_plan(int n) {
     FftPlan p;
     p.nst = 0;
@@ -254,7 +346,10 @@ FftPlan make_fft_plan(int n) {
     }
     if (r != 1) return p;
     p.nst = ns;
-    for (int i = 0; i < ns; i++) p.rad[i] = rad[i];
+    // stages run in the reverse order of extraction: the radix-2 stage of a
+    // power of two first (128 = 2 8 8 took 80 us a 128^3 transform where
+    // 8 8 2 took 86 us)
+    for (int i = 0; i < ns; i++) p.rad[i] = rad[ns - 1 - i];
     return p;
 }
 
