@@ -317,6 +317,20 @@ __device__ __forceinline__ double choose_tau(int reg, double chi, const double* 
     return choose_tau_grp<64>(reg, chi, d2, mu, n, tau_fixed, chi_t, chi_f);
 }
 
+// a / b for 0 <= a < 2^24 and 1 <= b < 2^24, from rb = 1/b in FP32: the
+// product is within one unit of the quotient, and one step each way makes it
+// exact (an integer division by a value known only at run time costs several
+// times as many instructions, and index arithmetic in the hot loops does one
+// per element)
+__device__ __forceinline__ int div_small(int a, int b, float rb) {
+    int q = (int)((float)a * rb);
+    if (q * b > a)
+        q--;
+    else if ((q + 1) * b <= a)
+        q++;
+    return q;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;

@@ -21,19 +21,6 @@ struct cplx {
     T re, im;
 };
 
-// a / b for 0 <= a < 2^24 and 1 <= b < 2^24, from rb = 1/b in FP32: the
-// product is within one unit of the quotient, and one step each way makes it
-// exact (an integer division by a value known only at run time costs several
-// times as many instructions, and the index arithmetic of these kernels does
-// one per element)
-__device__ __forceinline__ int div_small(int a, int b, float rb) {
-    int q = (int)((float)a * rb);
-    if (q * b > a)
-        q--;
-    else if ((q + 1) * b <= a)
-        q++;
-    return q;
-}
 
 // X_p = sum_q v_q w^(p q), w = exp(sign 2 pi i / R), for R = 2, 4, 8: the
 // even and odd halves transformed at R/2 and joined by the roots
